@@ -1,0 +1,89 @@
+"""Radiosity solve and facet flux (oracle; test infrastructure only).
+
+* emission, eq. (4): ``q = eps sigma T^4``; the radiation power of a facet is
+  ``eta = T^4`` (eq. (8) on nodes, the same quantity per facet here);
+* reflection matrix, eq. (11): ``C = I - Lambda F_paper`` with
+  ``Lambda_ii = (1 - eps_i) / A_i``.  With the per-area view factors of
+  ``viewfactor`` (``F_paper = diag(A) F``) this is ``C = I - diag(1 - eps) F``;
+* radiosity: ``J = C^-1 (sigma eps eta)``, the balance
+  ``J_i = eps_i sigma eta_i + (1 - eps_i) sum_j F_ij J_j``;
+* facet flux, eq. (12):
+  ``q_i = (sigma eps_i / A_i) sum_j eps_j sum_k F_paper_ik C^-1_kj (eta_j - eta_i)``.
+
+The dense system is solved by LU with partial pivoting (LAPACK getrf/getrs
+through scipy), in FP64.
+"""
+from __future__ import annotations
+
+import numpy as np
+import scipy.linalg as sla
+
+SIGMA = 5.670374e-8
+
+
+def reflection_matrix(F, eps):
+    """``C = I - diag(1 - eps) F`` (eq. (11) in the per-area convention)."""
+    n = F.shape[0]
+    return np.eye(n) - (1.0 - eps)[:, None] * F
+
+
+def emission(eps, T, sigma=SIGMA):
+    """Right-hand side ``sigma eps T^4`` (eq. (4)); T may be n or n x r."""
+    T = np.asarray(T, dtype=np.float64)
+    e = eps if T.ndim == 1 else eps[:, None]
+    return sigma * e * T**4
+
+
+class DenseRadiosity:
+    """Dense LU of the reflection matrix of one cavity, reused for every
+    right-hand side (as the paper reuses its factorisation)."""
+
+    def __init__(self, F, eps, sigma=SIGMA):
+        self.F = F
+        self.eps = np.asarray(eps, dtype=np.float64)
+        self.sigma = sigma
+        self.C = reflection_matrix(F, self.eps)
+        self.lu = sla.lu_factor(self.C)
+        # w = C^-1 eps and g = F w, used by the O(n) evaluation of eq. (12)
+        self.w = sla.lu_solve(self.lu, self.eps)
+        self.g = F @ self.w
+
+    def solve(self, b):
+        return sla.lu_solve(self.lu, b)
+
+    def radiosity(self, T):
+        return self.solve(emission(self.eps, T, self.sigma))
+
+    def flux(self, T, J=None):
+        """Eq. (12) rewritten with the radiosity J:
+        ``q_i = sigma eps_i [ (F C^-1 (eps eta))_i - eta_i (F C^-1 eps)_i ]``
+        ``    = eps_i [ (F J)_i - sigma eta_i g_i ]``,  ``g = F C^-1 eps``."""
+        T = np.asarray(T, dtype=np.float64)
+        if J is None:
+            J = self.radiosity(T)
+        eta = T**4
+        if T.ndim == 1:
+            return self.eps * (self.F @ J - self.sigma * eta * self.g)
+        return self.eps[:, None] * (self.F @ J - self.sigma * eta * self.g[:, None])
+
+
+def flux_eq12_literal(F, eps, area, T, sigma=SIGMA):
+    """Eq. (12) term by term with the paper's area-weighted view factor
+    ``F_paper = diag(A) F`` and ``C = I - Lambda F_paper``.  O(n^3); small n."""
+    eps = np.asarray(eps, dtype=np.float64)
+    A = np.asarray(area, dtype=np.float64)
+    Fp = A[:, None] * F
+    Lam = (1.0 - eps) / A
+    C = np.eye(F.shape[0]) - Lam[:, None] * Fp
+    M = Fp @ np.linalg.inv(C)            # M_ij = sum_k F_paper_ik C^-1_kj
+    eta = np.asarray(T, dtype=np.float64) ** 4
+    diff = eta[None, :] - eta[:, None]   # (eta_j - eta_i)
+    return (sigma * eps / A) * np.sum(eps[None, :] * M * diff, axis=1)
+
+
+def relative_l2(a, b, axis=0):
+    """``|a - b|_2 / |b|_2`` per right-hand side (the error measure of
+    eq. (36), applied to J, q or T)."""
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    return np.linalg.norm(a - b, axis=axis) / np.linalg.norm(b, axis=axis)

@@ -1,0 +1,75 @@
+"""Planted mistakes in copies of oracle formulas must fail the pins.
+
+Each test builds a deliberately wrong variant of one oracle step on the CPU
+and shows that the closed form / invariant used to pin that step rejects it.
+"""
+import math
+
+import numpy as np
+import scipy.linalg as sla
+
+from oracle import closed_forms, radiosity, viewfactor
+from workloads import meshes
+
+
+def _sphere_pin_error(vf_fn):
+    p, n, w = meshes.projected_sphere_points(2, radius=1.3, seed=3)
+    F = vf_fn(p, n, w)
+    ref = closed_forms.sphere_points_F(w, 1.3)
+    off = ~np.eye(w.size, dtype=bool)
+    return np.max(np.abs(F[off] - ref[off]) / ref[off])
+
+
+def _vf_variant(c, n, a, drop_area=False, wrong_power=False, sign_flip=False):
+    d = c[None, :, :] - c[:, None, :]
+    r2 = np.sum(d * d, axis=2)
+    ci = np.einsum("ik,ijk->ij", n, d)
+    cj = -np.einsum("jk,ijk->ij", n, d)
+    if sign_flip:
+        cj = -cj
+    num = np.maximum(ci, 0) * np.maximum(cj, 0) * (1.0 if drop_area else a[None, :])
+    den = math.pi * (r2 if wrong_power else r2 * r2)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        F = np.where(r2 > 0, num / den, 0.0)
+    np.fill_diagonal(F, 0.0)
+    return F
+
+
+def test_sphere_pin_accepts_oracle_and_rejects_mutants():
+    assert _sphere_pin_error(viewfactor.view_factor_matrix) < 1e-13
+    assert _sphere_pin_error(lambda c, n, a: _vf_variant(c, n, a)) < 1e-12
+    assert _sphere_pin_error(lambda c, n, a: _vf_variant(c, n, a, drop_area=True)) > 0.1
+    assert _sphere_pin_error(lambda c, n, a: _vf_variant(c, n, a, wrong_power=True)) > 0.1
+    assert _sphere_pin_error(lambda c, n, a: _vf_variant(c, n, a, sign_flip=True)) > 0.1
+
+
+def test_two_plate_pin_rejects_column_scaled_operator():
+    F = np.array([[0.0, 1.0], [1.0, 0.0]])
+    eps = np.array([0.8, 0.3])
+    T = np.array([400.0, 900.0])
+    exact = closed_forms.two_plates_flux(0.8, 0.3, 400.0, 900.0)
+    # mutant: C = I - F diag(1 - eps) (scaling on the wrong side)
+    C_bad = np.eye(2) - F * (1.0 - eps)[None, :]
+    b = radiosity.emission(eps, T)
+    J_bad = sla.solve(C_bad, b)
+    w_bad = sla.solve(C_bad, eps)
+    q_bad = eps * (F @ J_bad - radiosity.SIGMA * T**4 * (F @ w_bad))
+    assert abs(q_bad[0] - exact) > 1e-3 * abs(exact)
+    q_ok = radiosity.DenseRadiosity(F, eps).flux(T)
+    assert abs(q_ok[0] - exact) < 1e-12 * abs(exact)
+
+
+def test_literal_flux_pin_rejects_flux_without_g():
+    v, f = meshes.cylinder(16, 8, 3, seed=2)
+    from oracle import geometry
+    c, n, a = geometry.facets_from_triangles(v, meshes.inward(f))
+    rng = np.random.default_rng(0)
+    eps = rng.uniform(0.1, 0.9, a.size)
+    T = rng.uniform(300, 1500, a.size)
+    F = viewfactor.view_factor_matrix(c, n, a)
+    rad = radiosity.DenseRadiosity(F, eps)
+    ql = radiosity.flux_eq12_literal(F, eps, a, T)
+    J = rad.radiosity(T)
+    q_bad = eps * (F @ J - radiosity.SIGMA * T**4)   # mutant: g replaced by 1
+    assert np.linalg.norm(q_bad - ql) / np.linalg.norm(ql) > 1e-4
+    assert np.linalg.norm(rad.flux(T) - ql) / np.linalg.norm(ql) < 1e-12
