@@ -23,6 +23,14 @@ def two_plates_flux(eps1, eps2, T1, T2, sigma=SIGMA):
     return sigma * eps1 * eps2 * (T2**4 - T1**4) / (1.0 - (1.0 - eps1) * (1.0 - eps2))
 
 
+def two_plates_radiosity(eps1, eps2, T1, T2, sigma=SIGMA):
+    """Radiosity of plate 1 for two infinite plates: solving
+    ``J1 = eps1 sigma T1^4 + (1 - eps1) J2`` together with the same relation
+    for plate 2 gives ``J1 = sigma (eps1 T1^4 + (1 - eps1) eps2 T2^4) /
+    (1 - (1 - eps1)(1 - eps2))``."""
+    return sigma * (eps1 * T1**4 + (1.0 - eps1) * eps2 * T2**4) / (1.0 - (1.0 - eps1) * (1.0 - eps2))
+
+
 def sphere_points_F(weights, radius):
     """Exact ``F`` for points on a sphere with inward radial normals:
     ``F_ij = w_j / (4 pi R^2)`` off the diagonal, 0 on it."""

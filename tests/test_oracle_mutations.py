@@ -44,19 +44,17 @@ def test_sphere_pin_accepts_oracle_and_rejects_mutants():
 
 
 def test_two_plate_pin_rejects_column_scaled_operator():
+    """Scaling F by (1 - eps) on the wrong side leaves the two-plate flux
+    unchanged (F is symmetric there) but breaks the radiosity closed form."""
     F = np.array([[0.0, 1.0], [1.0, 0.0]])
     eps = np.array([0.8, 0.3])
     T = np.array([400.0, 900.0])
-    exact = closed_forms.two_plates_flux(0.8, 0.3, 400.0, 900.0)
-    # mutant: C = I - F diag(1 - eps) (scaling on the wrong side)
+    exact_J1 = closed_forms.two_plates_radiosity(0.8, 0.3, 400.0, 900.0)
     C_bad = np.eye(2) - F * (1.0 - eps)[None, :]
-    b = radiosity.emission(eps, T)
-    J_bad = sla.solve(C_bad, b)
-    w_bad = sla.solve(C_bad, eps)
-    q_bad = eps * (F @ J_bad - radiosity.SIGMA * T**4 * (F @ w_bad))
-    assert abs(q_bad[0] - exact) > 1e-3 * abs(exact)
-    q_ok = radiosity.DenseRadiosity(F, eps).flux(T)
-    assert abs(q_ok[0] - exact) < 1e-12 * abs(exact)
+    J_bad = sla.solve(C_bad, radiosity.emission(eps, T))
+    assert abs(J_bad[0] - exact_J1) > 1e-3 * abs(exact_J1)
+    J_ok = radiosity.DenseRadiosity(F, eps).radiosity(T)
+    assert abs(J_ok[0] - exact_J1) < 1e-13 * abs(exact_J1)
 
 
 def test_literal_flux_pin_rejects_flux_without_g():

@@ -113,6 +113,9 @@ def test_two_infinite_plates(e1, e2, T1, T2):
     assert q[1] == pytest.approx(-exact, abs=tol)
     ql = radiosity.flux_eq12_literal(F, np.array([e1, e2]), np.ones(2), np.array([T1, T2]))
     assert ql[0] == pytest.approx(exact, abs=tol)
+    J = rad.radiosity(np.array([T1, T2]))
+    assert J[0] == pytest.approx(closed_forms.two_plates_radiosity(e1, e2, T1, T2), rel=1e-14)
+    assert J[1] == pytest.approx(closed_forms.two_plates_radiosity(e2, e1, T2, T1), rel=1e-14)
 
 
 def test_projected_sphere_closed_form_solution():
