@@ -1,0 +1,287 @@
+/*
+ * hm.h -- C ABI of the hierarchical (H-matrix) view-factor radiosity library
+ * for AMD Instinct MI355X (gfx950).
+ *
+ * The library implements the hot path of "Hierarchical Block Low-rank
+ * Approximation of Cavity Radiation" (arXiv 2305.06891):
+ *   - facet geometry and the centroid-rule view factor of eq. (10)
+ *     (Sec. 3.2): F_ij = max(0,cos_i) max(0,cos_j) A_j / (pi r^2), F_ii = 0,
+ *     in the per-area convention (the paper's area-weighted F is diag(A) F);
+ *   - the geometric cluster tree of Algorithm 1 and the block tree of
+ *     Algorithm 2 with the admissibility condition of Sec. 4.2;
+ *   - adaptive cross approximation (Sec. 4.3, eq. (30)) of the admissible
+ *     blocks under the block-wise tolerance of eq. (31);
+ *   - the block-wise product x -> F x of Sec. 5.2 inside a Krylov solve of the
+ *     radiosity system C J = sigma eps T^4 with the reflection matrix of
+ *     eq. (11), C = I - diag(1 - eps) F, and the facet flux of eq. (12).
+ *
+ * Conventions (every function):
+ *   - Facet order at the ABI is the caller's ORIGINAL order.  The cluster
+ *     permutation never leaks out (except through hm_tree_stats/perm_out).
+ *   - Pointers are borrowed for the duration of the call unless stated.
+ *     "HOST" pointers are ordinary CPU memory; "DEVICE" pointers must be
+ *     device memory on the context's GPU (for example torch tensors) and are
+ *     used in stream order on the context's stream.
+ *   - Matrices of right-hand sides are column-major with a leading dimension
+ *     (ld >= n); column r of X starts at X + r*ld.
+ *   - Every call returns an hm_status; nothing throws across the ABI.  On
+ *     failure hm_last_error(ctx) describes the cause (NULL ctx: the message
+ *     is kept per thread and returned by hm_last_error(NULL)).
+ *   - Opaque handles are created by the library and released by the
+ *     matching *_destroy; destroying NULL is a no-op.
+ */
+#ifndef HM_H
+#define HM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  HM_OK = 0,
+  HM_EINVAL = 1,     /* invalid argument (sizes, ranges, NaN, zero area ...) */
+  HM_ENOMEM = 2,     /* device/host allocation failed or budget exceeded     */
+  HM_ENOTCONV = 3,   /* iteration did not reach the tolerance; best iterate  */
+  HM_EDEVICE = 4,    /* HIP runtime error                                    */
+  HM_EBUSY = 5,      /* result not ready yet (hm_poll)                       */
+  HM_ENOTFOUND = 6   /* unknown ticket or cavity id                          */
+} hm_status;
+
+typedef enum { HM_F64 = 0, HM_F32 = 1, HM_BF16 = 2 } hm_dtype;
+
+typedef struct hm_ctx hm_ctx;
+typedef struct hm_tree hm_tree;
+typedef struct hm_matrix hm_matrix;
+typedef struct hm_server hm_server;
+
+/* ------------------------------------------------------------------ context */
+
+/* Create a context bound to GPU `device` and HIP stream `hip_stream`
+ * (hipStream_t passed as void*; NULL = the library creates its own
+ * non-blocking stream).  One context per host thread / stream. */
+hm_status hm_ctx_create(int device, void* hip_stream, hm_ctx** out);
+void hm_ctx_destroy(hm_ctx* ctx);
+/* Block until all work the library queued on ctx's stream has finished. */
+hm_status hm_ctx_synchronize(hm_ctx* ctx);
+const char* hm_status_string(hm_status s);
+const char* hm_last_error(const hm_ctx* ctx);
+/* Library version string, e.g. "hmrad 1.0 gfx950". */
+const char* hm_version(void);
+
+/* ----------------------------------------------------------- facet geometry */
+
+/* Facet centroid, unit normal and area of every triangle (Sec. 3.1-3.2: the
+ * radiation surface is a set of flat facets with areas, centroids and plane
+ * normals).  HOST, FP64.  v: nv x 3 row-major vertices; tri: nt x 3
+ * row-major vertex indices.  The normal is (b-a) x (c-a) normalised, then
+ * oriented by `orient`: +1 keep, -1 flip, 0 flip if it points away from the
+ * vertex centroid of the mesh (valid for star-shaped cavities).  Outputs
+ * (caller-allocated HOST): centroid nt x 3, normal nt x 3, area nt.
+ * HM_EINVAL on an index out of range, a degenerate (zero-area) triangle or a
+ * non-finite coordinate. */
+hm_status hm_facets_from_triangles(int64_t nv, const double* v, int64_t nt, const int32_t* tri,
+                                   int orient, double* centroid, double* normal, double* area);
+
+/* ----------------------------------------------------- cluster / block tree */
+
+typedef struct {
+  int32_t leaf_size; /* n_min of Algorithm 1: a cluster with #tau <= leaf_size is a leaf (>= 1) */
+  double eta;        /* admissibility constant c of Sec. 4.2 (> 0) */
+} hm_tree_params;
+
+/* Build the index tree (Algorithm 1: split the centroid bounding box along
+ * its longest axis at the median, ties x<y<z, order by (coordinate, original
+ * index), left child gets floor(#tau/2)) and the block tree (Algorithm 2:
+ * a block is admissible iff min(diam s, diam t) <= eta * dist(s, t) with
+ * bounding-box diam/dist and dist > 0; an inadmissible block whose row or
+ * column cluster is a leaf becomes a dense leaf).  HOST inputs (copied):
+ * centroid n x 3, normal_into_cavity n x 3 (unit), area n (> 0).  ctx may be
+ * NULL (the tree is host data).  Destroy with hm_tree_destroy. */
+hm_status hm_build_cluster_tree(hm_ctx* ctx, int64_t n, const double* centroid,
+                                const double* normal_into_cavity, const double* area,
+                                const hm_tree_params* params, hm_tree** out);
+
+/* Counts of the tree; any output pointer may be NULL.  perm_out (HOST, n):
+ * perm_out[k] = original index of the facet at permuted position k. */
+hm_status hm_tree_stats(const hm_tree* tree, int64_t* n_nodes, int64_t* n_dense, int64_t* n_lowrank,
+                        int32_t* perm_out);
+
+/* Leaf blocks of the block tree in permuted positions, sorted by (row begin,
+ * column begin): dense_out (HOST, n_dense x 4) and lowrank_out (HOST,
+ * n_lowrank x 4), each row (row_begin, row_end, col_begin, col_end).  Either
+ * pointer may be NULL. */
+hm_status hm_tree_blocks(const hm_tree* tree, int32_t* dense_out, int32_t* lowrank_out);
+void hm_tree_destroy(hm_tree* tree);
+
+/* ------------------------------------------------------------- H-matrix */
+
+typedef struct {
+  double aca_tol;          /* eps_rel of eq. (31), in (0, 1) */
+  int32_t k_max;           /* rank cap of ACA; a block reaching it is stored dense (>= 1) */
+  hm_dtype lowrank_dtype;  /* storage of U, V: HM_F64, HM_F32 or HM_BF16 */
+  hm_dtype dense_dtype;    /* storage of near-field blocks: HM_F64 or HM_F32 */
+  int32_t keep_f32_copy;   /* with HM_BF16 factors: also keep FP32 factors (refinement residual) */
+  int32_t closed_row_scale;/* 1: closed-cavity row scaling of eqs. (32)-(34) (clamp the row sum
+                              to [0,1], divide rows with non-zero clamped sum by it); default 0 */
+} hm_assembly_params;
+
+/* Evaluate the near field (every inadmissible leaf block, FP64 evaluation
+ * of eq. (10) rounded to dense_dtype) and compress every admissible block by
+ * partial-pivoting ACA in FP64 (eq. (30); stop when |u_k||v_k| <= aca_tol *
+ * |sum u_l v_l^T|_F).  An admissible block whose ACA reaches the cap
+ * min(k_max, ceil(mn/(m+n))) without meeting the stop test, or whose rank k
+ * gives k(m+n) >= mn, is stored dense.  The matrix keeps what it needs; the
+ * tree may be destroyed afterwards.  Runs on ctx's stream and synchronises it. */
+hm_status hm_assemble_hmatrix(hm_ctx* ctx, const hm_tree* tree, const hm_assembly_params* params,
+                              hm_matrix** out);
+
+/* bytes_device: device bytes held by the matrix; entries_dense: sum of m*n
+ * over dense blocks; entries_lowrank: sum of k*(m+n) over low-rank blocks;
+ * max_rank; any pointer may be NULL. */
+hm_status hm_matrix_stats(const hm_matrix* M, int64_t* bytes_device, int64_t* entries_dense,
+                          int64_t* entries_lowrank, int32_t* max_rank);
+/* Extended statistics: n, number of dense / low-rank blocks, admissible
+ * blocks stored dense (fallbacks), sum of ranks.  Any pointer may be NULL. */
+hm_status hm_matrix_info(const hm_matrix* M, int64_t* n, int64_t* n_dense_blocks,
+                         int64_t* n_lowrank_blocks, int64_t* n_fallback, int64_t* rank_sum);
+void hm_matrix_destroy(hm_matrix* M);
+
+/* Y = alpha * F_H * X + beta * Y (Sec. 5.2: the block-wise product adds no
+ * approximation beyond the stored blocks).  X, Y: DEVICE, n x nrhs
+ * column-major, leading dims ldx, ldy, of type vec_dtype (HM_F64 or HM_F32).
+ * 1 <= nrhs <= 16.  use_f32_copy = 1 reads the FP32 copy of BF16 factors.
+ * Accumulation is in vec_dtype.  X and Y must not overlap. */
+hm_status hm_hmatvec(hm_ctx* ctx, const hm_matrix* M, int32_t nrhs, hm_dtype vec_dtype, const void* X,
+                     int64_t ldx, void* Y, int64_t ldy, double alpha, double beta);
+hm_status hm_hmatvec_ex(hm_ctx* ctx, const hm_matrix* M, int32_t nrhs, hm_dtype vec_dtype,
+                        int32_t use_f32_copy, const void* X, int64_t ldx, void* Y, int64_t ldy,
+                        double alpha, double beta);
+
+/* ----------------------------------------------------------- radiosity solve */
+
+typedef struct {
+  double rtol;             /* stop when |b - C J|_2 <= rtol |b|_2 per right-hand side */
+  int32_t restart;         /* GMRES restart length m (1..64) */
+  int32_t max_iter;        /* total Arnoldi steps per solve */
+  int32_t mixed_precision; /* 1: iterative refinement: FP64 residual with FP32 (or FP64)
+                              factors, inner GMRES with the stored (e.g. BF16) factors */
+  double ir_inner_rtol;    /* inner relative tolerance of each refinement step */
+  int32_t want_q;          /* compute the facet flux of eq. (12) */
+  int32_t vec_dtype;       /* Krylov vectors when not refining: HM_F64 or HM_F32 */
+} hm_solve_params;
+
+typedef struct {
+  int32_t iters;           /* Arnoldi steps (max over right-hand sides) */
+  int32_t outer_iters;     /* refinement steps (0 without refinement) */
+  int32_t matvecs;         /* H-matrix products issued (all precisions) */
+  double rel_residual;     /* max over right-hand sides of |b - C J| / |b| (FP64) */
+  double seconds;          /* wall time of the call */
+  int64_t bytes_moved;     /* algorithmic bytes of all products */
+} hm_solve_info;
+
+/* Solve (I - diag(1 - eps) F) J = sigma eps T^4 (eq. (11) with the per-area F;
+ * the radiosity balance J_i = eps_i sigma T_i^4 + (1 - eps_i) sum_j F_ij J_j)
+ * for nrhs temperature fields by restarted GMRES (classical Gram-Schmidt
+ * with re-orthogonalisation, x0 = b), and optionally the facet flux of
+ * eq. (12), evaluated as q = eps (F J - sigma T^4 g) with g = F C^-1 eps
+ * (g is computed once per matrix and emissivity field and cached).
+ * eps: DEVICE FP64 n, 0 < eps <= 1.  T: DEVICE FP64 n x nrhs (> 0).
+ * J, q: DEVICE FP64 n x nrhs (q may be NULL).  1 <= nrhs <= 16.
+ * Returns HM_ENOTCONV with the best iterate in J (and q) when rtol is not
+ * met within max_iter; info (may be NULL) is filled either way. */
+hm_status hm_solve_radiosity(hm_ctx* ctx, const hm_matrix* M, const double* eps, int32_t nrhs,
+                             const double* T, int64_t ldT, double sigma, const hm_solve_params* p,
+                             double* J, int64_t ldJ, double* q, int64_t ldq, hm_solve_info* info);
+
+/* Batched form: `count` independent cavities solved together; every
+ * H-matrix product and every Krylov kernel covers all of them in one launch
+ * (block-diagonal operator).  Arrays of length count; eps[i], T[i], J[i],
+ * q[i] are DEVICE pointers for cavity i (n_i rows, one right-hand side;
+ * q may be NULL or hold NULL entries).  info_out (HOST, count, may be NULL). */
+hm_status hm_solve_radiosity_batched(hm_ctx* ctx, int32_t count, const hm_matrix* const* M,
+                                     const double* const* eps, const double* const* T, double sigma,
+                                     const hm_solve_params* p, double* const* J, double* const* q,
+                                     hm_solve_info* info_out);
+
+/* ------------------------------------------------------------ transient */
+
+typedef struct {
+  double mc;          /* heat capacity per area rho*c*thickness, J/(m^2 K) */
+  double dt;          /* time step, s */
+  int32_t steps;      /* backward-Euler steps */
+  double newton_rtol; /* stop when |R|_2 <= newton_rtol |mc T^n / dt|_2 per scenario */
+  int32_t max_newton; /* Newton updates per step */
+} hm_transient_params;
+
+typedef struct {
+  int32_t steps_done;
+  int32_t newton_total;   /* Newton iterations summed over steps */
+  int32_t newton_max;     /* most Newton iterations in one step */
+  int32_t matvecs;
+  double seconds;
+  double max_rel_residual;/* largest final |R| / |mc T^n/dt| over steps and scenarios */
+} hm_transient_info;
+
+/* Lumped implicit-Euler radiative exchange on one cavity (analogue of the
+ * time discretisation of Sec. 3.3): mc (T - T^n)/dt = q(T) + s per facet,
+ * with q of eq. (12).  Each step runs Newton's method with the local
+ * Jacobian D = mc/dt + 4 sigma eps g T^3, T <- T - R/D; each Newton
+ * iteration solves the radiosity system for all nrhs scenarios at once.
+ * T: DEVICE FP64 n x nrhs, in: T^0, out: T^steps.  src: DEVICE FP64
+ * n x nrhs (W/m^2).  eps: DEVICE FP64 n.  history (DEVICE FP64,
+ * (steps+1) x ld x nrhs blocks, may be NULL) receives T^0..T^steps. */
+hm_status hm_transient_run(hm_ctx* ctx, const hm_matrix* M, const double* eps, int32_t nrhs, double* T,
+                           int64_t ldT, const double* src, int64_t ldS, double sigma,
+                           const hm_transient_params* tp, const hm_solve_params* sp, double* history,
+                           hm_transient_info* info);
+
+/* ------------------------------------------------------------- serving */
+
+typedef struct {
+  int64_t hbm_budget_bytes;  /* device bytes allowed for resident H-matrices + solve buffers */
+  int32_t max_active;        /* most requests advanced together */
+  int32_t max_rhs_per_slot;  /* right-hand sides of one cavity batched in one slot (<= 16) */
+  hm_solve_params solve;
+  double sigma;
+} hm_server_params;
+
+typedef struct {
+  int64_t submitted, completed, rejected;
+  int64_t assemblies, evictions, cache_hits;
+  int64_t rounds;            /* batched solve rounds run */
+  double busy_seconds;
+  int64_t resident_bytes;
+} hm_server_stats;
+
+/* A serving loop owned by a background host thread: requests (radiosity
+ * solves of registered cavities) are admitted while the resident H-matrices
+ * and the solve buffers fit hbm_budget_bytes, advanced together in shared
+ * products, and retired as they converge; new requests join at the next
+ * round.  H-matrices stay resident across requests (least-recently-used
+ * eviction).  Thread-safe. */
+hm_status hm_server_create(hm_ctx* ctx, const hm_server_params* p, hm_server** out);
+/* Register a cavity: the tree is copied; eps_host (HOST, n) is copied;
+ * assembly happens lazily on first use. */
+hm_status hm_server_register_cavity(hm_server* s, uint64_t cavity_id, const hm_tree* tree,
+                                    const double* eps_host, const hm_assembly_params* ap);
+/* Queue a request of nrhs temperature fields (HOST n x nrhs column-major,
+ * copied).  HM_ENOTFOUND for an unknown cavity, HM_EINVAL for bad sizes. */
+hm_status hm_submit(hm_server* s, uint64_t cavity_id, int32_t nrhs, const double* T_host, uint64_t* ticket);
+/* done = 1 when the request finished: J_host / q_host (HOST n x nrhs, may
+ * be NULL) and info receive the result and the ticket is released.  Returns
+ * HM_EBUSY with done = 0 while running, HM_ENOTFOUND for unknown tickets,
+ * or the request's own status when it failed. */
+hm_status hm_poll(hm_server* s, uint64_t ticket, int32_t* done, double* J_host, double* q_host,
+                  hm_solve_info* info, double* latency_seconds);
+hm_status hm_server_stats_get(hm_server* s, hm_server_stats* out);
+/* Stop the loop after in-flight work finished; pending tickets stay pollable
+ * until destroy. */
+void hm_server_destroy(hm_server* s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HM_H */

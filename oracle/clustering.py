@@ -116,8 +116,8 @@ def build_block_tree(root: Cluster, eta: float):
                     rec(sc, tc)
 
     rec(root, root)
-    dense.sort()
-    lowrank.sort()
+    dense.sort(key=lambda b: (b[0], b[2]))
+    lowrank.sort(key=lambda b: (b[0], b[2]))
     return dense, lowrank
 
 

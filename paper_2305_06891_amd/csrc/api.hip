@@ -1,0 +1,421 @@
+// C entry points of the library (see include/hm.h): contexts, assembly,
+// products, solves and the transient driver.
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <cmath>
+#include <map>
+
+#include "dev_common.hpp"
+#include "solve.hpp"
+
+namespace hm {
+
+namespace {
+thread_local std::string g_tl_error;
+std::atomic<uint64_t> g_next_id{1};
+}  // namespace
+
+const char* tl_error() { return g_tl_error.c_str(); }
+void set_tl_error(const std::string& m) { g_tl_error = m; }
+
+hm_matrix* assemble(hm_ctx& ctx, const hm_tree& t, const hm_assembly_params& p);
+
+// Per-matrix cache: compositions for plain products, permuted vector
+// buffers, and batched-solve state keyed by the ids of its matrices.
+struct MatCache {
+  std::map<int, std::unique_ptr<Composition>> comps;
+  DevBuf xp, yp;
+  std::map<std::vector<uint64_t>, std::unique_ptr<Batch>> batches;
+};
+
+MatCache& cache_of(const hm_matrix& M) {
+  auto& mm = const_cast<hm_matrix&>(M);
+  if (!mm.cache) mm.cache = std::shared_ptr<void>(new MatCache(), [](void* p) { delete (MatCache*)p; });
+  return *(MatCache*)mm.cache.get();
+}
+
+Batch& batch_for(const std::vector<const hm_matrix*>& mats, int nrhs, hipStream_t s) {
+  std::vector<uint64_t> key;
+  for (const auto* M : mats) key.push_back(M->id);
+  key.push_back((uint64_t)nrhs);
+  MatCache& mc = cache_of(*mats[0]);
+  auto it = mc.batches.find(key);
+  if (it != mc.batches.end()) return *it->second;
+  auto b = std::make_unique<Batch>(mats, nrhs, s);
+  Batch& r = *b;
+  mc.batches[key] = std::move(b);
+  return r;
+}
+
+template <class VT>
+__global__ void k_perm_gather(const int32_t* __restrict__ perm, const VT* __restrict__ in, int64_t ldi,
+                              VT* __restrict__ out, int64_t ldo, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = blockIdx.y;
+  if (i < n) out[i + j * ldo] = in[perm[i] + j * ldi];
+}
+
+template <class VT>
+__global__ void k_perm_scatter(const int32_t* __restrict__ perm, const VT* __restrict__ in, int64_t ldi,
+                               VT* __restrict__ out, int64_t ldo, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = blockIdx.y;
+  if (i < n) out[perm[i] + j * ldo] = in[i + j * ldi];
+}
+
+__global__ void k_check_range(const double* __restrict__ v, int64_t n, int64_t ld, int ncol, double lo, double hi,
+                              int lo_open, int* bad) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = blockIdx.y;
+  if (i >= n || j >= ncol) return;
+  const double x = v[i + j * ld];
+  const bool ok = (lo_open ? x > lo : x >= lo) && x <= hi;  // false for NaN
+  if (!ok) atomicOr(bad, 1);
+}
+
+// Device-side validation of caller vectors (no copy to the host).
+void check_device_range(hm_ctx& c, const double* v, int64_t n, int64_t ld, int ncol, double lo, double hi,
+                        bool lo_open, const char* what) {
+  DevBuf flag(4);
+  HM_HIP(hipMemsetAsync(flag.get(), 0, 4, c.stream));
+  hipLaunchKernelGGL(k_check_range, dim3((unsigned)((n + 255) / 256), (unsigned)ncol), dim3(256), 0, c.stream, v, n,
+                     ld, ncol, lo, hi, lo_open ? 1 : 0, flag.get<int>());
+  HM_HIP(hipGetLastError());
+  int bad = 0;
+  HM_HIP(hipMemcpyAsync(&bad, flag.get(), 4, hipMemcpyDeviceToHost, c.stream));
+  HM_HIP(hipStreamSynchronize(c.stream));
+  if (bad) fail(HM_EINVAL, std::string(what) + " out of range or not finite");
+}
+
+}  // namespace hm
+
+int64_t hm_matrix::bytes_device() const {
+  int64_t b = (int64_t)(dense.bytes() + U.bytes() + V.bytes() + U_hi.bytes() + V_hi.bytes() + d_perm.bytes());
+  b += (int64_t)(plan.d_p1.bytes() + plan.d_p1_task.bytes() + plan.d_p2.bytes() + plan.d_p2_task.bytes() +
+                 plan.d_segs.bytes());
+  return b;
+}
+
+using namespace hm;
+
+namespace {
+
+template <class F>
+hm_status guarded(hm_ctx* ctx, F&& f) {
+  try {
+    if (ctx) HM_HIP(hipSetDevice(ctx->device));
+    f();
+    return HM_OK;
+  } catch (const Error& e) {
+    if (ctx) ctx->last_error = e.what();
+    set_tl_error(e.what());
+    return e.code;
+  } catch (const std::bad_alloc&) {
+    if (ctx) ctx->last_error = "out of host memory";
+    set_tl_error("out of host memory");
+    return HM_ENOMEM;
+  } catch (const std::exception& e) {
+    if (ctx) ctx->last_error = e.what();
+    set_tl_error(e.what());
+    return HM_EDEVICE;
+  }
+}
+
+void check_params(const hm_solve_params* p) {
+  HM_REQUIRE(p, "solve: NULL params");
+  HM_REQUIRE(p->rtol > 0.0 && p->rtol < 1.0, "solve: rtol must be in (0, 1)");
+  HM_REQUIRE(p->restart >= 1 && p->restart <= MAXM, "solve: restart must be in 1..64");
+  HM_REQUIRE(p->max_iter >= 1, "solve: max_iter must be >= 1");
+  HM_REQUIRE(!p->mixed_precision || (p->ir_inner_rtol > 0.0 && p->ir_inner_rtol < 1.0),
+             "solve: ir_inner_rtol must be in (0, 1)");
+  HM_REQUIRE(p->vec_dtype == HM_F64 || p->vec_dtype == HM_F32, "solve: vec_dtype must be HM_F64 or HM_F32");
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* hm_version(void) { return "hmrad 1.0 gfx950"; }
+
+const char* hm_status_string(hm_status s) {
+  switch (s) {
+    case HM_OK: return "ok";
+    case HM_EINVAL: return "invalid argument";
+    case HM_ENOMEM: return "out of memory";
+    case HM_ENOTCONV: return "not converged";
+    case HM_EDEVICE: return "device error";
+    case HM_EBUSY: return "busy";
+    case HM_ENOTFOUND: return "not found";
+  }
+  return "unknown status";
+}
+
+const char* hm_last_error(const hm_ctx* ctx) { return ctx ? ctx->last_error.c_str() : tl_error(); }
+
+hm_status hm_ctx_create(int device, void* hip_stream, hm_ctx** out) {
+  if (!out) {
+    set_tl_error("hm_ctx_create: NULL out");
+    return HM_EINVAL;
+  }
+  auto c = std::make_unique<hm_ctx>();
+  c->device = device;
+  hm_status st = guarded(nullptr, [&] {
+    int nd = 0;
+    HM_HIP(hipGetDeviceCount(&nd));
+    HM_REQUIRE(device >= 0 && device < nd, "hm_ctx_create: no such device");
+    HM_HIP(hipSetDevice(device));
+    if (hip_stream) {
+      c->stream = (hipStream_t)hip_stream;
+    } else {
+      HM_HIP(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
+      c->own_stream = true;
+    }
+  });
+  if (st == HM_OK) *out = c.release();
+  return st;
+}
+
+void hm_ctx_destroy(hm_ctx* ctx) {
+  if (!ctx) return;
+  if (ctx->own_stream) {
+    (void)hipSetDevice(ctx->device);
+    (void)hipStreamSynchronize(ctx->stream);
+    (void)hipStreamDestroy(ctx->stream);
+  }
+  delete ctx;
+}
+
+hm_status hm_ctx_synchronize(hm_ctx* ctx) {
+  if (!ctx) return HM_EINVAL;
+  return guarded(ctx, [&] { HM_HIP(hipStreamSynchronize(ctx->stream)); });
+}
+
+hm_status hm_assemble_hmatrix(hm_ctx* ctx, const hm_tree* tree, const hm_assembly_params* p, hm_matrix** out) {
+  if (!ctx) {
+    set_tl_error("hm_assemble_hmatrix: NULL ctx");
+    return HM_EINVAL;
+  }
+  return guarded(ctx, [&] {
+    HM_REQUIRE(tree && p && out, "hm_assemble_hmatrix: NULL argument");
+    HM_REQUIRE(p->aca_tol > 0.0 && p->aca_tol < 1.0, "hm_assemble_hmatrix: aca_tol must be in (0, 1)");
+    HM_REQUIRE(p->k_max >= 1, "hm_assemble_hmatrix: k_max must be >= 1");
+    HM_REQUIRE(p->lowrank_dtype == HM_F64 || p->lowrank_dtype == HM_F32 || p->lowrank_dtype == HM_BF16,
+               "hm_assemble_hmatrix: bad lowrank_dtype");
+    HM_REQUIRE(p->dense_dtype == HM_F64 || p->dense_dtype == HM_F32, "hm_assemble_hmatrix: bad dense_dtype");
+    HM_REQUIRE(!(p->dense_dtype == HM_F64 && p->lowrank_dtype == HM_BF16),
+               "hm_assemble_hmatrix: BF16 factors need FP32 near field");
+    hm_matrix* M = assemble(*ctx, *tree, *p);
+    M->id = g_next_id++;
+    *out = M;
+  });
+}
+
+hm_status hm_matrix_stats(const hm_matrix* M, int64_t* bytes, int64_t* ed, int64_t* el, int32_t* maxr) {
+  if (!M) {
+    set_tl_error("hm_matrix_stats: NULL matrix");
+    return HM_EINVAL;
+  }
+  if (bytes) *bytes = M->bytes_device();
+  if (ed) *ed = M->dense_entries;
+  if (el) *el = M->lr_entries;
+  if (maxr) *maxr = M->max_rank;
+  return HM_OK;
+}
+
+hm_status hm_matrix_info(const hm_matrix* M, int64_t* n, int64_t* nd, int64_t* nl, int64_t* nf, int64_t* rs) {
+  if (!M) {
+    set_tl_error("hm_matrix_info: NULL matrix");
+    return HM_EINVAL;
+  }
+  if (n) *n = M->n;
+  if (nd) *nd = M->n_dense_blocks;
+  if (nl) *nl = M->n_lr_blocks;
+  if (nf) *nf = M->n_fallback;
+  if (rs) *rs = M->rank_sum;
+  return HM_OK;
+}
+
+void hm_matrix_destroy(hm_matrix* M) {
+  if (!M) return;
+  (void)hipSetDevice(M->device);
+  (void)hipDeviceSynchronize();
+  delete M;
+}
+
+hm_status hm_hmatvec_ex(hm_ctx* ctx, const hm_matrix* M, int32_t nrhs, hm_dtype vt, int32_t use_hi, const void* X,
+                        int64_t ldx, void* Y, int64_t ldy, double alpha, double beta) {
+  if (!ctx) {
+    set_tl_error("hm_hmatvec: NULL ctx");
+    return HM_EINVAL;
+  }
+  return guarded(ctx, [&] {
+    HM_REQUIRE(M && X && Y, "hm_hmatvec: NULL argument");
+    HM_REQUIRE(nrhs >= 1 && nrhs <= 16, "hm_hmatvec: nrhs must be in 1..16");
+    HM_REQUIRE(vt == HM_F64 || vt == HM_F32, "hm_hmatvec: vec_dtype must be HM_F64 or HM_F32");
+    HM_REQUIRE(ldx >= M->n && ldy >= M->n, "hm_hmatvec: leading dimension smaller than n");
+    HM_REQUIRE(std::isfinite(alpha) && std::isfinite(beta), "hm_hmatvec: alpha/beta must be finite");
+    std::lock_guard<std::mutex> lk(const_cast<hm_matrix*>(M)->mu);
+    hipStream_t s = ctx->stream;
+    MatCache& mc = cache_of(*M);
+    const int W = pad_width(nrhs);
+    auto& comp = mc.comps[W];
+    if (!comp) comp = make_composition({M}, W, 8, s);
+    const int64_t n = M->n;
+    const size_t need = (size_t)n * W * 8;
+    if (mc.xp.bytes() < need) {
+      mc.xp.alloc(need);
+      mc.yp.alloc(need);
+    }
+    const int vb = vt == HM_F64 ? 8 : 4;
+    dim3 grid((unsigned)((n + 255) / 256), (unsigned)nrhs);
+    const int32_t* perm = M->d_perm.get<int32_t>();
+    if (vb == 8) {
+      hipLaunchKernelGGL(k_perm_gather<double>, grid, dim3(256), 0, s, perm, (const double*)X, ldx,
+                         mc.xp.get<double>(), n, n);
+      if (beta != 0.0)
+        hipLaunchKernelGGL(k_perm_gather<double>, grid, dim3(256), 0, s, perm, (const double*)Y, ldy,
+                           mc.yp.get<double>(), n, n);
+    } else {
+      hipLaunchKernelGGL(k_perm_gather<float>, grid, dim3(256), 0, s, perm, (const float*)X, ldx, mc.xp.get<float>(),
+                         n, n);
+      if (beta != 0.0)
+        hipLaunchKernelGGL(k_perm_gather<float>, grid, dim3(256), 0, s, perm, (const float*)Y, ldy,
+                           mc.yp.get<float>(), n, n);
+    }
+    HM_HIP(hipGetLastError());
+    Epilogue ep;
+    ep.a_acc = alpha;
+    ep.a_z = beta;
+    ep.z = beta != 0.0 ? mc.yp.get() : nullptr;
+    ep.ldz = n;
+    launch_matvec(*comp, nrhs, vb, use_hi != 0, mc.xp.get(), n, mc.yp.get(), n, ep, nullptr, s);
+    if (vb == 8)
+      hipLaunchKernelGGL(k_perm_scatter<double>, grid, dim3(256), 0, s, perm, mc.yp.get<double>(), n, (double*)Y, ldy, n);
+    else
+      hipLaunchKernelGGL(k_perm_scatter<float>, grid, dim3(256), 0, s, perm, mc.yp.get<float>(), n, (float*)Y, ldy, n);
+    HM_HIP(hipGetLastError());
+  });
+}
+
+hm_status hm_hmatvec(hm_ctx* ctx, const hm_matrix* M, int32_t nrhs, hm_dtype vt, const void* X, int64_t ldx,
+                     void* Y, int64_t ldy, double alpha, double beta) {
+  return hm_hmatvec_ex(ctx, M, nrhs, vt, 0, X, ldx, Y, ldy, alpha, beta);
+}
+
+static void fill_info(hm_solve_info* info, const SolveResult& R, double secs, int sys_begin, int sys_end) {
+  if (!info) return;
+  info->iters = R.iters;
+  info->outer_iters = R.outer;
+  info->matvecs = R.matvecs;
+  info->bytes_moved = R.bytes;
+  info->seconds = secs;
+  double rr = 0.0;
+  for (int q = sys_begin; q < sys_end && q < (int)R.rel_res.size(); ++q) rr = std::max(rr, R.rel_res[q]);
+  info->rel_residual = rr;
+}
+
+hm_status hm_solve_radiosity(hm_ctx* ctx, const hm_matrix* M, const double* eps, int32_t nrhs, const double* T,
+                             int64_t ldT, double sigma, const hm_solve_params* p, double* J, int64_t ldJ, double* q,
+                             int64_t ldq, hm_solve_info* info) {
+  if (!ctx) {
+    set_tl_error("hm_solve_radiosity: NULL ctx");
+    return HM_EINVAL;
+  }
+  bool conv = true;
+  hm_status st = guarded(ctx, [&] {
+    const auto t0 = std::chrono::steady_clock::now();
+    HM_REQUIRE(M && eps && T && J, "hm_solve_radiosity: NULL argument");
+    HM_REQUIRE(nrhs >= 1 && nrhs <= 16, "hm_solve_radiosity: nrhs must be in 1..16");
+    HM_REQUIRE(ldT >= M->n && ldJ >= M->n && (!q || ldq >= M->n), "hm_solve_radiosity: leading dimension < n");
+    HM_REQUIRE(sigma > 0.0 && std::isfinite(sigma), "hm_solve_radiosity: sigma must be > 0");
+    check_params(p);
+    check_device_range(*ctx, eps, M->n, M->n, 1, 0.0, 1.0, true, "eps");
+    check_device_range(*ctx, T, M->n, ldT, nrhs, 0.0, INFINITY, true, "T");
+    std::lock_guard<std::mutex> lk(const_cast<hm_matrix*>(M)->mu);
+    Batch& B = batch_for({M}, nrhs, ctx->stream);
+    SolveResult R = B.solve({eps}, {T}, {ldT}, sigma, *p, {J}, {ldJ}, {q}, {ldq}, ctx->stream);
+    HM_HIP(hipStreamSynchronize(ctx->stream));
+    const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    fill_info(info, R, secs, 0, (int)R.rel_res.size());
+    conv = R.converged;
+  });
+  if (st == HM_OK && !conv) {
+    ctx->last_error = "hm_solve_radiosity: tolerance not reached within max_iter";
+    return HM_ENOTCONV;
+  }
+  return st;
+}
+
+hm_status hm_solve_radiosity_batched(hm_ctx* ctx, int32_t count, const hm_matrix* const* M, const double* const* eps,
+                                     const double* const* T, double sigma, const hm_solve_params* p,
+                                     double* const* J, double* const* q, hm_solve_info* info_out) {
+  if (!ctx) {
+    set_tl_error("hm_solve_radiosity_batched: NULL ctx");
+    return HM_EINVAL;
+  }
+  bool conv = true;
+  hm_status st = guarded(ctx, [&] {
+    const auto t0 = std::chrono::steady_clock::now();
+    HM_REQUIRE(count >= 1 && M && eps && T && J, "hm_solve_radiosity_batched: bad arguments");
+    HM_REQUIRE(sigma > 0.0 && std::isfinite(sigma), "hm_solve_radiosity_batched: sigma must be > 0");
+    check_params(p);
+    std::vector<const hm_matrix*> mats(M, M + count);
+    std::vector<const double*> ev(eps, eps + count), Tv(T, T + count);
+    std::vector<double*> Jv(J, J + count), qv(count, nullptr);
+    if (q) qv.assign(q, q + count);
+    std::vector<int64_t> ld(count);
+    for (int i = 0; i < count; ++i) {
+      HM_REQUIRE(mats[i] && ev[i] && Tv[i] && Jv[i], "hm_solve_radiosity_batched: NULL entry");
+      HM_REQUIRE(mats[i]->device == ctx->device, "hm_solve_radiosity_batched: matrix on another device");
+      ld[i] = mats[i]->n;
+    }
+    std::lock_guard<std::mutex> lk(const_cast<hm_matrix*>(mats[0])->mu);
+    Batch& B = batch_for(mats, 1, ctx->stream);
+    SolveResult R = B.solve(ev, Tv, ld, sigma, *p, Jv, ld, qv, ld, ctx->stream);
+    HM_HIP(hipStreamSynchronize(ctx->stream));
+    const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    if (info_out)
+      for (int i = 0; i < count; ++i) fill_info(&info_out[i], R, secs, i, i + 1);
+    conv = R.converged;
+  });
+  if (st == HM_OK && !conv) {
+    ctx->last_error = "hm_solve_radiosity_batched: tolerance not reached within max_iter";
+    return HM_ENOTCONV;
+  }
+  return st;
+}
+
+hm_status hm_transient_run(hm_ctx* ctx, const hm_matrix* M, const double* eps, int32_t nrhs, double* T, int64_t ldT,
+                           const double* src, int64_t ldS, double sigma, const hm_transient_params* tp,
+                           const hm_solve_params* sp, double* history, hm_transient_info* info) {
+  if (!ctx) {
+    set_tl_error("hm_transient_run: NULL ctx");
+    return HM_EINVAL;
+  }
+  return guarded(ctx, [&] {
+    const auto t0 = std::chrono::steady_clock::now();
+    HM_REQUIRE(M && eps && T && src && tp, "hm_transient_run: NULL argument");
+    HM_REQUIRE(nrhs >= 1 && nrhs <= 16, "hm_transient_run: nrhs must be in 1..16");
+    HM_REQUIRE(ldT >= M->n && ldS >= M->n, "hm_transient_run: leading dimension < n");
+    HM_REQUIRE(tp->mc > 0 && tp->dt > 0 && tp->steps >= 0 && tp->max_newton >= 1 && tp->newton_rtol > 0,
+               "hm_transient_run: bad transient parameters");
+    HM_REQUIRE(sigma > 0.0 && std::isfinite(sigma), "hm_transient_run: sigma must be > 0");
+    check_params(sp);
+    check_device_range(*ctx, eps, M->n, M->n, 1, 0.0, 1.0, true, "eps");
+    check_device_range(*ctx, T, M->n, ldT, nrhs, 0.0, INFINITY, true, "T");
+    std::lock_guard<std::mutex> lk(const_cast<hm_matrix*>(M)->mu);
+    Batch& B = batch_for({M}, nrhs, ctx->stream);
+    TransientResult R = B.transient({eps}, T, ldT, src, ldS, sigma, *tp, *sp, history, ctx->stream);
+    if (info) {
+      info->steps_done = R.steps_done;
+      info->newton_total = R.newton_total;
+      info->newton_max = R.newton_max;
+      info->matvecs = R.matvecs;
+      info->max_rel_residual = R.max_rel_residual;
+      info->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    }
+  });
+}
+
+}  // extern "C"

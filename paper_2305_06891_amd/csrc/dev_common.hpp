@@ -1,0 +1,55 @@
+// Device helpers shared by the gfx950 kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace hm {
+
+using bf16_t = uint16_t;  // bfloat16 storage (upper half of an IEEE binary32)
+
+__host__ __device__ inline float bf16_to_f32(bf16_t h) {
+  union { uint32_t u; float f; } c;
+  c.u = (uint32_t)h << 16;
+  return c.f;
+}
+
+// Round-to-nearest-even conversion; NaN stays NaN.
+__host__ __device__ inline bf16_t f32_to_bf16(float f) {
+  union { uint32_t u; float f; } c;
+  c.f = f;
+  if ((c.u & 0x7f800000u) == 0x7f800000u && (c.u & 0x007fffffu)) return (bf16_t)((c.u >> 16) | 0x40);
+  uint32_t lsb = (c.u >> 16) & 1u;
+  c.u += 0x7fffu + lsb;
+  return (bf16_t)(c.u >> 16);
+}
+
+template <class T> struct Cvt;
+template <> struct Cvt<double> {
+  __device__ static double to_f64(double v) { return v; }
+  __device__ static double from_f64(double v) { return v; }
+};
+template <> struct Cvt<float> {
+  __device__ static double to_f64(float v) { return v; }
+  __device__ static float from_f64(double v) { return (float)v; }
+};
+template <> struct Cvt<bf16_t> {
+  __device__ static double to_f64(bf16_t v) { return bf16_to_f32(v); }
+  // FP64 -> FP32 -> BF16 (double rounding is harmless at BF16 precision for
+  // the magnitudes stored here; the FP32 step is exact for the result bits)
+  __device__ static bf16_t from_f64(double v) { return f32_to_bf16((float)v); }
+};
+
+// Load an element of storage type MT as the arithmetic type VT.
+template <class VT, class MT> __device__ inline VT ld_as(const MT* p) { return (VT)(*p); }
+template <> __device__ inline float ld_as<float, bf16_t>(const bf16_t* p) { return bf16_to_f32(*p); }
+template <> __device__ inline double ld_as<double, bf16_t>(const bf16_t* p) { return (double)bf16_to_f32(*p); }
+
+template <class T> __device__ inline T wave_sum(T v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+}  // namespace hm

@@ -1,0 +1,271 @@
+// Internal declarations of the hierarchical view-factor radiosity library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <memory>
+#include <mutex>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "../../include/hm.h"
+
+namespace hm {
+
+// ---------------------------------------------------------------- errors
+struct Error : std::runtime_error {
+  hm_status code;
+  Error(hm_status c, const std::string& m) : std::runtime_error(m), code(c) {}
+};
+
+[[noreturn]] inline void fail(hm_status c, const std::string& m) { throw Error(c, m); }
+
+#define HM_HIP(call)                                                                        \
+  do {                                                                                      \
+    hipError_t e_ = (call);                                                                 \
+    if (e_ != hipSuccess)                                                                   \
+      ::hm::fail(e_ == hipErrorOutOfMemory ? HM_ENOMEM : HM_EDEVICE,                        \
+                 std::string(#call) + ": " + hipGetErrorString(e_));                        \
+  } while (0)
+
+#define HM_REQUIRE(cond, msg)                   \
+  do {                                          \
+    if (!(cond)) ::hm::fail(HM_EINVAL, (msg));  \
+  } while (0)
+
+// ---------------------------------------------------------------- device memory
+// Caching device allocator: freed blocks are kept per (device, size class)
+// and handed out again, so per-call workspaces do not pay hipMalloc/hipFree.
+void* pool_alloc(size_t bytes, size_t* granted);
+void pool_free(void* p, size_t granted);
+int64_t pool_cached_bytes();
+void pool_trim();
+
+// Owning device allocation from the pool, move-only.
+class DevBuf {
+ public:
+  DevBuf() = default;
+  explicit DevBuf(size_t bytes) { alloc(bytes); }
+  ~DevBuf() { release(); }
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  DevBuf(DevBuf&& o) noexcept : p_(o.p_), n_(o.n_), g_(o.g_) { o.p_ = nullptr; o.n_ = o.g_ = 0; }
+  DevBuf& operator=(DevBuf&& o) noexcept {
+    if (this != &o) { release(); p_ = o.p_; n_ = o.n_; g_ = o.g_; o.p_ = nullptr; o.n_ = o.g_ = 0; }
+    return *this;
+  }
+  void alloc(size_t bytes) {
+    release();
+    if (bytes == 0) return;
+    p_ = pool_alloc(bytes, &g_);
+    n_ = bytes;
+  }
+  void release() {
+    if (p_) pool_free(p_, g_);
+    p_ = nullptr;
+    n_ = g_ = 0;
+  }
+  template <class T = void> T* get() const { return static_cast<T*>(p_); }
+  size_t bytes() const { return n_; }
+ private:
+  void* p_ = nullptr;
+  size_t n_ = 0, g_ = 0;
+};
+
+template <class T>
+inline void upload(DevBuf& b, const std::vector<T>& v, hipStream_t s) {
+  b.alloc(v.size() * sizeof(T) + (v.empty() ? 0 : 0));
+  if (!v.empty()) HM_HIP(hipMemcpyAsync(b.get(), v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s));
+}
+
+inline size_t dtype_size(hm_dtype t) { return t == HM_F64 ? 8 : (t == HM_F32 ? 4 : 2); }
+
+// ---------------------------------------------------------------- context
+}  // namespace hm
+
+struct hm_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  std::string last_error;
+};
+
+namespace hm {
+
+// ---------------------------------------------------------------- tree (host)
+struct ClusterNode {
+  int32_t begin, end;   // permuted positions [begin, end)
+  double lo[3], hi[3];  // bounding box of the centroids
+  int32_t child[2];     // -1 for a leaf
+  int32_t level;
+};
+
+struct BlockRef {
+  int32_t rb, re, cb, ce;  // rows [rb, re) x cols [cb, ce), permuted positions
+};
+
+}  // namespace hm
+
+struct hm_tree {
+  int64_t n = 0;
+  hm_tree_params params{};
+  std::vector<double> c, nrm, area;     // original order (copied)
+  std::vector<int32_t> perm;            // perm[k] = original index at position k
+  std::vector<hm::ClusterNode> nodes;   // nodes[0] = root
+  std::vector<int32_t> leaves;          // node indices of the leaves, in order
+  std::vector<hm::BlockRef> dense, lowrank;
+};
+
+namespace hm {
+
+void build_tree(hm_tree& t);  // fills perm, nodes, leaves, dense, lowrank from c, params
+
+// ---------------------------------------------------------------- matvec plan
+// Phase 1 item: partial t = V_b^T x over rows [r0, r0+nr) of V_b and rank
+// columns [l0, l0+nl).
+struct P1Item {
+  int64_t v_off;    // element offset of V_b (column-major n_b x k_b)
+  int32_t ld;       // n_b
+  int32_t r0, nr;
+  int32_t l0, nl;
+  int32_t xrow;     // permuted x row of the chunk's first row
+  int32_t trow;     // t index of rank column l0
+  int32_t part;     // first partial slot of the (block, column group); -1 if single
+  int32_t pidx, nparts;
+  int32_t counter;
+  int32_t pad;
+};
+
+// Phase 2 item: rows [row0, row0+m) (m <= 64) times a run of segments.
+struct P2Item {
+  int32_t row0, m;
+  int32_t seg0, nseg;
+  int32_t part, pidx, nparts, counter;
+};
+
+// One segment: columns of a dense block or of a U factor, restricted to the
+// rows of a tile; column c of the segment starts at arena + off + c*ld.
+struct Seg {
+  int64_t off;
+  int32_t ld;
+  int32_t w;
+  int32_t src;   // >= 0: x row src + c; < 0: t index (~src) + c
+  int32_t kind;  // 0: dense arena, 1: U arena
+};
+
+constexpr int KG = 8;        // rank columns per phase-1 item
+constexpr int P1_RCH = 2048; // rows per phase-1 item
+constexpr int TILE = 64;     // rows per phase-2 tile (one wave, lane = row)
+
+struct Plan {
+  std::vector<P1Item> p1;
+  std::vector<int32_t> p1_task;  // item begin per task, size ntasks + 1
+  std::vector<P2Item> p2;
+  std::vector<int32_t> p2_task;
+  std::vector<Seg> segs;
+  int32_t n_p1_parts = 0, n_p2_parts = 0;
+  int32_t n_p1_counters = 0, n_p2_counters = 0;
+  DevBuf d_p1, d_p1_task, d_p2, d_p2_task, d_segs;
+};
+
+// Device descriptor of one slot of a batched product.
+struct SlotDev {
+  const P1Item* p1;
+  const int32_t* p1_task;
+  const P2Item* p2;
+  const int32_t* p2_task;
+  const Seg* segs;
+  const void* dense;
+  const void* U;
+  const void* V;
+  unsigned* cnt1;
+  unsigned* cnt2;
+  void* part1;
+  void* part2;
+  void* t;
+  int64_t ldt;
+  int64_t xoff;
+  int32_t p1_task_begin, p2_task_begin;
+  int32_t n, slot;
+};
+
+}  // namespace hm
+
+struct hm_matrix {
+  uint64_t id = 0;  // unique per process, keys cached batches
+  int device = 0;
+  int64_t n = 0;
+  hm_dtype dense_dtype = HM_F32, lr_dtype = HM_F32;
+  bool has_hi = false;  // FP32 copies of BF16 factors
+  std::vector<int32_t> perm;
+  hm::DevBuf d_perm;                         // int32 perm
+  hm::DevBuf dense, U, V, U_hi, V_hi;        // arenas
+  int64_t dense_entries = 0, lr_entries = 0, Ktot = 0;
+  int64_t n_dense_blocks = 0, n_lr_blocks = 0, n_fallback = 0, rank_sum = 0;
+  int32_t max_rank = 0;
+  hm::Plan plan;
+  // cached per-(ctx) compositions and the flux helper g, keyed by eps
+  std::mutex mu;
+  std::shared_ptr<void> cache;
+  int64_t bytes_device() const;
+};
+
+namespace hm {
+
+// ---------------------------------------------------------------- batched product
+// A set of matrices laid out one after another in a combined row space.
+struct Composition {
+  int nr = 1;                 // right-hand sides per row
+  int vec_bytes = 8;          // 8: FP64 vectors, 4: FP32
+  std::vector<const hm_matrix*> mats;
+  std::vector<int64_t> xoff;  // row offset per slot
+  int64_t N = 0;              // total rows
+  int32_t p1_tasks = 0, p2_tasks = 0;
+  std::vector<SlotDev> slots_lo, slots_hi;  // hi: FP32 copies of BF16 factors
+  DevBuf d_slots_lo, d_slots_hi;
+  DevBuf t, part1, part2, cnt1, cnt2;
+  int64_t bytes_lo = 0, bytes_hi = 0;     // algorithmic matrix bytes per product
+};
+
+void build_plan(hm_matrix& M, const std::vector<struct LrInfo>& lr, const std::vector<struct DnInfo>& dn,
+                const hm_tree& t, hipStream_t s);
+
+std::unique_ptr<Composition> make_composition(const std::vector<const hm_matrix*>& mats, int nr,
+                                              int vec_bytes, hipStream_t s);
+
+// y = epilogue(F x) on every active slot of a composition.
+// Epilogue per row i, column j:  y = a_acc * w_i * (F x)_i + a_x * x_i + a_z * z_i
+// (w = rowscale, 1 when NULL; z may be NULL when a_z == 0).
+struct Epilogue {
+  const void* rowscale = nullptr;
+  double a_acc = 1.0, a_x = 0.0, a_z = 0.0;
+  const void* z = nullptr;
+  int64_t ldz = 0;
+};
+
+// nrr: right-hand sides actually present (<= C.nr, the padded width).
+// vb: vector element bytes (8: FP64, 4: FP32).
+void launch_matvec(const Composition& C, int nrr, int vb, bool hi, const void* X, int64_t ldx, void* Y, int64_t ldy,
+                   const Epilogue& ep, const int* slot_active, hipStream_t s);
+
+inline int pad_width(int nrhs) { return nrhs <= 1 ? 1 : nrhs <= 2 ? 2 : nrhs <= 4 ? 4 : nrhs <= 8 ? 8 : 16; }
+int64_t matrix_bytes(const hm_matrix& M, bool hi);
+
+struct LrInfo {
+  BlockRef b;
+  int32_t k;
+  int64_t u_off, v_off;  // element offsets in the U / V arenas
+};
+struct DnInfo {
+  BlockRef b;
+  int64_t off;           // element offset in the dense arena (column-major m x n)
+};
+
+// ---------------------------------------------------------------- misc helpers
+const char* tl_error();
+void set_tl_error(const std::string& m);
+
+}  // namespace hm

@@ -1,0 +1,422 @@
+// Batched restarted GMRES (classical Gram-Schmidt with one re-orthogonalisation)
+// for the radiosity system (I - diag(1 - eps) F) J = b of eq. (11).
+// All systems of a batch advance in lockstep; a system leaves the cycle as
+// soon as its residual estimate meets the tolerance, and an H-matrix slot is
+// skipped once none of its systems is active.  Dot products and norms are
+// accumulated in FP64 and reduced in a fixed order.
+#include <algorithm>
+#include <cmath>
+
+#include "dev_common.hpp"
+#include "krylov.hpp"
+
+namespace hm {
+
+void SysSet::build(const Composition& C, const std::vector<std::vector<int>>& cols_per_slot, hipStream_t s) {
+  sys.clear();
+  chunks.clear();
+  nparts = 0;
+  for (size_t q = 0; q < C.mats.size(); ++q) {
+    for (int col : cols_per_slot[q]) {
+      SysDev d{C.xoff[q], (int32_t)C.mats[q]->n, col, (int32_t)q, 0};
+      const int32_t sid = (int32_t)sys.size();
+      sys.push_back(d);
+      const int32_t nch = (int32_t)((d.n + GS_ROWS - 1) / GS_ROWS);
+      for (int32_t c = 0; c < nch; ++c) {
+        const int32_t r0 = (int32_t)((int64_t)d.n * c / nch);
+        const int32_t r1 = (int32_t)((int64_t)d.n * (c + 1) / nch);
+        chunks.push_back(ChunkDev{sid, r0, r1 - r0, nparts, c, nch});
+      }
+      nparts += nch;
+    }
+  }
+  upload(d_sys, sys, s);
+  upload(d_chunks, chunks, s);
+}
+
+void Krylov::init(const Composition& Cm, SysSet& Ss, int vec_bytes, int restart, hipStream_t s) {
+  HM_REQUIRE(restart >= 1 && restart <= MAXM, "gmres: restart must be in 1..64");
+  C = &Cm;
+  S = &Ss;
+  vb = vec_bytes;
+  m = restart;
+  ld = Cm.N;
+  blk = ld * Cm.nr;
+  const int ns = Ss.size();
+  basis.alloc((size_t)(m + 1) * blk * vb);
+  w.alloc((size_t)blk * vb);
+  r.alloc((size_t)blk * vb);
+  H.alloc((size_t)ns * MAXM * (MAXM + 1) * 8);
+  cs.alloc((size_t)ns * MAXM * 8);
+  sn.alloc((size_t)ns * MAXM * 8);
+  g.alloc((size_t)ns * (MAXM + 1) * 8);
+  hA.alloc((size_t)ns * (MAXM + 1) * 8);
+  hB.alloc((size_t)ns * (MAXM + 1) * 8);
+  hn.alloc((size_t)ns * 8);
+  beta.alloc((size_t)ns * 8);
+  bnorm.alloc((size_t)ns * 8);
+  tol.alloc((size_t)ns * 8);
+  act.alloc((size_t)ns * 4);
+  steps.alloc((size_t)ns * 4);
+  slot_cnt.alloc(std::max<size_t>(1, Cm.mats.size()) * 4);
+  part.alloc((size_t)std::max(1, Ss.nparts) * (MAXM + 1) * 8);
+  cnt.alloc((size_t)ns * 4);
+  HM_HIP(hipMemsetAsync(cnt.get(), 0, cnt.bytes(), s));
+  HM_HIP(hipMemsetAsync(basis.get(), 0, basis.bytes(), s));
+  HM_HIP(hipMemsetAsync(w.get(), 0, w.bytes(), s));
+  HM_HIP(hipMemsetAsync(r.get(), 0, r.bytes(), s));
+}
+
+// ------------------------------------------------------------------ kernels
+struct GsArgs {
+  const SysDev* sys;
+  const ChunkDev* chunks;
+  int mode;        // 0 dots, 1 update(hA)+dots, 2 update(hB)+norm+Givens, 3 norm -> beta
+  int j;           // Arnoldi step
+  void* w;         // vector block being orthogonalised / normed
+  const void* basis;
+  int64_t ld, blk;
+  double* hA;
+  double* hB;
+  double* H;
+  double* cs;
+  double* sn;
+  double* g;
+  double* hn;
+  double* beta;
+  const double* tol;
+  int* act;
+  int* steps;
+  int* slot_cnt;
+  double* part;
+  unsigned* cnt;
+};
+
+template <class VT>
+__global__ __launch_bounds__(GS_T) void k_gs(GsArgs a) {
+  __shared__ double coef[MAXM + 1];
+  __shared__ double red[GS_T / 64][MAXM + 2];
+  __shared__ int last;
+  const ChunkDev c = a.chunks[blockIdx.x];
+  const int s = c.sys;
+  if (a.mode != 3 && !a.act[s]) return;
+  const SysDev sy = a.sys[s];
+  const int64_t base = (int64_t)sy.col * a.ld + sy.row0 + c.r0;
+  VT* w = (VT*)a.w + base;
+  const VT* Vb = (const VT*)a.basis + base;
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  const int L = (a.mode <= 1) ? a.j + 1 : 0;
+  if (a.mode == 1 || a.mode == 2) {
+    const double* src = a.mode == 1 ? a.hA : a.hB;
+    for (int l = tid; l <= a.j; l += GS_T) coef[l] = src[(int64_t)s * (MAXM + 1) + l];
+    __syncthreads();
+  }
+  double wv[GS_RPT];
+#pragma unroll
+  for (int q = 0; q < GS_RPT; ++q) {
+    const int r = tid + q * GS_T;
+    wv[q] = r < c.nr ? (double)w[r] : 0.0;
+  }
+  if (a.mode == 1 || a.mode == 2) {
+    for (int l = 0; l <= a.j; ++l) {
+      const double cl = coef[l];
+      const VT* v = Vb + (int64_t)l * a.blk;
+#pragma unroll
+      for (int q = 0; q < GS_RPT; ++q) {
+        const int r = tid + q * GS_T;
+        if (r < c.nr) wv[q] -= cl * (double)v[r];
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < GS_RPT; ++q) {
+      const int r = tid + q * GS_T;
+      if (r < c.nr) {
+        w[r] = (VT)wv[q];
+        wv[q] = (double)(VT)wv[q];  // continue with the stored value
+      }
+    }
+  }
+  // partial sums: L dot products, or one squared norm
+  const int nv = L > 0 ? L : 1;
+  for (int l = 0; l < nv; ++l) {
+    double d = 0.0;
+    if (L > 0) {
+      const VT* v = Vb + (int64_t)l * a.blk;
+#pragma unroll
+      for (int q = 0; q < GS_RPT; ++q) {
+        const int r = tid + q * GS_T;
+        if (r < c.nr) d += (double)v[r] * wv[q];
+      }
+    } else {
+#pragma unroll
+      for (int q = 0; q < GS_RPT; ++q) d += wv[q] * wv[q];
+    }
+    d = wave_sum(d);
+    if (lane == 0) red[wid][l] = d;
+  }
+  __syncthreads();
+  double* P0 = a.part + (int64_t)c.part * (MAXM + 1);
+  if (tid < nv) {
+    double t = red[0][tid];
+    for (int q = 1; q < GS_T / 64; ++q) t += red[q][tid];
+    P0[(int64_t)c.pidx * (MAXM + 1) + tid] = t;
+  }
+  if (c.nparts > 1) {
+    __threadfence();
+    __syncthreads();
+    if (tid == 0) last = atomicAdd(&a.cnt[s], 1u) == (unsigned)(c.nparts - 1);
+    __syncthreads();
+    if (!last) return;
+    __threadfence();
+  } else {
+    __syncthreads();
+  }
+  // last chunk of the system: fixed-order sum of the partials
+  if (tid < nv) {
+    double t = 0.0;
+    for (int p = 0; p < c.nparts; ++p) t += P0[(int64_t)p * (MAXM + 1) + tid];
+    red[0][tid] = t;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    if (c.nparts > 1) a.cnt[s] = 0u;
+    double* hs = a.mode == 0 ? a.hA : a.hB;
+    if (a.mode <= 1) {
+      for (int l = 0; l < L; ++l) hs[(int64_t)s * (MAXM + 1) + l] = red[0][l];
+    } else if (a.mode == 3) {
+      a.beta[s] = sqrt(red[0][0]);
+    } else {
+      // finish column j of the Hessenberg matrix and its Givens rotation
+      const int j = a.j;
+      const double hnrm = sqrt(red[0][0]);
+      double col[MAXM + 1];
+      for (int i = 0; i <= j; ++i) col[i] = a.hA[(int64_t)s * (MAXM + 1) + i] + a.hB[(int64_t)s * (MAXM + 1) + i];
+      col[j + 1] = hnrm;
+      double* cs = a.cs + (int64_t)s * MAXM;
+      double* sn = a.sn + (int64_t)s * MAXM;
+      for (int i = 0; i < j; ++i) {
+        const double t0 = cs[i] * col[i] + sn[i] * col[i + 1];
+        col[i + 1] = -sn[i] * col[i] + cs[i] * col[i + 1];
+        col[i] = t0;
+      }
+      const double x0 = col[j], x1 = col[j + 1];
+      const double rr = hypot(x0, x1);
+      double cj = 1.0, sj = 0.0;
+      if (rr > 0.0) {
+        cj = x0 / rr;
+        sj = x1 / rr;
+      }
+      col[j] = rr;
+      col[j + 1] = 0.0;
+      cs[j] = cj;
+      sn[j] = sj;
+      double* gs = a.g + (int64_t)s * (MAXM + 1);
+      const double gj = gs[j];
+      gs[j] = cj * gj;
+      gs[j + 1] = -sj * gj;
+      double* Hc = a.H + ((int64_t)s * MAXM + j) * (MAXM + 1);
+      for (int i = 0; i <= j + 1; ++i) Hc[i] = col[i];
+      a.steps[s] = j + 1;
+      a.hn[s] = hnrm;
+      const double res = fabs(gs[j + 1]);
+      if (res <= a.tol[s] || !(hnrm > 0.0) || rr == 0.0) {
+        a.act[s] = 0;
+        atomicSub(&a.slot_cnt[sy.slot], 1);
+      }
+    }
+  }
+}
+
+// dst = src / div[s] on the active systems (div = hn or beta).
+template <class VT>
+__global__ __launch_bounds__(GS_T) void k_scale(const SysDev* __restrict__ sys, const ChunkDev* __restrict__ chunks,
+                                                const int* __restrict__ act, const double* __restrict__ div,
+                                                const VT* __restrict__ src, VT* __restrict__ dst, int64_t ld) {
+  const ChunkDev c = chunks[blockIdx.x];
+  if (!act[c.sys]) return;
+  const SysDev sy = sys[c.sys];
+  const int64_t base = (int64_t)sy.col * ld + sy.row0 + c.r0;
+  const double inv = 1.0 / div[c.sys];
+  for (int r = threadIdx.x; r < c.nr; r += GS_T) dst[base + r] = (VT)((double)src[base + r] * inv);
+}
+
+// x += V y with H(0:k,0:k) y = g(0:k) (k = steps of the system).
+template <class VT>
+__global__ __launch_bounds__(GS_T) void k_xupdate(const SysDev* __restrict__ sys, const ChunkDev* __restrict__ chunks,
+                                                  const int* __restrict__ steps, const double* __restrict__ H,
+                                                  const double* __restrict__ g, const VT* __restrict__ basis,
+                                                  int64_t ld, int64_t blk, VT* __restrict__ x) {
+  __shared__ double y[MAXM];
+  const ChunkDev c = chunks[blockIdx.x];
+  const int s = c.sys;
+  const int k = steps[s];
+  if (k <= 0) return;
+  if (threadIdx.x == 0) {
+    const double* gs = g + (int64_t)s * (MAXM + 1);
+    for (int i = k - 1; i >= 0; --i) {
+      double t = gs[i];
+      for (int l = i + 1; l < k; ++l) t -= H[((int64_t)s * MAXM + l) * (MAXM + 1) + i] * y[l];
+      y[i] = t / H[((int64_t)s * MAXM + i) * (MAXM + 1) + i];
+    }
+  }
+  __syncthreads();
+  const SysDev sy = sys[s];
+  const int64_t base = (int64_t)sy.col * ld + sy.row0 + c.r0;
+  for (int r = threadIdx.x; r < c.nr; r += GS_T) {
+    double acc = (double)x[base + r];
+    for (int l = 0; l < k; ++l) acc += (double)basis[(int64_t)l * blk + base + r] * y[l];
+    x[base + r] = (VT)acc;
+  }
+}
+
+// ------------------------------------------------------------------ driver
+namespace {
+
+GsArgs gs_args(Krylov& K, int mode, int j, void* wvec) {
+  GsArgs a;
+  a.sys = K.S->d_sys.get<SysDev>();
+  a.chunks = K.S->d_chunks.get<ChunkDev>();
+  a.mode = mode;
+  a.j = j;
+  a.w = wvec;
+  a.basis = K.basis.get();
+  a.ld = K.ld;
+  a.blk = K.blk;
+  a.hA = K.hA.get<double>();
+  a.hB = K.hB.get<double>();
+  a.H = K.H.get<double>();
+  a.cs = K.cs.get<double>();
+  a.sn = K.sn.get<double>();
+  a.g = K.g.get<double>();
+  a.hn = K.hn.get<double>();
+  a.beta = K.beta.get<double>();
+  a.tol = K.tol.get<double>();
+  a.act = K.act.get<int>();
+  a.steps = K.steps.get<int>();
+  a.slot_cnt = K.slot_cnt.get<int>();
+  a.part = K.part.get<double>();
+  a.cnt = K.cnt.get<unsigned>();
+  return a;
+}
+
+template <class VT>
+void run_gs(Krylov& K, int mode, int j, void* wvec, hipStream_t s) {
+  const unsigned nb = (unsigned)K.S->chunks.size();
+  if (nb == 0) return;
+  hipLaunchKernelGGL(k_gs<VT>, dim3(nb), dim3(GS_T), 0, s, gs_args(K, mode, j, wvec));
+  HM_HIP(hipGetLastError());
+}
+
+template <class VT>
+void run_scale(Krylov& K, const double* div, const void* src, void* dst, hipStream_t s) {
+  const unsigned nb = (unsigned)K.S->chunks.size();
+  hipLaunchKernelGGL(k_scale<VT>, dim3(nb), dim3(GS_T), 0, s, K.S->d_sys.get<SysDev>(),
+                     K.S->d_chunks.get<ChunkDev>(), K.act.get<int>(), div, (const VT*)src, (VT*)dst, K.ld);
+  HM_HIP(hipGetLastError());
+}
+
+template <class VT>
+GmresStats gmres_t(Krylov& K, bool hi, const void* omeps, const void* b, void* x, double rtol, int max_iter,
+                   hipStream_t s) {
+  const Composition& C = *K.C;
+  const int ns = K.S->size();
+  const int nslots = (int)C.mats.size();
+  GmresStats st;
+  st.rel_res.assign(ns, 0.0);
+  const int64_t mbytes = hi ? C.bytes_hi : C.bytes_lo;
+  // |b| per system
+  std::vector<double> bn(ns), beta(ns), tolv(ns);
+  run_gs<VT>(K, 3, 0, const_cast<void*>(b), s);
+  HM_HIP(hipMemcpyAsync(bn.data(), K.beta.get(), ns * 8, hipMemcpyDeviceToHost, s));
+  HM_HIP(hipStreamSynchronize(s));
+  for (int q = 0; q < ns; ++q) tolv[q] = rtol * bn[q];
+  HM_HIP(hipMemcpyAsync(K.tol.get(), tolv.data(), ns * 8, hipMemcpyHostToDevice, s));
+  HM_HIP(hipMemcpyAsync(K.bnorm.get(), bn.data(), ns * 8, hipMemcpyHostToDevice, s));
+  Epilogue res_ep;  // r = b - (x - (1-eps) F x) = b - x + (1-eps) F x
+  res_ep.rowscale = omeps;
+  res_ep.a_acc = 1.0;
+  res_ep.a_x = -1.0;
+  res_ep.a_z = 1.0;
+  res_ep.z = b;
+  res_ep.ldz = K.ld;
+  Epilogue op_ep;   // w = v - (1-eps) F v
+  op_ep.rowscale = omeps;
+  op_ep.a_acc = -1.0;
+  op_ep.a_x = 1.0;
+  const int nrr = C.nr;
+  std::vector<int> act(ns), cnt(nslots);
+  std::vector<double> g0((size_t)ns * (MAXM + 1), 0.0);
+  int iters = 0;
+  for (;;) {
+    // true residual and its norm
+    launch_matvec(C, nrr, K.vb, hi, x, K.ld, K.basis.get(), K.ld, res_ep, nullptr, s);
+    st.matvecs++;
+    st.bytes += mbytes;
+    run_gs<VT>(K, 3, 0, K.basis.get(), s);
+    HM_HIP(hipMemcpyAsync(beta.data(), K.beta.get(), ns * 8, hipMemcpyDeviceToHost, s));
+    HM_HIP(hipStreamSynchronize(s));
+    int nact = 0;
+    std::fill(cnt.begin(), cnt.end(), 0);
+    for (int q = 0; q < ns; ++q) {
+      st.rel_res[q] = bn[q] > 0 ? beta[q] / bn[q] : 0.0;
+      act[q] = beta[q] > tolv[q] && std::isfinite(beta[q]) ? 1 : 0;
+      if (act[q]) {
+        ++nact;
+        cnt[K.S->sys[q].slot]++;
+      }
+      g0[(size_t)q * (MAXM + 1)] = beta[q];
+    }
+    if (nact == 0) break;
+    if (iters >= max_iter) {
+      st.converged = false;
+      break;
+    }
+    HM_HIP(hipMemcpyAsync(K.act.get(), act.data(), ns * 4, hipMemcpyHostToDevice, s));
+    HM_HIP(hipMemcpyAsync(K.slot_cnt.get(), cnt.data(), nslots * 4, hipMemcpyHostToDevice, s));
+    HM_HIP(hipMemcpyAsync(K.g.get(), g0.data(), g0.size() * 8, hipMemcpyHostToDevice, s));
+    HM_HIP(hipMemsetAsync(K.steps.get(), 0, ns * 4, s));
+    run_scale<VT>(K, K.beta.get<double>(), K.basis.get(), K.basis.get(), s);
+    for (int j = 0; j < K.m && iters < max_iter; ++j) {
+      char* vj = K.basis.get<char>() + (size_t)j * K.blk * K.vb;
+      char* vj1 = vj + (size_t)K.blk * K.vb;
+      launch_matvec(C, nrr, K.vb, hi, vj, K.ld, K.w.get(), K.ld, op_ep, K.slot_cnt.get<int>(), s);
+      st.matvecs++;
+      st.bytes += mbytes;
+      run_gs<VT>(K, 0, j, K.w.get(), s);
+      run_gs<VT>(K, 1, j, K.w.get(), s);
+      run_gs<VT>(K, 2, j, K.w.get(), s);
+      run_scale<VT>(K, K.hn.get<double>(), K.w.get(), vj1, s);
+      ++iters;
+      HM_HIP(hipMemcpyAsync(cnt.data(), K.slot_cnt.get(), nslots * 4, hipMemcpyDeviceToHost, s));
+      HM_HIP(hipStreamSynchronize(s));
+      int left = 0;
+      for (int v : cnt) left += v;
+      if (left == 0) break;
+    }
+    const unsigned nb = (unsigned)K.S->chunks.size();
+    hipLaunchKernelGGL(k_xupdate<VT>, dim3(nb), dim3(GS_T), 0, s, K.S->d_sys.get<SysDev>(),
+                       K.S->d_chunks.get<ChunkDev>(), K.steps.get<int>(), K.H.get<double>(), K.g.get<double>(),
+                       (const VT*)K.basis.get(), K.ld, K.blk, (VT*)x);
+    HM_HIP(hipGetLastError());
+  }
+  st.iters = iters;
+  return st;
+}
+
+}  // namespace
+
+GmresStats gmres(Krylov& K, bool hi, const void* omeps, const void* b, void* x, double rtol, int max_iter,
+                 hipStream_t s) {
+  if (K.vb == 8) return gmres_t<double>(K, hi, omeps, b, x, rtol, max_iter, s);
+  return gmres_t<float>(K, hi, omeps, b, x, rtol, max_iter, s);
+}
+
+void block_norms(Krylov& K, const void* v, std::vector<double>& out, hipStream_t s) {
+  if (K.vb == 8) run_gs<double>(K, 3, 0, const_cast<void*>(v), s);
+  else run_gs<float>(K, 3, 0, const_cast<void*>(v), s);
+  out.resize(K.S->size());
+  HM_HIP(hipMemcpyAsync(out.data(), K.beta.get(), out.size() * 8, hipMemcpyDeviceToHost, s));
+  HM_HIP(hipStreamSynchronize(s));
+}
+
+}  // namespace hm

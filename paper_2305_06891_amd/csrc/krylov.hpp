@@ -1,0 +1,65 @@
+// Batched restarted GMRES on gfx950 for the radiosity system
+// (I - diag(1 - eps) F) J = b, with F applied as an H-matrix product.
+#pragma once
+
+#include "hm_internal.hpp"
+
+namespace hm {
+
+constexpr int MAXM = 64;       // largest restart length
+constexpr int GS_T = 256;      // threads per reduction chunk
+constexpr int GS_RPT = 8;      // rows per thread
+constexpr int GS_ROWS = GS_T * GS_RPT;
+
+// One independent linear system: rows [row0, row0+n) of column col of the
+// combined N x width vector block, belonging to slot `slot`.
+struct SysDev {
+  int64_t row0;
+  int32_t n, col, slot, pad;
+};
+
+struct ChunkDev {
+  int32_t sys, r0, nr, part, pidx, nparts;
+};
+
+// Systems of a composition plus their reduction chunks (host + device).
+struct SysSet {
+  std::vector<SysDev> sys;
+  std::vector<ChunkDev> chunks;
+  int32_t nparts = 0;
+  DevBuf d_sys, d_chunks;
+  void build(const Composition& C, const std::vector<std::vector<int>>& cols_per_slot, hipStream_t s);
+  int size() const { return (int)sys.size(); }
+};
+
+struct GmresStats {
+  int iters = 0;       // Arnoldi steps (max over systems)
+  int matvecs = 0;
+  int64_t bytes = 0;
+  std::vector<double> rel_res;  // final |b - Cx| / |b| per system
+  bool converged = true;
+};
+
+// Workspace of the Krylov iteration for one composition and vector type.
+struct Krylov {
+  const Composition* C = nullptr;
+  SysSet* S = nullptr;
+  int vb = 8;           // vector element bytes
+  int m = 30;
+  int64_t ld = 0;       // leading dimension of vector blocks (= C->N)
+  int64_t blk = 0;      // elements per vector block (ld * width)
+  DevBuf basis, w, r;   // basis: (m+1) blocks
+  DevBuf H, cs, sn, g, hA, hB, hn, beta, bnorm, tol, act, steps, slot_cnt, part, cnt;
+  void init(const Composition& C, SysSet& S, int vec_bytes, int restart, hipStream_t s);
+};
+
+// Solve C x = b for every system of S.  b, x: vector blocks (ld = C.N) of
+// the Krylov vector type; x holds the initial guess on entry.  omeps: per
+// row (1 - eps) in the vector type.  hi selects the FP32 factor copy.
+GmresStats gmres(Krylov& K, bool hi, const void* omeps, const void* b, void* x, double rtol, int max_iter,
+                 hipStream_t s);
+
+// Per-system 2-norms of a vector block (FP64 accumulation).
+void block_norms(Krylov& K, const void* v, std::vector<double>& out, hipStream_t s);
+
+}  // namespace hm

@@ -1,0 +1,586 @@
+// Serving loop: radiosity solves of registered cavities, continuously
+// batched.  A background host thread owns the device work.  Requests are
+// admitted while the resident H-matrices and the solve buffers fit the HBM
+// budget; all admitted requests advance together, one refinement round at a
+// time (FP64 residual with the most accurate stored factors, then an inner
+// FP32 GMRES with the stored factors), sharing every H-matrix product and
+// every Krylov kernel launch; requests that arrive meanwhile join at the
+// next round, and converged requests leave with their radiosity and flux.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <condition_variable>
+#include <deque>
+#include <map>
+#include <thread>
+
+#include "dev_common.hpp"
+#include "solve.hpp"
+
+namespace hm {
+
+hm_matrix* assemble(hm_ctx& ctx, const hm_tree& t, const hm_assembly_params& p);
+int64_t matrix_bytes(const hm_matrix& M, bool hi);
+
+namespace {
+
+double now_s() {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+template <class VT>
+__global__ void k_srv_gather(const int32_t* __restrict__ perm, const double* __restrict__ in, int64_t ldi,
+                             VT* __restrict__ out, int64_t ldo, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = blockIdx.y;
+  if (i < n) out[i + j * ldo] = (VT)in[perm[i] + j * ldi];
+}
+
+__global__ void k_srv_scatter(const int32_t* __restrict__ perm, const double* __restrict__ in, int64_t ldi,
+                              double* __restrict__ out, int64_t ldo, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = blockIdx.y;
+  if (i < n) out[perm[i] + j * ldo] = in[i + j * ldi];
+}
+
+// b = sigma eps T^4 (permuted)
+__global__ void k_srv_rhs(const double* __restrict__ eps, const double* __restrict__ T, double* __restrict__ b,
+                          int64_t n, double sigma) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = blockIdx.y;
+  if (i < n) {
+    const double t = T[i + j * n];
+    const double t2 = t * t;
+    b[i + j * n] = sigma * eps[i] * (t2 * t2);
+  }
+}
+
+__global__ void k_srv_flux(const double* __restrict__ eps, const double* __restrict__ T, const double* __restrict__ H,
+                           const double* __restrict__ g, double* __restrict__ q, int64_t n, double sigma) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = blockIdx.y;
+  if (i < n) {
+    const double t = T[i + j * n];
+    const double t2 = t * t;
+    q[i + j * n] = eps[i] * (H[i + j * n] - sigma * (t2 * t2) * g[i]);
+  }
+}
+
+template <class A, class B>
+__global__ void k_srv_cast(const A* __restrict__ a, B* __restrict__ b, int64_t n) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < n) b[k] = (B)a[k];
+}
+
+__global__ void k_srv_acc(const float* __restrict__ x, double* __restrict__ y, int64_t n) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < n) y[k] += (double)x[k];
+}
+
+dim3 g2(int64_t n, int cols) { return dim3((unsigned)((n + 255) / 256), (unsigned)cols); }
+
+}  // namespace
+
+struct SrvCavity {
+  uint64_t id = 0;
+  std::unique_ptr<hm_tree> tree;
+  std::vector<double> eps;
+  hm_assembly_params ap{};
+  hm_matrix* M = nullptr;
+  DevBuf eps_d;          // original order
+  DevBuf epsp, om64;     // permuted eps, 1 - eps
+  DevBuf om32;
+  DevBuf g;              // F C^-1 eps, permuted
+  int64_t bytes = 0;     // device bytes while resident
+  uint64_t last_use = 0;
+  int refs = 0;
+  ~SrvCavity() { delete M; }
+};
+
+struct SrvReq {
+  uint64_t ticket = 0, cid = 0;
+  int nrhs = 0;
+  int64_t n = 0;
+  std::vector<double> T;          // host, original order, n x nrhs
+  DevBuf Tp, b64, J64;            // device, permuted, n x nrhs
+  std::vector<double> J, q;       // results (host)
+  hm_status status = HM_OK;
+  bool done = false;
+  double t_submit = 0, t_done = 0;
+  int rounds = 0, inner = 0, matvecs = 0;
+  int64_t bytes = 0;
+  double rel_res = 0;
+};
+
+}  // namespace hm
+
+struct hm_server {
+  hm_server_params p{};
+  int device = 0;
+  hipStream_t stream = nullptr;
+  std::mutex mu;
+  std::condition_variable cv;
+  std::map<uint64_t, std::unique_ptr<hm::SrvCavity>> cav;
+  std::map<uint64_t, std::unique_ptr<hm::SrvReq>> req;
+  std::deque<uint64_t> queue;
+  std::vector<uint64_t> active;
+  uint64_t next_ticket = 1, clock = 0;
+  bool stop = false;
+  hm_server_stats st{};
+  std::thread worker;
+  hm_ctx ctx;  // the worker's own context (device + private stream)
+  void run();
+  void round(std::vector<hm::SrvReq*>& act);
+  bool admit_one(hm::SrvReq& r);
+  int64_t resident() const;
+};
+
+using namespace hm;
+
+int64_t hm_server::resident() const {
+  int64_t b = 0;
+  for (auto& kv : cav)
+    if (kv.second->M) b += kv.second->bytes;
+  return b;
+}
+
+// Make the request's cavity resident (evicting idle cavities, least recently
+// used first, while over budget) and allocate its vectors.  Called without
+// the lock held; the worker thread is the only one touching device state.
+bool hm_server::admit_one(SrvReq& r) {
+  SrvCavity* c;
+  {
+    std::lock_guard<std::mutex> lk(mu);
+    c = cav.at(r.cid).get();
+  }
+  const int64_t vec_bytes = r.n * r.nrhs * 8 * 3;
+  if (!c->M) {
+    // evict idle cavities until the estimate fits
+    const int64_t est = c->bytes > 0 ? c->bytes : r.n * 2500 * 4;
+    for (;;) {
+      if (resident() + est + vec_bytes <= p.hbm_budget_bytes) break;
+      SrvCavity* lru = nullptr;
+      for (auto& kv : cav)
+        if (kv.second->M && kv.second->refs == 0 && (!lru || kv.second->last_use < lru->last_use)) lru = kv.second.get();
+      if (!lru) break;
+      HM_HIP(hipStreamSynchronize(stream));
+      delete lru->M;
+      lru->M = nullptr;
+      lru->epsp.release();
+      lru->om64.release();
+      lru->om32.release();
+      lru->g.release();
+      std::lock_guard<std::mutex> lk(mu);
+      st.evictions++;
+    }
+    if (resident() + est + vec_bytes > p.hbm_budget_bytes && !active.empty()) return false;  // wait
+    c->M = assemble(ctx, *c->tree, c->ap);
+    c->M->id = 0x8000000000000000ull | c->id;
+    const int64_t n = c->M->n;
+    // permuted emissivities and g = F C^-1 eps for the flux (eq. (12))
+    c->eps_d.alloc(n * 8);
+    HM_HIP(hipMemcpyAsync(c->eps_d.get(), c->eps.data(), n * 8, hipMemcpyHostToDevice, stream));
+    c->epsp.alloc(n * 8);
+    hipLaunchKernelGGL(k_srv_gather<double>, g2(n, 1), dim3(256), 0, stream, c->M->d_perm.get<int32_t>(),
+                       c->eps_d.get<double>(), n, c->epsp.get<double>(), n, n);
+    std::vector<double> om(n);
+    for (int64_t i = 0; i < n; ++i) om[i] = 1.0 - c->eps[c->M->perm[i]];
+    std::vector<float> om32(om.begin(), om.end());
+    upload(c->om64, om, stream);
+    upload(c->om32, om32, stream);
+    {
+      Batch B({c->M}, 1, stream);
+      B.io({c->eps_d.get<double>()}, {}, 0, nullptr, stream);
+      B.gather(B.epsp.get<double>(), 1, stream);
+      B.ensure_g({c->eps_d.get<double>()}, stream);
+      c->g.alloc(n * 8);
+      HM_HIP(hipMemcpyAsync(c->g.get(), B.g.get(), n * 8, hipMemcpyDeviceToDevice, stream));
+      HM_HIP(hipStreamSynchronize(stream));
+    }
+    c->bytes = c->M->bytes_device() + n * 8 * 4;
+    std::lock_guard<std::mutex> lk(mu);
+    st.assemblies++;
+  } else {
+    std::lock_guard<std::mutex> lk(mu);
+    st.cache_hits++;
+  }
+  c->refs++;
+  c->last_use = ++clock;
+  // request vectors (permuted)
+  const int64_t n = r.n;
+  DevBuf Th(n * r.nrhs * 8);
+  HM_HIP(hipMemcpyAsync(Th.get(), r.T.data(), n * r.nrhs * 8, hipMemcpyHostToDevice, stream));
+  r.Tp.alloc(n * r.nrhs * 8);
+  r.b64.alloc(n * r.nrhs * 8);
+  r.J64.alloc(n * r.nrhs * 8);
+  hipLaunchKernelGGL(k_srv_gather<double>, g2(n, r.nrhs), dim3(256), 0, stream, c->M->d_perm.get<int32_t>(),
+                     Th.get<double>(), n, r.Tp.get<double>(), n, n);
+  hipLaunchKernelGGL(k_srv_rhs, g2(n, r.nrhs), dim3(256), 0, stream, c->epsp.get<double>(), r.Tp.get<double>(),
+                     r.b64.get<double>(), n, p.sigma);
+  HM_HIP(hipMemsetAsync(r.J64.get(), 0, n * r.nrhs * 8, stream));
+  HM_HIP(hipStreamSynchronize(stream));
+  return true;
+}
+
+// One refinement round for every active request.
+void hm_server::round(std::vector<SrvReq*>& act) {
+  hipStream_t s = stream;
+  std::vector<const hm_matrix*> mats;
+  std::vector<SrvCavity*> cs;
+  int maxr = 1;
+  for (auto* r : act) {
+    SrvCavity* c = cav.at(r->cid).get();
+    cs.push_back(c);
+    mats.push_back(c->M);
+    maxr = std::max(maxr, r->nrhs);
+  }
+  const int W = pad_width(maxr);
+  auto C = make_composition(mats, W, 8, s);
+  const int64_t N = C->N;
+  std::vector<std::vector<int>> cols(act.size());
+  for (size_t q = 0; q < act.size(); ++q)
+    for (int j = 0; j < act[q]->nrhs; ++j) cols[q].push_back(j);
+  SysSet S;
+  S.build(*C, cols, s);
+  const size_t blk = (size_t)N * W;
+  DevBuf b64(blk * 8), x64(blk * 8), r64(blk * 8), om64(N * 8), om32(N * 4), b32(blk * 4), x32(blk * 4);
+  HM_HIP(hipMemsetAsync(b64.get(), 0, blk * 8, s));
+  HM_HIP(hipMemsetAsync(x64.get(), 0, blk * 8, s));
+  for (size_t q = 0; q < act.size(); ++q) {
+    const int64_t off = C->xoff[q], n = act[q]->n;
+    HM_HIP(hipMemcpy2DAsync(b64.get<double>() + off, N * 8, act[q]->b64.get(), n * 8, n * 8, act[q]->nrhs,
+                            hipMemcpyDeviceToDevice, s));
+    HM_HIP(hipMemcpy2DAsync(x64.get<double>() + off, N * 8, act[q]->J64.get(), n * 8, n * 8, act[q]->nrhs,
+                            hipMemcpyDeviceToDevice, s));
+    HM_HIP(hipMemcpyAsync(om64.get<double>() + off, cs[q]->om64.get(), n * 8, hipMemcpyDeviceToDevice, s));
+    HM_HIP(hipMemcpyAsync(om32.get<float>() + off, cs[q]->om32.get(), n * 4, hipMemcpyDeviceToDevice, s));
+  }
+  // FP64 residual r = b - C J with the most accurate stored factors
+  Epilogue ep;
+  ep.rowscale = om64.get();
+  ep.a_acc = 1.0;
+  ep.a_x = -1.0;
+  ep.a_z = 1.0;
+  ep.z = b64.get();
+  ep.ldz = N;
+  launch_matvec(*C, W, 8, true, x64.get(), N, r64.get(), N, ep, nullptr, s);
+  Krylov K8;
+  K8.init(*C, S, 8, 1, s);
+  std::vector<double> rn, bn;
+  block_norms(K8, r64.get(), rn, s);
+  block_norms(K8, b64.get(), bn, s);
+  // per request: converged?
+  std::vector<int> fin(act.size(), 1), slot_active(act.size(), 0);
+  std::vector<double> worst(act.size(), 0.0);
+  for (int k = 0; k < S.size(); ++k) {
+    const int q = S.sys[k].slot;
+    const double rel = bn[k] > 0 ? rn[k] / bn[k] : 0.0;
+    worst[q] = std::max(worst[q], rel);
+    if (rn[k] > p.solve.rtol * bn[k]) fin[q] = 0;
+  }
+  for (size_t q = 0; q < act.size(); ++q) {
+    act[q]->matvecs++;
+    act[q]->bytes += matrix_bytes(*mats[q], true);
+    act[q]->rel_res = worst[q];
+    if (!fin[q] && act[q]->rounds >= 40) fin[q] = 1;  // give up: reported as not converged
+  }
+  // finishing requests: flux and results
+  bool any_fin = false;
+  for (size_t q = 0; q < act.size(); ++q) {
+    slot_active[q] = fin[q];
+    any_fin |= fin[q] != 0;
+  }
+  if (any_fin) {
+    DevBuf H(blk * 8), d_sa(act.size() * 4);
+    HM_HIP(hipMemcpyAsync(d_sa.get(), slot_active.data(), act.size() * 4, hipMemcpyHostToDevice, s));
+    launch_matvec(*C, W, 8, true, x64.get(), N, H.get(), N, Epilogue{}, d_sa.get<int>(), s);
+    for (size_t q = 0; q < act.size(); ++q) {
+      if (!fin[q]) continue;
+      SrvReq& r = *act[q];
+      const int64_t n = r.n, off = C->xoff[q];
+      DevBuf Hq(n * r.nrhs * 8), Jq(n * r.nrhs * 8), qq(n * r.nrhs * 8), Jo(n * r.nrhs * 8), qo(n * r.nrhs * 8);
+      HM_HIP(hipMemcpy2DAsync(Hq.get(), n * 8, H.get<double>() + off, N * 8, n * 8, r.nrhs, hipMemcpyDeviceToDevice, s));
+      HM_HIP(hipMemcpy2DAsync(Jq.get(), n * 8, x64.get<double>() + off, N * 8, n * 8, r.nrhs, hipMemcpyDeviceToDevice, s));
+      hipLaunchKernelGGL(k_srv_flux, g2(n, r.nrhs), dim3(256), 0, s, cs[q]->epsp.get<double>(), r.Tp.get<double>(),
+                         Hq.get<double>(), cs[q]->g.get<double>(), qq.get<double>(), n, p.sigma);
+      hipLaunchKernelGGL(k_srv_scatter, g2(n, r.nrhs), dim3(256), 0, s, mats[q]->d_perm.get<int32_t>(),
+                         Jq.get<double>(), n, Jo.get<double>(), n, n);
+      hipLaunchKernelGGL(k_srv_scatter, g2(n, r.nrhs), dim3(256), 0, s, mats[q]->d_perm.get<int32_t>(),
+                         qq.get<double>(), n, qo.get<double>(), n, n);
+      r.J.resize(n * r.nrhs);
+      r.q.resize(n * r.nrhs);
+      HM_HIP(hipMemcpyAsync(r.J.data(), Jo.get(), n * r.nrhs * 8, hipMemcpyDeviceToHost, s));
+      HM_HIP(hipMemcpyAsync(r.q.data(), qo.get(), n * r.nrhs * 8, hipMemcpyDeviceToHost, s));
+      HM_HIP(hipStreamSynchronize(s));
+      r.matvecs++;
+      r.bytes += matrix_bytes(*mats[q], true);
+    }
+  }
+  // continuing requests: inner FP32 GMRES with the stored factors on C d = r
+  bool any_cont = false;
+  for (size_t q = 0; q < act.size(); ++q) any_cont |= !fin[q];
+  if (any_cont) {
+    hipLaunchKernelGGL((k_srv_cast<double, float>), dim3((unsigned)((blk + 255) / 256)), dim3(256), 0, s,
+                       r64.get<double>(), b32.get<float>(), (int64_t)blk);
+    for (int k = 0; k < S.size(); ++k) {
+      const int q = S.sys[k].slot;
+      if (fin[q] || rn[k] <= p.solve.rtol * bn[k]) {
+        const SysDev& sd = S.sys[k];
+        HM_HIP(hipMemsetAsync(b32.get<float>() + sd.col * N + sd.row0, 0, (size_t)sd.n * 4, s));
+      }
+    }
+    HM_HIP(hipMemcpyAsync(x32.get(), b32.get(), blk * 4, hipMemcpyDeviceToDevice, s));
+    Krylov K4;
+    K4.init(*C, S, 4, p.solve.restart, s);
+    const double inner = p.solve.mixed_precision ? p.solve.ir_inner_rtol : std::min(p.solve.ir_inner_rtol, 1e-5);
+    GmresStats gs = gmres(K4, false, om32.get(), b32.get(), x32.get(), inner, p.solve.max_iter, s);
+    hipLaunchKernelGGL(k_srv_acc, dim3((unsigned)((blk + 255) / 256)), dim3(256), 0, s, x32.get<float>(),
+                       x64.get<double>(), (int64_t)blk);
+    for (size_t q = 0; q < act.size(); ++q) {
+      if (fin[q]) continue;
+      SrvReq& r = *act[q];
+      HM_HIP(hipMemcpy2DAsync(r.J64.get(), r.n * 8, x64.get<double>() + C->xoff[q], N * 8, r.n * 8, r.nrhs,
+                              hipMemcpyDeviceToDevice, s));
+      r.inner += gs.iters;
+      r.matvecs += gs.matvecs;
+      r.bytes += gs.bytes / (int64_t)act.size();
+    }
+  }
+  HM_HIP(hipStreamSynchronize(s));
+  // retire
+  const double t = now_s();
+  std::lock_guard<std::mutex> lk(mu);
+  st.rounds++;
+  for (size_t q = 0; q < act.size(); ++q) {
+    SrvReq& r = *act[q];
+    r.rounds++;
+    if (!fin[q]) continue;
+    r.done = true;
+    r.t_done = t;
+    r.status = worst[q] <= p.solve.rtol ? HM_OK : HM_ENOTCONV;
+    r.Tp.release();
+    r.b64.release();
+    r.J64.release();
+    cs[q]->refs--;
+    st.completed++;
+  }
+}
+
+void hm_server::run() {
+  (void)hipSetDevice(device);
+  for (;;) {
+    std::vector<uint64_t> pending;
+    {
+      std::unique_lock<std::mutex> lk(mu);
+      cv.wait(lk, [&] { return stop || !queue.empty() || !active.empty(); });
+      if (stop && active.empty()) return;
+    }
+    const double t0 = now_s();
+    try {
+      // admission: FIFO while slots are free and the budget allows
+      for (;;) {
+        uint64_t tk = 0;
+        {
+          std::lock_guard<std::mutex> lk(mu);
+          if (stop || queue.empty() || (int)active.size() >= p.max_active) break;
+          tk = queue.front();
+        }
+        SrvReq* r;
+        {
+          std::lock_guard<std::mutex> lk(mu);
+          r = req.at(tk).get();
+        }
+        bool ok = admit_one(*r);
+        std::lock_guard<std::mutex> lk(mu);
+        if (!ok) break;
+        queue.pop_front();
+        active.push_back(tk);
+      }
+      std::vector<SrvReq*> act;
+      {
+        std::lock_guard<std::mutex> lk(mu);
+        for (uint64_t tk : active) act.push_back(req.at(tk).get());
+      }
+      if (!act.empty()) round(act);
+      std::lock_guard<std::mutex> lk(mu);
+      std::vector<uint64_t> still;
+      for (uint64_t tk : active)
+        if (!req.at(tk)->done) still.push_back(tk);
+      active.swap(still);
+      st.busy_seconds += now_s() - t0;
+      st.resident_bytes = resident();
+    } catch (const Error& e) {
+      // fail every active request with the error; keep serving
+      (void)hipGetLastError();
+      std::lock_guard<std::mutex> lk(mu);
+      for (uint64_t tk : active) {
+        SrvReq& r = *req.at(tk);
+        r.done = true;
+        r.status = e.code;
+        r.t_done = now_s();
+        auto it = cav.find(r.cid);
+        if (it != cav.end() && it->second->refs > 0) it->second->refs--;
+      }
+      active.clear();
+      ctx.last_error = e.what();
+    }
+    cv.notify_all();
+  }
+}
+
+extern "C" {
+
+hm_status hm_server_create(hm_ctx* ctx, const hm_server_params* p, hm_server** out) {
+  if (!ctx || !p || !out) {
+    set_tl_error("hm_server_create: NULL argument");
+    return HM_EINVAL;
+  }
+  try {
+    HM_REQUIRE(p->hbm_budget_bytes > 0 && p->max_active >= 1, "hm_server_create: bad budget or max_active");
+    HM_REQUIRE(p->max_rhs_per_slot >= 1 && p->max_rhs_per_slot <= 16, "hm_server_create: max_rhs_per_slot in 1..16");
+    HM_REQUIRE(p->sigma > 0.0, "hm_server_create: sigma must be > 0");
+    HM_REQUIRE(p->solve.rtol > 0 && p->solve.rtol < 1 && p->solve.restart >= 1 && p->solve.restart <= MAXM &&
+                   p->solve.max_iter >= 1 && p->solve.ir_inner_rtol > 0 && p->solve.ir_inner_rtol < 1,
+               "hm_server_create: bad solve parameters");
+    auto s = std::make_unique<hm_server>();
+    s->p = *p;
+    s->device = ctx->device;
+    HM_HIP(hipSetDevice(ctx->device));
+    HM_HIP(hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking));
+    s->ctx.device = ctx->device;
+    s->ctx.stream = s->stream;
+    hm_server* raw = s.get();
+    s->worker = std::thread([raw] { raw->run(); });
+    *out = s.release();
+    return HM_OK;
+  } catch (const Error& e) {
+    ctx->last_error = e.what();
+    set_tl_error(e.what());
+    return e.code;
+  }
+}
+
+hm_status hm_server_register_cavity(hm_server* s, uint64_t cid, const hm_tree* tree, const double* eps_host,
+                                    const hm_assembly_params* ap) {
+  if (!s || !tree || !eps_host || !ap) {
+    set_tl_error("hm_server_register_cavity: NULL argument");
+    return HM_EINVAL;
+  }
+  try {
+    for (int64_t i = 0; i < tree->n; ++i)
+      HM_REQUIRE(eps_host[i] > 0.0 && eps_host[i] <= 1.0, "hm_server_register_cavity: eps must be in (0, 1]");
+    HM_REQUIRE(ap->aca_tol > 0 && ap->aca_tol < 1 && ap->k_max >= 1, "hm_server_register_cavity: bad assembly parameters");
+    auto c = std::make_unique<SrvCavity>();
+    c->id = cid;
+    c->tree = std::make_unique<hm_tree>(*tree);
+    c->eps.assign(eps_host, eps_host + tree->n);
+    c->ap = *ap;
+    c->ap.closed_row_scale = 0;
+    std::lock_guard<std::mutex> lk(s->mu);
+    HM_REQUIRE(s->cav.find(cid) == s->cav.end(), "hm_server_register_cavity: id already registered");
+    s->cav[cid] = std::move(c);
+    return HM_OK;
+  } catch (const Error& e) {
+    set_tl_error(e.what());
+    return e.code;
+  }
+}
+
+hm_status hm_submit(hm_server* s, uint64_t cid, int32_t nrhs, const double* T_host, uint64_t* ticket) {
+  if (!s || !T_host || !ticket) {
+    set_tl_error("hm_submit: NULL argument");
+    return HM_EINVAL;
+  }
+  std::lock_guard<std::mutex> lk(s->mu);
+  auto it = s->cav.find(cid);
+  if (it == s->cav.end()) {
+    set_tl_error("hm_submit: unknown cavity id");
+    return HM_ENOTFOUND;
+  }
+  if (nrhs < 1 || nrhs > s->p.max_rhs_per_slot) {
+    set_tl_error("hm_submit: nrhs out of range");
+    s->st.rejected++;
+    return HM_EINVAL;
+  }
+  const int64_t n = it->second->tree->n;
+  for (int64_t k = 0; k < n * nrhs; ++k)
+    if (!(T_host[k] > 0.0) || !std::isfinite(T_host[k])) {
+      set_tl_error("hm_submit: temperatures must be positive and finite");
+      s->st.rejected++;
+      return HM_EINVAL;
+    }
+  auto r = std::make_unique<SrvReq>();
+  r->ticket = s->next_ticket++;
+  r->cid = cid;
+  r->nrhs = nrhs;
+  r->n = n;
+  r->T.assign(T_host, T_host + n * nrhs);
+  r->t_submit = now_s();
+  *ticket = r->ticket;
+  s->queue.push_back(r->ticket);
+  s->req[r->ticket] = std::move(r);
+  s->st.submitted++;
+  s->cv.notify_all();
+  return HM_OK;
+}
+
+hm_status hm_poll(hm_server* s, uint64_t ticket, int32_t* done, double* J_host, double* q_host, hm_solve_info* info,
+                  double* latency) {
+  if (!s || !done) {
+    set_tl_error("hm_poll: NULL argument");
+    return HM_EINVAL;
+  }
+  std::lock_guard<std::mutex> lk(s->mu);
+  auto it = s->req.find(ticket);
+  if (it == s->req.end()) {
+    *done = 0;
+    set_tl_error("hm_poll: unknown ticket");
+    return HM_ENOTFOUND;
+  }
+  SrvReq& r = *it->second;
+  if (!r.done) {
+    *done = 0;
+    return HM_EBUSY;
+  }
+  *done = 1;
+  if (J_host && !r.J.empty()) std::copy(r.J.begin(), r.J.end(), J_host);
+  if (q_host && !r.q.empty()) std::copy(r.q.begin(), r.q.end(), q_host);
+  if (info) {
+    info->iters = r.inner;
+    info->outer_iters = r.rounds;
+    info->matvecs = r.matvecs;
+    info->rel_residual = r.rel_res;
+    info->seconds = r.t_done - r.t_submit;
+    info->bytes_moved = r.bytes;
+  }
+  if (latency) *latency = r.t_done - r.t_submit;
+  const hm_status st = r.status;
+  s->req.erase(it);
+  return st;
+}
+
+hm_status hm_server_stats_get(hm_server* s, hm_server_stats* out) {
+  if (!s || !out) return HM_EINVAL;
+  std::lock_guard<std::mutex> lk(s->mu);
+  *out = s->st;
+  return HM_OK;
+}
+
+void hm_server_destroy(hm_server* s) {
+  if (!s) return;
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->stop = true;
+    s->queue.clear();
+  }
+  s->cv.notify_all();
+  if (s->worker.joinable()) s->worker.join();
+  (void)hipSetDevice(s->device);
+  (void)hipStreamSynchronize(s->stream);
+  s->cav.clear();
+  s->req.clear();
+  (void)hipStreamDestroy(s->stream);
+  delete s;
+}
+
+}  // extern "C"

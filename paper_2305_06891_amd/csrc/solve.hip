@@ -1,0 +1,449 @@
+// Radiosity solves on top of the batched H-matrix product and GMRES:
+// right-hand side sigma eps T^4 (eq. (4)), reflection operator of eq. (11),
+// facet flux of eq. (12), optional mixed-precision iterative refinement and
+// the lumped implicit-Euler transient (analogue of Sec. 3.3).
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <map>
+
+#include "dev_common.hpp"
+#include "krylov.hpp"
+#include "solve.hpp"
+
+namespace hm {
+
+// ------------------------------------------------------------------ kernels
+__device__ inline int io_slot(const SlotIO* __restrict__ io, int ns, int64_t row) {
+  int lo = 0, hi = ns - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (io[mid].xoff <= row) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+// dst[row + j*N] = in_slot[perm[i] + j*ld] (permuted copy), j < ncol; 0 for j >= ncol_slot
+__global__ void k_gather(const SlotIO* __restrict__ io, int ns, int64_t N, int ncol, double* __restrict__ dst) {
+  const int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = blockIdx.y;
+  if (row >= N) return;
+  const SlotIO s = io[io_slot(io, ns, row)];
+  const int64_t i = row - s.xoff;
+  dst[row + j * N] = (j < ncol && s.in) ? s.in[s.perm[i] + j * s.ld] : 0.0;
+}
+
+__global__ void k_scatter(const SlotIO* __restrict__ io, int ns, int64_t N, int ncol, const double* __restrict__ src) {
+  const int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = blockIdx.y;
+  if (row >= N || j >= ncol) return;
+  const SlotIO s = io[io_slot(io, ns, row)];
+  if (!s.out) return;
+  const int64_t i = row - s.xoff;
+  s.out[s.perm[i] + j * s.ld] = src[row + j * N];
+}
+
+// b = sigma eps T^4 and its cast; zero in padded columns
+template <class VT>
+__global__ void k_rhs(const double* __restrict__ eps, const double* __restrict__ T, int64_t N, int ncol,
+                      double sigma, double* __restrict__ b64, VT* __restrict__ bv) {
+  const int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = blockIdx.y;
+  if (row >= N) return;
+  const int64_t k = row + j * N;
+  double v = 0.0;
+  if (j < ncol) {
+    const double t = T[k];
+    const double t2 = t * t;
+    v = sigma * eps[row] * (t2 * t2);
+  }
+  if (b64) b64[k] = v;
+  if (bv) bv[k] = (VT)v;
+}
+
+template <class VT>
+__global__ void k_omeps(const double* __restrict__ eps, int64_t N, VT* __restrict__ out) {
+  const int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (row < N) out[row] = (VT)(1.0 - eps[row]);
+}
+
+template <class A, class B>
+__global__ void k_cast(const A* __restrict__ a, B* __restrict__ b, int64_t n) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < n) b[k] = (B)a[k];
+}
+
+// y += (double) x
+template <class VT>
+__global__ void k_acc(const VT* __restrict__ x, double* __restrict__ y, int64_t n) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < n) y[k] += (double)x[k];
+}
+
+// q = eps (H - sigma T^4 g)  (eq. (12) through J and g = F C^-1 eps)
+__global__ void k_flux(const double* __restrict__ eps, const double* __restrict__ T, const double* __restrict__ H,
+                       const double* __restrict__ g, int64_t N, int ncol, double sigma, double* __restrict__ q) {
+  const int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = blockIdx.y;
+  if (row >= N || j >= ncol) return;
+  const int64_t k = row + j * N;
+  const double t = T[k];
+  const double t2 = t * t;
+  q[k] = eps[row] * (H[k] - sigma * (t2 * t2) * g[row]);
+}
+
+// Newton residual R = mc (T - Tn)/dt - q - s, and the update T <- T - R / D
+// with D = mc/dt + 4 sigma eps g T^3 (mode 1), or only R (mode 0).
+__global__ void k_newton(const double* __restrict__ eps, const double* __restrict__ g, const double* __restrict__ q,
+                         const double* __restrict__ src, const double* __restrict__ Tn, double* __restrict__ T,
+                         double* __restrict__ R, int64_t N, int ncol, double mc, double dt, double sigma,
+                         const int* __restrict__ upd) {
+  const int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = blockIdx.y;
+  if (row >= N || j >= ncol) return;
+  const int64_t k = row + j * N;
+  const double t = T[k];
+  const double r = mc * (t - Tn[k]) / dt - q[k] - src[k];
+  R[k] = r;
+  if (upd && upd[j]) {
+    const double D = mc / dt + 4.0 * sigma * eps[row] * g[row] * (t * t * t);
+    T[k] = t - r / D;
+  }
+}
+
+__global__ void k_differs(const double* __restrict__ a, const double* __restrict__ b, int64_t n, int* flag) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < n && a[k] != b[k]) atomicOr(flag, 1);
+}
+
+namespace {
+
+dim3 grid_rows(int64_t N, int cols = 1) { return dim3((unsigned)((N + 255) / 256), (unsigned)cols); }
+
+}  // namespace
+
+// ------------------------------------------------------------------ batch state
+Batch::Batch(const std::vector<const hm_matrix*>& m, int nrhs_, hipStream_t s) : mats(m), nrhs(nrhs_) {
+  W = pad_width(nrhs);
+  C = make_composition(mats, W, 8, s);
+  N = C->N;
+  std::vector<std::vector<int>> cols(mats.size());
+  for (auto& c : cols)
+    for (int j = 0; j < nrhs; ++j) c.push_back(j);
+  S.build(*C, cols, s);
+  const size_t vb = (size_t)N * W * 8;
+  Tp.alloc(vb);
+  b64.alloc(vb);
+  x64.alloc(vb);
+  r64.alloc(vb);
+  H64.alloc(vb);
+  epsp.alloc(N * 8);
+  omeps64.alloc(N * 8);
+  HM_HIP(hipMemsetAsync(Tp.get(), 0, vb, s));
+  HM_HIP(hipMemsetAsync(x64.get(), 0, vb, s));
+  HM_HIP(hipMemsetAsync(r64.get(), 0, vb, s));
+  for (const auto* M : mats) {
+    SlotIO io{};
+    io.perm = M->d_perm.get<int32_t>();
+    io.n = M->n;
+    ios.push_back(io);
+  }
+  int64_t off = 0;
+  for (auto& io : ios) {
+    io.xoff = off;
+    off += io.n;
+  }
+  d_ios.alloc(ios.size() * sizeof(SlotIO));
+}
+
+Krylov& Batch::krylov(int vb, int restart, hipStream_t s) {
+  Krylov& K = vb == 8 ? K64 : K32;
+  bool& ok = vb == 8 ? k64 : k32;
+  if (!ok || K.m != restart) {
+    if (vb == 4 && !b32.get()) {
+      const size_t by = (size_t)N * W * 4;
+      b32.alloc(by);
+      x32.alloc(by);
+      omeps32.alloc(N * 4);
+      HM_HIP(hipMemsetAsync(x32.get(), 0, by, s));
+    }
+    K.init(*C, S, vb, restart, s);
+    ok = true;
+  }
+  return K;
+}
+
+void Batch::io(const std::vector<const double*>& in, const std::vector<double*>& out, int64_t ld_in_default,
+               const std::vector<int64_t>* lds, hipStream_t s) {
+  for (size_t q = 0; q < ios.size(); ++q) {
+    ios[q].in = q < in.size() ? in[q] : nullptr;
+    ios[q].out = q < out.size() ? out[q] : nullptr;
+    ios[q].ld = lds ? (*lds)[q] : (ld_in_default > 0 ? ld_in_default : ios[q].n);
+  }
+  HM_HIP(hipMemcpyAsync(d_ios.get(), ios.data(), ios.size() * sizeof(SlotIO), hipMemcpyHostToDevice, s));
+  HM_HIP(hipStreamSynchronize(s));  // the host table is rewritten by the next call
+}
+
+void Batch::gather(double* dst, int ncol, hipStream_t s) {
+  hipLaunchKernelGGL(k_gather, grid_rows(N, W), dim3(256), 0, s, d_ios.get<SlotIO>(), (int)ios.size(), N, ncol, dst);
+  HM_HIP(hipGetLastError());
+}
+
+void Batch::scatter(const double* src, int ncol, hipStream_t s) {
+  hipLaunchKernelGGL(k_scatter, grid_rows(N, ncol), dim3(256), 0, s, d_ios.get<SlotIO>(), (int)ios.size(), N, ncol,
+                     src);
+  HM_HIP(hipGetLastError());
+}
+
+// g = F C^-1 eps per slot (the flux helper of eq. (12)); FP64 vectors with
+// the most accurate stored factors, solved to 1e-13.
+void Batch::ensure_g(const std::vector<const double*>& eps_user, hipStream_t s) {
+  // epsp holds the permuted emissivities of this call; g is reused while they are unchanged
+  if (g_ready) {
+    int flag = 0;
+    HM_HIP(hipMemsetAsync(d_flag.get(), 0, 4, s));
+    hipLaunchKernelGGL(k_differs, grid_rows(N), dim3(256), 0, s, epsp.get<double>(), g_eps.get<double>(), N,
+                       d_flag.get<int>());
+    HM_HIP(hipMemcpyAsync(&flag, d_flag.get(), 4, hipMemcpyDeviceToHost, s));
+    HM_HIP(hipStreamSynchronize(s));
+    if (!flag) return;
+  }
+  if (!gb) gb = std::make_unique<Batch>(mats, 1, s);
+  Batch& B = *gb;
+  B.io(eps_user, {}, 0, nullptr, s);
+  B.gather(B.epsp.get<double>(), 1, s);
+  hipLaunchKernelGGL(k_omeps<double>, grid_rows(B.N), dim3(256), 0, s, B.epsp.get<double>(), B.N,
+                     B.omeps64.get<double>());
+  HM_HIP(hipMemcpyAsync(B.b64.get(), B.epsp.get(), B.N * 8, hipMemcpyDeviceToDevice, s));
+  HM_HIP(hipMemcpyAsync(B.x64.get(), B.epsp.get(), B.N * 8, hipMemcpyDeviceToDevice, s));
+  Krylov& K = B.krylov(8, 30, s);
+  GmresStats st = gmres(K, true, B.omeps64.get(), B.b64.get(), B.x64.get(), 1e-13, 2000, s);
+  (void)st;
+  if (!g.get()) g.alloc(N * 8);
+  if (!g_eps.get()) g_eps.alloc(N * 8);
+  if (!d_flag.get()) d_flag.alloc(4);
+  launch_matvec(*B.C, 1, 8, true, B.x64.get(), B.N, g.get(), B.N, Epilogue{}, nullptr, s);
+  HM_HIP(hipMemcpyAsync(g_eps.get(), epsp.get(), N * 8, hipMemcpyDeviceToDevice, s));
+  HM_HIP(hipStreamSynchronize(s));
+  g_ready = true;
+}
+
+SolveResult Batch::solve(const std::vector<const double*>& eps_user, const std::vector<const double*>& T_user,
+                         const std::vector<int64_t>& ldT, double sigma, const hm_solve_params& p,
+                         const std::vector<double*>& J_user, const std::vector<int64_t>& ldJ,
+                         const std::vector<double*>& q_user, const std::vector<int64_t>& ldq, hipStream_t s) {
+  SolveResult R;
+  const bool want_q = p.want_q && std::any_of(q_user.begin(), q_user.end(), [](double* v) { return v != nullptr; });
+  // permuted inputs
+  io(eps_user, {}, 0, nullptr, s);
+  gather(epsp.get<double>(), 1, s);
+  hipLaunchKernelGGL(k_omeps<double>, grid_rows(N), dim3(256), 0, s, epsp.get<double>(), N, omeps64.get<double>());
+  io(T_user, {}, 0, &ldT, s);
+  gather(Tp.get<double>(), nrhs, s);
+  prepare_rhs(sigma, p, s);
+  R = solve_prepared(p, s);
+  if (want_q) {
+    ensure_g(eps_user, s);
+    flux(sigma, s);
+  }
+  io({}, J_user, 0, &ldJ, s);
+  scatter(x64.get<double>(), nrhs, s);
+  if (want_q) {
+    io({}, q_user, 0, &ldq, s);
+    scatter(H64.get<double>(), nrhs, s);
+  }
+  return R;
+}
+
+void Batch::prepare_rhs(double sigma, const hm_solve_params& p, hipStream_t s) {
+  const bool f32 = p.mixed_precision || p.vec_dtype == HM_F32;
+  if (f32) {
+    krylov(4, p.restart, s);
+    hipLaunchKernelGGL(k_omeps<float>, grid_rows(N), dim3(256), 0, s, epsp.get<double>(), N, omeps32.get<float>());
+  }
+  hipLaunchKernelGGL(k_rhs<float>, grid_rows(N, W), dim3(256), 0, s, epsp.get<double>(), Tp.get<double>(), N, nrhs,
+                     sigma, b64.get<double>(), f32 ? b32.get<float>() : (float*)nullptr);
+  HM_HIP(hipGetLastError());
+}
+
+SolveResult Batch::solve_prepared(const hm_solve_params& p, hipStream_t s, bool warm) {
+  SolveResult R;
+  const int64_t tot = N * W;
+  const unsigned gb_ = (unsigned)((tot + 255) / 256);
+  if (!p.mixed_precision && p.vec_dtype != HM_F32) {
+    Krylov& K = krylov(8, p.restart, s);
+    if (!warm) HM_HIP(hipMemcpyAsync(x64.get(), b64.get(), tot * 8, hipMemcpyDeviceToDevice, s));
+    GmresStats st = gmres(K, false, omeps64.get(), b64.get(), x64.get(), p.rtol, p.max_iter, s);
+    R.iters = st.iters;
+    R.matvecs = st.matvecs;
+    R.bytes = st.bytes;
+    R.rel_res = st.rel_res;
+    R.converged = st.converged;
+  } else if (!p.mixed_precision) {
+    Krylov& K = krylov(4, p.restart, s);
+    if (warm) hipLaunchKernelGGL((k_cast<double, float>), dim3(gb_), dim3(256), 0, s, x64.get<double>(), x32.get<float>(), tot);
+    else HM_HIP(hipMemcpyAsync(x32.get(), b32.get(), tot * 4, hipMemcpyDeviceToDevice, s));
+    GmresStats st = gmres(K, false, omeps32.get(), b32.get(), x32.get(), p.rtol, p.max_iter, s);
+    hipLaunchKernelGGL((k_cast<float, double>), dim3(gb_), dim3(256), 0, s, x32.get<float>(), x64.get<double>(), tot);
+    R.iters = st.iters;
+    R.matvecs = st.matvecs;
+    R.bytes = st.bytes;
+    R.converged = st.converged;
+    // report the residual in FP64 against the same stored operator
+    Krylov& K8 = krylov(8, p.restart, s);
+    residual64(false, s);
+    R.matvecs++;
+    R.bytes += C->bytes_lo;
+    std::vector<double> rn, bn;
+    block_norms(K8, r64.get(), rn, s);
+    block_norms(K8, b64.get(), bn, s);
+    R.rel_res.resize(rn.size());
+    for (size_t q = 0; q < rn.size(); ++q) R.rel_res[q] = bn[q] > 0 ? rn[q] / bn[q] : 0.0;
+  } else {
+    // iterative refinement: FP64 residual with the FP32 (hi) factors, inner
+    // FP32 GMRES with the stored (BF16) factors on C d = r, J += d.
+    Krylov& K8 = krylov(8, p.restart, s);
+    Krylov& K4 = krylov(4, p.restart, s);
+    if (!warm) HM_HIP(hipMemsetAsync(x64.get(), 0, tot * 8, s));
+    std::vector<double> bn, rn;
+    block_norms(K8, b64.get(), bn, s);
+    R.converged = false;
+    int outer = 0, inner_total = 0;
+    for (;;) {
+      residual64(true, s);
+      R.matvecs++;
+      R.bytes += C->bytes_hi;
+      block_norms(K8, r64.get(), rn, s);
+      bool done = true;
+      R.rel_res.resize(rn.size());
+      for (size_t q = 0; q < rn.size(); ++q) {
+        R.rel_res[q] = bn[q] > 0 ? rn[q] / bn[q] : 0.0;
+        if (rn[q] > p.rtol * bn[q]) done = false;
+      }
+      if (done) {
+        R.converged = true;
+        break;
+      }
+      if (outer >= 30 || inner_total >= p.max_iter) break;
+      // systems already converged get a zero right-hand side (no inner work)
+      hipLaunchKernelGGL((k_cast<double, float>), dim3(gb_), dim3(256), 0, s, r64.get<double>(), b32.get<float>(), tot);
+      for (size_t q = 0; q < rn.size(); ++q) {
+        if (rn[q] <= p.rtol * bn[q]) {
+          const SysDev& sd = S.sys[q];
+          HM_HIP(hipMemsetAsync(b32.get<float>() + sd.col * N + sd.row0, 0, (size_t)sd.n * 4, s));
+        }
+      }
+      HM_HIP(hipMemcpyAsync(x32.get(), b32.get(), tot * 4, hipMemcpyDeviceToDevice, s));
+      GmresStats st = gmres(K4, false, omeps32.get(), b32.get(), x32.get(), p.ir_inner_rtol, p.max_iter, s);
+      hipLaunchKernelGGL(k_acc<float>, dim3(gb_), dim3(256), 0, s, x32.get<float>(), x64.get<double>(), tot);
+      R.iters += st.iters;
+      R.matvecs += st.matvecs;
+      R.bytes += st.bytes;
+      inner_total += st.iters;
+      ++outer;
+    }
+    R.outer = outer;
+  }
+  return R;
+}
+
+// r64 = b64 - C x64 with FP64 vectors (hi: FP32 copy of BF16 factors)
+void Batch::residual64(bool hi, hipStream_t s) {
+  Epilogue ep;
+  ep.rowscale = omeps64.get();
+  ep.a_acc = 1.0;
+  ep.a_x = -1.0;
+  ep.a_z = 1.0;
+  ep.z = b64.get();
+  ep.ldz = N;
+  launch_matvec(*C, nrhs, 8, hi, x64.get(), N, r64.get(), N, ep, nullptr, s);
+}
+
+// H64 <- q = eps (F J - sigma T^4 g), J = x64
+void Batch::flux(double sigma, hipStream_t s) {
+  launch_matvec(*C, nrhs, 8, true, x64.get(), N, H64.get(), N, Epilogue{}, nullptr, s);
+  hipLaunchKernelGGL(k_flux, grid_rows(N, nrhs), dim3(256), 0, s, epsp.get<double>(), Tp.get<double>(),
+                     H64.get<double>(), g.get<double>(), N, nrhs, sigma, H64.get<double>());
+  HM_HIP(hipGetLastError());
+}
+
+// ------------------------------------------------------------------ transient
+TransientResult Batch::transient(const std::vector<const double*>& eps_user, double* T_user, int64_t ldT,
+                                 const double* src_user, int64_t ldS, double sigma, const hm_transient_params& tp,
+                                 const hm_solve_params& sp, double* history, hipStream_t s) {
+  TransientResult TR;
+  io(eps_user, {}, 0, nullptr, s);
+  gather(epsp.get<double>(), 1, s);
+  hipLaunchKernelGGL(k_omeps<double>, grid_rows(N), dim3(256), 0, s, epsp.get<double>(), N, omeps64.get<double>());
+  ensure_g(eps_user, s);
+  std::vector<int64_t> ldv{ldT};
+  io({T_user}, {}, 0, &ldv, s);
+  gather(Tp.get<double>(), nrhs, s);
+  std::vector<int64_t> lds{ldS};
+  DevBuf srcp(N * W * 8), Tn(N * W * 8), Rv(N * W * 8), d_upd(W * 4);
+  io({src_user}, {}, 0, &lds, s);
+  gather(srcp.get<double>(), nrhs, s);
+  std::vector<int64_t> ldh{ldT};
+  if (history) {
+    io({}, {history}, 0, &ldh, s);
+    scatter(Tp.get<double>(), nrhs, s);
+  }
+  Krylov& K8 = krylov(8, sp.restart, s);
+  std::vector<int> upd(W, 0);
+  bool have_J = false;
+  for (int step = 0; step < tp.steps; ++step) {
+    HM_HIP(hipMemcpyAsync(Tn.get(), Tp.get(), N * W * 8, hipMemcpyDeviceToDevice, s));
+    std::vector<double> scale;
+    block_norms(K8, Tn.get(), scale, s);
+    for (auto& v : scale) v *= tp.mc / tp.dt;
+    int it = 0;
+    for (;;) {
+      // q(T): radiosity solve (warm start from the previous iterate) and flux
+      prepare_rhs(sigma, sp, s);
+      SolveResult R = solve_prepared(sp, s, have_J);
+      have_J = true;
+      TR.matvecs += R.matvecs + 1;
+      flux(sigma, s);  // H64 = q
+      std::fill(upd.begin(), upd.end(), 0);
+      hipLaunchKernelGGL(k_newton, grid_rows(N, nrhs), dim3(256), 0, s, epsp.get<double>(), g.get<double>(),
+                         H64.get<double>(), srcp.get<double>(), Tn.get<double>(), Tp.get<double>(), Rv.get<double>(),
+                         N, nrhs, tp.mc, tp.dt, sigma, (const int*)nullptr);
+      HM_HIP(hipGetLastError());
+      std::vector<double> rn;
+      block_norms(K8, Rv.get(), rn, s);
+      bool done = true;
+      double worst = 0.0;
+      for (int j = 0; j < nrhs; ++j) {
+        const double rel = scale[j] > 0 ? rn[j] / scale[j] : 0.0;
+        worst = std::max(worst, rel);
+        upd[j] = rel > tp.newton_rtol ? 1 : 0;
+        if (upd[j]) done = false;
+      }
+      if (done || it >= tp.max_newton) {
+        TR.max_rel_residual = std::max(TR.max_rel_residual, worst);
+        break;
+      }
+      HM_HIP(hipMemcpyAsync(d_upd.get(), upd.data(), W * 4, hipMemcpyHostToDevice, s));
+      hipLaunchKernelGGL(k_newton, grid_rows(N, nrhs), dim3(256), 0, s, epsp.get<double>(), g.get<double>(),
+                         H64.get<double>(), srcp.get<double>(), Tn.get<double>(), Tp.get<double>(), Rv.get<double>(),
+                         N, nrhs, tp.mc, tp.dt, sigma, d_upd.get<int>());
+      HM_HIP(hipGetLastError());
+      ++it;
+    }
+    TR.newton_total += it;
+    TR.newton_max = std::max(TR.newton_max, it);
+    TR.steps_done = step + 1;
+    if (history) {
+      io({}, {history + (int64_t)(step + 1) * ldT * nrhs}, 0, &ldh, s);
+      scatter(Tp.get<double>(), nrhs, s);
+    }
+  }
+  io({}, {T_user}, 0, &ldv, s);
+  scatter(Tp.get<double>(), nrhs, s);
+  HM_HIP(hipStreamSynchronize(s));
+  return TR;
+}
+
+}  // namespace hm

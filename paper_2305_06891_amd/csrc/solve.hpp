@@ -1,0 +1,67 @@
+// Batched radiosity solve state (one or more cavities, 1..16 right-hand sides).
+#pragma once
+
+#include "krylov.hpp"
+
+namespace hm {
+
+// Caller arrays of one slot for a permuted gather / scatter.
+struct SlotIO {
+  const double* in;   // caller array of the slot (original order)
+  double* out;
+  int64_t ld;         // leading dimension of the caller array
+  const int32_t* perm;
+  int64_t xoff;
+  int64_t n;
+};
+
+struct SolveResult {
+  int iters = 0, outer = 0, matvecs = 0;
+  int64_t bytes = 0;
+  bool converged = true;
+  std::vector<double> rel_res;  // per system (slot-major, then column)
+};
+
+struct TransientResult {
+  int steps_done = 0, newton_total = 0, newton_max = 0, matvecs = 0;
+  double max_rel_residual = 0.0;
+};
+
+// Everything one batched solve needs, kept between calls on the same set of
+// matrices: the composition of their products, the systems, the Krylov
+// workspaces and the permuted vectors (combined row space N x W).
+struct Batch {
+  std::vector<const hm_matrix*> mats;
+  int nrhs = 1, W = 1;
+  int64_t N = 0;
+  std::unique_ptr<Composition> C;
+  SysSet S;
+  Krylov K64, K32;
+  bool k64 = false, k32 = false;
+  DevBuf Tp, epsp, omeps64, omeps32, b64, b32, x64, x32, r64, H64, g, g_eps, d_flag;
+  std::vector<SlotIO> ios;
+  DevBuf d_ios;
+  std::unique_ptr<Batch> gb;  // width-1 batch for g = F C^-1 eps
+  bool g_ready = false;
+
+  Batch(const std::vector<const hm_matrix*>& mats, int nrhs, hipStream_t s);
+  Krylov& krylov(int vb, int restart, hipStream_t s);
+  void io(const std::vector<const double*>& in, const std::vector<double*>& out, int64_t ld_in_default,
+          const std::vector<int64_t>* lds, hipStream_t s);
+  void gather(double* dst, int ncol, hipStream_t s);
+  void scatter(const double* src, int ncol, hipStream_t s);
+  void ensure_g(const std::vector<const double*>& eps_user, hipStream_t s);
+  void prepare_rhs(double sigma, const hm_solve_params& p, hipStream_t s);
+  SolveResult solve_prepared(const hm_solve_params& p, hipStream_t s, bool warm = false);
+  void residual64(bool hi, hipStream_t s);
+  void flux(double sigma, hipStream_t s);
+  SolveResult solve(const std::vector<const double*>& eps, const std::vector<const double*>& T,
+                    const std::vector<int64_t>& ldT, double sigma, const hm_solve_params& p,
+                    const std::vector<double*>& J, const std::vector<int64_t>& ldJ, const std::vector<double*>& q,
+                    const std::vector<int64_t>& ldq, hipStream_t s);
+  TransientResult transient(const std::vector<const double*>& eps, double* T, int64_t ldT, const double* src,
+                            int64_t ldS, double sigma, const hm_transient_params& tp, const hm_solve_params& sp,
+                            double* history, hipStream_t s);
+};
+
+}  // namespace hm
