@@ -60,8 +60,9 @@ typedef struct hm_server hm_server;
 /* ------------------------------------------------------------------ context */
 
 /* Create a context bound to GPU `device` and HIP stream `hip_stream`
- * (hipStream_t passed as void*; NULL = the library creates its own
- * non-blocking stream).  One context per host thread / stream. */
+ * (hipStream_t passed as void*; NULL = the device's null stream, which is
+ * also torch's default stream).  All work of the context is ordered on that
+ * stream.  One context per host thread / stream. */
 hm_status hm_ctx_create(int device, void* hip_stream, hm_ctx** out);
 void hm_ctx_destroy(hm_ctx* ctx);
 /* Block until all work the library queued on ctx's stream has finished. */
@@ -159,6 +160,19 @@ hm_status hm_hmatvec(hm_ctx* ctx, const hm_matrix* M, int32_t nrhs, hm_dtype vec
 hm_status hm_hmatvec_ex(hm_ctx* ctx, const hm_matrix* M, int32_t nrhs, hm_dtype vec_dtype,
                         int32_t use_f32_copy, const void* X, int64_t ldx, void* Y, int64_t ldy,
                         double alpha, double beta);
+
+/* Timing of the product's two kernels, measured with HIP events recorded on
+ * ctx's stream around each kernel of `reps` products y = F_H x on internal
+ * permuted vectors (x = 1).  Before each product `flush_bytes` (>= 0) of
+ * device memory are overwritten so that the 256 MB last-level cache holds
+ * none of the matrix.  Outputs (HOST, any may be NULL): average ms of phase 1
+ * (t = V^T x), of phase 2 (y = D x + U t) and of the whole product, and the
+ * algorithmic bytes of each phase per product: phase 1 reads every V factor
+ * once plus x and writes t; phase 2 reads every dense block and U factor once
+ * plus x and t and writes y. */
+hm_status hm_hmatvec_profile(hm_ctx* ctx, const hm_matrix* M, int32_t nrhs, hm_dtype vec_dtype,
+                             int32_t use_f32_copy, int32_t reps, int64_t flush_bytes, double* ms_phase1,
+                             double* ms_phase2, double* ms_total, int64_t* bytes_phase1, int64_t* bytes_phase2);
 
 /* ----------------------------------------------------------- radiosity solve */
 

@@ -21,7 +21,7 @@ ARCH = os.environ.get("HM_OFFLOAD_ARCH", "gfx950")
 HIPCC = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function", "-Wno-unused-variable",
-          "-Wno-unused-result", "-ffp-contract=fast"]
+          "-Wno-unused-result", "-ffp-contract=on"]
 # packed FP32 instructions are disabled for all device code
 DEVICE = ["--offload-arch=" + ARCH, "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           "-munsafe-fp-atomics"]

@@ -165,12 +165,7 @@ hm_status hm_ctx_create(int device, void* hip_stream, hm_ctx** out) {
     HM_HIP(hipGetDeviceCount(&nd));
     HM_REQUIRE(device >= 0 && device < nd, "hm_ctx_create: no such device");
     HM_HIP(hipSetDevice(device));
-    if (hip_stream) {
-      c->stream = (hipStream_t)hip_stream;
-    } else {
-      HM_HIP(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
-      c->own_stream = true;
-    }
+    c->stream = (hipStream_t)hip_stream;  // NULL: the null stream
   });
   if (st == HM_OK) *out = c.release();
   return st;
@@ -301,6 +296,68 @@ hm_status hm_hmatvec_ex(hm_ctx* ctx, const hm_matrix* M, int32_t nrhs, hm_dtype 
 hm_status hm_hmatvec(hm_ctx* ctx, const hm_matrix* M, int32_t nrhs, hm_dtype vt, const void* X, int64_t ldx,
                      void* Y, int64_t ldy, double alpha, double beta) {
   return hm_hmatvec_ex(ctx, M, nrhs, vt, 0, X, ldx, Y, ldy, alpha, beta);
+}
+
+hm_status hm_hmatvec_profile(hm_ctx* ctx, const hm_matrix* M, int32_t nrhs, hm_dtype vt, int32_t use_hi, int32_t reps,
+                             int64_t flush_bytes, double* ms1, double* ms2, double* mst, int64_t* b1, int64_t* b2) {
+  if (!ctx) {
+    set_tl_error("hm_hmatvec_profile: NULL ctx");
+    return HM_EINVAL;
+  }
+  return guarded(ctx, [&] {
+    HM_REQUIRE(M && reps >= 1 && nrhs >= 1 && nrhs <= 16 && flush_bytes >= 0, "hm_hmatvec_profile: bad arguments");
+    HM_REQUIRE(vt == HM_F64 || vt == HM_F32, "hm_hmatvec_profile: vec_dtype must be HM_F64 or HM_F32");
+    std::lock_guard<std::mutex> lk(const_cast<hm_matrix*>(M)->mu);
+    hipStream_t s = ctx->stream;
+    MatCache& mc = cache_of(*M);
+    const int W = pad_width(nrhs);
+    auto& comp = mc.comps[W];
+    if (!comp) comp = make_composition({M}, W, 8, s);
+    const int64_t n = M->n;
+    const int vb = vt == HM_F64 ? 8 : 4;
+    DevBuf X((size_t)n * W * vb), Y((size_t)n * W * vb), flush(flush_bytes > 0 ? (size_t)flush_bytes : 0);
+    {
+      std::vector<char> h((size_t)n * W * vb);
+      if (vb == 8) {
+        double* d = (double*)h.data();
+        for (int64_t k = 0; k < n * W; ++k) d[k] = 1.0;
+      } else {
+        float* f = (float*)h.data();
+        for (int64_t k = 0; k < n * W; ++k) f[k] = 1.0f;
+      }
+      HM_HIP(hipMemcpyAsync(X.get(), h.data(), h.size(), hipMemcpyHostToDevice, s));
+      HM_HIP(hipStreamSynchronize(s));
+    }
+    hipEvent_t ev[3];
+    for (auto& e : ev) HM_HIP(hipEventCreate(&e));
+    double t1 = 0, t2 = 0;
+    const bool hi = use_hi != 0;
+    try {
+      for (int r = 0; r < reps; ++r) {
+        if (flush_bytes > 0) HM_HIP(hipMemsetAsync(flush.get(), r & 0xff, (size_t)flush_bytes, s));
+        launch_matvec(*comp, nrhs, vb, hi, X.get(), n, Y.get(), n, Epilogue{}, nullptr, s, ev);
+        HM_HIP(hipEventSynchronize(ev[2]));
+        float a = 0, b = 0;
+        HM_HIP(hipEventElapsedTime(&a, ev[0], ev[1]));
+        HM_HIP(hipEventElapsedTime(&b, ev[1], ev[2]));
+        t1 += a;
+        t2 += b;
+      }
+    } catch (...) {
+      for (auto& e : ev) (void)hipEventDestroy(e);
+      throw;
+    }
+    for (auto& e : ev) HM_HIP(hipEventDestroy(e));
+    const bool use_f32 = hi && M->has_hi;
+    const int64_t sl = use_f32 ? 4 : (int64_t)dtype_size(M->lr_dtype);
+    const int64_t sd = (int64_t)dtype_size(M->dense_dtype);
+    const int64_t vecs = (int64_t)nrhs * vb;
+    if (ms1) *ms1 = t1 / reps;
+    if (ms2) *ms2 = t2 / reps;
+    if (mst) *mst = (t1 + t2) / reps;
+    if (b1) *b1 = M->v_entries * sl + vecs * (n + M->Ktot);
+    if (b2) *b2 = M->dense_entries * sd + M->u_entries * sl + vecs * (2 * n + M->Ktot);
+  });
 }
 
 static void fill_info(hm_solve_info* info, const SolveResult& R, double secs, int sys_begin, int sys_end) {

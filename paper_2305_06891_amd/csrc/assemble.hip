@@ -493,6 +493,8 @@ hm_matrix* assemble(hm_ctx& ctx, const hm_tree& t, const hm_assembly_params& p) 
   for (const auto& l : lr) {
     ktot += l.k;
     lre += (int64_t)l.k * ((l.b.re - l.b.rb) + (l.b.ce - l.b.cb));
+    M->u_entries += (int64_t)l.k * (l.b.re - l.b.rb);
+    M->v_entries += (int64_t)l.k * (l.b.ce - l.b.cb);
     M->max_rank = std::max(M->max_rank, l.k);
   }
   M->Ktot = ktot;

@@ -204,6 +204,7 @@ struct hm_matrix {
   hm::DevBuf d_perm;                         // int32 perm
   hm::DevBuf dense, U, V, U_hi, V_hi;        // arenas
   int64_t dense_entries = 0, lr_entries = 0, Ktot = 0;
+  int64_t u_entries = 0, v_entries = 0;  // sum k*m and sum k*n over low-rank blocks
   int64_t n_dense_blocks = 0, n_lr_blocks = 0, n_fallback = 0, rank_sum = 0;
   int32_t max_rank = 0;
   hm::Plan plan;
@@ -249,7 +250,7 @@ struct Epilogue {
 // nrr: right-hand sides actually present (<= C.nr, the padded width).
 // vb: vector element bytes (8: FP64, 4: FP32).
 void launch_matvec(const Composition& C, int nrr, int vb, bool hi, const void* X, int64_t ldx, void* Y, int64_t ldy,
-                   const Epilogue& ep, const int* slot_active, hipStream_t s);
+                   const Epilogue& ep, const int* slot_active, hipStream_t s, hipEvent_t* ev = nullptr);
 
 inline int pad_width(int nrhs) { return nrhs <= 1 ? 1 : nrhs <= 2 ? 2 : nrhs <= 4 ? 4 : nrhs <= 8 ? 8 : 16; }
 int64_t matrix_bytes(const hm_matrix& M, bool hi);

@@ -149,8 +149,7 @@ hm_status hm_facets_from_triangles(int64_t nv, const double* v, int64_t nt, cons
       cr[2] = e1[0] * e2[1] - e1[1] * e2[0];
       double tw = std::sqrt((cr[0] * cr[0] + cr[1] * cr[1]) + cr[2] * cr[2]);
       HM_REQUIRE(tw > 0.0 && std::isfinite(tw), "hm_facets_from_triangles: degenerate triangle");
-      double s = 1.0 / tw;
-      double nn[3] = {cr[0] * s, cr[1] * s, cr[2] * s};
+      double nn[3] = {cr[0] / tw, cr[1] / tw, cr[2] / tw};
       bool flip = orient < 0;
       if (orient == 0) {
         double d = (nn[0] * (cen[0] - g[0]) + nn[1] * (cen[1] - g[1])) + nn[2] * (cen[2] - g[2]);

@@ -467,13 +467,15 @@ namespace {
 
 template <class DT, class LT, class VT, int NR>
 void launch_typed(const Composition& C, int nrr, bool hi, const void* X, int64_t ldx, void* Y, int64_t ldy,
-                  const Epilogue& ep, const int* slot_active, hipStream_t s) {
+                  const Epilogue& ep, const int* slot_active, hipStream_t s, hipEvent_t* ev) {
+  if (ev) HM_HIP(hipEventRecord(ev[0], s));
   const SlotDev* slots = (hi ? C.d_slots_hi : C.d_slots_lo).get<SlotDev>();
   const int ns = (int)C.mats.size();
   if (C.p1_tasks > 0) {
     hipLaunchKernelGGL((k_phase1<LT, VT, NR>), dim3((C.p1_tasks + 3) / 4), dim3(256), 0, s, slots, ns, C.p1_tasks,
                        slot_active, nrr, (const VT*)X, ldx);
   }
+  if (ev) HM_HIP(hipEventRecord(ev[1], s));
   EpiDev<VT> e;
   e.rowscale = (const VT*)ep.rowscale;
   e.a_acc = (VT)ep.a_acc;
@@ -485,18 +487,19 @@ void launch_typed(const Composition& C, int nrr, bool hi, const void* X, int64_t
     hipLaunchKernelGGL((k_phase2<DT, LT, VT, NR>), dim3((C.p2_tasks + 3) / 4), dim3(256), 0, s, slots, ns,
                        C.p2_tasks, slot_active, nrr, (const VT*)X, ldx, (VT*)Y, ldy, e);
   }
+  if (ev) HM_HIP(hipEventRecord(ev[2], s));
   HM_HIP(hipGetLastError());
 }
 
 template <class DT, class LT, class VT>
 void launch_nr(const Composition& C, int nrr, bool hi, const void* X, int64_t ldx, void* Y, int64_t ldy,
-               const Epilogue& ep, const int* sa, hipStream_t s) {
+               const Epilogue& ep, const int* sa, hipStream_t s, hipEvent_t* ev) {
   switch (C.nr) {
-    case 1: launch_typed<DT, LT, VT, 1>(C, nrr, hi, X, ldx, Y, ldy, ep, sa, s); break;
-    case 2: launch_typed<DT, LT, VT, 2>(C, nrr, hi, X, ldx, Y, ldy, ep, sa, s); break;
-    case 4: launch_typed<DT, LT, VT, 4>(C, nrr, hi, X, ldx, Y, ldy, ep, sa, s); break;
-    case 8: launch_typed<DT, LT, VT, 8>(C, nrr, hi, X, ldx, Y, ldy, ep, sa, s); break;
-    case 16: launch_typed<DT, LT, VT, 16>(C, nrr, hi, X, ldx, Y, ldy, ep, sa, s); break;
+    case 1: launch_typed<DT, LT, VT, 1>(C, nrr, hi, X, ldx, Y, ldy, ep, sa, s, ev); break;
+    case 2: launch_typed<DT, LT, VT, 2>(C, nrr, hi, X, ldx, Y, ldy, ep, sa, s, ev); break;
+    case 4: launch_typed<DT, LT, VT, 4>(C, nrr, hi, X, ldx, Y, ldy, ep, sa, s, ev); break;
+    case 8: launch_typed<DT, LT, VT, 8>(C, nrr, hi, X, ldx, Y, ldy, ep, sa, s, ev); break;
+    case 16: launch_typed<DT, LT, VT, 16>(C, nrr, hi, X, ldx, Y, ldy, ep, sa, s, ev); break;
     default: fail(HM_EINVAL, "matvec: composition width must be 1, 2, 4, 8 or 16");
   }
 }
@@ -504,7 +507,7 @@ void launch_nr(const Composition& C, int nrr, bool hi, const void* X, int64_t ld
 }  // namespace
 
 void launch_matvec(const Composition& C, int nrr, int vb, bool hi, const void* X, int64_t ldx, void* Y, int64_t ldy,
-                   const Epilogue& ep, const int* slot_active, hipStream_t s) {
+                   const Epilogue& ep, const int* slot_active, hipStream_t s, hipEvent_t* ev) {
   HM_REQUIRE(!C.mats.empty(), "matvec: empty composition");
   HM_REQUIRE(nrr >= 1 && nrr <= C.nr, "matvec: more right-hand sides than the composition holds");
   const hm_matrix& M0 = *C.mats[0];
@@ -515,14 +518,14 @@ void launch_matvec(const Composition& C, int nrr, int vb, bool hi, const void* X
   const hm_dtype lt = use_hi ? HM_F32 : M0.lr_dtype;
   const hm_dtype dt = M0.dense_dtype;
   if (vb == 8) {
-    if (dt == HM_F64 && lt == HM_F64) return launch_nr<double, double, double>(C, nrr, use_hi, X, ldx, Y, ldy, ep, slot_active, s);
-    if (dt == HM_F32 && lt == HM_F32) return launch_nr<float, float, double>(C, nrr, use_hi, X, ldx, Y, ldy, ep, slot_active, s);
-    if (dt == HM_F32 && lt == HM_BF16) return launch_nr<float, bf16_t, double>(C, nrr, use_hi, X, ldx, Y, ldy, ep, slot_active, s);
-    if (dt == HM_F64 && lt == HM_F32) return launch_nr<double, float, double>(C, nrr, use_hi, X, ldx, Y, ldy, ep, slot_active, s);
+    if (dt == HM_F64 && lt == HM_F64) return launch_nr<double, double, double>(C, nrr, use_hi, X, ldx, Y, ldy, ep, slot_active, s, ev);
+    if (dt == HM_F32 && lt == HM_F32) return launch_nr<float, float, double>(C, nrr, use_hi, X, ldx, Y, ldy, ep, slot_active, s, ev);
+    if (dt == HM_F32 && lt == HM_BF16) return launch_nr<float, bf16_t, double>(C, nrr, use_hi, X, ldx, Y, ldy, ep, slot_active, s, ev);
+    if (dt == HM_F64 && lt == HM_F32) return launch_nr<double, float, double>(C, nrr, use_hi, X, ldx, Y, ldy, ep, slot_active, s, ev);
   } else {
-    if (dt == HM_F32 && lt == HM_F32) return launch_nr<float, float, float>(C, nrr, use_hi, X, ldx, Y, ldy, ep, slot_active, s);
-    if (dt == HM_F32 && lt == HM_BF16) return launch_nr<float, bf16_t, float>(C, nrr, use_hi, X, ldx, Y, ldy, ep, slot_active, s);
-    if (dt == HM_F64 && lt == HM_F64) return launch_nr<double, double, float>(C, nrr, use_hi, X, ldx, Y, ldy, ep, slot_active, s);
+    if (dt == HM_F32 && lt == HM_F32) return launch_nr<float, float, float>(C, nrr, use_hi, X, ldx, Y, ldy, ep, slot_active, s, ev);
+    if (dt == HM_F32 && lt == HM_BF16) return launch_nr<float, bf16_t, float>(C, nrr, use_hi, X, ldx, Y, ldy, ep, slot_active, s, ev);
+    if (dt == HM_F64 && lt == HM_F64) return launch_nr<double, double, float>(C, nrr, use_hi, X, ldx, Y, ldy, ep, slot_active, s, ev);
   }
   fail(HM_EINVAL, "matvec: unsupported combination of storage and vector types");
 }

@@ -12,6 +12,11 @@ import os
 
 import numpy as np
 
+# torch is imported before the library is opened: torch loads its own HIP
+# runtime (SONAME libamdhip64.so.7), and the library's dependency on that
+# SONAME then binds to the same runtime instead of loading a second copy.
+import torch  # noqa: E402,F401
+
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libhmrad.so")
 
@@ -94,6 +99,8 @@ _PROTOS = {
                              C.c_double]),
     "hm_hmatvec_ex": (C.c_int, [_vp, _vp, C.c_int32, C.c_int, C.c_int32, _vp, C.c_int64, _vp, C.c_int64,
                                 C.c_double, C.c_double]),
+    "hm_hmatvec_profile": (C.c_int, [_vp, _vp, C.c_int32, C.c_int, C.c_int32, C.c_int32, C.c_int64,
+                                     _dp, _dp, _dp, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
     "hm_solve_radiosity": (C.c_int, [_vp, _vp, _vp, C.c_int32, _vp, C.c_int64, C.c_double,
                                      C.POINTER(hm_solve_params), _vp, C.c_int64, _vp, C.c_int64,
                                      C.POINTER(hm_solve_info)]),
@@ -289,6 +296,19 @@ def hm_hmatvec(ctx, M: HMatrix, X, Y, alpha=1.0, beta=0.0, use_f32_copy=False):
     _check(lib.hm_hmatvec_ex(ctx.handle, M._h, nr, vt, int(use_f32_copy), _dev_ptr(X), _ld(X), _dev_ptr(Y, X.dtype),
                              _ld(Y), float(alpha), float(beta)), ctx.handle)
     return Y
+
+
+def hm_hmatvec_profile(ctx, M: HMatrix, nrhs=1, vec_dtype=HM_F32, use_f32_copy=False, reps=20,
+                       flush_bytes=512 << 20):
+    """Average per-kernel times (HIP events on ctx's stream) and algorithmic
+    bytes of the two product kernels."""
+    m1, m2, mt = C.c_double(), C.c_double(), C.c_double()
+    b1, b2 = C.c_int64(), C.c_int64()
+    _check(lib.hm_hmatvec_profile(ctx.handle, M._h, int(nrhs), int(vec_dtype), int(use_f32_copy), int(reps),
+                                  int(flush_bytes), C.byref(m1), C.byref(m2), C.byref(mt), C.byref(b1),
+                                  C.byref(b2)), ctx.handle)
+    return {"ms_phase1": m1.value, "ms_phase2": m2.value, "ms_total": mt.value, "bytes_phase1": b1.value,
+            "bytes_phase2": b2.value}
 
 
 def solve_params(rtol=1e-12, restart=30, max_iter=1000, mixed_precision=0, ir_inner_rtol=1e-4, want_q=1,

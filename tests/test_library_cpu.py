@@ -4,7 +4,7 @@
   declares;
 * facet geometry and the cluster / block trees computed by the library's C++
   host code agree with the oracle: trees and block lists bit-exactly
-  (integers), geometry to FP64 rounding;
+  (integers) and the facet geometry bit-exactly (same IEEE operations);
 * argument validation returns HM_EINVAL.
 """
 import ctypes as C
@@ -42,9 +42,8 @@ def test_facets_match_oracle_geometry():
         f = meshes.inward(f)
         c, n, a = hm.hm_facets_from_triangles(v, f, orient=1)
         co, no, ao = geometry.facets_from_triangles(v, f)
-        assert np.max(np.abs(c - co)) <= 1e-15 * np.max(np.abs(co))
-        assert np.max(np.abs(n - no)) <= 4e-16
-        assert np.max(np.abs(a - ao) / ao) <= 4e-16
+        # same IEEE operations in the same order on both sides: bit-exact
+        assert np.array_equal(c, co) and np.array_equal(n, no) and np.array_equal(a, ao)
         # orientation: automatic mode points the normals into a star-shaped cavity
         c2, n2, _ = hm.hm_facets_from_triangles(v, meshes.inward(f), orient=0)
         assert np.all(np.einsum("ij,ij->i", n2, c2) < 0)
