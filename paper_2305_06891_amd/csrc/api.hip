@@ -92,7 +92,7 @@ void check_device_range(hm_ctx& c, const double* v, int64_t n, int64_t ld, int n
 
 int64_t hm_matrix::bytes_device() const {
   int64_t b = (int64_t)(dense.bytes() + U.bytes() + V.bytes() + U_hi.bytes() + V_hi.bytes() + d_perm.bytes());
-  b += (int64_t)(plan.d_p1.bytes() + plan.d_p1_task.bytes() + plan.d_p2.bytes() + plan.d_p2_task.bytes() +
+  b += (int64_t)(plan.d_p1.bytes() + plan.d_p1_task.bytes() + plan.d_p1red.bytes() + plan.d_p2t.bytes() + plan.d_p2.bytes() +
                  plan.d_segs.bytes());
   return b;
 }

@@ -36,24 +36,6 @@ __device__ __forceinline__ double view_factor(const Geo& g, int i, int j) {
 }
 #pragma clang fp contract(on)
 
-struct DnDev {
-  int32_t rb, re, cb, ce;
-  int64_t off;
-};
-
-// One workgroup per dense block; column-major m x n output.
-template <class OT>
-__global__ __launch_bounds__(256) void k_nearfield(const DnDev* __restrict__ blocks, Geo g, OT* __restrict__ out) {
-  const DnDev b = blocks[blockIdx.x];
-  const int m = b.re - b.rb, n = b.ce - b.cb;
-  const int64_t mn = (int64_t)m * n;
-  OT* o = out + b.off;
-  for (int64_t e = threadIdx.x; e < mn; e += blockDim.x) {
-    const int r = (int)(e % m), c = (int)(e / m);
-    o[e] = Cvt<OT>::from_f64(view_factor(g, b.rb + r, b.cb + c));
-  }
-}
-
 struct AcaDev {
   int32_t rb, re, cb, ce;
   int32_t kcap, pad;
@@ -230,55 +212,95 @@ __global__ __launch_bounds__(ACA_T) void k_aca(const AcaDev* __restrict__ blocks
 
 struct CompactDev {
   int64_t su, sv;   // scratch offsets of U, V (doubles)
-  int64_t du, dv;   // destination offsets (elements) in the stage buffers
+  int64_t du, dv;   // destination offsets (elements) in the stage buffer
   int32_t m, n, k, pad;
 };
 
-// Copy the first k columns of the FP64 scratch factors into the storage
-// type (and optionally an FP32 copy).
-template <class OT>
+// Copy the first k columns of the FP64 scratch factors into a stage buffer
+// (FP64 for FP64 storage, FP32 otherwise).
+template <class ST>
 __global__ __launch_bounds__(256) void k_compact(const CompactDev* __restrict__ cd, const double* __restrict__ scratch,
-                                                 OT* __restrict__ U, OT* __restrict__ V, float* __restrict__ Uhi,
-                                                 float* __restrict__ Vhi) {
+                                                 ST* __restrict__ stage) {
   const CompactDev c = cd[blockIdx.x];
   const int64_t nu = (int64_t)c.m * c.k, nv = (int64_t)c.n * c.k;
-  for (int64_t e = threadIdx.x; e < nu; e += blockDim.x) {
-    const double x = scratch[c.su + e];
-    U[c.du + e] = Cvt<OT>::from_f64(x);
-    if (Uhi) Uhi[c.du + e] = (float)x;
-  }
-  for (int64_t e = threadIdx.x; e < nv; e += blockDim.x) {
-    const double x = scratch[c.sv + e];
-    V[c.dv + e] = Cvt<OT>::from_f64(x);
-    if (Vhi) Vhi[c.dv + e] = (float)x;
+  for (int64_t e = threadIdx.x; e < nu; e += blockDim.x) stage[c.du + e] = (ST)scratch[c.su + e];
+  for (int64_t e = threadIdx.x; e < nv; e += blockDim.x) stage[c.dv + e] = (ST)scratch[c.sv + e];
+}
+
+// Near field straight into the phase-2 panels: element (r, c) of the segment
+// goes to base + ((col / 4) * m + r) * 4 + col % 4 with col = col0 + c.
+template <class OT>
+__global__ __launch_bounds__(256) void k_nf_pack(const NfDev* __restrict__ nf, Geo g, OT* __restrict__ out) {
+  const NfDev d = nf[blockIdx.x];
+  const int64_t tot = (int64_t)d.m * d.w;
+  for (int64_t e = threadIdx.x; e < tot; e += blockDim.x) {
+    const int r = (int)(e % d.m), c = (int)(e / d.m);
+    const int col = d.col0 + c;
+    out[d.base + ((int64_t)(col >> 2) * d.m + r) * 4 + (col & 3)] =
+        Cvt<OT>::from_f64(view_factor(g, d.row0 + r, d.cb + c));
   }
 }
 
-// Row scaling of the stored blocks (closed cavity, eqs. (32)-(34)): row i
-// of every dense block and of every U factor is multiplied by scale[i].
-struct ScaleDev {
-  int64_t off;
-  int32_t rb, m, w, kind;  // kind 0 dense (m x w), 1 U (m x w)
-};
-
-template <class DT, class LT>
-__global__ __launch_bounds__(256) void k_rowscale(const ScaleDev* __restrict__ sd, const double* __restrict__ scale,
-                                                  DT* __restrict__ dense, LT* __restrict__ U, float* __restrict__ Uhi) {
-  const ScaleDev s = sd[blockIdx.x];
-  const int64_t tot = (int64_t)s.m * s.w;
+// U factor rows of one tile into a phase-2 panel (storage type and FP32 copy).
+template <class ST, class OT>
+__global__ __launch_bounds__(256) void k_u_pack(const URepack* __restrict__ ur, const void* const* __restrict__ stages,
+                                                OT* __restrict__ out, float* __restrict__ out_hi) {
+  const URepack d = ur[blockIdx.x];
+  const ST* src = (const ST*)stages[d.stage] + d.src;
+  const int64_t tot = (int64_t)d.m * d.k;
   for (int64_t e = threadIdx.x; e < tot; e += blockDim.x) {
-    const int r = (int)(e % s.m);
-    const double f = scale[s.rb + r];
-    if (s.kind == 0) {
-      dense[s.off + e] = Cvt<DT>::from_f64(Cvt<DT>::to_f64(dense[s.off + e]) * f);
-    } else {
-      const int64_t q = s.off + e;
-      if (Uhi) {
-        const double x = (double)Uhi[q] * f;
-        Uhi[q] = (float)x;
-        U[q] = Cvt<LT>::from_f64(x);
+    const int r = (int)(e % d.m), c = (int)(e / d.m);
+    const int col = d.col0 + c;
+    const double x = (double)src[(int64_t)c * d.ld + r];
+    const int64_t o = d.base + ((int64_t)(col >> 2) * d.m + r) * 4 + (col & 3);
+    out[o] = Cvt<OT>::from_f64(x);
+    if (out_hi) out_hi[o] = (float)x;
+  }
+}
+
+// V factor of one block into the group panels of its column cluster:
+// element (r, l) goes to group g = pc / 64 (pc = lc0 + l), at
+// ((r / 4) * gw + pc % 64) * 4 + r % 4 inside the group.
+template <class ST, class OT>
+__global__ __launch_bounds__(256) void k_v_pack(const VRepack* __restrict__ vr, const void* const* __restrict__ stages,
+                                                OT* __restrict__ out, float* __restrict__ out_hi) {
+  const VRepack d = vr[blockIdx.x];
+  const ST* src = (const ST*)stages[d.stage] + d.src;
+  const int64_t tot = (int64_t)d.n * d.k;
+  for (int64_t e = threadIdx.x; e < tot; e += blockDim.x) {
+    const int r = (int)(e % d.n), l = (int)(e / d.n);
+    const int pc = d.lc0 + l;
+    const int g = pc / P1_GW, lp = pc % P1_GW;
+    const int gw = min(P1_GW, d.ktau - g * P1_GW);
+    const int64_t o = d.tau_base + (int64_t)g * P1_GW * d.np + ((int64_t)(r >> 2) * gw + lp) * 4 + (r & 3);
+    const double x = (double)src[e];
+    out[o] = Cvt<OT>::from_f64(x);
+    if (out_hi) out_hi[o] = (float)x;
+  }
+}
+
+// Row scaling of the phase-2 panels (closed cavity, eqs. (32)-(34)): every
+// element of row row0 + r of a tile's items is multiplied by scale[row0 + r].
+template <class DT, class LT>
+__global__ __launch_bounds__(256) void k_panel_rowscale(const P2Tile* __restrict__ tiles, const P2Item* __restrict__ items,
+                                                        const double* __restrict__ scale, DT* __restrict__ dense,
+                                                        LT* __restrict__ U, float* __restrict__ Uhi) {
+  const P2Tile tl = tiles[blockIdx.x];
+  for (int k = 0; k < tl.nit; ++k) {
+    const P2Item it = items[tl.it0 + k];
+    const int64_t tot = (int64_t)tl.m * it.w;
+    for (int64_t e = threadIdx.x; e < tot; e += blockDim.x) {
+      const int r = (int)((e >> 2) % tl.m);
+      const double f = scale[tl.row0 + r];
+      const int64_t o = it.base + e;
+      if (it.kind == 0) {
+        dense[o] = Cvt<DT>::from_f64(Cvt<DT>::to_f64(dense[o]) * f);
+      } else if (Uhi) {
+        const double x = (double)Uhi[o] * f;
+        Uhi[o] = (float)x;
+        U[o] = Cvt<LT>::from_f64(x);
       } else {
-        U[q] = Cvt<LT>::from_f64(Cvt<LT>::to_f64(U[q]) * f);
+        U[o] = Cvt<LT>::from_f64(Cvt<LT>::to_f64(U[o]) * f);
       }
     }
   }
@@ -309,7 +331,7 @@ void dispatch_dtype(hm_dtype t, F&& f) {
 
 }  // namespace
 
-void closed_row_scale(hm_matrix& M, const std::vector<DnInfo>& dn, const std::vector<LrInfo>& lr, hipStream_t s);
+void closed_row_scale(hm_matrix& M, hipStream_t s);
 
 hm_matrix* assemble(hm_ctx& ctx, const hm_tree& t, const hm_assembly_params& p) {
   hipStream_t s = ctx.stream;
@@ -340,26 +362,21 @@ hm_matrix* assemble(hm_ctx& ctx, const hm_tree& t, const hm_assembly_params& p) 
 
   // ---- ACA on the admissible blocks, in batches bounded by a scratch budget
   const int kmax = std::min<int>(p.k_max, ACA_KMAX);
+  const bool st64 = p.lowrank_dtype == HM_F64;
+  const size_t ses = st64 ? 8 : 4;
   size_t free_b = 0, total_b = 0;
   HM_HIP(hipMemGetInfo(&free_b, &total_b));
   const int64_t budget = std::max<int64_t>(256ll << 20, std::min<int64_t>(8ll << 30, (int64_t)free_b / 4));
-  std::vector<int32_t> order(t.lowrank.size());
-  for (size_t q = 0; q < order.size(); ++q) order[q] = (int32_t)q;
   std::vector<LrInfo> lr;
-  std::vector<DnInfo> dn;
-  for (const auto& b : t.dense) dn.push_back(DnInfo{b, 0});
-  struct Stage { DevBuf U, V, Uhi, Vhi; int64_t nu, nv; };
-  std::vector<Stage> stages;
-  std::vector<int64_t> lr_stage_u, lr_stage_v;  // offsets inside the stage; fixed up below
-  std::vector<int32_t> lr_stage;
-  const size_t es = dtype_size(p.lowrank_dtype);
+  std::vector<BlockRef> dn(t.dense.begin(), t.dense.end());
+  std::vector<DevBuf> stages;
   DevBuf scratch, flags, d_blk, d_rank, d_status, d_cd;
   size_t pos = 0;
-  while (pos < order.size()) {
+  while (pos < t.lowrank.size()) {
     std::vector<AcaDev> batch;
     int64_t sd = 0, sf = 0;
-    while (pos < order.size()) {
-      const BlockRef& b = t.lowrank[order[pos]];
+    while (pos < t.lowrank.size()) {
+      const BlockRef& b = t.lowrank[pos];
       const int m = b.re - b.rb, nn = b.ce - b.cb;
       const int64_t kc = rank_cap(m, nn, kmax);
       const int64_t need = kc * (m + nn) * 8 + m * 4;
@@ -371,61 +388,49 @@ hm_matrix* assemble(hm_ctx& ctx, const hm_tree& t, const hm_assembly_params& p) 
       ++pos;
     }
     // largest blocks first for the hardware dispatcher
-    std::vector<int32_t> bidx(batch.size());
-    for (size_t q = 0; q < bidx.size(); ++q) bidx[q] = (int32_t)q;
-    std::vector<AcaDev> sorted(batch.size());
-    std::stable_sort(bidx.begin(), bidx.end(), [&](int32_t x, int32_t y) {
-      return (int64_t)(batch[x].re - batch[x].rb) * (batch[x].ce - batch[x].cb) >
-             (int64_t)(batch[y].re - batch[y].rb) * (batch[y].ce - batch[y].cb);
+    std::stable_sort(batch.begin(), batch.end(), [](const AcaDev& x, const AcaDev& y) {
+      return (int64_t)(x.re - x.rb) * (x.ce - x.cb) > (int64_t)(y.re - y.rb) * (y.ce - y.cb);
     });
-    for (size_t q = 0; q < bidx.size(); ++q) sorted[q] = batch[bidx[q]];
     if ((size_t)sd * 8 > scratch.bytes()) scratch.alloc((size_t)sd * 8);
     if ((size_t)sf * 4 > flags.bytes()) flags.alloc((size_t)sf * 4);
-    upload(d_blk, sorted, s);
-    d_rank.alloc(sorted.size() * 4);
-    d_status.alloc(sorted.size() * 4);
-    hipLaunchKernelGGL(k_aca, dim3((unsigned)sorted.size()), dim3(ACA_T), 0, s, d_blk.get<AcaDev>(), g, p.aca_tol,
+    upload(d_blk, batch, s);
+    d_rank.alloc(batch.size() * 4);
+    d_status.alloc(batch.size() * 4);
+    hipLaunchKernelGGL(k_aca, dim3((unsigned)batch.size()), dim3(ACA_T), 0, s, d_blk.get<AcaDev>(), g, p.aca_tol,
                        scratch.get<double>(), flags.get<int>(), d_rank.get<int>(), d_status.get<int>());
     HM_HIP(hipGetLastError());
-    std::vector<int> rk(sorted.size()), st(sorted.size());
+    std::vector<int> rk(batch.size()), st(batch.size());
     HM_HIP(hipMemcpyAsync(rk.data(), d_rank.get(), rk.size() * 4, hipMemcpyDeviceToHost, s));
     HM_HIP(hipMemcpyAsync(st.data(), d_status.get(), st.size() * 4, hipMemcpyDeviceToHost, s));
     HM_HIP(hipStreamSynchronize(s));
-    // classify: low rank (k(m+n) < mn and converged), rank zero (dropped), dense fallback
+    // classify: low rank (converged and k(m+n) < mn), rank zero (dropped), dense fallback
     std::vector<CompactDev> cd;
-    Stage stg;
-    stg.nu = stg.nv = 0;
-    for (size_t q = 0; q < sorted.size(); ++q) {
-      const AcaDev& a = sorted[q];
+    int64_t off = 0;
+    for (size_t q = 0; q < batch.size(); ++q) {
+      const AcaDev& a = batch[q];
       const int m = a.re - a.rb, nn = a.ce - a.cb;
       const int k = rk[q];
       BlockRef br{a.rb, a.re, a.cb, a.ce};
       if (!st[q] || (int64_t)k * (m + nn) >= (int64_t)m * nn) {
-        dn.push_back(DnInfo{br, 0});
+        dn.push_back(br);
         M->n_fallback++;
         continue;
       }
       if (k == 0) continue;  // exactly zero block
-      cd.push_back(CompactDev{a.u_off, a.v_off, stg.nu, stg.nv, m, nn, k, 0});
-      lr.push_back(LrInfo{br, k, stg.nu, stg.nv});
-      lr_stage.push_back((int32_t)stages.size());
-      stg.nu += (int64_t)m * k;
-      stg.nv += (int64_t)nn * k;
+      cd.push_back(CompactDev{a.u_off, a.v_off, off, off + (int64_t)m * k, m, nn, k, 0});
+      lr.push_back(LrInfo{br, k, (int32_t)stages.size(), off, off + (int64_t)m * k});
+      off += (int64_t)k * (m + nn);
     }
+    DevBuf stg;
     if (!cd.empty()) {
-      stg.U.alloc(stg.nu * es);
-      stg.V.alloc(stg.nv * es);
-      if (M->has_hi) {
-        stg.Uhi.alloc(stg.nu * 4);
-        stg.Vhi.alloc(stg.nv * 4);
-      }
+      stg.alloc(off * ses);
       upload(d_cd, cd, s);
-      dispatch_dtype(p.lowrank_dtype, [&](auto* tag) {
-        using OT = std::remove_pointer_t<decltype(tag)>;
-        hipLaunchKernelGGL(k_compact<OT>, dim3((unsigned)cd.size()), dim3(256), 0, s, d_cd.get<CompactDev>(),
-                           scratch.get<double>(), stg.U.get<OT>(), stg.V.get<OT>(), stg.Uhi.get<float>(),
-                           stg.Vhi.get<float>());
-      });
+      if (st64)
+        hipLaunchKernelGGL(k_compact<double>, dim3((unsigned)cd.size()), dim3(256), 0, s, d_cd.get<CompactDev>(),
+                           scratch.get<double>(), stg.get<double>());
+      else
+        hipLaunchKernelGGL(k_compact<float>, dim3((unsigned)cd.size()), dim3(256), 0, s, d_cd.get<CompactDev>(),
+                           scratch.get<double>(), stg.get<float>());
       HM_HIP(hipGetLastError());
       HM_HIP(hipStreamSynchronize(s));  // scratch is reused by the next batch
     }
@@ -433,111 +438,85 @@ hm_matrix* assemble(hm_ctx& ctx, const hm_tree& t, const hm_assembly_params& p) 
   }
   scratch.release();
   flags.release();
-
-  // ---- consolidate the factor stages into one U and one V arena
-  std::vector<int64_t> su(stages.size() + 1, 0), sv(stages.size() + 1, 0);
-  for (size_t q = 0; q < stages.size(); ++q) {
-    su[q + 1] = su[q] + stages[q].nu;
-    sv[q + 1] = sv[q] + stages[q].nv;
-  }
-  M->U.alloc(su.back() * es);
-  M->V.alloc(sv.back() * es);
-  if (M->has_hi) {
-    M->U_hi.alloc(su.back() * 4);
-    M->V_hi.alloc(sv.back() * 4);
-  }
-  for (size_t q = 0; q < stages.size(); ++q) {
-    if (stages[q].nu == 0) continue;
-    HM_HIP(hipMemcpyAsync(M->U.get<char>() + su[q] * es, stages[q].U.get(), stages[q].nu * es, hipMemcpyDeviceToDevice, s));
-    HM_HIP(hipMemcpyAsync(M->V.get<char>() + sv[q] * es, stages[q].V.get(), stages[q].nv * es, hipMemcpyDeviceToDevice, s));
-    if (M->has_hi) {
-      HM_HIP(hipMemcpyAsync(M->U_hi.get<char>() + su[q] * 4, stages[q].Uhi.get(), stages[q].nu * 4, hipMemcpyDeviceToDevice, s));
-      HM_HIP(hipMemcpyAsync(M->V_hi.get<char>() + sv[q] * 4, stages[q].Vhi.get(), stages[q].nv * 4, hipMemcpyDeviceToDevice, s));
-    }
-  }
-  for (size_t q = 0; q < lr.size(); ++q) {
-    lr[q].u_off += su[lr_stage[q]];
-    lr[q].v_off += sv[lr_stage[q]];
-  }
-  HM_HIP(hipStreamSynchronize(s));
-  stages.clear();
-
-  // ---- dense near field (tree-dense blocks and ACA fallbacks)
-  int64_t doff = 0;
-  std::vector<DnDev> dd;
-  for (auto& d : dn) {
-    d.off = doff;
-    doff += (int64_t)(d.b.re - d.b.rb) * (d.b.ce - d.b.cb);
-    dd.push_back(DnDev{d.b.rb, d.b.re, d.b.cb, d.b.ce, d.off});
-  }
-  const size_t ds = dtype_size(p.dense_dtype);
-  M->dense.alloc(doff * ds);
-  if (!dd.empty()) {
-    DevBuf d_dd;
-    upload(d_dd, dd, s);
-    if (p.dense_dtype == HM_F64)
-      hipLaunchKernelGGL(k_nearfield<double>, dim3((unsigned)dd.size()), dim3(256), 0, s, d_dd.get<DnDev>(), g,
-                         M->dense.get<double>());
-    else
-      hipLaunchKernelGGL(k_nearfield<float>, dim3((unsigned)dd.size()), dim3(256), 0, s, d_dd.get<DnDev>(), g,
-                         M->dense.get<float>());
-    HM_HIP(hipGetLastError());
-    HM_HIP(hipStreamSynchronize(s));
-  }
+  std::sort(dn.begin(), dn.end(), [](const BlockRef& x, const BlockRef& y) {
+    return x.rb != y.rb ? x.rb < y.rb : x.cb < y.cb;
+  });
 
   // ---- statistics
-  M->dense_entries = doff;
+  for (const auto& d : dn) M->dense_entries += (int64_t)(d.re - d.rb) * (d.ce - d.cb);
   M->n_dense_blocks = (int64_t)dn.size();
   M->n_lr_blocks = (int64_t)lr.size();
-  int64_t ktot = 0, lre = 0;
   for (const auto& l : lr) {
-    ktot += l.k;
-    lre += (int64_t)l.k * ((l.b.re - l.b.rb) + (l.b.ce - l.b.cb));
+    M->rank_sum += l.k;
     M->u_entries += (int64_t)l.k * (l.b.re - l.b.rb);
     M->v_entries += (int64_t)l.k * (l.b.ce - l.b.cb);
     M->max_rank = std::max(M->max_rank, l.k);
   }
-  M->Ktot = ktot;
-  M->rank_sum = ktot;
-  M->lr_entries = lre;
+  M->lr_entries = M->u_entries + M->v_entries;
 
-  build_plan(*M, lr, dn, t, s);
-  if (p.closed_row_scale) closed_row_scale(*M, dn, lr, s);
+  // ---- plan, panel arenas, packing
+  PackLists pk;
+  build_plan(*M, lr, dn, t, pk, s);
+  const Plan& P = M->plan;
+  const size_t ds = dtype_size(p.dense_dtype), ls = dtype_size(p.lowrank_dtype);
+  M->dense.alloc(std::max<int64_t>(1, P.dense_elems) * ds);
+  M->U.alloc(std::max<int64_t>(1, P.u_elems) * ls);
+  M->V.alloc(std::max<int64_t>(1, P.v_elems) * ls);
+  HM_HIP(hipMemsetAsync(M->dense.get(), 0, M->dense.bytes(), s));
+  HM_HIP(hipMemsetAsync(M->U.get(), 0, M->U.bytes(), s));
+  HM_HIP(hipMemsetAsync(M->V.get(), 0, M->V.bytes(), s));
+  if (M->has_hi) {
+    M->U_hi.alloc(std::max<int64_t>(1, P.u_elems) * 4);
+    M->V_hi.alloc(std::max<int64_t>(1, P.v_elems) * 4);
+    HM_HIP(hipMemsetAsync(M->U_hi.get(), 0, M->U_hi.bytes(), s));
+    HM_HIP(hipMemsetAsync(M->V_hi.get(), 0, M->V_hi.bytes(), s));
+  }
+  if (!pk.nf.empty()) {
+    DevBuf d_nf;
+    upload(d_nf, pk.nf, s);
+    if (p.dense_dtype == HM_F64)
+      hipLaunchKernelGGL(k_nf_pack<double>, dim3((unsigned)pk.nf.size()), dim3(256), 0, s, d_nf.get<NfDev>(), g,
+                         M->dense.get<double>());
+    else
+      hipLaunchKernelGGL(k_nf_pack<float>, dim3((unsigned)pk.nf.size()), dim3(256), 0, s, d_nf.get<NfDev>(), g,
+                         M->dense.get<float>());
+    HM_HIP(hipGetLastError());
+    HM_HIP(hipStreamSynchronize(s));
+  }
+  if (!lr.empty()) {
+    std::vector<const void*> sp(stages.size());
+    for (size_t q = 0; q < stages.size(); ++q) sp[q] = stages[q].get();
+    DevBuf d_sp, d_ur, d_vr;
+    upload(d_sp, sp, s);
+    upload(d_ur, pk.ur, s);
+    upload(d_vr, pk.vr, s);
+    float* uh = M->has_hi ? M->U_hi.get<float>() : nullptr;
+    float* vh = M->has_hi ? M->V_hi.get<float>() : nullptr;
+    auto go = [&](auto* stag, auto* otag) {
+      using ST = std::remove_pointer_t<decltype(stag)>;
+      using OT = std::remove_pointer_t<decltype(otag)>;
+      if (!pk.ur.empty())
+        hipLaunchKernelGGL((k_u_pack<ST, OT>), dim3((unsigned)pk.ur.size()), dim3(256), 0, s, d_ur.get<URepack>(),
+                           d_sp.get<const void*>(), M->U.get<OT>(), uh);
+      if (!pk.vr.empty())
+        hipLaunchKernelGGL((k_v_pack<ST, OT>), dim3((unsigned)pk.vr.size()), dim3(256), 0, s, d_vr.get<VRepack>(),
+                           d_sp.get<const void*>(), M->V.get<OT>(), vh);
+    };
+    if (p.lowrank_dtype == HM_F64) go((double*)0, (double*)0);
+    else if (p.lowrank_dtype == HM_F32) go((float*)0, (float*)0);
+    else go((float*)0, (bf16_t*)0);
+    HM_HIP(hipGetLastError());
+    HM_HIP(hipStreamSynchronize(s));
+  }
+  stages.clear();
+  if (p.closed_row_scale) closed_row_scale(*M, s);
   HM_HIP(hipStreamSynchronize(s));
   return M.release();
 }
 
-void apply_row_scale(hm_matrix& M, const std::vector<DnInfo>& dn, const std::vector<LrInfo>& lr,
-                     const double* d_scale, hipStream_t s) {
-  std::vector<ScaleDev> sd;
-  for (const auto& d : dn)
-    sd.push_back(ScaleDev{d.off, d.b.rb, d.b.re - d.b.rb, d.b.ce - d.b.cb, 0});
-  for (const auto& l : lr) sd.push_back(ScaleDev{l.u_off, l.b.rb, l.b.re - l.b.rb, l.k, 1});
-  if (sd.empty()) return;
-  DevBuf d_sd;
-  upload(d_sd, sd, s);
-  auto go = [&](auto* dt, auto* lt) {
-    using DT = std::remove_pointer_t<decltype(dt)>;
-    using LT = std::remove_pointer_t<decltype(lt)>;
-    hipLaunchKernelGGL((k_rowscale<DT, LT>), dim3((unsigned)sd.size()), dim3(256), 0, s, d_sd.get<ScaleDev>(),
-                       d_scale, M.dense.get<DT>(), M.U.get<LT>(), M.has_hi ? M.U_hi.get<float>() : nullptr);
-  };
-  if (M.dense_dtype == HM_F64) {
-    if (M.lr_dtype == HM_F64) go((double*)0, (double*)0);
-    else if (M.lr_dtype == HM_F32) go((double*)0, (float*)0);
-    else go((double*)0, (bf16_t*)0);
-  } else {
-    if (M.lr_dtype == HM_F64) go((float*)0, (double*)0);
-    else if (M.lr_dtype == HM_F32) go((float*)0, (float*)0);
-    else go((float*)0, (bf16_t*)0);
-  }
-  HM_HIP(hipGetLastError());
-  HM_HIP(hipStreamSynchronize(s));
-}
-
 // Closed-cavity treatment (eqs. (32)-(34)): s = F_H 1 (the per-area row sum),
 // c = clamp(s, 0, 1), rows with c != 0 divided by c.
-void closed_row_scale(hm_matrix& M, const std::vector<DnInfo>& dn, const std::vector<LrInfo>& lr, hipStream_t s) {
+void closed_row_scale(hm_matrix& M, hipStream_t s) {
   const int64_t n = M.n;
   DevBuf ones(n * 8), rs(n * 8), scale(n * 8);
   std::vector<double> h(n, 1.0);
@@ -548,7 +527,28 @@ void closed_row_scale(hm_matrix& M, const std::vector<DnInfo>& dn, const std::ve
   hipLaunchKernelGGL(k_closed_scale, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, rs.get<double>(),
                      scale.get<double>(), n);
   HM_HIP(hipGetLastError());
-  apply_row_scale(M, dn, lr, scale.get<double>(), s);
+  const unsigned ni = (unsigned)M.plan.p2t.size();
+  if (ni) {
+    const P2Tile* tl = M.plan.d_p2t.get<P2Tile>();
+    const P2Item* it = M.plan.d_p2.get<P2Item>();
+    float* uh = M.has_hi ? M.U_hi.get<float>() : nullptr;
+    auto go = [&](auto* dt, auto* lt) {
+      using DT = std::remove_pointer_t<decltype(dt)>;
+      using LT = std::remove_pointer_t<decltype(lt)>;
+      hipLaunchKernelGGL((k_panel_rowscale<DT, LT>), dim3(ni), dim3(256), 0, s, tl, it, scale.get<double>(),
+                         M.dense.get<DT>(), M.U.get<LT>(), uh);
+    };
+    if (M.dense_dtype == HM_F64) {
+      if (M.lr_dtype == HM_F64) go((double*)0, (double*)0);
+      else go((double*)0, (float*)0);
+    } else {
+      if (M.lr_dtype == HM_F32) go((float*)0, (float*)0);
+      else if (M.lr_dtype == HM_BF16) go((float*)0, (bf16_t*)0);
+      else go((float*)0, (double*)0);
+    }
+    HM_HIP(hipGetLastError());
+  }
+  HM_HIP(hipStreamSynchronize(s));
 }
 
 }  // namespace hm

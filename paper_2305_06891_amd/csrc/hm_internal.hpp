@@ -124,72 +124,111 @@ namespace hm {
 void build_tree(hm_tree& t);  // fills perm, nodes, leaves, dense, lowrank from c, params
 
 // ---------------------------------------------------------------- matvec plan
-// Phase 1 item: partial t = V_b^T x over rows [r0, r0+nr) of V_b and rank
-// columns [l0, l0+nl).
+// Both phases stream panels laid out so that every lane loads 16 contiguous
+// bytes (4 elements) and a wave's load covers one contiguous run:
+//  * phase 2 item panel (m rows <= 64, w columns, w % 4 == 0): element
+//    (r, c) at base + ((c / 4) * m + r) * 4 + c % 4  (lane = row);
+//  * phase 1 group panel (gw <= 64 rank columns of the V factors of one
+//    column cluster, rows padded to a multiple of 4): element (r, l) at
+//    base + ((r / 4) * gw + l) * 4 + r % 4  (lane = rank column).
+constexpr int QW = 4;          // elements per lane vector
+constexpr int P2_MAXW = 256;   // padded columns per phase-2 item
+constexpr int P1_GW = 64;      // rank columns per phase-1 group (one per lane)
+constexpr int P1_RCH = 256;    // rows per phase-1 item (multiple of 4)
+constexpr int P1_XST = 256;    // rows of x staged in LDS at a time
+constexpr int TILE = 64;       // rows per phase-2 tile (lane = row)
+constexpr int P2_WAVES = 8;    // waves per phase-2 workgroup (one tile each)
+constexpr int P2_MAXSEG = 64;  // input runs per phase-2 item
+
+// Phase 1 item: t (or a partial of it) for the gw columns of one group over
+// row quads [q0, q0 + nq) of its column cluster.
 struct P1Item {
-  int64_t v_off;    // element offset of V_b (column-major n_b x k_b)
-  int32_t ld;       // n_b
-  int32_t r0, nr;
-  int32_t l0, nl;
-  int32_t xrow;     // permuted x row of the chunk's first row
-  int32_t trow;     // t index of rank column l0
-  int32_t part;     // first partial slot of the (block, column group); -1 if single
-  int32_t pidx, nparts;
-  int32_t counter;
+  int64_t base;     // element offset of the group panel
+  int32_t gw;       // columns in the group
+  int32_t q0, nq;   // row quads
+  int32_t nrows;    // valid rows of the cluster (the rest is zero padding)
+  int32_t xrow;     // permuted x row of the cluster's first row
+  int32_t trow;     // t index of the group's first column
+  int32_t part;     // partial slot of this item; -1: write t directly
   int32_t pad;
 };
 
-// Phase 2 item: rows [row0, row0+m) (m <= 64) times a run of segments.
+// Groups whose rows are split over several items: t = sum of their partials
+// (added in item order by a separate kernel).
+struct P1Red {
+  int32_t trow, gw, part0, nparts;
+};
+
+// Phase 2 tile: rows [row0, row0+m) and its items [it0, it0+nit); wave w of
+// the tile's workgroup takes items it0 + w, it0 + w + P2_WAVES, ...
+struct P2Tile {
+  int32_t row0, m, it0, nit;
+};
+
+// Phase 2 item: a panel of w columns (m rows of its tile).
 struct P2Item {
-  int32_t row0, m;
+  int64_t base;     // element offset of the panel in its arena
+  int32_t w;        // padded column count (multiple of 4)
   int32_t seg0, nseg;
-  int32_t part, pidx, nparts, counter;
+  int32_t kind;     // 0: dense arena, 1: U arena
 };
 
-// One segment: columns of a dense block or of a U factor, restricted to the
-// rows of a tile; column c of the segment starts at arena + off + c*ld.
+// Input run of a phase-2 item: columns [col0, col0+w) take x (src >= 0) or
+// t (index ~src) entries src.., src+w-1.
 struct Seg {
-  int64_t off;
-  int32_t ld;
-  int32_t w;
-  int32_t src;   // >= 0: x row src + c; < 0: t index (~src) + c
-  int32_t kind;  // 0: dense arena, 1: U arena
+  int32_t col0, w, src, pad;
 };
-
-constexpr int KG = 8;        // rank columns per phase-1 item
-constexpr int P1_RCH = 2048; // rows per phase-1 item
-constexpr int TILE = 64;     // rows per phase-2 tile (one wave, lane = row)
 
 struct Plan {
   std::vector<P1Item> p1;
   std::vector<int32_t> p1_task;  // item begin per task, size ntasks + 1
+  std::vector<P1Red> p1red;
+  std::vector<P2Tile> p2t;
   std::vector<P2Item> p2;
-  std::vector<int32_t> p2_task;
   std::vector<Seg> segs;
-  int32_t n_p1_parts = 0, n_p2_parts = 0;
-  int32_t n_p1_counters = 0, n_p2_counters = 0;
-  DevBuf d_p1, d_p1_task, d_p2, d_p2_task, d_segs;
+  int32_t n_p1_parts = 0;
+  int64_t dense_elems = 0, u_elems = 0, v_elems = 0;  // panel arena sizes
+  DevBuf d_p1, d_p1_task, d_p1red, d_p2t, d_p2, d_segs;
 };
 
 // Device descriptor of one slot of a batched product.
 struct SlotDev {
   const P1Item* p1;
   const int32_t* p1_task;
+  const P1Red* p1red;
+  const P2Tile* p2t;
   const P2Item* p2;
-  const int32_t* p2_task;
   const Seg* segs;
   const void* dense;
   const void* U;
   const void* V;
-  unsigned* cnt1;
-  unsigned* cnt2;
   void* part1;
-  void* part2;
   void* t;
   int64_t ldt;
   int64_t xoff;
-  int32_t p1_task_begin, p2_task_begin;
-  int32_t n, slot;
+  int32_t p1_task_begin, p1red_begin, p2_tile_begin;
+  int32_t n, slot, pad;
+};
+
+// Packing work lists produced with the plan (consumed once by assembly).
+struct NfDev {     // dense segment: F(row0 + r, cb + c) -> item panel
+  int64_t base;
+  int32_t row0, m, cb, w, col0, pad;
+};
+struct URepack {   // U_b rows of a tile -> item panel
+  int64_t src;     // stage element offset of U_b(row0 - rb, 0)
+  int64_t base;
+  int32_t stage, ld, m, k, col0, pad;
+};
+struct VRepack {   // V_b -> group panels of its column cluster
+  int64_t src;     // stage element offset of V_b
+  int64_t tau_base;
+  int32_t stage, n, k, lc0, ktau, np;
+};
+struct PackLists {
+  std::vector<NfDev> nf;
+  std::vector<URepack> ur;
+  std::vector<VRepack> vr;
 };
 
 }  // namespace hm
@@ -224,15 +263,18 @@ struct Composition {
   std::vector<const hm_matrix*> mats;
   std::vector<int64_t> xoff;  // row offset per slot
   int64_t N = 0;              // total rows
-  int32_t p1_tasks = 0, p2_tasks = 0;
+  int32_t p1_tasks = 0, p1_reds = 0, p2_tiles = 0;
   std::vector<SlotDev> slots_lo, slots_hi;  // hi: FP32 copies of BF16 factors
   DevBuf d_slots_lo, d_slots_hi;
-  DevBuf t, part1, part2, cnt1, cnt2;
+  DevBuf t, part1;
   int64_t bytes_lo = 0, bytes_hi = 0;     // algorithmic matrix bytes per product
 };
 
-void build_plan(hm_matrix& M, const std::vector<struct LrInfo>& lr, const std::vector<struct DnInfo>& dn,
-                const hm_tree& t, hipStream_t s);
+void build_plan(hm_matrix& M, const std::vector<struct LrInfo>& lr, const std::vector<BlockRef>& dn,
+                const hm_tree& t, PackLists& pk, hipStream_t s);
+// The host part of build_plan (no device calls): items, tasks, arena sizes.
+void plan_host(hm_matrix& M, const std::vector<struct LrInfo>& lr, const std::vector<BlockRef>& dn,
+               const hm_tree& t, PackLists& pk);
 
 std::unique_ptr<Composition> make_composition(const std::vector<const hm_matrix*>& mats, int nr,
                                               int vec_bytes, hipStream_t s);
@@ -258,11 +300,8 @@ int64_t matrix_bytes(const hm_matrix& M, bool hi);
 struct LrInfo {
   BlockRef b;
   int32_t k;
-  int64_t u_off, v_off;  // element offsets in the U / V arenas
-};
-struct DnInfo {
-  BlockRef b;
-  int64_t off;           // element offset in the dense arena (column-major m x n)
+  int32_t stage;         // stage buffer holding the FP32/FP64 factors
+  int64_t su, sv;        // element offsets of U_b (m x k) and V_b (n x k), column-major
 };
 
 // ---------------------------------------------------------------- misc helpers

@@ -2,13 +2,17 @@
 //   phase 1:  t_b = V_b^T x_tau          for every low-rank block b
 //   phase 2:  y_sigma += D_b x_tau  and  y_sigma += U_b t_b, row tile by row tile.
 // Both phases are bandwidth kernels: every stored entry is read once per
-// product.  Work is cut into items of similar byte size; an item whose
-// output is shared with other items writes a partial sum, and the last item
-// to finish (device-scope atomic counter) adds the partials in a fixed
-// order, so results do not depend on scheduling.  Several matrices can be
-// multiplied in one launch ("slots" of a block-diagonal operator).
+// product, from panels packed so that each lane loads 16 contiguous bytes and
+// each wave load is one contiguous run (see the layouts in hm_internal.hpp).
+// Phase 2 runs one workgroup per row tile whose waves share the tile's
+// byte-balanced items and add their sums in LDS in a fixed order; phase-1
+// groups whose rows are split over several items write partials that a
+// separate kernel adds in item order.  No kernel communicates across
+// workgroups, so results do not depend on scheduling.  Several matrices can
+// be multiplied in one launch ("slots" of a block-diagonal operator).
 #include <algorithm>
 #include <cmath>
+#include <map>
 #include <numeric>
 
 #include "dev_common.hpp"
@@ -19,24 +23,85 @@ namespace hm {
 // ------------------------------------------------------------------ plan
 namespace {
 
-constexpr int64_t ITEM_BYTES = 64 << 10;  // target matrix bytes per phase-2 item
-constexpr int64_t TASK_BYTES = 24 << 10;  // minimum matrix bytes per wave task
+constexpr int64_t ITEM_BYTES = 64 << 10;  // target matrix bytes per phase-2 item (FP32)
+constexpr int64_t TASK_BYTES = 32 << 10;  // minimum matrix bytes per wave task
 
 struct Tile {
   int32_t row0, m;
 };
 
+inline int32_t round4(int32_t v) { return (v + 3) & ~3; }
+
 }  // namespace
 
-void build_plan(hm_matrix& M, const std::vector<LrInfo>& lr, const std::vector<DnInfo>& dn, const hm_tree& t,
-                hipStream_t s) {
+void plan_host(hm_matrix& M, const std::vector<LrInfo>& lr, const std::vector<BlockRef>& dn, const hm_tree& t,
+               PackLists& pk) {
   Plan& P = M.plan;
   P.p1.clear();
+  P.p1red.clear();
+  P.p2t.clear();
   P.p2.clear();
   P.segs.clear();
-  P.p1_task.clear();
-  P.p2_task.clear();
-  // tiles: leaves cut into <= TILE rows
+  pk.nf.clear();
+  pk.ur.clear();
+  pk.vr.clear();
+  // ---- column clusters of the low-rank blocks, their group panels and t layout
+  std::vector<int32_t> ord(lr.size());
+  std::iota(ord.begin(), ord.end(), 0);
+  std::stable_sort(ord.begin(), ord.end(), [&](int32_t a, int32_t b) {
+    const BlockRef &x = lr[a].b, &y = lr[b].b;
+    if (x.cb != y.cb) return x.cb < y.cb;
+    if (x.ce != y.ce) return x.ce < y.ce;
+    return x.rb < y.rb;
+  });
+  std::vector<int32_t> tidx(lr.size());  // t index of rank column 0 of each block
+  int64_t tcur = 0, vcur = 0;
+  int32_t parts1 = 0;
+  std::vector<int64_t> item_bytes1;
+  for (size_t q = 0; q < ord.size();) {
+    size_t e = q;
+    const BlockRef& b0 = lr[ord[q]].b;
+    int32_t ktau = 0;
+    while (e < ord.size() && lr[ord[e]].b.cb == b0.cb && lr[ord[e]].b.ce == b0.ce) ktau += lr[ord[e++]].k;
+    const int32_t n = b0.ce - b0.cb, np = round4(n);
+    const int64_t tau_base = vcur;
+    int32_t lc = 0;
+    for (size_t z = q; z < e; ++z) {
+      const LrInfo& L = lr[ord[z]];
+      tidx[ord[z]] = (int32_t)(tcur + lc);
+      pk.vr.push_back(VRepack{L.sv, tau_base, L.stage, n, L.k, lc, ktau, np});
+      lc += L.k;
+    }
+    const int32_t ngroups = (ktau + P1_GW - 1) / P1_GW;
+    const int32_t nq = np / 4;
+    const int32_t qch = P1_RCH / 4;
+    const int32_t nch = (nq + qch - 1) / qch;
+    for (int32_t g = 0; g < ngroups; ++g) {
+      const int32_t gw = std::min(P1_GW, ktau - g * P1_GW);
+      const int32_t trow = (int32_t)(tcur + g * P1_GW);
+      if (nch > 1) P.p1red.push_back(P1Red{trow, gw, parts1, nch});
+      for (int32_t c = 0; c < nch; ++c) {
+        P1Item it{};
+        it.base = tau_base + (int64_t)g * P1_GW * np;
+        it.gw = gw;
+        it.q0 = c * qch;
+        it.nq = std::min(qch, nq - c * qch);
+        it.nrows = n;
+        it.xrow = b0.cb;
+        it.trow = trow;
+        it.part = nch > 1 ? parts1 + c : -1;
+        P.p1.push_back(it);
+        item_bytes1.push_back((int64_t)it.nq * 4 * gw * 4);
+      }
+      if (nch > 1) parts1 += nch;
+    }
+    vcur += (int64_t)np * ktau;
+    tcur += ktau;
+    q = e;
+  }
+  HM_REQUIRE(tcur < (int64_t)1 << 30, "build_plan: too many rank columns");
+  P.v_elems = vcur;
+  // ---- row tiles: leaves cut into <= TILE rows
   std::vector<Tile> tiles;
   for (int32_t li : t.leaves) {
     const auto& nd = t.nodes[li];
@@ -50,128 +115,122 @@ void build_plan(hm_matrix& M, const std::vector<LrInfo>& lr, const std::vector<D
   }
   std::vector<int32_t> row0s(tiles.size());
   for (size_t q = 0; q < tiles.size(); ++q) row0s[q] = tiles[q].row0;
-  // t offsets of the low-rank blocks
-  std::vector<int32_t> toff(lr.size());
-  int64_t kt = 0;
-  for (size_t q = 0; q < lr.size(); ++q) {
-    toff[q] = (int32_t)kt;
-    kt += lr[q].k;
-  }
-  HM_REQUIRE(kt < (int64_t)1 << 30, "build_plan: too many rank columns");
-  // ---- phase 2 segments per tile
-  std::vector<std::vector<Seg>> tseg(tiles.size());
-  auto add = [&](const BlockRef& b, int64_t off, int32_t w, int32_t src, int32_t kind) {
-    size_t q = std::lower_bound(row0s.begin(), row0s.end(), b.rb) - row0s.begin();
-    for (; q < tiles.size() && tiles[q].row0 < b.re; ++q) {
-      Seg sg;
-      sg.off = off + (tiles[q].row0 - b.rb);
-      sg.ld = b.re - b.rb;
-      sg.w = w;
-      sg.src = src;
-      sg.kind = kind;
-      tseg[q].push_back(sg);
-    }
+  // ---- per-tile column runs: (kind, src, width, block index)
+  struct Run {
+    int32_t kind, src, w, blk;
   };
-  for (const auto& d : dn) add(d.b, d.off, d.b.ce - d.b.cb, d.b.cb, 0);
-  for (size_t q = 0; q < lr.size(); ++q) add(lr[q].b, lr[q].u_off, lr[q].k, ~toff[q], 1);
-  int32_t parts2 = 0, counters2 = 0;
-  std::vector<int64_t> item_bytes2;
+  std::vector<std::vector<Run>> truns(tiles.size());
+  auto add = [&](const BlockRef& b, int32_t kind, int32_t src, int32_t w, int32_t blk) {
+    size_t q = std::lower_bound(row0s.begin(), row0s.end(), b.rb) - row0s.begin();
+    for (; q < tiles.size() && tiles[q].row0 < b.re; ++q) truns[q].push_back(Run{kind, src, w, blk});
+  };
+  for (size_t q = 0; q < dn.size(); ++q) add(dn[q], 0, dn[q].cb, dn[q].ce - dn[q].cb, (int32_t)q);
+  for (size_t q = 0; q < lr.size(); ++q) add(lr[q].b, 1, ~tidx[q], lr[q].k, (int32_t)q);
+  int64_t dcur = 0, ucur = 0;
   for (size_t q = 0; q < tiles.size(); ++q) {
-    auto& v = tseg[q];
-    std::stable_sort(v.begin(), v.end(), [](const Seg& a, const Seg& b) {
+    auto& v = truns[q];
+    std::stable_sort(v.begin(), v.end(), [](const Run& a, const Run& b) {
       if (a.kind != b.kind) return a.kind < b.kind;
       return a.src < b.src;
     });
-    const int64_t rowbytes = (int64_t)tiles[q].m * 4;
-    std::vector<std::pair<int32_t, int32_t>> runs;  // [seg begin, seg end) per item
-    int32_t b0 = (int32_t)P.segs.size();
-    int64_t acc = 0;
-    int32_t cur = b0;
-    for (size_t k = 0; k < v.size(); ++k) {
-      const int64_t sb = rowbytes * v[k].w;
-      if (acc > 0 && acc + sb > ITEM_BYTES) {
-        runs.emplace_back(cur, (int32_t)(b0 + k));
-        cur = (int32_t)(b0 + k);
-        acc = 0;
+    const int32_t m = tiles[q].m;
+    const int32_t row0 = tiles[q].row0;
+    P2Tile tl{row0, m, (int32_t)P.p2.size(), 0};
+    // columns of each kind, split into parts of nearly equal width so that
+    // the waves of the tile's workgroup get the same number of bytes
+    int32_t W[2] = {0, 0};
+    for (const Run& r : v) W[r.kind] += r.w;
+    const int32_t Wt = W[0] + W[1];
+    const int32_t cN = (Wt + P2_WAVES * P2_MAXW - 1) / (P2_WAVES * P2_MAXW);
+    const int32_t N = std::max<int32_t>(1, std::min<int32_t>(P2_WAVES * std::max(1, cN), (Wt + 15) / 16));
+    int32_t nk[2];
+    nk[0] = W[0] > 0 ? std::max<int32_t>(1, (int32_t)std::lround((double)N * W[0] / std::max(1, Wt))) : 0;
+    nk[1] = W[1] > 0 ? std::max<int32_t>(1, N - nk[0]) : 0;
+    for (int kd = 0; kd < 2; ++kd)
+      if (W[kd] > 0) nk[kd] = std::max(nk[kd], (W[kd] + P2_MAXW - 1) / P2_MAXW);
+    // walk the runs of each kind, cutting at the part boundaries
+    size_t r0 = 0;
+    for (int kd = 0; kd < 2; ++kd) {
+      std::vector<Run> kv;
+      while (r0 < v.size() && v[r0].kind == kd) kv.push_back(v[r0++]);
+      if (kv.empty()) continue;
+      std::vector<int32_t> cut;
+      for (int32_t i = 0; i <= nk[kd]; ++i)
+        cut.push_back(i == nk[kd] ? W[kd] : std::min(W[kd], round4((int32_t)((int64_t)W[kd] * i / nk[kd]))));
+      size_t ri = 0;
+      int32_t roff = 0;  // columns of kv[ri] already used
+      for (int32_t i = 0; i < nk[kd]; ++i) {
+        int32_t want = cut[i + 1] - cut[i];
+        while (want > 0) {
+          // one item: up to want columns and P2_MAXSEG runs
+          P2Item it{};
+          it.kind = kd;
+          it.seg0 = (int32_t)P.segs.size();
+          int32_t col = 0;
+          while (want > 0 && (int32_t)P.segs.size() - it.seg0 < P2_MAXSEG) {
+            const Run& R = kv[ri];
+            const int32_t take = std::min(want, R.w - roff);
+            const int32_t src = kd == 0 ? R.src + roff : ~((~R.src) + roff);
+            P.segs.push_back(Seg{col, take, src, 0});
+            if (kd == 0) {
+              pk.nf.push_back(NfDev{0, row0, m, R.src + roff, take, col, 0});
+            } else {
+              const LrInfo& L = lr[R.blk];
+              const int32_t ld = L.b.re - L.b.rb;
+              pk.ur.push_back(URepack{L.su + (row0 - L.b.rb) + (int64_t)roff * ld, 0, L.stage, ld, m, take, col, 0});
+            }
+            col += take;
+            want -= take;
+            roff += take;
+            if (roff == R.w) {
+              ++ri;
+              roff = 0;
+            }
+          }
+          it.nseg = (int32_t)P.segs.size() - it.seg0;
+          it.w = round4(col);
+          int64_t& cur = kd == 0 ? dcur : ucur;
+          it.base = cur;
+          cur += (int64_t)m * it.w;
+          // the packing entries just added belong to this item
+          if (kd == 0)
+            for (size_t z = pk.nf.size() - it.nseg; z < pk.nf.size(); ++z) pk.nf[z].base = it.base;
+          else
+            for (size_t z = pk.ur.size() - it.nseg; z < pk.ur.size(); ++z) pk.ur[z].base = it.base;
+          P.p2.push_back(it);
+        }
       }
-      acc += sb;
     }
-    runs.emplace_back(cur, (int32_t)(b0 + v.size()));
-    for (const auto& sg : v) P.segs.push_back(sg);
-    const int32_t np = (int32_t)runs.size();
-    const int32_t part = np > 1 ? parts2 : -1;
-    if (np > 1) {
-      parts2 += np;
-      ++counters2;
-    }
-    for (int32_t k = 0; k < np; ++k) {
-      P2Item it{tiles[q].row0, tiles[q].m, runs[k].first, runs[k].second - runs[k].first, part, k, np,
-                np > 1 ? counters2 - 1 : 0};
-      P.p2.push_back(it);
-      int64_t by = 0;
-      for (int32_t z = runs[k].first; z < runs[k].second; ++z) by += rowbytes * P.segs[z].w;
-      item_bytes2.push_back(by);
+    tl.nit = (int32_t)P.p2.size() - tl.it0;
+    P.p2t.push_back(tl);
+  }
+  P.dense_elems = dcur;
+  P.u_elems = ucur;
+  // ---- phase-1 tasks: consecutive items of at least TASK_BYTES
+  P.p1_task.clear();
+  P.p1_task.push_back(0);
+  int64_t acc = 0;
+  for (size_t k = 0; k < item_bytes1.size(); ++k) {
+    acc += item_bytes1[k];
+    if (acc >= TASK_BYTES) {
+      P.p1_task.push_back((int32_t)(k + 1));
+      acc = 0;
     }
   }
-  // ---- phase 1 items
-  int32_t parts1 = 0, counters1 = 0;
-  std::vector<int64_t> item_bytes1;
-  for (size_t q = 0; q < lr.size(); ++q) {
-    const int32_t nb = lr[q].b.ce - lr[q].b.cb;
-    const int32_t k = lr[q].k;
-    const int32_t nch = (nb + P1_RCH - 1) / P1_RCH;
-    for (int32_t l0 = 0; l0 < k; l0 += KG) {
-      const int32_t nl = std::min(KG, k - l0);
-      const int32_t part = nch > 1 ? parts1 : -1;
-      if (nch > 1) {
-        parts1 += nch;
-        ++counters1;
-      }
-      for (int32_t c = 0; c < nch; ++c) {
-        const int32_t r0 = (int32_t)((int64_t)nb * c / nch);
-        const int32_t r1 = (int32_t)((int64_t)nb * (c + 1) / nch);
-        P1Item it{};
-        it.v_off = lr[q].v_off;
-        it.ld = nb;
-        it.r0 = r0;
-        it.nr = r1 - r0;
-        it.l0 = l0;
-        it.nl = nl;
-        it.xrow = lr[q].b.cb + r0;
-        it.trow = toff[q] + l0;
-        it.part = part;
-        it.pidx = c;
-        it.nparts = nch;
-        it.counter = nch > 1 ? counters1 - 1 : 0;
-        P.p1.push_back(it);
-        item_bytes1.push_back((int64_t)(r1 - r0) * nl * 4);
-      }
-    }
-  }
-  // ---- tasks: consecutive items of at least TASK_BYTES
-  auto pack = [](const std::vector<int64_t>& by, std::vector<int32_t>& task) {
-    task.clear();
-    task.push_back(0);
-    int64_t acc = 0;
-    for (size_t k = 0; k < by.size(); ++k) {
-      acc += by[k];
-      if (acc >= TASK_BYTES) {
-        task.push_back((int32_t)(k + 1));
-        acc = 0;
-      }
-    }
-    if (task.back() != (int32_t)by.size()) task.push_back((int32_t)by.size());
-  };
-  pack(item_bytes1, P.p1_task);
-  pack(item_bytes2, P.p2_task);
+  if (P.p1_task.back() != (int32_t)item_bytes1.size()) P.p1_task.push_back((int32_t)item_bytes1.size());
   P.n_p1_parts = parts1;
-  P.n_p2_parts = parts2;
-  P.n_p1_counters = counters1;
-  P.n_p2_counters = counters2;
+  M.Ktot = tcur;
+}
+
+void build_plan(hm_matrix& M, const std::vector<LrInfo>& lr, const std::vector<BlockRef>& dn, const hm_tree& t,
+                PackLists& pk, hipStream_t s) {
+  plan_host(M, lr, dn, t, pk);
+  Plan& P = M.plan;
   upload(P.d_p1, P.p1, s);
   upload(P.d_p1_task, P.p1_task, s);
+  upload(P.d_p1red, P.p1red, s);
+  upload(P.d_p2t, P.p2t, s);
   upload(P.d_p2, P.p2, s);
-  upload(P.d_p2_task, P.p2_task, s);
   upload(P.d_segs, P.segs, s);
   HM_HIP(hipStreamSynchronize(s));
 }
@@ -189,56 +248,45 @@ std::unique_ptr<Composition> make_composition(const std::vector<const hm_matrix*
   C->nr = nr;
   C->vec_bytes = vec_bytes;
   C->mats = mats;
-  int64_t tsz = 0, p1 = 0, p2 = 0, c1 = 0, c2 = 0;
+  int64_t tsz = 0, p1 = 0;
   for (const auto* M : mats) {
     C->xoff.push_back(C->N);
     C->N += M->n;
     tsz += M->Ktot;
     p1 += M->plan.n_p1_parts;
-    p2 += M->plan.n_p2_parts;
-    c1 += M->plan.n_p1_counters;
-    c2 += M->plan.n_p2_counters;
   }
   const int64_t eb = 8;  // buffers sized for FP64 so one composition serves both vector types
   C->t.alloc(std::max<int64_t>(1, tsz * nr) * eb);
-  C->part1.alloc(std::max<int64_t>(1, p1 * KG * nr) * eb);
-  C->part2.alloc(std::max<int64_t>(1, p2 * TILE * nr) * eb);
-  C->cnt1.alloc(std::max<int64_t>(1, c1) * 4);
-  C->cnt2.alloc(std::max<int64_t>(1, c2) * 4);
-  HM_HIP(hipMemsetAsync(C->cnt1.get(), 0, C->cnt1.bytes(), s));
-  HM_HIP(hipMemsetAsync(C->cnt2.get(), 0, C->cnt2.bytes(), s));
+  C->part1.alloc(std::max<int64_t>(1, p1 * P1_GW * nr) * eb);
   int64_t to = 0;
-  p1 = p2 = c1 = c2 = 0;
-  int32_t t1 = 0, t2 = 0;
+  p1 = 0;
+  int32_t t1 = 0, r1 = 0, t2 = 0;
   for (size_t q = 0; q < mats.size(); ++q) {
     const hm_matrix& M = *mats[q];
     SlotDev d{};
     d.p1 = M.plan.d_p1.get<P1Item>();
     d.p1_task = M.plan.d_p1_task.get<int32_t>();
+    d.p1red = M.plan.d_p1red.get<P1Red>();
+    d.p2t = M.plan.d_p2t.get<P2Tile>();
     d.p2 = M.plan.d_p2.get<P2Item>();
-    d.p2_task = M.plan.d_p2_task.get<int32_t>();
     d.segs = M.plan.d_segs.get<Seg>();
     d.dense = M.dense.get();
     d.U = M.U.get();
     d.V = M.V.get();
-    d.cnt1 = C->cnt1.get<unsigned>() + c1;
-    d.cnt2 = C->cnt2.get<unsigned>() + c2;
-    d.part1 = C->part1.get<char>() + p1 * KG * nr * eb;
-    d.part2 = C->part2.get<char>() + p2 * TILE * nr * eb;
+    d.part1 = C->part1.get<char>() + p1 * P1_GW * nr * eb;
     d.t = C->t.get<char>() + to * nr * eb;
     d.ldt = std::max<int64_t>(1, M.Ktot);
     d.xoff = C->xoff[q];
     d.p1_task_begin = t1;
-    d.p2_task_begin = t2;
+    d.p1red_begin = r1;
+    d.p2_tile_begin = t2;
     d.n = (int32_t)M.n;
     d.slot = (int32_t)q;
     t1 += (int32_t)M.plan.p1_task.size() - 1;
-    t2 += (int32_t)M.plan.p2_task.size() - 1;
+    r1 += (int32_t)M.plan.p1red.size();
+    t2 += (int32_t)M.plan.p2t.size();
     to += M.Ktot;
     p1 += M.plan.n_p1_parts;
-    p2 += M.plan.n_p2_parts;
-    c1 += M.plan.n_p1_counters;
-    c2 += M.plan.n_p2_counters;
     C->slots_lo.push_back(d);
     SlotDev h = d;
     if (M.has_hi) {
@@ -250,7 +298,8 @@ std::unique_ptr<Composition> make_composition(const std::vector<const hm_matrix*
     C->bytes_hi += matrix_bytes(M, true);
   }
   C->p1_tasks = t1;
-  C->p2_tasks = t2;
+  C->p1_reds = r1;
+  C->p2_tiles = t2;
   upload(C->d_slots_lo, C->slots_lo, s);
   upload(C->d_slots_hi, C->slots_hi, s);
   HM_HIP(hipStreamSynchronize(s));
@@ -266,38 +315,50 @@ struct EpiDev {
   int64_t ldz;
 };
 
-__device__ inline int find_slot(const SlotDev* __restrict__ slots, int nslots, int task, bool phase1) {
+// Slot of a global work index: the last slot whose first index is <= task
+// (which = 0: phase-1 tasks, 1: phase-1 reductions, 2: phase-2 tiles).
+__device__ inline int find_slot(const SlotDev* __restrict__ slots, int nslots, int task, int which) {
   int lo = 0, hi = nslots - 1;
   while (lo < hi) {
     const int mid = (lo + hi + 1) >> 1;
-    const int b = phase1 ? slots[mid].p1_task_begin : slots[mid].p2_task_begin;
+    const int b = which == 0 ? slots[mid].p1_task_begin : (which == 1 ? slots[mid].p1red_begin : slots[mid].p2_tile_begin);
     if (b <= task) lo = mid;
     else hi = mid - 1;
   }
   return lo;
 }
 
-// acc[j] += sum_c A(lane, c) * src[c + j*lds], lane = row of the tile
-template <class MT, class VT, int NR>
-__device__ __forceinline__ void seg_accumulate(const MT* __restrict__ a, int ld, int w, const VT* __restrict__ src,
-                                               int64_t lds, bool act, int nrr, VT* acc) {
-  int c = 0;
-  for (; c + 8 <= w; c += 8) {
-    VT v[8];
-#pragma unroll
-    for (int q = 0; q < 8; ++q) v[q] = act ? ld_as<VT>(a + (int64_t)(c + q) * ld) : VT(0);
-#pragma unroll
-    for (int q = 0; q < 8; ++q)
-#pragma unroll
-      for (int j = 0; j < NR; ++j)
-        if (j < nrr) acc[j] += v[q] * src[c + q + j * lds];
+// Four consecutive stored elements as the arithmetic type.
+template <class VT, class MT> struct Ld4;
+template <class VT> struct Ld4<VT, float> {
+  __device__ static void go(const float* p, VT* o) {
+    const float4 v = *reinterpret_cast<const float4*>(p);
+    o[0] = v.x; o[1] = v.y; o[2] = v.z; o[3] = v.w;
   }
-  for (; c < w; ++c) {
-    const VT v = act ? ld_as<VT>(a + (int64_t)c * ld) : VT(0);
-#pragma unroll
-    for (int j = 0; j < NR; ++j)
-      if (j < nrr) acc[j] += v * src[c + j * lds];
+};
+template <class VT> struct Ld4<VT, double> {
+  __device__ static void go(const double* p, VT* o) {
+    const double2 a = reinterpret_cast<const double2*>(p)[0];
+    const double2 b = reinterpret_cast<const double2*>(p)[1];
+    o[0] = (VT)a.x; o[1] = (VT)a.y; o[2] = (VT)b.x; o[3] = (VT)b.y;
   }
+};
+template <class VT> struct Ld4<VT, bf16_t> {
+  __device__ static void go(const bf16_t* p, VT* o) {
+    const uint2 v = *reinterpret_cast<const uint2*>(p);
+    o[0] = (VT)bf16_to_f32((bf16_t)(v.x & 0xffffu));
+    o[1] = (VT)bf16_to_f32((bf16_t)(v.x >> 16));
+    o[2] = (VT)bf16_to_f32((bf16_t)(v.y & 0xffffu));
+    o[3] = (VT)bf16_to_f32((bf16_t)(v.y >> 16));
+  }
+};
+
+// Ordering of LDS traffic inside one wave (no workgroup barrier: the waves of
+// a workgroup run independent tasks).
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
 template <class VT, int NR>
@@ -316,164 +377,274 @@ __device__ __forceinline__ void epilogue_store(int row, int lane, int m, int nrr
   }
 }
 
-template <class DT, class LT, class VT, int NR>
-__global__ __launch_bounds__(256) void k_phase2(const SlotDev* __restrict__ slots, int nslots, int ntasks,
-                                                const int* __restrict__ slot_active, int nrr, const VT* __restrict__ X,
-                                                int64_t ldx, VT* __restrict__ Y, int64_t ldy, EpiDev<VT> ep) {
-  const int lane = threadIdx.x & 63;
-  const int task = blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (task >= ntasks) return;
-  const int si = find_slot(slots, nslots, task, false);
-  const SlotDev& S = slots[si];
-  if (slot_active && !slot_active[S.slot]) return;
-  const int lt = task - S.p2_task_begin;
-  const int ib = S.p2_task[lt], ie = S.p2_task[lt + 1];
-  const VT* Xs = X + S.xoff;
-  VT* Ys = Y + S.xoff;
-  const VT* Ts = (const VT*)S.t;
-  EpiDev<VT> e = ep;
-  if (e.rowscale) e.rowscale += S.xoff;
-  if (e.z) e.z += S.xoff;
-  for (int it = ib; it < ie; ++it) {
-    const P2Item item = S.p2[it];
-    const bool act = lane < item.m;
-    VT acc[NR];
+// 16-byte loads kept in flight per lane (registers: 4 values each).
+template <class VT, int NR>
+constexpr int load_depth() {
+  return sizeof(VT) * NR <= 8 ? 16 : (NR <= 4 ? 8 : 4);
+}
+
+// acc[j] += sum over column quads [g0, g1) of A(lane, c) * in[c - 4*g0][j]
+template <class MT, class VT, int NR>
+__device__ __forceinline__ void panel_accumulate(const MT* __restrict__ a, int m, int g0, int g1,
+                                                 const VT* __restrict__ in, bool act, VT* acc) {
+  const int64_t step = (int64_t)m * 4;
+  constexpr int UN = load_depth<VT, NR>();
+  int g = g0;
+  for (; g + UN <= g1; g += UN) {
+    VT v[UN][4];
 #pragma unroll
-    for (int j = 0; j < NR; ++j) acc[j] = VT(0);
-    for (int sg = item.seg0; sg < item.seg0 + item.nseg; ++sg) {
-      const Seg seg = S.segs[sg];
-      const VT* src;
-      int64_t lds;
-      if (seg.src >= 0) {
-        src = Xs + seg.src;
-        lds = ldx;
-      } else {
-        src = Ts + (~seg.src);
-        lds = S.ldt;
-      }
-      if (seg.kind == 0)
-        seg_accumulate<DT, VT, NR>((const DT*)S.dense + seg.off + lane, seg.ld, seg.w, src, lds, act, nrr, acc);
-      else
-        seg_accumulate<LT, VT, NR>((const LT*)S.U + seg.off + lane, seg.ld, seg.w, src, lds, act, nrr, acc);
+    for (int u = 0; u < UN; ++u) {
+      if (act) Ld4<VT, MT>::go(a + (g + u) * step, v[u]);
+      else v[u][0] = v[u][1] = v[u][2] = v[u][3] = VT(0);
     }
-    const int row = item.row0 + lane;
-    if (item.nparts == 1) {
-      epilogue_store<VT, NR>(row, lane, item.m, nrr, acc, Xs, ldx, Ys, ldy, e);
-    } else {
-      VT* P0 = (VT*)S.part2 + (int64_t)item.part * TILE * NR;
-      VT* P = P0 + (int64_t)item.pidx * TILE * NR;
 #pragma unroll
-      for (int j = 0; j < NR; ++j) P[j * TILE + lane] = acc[j];
-      __threadfence();
-      unsigned old = 0;
-      if (lane == 0) old = atomicAdd(&S.cnt2[item.counter], 1u);
-      old = __shfl(old, 0, 64);
-      if (old == (unsigned)(item.nparts - 1)) {
-        __threadfence();
-        VT sum[NR];
+    for (int u = 0; u < UN; ++u)
 #pragma unroll
-        for (int j = 0; j < NR; ++j) sum[j] = VT(0);
-        for (int p = 0; p < item.nparts; ++p)
+      for (int e = 0; e < 4; ++e)
 #pragma unroll
-          for (int j = 0; j < NR; ++j) sum[j] += P0[(int64_t)p * TILE * NR + j * TILE + lane];
-        epilogue_store<VT, NR>(row, lane, item.m, nrr, sum, Xs, ldx, Ys, ldy, e);
-        if (lane == 0) S.cnt2[item.counter] = 0u;
-      }
-    }
+        for (int j = 0; j < NR; ++j) acc[j] += v[u][e] * in[((g - g0 + u) * 4 + e) * NR + j];
+  }
+  for (; g < g1; ++g) {
+    VT v[4];
+    if (act) Ld4<VT, MT>::go(a + g * step, v);
+    else v[0] = v[1] = v[2] = v[3] = VT(0);
+#pragma unroll
+    for (int e = 0; e < 4; ++e)
+#pragma unroll
+      for (int j = 0; j < NR; ++j) acc[j] += v[e] * in[((g - g0) * 4 + e) * NR + j];
   }
 }
 
-// Phase 1: t[trow + l] (+ j*ldt) = sum_r V(r0 + r, l0 + l) x(xrow + r), lane = row of V.
-template <class LT, class VT, int NR>
-__global__ __launch_bounds__(256) void k_phase1(const SlotDev* __restrict__ slots, int nslots, int ntasks,
-                                                const int* __restrict__ slot_active, int nrr,
-                                                const VT* __restrict__ X, int64_t ldx) {
-  constexpr int SG = NR <= 2 ? KG : (NR <= 4 ? 4 : (NR <= 8 ? 2 : 1));  // rank columns per pass
+// Staged columns per chunk: at most P2_MAXW and 4 KB of inputs per wave.
+template <class VT, int NR>
+constexpr int p2_chunk() {
+  return (int)std::min<int64_t>(P2_MAXW, ((4096 / ((int64_t)NR * sizeof(VT))) / 4) * 4);
+}
+
+// Phase 2: one workgroup per row tile, lane = row of the tile; the waves
+// share the tile's items and add their sums in LDS in wave order.
+template <class DT, class LT, class VT, int NR>
+__global__ __launch_bounds__(64 * P2_WAVES) void k_phase2(const SlotDev* __restrict__ slots, int nslots,
+                                                          const int* __restrict__ slot_active, int nrr,
+                                                          const VT* __restrict__ X, int64_t ldx,
+                                                          VT* __restrict__ Y, int64_t ldy, EpiDev<VT> ep) {
+  constexpr int CW = p2_chunk<VT, NR>();
+  constexpr int RJ = NR < 4 ? NR : 4;
+  __shared__ VT lds_in[P2_WAVES][CW * NR];
+  __shared__ Seg lds_seg[P2_WAVES][P2_MAXSEG];
+  __shared__ VT lds_red[P2_WAVES][RJ][TILE];
   const int lane = threadIdx.x & 63;
-  const int task = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int wv = threadIdx.x >> 6;
+  const int tile = blockIdx.x;
+  const int si = find_slot(slots, nslots, tile, 2);
+  const SlotDev& S = slots[si];
+  if (slot_active && !slot_active[S.slot]) return;  // uniform over the workgroup
+  const P2Tile T = S.p2t[tile - S.p2_tile_begin];
+  const VT* Xs = X + S.xoff;
+  VT* Ys = Y + S.xoff;
+  const VT* Ts = (const VT*)S.t;
+  VT* in = lds_in[wv];
+  Seg* sg_lds = lds_seg[wv];
+  const bool act = lane < T.m;
+  VT acc[NR];
+#pragma unroll
+  for (int j = 0; j < NR; ++j) acc[j] = VT(0);
+  for (int k = wv; k < T.nit; k += P2_WAVES) {
+    const P2Item item = S.p2[T.it0 + k];
+    wave_lds_sync();
+    for (int q = lane; q < item.nseg; q += 64) sg_lds[q] = S.segs[item.seg0 + q];
+    wave_lds_sync();
+    const Seg lastseg = sg_lds[item.nseg - 1];
+    const int wtrue = lastseg.col0 + lastseg.w;
+    for (int c0 = 0; c0 < item.w; c0 += CW) {
+      const int cw = min(CW, item.w - c0);
+      // stage inputs of columns [c0, c0 + cw): every lane finds the run of
+      // each of its columns and gathers, so all gathers are in flight at once
+      wave_lds_sync();
+      for (int cc = lane; cc < cw; cc += 64) {
+        const int c = c0 + cc;
+        VT v[NR];
+#pragma unroll
+        for (int j = 0; j < NR; ++j) v[j] = VT(0);
+        if (c < wtrue) {
+          int lo = 0, hi = item.nseg - 1;
+          while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (sg_lds[mid].col0 <= c) lo = mid;
+            else hi = mid - 1;
+          }
+          const Seg sg = sg_lds[lo];
+          const int kk = c - sg.col0;
+          if (sg.src >= 0) {
+#pragma unroll
+            for (int j = 0; j < NR; ++j)
+              if (j < nrr) v[j] = Xs[sg.src + kk + j * ldx];
+          } else {
+#pragma unroll
+            for (int j = 0; j < NR; ++j)
+              if (j < nrr) v[j] = Ts[(~sg.src) + kk + j * S.ldt];
+          }
+        }
+#pragma unroll
+        for (int j = 0; j < NR; ++j) in[cc * NR + j] = v[j];
+      }
+      wave_lds_sync();
+      if (item.kind == 0)
+        panel_accumulate<DT, VT, NR>((const DT*)S.dense + item.base + lane * 4, T.m, c0 >> 2, (c0 + cw) >> 2, in,
+                                     act, acc);
+      else
+        panel_accumulate<LT, VT, NR>((const LT*)S.U + item.base + lane * 4, T.m, c0 >> 2, (c0 + cw) >> 2, in, act,
+                                     acc);
+    }
+  }
+  // combine the waves in order and finish the tile
+  VT sum[NR];
+#pragma unroll
+  for (int j = 0; j < NR; ++j) sum[j] = VT(0);
+#pragma unroll
+  for (int j0 = 0; j0 < NR; j0 += RJ) {
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < RJ; ++j) lds_red[wv][j][lane] = acc[j0 + j];
+    __syncthreads();
+    if (wv == 0) {
+#pragma unroll
+      for (int j = 0; j < RJ; ++j) {
+        VT t = lds_red[0][j][lane];
+        for (int w = 1; w < P2_WAVES; ++w) t += lds_red[w][j][lane];
+        sum[j0 + j] = t;
+      }
+    }
+  }
+  if (wv == 0) {
+    EpiDev<VT> e = ep;
+    if (e.rowscale) e.rowscale += S.xoff;
+    if (e.z) e.z += S.xoff;
+    epilogue_store<VT, NR>(T.row0 + lane, lane, T.m, nrr, sum, Xs, ldx, Ys, ldy, e);
+  }
+}
+
+// Phase 1: lane l owns rank column l of a group panel: t[trow + l] (+ j*ldt)
+// = sum_r V(r, l) x(xrow + r).
+template <class LT, class VT, int NR, int WPB>
+__global__ __launch_bounds__(64 * WPB) void k_phase1(const SlotDev* __restrict__ slots, int nslots, int ntasks,
+                                                     const int* __restrict__ slot_active, int nrr,
+                                                     const VT* __restrict__ X, int64_t ldx) {
+  __shared__ VT lds_x[WPB][P1_XST * NR];
+  const int lane = threadIdx.x & 63;
+  const int wv = threadIdx.x >> 6;
+  const int task = blockIdx.x * WPB + wv;
   if (task >= ntasks) return;
-  const int si = find_slot(slots, nslots, task, true);
+  const int si = find_slot(slots, nslots, task, 0);
   const SlotDev& S = slots[si];
   if (slot_active && !slot_active[S.slot]) return;
   const int lt = task - S.p1_task_begin;
   const int ib = S.p1_task[lt], ie = S.p1_task[lt + 1];
   const VT* Xs = X + S.xoff;
   VT* T = (VT*)S.t;
+  VT* xs = lds_x[wv];
   for (int it = ib; it < ie; ++it) {
     const P1Item item = S.p1[it];
-    const LT* Vb = (const LT*)S.V + item.v_off + item.r0;
-    // destination of the (rank column l, right-hand side j) sums
-    VT* P0 = (VT*)S.part1 + (int64_t)(item.part < 0 ? 0 : item.part) * KG * NR;
-    VT* dst;
-    int64_t sl, sj;
-    if (item.nparts == 1) {
-      dst = T + item.trow;
-      sl = 1;
-      sj = S.ldt;
+    const bool act = lane < item.gw;
+    const LT* a = (const LT*)S.V + item.base + (int64_t)lane * 4;
+    const int64_t step = (int64_t)item.gw * 4;
+    VT acc[NR];
+#pragma unroll
+    for (int j = 0; j < NR; ++j) acc[j] = VT(0);
+    for (int q0 = item.q0; q0 < item.q0 + item.nq; q0 += P1_XST / 4) {
+      const int nqc = min(P1_XST / 4, item.q0 + item.nq - q0);
+      wave_lds_sync();
+      for (int r = lane; r < nqc * 4; r += 64) {
+        const int row = q0 * 4 + r;
+#pragma unroll
+        for (int j = 0; j < NR; ++j)
+          xs[r * NR + j] = (j < nrr && row < item.nrows) ? Xs[item.xrow + row + j * ldx] : VT(0);
+      }
+      wave_lds_sync();
+      int q = 0;
+      constexpr int UN = load_depth<VT, NR>();
+      for (; q + UN <= nqc; q += UN) {
+        VT v[UN][4];
+#pragma unroll
+        for (int u = 0; u < UN; ++u) {
+          if (act) Ld4<VT, LT>::go(a + (int64_t)(q0 + q + u) * step, v[u]);
+          else v[u][0] = v[u][1] = v[u][2] = v[u][3] = VT(0);
+        }
+#pragma unroll
+        for (int u = 0; u < UN; ++u)
+#pragma unroll
+          for (int e = 0; e < 4; ++e)
+#pragma unroll
+            for (int j = 0; j < NR; ++j) acc[j] += v[u][e] * xs[((q + u) * 4 + e) * NR + j];
+      }
+      for (; q < nqc; ++q) {
+        VT v[4];
+        if (act) Ld4<VT, LT>::go(a + (int64_t)(q0 + q) * step, v);
+        else v[0] = v[1] = v[2] = v[3] = VT(0);
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+#pragma unroll
+          for (int j = 0; j < NR; ++j) acc[j] += v[e] * xs[(q * 4 + e) * NR + j];
+      }
+    }
+    if (item.part < 0) {
+      if (act)
+#pragma unroll
+        for (int j = 0; j < NR; ++j)
+          if (j < nrr) T[item.trow + lane + j * S.ldt] = acc[j];
     } else {
-      dst = P0 + (int64_t)item.pidx * KG * NR;
-      sl = NR;
-      sj = 1;
+      VT* P = (VT*)S.part1 + (int64_t)item.part * P1_GW * NR;
+#pragma unroll
+      for (int j = 0; j < NR; ++j) P[j * P1_GW + lane] = acc[j];
     }
-    for (int g0 = 0; g0 < item.nl; g0 += SG) {
-      VT acc[SG][NR];
+  }
+}
+
+// t of the row-split groups: the partials of a group added in item order.
+template <class VT, int NR>
+__global__ __launch_bounds__(256) void k_p1reduce(const SlotDev* __restrict__ slots, int nslots, int nreds,
+                                                  const int* __restrict__ slot_active, int nrr) {
+  const int lane = threadIdx.x & 63;
+  const int r = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (r >= nreds) return;
+  const SlotDev& S = slots[find_slot(slots, nslots, r, 1)];
+  if (slot_active && !slot_active[S.slot]) return;
+  const P1Red R = S.p1red[r - S.p1red_begin];
+  if (lane >= R.gw) return;
+  const VT* P0 = (const VT*)S.part1 + (int64_t)R.part0 * P1_GW * NR;
+  VT* T = (VT*)S.t;
 #pragma unroll
-      for (int q = 0; q < SG; ++q)
-#pragma unroll
-        for (int j = 0; j < NR; ++j) acc[q][j] = VT(0);
-      for (int r = lane; r < item.nr; r += 64) {
-        VT xv[NR];
-#pragma unroll
-        for (int j = 0; j < NR; ++j) xv[j] = j < nrr ? Xs[item.xrow + r + j * ldx] : VT(0);
-#pragma unroll
-        for (int q = 0; q < SG; ++q) {
-          if (g0 + q < item.nl) {
-            const VT a = ld_as<VT>(Vb + (int64_t)(item.l0 + g0 + q) * item.ld + r);
-#pragma unroll
-            for (int j = 0; j < NR; ++j) acc[q][j] += a * xv[j];
-          }
-        }
-      }
-#pragma unroll
-      for (int q = 0; q < SG; ++q)
-#pragma unroll
-        for (int j = 0; j < NR; ++j) {
-          const VT v = wave_sum(acc[q][j]);
-          if (lane == 0 && g0 + q < item.nl && j < nrr) dst[(g0 + q) * sl + j * sj] = v;
-        }
-    }
-    if (item.nparts > 1) {
-      __threadfence();
-      unsigned old = 0;
-      if (lane == 0) old = atomicAdd(&S.cnt1[item.counter], 1u);
-      old = __shfl(old, 0, 64);
-      if (old == (unsigned)(item.nparts - 1)) {
-        __threadfence();
-        const int tot = item.nl * NR;
-        for (int q = lane; q < tot; q += 64) {
-          VT sum = VT(0);
-          for (int p = 0; p < item.nparts; ++p) sum += P0[(int64_t)p * KG * NR + q];
-          const int l = q / NR, j = q % NR;
-          if (j < nrr) T[item.trow + l + j * S.ldt] = sum;
-        }
-        if (lane == 0) S.cnt1[item.counter] = 0u;
-      }
-    }
+  for (int j = 0; j < NR; ++j) {
+    if (j >= nrr) break;
+    VT sum = VT(0);
+    for (int p = 0; p < R.nparts; ++p) sum += P0[((int64_t)p * NR + j) * P1_GW + lane];
+    T[R.trow + lane + j * S.ldt] = sum;
   }
 }
 
 // ------------------------------------------------------------------ launch
 namespace {
 
+template <class VT, int NR>
+constexpr int p1_waves_per_block() {
+  // LDS per wave: P1_XST staged rows of NR values; keep a workgroup <= 64 KB
+  return (int64_t)P1_XST * NR * sizeof(VT) * 4 <= (64 << 10) ? 4 : ((int64_t)P1_XST * NR * sizeof(VT) * 2 <= (64 << 10) ? 2 : 1);
+}
+
 template <class DT, class LT, class VT, int NR>
 void launch_typed(const Composition& C, int nrr, bool hi, const void* X, int64_t ldx, void* Y, int64_t ldy,
                   const Epilogue& ep, const int* slot_active, hipStream_t s, hipEvent_t* ev) {
-  if (ev) HM_HIP(hipEventRecord(ev[0], s));
+  constexpr int WPB = p1_waves_per_block<VT, NR>();
   const SlotDev* slots = (hi ? C.d_slots_hi : C.d_slots_lo).get<SlotDev>();
   const int ns = (int)C.mats.size();
+  if (ev) HM_HIP(hipEventRecord(ev[0], s));
   if (C.p1_tasks > 0) {
-    hipLaunchKernelGGL((k_phase1<LT, VT, NR>), dim3((C.p1_tasks + 3) / 4), dim3(256), 0, s, slots, ns, C.p1_tasks,
-                       slot_active, nrr, (const VT*)X, ldx);
+    hipLaunchKernelGGL((k_phase1<LT, VT, NR, WPB>), dim3((C.p1_tasks + WPB - 1) / WPB), dim3(64 * WPB), 0, s, slots,
+                       ns, C.p1_tasks, slot_active, nrr, (const VT*)X, ldx);
+  }
+  if (C.p1_reds > 0) {
+    hipLaunchKernelGGL((k_p1reduce<VT, NR>), dim3((C.p1_reds + 3) / 4), dim3(256), 0, s, slots, ns, C.p1_reds,
+                       slot_active, nrr);
   }
   if (ev) HM_HIP(hipEventRecord(ev[1], s));
   EpiDev<VT> e;
@@ -483,9 +654,9 @@ void launch_typed(const Composition& C, int nrr, bool hi, const void* X, int64_t
   e.a_z = (VT)ep.a_z;
   e.z = (const VT*)ep.z;
   e.ldz = ep.ldz;
-  if (C.p2_tasks > 0) {
-    hipLaunchKernelGGL((k_phase2<DT, LT, VT, NR>), dim3((C.p2_tasks + 3) / 4), dim3(256), 0, s, slots, ns,
-                       C.p2_tasks, slot_active, nrr, (const VT*)X, ldx, (VT*)Y, ldy, e);
+  if (C.p2_tiles > 0) {
+    hipLaunchKernelGGL((k_phase2<DT, LT, VT, NR>), dim3(C.p2_tiles), dim3(64 * P2_WAVES), 0, s, slots, ns,
+                       slot_active, nrr, (const VT*)X, ldx, (VT*)Y, ldy, e);
   }
   if (ev) HM_HIP(hipEventRecord(ev[2], s));
   HM_HIP(hipGetLastError());

@@ -191,7 +191,7 @@ bool hm_server::admit_one(SrvReq& r) {
     {
       Batch B({c->M}, 1, stream);
       B.io({c->eps_d.get<double>()}, {}, 0, nullptr, stream);
-      B.gather(B.epsp.get<double>(), 1, stream);
+      B.gather(B.epsp.get<double>(), 1, 1, stream);
       B.ensure_g({c->eps_d.get<double>()}, stream);
       c->g.alloc(n * 8);
       HM_HIP(hipMemcpyAsync(c->g.get(), B.g.get(), n * 8, hipMemcpyDeviceToDevice, stream));

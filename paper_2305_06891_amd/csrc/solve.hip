@@ -186,8 +186,11 @@ void Batch::io(const std::vector<const double*>& in, const std::vector<double*>&
   HM_HIP(hipStreamSynchronize(s));  // the host table is rewritten by the next call
 }
 
-void Batch::gather(double* dst, int ncol, hipStream_t s) {
-  hipLaunchKernelGGL(k_gather, grid_rows(N, W), dim3(256), 0, s, d_ios.get<SlotIO>(), (int)ios.size(), N, ncol, dst);
+void Batch::gather(double* dst, int ncol, int dst_cols, hipStream_t s) {
+  // dst holds dst_cols columns of N rows: columns ncol..dst_cols-1 are zeroed
+  HM_REQUIRE(ncol >= 1 && ncol <= dst_cols && dst_cols <= W, "gather: bad column counts");
+  hipLaunchKernelGGL(k_gather, grid_rows(N, dst_cols), dim3(256), 0, s, d_ios.get<SlotIO>(), (int)ios.size(), N, ncol,
+                     dst);
   HM_HIP(hipGetLastError());
 }
 
@@ -213,7 +216,7 @@ void Batch::ensure_g(const std::vector<const double*>& eps_user, hipStream_t s) 
   if (!gb) gb = std::make_unique<Batch>(mats, 1, s);
   Batch& B = *gb;
   B.io(eps_user, {}, 0, nullptr, s);
-  B.gather(B.epsp.get<double>(), 1, s);
+  B.gather(B.epsp.get<double>(), 1, 1, s);
   hipLaunchKernelGGL(k_omeps<double>, grid_rows(B.N), dim3(256), 0, s, B.epsp.get<double>(), B.N,
                      B.omeps64.get<double>());
   HM_HIP(hipMemcpyAsync(B.b64.get(), B.epsp.get(), B.N * 8, hipMemcpyDeviceToDevice, s));
@@ -238,10 +241,10 @@ SolveResult Batch::solve(const std::vector<const double*>& eps_user, const std::
   const bool want_q = p.want_q && std::any_of(q_user.begin(), q_user.end(), [](double* v) { return v != nullptr; });
   // permuted inputs
   io(eps_user, {}, 0, nullptr, s);
-  gather(epsp.get<double>(), 1, s);
+  gather(epsp.get<double>(), 1, 1, s);
   hipLaunchKernelGGL(k_omeps<double>, grid_rows(N), dim3(256), 0, s, epsp.get<double>(), N, omeps64.get<double>());
   io(T_user, {}, 0, &ldT, s);
-  gather(Tp.get<double>(), nrhs, s);
+  gather(Tp.get<double>(), nrhs, W, s);
   prepare_rhs(sigma, p, s);
   R = solve_prepared(p, s);
   if (want_q) {
@@ -375,16 +378,16 @@ TransientResult Batch::transient(const std::vector<const double*>& eps_user, dou
                                  const hm_solve_params& sp, double* history, hipStream_t s) {
   TransientResult TR;
   io(eps_user, {}, 0, nullptr, s);
-  gather(epsp.get<double>(), 1, s);
+  gather(epsp.get<double>(), 1, 1, s);
   hipLaunchKernelGGL(k_omeps<double>, grid_rows(N), dim3(256), 0, s, epsp.get<double>(), N, omeps64.get<double>());
   ensure_g(eps_user, s);
   std::vector<int64_t> ldv{ldT};
   io({T_user}, {}, 0, &ldv, s);
-  gather(Tp.get<double>(), nrhs, s);
+  gather(Tp.get<double>(), nrhs, W, s);
   std::vector<int64_t> lds{ldS};
   DevBuf srcp(N * W * 8), Tn(N * W * 8), Rv(N * W * 8), d_upd(W * 4);
   io({src_user}, {}, 0, &lds, s);
-  gather(srcp.get<double>(), nrhs, s);
+  gather(srcp.get<double>(), nrhs, W, s);
   std::vector<int64_t> ldh{ldT};
   if (history) {
     io({}, {history}, 0, &ldh, s);

@@ -48,7 +48,7 @@ struct Batch {
   Krylov& krylov(int vb, int restart, hipStream_t s);
   void io(const std::vector<const double*>& in, const std::vector<double*>& out, int64_t ld_in_default,
           const std::vector<int64_t>* lds, hipStream_t s);
-  void gather(double* dst, int ncol, hipStream_t s);
+  void gather(double* dst, int ncol, int dst_cols, hipStream_t s);
   void scatter(const double* src, int ncol, hipStream_t s);
   void ensure_g(const std::vector<const double*>& eps_user, hipStream_t s);
   void prepare_rhs(double sigma, const hm_solve_params& p, hipStream_t s);
