@@ -88,11 +88,11 @@ def main():
     tree = hm.hm_build_cluster_tree(ctx, c, nrm, area, cav.leaf, cav.eta)
     t_tree = time.perf_counter() - t0
     t0 = time.perf_counter()
-    M = hm.hm_assemble_hmatrix(ctx, tree, cav.aca_tol, 256, hm.HM_F32, hm.HM_F32)
+    M = hm.hm_assemble_hmatrix(ctx, tree, cav.aca_tol, 256, hm.HM_F32, hm.HM_F32, autotune=1)
     torch.cuda.synchronize()
     t_asm = time.perf_counter() - t0
     st = M.stats()
-    log("matrix", st, "tree %.2fs assembly %.2fs" % (t_tree, t_asm))
+    log("matrix", st, "tree %.2fs assembly %.2fs" % (t_tree, t_asm), "tuning", M.tuning())
     eps = torch.as_tensor(cav.eps, device=dev)
     T = torch.as_tensor(cav.T[:, 0], device=dev)
     p = hm.solve_params(rtol=1e-7, restart=30, max_iter=300, want_q=1, vec_dtype=hm.HM_F32)

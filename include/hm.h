@@ -127,6 +127,10 @@ typedef struct {
   int32_t keep_f32_copy;   /* with HM_BF16 factors: also keep FP32 factors (refinement residual) */
   int32_t closed_row_scale;/* 1: closed-cavity row scaling of eqs. (32)-(34) (clamp the row sum
                               to [0,1], divide rows with non-zero clamped sum by it); default 0 */
+  int32_t autotune;        /* 1: time the candidate work splits of the product's first kernel
+                              (rows per item, bytes per wave task) on this matrix and keep the
+                              fastest; 0: fixed defaults (128 rows, 16 KB).  Results are the same
+                              bit for bit either way except for the order of partial sums. */
 } hm_assembly_params;
 
 /* Evaluate the near field (every inadmissible leaf block, FP64 evaluation
@@ -148,6 +152,11 @@ hm_status hm_matrix_stats(const hm_matrix* M, int64_t* bytes_device, int64_t* en
  * blocks stored dense (fallbacks), sum of ranks.  Any pointer may be NULL. */
 hm_status hm_matrix_info(const hm_matrix* M, int64_t* n, int64_t* n_dense_blocks,
                          int64_t* n_lowrank_blocks, int64_t* n_fallback, int64_t* rank_sum);
+/* Work split of the product's first kernel chosen at assembly (fixed or
+ * autotuned): rows per item and minimum bytes per wave task; timing_us (may
+ * be NULL) receives the measured microseconds of the chosen split, or 0 when
+ * nothing was timed.  Any pointer may be NULL. */
+hm_status hm_matrix_tuning(const hm_matrix* M, int32_t* p1_rows, int32_t* p1_task_bytes, double* timing_us);
 void hm_matrix_destroy(hm_matrix* M);
 
 /* Y = alpha * F_H * X + beta * Y (Sec. 5.2: the block-wise product adds no
@@ -161,18 +170,22 @@ hm_status hm_hmatvec_ex(hm_ctx* ctx, const hm_matrix* M, int32_t nrhs, hm_dtype 
                         int32_t use_f32_copy, const void* X, int64_t ldx, void* Y, int64_t ldy,
                         double alpha, double beta);
 
-/* Timing of the product's two kernels, measured with HIP events recorded on
- * ctx's stream around each kernel of `reps` products y = F_H x on internal
- * permuted vectors (x = 1).  Before each product `flush_bytes` (>= 0) of
- * device memory are overwritten so that the 256 MB last-level cache holds
- * none of the matrix.  Outputs (HOST, any may be NULL): average ms of phase 1
- * (t = V^T x), of phase 2 (y = D x + U t) and of the whole product, and the
- * algorithmic bytes of each phase per product: phase 1 reads every V factor
- * once plus x and writes t; phase 2 reads every dense block and U factor once
- * plus x and t and writes y. */
-hm_status hm_hmatvec_profile(hm_ctx* ctx, const hm_matrix* M, int32_t nrhs, hm_dtype vec_dtype,
-                             int32_t use_f32_copy, int32_t reps, int64_t flush_bytes, double* ms_phase1,
-                             double* ms_phase2, double* ms_total, int64_t* bytes_phase1, int64_t* bytes_phase2);
+/* Timing of the product's two kernels for `count` matrices applied as one
+ * block-diagonal operator (one launch per phase, as in the batched solve),
+ * measured with HIP events recorded on ctx's stream around each kernel of
+ * `reps` products y = F_H x on internal permuted vectors (x = 1).  Before
+ * each product `flush_bytes` (>= 0) of device memory are streamed through the
+ * caches (read only) so that the 256 MB last-level cache holds none of the
+ * matrix.  M: HOST array of count matrices on ctx's device.  Outputs (HOST,
+ * any may be NULL): average ms of phase 1 (t = V^T x, with the reduction of
+ * row-split partial sums), of phase 2 (y = D x + U t) and of the whole
+ * product, and the algorithmic bytes of each phase per product summed over
+ * the matrices: phase 1 reads every V factor once plus x and writes t;
+ * phase 2 reads every dense block and U factor once plus x and t and writes y. */
+hm_status hm_hmatvec_profile(hm_ctx* ctx, int32_t count, const hm_matrix* const* M, int32_t nrhs,
+                             hm_dtype vec_dtype, int32_t use_f32_copy, int32_t reps, int64_t flush_bytes,
+                             double* ms_phase1, double* ms_phase2, double* ms_total, int64_t* bytes_phase1,
+                             int64_t* bytes_phase2);
 
 /* ----------------------------------------------------------- radiosity solve */
 

@@ -64,6 +64,17 @@ __global__ void k_perm_scatter(const int32_t* __restrict__ perm, const VT* __res
   if (i < n) out[perm[i] + j * ldo] = in[i + j * ldi];
 }
 
+// Streams a buffer through the caches without writing it (evicts the
+// last-level cache with clean lines); the sum is kept only if it is NaN.
+__global__ void k_flush_read(const float4* __restrict__ p, int64_t n4, float* __restrict__ sink) {
+  float acc = 0.f;
+  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n4; k += (int64_t)gridDim.x * blockDim.x) {
+    const float4 v = p[k];
+    acc += v.x + v.y + v.z + v.w;
+  }
+  if (acc != acc) sink[0] = acc;
+}
+
 __global__ void k_check_range(const double* __restrict__ v, int64_t n, int64_t ld, int ncol, double lo, double hi,
                               int lo_open, int* bad) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -231,6 +242,17 @@ hm_status hm_matrix_info(const hm_matrix* M, int64_t* n, int64_t* nd, int64_t* n
   return HM_OK;
 }
 
+hm_status hm_matrix_tuning(const hm_matrix* M, int32_t* rows, int32_t* task_bytes, double* us) {
+  if (!M) {
+    set_tl_error("hm_matrix_tuning: NULL matrix");
+    return HM_EINVAL;
+  }
+  if (rows) *rows = M->plan.p1p.rows;
+  if (task_bytes) *task_bytes = M->plan.p1p.task_bytes;
+  if (us) *us = M->plan.p1_us;
+  return HM_OK;
+}
+
 void hm_matrix_destroy(hm_matrix* M) {
   if (!M) return;
   (void)hipSetDevice(M->device);
@@ -298,32 +320,38 @@ hm_status hm_hmatvec(hm_ctx* ctx, const hm_matrix* M, int32_t nrhs, hm_dtype vt,
   return hm_hmatvec_ex(ctx, M, nrhs, vt, 0, X, ldx, Y, ldy, alpha, beta);
 }
 
-hm_status hm_hmatvec_profile(hm_ctx* ctx, const hm_matrix* M, int32_t nrhs, hm_dtype vt, int32_t use_hi, int32_t reps,
-                             int64_t flush_bytes, double* ms1, double* ms2, double* mst, int64_t* b1, int64_t* b2) {
+hm_status hm_hmatvec_profile(hm_ctx* ctx, int32_t count, const hm_matrix* const* Ms, int32_t nrhs, hm_dtype vt,
+                             int32_t use_hi, int32_t reps, int64_t flush_bytes, double* ms1, double* ms2, double* mst,
+                             int64_t* b1, int64_t* b2) {
   if (!ctx) {
     set_tl_error("hm_hmatvec_profile: NULL ctx");
     return HM_EINVAL;
   }
   return guarded(ctx, [&] {
-    HM_REQUIRE(M && reps >= 1 && nrhs >= 1 && nrhs <= 16 && flush_bytes >= 0, "hm_hmatvec_profile: bad arguments");
+    HM_REQUIRE(count >= 1 && Ms && reps >= 1 && nrhs >= 1 && nrhs <= 16 && flush_bytes >= 0,
+               "hm_hmatvec_profile: bad arguments");
     HM_REQUIRE(vt == HM_F64 || vt == HM_F32, "hm_hmatvec_profile: vec_dtype must be HM_F64 or HM_F32");
-    std::lock_guard<std::mutex> lk(const_cast<hm_matrix*>(M)->mu);
+    std::vector<const hm_matrix*> mats(Ms, Ms + count);
+    for (const hm_matrix* M : mats) {
+      HM_REQUIRE(M, "hm_hmatvec_profile: NULL matrix");
+      HM_REQUIRE(M->device == ctx->device, "hm_hmatvec_profile: matrix lives on another device");
+    }
     hipStream_t s = ctx->stream;
-    MatCache& mc = cache_of(*M);
     const int W = pad_width(nrhs);
-    auto& comp = mc.comps[W];
-    if (!comp) comp = make_composition({M}, W, 8, s);
-    const int64_t n = M->n;
     const int vb = vt == HM_F64 ? 8 : 4;
-    DevBuf X((size_t)n * W * vb), Y((size_t)n * W * vb), flush(flush_bytes > 0 ? (size_t)flush_bytes : 0);
+    // a composition of its own: the matrices' cached compositions are left alone
+    auto comp = make_composition(mats, W, vb, s);
+    const int64_t N = comp->N;
+    DevBuf X((size_t)N * W * vb), Y((size_t)N * W * vb), flush(flush_bytes > 0 ? (size_t)flush_bytes : 0), sink(16);
+    if (flush_bytes > 0) HM_HIP(hipMemsetAsync(flush.get(), 0, (size_t)flush_bytes, s));
     {
-      std::vector<char> h((size_t)n * W * vb);
+      std::vector<char> h((size_t)N * W * vb);
       if (vb == 8) {
         double* d = (double*)h.data();
-        for (int64_t k = 0; k < n * W; ++k) d[k] = 1.0;
+        for (int64_t k = 0; k < N * W; ++k) d[k] = 1.0;
       } else {
         float* f = (float*)h.data();
-        for (int64_t k = 0; k < n * W; ++k) f[k] = 1.0f;
+        for (int64_t k = 0; k < N * W; ++k) f[k] = 1.0f;
       }
       HM_HIP(hipMemcpyAsync(X.get(), h.data(), h.size(), hipMemcpyHostToDevice, s));
       HM_HIP(hipStreamSynchronize(s));
@@ -334,8 +362,10 @@ hm_status hm_hmatvec_profile(hm_ctx* ctx, const hm_matrix* M, int32_t nrhs, hm_d
     const bool hi = use_hi != 0;
     try {
       for (int r = 0; r < reps; ++r) {
-        if (flush_bytes > 0) HM_HIP(hipMemsetAsync(flush.get(), r & 0xff, (size_t)flush_bytes, s));
-        launch_matvec(*comp, nrhs, vb, hi, X.get(), n, Y.get(), n, Epilogue{}, nullptr, s, ev);
+        if (flush_bytes > 0)
+          hipLaunchKernelGGL(k_flush_read, dim3(1024), dim3(256), 0, s, flush.get<float4>(), flush_bytes / 16,
+                             sink.get<float>());
+        launch_matvec(*comp, nrhs, vb, hi, X.get(), N, Y.get(), N, Epilogue{}, nullptr, s, ev);
         HM_HIP(hipEventSynchronize(ev[2]));
         float a = 0, b = 0;
         HM_HIP(hipEventElapsedTime(&a, ev[0], ev[1]));
@@ -348,15 +378,20 @@ hm_status hm_hmatvec_profile(hm_ctx* ctx, const hm_matrix* M, int32_t nrhs, hm_d
       throw;
     }
     for (auto& e : ev) HM_HIP(hipEventDestroy(e));
-    const bool use_f32 = hi && M->has_hi;
-    const int64_t sl = use_f32 ? 4 : (int64_t)dtype_size(M->lr_dtype);
-    const int64_t sd = (int64_t)dtype_size(M->dense_dtype);
+    int64_t by1 = 0, by2 = 0;
     const int64_t vecs = (int64_t)nrhs * vb;
+    for (const hm_matrix* M : mats) {
+      const bool use_f32 = hi && M->has_hi;
+      const int64_t sl = use_f32 ? 4 : (int64_t)dtype_size(M->lr_dtype);
+      const int64_t sd = (int64_t)dtype_size(M->dense_dtype);
+      by1 += M->v_entries * sl + vecs * (M->n + M->Ktot);
+      by2 += M->dense_entries * sd + M->u_entries * sl + vecs * (2 * M->n + M->Ktot);
+    }
     if (ms1) *ms1 = t1 / reps;
     if (ms2) *ms2 = t2 / reps;
     if (mst) *mst = (t1 + t2) / reps;
-    if (b1) *b1 = M->v_entries * sl + vecs * (n + M->Ktot);
-    if (b2) *b2 = M->dense_entries * sd + M->u_entries * sl + vecs * (2 * n + M->Ktot);
+    if (b1) *b1 = by1;
+    if (b2) *b2 = by2;
   });
 }
 

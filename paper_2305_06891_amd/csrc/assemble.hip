@@ -510,6 +510,7 @@ hm_matrix* assemble(hm_ctx& ctx, const hm_tree& t, const hm_assembly_params& p) 
   }
   stages.clear();
   if (p.closed_row_scale) closed_row_scale(*M, s);
+  if (p.autotune) autotune_phase1(*M, s);
   HM_HIP(hipStreamSynchronize(s));
   return M.release();
 }

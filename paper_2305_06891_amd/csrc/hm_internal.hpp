@@ -134,7 +134,6 @@ void build_tree(hm_tree& t);  // fills perm, nodes, leaves, dense, lowrank from 
 constexpr int QW = 4;          // elements per lane vector
 constexpr int P2_MAXW = 256;   // padded columns per phase-2 item
 constexpr int P1_GW = 64;      // rank columns per phase-1 group (one per lane)
-constexpr int P1_RCH = 256;    // rows per phase-1 item (multiple of 4)
 constexpr int P1_XST = 256;    // rows of x staged in LDS at a time
 constexpr int TILE = 64;       // rows per phase-2 tile (lane = row)
 constexpr int P2_WAVES = 8;    // waves per phase-2 workgroup (one tile each)
@@ -179,7 +178,24 @@ struct Seg {
   int32_t col0, w, src, pad;
 };
 
+// One column cluster tau of the low-rank blocks: its V factors form
+// ceil(ktau / P1_GW) group panels of np rows (n rounded up to 4).
+struct P1Tau {
+  int64_t vbase;    // element offset of the first group panel
+  int64_t trow;     // t index of rank column 0
+  int32_t xrow, n, np, ktau;
+};
+
+// Phase-1 work split (tunable; the panel layout does not depend on it).
+struct P1Params {
+  int32_t rows = 128;          // rows per item (multiple of 64)
+  int32_t task_bytes = 16384;  // minimum matrix bytes per wave task
+};
+
 struct Plan {
+  std::vector<P1Tau> taus;
+  P1Params p1p;
+  double p1_us = 0.0;  // measured time of the chosen split (0: not timed)
   std::vector<P1Item> p1;
   std::vector<int32_t> p1_task;  // item begin per task, size ntasks + 1
   std::vector<P1Red> p1red;
@@ -272,6 +288,13 @@ struct Composition {
 
 void build_plan(hm_matrix& M, const std::vector<struct LrInfo>& lr, const std::vector<BlockRef>& dn,
                 const hm_tree& t, PackLists& pk, hipStream_t s);
+// Phase-1 items, partial reductions and tasks of a plan for the given split.
+void plan_phase1(Plan& P, const P1Params& pp);
+// Re-split phase 1 and upload its lists (the matrix must not be in use).
+void replan_phase1(hm_matrix& M, const P1Params& pp, hipStream_t s);
+// Times the candidate phase-1 splits on M (FP32 vectors unless the factors
+// are FP64) and keeps the fastest.  Call before any composition of M exists.
+void autotune_phase1(hm_matrix& M, hipStream_t s);
 // The host part of build_plan (no device calls): items, tasks, arena sizes.
 void plan_host(hm_matrix& M, const std::vector<struct LrInfo>& lr, const std::vector<BlockRef>& dn,
                const hm_tree& t, PackLists& pk);

@@ -24,7 +24,6 @@ namespace hm {
 namespace {
 
 constexpr int64_t ITEM_BYTES = 64 << 10;  // target matrix bytes per phase-2 item (FP32)
-constexpr int64_t TASK_BYTES = 32 << 10;  // minimum matrix bytes per wave task
 
 struct Tile {
   int32_t row0, m;
@@ -56,8 +55,7 @@ void plan_host(hm_matrix& M, const std::vector<LrInfo>& lr, const std::vector<Bl
   });
   std::vector<int32_t> tidx(lr.size());  // t index of rank column 0 of each block
   int64_t tcur = 0, vcur = 0;
-  int32_t parts1 = 0;
-  std::vector<int64_t> item_bytes1;
+  P.taus.clear();
   for (size_t q = 0; q < ord.size();) {
     size_t e = q;
     const BlockRef& b0 = lr[ord[q]].b;
@@ -72,29 +70,7 @@ void plan_host(hm_matrix& M, const std::vector<LrInfo>& lr, const std::vector<Bl
       pk.vr.push_back(VRepack{L.sv, tau_base, L.stage, n, L.k, lc, ktau, np});
       lc += L.k;
     }
-    const int32_t ngroups = (ktau + P1_GW - 1) / P1_GW;
-    const int32_t nq = np / 4;
-    const int32_t qch = P1_RCH / 4;
-    const int32_t nch = (nq + qch - 1) / qch;
-    for (int32_t g = 0; g < ngroups; ++g) {
-      const int32_t gw = std::min(P1_GW, ktau - g * P1_GW);
-      const int32_t trow = (int32_t)(tcur + g * P1_GW);
-      if (nch > 1) P.p1red.push_back(P1Red{trow, gw, parts1, nch});
-      for (int32_t c = 0; c < nch; ++c) {
-        P1Item it{};
-        it.base = tau_base + (int64_t)g * P1_GW * np;
-        it.gw = gw;
-        it.q0 = c * qch;
-        it.nq = std::min(qch, nq - c * qch);
-        it.nrows = n;
-        it.xrow = b0.cb;
-        it.trow = trow;
-        it.part = nch > 1 ? parts1 + c : -1;
-        P.p1.push_back(it);
-        item_bytes1.push_back((int64_t)it.nq * 4 * gw * 4);
-      }
-      if (nch > 1) parts1 += nch;
-    }
+    P.taus.push_back(P1Tau{tau_base, tcur, b0.cb, n, np, ktau});
     vcur += (int64_t)np * ktau;
     tcur += ktau;
     q = e;
@@ -206,20 +182,59 @@ void plan_host(hm_matrix& M, const std::vector<LrInfo>& lr, const std::vector<Bl
   }
   P.dense_elems = dcur;
   P.u_elems = ucur;
-  // ---- phase-1 tasks: consecutive items of at least TASK_BYTES
-  P.p1_task.clear();
-  P.p1_task.push_back(0);
+  plan_phase1(P, P.p1p);
+  M.Ktot = tcur;
+}
+
+void plan_phase1(Plan& P, const P1Params& pp) {
+  HM_REQUIRE(pp.rows >= 64 && pp.rows % 64 == 0 && pp.task_bytes >= 0, "plan: bad phase-1 split");
+  P.p1p = pp;
+  P.p1.clear();
+  P.p1red.clear();
+  P.p1_task.assign(1, 0);
+  int32_t parts = 0;
   int64_t acc = 0;
-  for (size_t k = 0; k < item_bytes1.size(); ++k) {
-    acc += item_bytes1[k];
-    if (acc >= TASK_BYTES) {
-      P.p1_task.push_back((int32_t)(k + 1));
-      acc = 0;
+  const int32_t qch = pp.rows / 4;
+  for (const P1Tau& T : P.taus) {
+    const int32_t ngroups = (T.ktau + P1_GW - 1) / P1_GW;
+    const int32_t nq = T.np / 4;
+    const int32_t nch = (nq + qch - 1) / qch;
+    for (int32_t g = 0; g < ngroups; ++g) {
+      const int32_t gw = std::min(P1_GW, T.ktau - g * P1_GW);
+      const int32_t trow = (int32_t)(T.trow + g * P1_GW);
+      if (nch > 1) P.p1red.push_back(P1Red{trow, gw, parts, nch});
+      for (int32_t c = 0; c < nch; ++c) {
+        P1Item it{};
+        it.base = T.vbase + (int64_t)g * P1_GW * T.np;
+        it.gw = gw;
+        it.q0 = c * qch;
+        it.nq = std::min(qch, nq - c * qch);
+        it.nrows = T.n;
+        it.xrow = T.xrow;
+        it.trow = trow;
+        it.part = nch > 1 ? parts + c : -1;
+        P.p1.push_back(it);
+        // consecutive items of at least task_bytes form one wave's task
+        acc += (int64_t)it.nq * 4 * gw * 4;
+        if (acc >= pp.task_bytes) {
+          P.p1_task.push_back((int32_t)P.p1.size());
+          acc = 0;
+        }
+      }
+      if (nch > 1) parts += nch;
     }
   }
-  if (P.p1_task.back() != (int32_t)item_bytes1.size()) P.p1_task.push_back((int32_t)item_bytes1.size());
-  P.n_p1_parts = parts1;
-  M.Ktot = tcur;
+  if (P.p1_task.back() != (int32_t)P.p1.size()) P.p1_task.push_back((int32_t)P.p1.size());
+  P.n_p1_parts = parts;
+}
+
+void replan_phase1(hm_matrix& M, const P1Params& pp, hipStream_t s) {
+  Plan& P = M.plan;
+  plan_phase1(P, pp);
+  upload(P.d_p1, P.p1, s);
+  upload(P.d_p1_task, P.p1_task, s);
+  upload(P.d_p1red, P.p1red, s);
+  HM_HIP(hipStreamSynchronize(s));
 }
 
 void build_plan(hm_matrix& M, const std::vector<LrInfo>& lr, const std::vector<BlockRef>& dn, const hm_tree& t,
@@ -233,6 +248,69 @@ void build_plan(hm_matrix& M, const std::vector<LrInfo>& lr, const std::vector<B
   upload(P.d_p2, P.p2, s);
   upload(P.d_segs, P.segs, s);
   HM_HIP(hipStreamSynchronize(s));
+}
+
+// Streams a buffer through the caches without writing it; the sum is
+// stored only if it is NaN, which keeps the loads alive.
+__global__ void k_tune_flush(const float4* __restrict__ p, int64_t n4, float* __restrict__ sink) {
+  float acc = 0.f;
+  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n4; k += (int64_t)gridDim.x * blockDim.x) {
+    const float4 v = p[k];
+    acc += v.x + v.y + v.z + v.w;
+  }
+  if (acc != acc) sink[0] = acc;
+}
+
+void autotune_phase1(hm_matrix& M, hipStream_t s) {
+  if (M.plan.taus.empty()) return;
+  const int vb = M.lr_dtype == HM_F64 ? 8 : 4;
+  const int64_t n = M.n;
+  const int64_t vbytes = M.v_entries * (int64_t)dtype_size(M.lr_dtype);
+  // matrices whose factors could stay in the last-level cache are timed
+  // after a read of 512 MB, as in the solve where phase 2 runs in between
+  const int64_t flush_bytes = vbytes > (16 << 20) ? (int64_t)512 << 20 : 0;
+  DevBuf X((size_t)n * vb), Y((size_t)n * vb), flush(flush_bytes), sink(16);
+  HM_HIP(hipMemsetAsync(X.get(), 0, (size_t)n * vb, s));
+  if (flush_bytes) HM_HIP(hipMemsetAsync(flush.get(), 0, (size_t)flush_bytes, s));
+  hipEvent_t ev[3];
+  for (auto& e : ev) HM_HIP(hipEventCreate(&e));
+  const int rows[] = {64, 128, 256};
+  const int task[] = {0, 8 << 10, 16 << 10, 32 << 10, 64 << 10};
+  P1Params best = M.plan.p1p;
+  double best_us = 1e30;
+  try {
+    for (int r : rows)
+      for (int tb : task) {
+        P1Params pp;
+        pp.rows = r;
+        pp.task_bytes = tb;
+        replan_phase1(M, pp, s);
+        auto comp = make_composition({&M}, 1, vb, s);
+        double tot = 0;
+        const int reps = 6;
+        for (int k = 0; k < reps + 1; ++k) {
+          if (flush_bytes)
+            hipLaunchKernelGGL(k_tune_flush, dim3(1024), dim3(256), 0, s, flush.get<float4>(), flush_bytes / 16,
+                               sink.get<float>());
+          launch_matvec(*comp, 1, vb, false, X.get(), n, Y.get(), n, Epilogue{}, nullptr, s, ev);
+          HM_HIP(hipEventSynchronize(ev[2]));
+          float a = 0;
+          HM_HIP(hipEventElapsedTime(&a, ev[0], ev[1]));
+          if (k > 0) tot += a;  // the first product warms up
+        }
+        const double us = 1e3 * tot / reps;
+        if (us < best_us) {
+          best_us = us;
+          best = pp;
+        }
+      }
+  } catch (...) {
+    for (auto& e : ev) (void)hipEventDestroy(e);
+    throw;
+  }
+  for (auto& e : ev) HM_HIP(hipEventDestroy(e));
+  replan_phase1(M, best, s);
+  M.plan.p1_us = best_us;
 }
 
 int64_t matrix_bytes(const hm_matrix& M, bool hi) {
@@ -329,27 +407,36 @@ __device__ inline int find_slot(const SlotDev* __restrict__ slots, int nslots, i
 }
 
 // Four consecutive stored elements as the arithmetic type.
-template <class VT, class MT> struct Ld4;
-template <class VT> struct Ld4<VT, float> {
-  __device__ static void go(const float* p, VT* o) {
-    const float4 v = *reinterpret_cast<const float4*>(p);
-    o[0] = v.x; o[1] = v.y; o[2] = v.z; o[3] = v.w;
+// Four consecutive panel entries in their stored type (one 8-32 byte load);
+// they are converted to the vector type only when they are used, so a batch
+// of loads in flight costs the stored bytes in registers, not the widened ones.
+template <class MT> struct Quad;
+template <> struct Quad<float> {
+  float4 v;
+  __device__ void load(const float* p) { v = *reinterpret_cast<const float4*>(p); }
+  __device__ void zero() { v = make_float4(0.f, 0.f, 0.f, 0.f); }
+  template <class VT> __device__ VT get(int e) const {
+    return (VT)(e == 0 ? v.x : e == 1 ? v.y : e == 2 ? v.z : v.w);
   }
 };
-template <class VT> struct Ld4<VT, double> {
-  __device__ static void go(const double* p, VT* o) {
-    const double2 a = reinterpret_cast<const double2*>(p)[0];
-    const double2 b = reinterpret_cast<const double2*>(p)[1];
-    o[0] = (VT)a.x; o[1] = (VT)a.y; o[2] = (VT)b.x; o[3] = (VT)b.y;
+template <> struct Quad<double> {
+  double2 a, b;
+  __device__ void load(const double* p) {
+    a = reinterpret_cast<const double2*>(p)[0];
+    b = reinterpret_cast<const double2*>(p)[1];
+  }
+  __device__ void zero() { a = b = make_double2(0.0, 0.0); }
+  template <class VT> __device__ VT get(int e) const {
+    return (VT)(e == 0 ? a.x : e == 1 ? a.y : e == 2 ? b.x : b.y);
   }
 };
-template <class VT> struct Ld4<VT, bf16_t> {
-  __device__ static void go(const bf16_t* p, VT* o) {
-    const uint2 v = *reinterpret_cast<const uint2*>(p);
-    o[0] = (VT)bf16_to_f32((bf16_t)(v.x & 0xffffu));
-    o[1] = (VT)bf16_to_f32((bf16_t)(v.x >> 16));
-    o[2] = (VT)bf16_to_f32((bf16_t)(v.y & 0xffffu));
-    o[3] = (VT)bf16_to_f32((bf16_t)(v.y >> 16));
+template <> struct Quad<bf16_t> {
+  uint2 v;
+  __device__ void load(const bf16_t* p) { v = *reinterpret_cast<const uint2*>(p); }
+  __device__ void zero() { v = make_uint2(0u, 0u); }
+  template <class VT> __device__ VT get(int e) const {
+    const uint32_t w = e < 2 ? v.x : v.y;
+    return (VT)bf16_to_f32((bf16_t)((e & 1) ? (w >> 16) : (w & 0xffffu)));
   }
 };
 
@@ -378,40 +465,39 @@ __device__ __forceinline__ void epilogue_store(int row, int lane, int m, int nrr
 }
 
 // 16-byte loads kept in flight per lane (registers: 4 values each).
-template <class VT, int NR>
+// Batch length (loads in flight per lane): 8 quads, 16 for BF16 entries
+// summed in FP32; fewer with many right-hand sides, whose accumulators and
+// staged inputs take the registers.  Sized to stay at or below 128 VGPRs so
+// that two workgroups of eight waves fit on a compute unit.
+template <class MT, class VT, int NR>
 constexpr int load_depth() {
-  return sizeof(VT) * NR <= 8 ? 16 : (NR <= 4 ? 8 : 4);
+  return NR > 4 ? 4 : (sizeof(MT) == 2 && sizeof(VT) == 4 && NR == 1 ? 16 : 8);
 }
 
-// acc[j] += sum over column quads [g0, g1) of A(lane, c) * in[c - 4*g0][j]
+// acc[j] += sum over column quads [g0, g1) of A(lane, c) * in[c - 4*g0][j];
+// loads go out in batches of UN (the tail batch predicated), so a whole
+// batch is in flight before the first multiply-add waits.
 template <class MT, class VT, int NR>
 __device__ __forceinline__ void panel_accumulate(const MT* __restrict__ a, int m, int g0, int g1,
                                                  const VT* __restrict__ in, bool act, VT* acc) {
   const int64_t step = (int64_t)m * 4;
-  constexpr int UN = load_depth<VT, NR>();
-  int g = g0;
-  for (; g + UN <= g1; g += UN) {
-    VT v[UN][4];
+  constexpr int UN = load_depth<MT, VT, NR>();
+  for (int g = g0; g < g1; g += UN) {
+    Quad<MT> v[UN];
 #pragma unroll
     for (int u = 0; u < UN; ++u) {
-      if (act) Ld4<VT, MT>::go(a + (g + u) * step, v[u]);
-      else v[u][0] = v[u][1] = v[u][2] = v[u][3] = VT(0);
+      if (act && g + u < g1) v[u].load(a + (g + u) * step);
+      else v[u].zero();
     }
 #pragma unroll
     for (int u = 0; u < UN; ++u)
+      if (g + u < g1)
 #pragma unroll
-      for (int e = 0; e < 4; ++e)
+        for (int e = 0; e < 4; ++e) {
+          const VT w = v[u].template get<VT>(e);
 #pragma unroll
-        for (int j = 0; j < NR; ++j) acc[j] += v[u][e] * in[((g - g0 + u) * 4 + e) * NR + j];
-  }
-  for (; g < g1; ++g) {
-    VT v[4];
-    if (act) Ld4<VT, MT>::go(a + g * step, v);
-    else v[0] = v[1] = v[2] = v[3] = VT(0);
-#pragma unroll
-    for (int e = 0; e < 4; ++e)
-#pragma unroll
-      for (int j = 0; j < NR; ++j) acc[j] += v[e] * in[((g - g0) * 4 + e) * NR + j];
+          for (int j = 0; j < NR; ++j) acc[j] += w * in[((g - g0 + u) * 4 + e) * NR + j];
+        }
   }
 }
 
@@ -524,13 +610,25 @@ __global__ __launch_bounds__(64 * P2_WAVES) void k_phase2(const SlotDev* __restr
   }
 }
 
+// Value of v held by lane l (l wave-uniform), for every lane.
+__device__ __forceinline__ float lane_bcast(float v, int l) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+}
+__device__ __forceinline__ double lane_bcast(double v, int l) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), l);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
 // Phase 1: lane l owns rank column l of a group panel: t[trow + l] (+ j*ldt)
-// = sum_r V(r, l) x(xrow + r).
+// = sum_r V(r, l) x(xrow + r).  The x entries of 64 rows are read with one
+// coalesced load (lane = row) and handed to every lane by lane broadcast; the
+// V loads go out in predicated batches.
 template <class LT, class VT, int NR, int WPB>
 __global__ __launch_bounds__(64 * WPB) void k_phase1(const SlotDev* __restrict__ slots, int nslots, int ntasks,
                                                      const int* __restrict__ slot_active, int nrr,
                                                      const VT* __restrict__ X, int64_t ldx) {
-  __shared__ VT lds_x[WPB][P1_XST * NR];
   const int lane = threadIdx.x & 63;
   const int wv = threadIdx.x >> 6;
   const int task = blockIdx.x * WPB + wv;
@@ -542,50 +640,40 @@ __global__ __launch_bounds__(64 * WPB) void k_phase1(const SlotDev* __restrict__
   const int ib = S.p1_task[lt], ie = S.p1_task[lt + 1];
   const VT* Xs = X + S.xoff;
   VT* T = (VT*)S.t;
-  VT* xs = lds_x[wv];
+  constexpr int UN = 16;  // one 64-row chunk per batch of loads
   for (int it = ib; it < ie; ++it) {
     const P1Item item = S.p1[it];
     const bool act = lane < item.gw;
     const LT* a = (const LT*)S.V + item.base + (int64_t)lane * 4;
     const int64_t step = (int64_t)item.gw * 4;
+    const VT* xr = Xs + item.xrow;
+    const int qe = item.q0 + item.nq;
     VT acc[NR];
 #pragma unroll
     for (int j = 0; j < NR; ++j) acc[j] = VT(0);
-    for (int q0 = item.q0; q0 < item.q0 + item.nq; q0 += P1_XST / 4) {
-      const int nqc = min(P1_XST / 4, item.q0 + item.nq - q0);
-      wave_lds_sync();
-      for (int r = lane; r < nqc * 4; r += 64) {
-        const int row = q0 * 4 + r;
+    for (int q0 = item.q0; q0 < qe; q0 += 16) {
+      // rows 4*q0 .. 4*q0+63 of the panel; x beyond the group's rows reads as 0
+      const int r0 = q0 * 4;
+      const int q1 = q0 + 16 < qe ? q0 + 16 : qe;
+      VT xv[NR];
 #pragma unroll
-        for (int j = 0; j < NR; ++j)
-          xs[r * NR + j] = (j < nrr && row < item.nrows) ? Xs[item.xrow + row + j * ldx] : VT(0);
+      for (int j = 0; j < NR; ++j)
+        xv[j] = (j < nrr && r0 + lane < item.nrows) ? xr[r0 + lane + j * ldx] : VT(0);
+      Quad<LT> v[UN];
+#pragma unroll
+      for (int u = 0; u < UN; ++u) {
+        if (act && q0 + u < q1) v[u].load(a + (int64_t)(q0 + u) * step);
+        else v[u].zero();
       }
-      wave_lds_sync();
-      int q = 0;
-      constexpr int UN = load_depth<VT, NR>();
-      for (; q + UN <= nqc; q += UN) {
-        VT v[UN][4];
 #pragma unroll
-        for (int u = 0; u < UN; ++u) {
-          if (act) Ld4<VT, LT>::go(a + (int64_t)(q0 + q + u) * step, v[u]);
-          else v[u][0] = v[u][1] = v[u][2] = v[u][3] = VT(0);
-        }
+      for (int u = 0; u < UN; ++u)
+        if (q0 + u < q1)
 #pragma unroll
-        for (int u = 0; u < UN; ++u)
+          for (int e = 0; e < 4; ++e) {
+            const VT w = v[u].template get<VT>(e);
 #pragma unroll
-          for (int e = 0; e < 4; ++e)
-#pragma unroll
-            for (int j = 0; j < NR; ++j) acc[j] += v[u][e] * xs[((q + u) * 4 + e) * NR + j];
-      }
-      for (; q < nqc; ++q) {
-        VT v[4];
-        if (act) Ld4<VT, LT>::go(a + (int64_t)(q0 + q) * step, v);
-        else v[0] = v[1] = v[2] = v[3] = VT(0);
-#pragma unroll
-        for (int e = 0; e < 4; ++e)
-#pragma unroll
-          for (int j = 0; j < NR; ++j) acc[j] += v[e] * xs[(q * 4 + e) * NR + j];
-      }
+            for (int j = 0; j < NR; ++j) acc[j] += w * lane_bcast(xv[j], u * 4 + e);
+          }
     }
     if (item.part < 0) {
       if (act)
@@ -627,8 +715,7 @@ namespace {
 
 template <class VT, int NR>
 constexpr int p1_waves_per_block() {
-  // LDS per wave: P1_XST staged rows of NR values; keep a workgroup <= 64 KB
-  return (int64_t)P1_XST * NR * sizeof(VT) * 4 <= (64 << 10) ? 4 : ((int64_t)P1_XST * NR * sizeof(VT) * 2 <= (64 << 10) ? 2 : 1);
+  return 4;
 }
 
 template <class DT, class LT, class VT, int NR>

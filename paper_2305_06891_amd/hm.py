@@ -41,7 +41,8 @@ class hm_tree_params(C.Structure):
 
 class hm_assembly_params(C.Structure):
     _fields_ = [("aca_tol", C.c_double), ("k_max", C.c_int32), ("lowrank_dtype", C.c_int),
-                ("dense_dtype", C.c_int), ("keep_f32_copy", C.c_int32), ("closed_row_scale", C.c_int32)]
+                ("dense_dtype", C.c_int), ("keep_f32_copy", C.c_int32), ("closed_row_scale", C.c_int32),
+                ("autotune", C.c_int32)]
 
 
 class hm_solve_params(C.Structure):
@@ -94,12 +95,14 @@ _PROTOS = {
                                   C.POINTER(C.c_int32)]),
     "hm_matrix_info": (C.c_int, [_vp, C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.POINTER(C.c_int64),
                                  C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
+    "hm_matrix_tuning": (C.c_int, [_vp, C.POINTER(C.c_int32), C.POINTER(C.c_int32), _dp]),
     "hm_matrix_destroy": (None, [_vp]),
     "hm_hmatvec": (C.c_int, [_vp, _vp, C.c_int32, C.c_int, _vp, C.c_int64, _vp, C.c_int64, C.c_double,
                              C.c_double]),
     "hm_hmatvec_ex": (C.c_int, [_vp, _vp, C.c_int32, C.c_int, C.c_int32, _vp, C.c_int64, _vp, C.c_int64,
                                 C.c_double, C.c_double]),
-    "hm_hmatvec_profile": (C.c_int, [_vp, _vp, C.c_int32, C.c_int, C.c_int32, C.c_int32, C.c_int64,
+    "hm_hmatvec_profile": (C.c_int, [_vp, C.c_int32, C.POINTER(_vp), C.c_int32, C.c_int, C.c_int32, C.c_int32,
+                                     C.c_int64,
                                      _dp, _dp, _dp, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
     "hm_solve_radiosity": (C.c_int, [_vp, _vp, _vp, C.c_int32, _vp, C.c_int64, C.c_double,
                                      C.POINTER(hm_solve_params), _vp, C.c_int64, _vp, C.c_int64,
@@ -267,6 +270,13 @@ class HMatrix:
                 "max_rank": mr.value, "n": n.value, "n_dense_blocks": nd.value, "n_lowrank_blocks": nl.value,
                 "n_fallback": nf.value, "rank_sum": rs.value}
 
+    def tuning(self):
+        """Work split of the product's first kernel (rows per item, bytes per
+        wave task) and its measured time in microseconds (0: not timed)."""
+        r, tb, us = C.c_int32(), C.c_int32(), C.c_double()
+        _check(lib.hm_matrix_tuning(self._h, C.byref(r), C.byref(tb), C.byref(us)))
+        return {"p1_rows": r.value, "p1_task_bytes": tb.value, "p1_us": us.value}
+
     def close(self):
         if self._h:
             lib.hm_matrix_destroy(self._h)
@@ -280,9 +290,9 @@ class HMatrix:
 
 
 def hm_assemble_hmatrix(ctx, tree: Tree, aca_tol=1e-6, k_max=256, lowrank_dtype=HM_F32, dense_dtype=HM_F32,
-                        keep_f32_copy=0, closed_row_scale=0) -> HMatrix:
+                        keep_f32_copy=0, closed_row_scale=0, autotune=0) -> HMatrix:
     p = hm_assembly_params(float(aca_tol), int(k_max), int(lowrank_dtype), int(dense_dtype), int(keep_f32_copy),
-                           int(closed_row_scale))
+                           int(closed_row_scale), int(autotune))
     h = _vp()
     _check(lib.hm_assemble_hmatrix(ctx.handle, tree._h, C.byref(p), C.byref(h)), ctx.handle)
     return HMatrix(h, ctx)
@@ -298,15 +308,18 @@ def hm_hmatvec(ctx, M: HMatrix, X, Y, alpha=1.0, beta=0.0, use_f32_copy=False):
     return Y
 
 
-def hm_hmatvec_profile(ctx, M: HMatrix, nrhs=1, vec_dtype=HM_F32, use_f32_copy=False, reps=20,
+def hm_hmatvec_profile(ctx, M, nrhs=1, vec_dtype=HM_F32, use_f32_copy=False, reps=20,
                        flush_bytes=512 << 20):
     """Average per-kernel times (HIP events on ctx's stream) and algorithmic
-    bytes of the two product kernels."""
+    bytes of the two product kernels; M is one HMatrix or a list of them
+    (applied as one block-diagonal operator)."""
+    Ms = list(M) if isinstance(M, (list, tuple)) else [M]
+    marr = (C.c_void_p * len(Ms))(*[m._h for m in Ms])
     m1, m2, mt = C.c_double(), C.c_double(), C.c_double()
     b1, b2 = C.c_int64(), C.c_int64()
-    _check(lib.hm_hmatvec_profile(ctx.handle, M._h, int(nrhs), int(vec_dtype), int(use_f32_copy), int(reps),
-                                  int(flush_bytes), C.byref(m1), C.byref(m2), C.byref(mt), C.byref(b1),
-                                  C.byref(b2)), ctx.handle)
+    _check(lib.hm_hmatvec_profile(ctx.handle, len(Ms), marr, int(nrhs), int(vec_dtype), int(use_f32_copy),
+                                  int(reps), int(flush_bytes), C.byref(m1), C.byref(m2), C.byref(mt),
+                                  C.byref(b1), C.byref(b2)), ctx.handle)
     return {"ms_phase1": m1.value, "ms_phase2": m2.value, "ms_total": mt.value, "bytes_phase1": b1.value,
             "bytes_phase2": b2.value}
 
@@ -392,10 +405,10 @@ class Server:
         self._n = {}
 
     def register_cavity(self, cavity_id, tree: Tree, eps_host, aca_tol=1e-6, k_max=256, lowrank_dtype=HM_BF16,
-                        dense_dtype=HM_F32, keep_f32_copy=1):
+                        dense_dtype=HM_F32, keep_f32_copy=1, autotune=0):
         e = _f64(eps_host)
         ap = hm_assembly_params(float(aca_tol), int(k_max), int(lowrank_dtype), int(dense_dtype),
-                                int(keep_f32_copy), 0)
+                                int(keep_f32_copy), 0, int(autotune))
         _check(lib.hm_server_register_cavity(self._h, C.c_uint64(cavity_id), tree._h, _ptr(e), C.byref(ap)))
         self._n[cavity_id] = tree.n
 
