@@ -1,15 +1,25 @@
 """Benchmark of the hierarchical view-factor radiosity path on one MI355X.
 
-One step = one radiosity solve (radiosity J and facet flux q of eq. (12))
-of the workload's cavity with the H-matrix resident in HBM (assembled once
-before the timed region, as the paper reuses its matrix over all Newton
-iterations and time steps).  Prints ONE JSON line.
+Workload ``c3`` (default): 64 convex cavities (icospheres, ellipsoids,
+closed cylinders; 2k-35k facets, 696,072 in all) solved together as one
+block-diagonal system.  Low-rank factors are stored in BF16 (near field in
+FP32) with an FP32 copy of the factors for the FP64 refinement residual.
+One step = one batched radiosity solve of all 64 cavities (radiosity J and
+facet flux q of eq. (12), one right-hand side each) with the H-matrices
+resident in HBM, assembled once before the timed region as the paper reuses
+its matrix over all Newton iterations and time steps.  ``value`` counts
+solves (cavity right-hand sides) per second.  Beside it, on the same GPU and
+cavities: the plain FP32 H-solve (per-cavity FP32 GMRES, one cavity at a
+time, FP32 factors) and the batched FP32 solve.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c2]
+Workload ``c2``: the 20,176-facet jittered cylinder, plain FP32 H-solve.
+
+Prints ONE JSON line on stdout (progress goes to stderr).
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c3|c2]
 """
 import argparse
 import json
-import math
 import os
 import sys
 import time
@@ -20,61 +30,176 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+METRIC = "H-matvec % HBM peak; radiosity solves/s vs plain FP32 H-solve at 1e-6 rel err"
+RTOL = 1e-7            # residual target; with cond(C) ~ 5 a solve error below 1e-6
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def cpu_baseline_c2(cav, budget_s=25.0):
-    """The oracle (numpy/scipy FP64, dense F + LU) timed on a bounded sample:
-    the centroid-rule assembly of 1,024 full rows of the 20,176-facet matrix
-    (scaled by n/1024) plus the LU of the radiosity system of a 5,000-facet
-    cylinder of the same family (scaled by (n/5000)^3).  One solve of the
-    oracle is one assembly plus one factorisation plus O(n^2) solves."""
-    from oracle import geometry, radiosity, viewfactor
-    from workloads import meshes
+def _blas_threads():
     try:
         from threadpoolctl import threadpool_info
-        cores = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+        return max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
     except Exception:
-        cores = os.cpu_count()
-    c, nrm, area = geometry.facets_from_triangles(cav.v, cav.tri)
-    n = area.size
-    rows = np.arange(0, n, max(1, n // 1024))[:1024]
+        return os.cpu_count()
+
+
+def cpu_baseline_dense(sample, sizes):
+    """The oracle (numpy/scipy FP64: dense centroid-rule F, LU of the
+    radiosity system, g = F C^-1 eps) timed on one sample cavity, then scaled
+    to each cavity of the workload: assembly by (n/n_s)^2, factorisation by
+    (n/n_s)^3.  Returns solves per second for one right-hand side per cavity."""
+    from oracle import geometry, radiosity, viewfactor
+    c, nrm, area = geometry.facets_from_triangles(sample.v, sample.tri)
+    ns = area.size
     t0 = time.perf_counter()
-    viewfactor.view_factor_rows(c, nrm, area, rows)
-    t_rows = time.perf_counter() - t0
-    t_asm = t_rows * n / rows.size
-    v, f = meshes.cylinder_for_count(5000, seed=1)
-    from workloads.meshes import inward
-    cs, ns_, as_ = geometry.facets_from_triangles(v, inward(f))
-    Fs = viewfactor.view_factor_matrix(cs, ns_, as_)
-    eps = np.full(as_.size, 0.5)
+    F = viewfactor.view_factor_matrix(c, nrm, area)
+    t_asm = time.perf_counter() - t0
     t0 = time.perf_counter()
-    rad = radiosity.DenseRadiosity(Fs, eps)
+    rad = radiosity.DenseRadiosity(F, sample.eps)
+    rad.radiosity(sample.T[:, 0])
+    rad.flux(sample.T[:, 0])
     t_lu = time.perf_counter() - t0
-    t_solve = t_asm + t_lu * (n / as_.size) ** 3
-    return {"value": 1.0 / t_solve, "unit": "solves/s", "cores": cores, "kind": "oracle",
-            "sample": "centroid-rule assembly of %d of %d rows (%.2f s, scaled x%.1f) + dense LU of the "
-                      "%d-facet cylinder system incl. g = F C^-1 eps (%.2f s, scaled x%.1f by n^3)"
-                      % (rows.size, n, t_rows, n / rows.size, as_.size, t_lu, (n / as_.size) ** 3),
-            "seconds_per_solve": t_solve}
+    total = sum(t_asm * (n / ns) ** 2 + t_lu * (n / ns) ** 3 for n in sizes)
+    return {"value": len(sizes) / total, "unit": "solves/s", "cores": _blas_threads(), "kind": "oracle",
+            "sample": "dense FP64 oracle on %s (%d facets): assembly %.2f s, LU + g + J + q %.2f s; scaled to "
+                      "the %d cavities (assembly x(n/%d)^2, LU x(n/%d)^3)"
+                      % (sample.name, ns, t_asm, t_lu, len(sizes), ns, ns),
+            "seconds_per_step": total}
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="c2", choices=["c2"])
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print("bench.py measures one GPU only: the multi-GPU path (sharding row clusters with an all-gather of x "
-              "per product) is a design, not built here", file=sys.stderr)
-        sys.exit(2)
+def roofline(prof, bytes_total_lim=1 << 30):
+    k1 = (prof["bytes_phase1"] / 1e6) / prof["ms_phase1"] if prof["ms_phase1"] > 0 else 0.0
+    k2 = (prof["bytes_phase2"] / 1e6) / prof["ms_phase2"]
+    dom = "k_phase2" if prof["ms_phase2"] >= prof["ms_phase1"] else "k_phase1"
+    ach = k2 if dom == "k_phase2" else k1
+    tot = (prof["bytes_phase1"] + prof["bytes_phase2"]) / 1e6 / prof["ms_total"]
+    return {"bound": "hbm", "kernel": dom, "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": ach / HBM_PEAK_GBS, "traffic": None,
+            "bytes_per_launch": prof["bytes_phase2"] if dom == "k_phase2" else prof["bytes_phase1"],
+            "ms_per_launch": prof["ms_phase2"] if dom == "k_phase2" else prof["ms_phase1"],
+            "phase1_GBps": k1, "phase2_GBps": k2,
+            "matvec_ms": prof["ms_total"], "matvec_GBps": tot, "matvec_frac": tot / HBM_PEAK_GBS}
 
+
+def base_record(args, value, ms, dtype, config):
+    return {"metric": METRIC, "value": value, "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
+            "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": dtype, "data": "synthetic", "config": config}
+
+
+def run_c3(args):
+    import torch
+    from paper_2305_06891_amd import hm
+    from workloads import configs
+
+    dev = torch.device("cuda:0")
+    cavs = configs.c3_batch()
+    sizes = [c.n for c in cavs]
+    ctx = hm.Context(0)
+    t0 = time.perf_counter()
+    trees = []
+    for cav in cavs:
+        c, nrm, area = hm.hm_facets_from_triangles(cav.v, cav.tri, orient=1)
+        trees.append(hm.hm_build_cluster_tree(ctx, c, nrm, area, cav.leaf, cav.eta))
+    t_tree = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    Mx = [hm.hm_assemble_hmatrix(ctx, t, cav.aca_tol, 256, hm.HM_BF16, hm.HM_F32, keep_f32_copy=1, autotune=1)
+          for t, cav in zip(trees, cavs)]
+    torch.cuda.synchronize()
+    t_asm = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    M32 = [hm.hm_assemble_hmatrix(ctx, t, cav.aca_tol, 256, hm.HM_F32, hm.HM_F32, autotune=1)
+           for t, cav in zip(trees, cavs)]
+    torch.cuda.synchronize()
+    t_asm32 = time.perf_counter() - t0
+    stx = [m.stats() for m in Mx]
+    ent_d = sum(s["entries_dense"] for s in stx)
+    ent_l = sum(s["entries_lowrank"] for s in stx)
+    log("c3: %d cavities, %d facets; tree %.2fs; mixed assembly %.2fs, fp32 assembly %.2fs; entries dense %d "
+        "low-rank %d; device bytes mixed %.2f GB fp32 %.2f GB"
+        % (len(cavs), sum(sizes), t_tree, t_asm, t_asm32, ent_d, ent_l,
+           sum(s["bytes_device"] for s in stx) / 1e9, sum(m.stats()["bytes_device"] for m in M32) / 1e9))
+    eps = [torch.as_tensor(c.eps, device=dev) for c in cavs]
+    T = [torch.as_tensor(c.T[:, 0], device=dev) for c in cavs]
+    J = [torch.empty_like(t) for t in T]
+    q = [torch.empty_like(t) for t in T]
+
+    # --- headline: batched mixed-precision solve (BF16 factors + FP64 refinement)
+    pmx = hm.solve_params(rtol=RTOL, restart=30, max_iter=400, mixed_precision=1, ir_inner_rtol=1e-3, want_q=1)
+    for _ in range(args.warmup):
+        hm.hm_solve_radiosity_batched(ctx, Mx, eps, T, hm.SIGMA, pmx, J, q)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        _, _, infos = hm.hm_solve_radiosity_batched(ctx, Mx, eps, T, hm.SIGMA, pmx, J, q)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ms = 1e3 * dt / args.steps
+    value = len(cavs) * args.steps / dt
+    i0 = infos[0]
+    worst = max(i["rel_residual"] for i in infos)
+    log("batched mixed: %.2f ms/step = %.1f solves/s; outer %d inner %d matvecs %d worst residual %.2e"
+        % (ms, value, i0["outer_iters"], i0["iters"], i0["matvecs"], worst))
+
+    # --- batched FP32 (batching gain without the precision gain)
+    p32 = hm.solve_params(rtol=RTOL, restart=30, max_iter=400, want_q=1, vec_dtype=hm.HM_F32)
+    hm.hm_solve_radiosity_batched(ctx, M32, eps, T, hm.SIGMA, p32, J, q)
+    torch.cuda.synchronize()
+    nb = max(1, args.steps // 2)
+    t0 = time.perf_counter()
+    for _ in range(nb):
+        _, _, infb = hm.hm_solve_radiosity_batched(ctx, M32, eps, T, hm.SIGMA, p32, J, q)
+    torch.cuda.synchronize()
+    rate_b32 = len(cavs) * nb / (time.perf_counter() - t0)
+    log("batched fp32: %.1f solves/s, iters %d" % (rate_b32, infb[0]["iters"]))
+
+    # --- plain FP32 H-solve: one cavity at a time
+    for m, e, t, j, qq in zip(M32, eps, T, J, q):
+        hm.hm_solve_radiosity(ctx, m, e, t, hm.SIGMA, p32, j, qq)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    it_plain = []
+    for m, e, t, j, qq in zip(M32, eps, T, J, q):
+        _, _, inf = hm.hm_solve_radiosity(ctx, m, e, t, hm.SIGMA, p32, j, qq)
+        it_plain.append(inf["iters"])
+    torch.cuda.synchronize()
+    rate_plain = len(cavs) / (time.perf_counter() - t0)
+    log("plain fp32: %.1f solves/s, iters %d..%d" % (rate_plain, min(it_plain), max(it_plain)))
+
+    # --- roofline of the batched product (the inner BF16 product and the FP32 one)
+    prof = hm.hm_hmatvec_profile(ctx, Mx, 1, hm.HM_F32, reps=20, flush_bytes=0)
+    prof_hi = hm.hm_hmatvec_profile(ctx, Mx, 1, hm.HM_F64, use_f32_copy=True, reps=10, flush_bytes=0)
+    prof32 = hm.hm_hmatvec_profile(ctx, M32, 1, hm.HM_F32, reps=10, flush_bytes=0)
+    rf = roofline(prof)
+    log("profile bf16", prof, "\nprofile hi", prof_hi, "\nprofile fp32", prof32)
+    out = base_record(args, value, ms, "f32+f64", {
+        "workload": "c3_64_cavities_%d_facets" % sum(sizes), "cavities": len(cavs), "facets": sum(sizes),
+        "facets_min": min(sizes), "facets_max": max(sizes), "leaf": 64, "eta": 1.5, "aca_tol": 1e-6,
+        "storage": "bf16 low-rank factors, fp32 near field, fp32 factor copy for the residual",
+        "solver": "batched gmres(30) fp32 inside fp64 iterative refinement", "rtol": RTOL, "nrhs": 1})
+    out["roofline"] = rf
+    out["roofline_fp64_residual_product"] = roofline(prof_hi)
+    out["roofline_fp32_product"] = roofline(prof32)
+    out["plain_fp32"] = {"value": rate_plain, "unit": "solves/s", "iters_min": min(it_plain),
+                         "iters_max": max(it_plain)}
+    out["batched_fp32"] = {"value": rate_b32, "unit": "solves/s", "iters": infb[0]["iters"]}
+    out["speedup_vs_plain_fp32"] = value / rate_plain
+    out["solve"] = {"outer_iters": i0["outer_iters"], "inner_iters": i0["iters"], "matvecs": i0["matvecs"],
+                    "worst_rel_residual": worst}
+    out["matrix"] = {"entries_dense": ent_d, "entries_lowrank": ent_l,
+                     "bytes_device_mixed": sum(s["bytes_device"] for s in stx),
+                     "n_fallback": sum(s["n_fallback"] for s in stx), "max_rank": max(s["max_rank"] for s in stx)}
+    out["assembly_s"] = {"mixed": t_asm, "fp32": t_asm32, "trees": t_tree}
+    if not args.no_cpu_baseline:
+        sample = min(cavs, key=lambda c: abs(c.n - 5000))
+        out["cpu_baseline"] = cpu_baseline_dense(sample, sizes)
+    return out
+
+
+def run_c2(args):
     import torch
     from paper_2305_06891_amd import hm
     from workloads import configs
@@ -95,61 +220,59 @@ def main():
     log("matrix", st, "tree %.2fs assembly %.2fs" % (t_tree, t_asm), "tuning", M.tuning())
     eps = torch.as_tensor(cav.eps, device=dev)
     T = torch.as_tensor(cav.T[:, 0], device=dev)
-    p = hm.solve_params(rtol=1e-7, restart=30, max_iter=300, want_q=1, vec_dtype=hm.HM_F32)
+    p = hm.solve_params(rtol=RTOL, restart=30, max_iter=300, want_q=1, vec_dtype=hm.HM_F32)
     J = torch.empty_like(T)
     q = torch.empty_like(T)
     for _ in range(args.warmup):
         hm.hm_solve_radiosity(ctx, M, eps, T, hm.SIGMA, p, J, q)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    infos = []
     for _ in range(args.steps):
         _, _, info = hm.hm_solve_radiosity(ctx, M, eps, T, hm.SIGMA, p, J, q)
-        infos.append(info)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     ms = 1e3 * dt / args.steps
-    value = args.steps / dt
     log("solve: %.3f ms/step, iters %d, matvecs %d, rel residual %.2e" %
-        (ms, infos[-1]["iters"], infos[-1]["matvecs"], infos[-1]["rel_residual"]))
-
+        (ms, info["iters"], info["matvecs"], info["rel_residual"]))
+    # the 300 MB product fits the 256 MB last-level cache in part: flush it
     prof = hm.hm_hmatvec_profile(ctx, M, 1, hm.HM_F32, reps=20, flush_bytes=512 << 20)
-    k1 = (prof["bytes_phase1"] / 1e6) / prof["ms_phase1"] if prof["ms_phase1"] > 0 else 0.0
-    k2 = (prof["bytes_phase2"] / 1e6) / prof["ms_phase2"]
-    dom = "k_phase2" if prof["ms_phase2"] >= prof["ms_phase1"] else "k_phase1"
-    ach = k2 if dom == "k_phase2" else k1
-    log("profile", prof, "GB/s phase1 %.0f phase2 %.0f" % (k1, k2))
-    out = {
-        "metric": "H-matvec % HBM peak; radiosity solves/s vs plain FP32 H-solve at 1e-6 rel err",
-        "value": value,
-        "unit": "solves/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": ms,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f32",
-        "data": "synthetic",
-        "config": {"workload": cav.name, "facets": n, "leaf": cav.leaf, "eta": cav.eta, "aca_tol": cav.aca_tol,
-                   "storage": "fp32", "krylov": "gmres(30) fp32 vectors, fp64 dots", "rtol": 1e-7, "nrhs": 1,
-                   "solver": "plain FP32 H-solve"},
-        "roofline": {"bound": "hbm", "kernel": dom, "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": ach / HBM_PEAK_GBS, "traffic": None,
-                     "bytes_per_launch": prof["bytes_phase2"] if dom == "k_phase2" else prof["bytes_phase1"],
-                     "ms_per_launch": prof["ms_phase2"] if dom == "k_phase2" else prof["ms_phase1"],
-                     "matvec_ms": prof["ms_total"],
-                     "matvec_GBps": (prof["bytes_phase1"] + prof["bytes_phase2"]) / 1e6 / prof["ms_total"]},
-        "matrix": {k: st[k] for k in ("bytes_device", "entries_dense", "entries_lowrank", "max_rank",
-                                      "n_dense_blocks", "n_lowrank_blocks", "n_fallback")},
-        "assembly_s": t_asm,
-        "tree_s": t_tree,
-        "solve": {"iters": infos[-1]["iters"], "matvecs": infos[-1]["matvecs"],
-                  "rel_residual": infos[-1]["rel_residual"]},
-    }
+    log("profile", prof)
+    out = base_record(args, args.steps / dt, ms, "f32", {
+        "workload": cav.name, "facets": n, "leaf": cav.leaf, "eta": cav.eta, "aca_tol": cav.aca_tol,
+        "storage": "fp32", "solver": "plain FP32 H-solve, gmres(30) fp32 vectors, fp64 dots", "rtol": RTOL,
+        "nrhs": 1})
+    out["roofline"] = roofline(prof)
+    out["matrix"] = {k: st[k] for k in ("bytes_device", "entries_dense", "entries_lowrank", "max_rank",
+                                        "n_dense_blocks", "n_lowrank_blocks", "n_fallback")}
+    out["tuning"] = M.tuning()
+    out["assembly_s"] = t_asm
+    out["solve"] = {"iters": info["iters"], "matvecs": info["matvecs"], "rel_residual": info["rel_residual"]}
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline_c2(cav)
+        from workloads import meshes
+        from workloads.configs import Cavity
+        v, f = meshes.cylinder_for_count(5000, seed=1)
+        rng = np.random.default_rng(2)
+        nf = f.shape[0]
+        sample = Cavity("cylinder_%d" % nf, v, meshes.inward(f), rng.uniform(0.1, 0.9, nf),
+                        rng.uniform(300, 1500, (nf, 1)))
+        out["cpu_baseline"] = cpu_baseline_dense(sample, [n])
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="c3", choices=["c3", "c2"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: the multi-GPU path (row clusters sharded by stored bytes with an "
+              "all-gather of x per product, or whole cavities per GPU) is a design, not built here",
+              file=sys.stderr)
+        sys.exit(2)
+    out = run_c3(args) if args.workload == "c3" else run_c2(args)
     print(json.dumps(out), flush=True)
 
 

@@ -46,6 +46,19 @@ template <class VT, class MT> __device__ inline VT ld_as(const MT* p) { return (
 template <> __device__ inline float ld_as<float, bf16_t>(const bf16_t* p) { return bf16_to_f32(*p); }
 template <> __device__ inline double ld_as<double, bf16_t>(const bf16_t* p) { return (double)bf16_to_f32(*p); }
 
+// Global-memory views of pointers whose address space the compiler cannot
+// see (pointers read from descriptors): accesses through them compile to
+// global loads and stores rather than flat ones, which would also hold up
+// every wait on LDS results.
+// (The host pass only parses device code; it sees plain pointers.)
+#if defined(__HIP_DEVICE_COMPILE__)
+template <class T> using gptr = __attribute__((address_space(1))) T*;
+#else
+template <class T> using gptr = T*;
+#endif
+template <class T> __device__ __forceinline__ gptr<const T> gbl(const T* p) { return (gptr<const T>)p; }
+template <class T> __device__ __forceinline__ gptr<T> gbl_w(T* p) { return (gptr<T>)p; }
+
 template <class T> __device__ inline T wave_sum(T v) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);

@@ -406,36 +406,32 @@ __device__ inline int find_slot(const SlotDev* __restrict__ slots, int nslots, i
   return lo;
 }
 
-// Four consecutive stored elements as the arithmetic type.
 // Four consecutive panel entries in their stored type (one 8-32 byte load);
 // they are converted to the vector type only when they are used, so a batch
 // of loads in flight costs the stored bytes in registers, not the widened ones.
+using f32x4 = float __attribute__((ext_vector_type(4)));
+using f64x2 = double __attribute__((ext_vector_type(2)));
+using u32x2 = uint32_t __attribute__((ext_vector_type(2)));
+
 template <class MT> struct Quad;
 template <> struct Quad<float> {
-  float4 v;
-  __device__ void load(const float* p) { v = *reinterpret_cast<const float4*>(p); }
-  __device__ void zero() { v = make_float4(0.f, 0.f, 0.f, 0.f); }
-  template <class VT> __device__ VT get(int e) const {
-    return (VT)(e == 0 ? v.x : e == 1 ? v.y : e == 2 ? v.z : v.w);
-  }
+  f32x4 v;
+  __device__ void load(const float* p) { v = *gbl(reinterpret_cast<const f32x4*>(p)); }
+  template <class VT> __device__ VT get(int e) const { return (VT)v[e]; }
 };
 template <> struct Quad<double> {
-  double2 a, b;
+  f64x2 a, b;
   __device__ void load(const double* p) {
-    a = reinterpret_cast<const double2*>(p)[0];
-    b = reinterpret_cast<const double2*>(p)[1];
+    a = gbl(reinterpret_cast<const f64x2*>(p))[0];
+    b = gbl(reinterpret_cast<const f64x2*>(p))[1];
   }
-  __device__ void zero() { a = b = make_double2(0.0, 0.0); }
-  template <class VT> __device__ VT get(int e) const {
-    return (VT)(e == 0 ? a.x : e == 1 ? a.y : e == 2 ? b.x : b.y);
-  }
+  template <class VT> __device__ VT get(int e) const { return (VT)(e < 2 ? a[e] : b[e - 2]); }
 };
 template <> struct Quad<bf16_t> {
-  uint2 v;
-  __device__ void load(const bf16_t* p) { v = *reinterpret_cast<const uint2*>(p); }
-  __device__ void zero() { v = make_uint2(0u, 0u); }
+  u32x2 v;
+  __device__ void load(const bf16_t* p) { v = *gbl(reinterpret_cast<const u32x2*>(p)); }
   template <class VT> __device__ VT get(int e) const {
-    const uint32_t w = e < 2 ? v.x : v.y;
+    const uint32_t w = v[e >> 1];
     return (VT)bf16_to_f32((bf16_t)((e & 1) ? (w >> 16) : (w & 0xffffu)));
   }
 };
@@ -453,42 +449,39 @@ __device__ __forceinline__ void epilogue_store(int row, int lane, int m, int nrr
                                                const VT* __restrict__ X, int64_t ldx, VT* __restrict__ Y,
                                                int64_t ldy, const EpiDev<VT>& ep) {
   if (lane >= m) return;
-  const VT w = ep.rowscale ? ep.rowscale[row] : VT(1);
+  const VT w = ep.rowscale ? gbl(ep.rowscale)[row] : VT(1);
 #pragma unroll
   for (int j = 0; j < NR; ++j) {
     if (j >= nrr) break;
     VT o = ep.a_acc * w * acc[j];
-    if (ep.a_x != VT(0)) o += ep.a_x * X[row + j * ldx];
-    if (ep.a_z != VT(0)) o += ep.a_z * ep.z[row + j * ep.ldz];
-    Y[row + j * ldy] = o;
+    if (ep.a_x != VT(0)) o += ep.a_x * gbl(X)[row + j * ldx];
+    if (ep.a_z != VT(0)) o += ep.a_z * gbl(ep.z)[row + j * ep.ldz];
+    gbl_w(Y)[row + j * ldy] = o;
   }
 }
 
-// 16-byte loads kept in flight per lane (registers: 4 values each).
-// Batch length (loads in flight per lane): 8 quads, 16 for BF16 entries
-// summed in FP32; fewer with many right-hand sides, whose accumulators and
-// staged inputs take the registers.  Sized to stay at or below 128 VGPRs so
-// that two workgroups of eight waves fit on a compute unit.
+// Batch length (loads in flight per lane) of the second kernel: 16 quads
+// with FP32 sums of FP32/BF16 entries, 8 with FP64 entries or sums (twice
+// the registers per value), fewer with several right-hand sides.  Sized to stay at or
+// below 128 VGPRs so that two workgroups of eight waves fit on a compute unit.
 template <class MT, class VT, int NR>
 constexpr int load_depth() {
-  return NR > 4 ? 4 : (sizeof(MT) == 2 && sizeof(VT) == 4 && NR == 1 ? 16 : 8);
+  return NR > 4 ? 4 : (NR > 1 || sizeof(VT) == 8 || sizeof(MT) == 8 ? 8 : 16);
 }
 
-// acc[j] += sum over column quads [g0, g1) of A(lane, c) * in[c - 4*g0][j];
-// loads go out in batches of UN (the tail batch predicated), so a whole
-// batch is in flight before the first multiply-add waits.
+// acc[j] += sum over column quads [g0, g1) of A(row, c) * in[c - 4*g0][j]
+// for the panel row whose first quad entry is a.  Loads go out in batches of
+// UN; the tail batch re-reads the last quad instead of branching (its terms
+// are skipped), so no load needs a predicate.
 template <class MT, class VT, int NR>
 __device__ __forceinline__ void panel_accumulate(const MT* __restrict__ a, int m, int g0, int g1,
-                                                 const VT* __restrict__ in, bool act, VT* acc) {
+                                                 const VT* __restrict__ in, VT* acc) {
   const int64_t step = (int64_t)m * 4;
   constexpr int UN = load_depth<MT, VT, NR>();
   for (int g = g0; g < g1; g += UN) {
     Quad<MT> v[UN];
 #pragma unroll
-    for (int u = 0; u < UN; ++u) {
-      if (act && g + u < g1) v[u].load(a + (g + u) * step);
-      else v[u].zero();
-    }
+    for (int u = 0; u < UN; ++u) v[u].load(a + (g + u < g1 ? g + u : g1 - 1) * step);
 #pragma unroll
     for (int u = 0; u < UN; ++u)
       if (g + u < g1)
@@ -525,20 +518,21 @@ __global__ __launch_bounds__(64 * P2_WAVES) void k_phase2(const SlotDev* __restr
   const int si = find_slot(slots, nslots, tile, 2);
   const SlotDev& S = slots[si];
   if (slot_active && !slot_active[S.slot]) return;  // uniform over the workgroup
-  const P2Tile T = S.p2t[tile - S.p2_tile_begin];
+  const P2Tile T = *gbl(S.p2t + (tile - S.p2_tile_begin));
   const VT* Xs = X + S.xoff;
   VT* Ys = Y + S.xoff;
   const VT* Ts = (const VT*)S.t;
   VT* in = lds_in[wv];
   Seg* sg_lds = lds_seg[wv];
-  const bool act = lane < T.m;
+  // lanes past the tile's rows repeat its last row; their sums are not stored
+  const int prow = lane < T.m ? lane : T.m - 1;
   VT acc[NR];
 #pragma unroll
   for (int j = 0; j < NR; ++j) acc[j] = VT(0);
   for (int k = wv; k < T.nit; k += P2_WAVES) {
-    const P2Item item = S.p2[T.it0 + k];
+    const P2Item item = *gbl(S.p2 + (T.it0 + k));
     wave_lds_sync();
-    for (int q = lane; q < item.nseg; q += 64) sg_lds[q] = S.segs[item.seg0 + q];
+    for (int q = lane; q < item.nseg; q += 64) sg_lds[q] = gbl(S.segs)[item.seg0 + q];
     wave_lds_sync();
     const Seg lastseg = sg_lds[item.nseg - 1];
     const int wtrue = lastseg.col0 + lastseg.w;
@@ -564,11 +558,11 @@ __global__ __launch_bounds__(64 * P2_WAVES) void k_phase2(const SlotDev* __restr
           if (sg.src >= 0) {
 #pragma unroll
             for (int j = 0; j < NR; ++j)
-              if (j < nrr) v[j] = Xs[sg.src + kk + j * ldx];
+              if (j < nrr) v[j] = gbl(Xs)[sg.src + kk + j * ldx];
           } else {
 #pragma unroll
             for (int j = 0; j < NR; ++j)
-              if (j < nrr) v[j] = Ts[(~sg.src) + kk + j * S.ldt];
+              if (j < nrr) v[j] = gbl(Ts)[(~sg.src) + kk + j * S.ldt];
           }
         }
 #pragma unroll
@@ -576,11 +570,10 @@ __global__ __launch_bounds__(64 * P2_WAVES) void k_phase2(const SlotDev* __restr
       }
       wave_lds_sync();
       if (item.kind == 0)
-        panel_accumulate<DT, VT, NR>((const DT*)S.dense + item.base + lane * 4, T.m, c0 >> 2, (c0 + cw) >> 2, in,
-                                     act, acc);
-      else
-        panel_accumulate<LT, VT, NR>((const LT*)S.U + item.base + lane * 4, T.m, c0 >> 2, (c0 + cw) >> 2, in, act,
+        panel_accumulate<DT, VT, NR>((const DT*)S.dense + item.base + prow * 4, T.m, c0 >> 2, (c0 + cw) >> 2, in,
                                      acc);
+      else
+        panel_accumulate<LT, VT, NR>((const LT*)S.U + item.base + prow * 4, T.m, c0 >> 2, (c0 + cw) >> 2, in, acc);
     }
   }
   // combine the waves in order and finish the tile
@@ -637,14 +630,17 @@ __global__ __launch_bounds__(64 * WPB) void k_phase1(const SlotDev* __restrict__
   const SlotDev& S = slots[si];
   if (slot_active && !slot_active[S.slot]) return;
   const int lt = task - S.p1_task_begin;
-  const int ib = S.p1_task[lt], ie = S.p1_task[lt + 1];
+  const int ib = gbl(S.p1_task)[lt], ie = gbl(S.p1_task)[lt + 1];
   const VT* Xs = X + S.xoff;
   VT* T = (VT*)S.t;
-  constexpr int UN = 16;  // one 64-row chunk per batch of loads
+  // one 64-row chunk per batch of loads (two batches when the entries or
+  // the sums are FP64, to stay within 128 VGPRs)
+  constexpr int UN = sizeof(LT) + sizeof(VT) > 8 ? 8 : 16;
   for (int it = ib; it < ie; ++it) {
-    const P1Item item = S.p1[it];
+    const P1Item item = *gbl(S.p1 + it);
     const bool act = lane < item.gw;
-    const LT* a = (const LT*)S.V + item.base + (int64_t)lane * 4;
+    // lanes past the group's columns repeat its last column (not stored)
+    const LT* a = (const LT*)S.V + item.base + (int64_t)(act ? lane : item.gw - 1) * 4;
     const int64_t step = (int64_t)item.gw * 4;
     const VT* xr = Xs + item.xrow;
     const int qe = item.q0 + item.nq;
@@ -658,32 +654,32 @@ __global__ __launch_bounds__(64 * WPB) void k_phase1(const SlotDev* __restrict__
       VT xv[NR];
 #pragma unroll
       for (int j = 0; j < NR; ++j)
-        xv[j] = (j < nrr && r0 + lane < item.nrows) ? xr[r0 + lane + j * ldx] : VT(0);
-      Quad<LT> v[UN];
+        xv[j] = (j < nrr && r0 + lane < item.nrows) ? gbl(xr)[r0 + lane + j * ldx] : VT(0);
+      for (int h = 0; h < 16; h += UN) {
+        const int qb = q0 + h;
+        Quad<LT> v[UN];
 #pragma unroll
-      for (int u = 0; u < UN; ++u) {
-        if (act && q0 + u < q1) v[u].load(a + (int64_t)(q0 + u) * step);
-        else v[u].zero();
+        for (int u = 0; u < UN; ++u) v[u].load(a + (int64_t)(qb + u < q1 ? qb + u : q1 - 1) * step);
+#pragma unroll
+        for (int u = 0; u < UN; ++u)
+          if (qb + u < q1)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+              const VT w = v[u].template get<VT>(e);
+#pragma unroll
+              for (int j = 0; j < NR; ++j) acc[j] += w * lane_bcast(xv[j], (h + u) * 4 + e);
+            }
       }
-#pragma unroll
-      for (int u = 0; u < UN; ++u)
-        if (q0 + u < q1)
-#pragma unroll
-          for (int e = 0; e < 4; ++e) {
-            const VT w = v[u].template get<VT>(e);
-#pragma unroll
-            for (int j = 0; j < NR; ++j) acc[j] += w * lane_bcast(xv[j], u * 4 + e);
-          }
     }
     if (item.part < 0) {
       if (act)
 #pragma unroll
         for (int j = 0; j < NR; ++j)
-          if (j < nrr) T[item.trow + lane + j * S.ldt] = acc[j];
+          if (j < nrr) gbl_w(T)[item.trow + lane + j * S.ldt] = acc[j];
     } else {
       VT* P = (VT*)S.part1 + (int64_t)item.part * P1_GW * NR;
 #pragma unroll
-      for (int j = 0; j < NR; ++j) P[j * P1_GW + lane] = acc[j];
+      for (int j = 0; j < NR; ++j) gbl_w(P)[j * P1_GW + lane] = acc[j];
     }
   }
 }
@@ -697,7 +693,7 @@ __global__ __launch_bounds__(256) void k_p1reduce(const SlotDev* __restrict__ sl
   if (r >= nreds) return;
   const SlotDev& S = slots[find_slot(slots, nslots, r, 1)];
   if (slot_active && !slot_active[S.slot]) return;
-  const P1Red R = S.p1red[r - S.p1red_begin];
+  const P1Red R = *gbl(S.p1red + (r - S.p1red_begin));
   if (lane >= R.gw) return;
   const VT* P0 = (const VT*)S.part1 + (int64_t)R.part0 * P1_GW * NR;
   VT* T = (VT*)S.t;
@@ -705,8 +701,8 @@ __global__ __launch_bounds__(256) void k_p1reduce(const SlotDev* __restrict__ sl
   for (int j = 0; j < NR; ++j) {
     if (j >= nrr) break;
     VT sum = VT(0);
-    for (int p = 0; p < R.nparts; ++p) sum += P0[((int64_t)p * NR + j) * P1_GW + lane];
-    T[R.trow + lane + j * S.ldt] = sum;
+    for (int p = 0; p < R.nparts; ++p) sum += gbl(P0)[((int64_t)p * NR + j) * P1_GW + lane];
+    gbl_w(T)[R.trow + lane + j * S.ldt] = sum;
   }
 }
 
