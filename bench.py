@@ -84,6 +84,48 @@ def roofline(prof, bytes_total_lim=1 << 30):
             "matvec_ms": prof["ms_total"], "matvec_GBps": tot, "matvec_frac": tot / HBM_PEAK_GBS}
 
 
+KERNEL_SOURCES = ("paper_2305_06891_amd/csrc/matvec.hip", "paper_2305_06891_amd/csrc/dev_common.hpp",
+                  "paper_2305_06891_amd/csrc/hm_internal.hpp")
+COUNTERS = os.path.join(ROOT, "profiles", "hmatvec_c3_batch_hbm_counters.md")
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed FETCH_SIZE /
+    WRITE_SIZE summary (calibrated against a plain copy kernel), or None when
+    the kernel sources changed since those counters were taken."""
+    import hashlib
+    try:
+        txt = open(COUNTERS).read()
+    except OSError:
+        return None
+    h = hashlib.sha256()
+    for s in KERNEL_SOURCES:
+        h.update(open(os.path.join(ROOT, s), "rb").read())
+    if ("`%s`" % h.hexdigest()[:16]) not in txt:
+        return None
+    for line in txt.splitlines():
+        if line.startswith("traffic_bytes %s:" % kernel):
+            return int(line.split(":")[1])
+    return None
+
+
+def copy_ceiling_gbps():
+    """Streaming copy b = 1.0 * a of 1 GiB (torch elementwise kernel): bytes
+    read + written per second, best of 5 (HIP events)."""
+    import torch
+    a = torch.ones(256 << 20, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    best = 1e30
+    for _ in range(6):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        torch.mul(a, 1.0, out=b)
+        e1.record()
+        e1.synchronize()
+        best = min(best, e0.elapsed_time(e1))
+    return 2 * a.numel() * 4 / 1e6 / best
+
+
 def base_record(args, value, ms, dtype, config):
     return {"metric": METRIC, "value": value, "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
             "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
@@ -174,7 +216,12 @@ def run_c3(args):
     prof_hi = hm.hm_hmatvec_profile(ctx, Mx, 1, hm.HM_F64, use_f32_copy=True, reps=10, flush_bytes=0)
     prof32 = hm.hm_hmatvec_profile(ctx, M32, 1, hm.HM_F32, reps=10, flush_bytes=0)
     rf = roofline(prof)
-    log("profile bf16", prof, "\nprofile hi", prof_hi, "\nprofile fp32", prof32)
+    rf["traffic"] = measured_traffic("k_phase2<float, bf16, float, 1>" if rf["kernel"] == "k_phase2"
+                                     else "k_phase1<bf16, float, 1, 4>")
+    ceil = copy_ceiling_gbps()
+    rf["copy_ceiling_GBps"] = ceil
+    rf["frac_of_copy_ceiling"] = rf["achieved"] / ceil
+    log("profile bf16", prof, "\nprofile hi", prof_hi, "\nprofile fp32", prof32, "\ncopy ceiling %.0f GB/s" % ceil)
     out = base_record(args, value, ms, "f32+f64", {
         "workload": "c3_64_cavities_%d_facets" % sum(sizes), "cavities": len(cavs), "facets": sum(sizes),
         "facets_min": min(sizes), "facets_max": max(sizes), "leaf": 64, "eta": 1.5, "aca_tol": 1e-6,
@@ -197,6 +244,40 @@ def run_c3(args):
         sample = min(cavs, key=lambda c: abs(c.n - 5000))
         out["cpu_baseline"] = cpu_baseline_dense(sample, sizes)
     return out
+
+
+def run_kernels_only(args):
+    """Only the product kernels of the 64-cavity batch (no solves), for
+    profiler runs: 20 BF16-factor products with FP32 vectors, 10 products on
+    the FP32 factor copy with FP64 vectors, then 5 elementwise copies of
+    1 GiB (b = 1.0 * a: a plain streaming kernel of known size that
+    calibrates the HBM byte counters)."""
+    import torch
+    from paper_2305_06891_amd import hm
+    from workloads import configs
+
+    cavs = configs.c3_batch()
+    ctx = hm.Context(0)
+    Mx = []
+    for cav in cavs:
+        c, nrm, area = hm.hm_facets_from_triangles(cav.v, cav.tri, orient=1)
+        t = hm.hm_build_cluster_tree(ctx, c, nrm, area, cav.leaf, cav.eta)
+        Mx.append(hm.hm_assemble_hmatrix(ctx, t, cav.aca_tol, 256, hm.HM_BF16, hm.HM_F32, keep_f32_copy=1,
+                                         autotune=1))
+    torch.cuda.synchronize()
+    log("assembled %d cavities" % len(Mx))
+    prof = hm.hm_hmatvec_profile(ctx, Mx, 1, hm.HM_F32, reps=20, flush_bytes=0)
+    log("bf16 product x20:", prof)
+    prof_hi = hm.hm_hmatvec_profile(ctx, Mx, 1, hm.HM_F64, use_f32_copy=True, reps=10, flush_bytes=0)
+    log("fp32-copy product, fp64 vectors x10:", prof_hi)
+    a = torch.ones(256 << 20, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(5):
+        torch.mul(a, 1.0, out=b)
+    torch.cuda.synchronize()
+    log("copied 5 x %d bytes" % (a.numel() * 4))
+    return {"kernels_only": True, "roofline": roofline(prof), "roofline_fp64_residual_product": roofline(prof_hi),
+            "copy_bytes": a.numel() * 4}
 
 
 def run_c2(args):
@@ -266,13 +347,18 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="c3", choices=["c3", "c2"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--kernels-only", action="store_true",
+                    help="profiling aid: only the batched product kernels and a calibration copy, no solves")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the multi-GPU path (row clusters sharded by stored bytes with an "
               "all-gather of x per product, or whole cavities per GPU) is a design, not built here",
               file=sys.stderr)
         sys.exit(2)
-    out = run_c3(args) if args.workload == "c3" else run_c2(args)
+    if args.kernels_only:
+        out = run_kernels_only(args)
+    else:
+        out = run_c3(args) if args.workload == "c3" else run_c2(args)
     print(json.dumps(out), flush=True)
 
 
