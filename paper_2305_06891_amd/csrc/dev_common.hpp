@@ -59,6 +59,20 @@ template <class T> using gptr = T*;
 template <class T> __device__ __forceinline__ gptr<const T> gbl(const T* p) { return (gptr<const T>)p; }
 template <class T> __device__ __forceinline__ gptr<T> gbl_w(T* p) { return (gptr<T>)p; }
 
+// A descriptor that every lane of the wave reads at the same address,
+// returned in scalar registers (readfirstlane per 32-bit word), so that the
+// compiler treats its fields as wave-uniform: branches on them stay scalar
+// and do not wait on unrelated loads.
+template <class T> __device__ __forceinline__ T uniform_load(const T* p) {
+  static_assert(sizeof(T) % 4 == 0, "descriptor size must be a multiple of 4");
+  T v = *gbl(p);
+  int* w = reinterpret_cast<int*>(&v);
+#pragma unroll
+  for (int k = 0; k < (int)(sizeof(T) / 4); ++k) w[k] = __builtin_amdgcn_readfirstlane(w[k]);
+  return v;
+}
+__device__ __forceinline__ int uniform_int(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
 template <class T> __device__ inline T wave_sum(T v) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);

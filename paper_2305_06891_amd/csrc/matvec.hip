@@ -11,6 +11,7 @@
 // workgroups, so results do not depend on scheduling.  Several matrices can
 // be multiplied in one launch ("slots" of a block-diagonal operator).
 #include <algorithm>
+#include <type_traits>
 #include <cmath>
 #include <map>
 #include <numeric>
@@ -399,7 +400,8 @@ __device__ inline int find_slot(const SlotDev* __restrict__ slots, int nslots, i
   int lo = 0, hi = nslots - 1;
   while (lo < hi) {
     const int mid = (lo + hi + 1) >> 1;
-    const int b = which == 0 ? slots[mid].p1_task_begin : (which == 1 ? slots[mid].p1red_begin : slots[mid].p2_tile_begin);
+    const int* f = which == 0 ? &slots[mid].p1_task_begin : (which == 1 ? &slots[mid].p1red_begin : &slots[mid].p2_tile_begin);
+    const int b = uniform_int(*gbl(f));
     if (b <= task) lo = mid;
     else hi = mid - 1;
   }
@@ -500,6 +502,43 @@ constexpr int p2_chunk() {
   return (int)std::min<int64_t>(P2_MAXW, ((4096 / ((int64_t)NR * sizeof(VT))) / 4) * 4);
 }
 
+// Stages the inputs of item columns [c0, c0 + cw) in LDS (in[col][rhs]):
+// every lane finds the run of each of its columns and gathers, so all
+// gathers are in flight at once; columns past the item's width read 0.
+template <class VT, int NR>
+__device__ __forceinline__ void stage_inputs(VT* in, const Seg* sg_lds, int nseg, int wtrue, int c0, int cw, int lane,
+                                             int nrr, const VT* Xs, int64_t ldx, const VT* Ts, int64_t ldt) {
+  wave_lds_sync();
+  for (int cc = lane; cc < cw; cc += 64) {
+    const int c = c0 + cc;
+    VT v[NR];
+#pragma unroll
+    for (int j = 0; j < NR; ++j) v[j] = VT(0);
+    if (c < wtrue) {
+      int lo = 0, hi = nseg - 1;
+      while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (sg_lds[mid].col0 <= c) lo = mid;
+        else hi = mid - 1;
+      }
+      const Seg sg = sg_lds[lo];
+      const int kk = c - sg.col0;
+      if (sg.src >= 0) {
+#pragma unroll
+        for (int j = 0; j < NR; ++j)
+          if (j < nrr) v[j] = gbl(Xs)[sg.src + kk + j * ldx];
+      } else {
+#pragma unroll
+        for (int j = 0; j < NR; ++j)
+          if (j < nrr) v[j] = gbl(Ts)[(~sg.src) + kk + j * ldt];
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < NR; ++j) in[cc * NR + j] = v[j];
+  }
+  wave_lds_sync();
+}
+
 // Phase 2: one workgroup per row tile, lane = row of the tile; the waves
 // share the tile's items and add their sums in LDS in wave order.
 template <class DT, class LT, class VT, int NR>
@@ -516,9 +555,9 @@ __global__ __launch_bounds__(64 * P2_WAVES) void k_phase2(const SlotDev* __restr
   const int wv = threadIdx.x >> 6;
   const int tile = blockIdx.x;
   const int si = find_slot(slots, nslots, tile, 2);
-  const SlotDev& S = slots[si];
-  if (slot_active && !slot_active[S.slot]) return;  // uniform over the workgroup
-  const P2Tile T = *gbl(S.p2t + (tile - S.p2_tile_begin));
+  const SlotDev S = uniform_load(slots + si);
+  if (slot_active && !uniform_int(*gbl(slot_active + S.slot))) return;  // uniform over the workgroup
+  const P2Tile T = uniform_load(S.p2t + (tile - S.p2_tile_begin));
   const VT* Xs = X + S.xoff;
   VT* Ys = Y + S.xoff;
   const VT* Ts = (const VT*)S.t;
@@ -530,7 +569,7 @@ __global__ __launch_bounds__(64 * P2_WAVES) void k_phase2(const SlotDev* __restr
 #pragma unroll
   for (int j = 0; j < NR; ++j) acc[j] = VT(0);
   for (int k = wv; k < T.nit; k += P2_WAVES) {
-    const P2Item item = *gbl(S.p2 + (T.it0 + k));
+    const P2Item item = uniform_load(S.p2 + (T.it0 + k));
     wave_lds_sync();
     for (int q = lane; q < item.nseg; q += 64) sg_lds[q] = gbl(S.segs)[item.seg0 + q];
     wave_lds_sync();
@@ -538,37 +577,7 @@ __global__ __launch_bounds__(64 * P2_WAVES) void k_phase2(const SlotDev* __restr
     const int wtrue = lastseg.col0 + lastseg.w;
     for (int c0 = 0; c0 < item.w; c0 += CW) {
       const int cw = min(CW, item.w - c0);
-      // stage inputs of columns [c0, c0 + cw): every lane finds the run of
-      // each of its columns and gathers, so all gathers are in flight at once
-      wave_lds_sync();
-      for (int cc = lane; cc < cw; cc += 64) {
-        const int c = c0 + cc;
-        VT v[NR];
-#pragma unroll
-        for (int j = 0; j < NR; ++j) v[j] = VT(0);
-        if (c < wtrue) {
-          int lo = 0, hi = item.nseg - 1;
-          while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (sg_lds[mid].col0 <= c) lo = mid;
-            else hi = mid - 1;
-          }
-          const Seg sg = sg_lds[lo];
-          const int kk = c - sg.col0;
-          if (sg.src >= 0) {
-#pragma unroll
-            for (int j = 0; j < NR; ++j)
-              if (j < nrr) v[j] = gbl(Xs)[sg.src + kk + j * ldx];
-          } else {
-#pragma unroll
-            for (int j = 0; j < NR; ++j)
-              if (j < nrr) v[j] = gbl(Ts)[(~sg.src) + kk + j * S.ldt];
-          }
-        }
-#pragma unroll
-        for (int j = 0; j < NR; ++j) in[cc * NR + j] = v[j];
-      }
-      wave_lds_sync();
+      stage_inputs<VT, NR>(in, sg_lds, item.nseg, wtrue, c0, cw, lane, nrr, Xs, ldx, Ts, S.ldt);
       if (item.kind == 0)
         panel_accumulate<DT, VT, NR>((const DT*)S.dense + item.base + prow * 4, T.m, c0 >> 2, (c0 + cw) >> 2, in,
                                      acc);
@@ -627,17 +636,17 @@ __global__ __launch_bounds__(64 * WPB) void k_phase1(const SlotDev* __restrict__
   const int task = blockIdx.x * WPB + wv;
   if (task >= ntasks) return;
   const int si = find_slot(slots, nslots, task, 0);
-  const SlotDev& S = slots[si];
-  if (slot_active && !slot_active[S.slot]) return;
+  const SlotDev S = uniform_load(slots + si);
+  if (slot_active && !uniform_int(*gbl(slot_active + S.slot))) return;
   const int lt = task - S.p1_task_begin;
-  const int ib = gbl(S.p1_task)[lt], ie = gbl(S.p1_task)[lt + 1];
+  const int ib = uniform_int(gbl(S.p1_task)[lt]), ie = uniform_int(gbl(S.p1_task)[lt + 1]);
   const VT* Xs = X + S.xoff;
   VT* T = (VT*)S.t;
   // one 64-row chunk per batch of loads (two batches when the entries or
   // the sums are FP64, to stay within 128 VGPRs)
   constexpr int UN = sizeof(LT) + sizeof(VT) > 8 ? 8 : 16;
   for (int it = ib; it < ie; ++it) {
-    const P1Item item = *gbl(S.p1 + it);
+    const P1Item item = uniform_load(S.p1 + it);
     const bool act = lane < item.gw;
     // lanes past the group's columns repeat its last column (not stored)
     const LT* a = (const LT*)S.V + item.base + (int64_t)(act ? lane : item.gw - 1) * 4;
@@ -652,9 +661,13 @@ __global__ __launch_bounds__(64 * WPB) void k_phase1(const SlotDev* __restrict__
       const int r0 = q0 * 4;
       const int q1 = q0 + 16 < qe ? q0 + 16 : qe;
       VT xv[NR];
+      {
+        const int rr = min(r0 + lane, item.nrows - 1);
 #pragma unroll
-      for (int j = 0; j < NR; ++j)
-        xv[j] = (j < nrr && r0 + lane < item.nrows) ? gbl(xr)[r0 + lane + j * ldx] : VT(0);
+        for (int j = 0; j < NR; ++j) xv[j] = gbl(xr)[rr + (int64_t)min(j, nrr - 1) * ldx];
+#pragma unroll
+        for (int j = 0; j < NR; ++j) xv[j] = (j < nrr && r0 + lane < item.nrows) ? xv[j] : VT(0);
+      }
       for (int h = 0; h < 16; h += UN) {
         const int qb = q0 + h;
         Quad<LT> v[UN];
@@ -684,30 +697,258 @@ __global__ __launch_bounds__(64 * WPB) void k_phase1(const SlotDev* __restrict__
   }
 }
 
-// t of the row-split groups: the partials of a group added in item order.
+// t of the row-split groups: one workgroup per group; wave w adds the
+// partials p = w, w + 4, ... in order (all right-hand sides in flight), and
+// the four wave sums are added in wave order: a fixed order, independent of
+// the rest of the batch.
 template <class VT, int NR>
 __global__ __launch_bounds__(256) void k_p1reduce(const SlotDev* __restrict__ slots, int nslots, int nreds,
                                                   const int* __restrict__ slot_active, int nrr) {
+  __shared__ VT red[4][NR][64];
   const int lane = threadIdx.x & 63;
-  const int r = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int wv = threadIdx.x >> 6;
+  const int r = blockIdx.x;
   if (r >= nreds) return;
-  const SlotDev& S = slots[find_slot(slots, nslots, r, 1)];
-  if (slot_active && !slot_active[S.slot]) return;
-  const P1Red R = *gbl(S.p1red + (r - S.p1red_begin));
-  if (lane >= R.gw) return;
+  const SlotDev S = uniform_load(slots + find_slot(slots, nslots, r, 1));
+  if (slot_active && !uniform_int(*gbl(slot_active + S.slot))) return;  // uniform over the workgroup
+  const P1Red R = uniform_load(S.p1red + (r - S.p1red_begin));
   const VT* P0 = (const VT*)S.part1 + (int64_t)R.part0 * P1_GW * NR;
-  VT* T = (VT*)S.t;
+  VT acc[NR];
 #pragma unroll
-  for (int j = 0; j < NR; ++j) {
-    if (j >= nrr) break;
-    VT sum = VT(0);
-    for (int p = 0; p < R.nparts; ++p) sum += gbl(P0)[((int64_t)p * NR + j) * P1_GW + lane];
-    gbl_w(T)[R.trow + lane + j * S.ldt] = sum;
+  for (int j = 0; j < NR; ++j) acc[j] = VT(0);
+  for (int p = wv; p < R.nparts; p += 4) {
+    const VT* Pp = P0 + (int64_t)p * NR * P1_GW;
+#pragma unroll
+    for (int j = 0; j < NR; ++j) acc[j] += gbl(Pp)[j * P1_GW + lane];
+  }
+#pragma unroll
+  for (int j = 0; j < NR; ++j) red[wv][j][lane] = acc[j];
+  __syncthreads();
+  if (wv == 0 && lane < R.gw) {
+    VT* T = (VT*)S.t;
+#pragma unroll
+    for (int j = 0; j < NR; ++j)
+      if (j < nrr) gbl_w(T)[R.trow + lane + j * S.ldt] = ((red[0][j][lane] + red[1][j][lane]) + red[2][j][lane]) + red[3][j][lane];
   }
 }
 
 // ------------------------------------------------------------------ launch
 namespace {
+
+// ---- 16 right-hand sides: the products are dense contractions (16 rank
+// columns or rows x 16 right-hand sides per 4-deep step) and run on the
+// matrix cores with v_mfma_f32_16x16x4f32.  Operand layout of that
+// instruction for lane l (li = l % 16, lk = l / 16): A[li][lk], B[lk][li];
+// the result holds D[4 lk + v][li] in element v.  The depth index of a step
+// may stand for any four panel columns as long as A and B agree, so each
+// lane loads one 16-byte quad of its panel row (lane group lk taking the
+// next quad) and element e of the four quads feeds step e: one 16-byte load
+// per lane serves four steps, as in the one-right-hand-side kernels.
+
+__device__ __forceinline__ f32x4 mfma16(float a, float b, f32x4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+// Phase 1, 16 right-hand sides: t[trow + col][j] = sum_r V(r, col) x(xrow + r, j)
+// for the <= 64 rank columns of a group panel (four 16-column tiles).  The
+// x rows of a 64-row chunk are staged in LDS (row-major, 16 values a row),
+// zero past the item's rows.
+template <class LT>
+__global__ __launch_bounds__(256) void k_phase1_mfma(const SlotDev* __restrict__ slots, int nslots, int ntasks,
+                                                     const int* __restrict__ slot_active, int nrr,
+                                                     const float* __restrict__ X, int64_t ldx) {
+  constexpr int NR = 16;
+  __shared__ float lds_x[4][64 * NR];
+  const int lane = threadIdx.x & 63;
+  const int wv = threadIdx.x >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  const int task = blockIdx.x * 4 + wv;
+  if (task >= ntasks) return;
+  const int si = find_slot(slots, nslots, task, 0);
+  const SlotDev S = uniform_load(slots + si);
+  if (slot_active && !uniform_int(*gbl(slot_active + S.slot))) return;
+  const int lt = task - S.p1_task_begin;
+  const int ib = uniform_int(gbl(S.p1_task)[lt]), ie = uniform_int(gbl(S.p1_task)[lt + 1]);
+  const float* Xs = X + S.xoff;
+  float* T = (float*)S.t;
+  float* xs = lds_x[wv];
+  for (int it = ib; it < ie; ++it) {
+    const P1Item item = uniform_load(S.p1 + it);
+    const int ntile = (item.gw + 15) >> 4;
+    const LT* vb = (const LT*)S.V + item.base;
+    const int64_t step = (int64_t)item.gw * 4;
+    // lanes past the group's columns repeat its last column (not stored)
+    int coff[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) coff[t] = min(16 * t + li, item.gw - 1) * 4;
+    const float* xr = Xs + item.xrow;
+    const int qe = item.q0 + item.nq;
+    const int rend = min(item.nrows, qe * 4);
+    f32x4 acc[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int q0 = item.q0; q0 < qe; q0 += 16) {
+      const int r0 = q0 * 4;
+      // x rows of the chunk (clamped into the item and the caller's columns;
+      // values past them become zero below), then the chunk's panel quads:
+      // one round trip covers both
+      const int rr = min(r0 + lane, rend - 1);
+      float xv[NR];
+#pragma unroll
+      for (int j = 0; j < NR; ++j) xv[j] = gbl(xr)[rr + (int64_t)min(j, nrr - 1) * ldx];
+      // four steps of four quads: lane group lk takes quad q0 + 4 st + lk;
+      // all four column tiles are computed (past the group's width they
+      // repeat its last column and are not stored)
+      Quad<LT> a[4][4];
+#pragma unroll
+      for (int st = 0; st < 4; ++st) {
+        const int q = q0 + 4 * st + lk;
+        const int64_t qo = (int64_t)(q < qe ? q : qe - 1) * step;
+#pragma unroll
+        for (int t = 0; t < 4; ++t) a[st][t].load(vb + qo + coff[t]);
+      }
+      wave_lds_sync();
+#pragma unroll
+      for (int j = 0; j < NR; ++j) xs[lane * NR + j] = (j < nrr && r0 + lane < rend) ? xv[j] : 0.f;
+      wave_lds_sync();
+      // rows past the item are zero in xs, so the clamped quads add nothing
+#pragma unroll
+      for (int st = 0; st < 4; ++st)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const float b = xs[((4 * st + lk) * 4 + e) * NR + li];
+#pragma unroll
+          for (int t = 0; t < 4; ++t) acc[t] = mfma16(a[st][t].template get<float>(e), b, acc[t]);
+        }
+    }
+    if (item.part < 0) {
+      if (li < nrr)
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int col = 16 * t + 4 * lk + v;
+            if (t < ntile && col < item.gw) gbl_w(T)[item.trow + col + li * S.ldt] = acc[t][v];
+          }
+    } else {
+      float* P = (float*)S.part1 + (int64_t)item.part * P1_GW * NR;
+#pragma unroll
+      for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+          if (t < ntile) gbl_w(P)[li * P1_GW + 16 * t + 4 * lk + v] = acc[t][v];
+    }
+  }
+}
+
+// The 16 quads [g, g + 16) of an item panel of m rows, for the four 16-row
+// tiles (lanes past m repeat row m - 1; quads past g1 repeat quad g1 - 1).
+template <class MT>
+__device__ __forceinline__ void load_quads16(Quad<MT> (&av)[4][4], const MT* __restrict__ a, int m, int g, int g1,
+                                             int li, int lk) {
+#pragma unroll
+  for (int st = 0; st < 4; ++st) {
+    const int q = g + 4 * st + lk;
+    const int64_t go = (int64_t)(q < g1 ? q : g1 - 1) * m * 4;
+#pragma unroll
+    for (int rt = 0; rt < 4; ++rt) av[st][rt].load(a + go + min(16 * rt + li, m - 1) * 4);
+  }
+}
+
+// acc[rt] += the loaded quads times the staged inputs in[col][rhs] of the
+// chunk's columns (lane groups whose quad lies past the chunk add zero).
+template <class MT>
+__device__ __forceinline__ void mfma_quads16(const Quad<MT> (&av)[4][4], const float* __restrict__ in, int nq, int li,
+                                             int lk, f32x4* acc) {
+#pragma unroll
+  for (int st = 0; st < 4; ++st) {
+    const bool in_item = 4 * st + lk < nq;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const float b = in_item ? in[((4 * st + lk) * 4 + e) * 16 + li] : 0.f;
+#pragma unroll
+      for (int rt = 0; rt < 4; ++rt) acc[rt] = mfma16(av[st][rt].template get<float>(e), b, acc[rt]);
+    }
+  }
+}
+
+// Phase 2, 16 right-hand sides: as k_phase2, with the row tile split into
+// four 16-row MFMA tiles; the waves' sums meet in LDS in wave order.
+template <class DT, class LT>
+__global__ __launch_bounds__(64 * P2_WAVES) void k_phase2_mfma(const SlotDev* __restrict__ slots, int nslots,
+                                                               const int* __restrict__ slot_active, int nrr,
+                                                               const float* __restrict__ X, int64_t ldx,
+                                                               float* __restrict__ Y, int64_t ldy, EpiDev<float> ep) {
+  constexpr int NR = 16;
+  constexpr int CW = 64;  // staged columns per chunk (4 KB per wave)
+  __shared__ float lds_in[P2_WAVES][CW * NR];  // reused for the wave sums [wave][rhs][row]
+  __shared__ Seg lds_seg[P2_WAVES][P2_MAXSEG];
+  const int lane = threadIdx.x & 63;
+  const int wv = threadIdx.x >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  const int tile = blockIdx.x;
+  const int si = find_slot(slots, nslots, tile, 2);
+  const SlotDev S = uniform_load(slots + si);
+  if (slot_active && !uniform_int(*gbl(slot_active + S.slot))) return;  // uniform over the workgroup
+  const P2Tile T = uniform_load(S.p2t + (tile - S.p2_tile_begin));
+  const float* Xs = X + S.xoff;
+  float* Ys = Y + S.xoff;
+  const float* Ts = (const float*)S.t;
+  float* in = lds_in[wv];
+  Seg* sg_lds = lds_seg[wv];
+  f32x4 acc[4];
+#pragma unroll
+  for (int rt = 0; rt < 4; ++rt) acc[rt] = f32x4{0.f, 0.f, 0.f, 0.f};
+  for (int k = wv; k < T.nit; k += P2_WAVES) {
+    const P2Item item = uniform_load(S.p2 + (T.it0 + k));
+    wave_lds_sync();
+    for (int q = lane; q < item.nseg; q += 64) sg_lds[q] = gbl(S.segs)[item.seg0 + q];
+    wave_lds_sync();
+    const Seg lastseg = sg_lds[item.nseg - 1];
+    const int wtrue = lastseg.col0 + lastseg.w;
+    // per chunk of 64 columns: the panel loads go out first, the input
+    // gathers overlap them, then 64 matrix-core steps
+    if (item.kind == 0) {
+      const DT* pa = (const DT*)S.dense + item.base;
+      for (int c0 = 0; c0 < item.w; c0 += CW) {
+        const int cw = min(CW, item.w - c0);
+        Quad<DT> av[4][4];
+        load_quads16<DT>(av, pa, T.m, c0 >> 2, (c0 + cw) >> 2, li, lk);
+        stage_inputs<float, NR>(in, sg_lds, item.nseg, wtrue, c0, cw, lane, nrr, Xs, ldx, Ts, S.ldt);
+        mfma_quads16<DT>(av, in, cw >> 2, li, lk, acc);
+      }
+    } else {
+      const LT* pa = (const LT*)S.U + item.base;
+      for (int c0 = 0; c0 < item.w; c0 += CW) {
+        const int cw = min(CW, item.w - c0);
+        Quad<LT> av[4][4];
+        load_quads16<LT>(av, pa, T.m, c0 >> 2, (c0 + cw) >> 2, li, lk);
+        stage_inputs<float, NR>(in, sg_lds, item.nseg, wtrue, c0, cw, lane, nrr, Xs, ldx, Ts, S.ldt);
+        mfma_quads16<LT>(av, in, cw >> 2, li, lk, acc);
+      }
+    }
+  }
+  __syncthreads();
+  float* red = &lds_in[0][0];
+#pragma unroll
+  for (int rt = 0; rt < 4; ++rt)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) red[(wv * NR + li) * TILE + 16 * rt + 4 * lk + v] = acc[rt][v];
+  __syncthreads();
+  if (wv == 0) {
+    float sum[NR];
+#pragma unroll
+    for (int j = 0; j < NR; ++j) {
+      float t = red[j * TILE + lane];
+      for (int w = 1; w < P2_WAVES; ++w) t += red[(w * NR + j) * TILE + lane];
+      sum[j] = t;
+    }
+    EpiDev<float> e = ep;
+    if (e.rowscale) e.rowscale += S.xoff;
+    if (e.z) e.z += S.xoff;
+    epilogue_store<float, NR>(T.row0 + lane, lane, T.m, nrr, sum, Xs, ldx, Ys, ldy, e);
+  }
+}
 
 template <class VT, int NR>
 constexpr int p1_waves_per_block() {
@@ -720,13 +961,19 @@ void launch_typed(const Composition& C, int nrr, bool hi, const void* X, int64_t
   constexpr int WPB = p1_waves_per_block<VT, NR>();
   const SlotDev* slots = (hi ? C.d_slots_hi : C.d_slots_lo).get<SlotDev>();
   const int ns = (int)C.mats.size();
+  // 16 right-hand sides with FP32 sums of FP32/BF16 entries: matrix cores
+  constexpr bool mfma = NR == 16 && std::is_same<VT, float>::value && sizeof(DT) == 4 && sizeof(LT) <= 4;
   if (ev) HM_HIP(hipEventRecord(ev[0], s));
   if (C.p1_tasks > 0) {
-    hipLaunchKernelGGL((k_phase1<LT, VT, NR, WPB>), dim3((C.p1_tasks + WPB - 1) / WPB), dim3(64 * WPB), 0, s, slots,
-                       ns, C.p1_tasks, slot_active, nrr, (const VT*)X, ldx);
+    if constexpr (mfma)
+      hipLaunchKernelGGL((k_phase1_mfma<LT>), dim3((C.p1_tasks + 3) / 4), dim3(256), 0, s, slots, ns, C.p1_tasks,
+                         slot_active, nrr, (const float*)X, ldx);
+    else
+      hipLaunchKernelGGL((k_phase1<LT, VT, NR, WPB>), dim3((C.p1_tasks + WPB - 1) / WPB), dim3(64 * WPB), 0, s,
+                         slots, ns, C.p1_tasks, slot_active, nrr, (const VT*)X, ldx);
   }
   if (C.p1_reds > 0) {
-    hipLaunchKernelGGL((k_p1reduce<VT, NR>), dim3((C.p1_reds + 3) / 4), dim3(256), 0, s, slots, ns, C.p1_reds,
+    hipLaunchKernelGGL((k_p1reduce<VT, NR>), dim3(C.p1_reds), dim3(256), 0, s, slots, ns, C.p1_reds,
                        slot_active, nrr);
   }
   if (ev) HM_HIP(hipEventRecord(ev[1], s));
@@ -738,8 +985,12 @@ void launch_typed(const Composition& C, int nrr, bool hi, const void* X, int64_t
   e.z = (const VT*)ep.z;
   e.ldz = ep.ldz;
   if (C.p2_tiles > 0) {
-    hipLaunchKernelGGL((k_phase2<DT, LT, VT, NR>), dim3(C.p2_tiles), dim3(64 * P2_WAVES), 0, s, slots, ns,
-                       slot_active, nrr, (const VT*)X, ldx, (VT*)Y, ldy, e);
+    if constexpr (mfma)
+      hipLaunchKernelGGL((k_phase2_mfma<DT, LT>), dim3(C.p2_tiles), dim3(64 * P2_WAVES), 0, s, slots, ns,
+                         slot_active, nrr, (const float*)X, ldx, (float*)Y, ldy, e);
+    else
+      hipLaunchKernelGGL((k_phase2<DT, LT, VT, NR>), dim3(C.p2_tiles), dim3(64 * P2_WAVES), 0, s, slots, ns,
+                         slot_active, nrr, (const VT*)X, ldx, (VT*)Y, ldy, e);
   }
   if (ev) HM_HIP(hipEventRecord(ev[2], s));
   HM_HIP(hipGetLastError());
