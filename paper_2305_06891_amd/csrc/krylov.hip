@@ -18,7 +18,7 @@ void SysSet::build(const Composition& C, const std::vector<std::vector<int>>& co
   nparts = 0;
   for (size_t q = 0; q < C.mats.size(); ++q) {
     for (int col : cols_per_slot[q]) {
-      SysDev d{C.xoff[q], (int32_t)C.mats[q]->n, col, (int32_t)q, 0};
+      SysDev d{C.xoff[q], (int32_t)C.mats[q]->n, col, (int32_t)q, (int32_t)chunks.size()};
       const int32_t sid = (int32_t)sys.size();
       sys.push_back(d);
       const int32_t nch = (int32_t)((d.n + GS_ROWS - 1) / GS_ROWS);
@@ -96,7 +96,6 @@ template <class VT>
 __global__ __launch_bounds__(GS_T) void k_gs(GsArgs a) {
   __shared__ double coef[MAXM + 1];
   __shared__ double red[GS_T / 64][MAXM + 2];
-  __shared__ int last;
   const ChunkDev c = a.chunks[blockIdx.x];
   const int s = c.sys;
   if (a.mode != 3 && !a.act[s]) return;
@@ -161,68 +160,69 @@ __global__ __launch_bounds__(GS_T) void k_gs(GsArgs a) {
     for (int q = 1; q < GS_T / 64; ++q) t += red[q][tid];
     P0[(int64_t)c.pidx * (MAXM + 1) + tid] = t;
   }
-  if (c.nparts > 1) {
-    __threadfence();
-    __syncthreads();
-    if (tid == 0) last = atomicAdd(&a.cnt[s], 1u) == (unsigned)(c.nparts - 1);
-    __syncthreads();
-    if (!last) return;
-    __threadfence();
-  } else {
-    __syncthreads();
-  }
-  // last chunk of the system: fixed-order sum of the partials
-  if (tid < nv) {
+}
+
+// One block per system: the chunk partials of k_gs added in chunk order,
+// then the step's bookkeeping (Hessenberg entries, norm, Givens rotation).
+__global__ __launch_bounds__(64) void k_gs_final(GsArgs a, int nsys) {
+  __shared__ double red[MAXM + 1];
+  const int s = blockIdx.x;
+  if (s >= nsys) return;
+  if (a.mode != 3 && !a.act[s]) return;
+  const SysDev sy = a.sys[s];
+  const ChunkDev c0 = a.chunks[sy.chunk0];
+  const int L = (a.mode <= 1) ? a.j + 1 : 0;
+  const int nv = L > 0 ? L : 1;
+  const double* P0 = a.part + (int64_t)c0.part * (MAXM + 1);
+  for (int l = threadIdx.x; l < nv; l += 64) {
     double t = 0.0;
-    for (int p = 0; p < c.nparts; ++p) t += P0[(int64_t)p * (MAXM + 1) + tid];
-    red[0][tid] = t;
+    for (int p = 0; p < c0.nparts; ++p) t += P0[(int64_t)p * (MAXM + 1) + l];
+    red[l] = t;
   }
   __syncthreads();
-  if (tid == 0) {
-    if (c.nparts > 1) a.cnt[s] = 0u;
-    double* hs = a.mode == 0 ? a.hA : a.hB;
-    if (a.mode <= 1) {
-      for (int l = 0; l < L; ++l) hs[(int64_t)s * (MAXM + 1) + l] = red[0][l];
-    } else if (a.mode == 3) {
-      a.beta[s] = sqrt(red[0][0]);
-    } else {
-      // finish column j of the Hessenberg matrix and its Givens rotation
-      const int j = a.j;
-      const double hnrm = sqrt(red[0][0]);
-      double col[MAXM + 1];
-      for (int i = 0; i <= j; ++i) col[i] = a.hA[(int64_t)s * (MAXM + 1) + i] + a.hB[(int64_t)s * (MAXM + 1) + i];
-      col[j + 1] = hnrm;
-      double* cs = a.cs + (int64_t)s * MAXM;
-      double* sn = a.sn + (int64_t)s * MAXM;
-      for (int i = 0; i < j; ++i) {
-        const double t0 = cs[i] * col[i] + sn[i] * col[i + 1];
-        col[i + 1] = -sn[i] * col[i] + cs[i] * col[i + 1];
-        col[i] = t0;
-      }
-      const double x0 = col[j], x1 = col[j + 1];
-      const double rr = hypot(x0, x1);
-      double cj = 1.0, sj = 0.0;
-      if (rr > 0.0) {
-        cj = x0 / rr;
-        sj = x1 / rr;
-      }
-      col[j] = rr;
-      col[j + 1] = 0.0;
-      cs[j] = cj;
-      sn[j] = sj;
-      double* gs = a.g + (int64_t)s * (MAXM + 1);
-      const double gj = gs[j];
-      gs[j] = cj * gj;
-      gs[j + 1] = -sj * gj;
-      double* Hc = a.H + ((int64_t)s * MAXM + j) * (MAXM + 1);
-      for (int i = 0; i <= j + 1; ++i) Hc[i] = col[i];
-      a.steps[s] = j + 1;
-      a.hn[s] = hnrm;
-      const double res = fabs(gs[j + 1]);
-      if (res <= a.tol[s] || !(hnrm > 0.0) || rr == 0.0) {
-        a.act[s] = 0;
-        atomicSub(&a.slot_cnt[sy.slot], 1);
-      }
+  if (threadIdx.x != 0) return;
+  double* hs = a.mode == 0 ? a.hA : a.hB;
+  if (a.mode <= 1) {
+    for (int l = 0; l < L; ++l) hs[(int64_t)s * (MAXM + 1) + l] = red[l];
+  } else if (a.mode == 3) {
+    a.beta[s] = sqrt(red[0]);
+  } else {
+    // finish column j of the Hessenberg matrix and its Givens rotation
+    const int j = a.j;
+    const double hnrm = sqrt(red[0]);
+    double col[MAXM + 1];
+    for (int i = 0; i <= j; ++i) col[i] = a.hA[(int64_t)s * (MAXM + 1) + i] + a.hB[(int64_t)s * (MAXM + 1) + i];
+    col[j + 1] = hnrm;
+    double* cs = a.cs + (int64_t)s * MAXM;
+    double* sn = a.sn + (int64_t)s * MAXM;
+    for (int i = 0; i < j; ++i) {
+      const double t0 = cs[i] * col[i] + sn[i] * col[i + 1];
+      col[i + 1] = -sn[i] * col[i] + cs[i] * col[i + 1];
+      col[i] = t0;
+    }
+    const double x0 = col[j], x1 = col[j + 1];
+    const double rr = hypot(x0, x1);
+    double cj = 1.0, sj = 0.0;
+    if (rr > 0.0) {
+      cj = x0 / rr;
+      sj = x1 / rr;
+    }
+    col[j] = rr;
+    col[j + 1] = 0.0;
+    cs[j] = cj;
+    sn[j] = sj;
+    double* gs = a.g + (int64_t)s * (MAXM + 1);
+    const double gj = gs[j];
+    gs[j] = cj * gj;
+    gs[j + 1] = -sj * gj;
+    double* Hc = a.H + ((int64_t)s * MAXM + j) * (MAXM + 1);
+    for (int i = 0; i <= j + 1; ++i) Hc[i] = col[i];
+    a.steps[s] = j + 1;
+    a.hn[s] = hnrm;
+    const double res = fabs(gs[j + 1]);
+    if (res <= a.tol[s] || !(hnrm > 0.0) || rr == 0.0) {
+      a.act[s] = 0;
+      atomicSub(&a.slot_cnt[sy.slot], 1);
     }
   }
 }
@@ -303,7 +303,9 @@ template <class VT>
 void run_gs(Krylov& K, int mode, int j, void* wvec, hipStream_t s) {
   const unsigned nb = (unsigned)K.S->chunks.size();
   if (nb == 0) return;
-  hipLaunchKernelGGL(k_gs<VT>, dim3(nb), dim3(GS_T), 0, s, gs_args(K, mode, j, wvec));
+  const GsArgs a = gs_args(K, mode, j, wvec);
+  hipLaunchKernelGGL(k_gs<VT>, dim3(nb), dim3(GS_T), 0, s, a);
+  hipLaunchKernelGGL(k_gs_final, dim3((unsigned)K.S->size()), dim3(64), 0, s, a, K.S->size());
   HM_HIP(hipGetLastError());
 }
 
@@ -344,7 +346,7 @@ GmresStats gmres_t(Krylov& K, bool hi, const void* omeps, const void* b, void* x
   op_ep.a_acc = -1.0;
   op_ep.a_x = 1.0;
   const int nrr = C.nr;
-  std::vector<int> act(ns), cnt(nslots);
+  std::vector<int> act(ns), cnt(nslots), stp(ns);
   std::vector<double> g0((size_t)ns * (MAXM + 1), 0.0);
   int iters = 0;
   for (;;) {
@@ -376,23 +378,33 @@ GmresStats gmres_t(Krylov& K, bool hi, const void* omeps, const void* b, void* x
     HM_HIP(hipMemcpyAsync(K.g.get(), g0.data(), g0.size() * 8, hipMemcpyHostToDevice, s));
     HM_HIP(hipMemsetAsync(K.steps.get(), 0, ns * 4, s));
     run_scale<VT>(K, K.beta.get<double>(), K.basis.get(), K.basis.get(), s);
-    for (int j = 0; j < K.m && iters < max_iter; ++j) {
+    // Arnoldi steps; the host looks at the active count every SYNC steps
+    // (steps launched after every system has converged find nothing active
+    // and return at once)
+    constexpr int SYNC = 4;
+    for (int j = 0; j < K.m && iters + j < max_iter; ++j) {
       char* vj = K.basis.get<char>() + (size_t)j * K.blk * K.vb;
       char* vj1 = vj + (size_t)K.blk * K.vb;
       launch_matvec(C, nrr, K.vb, hi, vj, K.ld, K.w.get(), K.ld, op_ep, K.slot_cnt.get<int>(), s);
-      st.matvecs++;
-      st.bytes += mbytes;
       run_gs<VT>(K, 0, j, K.w.get(), s);
       run_gs<VT>(K, 1, j, K.w.get(), s);
       run_gs<VT>(K, 2, j, K.w.get(), s);
       run_scale<VT>(K, K.hn.get<double>(), K.w.get(), vj1, s);
-      ++iters;
-      HM_HIP(hipMemcpyAsync(cnt.data(), K.slot_cnt.get(), nslots * 4, hipMemcpyDeviceToHost, s));
-      HM_HIP(hipStreamSynchronize(s));
-      int left = 0;
-      for (int v : cnt) left += v;
-      if (left == 0) break;
+      if ((j + 1) % SYNC == 0 || j + 1 == K.m || iters + j + 1 >= max_iter) {
+        HM_HIP(hipMemcpyAsync(cnt.data(), K.slot_cnt.get(), nslots * 4, hipMemcpyDeviceToHost, s));
+        HM_HIP(hipStreamSynchronize(s));
+        int left = 0;
+        for (int v : cnt) left += v;
+        if (left == 0) break;
+      }
     }
+    // steps taken in this cycle: the most any system took
+    HM_HIP(hipMemcpyAsync(stp.data(), K.steps.get(), ns * 4, hipMemcpyDeviceToHost, s));
+    HM_HIP(hipStreamSynchronize(s));
+    const int cyc = *std::max_element(stp.begin(), stp.end());
+    iters += cyc;
+    st.matvecs += cyc;
+    st.bytes += (int64_t)cyc * mbytes;
     const unsigned nb = (unsigned)K.S->chunks.size();
     hipLaunchKernelGGL(k_xupdate<VT>, dim3(nb), dim3(GS_T), 0, s, K.S->d_sys.get<SysDev>(),
                        K.S->d_chunks.get<ChunkDev>(), K.steps.get<int>(), K.H.get<double>(), K.g.get<double>(),

@@ -15,7 +15,7 @@ constexpr int GS_ROWS = GS_T * GS_RPT;
 // combined N x width vector block, belonging to slot `slot`.
 struct SysDev {
   int64_t row0;
-  int32_t n, col, slot, pad;
+  int32_t n, col, slot, chunk0;  // chunk0: index of the system's first reduction chunk
 };
 
 struct ChunkDev {

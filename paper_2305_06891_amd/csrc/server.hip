@@ -154,14 +154,22 @@ bool hm_server::admit_one(SrvReq& r) {
     c = cav.at(r.cid).get();
   }
   const int64_t vec_bytes = r.n * r.nrhs * 8 * 3;
+  auto resident_locked = [&] {
+    std::lock_guard<std::mutex> lk(mu);
+    return resident();
+  };
   if (!c->M) {
     // evict idle cavities until the estimate fits
     const int64_t est = c->bytes > 0 ? c->bytes : r.n * 2500 * 4;
     for (;;) {
-      if (resident() + est + vec_bytes <= p.hbm_budget_bytes) break;
+      if (resident_locked() + est + vec_bytes <= p.hbm_budget_bytes) break;
       SrvCavity* lru = nullptr;
-      for (auto& kv : cav)
-        if (kv.second->M && kv.second->refs == 0 && (!lru || kv.second->last_use < lru->last_use)) lru = kv.second.get();
+      {
+        std::lock_guard<std::mutex> lk(mu);
+        for (auto& kv : cav)
+          if (kv.second->M && kv.second->refs == 0 && (!lru || kv.second->last_use < lru->last_use))
+            lru = kv.second.get();
+      }
       if (!lru) break;
       HM_HIP(hipStreamSynchronize(stream));
       delete lru->M;
@@ -173,7 +181,12 @@ bool hm_server::admit_one(SrvReq& r) {
       std::lock_guard<std::mutex> lk(mu);
       st.evictions++;
     }
-    if (resident() + est + vec_bytes > p.hbm_budget_bytes && !active.empty()) return false;  // wait
+    bool busy;
+    {
+      std::lock_guard<std::mutex> lk(mu);
+      busy = !active.empty();
+    }
+    if (resident_locked() + est + vec_bytes > p.hbm_budget_bytes && busy) return false;  // wait
     c->M = assemble(ctx, *c->tree, c->ap);
     c->M->id = 0x8000000000000000ull | c->id;
     const int64_t n = c->M->n;
@@ -228,11 +241,14 @@ void hm_server::round(std::vector<SrvReq*>& act) {
   std::vector<const hm_matrix*> mats;
   std::vector<SrvCavity*> cs;
   int maxr = 1;
-  for (auto* r : act) {
-    SrvCavity* c = cav.at(r->cid).get();
-    cs.push_back(c);
-    mats.push_back(c->M);
-    maxr = std::max(maxr, r->nrhs);
+  {
+    std::lock_guard<std::mutex> lk(mu);
+    for (auto* r : act) {
+      SrvCavity* c = cav.at(r->cid).get();
+      cs.push_back(c);
+      mats.push_back(c->M);
+      maxr = std::max(maxr, r->nrhs);
+    }
   }
   const int W = pad_width(maxr);
   auto C = make_composition(mats, W, 8, s);
@@ -355,14 +371,17 @@ void hm_server::round(std::vector<SrvReq*>& act) {
     SrvReq& r = *act[q];
     r.rounds++;
     if (!fin[q]) continue;
-    r.done = true;
-    r.t_done = t;
-    r.status = worst[q] <= p.solve.rtol ? HM_OK : HM_ENOTCONV;
     r.Tp.release();
     r.b64.release();
     r.J64.release();
     cs[q]->refs--;
     st.completed++;
+    // leave the active list in the same critical section that publishes the
+    // result: once done is set the client may poll and erase the request
+    active.erase(std::find(active.begin(), active.end(), r.ticket));
+    r.done = true;
+    r.t_done = t;
+    r.status = worst[q] <= p.solve.rtol ? HM_OK : HM_ENOTCONV;
   }
 }
 
@@ -390,7 +409,22 @@ void hm_server::run() {
           std::lock_guard<std::mutex> lk(mu);
           r = req.at(tk).get();
         }
-        bool ok = admit_one(*r);
+        bool ok = false;
+        try {
+          ok = admit_one(*r);
+        } catch (const std::exception& e) {
+          // this request cannot be admitted (assembly or allocation failed):
+          // fail it alone and keep serving the others
+          (void)hipGetLastError();
+          const Error* he = dynamic_cast<const Error*>(&e);
+          std::lock_guard<std::mutex> lk(mu);
+          queue.pop_front();
+          r->status = he ? he->code : HM_EDEVICE;
+          r->t_done = now_s();
+          r->done = true;
+          ctx.last_error = e.what();
+          continue;
+        }
         std::lock_guard<std::mutex> lk(mu);
         if (!ok) break;
         queue.pop_front();
@@ -401,25 +435,24 @@ void hm_server::run() {
         std::lock_guard<std::mutex> lk(mu);
         for (uint64_t tk : active) act.push_back(req.at(tk).get());
       }
-      if (!act.empty()) round(act);
+      if (!act.empty()) round(act);  // retires finished requests from active
       std::lock_guard<std::mutex> lk(mu);
-      std::vector<uint64_t> still;
-      for (uint64_t tk : active)
-        if (!req.at(tk)->done) still.push_back(tk);
-      active.swap(still);
       st.busy_seconds += now_s() - t0;
       st.resident_bytes = resident();
-    } catch (const Error& e) {
+    } catch (const std::exception& e) {
       // fail every active request with the error; keep serving
       (void)hipGetLastError();
+      const Error* he = dynamic_cast<const Error*>(&e);
       std::lock_guard<std::mutex> lk(mu);
       for (uint64_t tk : active) {
-        SrvReq& r = *req.at(tk);
-        r.done = true;
-        r.status = e.code;
-        r.t_done = now_s();
+        auto rit = req.find(tk);
+        if (rit == req.end()) continue;
+        SrvReq& r = *rit->second;
         auto it = cav.find(r.cid);
         if (it != cav.end() && it->second->refs > 0) it->second->refs--;
+        r.status = he ? he->code : HM_EDEVICE;
+        r.t_done = now_s();
+        r.done = true;
       }
       active.clear();
       ctx.last_error = e.what();

@@ -315,9 +315,14 @@ SolveResult Batch::solve_prepared(const hm_solve_params& p, hipStream_t s, bool 
     R.converged = false;
     int outer = 0, inner_total = 0;
     for (;;) {
-      residual64(true, s);
-      R.matvecs++;
-      R.bytes += C->bytes_hi;
+      if (outer == 0 && !warm) {
+        // x = 0: the residual is b itself, no product needed
+        HM_HIP(hipMemcpyAsync(r64.get(), b64.get(), tot * 8, hipMemcpyDeviceToDevice, s));
+      } else {
+        residual64(true, s);
+        R.matvecs++;
+        R.bytes += C->bytes_hi;
+      }
       block_norms(K8, r64.get(), rn, s);
       bool done = true;
       R.rel_res.resize(rn.size());
