@@ -60,12 +60,17 @@ template <class T> __device__ __forceinline__ gptr<const T> gbl(const T* p) { re
 template <class T> __device__ __forceinline__ gptr<T> gbl_w(T* p) { return (gptr<T>)p; }
 
 // A descriptor that every lane of the wave reads at the same address,
-// returned in scalar registers (readfirstlane per 32-bit word), so that the
-// compiler treats its fields as wave-uniform: branches on them stay scalar
-// and do not wait on unrelated loads.
+// loaded through the constant address space (scalar loads into SGPRs; the
+// descriptors do not change while a kernel runs) and kept wave-uniform, so
+// that branches on its fields stay scalar and do not wait on unrelated loads.
+#if defined(__HIP_DEVICE_COMPILE__)
+template <class T> using cptr = __attribute__((address_space(4))) T*;
+#else
+template <class T> using cptr = T*;
+#endif
 template <class T> __device__ __forceinline__ T uniform_load(const T* p) {
   static_assert(sizeof(T) % 4 == 0, "descriptor size must be a multiple of 4");
-  T v = *gbl(p);
+  T v = *(cptr<const T>)p;
   int* w = reinterpret_cast<int*>(&v);
 #pragma unroll
   for (int k = 0; k < (int)(sizeof(T) / 4); ++k) w[k] = __builtin_amdgcn_readfirstlane(w[k]);

@@ -282,6 +282,9 @@ struct Composition {
   int32_t p1_tasks = 0, p1_reds = 0, p2_tiles = 0;
   std::vector<SlotDev> slots_lo, slots_hi;  // hi: FP32 copies of BF16 factors
   DevBuf d_slots_lo, d_slots_hi;
+  // slot of every phase-1 task, then of every reduction, then of every tile
+  std::vector<int32_t> slot_of;
+  DevBuf d_slot_of;
   DevBuf t, part1;
   int64_t bytes_lo = 0, bytes_hi = 0;     // algorithmic matrix bytes per product
 };

@@ -379,6 +379,15 @@ std::unique_ptr<Composition> make_composition(const std::vector<const hm_matrix*
   C->p1_tasks = t1;
   C->p1_reds = r1;
   C->p2_tiles = t2;
+  C->slot_of.clear();
+  for (int pass = 0; pass < 3; ++pass)
+    for (size_t q = 0; q < mats.size(); ++q) {
+      const Plan& P = mats[q]->plan;
+      const size_t cnt = pass == 0 ? P.p1_task.size() - 1 : (pass == 1 ? P.p1red.size() : P.p2t.size());
+      C->slot_of.insert(C->slot_of.end(), cnt, (int32_t)q);
+    }
+  C->slot_of.push_back(0);  // never empty
+  upload(C->d_slot_of, C->slot_of, s);
   upload(C->d_slots_lo, C->slots_lo, s);
   upload(C->d_slots_hi, C->slots_hi, s);
   HM_HIP(hipStreamSynchronize(s));
@@ -393,20 +402,6 @@ struct EpiDev {
   const VT* z;
   int64_t ldz;
 };
-
-// Slot of a global work index: the last slot whose first index is <= task
-// (which = 0: phase-1 tasks, 1: phase-1 reductions, 2: phase-2 tiles).
-__device__ inline int find_slot(const SlotDev* __restrict__ slots, int nslots, int task, int which) {
-  int lo = 0, hi = nslots - 1;
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    const int* f = which == 0 ? &slots[mid].p1_task_begin : (which == 1 ? &slots[mid].p1red_begin : &slots[mid].p2_tile_begin);
-    const int b = uniform_int(*gbl(f));
-    if (b <= task) lo = mid;
-    else hi = mid - 1;
-  }
-  return lo;
-}
 
 // Four consecutive panel entries in their stored type (one 8-32 byte load);
 // they are converted to the vector type only when they are used, so a batch
@@ -438,12 +433,14 @@ template <> struct Quad<bf16_t> {
   }
 };
 
-// Ordering of LDS traffic inside one wave (no workgroup barrier: the waves of
-// a workgroup run independent tasks).
+// Ordering of LDS traffic inside one wave (no workgroup barrier: the waves
+// of a workgroup run independent tasks).  A wave's LDS operations execute in
+// issue order, so only the compiler must keep them in program order: a
+// signal fence does that without waiting on outstanding global loads.
 __device__ __forceinline__ void wave_lds_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
   __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
 }
 
 template <class VT, int NR>
@@ -462,38 +459,36 @@ __device__ __forceinline__ void epilogue_store(int row, int lane, int m, int nrr
   }
 }
 
-// Batch length (loads in flight per lane) of the second kernel: 16 quads
-// with FP32 sums of FP32/BF16 entries, 8 with FP64 entries or sums (twice
-// the registers per value), fewer with several right-hand sides.  Sized to stay at or
-// below 128 VGPRs so that two workgroups of eight waves fit on a compute unit.
+// Quads per load batch of the second kernel; two batches are in flight
+// (the next one is loaded while the current one is used): 8 quads of FP32
+// entries with FP32 sums, 16 of BF16 entries (the same bytes), 4 with FP64
+// entries or sums or several right-hand sides, which take more registers.
 template <class MT, class VT, int NR>
 constexpr int load_depth() {
-  return NR > 4 ? 4 : (NR > 1 || sizeof(VT) == 8 || sizeof(MT) == 8 ? 8 : 16);
+  return (NR > 1 || sizeof(VT) == 8 || sizeof(MT) == 8) ? 4 : (sizeof(MT) == 2 ? 16 : 8);
 }
 
-// acc[j] += sum over column quads [g0, g1) of A(row, c) * in[c - 4*g0][j]
-// for the panel row whose first quad entry is a.  Loads go out in batches of
-// UN; the tail batch re-reads the last quad instead of branching (its terms
-// are skipped), so no load needs a predicate.
-template <class MT, class VT, int NR>
-__device__ __forceinline__ void panel_accumulate(const MT* __restrict__ a, int m, int g0, int g1,
-                                                 const VT* __restrict__ in, VT* acc) {
-  const int64_t step = (int64_t)m * 4;
-  constexpr int UN = load_depth<MT, VT, NR>();
-  for (int g = g0; g < g1; g += UN) {
-    Quad<MT> v[UN];
+// One batch: quads [g, g + UN) of a panel row (the tail re-reads quad g1 - 1
+// instead of branching; its terms are skipped).
+template <class MT, int UN>
+__device__ __forceinline__ void quads_load(Quad<MT> (&v)[UN], const MT* __restrict__ a, int64_t step, int g, int g1) {
 #pragma unroll
-    for (int u = 0; u < UN; ++u) v[u].load(a + (g + u < g1 ? g + u : g1 - 1) * step);
+  for (int u = 0; u < UN; ++u) v[u].load(a + (int64_t)(g + u < g1 ? g + u : g1 - 1) * step);
+}
+
+// acc[j] += sum over the batch's quads (< g1) of A(row, c) * in[c - 4 g0][j].
+template <class MT, class VT, int NR, int UN>
+__device__ __forceinline__ void quads_fma(const Quad<MT> (&v)[UN], int g, int g0, int g1, const VT* __restrict__ in,
+                                          VT* acc) {
 #pragma unroll
-    for (int u = 0; u < UN; ++u)
-      if (g + u < g1)
+  for (int u = 0; u < UN; ++u)
+    if (g + u < g1)
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          const VT w = v[u].template get<VT>(e);
+      for (int e = 0; e < 4; ++e) {
+        const VT w = v[u].template get<VT>(e);
 #pragma unroll
-          for (int j = 0; j < NR; ++j) acc[j] += w * in[((g - g0 + u) * 4 + e) * NR + j];
-        }
-  }
+        for (int j = 0; j < NR; ++j) acc[j] += w * in[((g - g0 + u) * 4 + e) * NR + j];
+      }
 }
 
 // Staged columns per chunk: at most P2_MAXW and 4 KB of inputs per wave.
@@ -502,47 +497,91 @@ constexpr int p2_chunk() {
   return (int)std::min<int64_t>(P2_MAXW, ((4096 / ((int64_t)NR * sizeof(VT))) / 4) * 4);
 }
 
-// Stages the inputs of item columns [c0, c0 + cw) in LDS (in[col][rhs]):
-// every lane finds the run of each of its columns and gathers, so all
-// gathers are in flight at once; columns past the item's width read 0.
-template <class VT, int NR>
-__device__ __forceinline__ void stage_inputs(VT* in, const Seg* sg_lds, int nseg, int wtrue, int c0, int cw, int lane,
-                                             int nrr, const VT* Xs, int64_t ldx, const VT* Ts, int64_t ldt) {
-  wave_lds_sync();
-  for (int cc = lane; cc < cw; cc += 64) {
+// Inputs of item columns [c0, c0 + cw) staged in two steps, so that panel
+// loads can be issued in between and stay in flight (the vector-memory
+// counter retires loads in issue order): stage_issue finds the run of each
+// of the lane's columns (LDS) and issues its gathers into registers;
+// stage_commit writes them to LDS (in[col][rhs]).  Columns past the item's
+// width read 0; clamped addresses keep every gather in bounds.
+template <class VT, int NR, int CW>
+struct Staged {
+  static constexpr int K = CW >= 64 ? CW / 64 : 1;
+  VT v[K][NR];
+};
+
+template <class VT, int NR, int CW>
+__device__ __forceinline__ void stage_issue(Staged<VT, NR, CW>& st, const Seg* sg_lds, int nseg, int wtrue, int c0,
+                                            int cw, int lane, int nrr, const VT* Xs, int64_t ldx, const VT* Ts,
+                                            int64_t ldt) {
+#pragma unroll
+  for (int k = 0; k < Staged<VT, NR, CW>::K; ++k) {
+    const int cc = lane + 64 * k;
     const int c = c0 + cc;
-    VT v[NR];
-#pragma unroll
-    for (int j = 0; j < NR; ++j) v[j] = VT(0);
-    if (c < wtrue) {
-      int lo = 0, hi = nseg - 1;
-      while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (sg_lds[mid].col0 <= c) lo = mid;
-        else hi = mid - 1;
-      }
-      const Seg sg = sg_lds[lo];
-      const int kk = c - sg.col0;
-      if (sg.src >= 0) {
-#pragma unroll
-        for (int j = 0; j < NR; ++j)
-          if (j < nrr) v[j] = gbl(Xs)[sg.src + kk + j * ldx];
-      } else {
-#pragma unroll
-        for (int j = 0; j < NR; ++j)
-          if (j < nrr) v[j] = gbl(Ts)[(~sg.src) + kk + j * ldt];
-      }
+    const bool valid = cc < cw && c < wtrue;
+    const int cs = min(c, wtrue - 1);
+    int lo = 0, hi = nseg - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (sg_lds[mid].col0 <= cs) lo = mid;
+      else hi = mid - 1;
     }
+    const Seg sg = sg_lds[lo];
+    const int kk = cs - sg.col0;
+    const VT* src = sg.src >= 0 ? Xs + sg.src + kk : Ts + (~sg.src) + kk;
+    const int64_t ld = sg.src >= 0 ? ldx : ldt;
+    VT t[NR];
 #pragma unroll
-    for (int j = 0; j < NR; ++j) in[cc * NR + j] = v[j];
+    for (int j = 0; j < NR; ++j) t[j] = gbl(src)[(int64_t)min(j, nrr - 1) * ld];
+#pragma unroll
+    for (int j = 0; j < NR; ++j) st.v[k][j] = (valid && j < nrr) ? t[j] : VT(0);
+  }
+}
+
+template <class VT, int NR, int CW>
+__device__ __forceinline__ void stage_commit(const Staged<VT, NR, CW>& st, VT* in, int lane, int cw) {
+  wave_lds_sync();
+#pragma unroll
+  for (int k = 0; k < Staged<VT, NR, CW>::K; ++k) {
+    const int cc = lane + 64 * k;
+    if (cc < cw)
+#pragma unroll
+      for (int j = 0; j < NR; ++j) in[cc * NR + j] = st.v[k][j];
   }
   wave_lds_sync();
+}
+
+// acc += one item panel (m rows, w columns) times its inputs, chunk by
+// chunk: the chunk's first batch of panel loads goes out before its inputs
+// are staged, and each later batch is loaded while the previous one is used.
+template <class MT, class VT, int NR>
+__device__ __forceinline__ void panel_item(const MT* __restrict__ a, int m, int w, VT* in, const Seg* sg_lds, int nseg,
+                                           int wtrue, int lane, int nrr, const VT* Xs, int64_t ldx, const VT* Ts,
+                                           int64_t ldt, VT* acc) {
+  constexpr int CW = p2_chunk<VT, NR>();
+  constexpr int UN = load_depth<MT, VT, NR>();
+  const int64_t step = (int64_t)m * 4;
+  for (int c0 = 0; c0 < w; c0 += CW) {
+    const int cw = min(CW, w - c0);
+    const int g0 = c0 >> 2, g1 = (c0 + cw) >> 2;
+    Staged<VT, NR, CW> st;
+    stage_issue<VT, NR, CW>(st, sg_lds, nseg, wtrue, c0, cw, lane, nrr, Xs, ldx, Ts, ldt);
+    Quad<MT> va[UN], vb[UN];
+    quads_load<MT, UN>(va, a, step, g0, g1);
+    stage_commit<VT, NR, CW>(st, in, lane, cw);
+    for (int g = g0; g < g1; g += 2 * UN) {
+      if (g + UN < g1) quads_load<MT, UN>(vb, a, step, g + UN, g1);
+      quads_fma<MT, VT, NR, UN>(va, g, g0, g1, in, acc);
+      if (g + UN >= g1) break;
+      if (g + 2 * UN < g1) quads_load<MT, UN>(va, a, step, g + 2 * UN, g1);
+      quads_fma<MT, VT, NR, UN>(vb, g + UN, g0, g1, in, acc);
+    }
+  }
 }
 
 // Phase 2: one workgroup per row tile, lane = row of the tile; the waves
 // share the tile's items and add their sums in LDS in wave order.
 template <class DT, class LT, class VT, int NR>
-__global__ __launch_bounds__(64 * P2_WAVES) void k_phase2(const SlotDev* __restrict__ slots, int nslots,
+__global__ __launch_bounds__(64 * P2_WAVES) void k_phase2(const SlotDev* __restrict__ slots, const int* __restrict__ slot_of,
                                                           const int* __restrict__ slot_active, int nrr,
                                                           const VT* __restrict__ X, int64_t ldx,
                                                           VT* __restrict__ Y, int64_t ldy, EpiDev<VT> ep) {
@@ -552,10 +591,9 @@ __global__ __launch_bounds__(64 * P2_WAVES) void k_phase2(const SlotDev* __restr
   __shared__ Seg lds_seg[P2_WAVES][P2_MAXSEG];
   __shared__ VT lds_red[P2_WAVES][RJ][TILE];
   const int lane = threadIdx.x & 63;
-  const int wv = threadIdx.x >> 6;
+  const int wv = uniform_int(threadIdx.x >> 6);  // wave index (uniform)
   const int tile = blockIdx.x;
-  const int si = find_slot(slots, nslots, tile, 2);
-  const SlotDev S = uniform_load(slots + si);
+  const SlotDev S = uniform_load(slots + uniform_load(slot_of + tile));
   if (slot_active && !uniform_int(*gbl(slot_active + S.slot))) return;  // uniform over the workgroup
   const P2Tile T = uniform_load(S.p2t + (tile - S.p2_tile_begin));
   const VT* Xs = X + S.xoff;
@@ -575,15 +613,12 @@ __global__ __launch_bounds__(64 * P2_WAVES) void k_phase2(const SlotDev* __restr
     wave_lds_sync();
     const Seg lastseg = sg_lds[item.nseg - 1];
     const int wtrue = lastseg.col0 + lastseg.w;
-    for (int c0 = 0; c0 < item.w; c0 += CW) {
-      const int cw = min(CW, item.w - c0);
-      stage_inputs<VT, NR>(in, sg_lds, item.nseg, wtrue, c0, cw, lane, nrr, Xs, ldx, Ts, S.ldt);
-      if (item.kind == 0)
-        panel_accumulate<DT, VT, NR>((const DT*)S.dense + item.base + prow * 4, T.m, c0 >> 2, (c0 + cw) >> 2, in,
-                                     acc);
-      else
-        panel_accumulate<LT, VT, NR>((const LT*)S.U + item.base + prow * 4, T.m, c0 >> 2, (c0 + cw) >> 2, in, acc);
-    }
+    if (item.kind == 0)
+      panel_item<DT, VT, NR>((const DT*)S.dense + item.base + prow * 4, T.m, item.w, in, sg_lds, item.nseg, wtrue, lane,
+                             nrr, Xs, ldx, Ts, S.ldt, acc);
+    else
+      panel_item<LT, VT, NR>((const LT*)S.U + item.base + prow * 4, T.m, item.w, in, sg_lds, item.nseg, wtrue, lane,
+                             nrr, Xs, ldx, Ts, S.ldt, acc);
   }
   // combine the waves in order and finish the tile
   VT sum[NR];
@@ -628,15 +663,14 @@ __device__ __forceinline__ double lane_bcast(double v, int l) {
 // coalesced load (lane = row) and handed to every lane by lane broadcast; the
 // V loads go out in predicated batches.
 template <class LT, class VT, int NR, int WPB>
-__global__ __launch_bounds__(64 * WPB) void k_phase1(const SlotDev* __restrict__ slots, int nslots, int ntasks,
+__global__ __launch_bounds__(64 * WPB) void k_phase1(const SlotDev* __restrict__ slots, const int* __restrict__ slot_of, int ntasks,
                                                      const int* __restrict__ slot_active, int nrr,
                                                      const VT* __restrict__ X, int64_t ldx) {
   const int lane = threadIdx.x & 63;
-  const int wv = threadIdx.x >> 6;
+  const int wv = uniform_int(threadIdx.x >> 6);  // wave index (uniform)
   const int task = blockIdx.x * WPB + wv;
   if (task >= ntasks) return;
-  const int si = find_slot(slots, nslots, task, 0);
-  const SlotDev S = uniform_load(slots + si);
+  const SlotDev S = uniform_load(slots + uniform_load(slot_of + task));
   if (slot_active && !uniform_int(*gbl(slot_active + S.slot))) return;
   const int lt = task - S.p1_task_begin;
   const int ib = uniform_int(gbl(S.p1_task)[lt]), ie = uniform_int(gbl(S.p1_task)[lt + 1]);
@@ -697,38 +731,73 @@ __global__ __launch_bounds__(64 * WPB) void k_phase1(const SlotDev* __restrict__
   }
 }
 
-// t of the row-split groups: one workgroup per group; wave w adds the
-// partials p = w, w + 4, ... in order (all right-hand sides in flight), and
-// the four wave sums are added in wave order: a fixed order, independent of
-// the rest of the batch.
+// t of the row-split groups, lane = rank column.  WPR waves per group
+// (1 with one or two right-hand sides, 4 with more, whose groups carry more
+// partials): wave w reads the partials p = w, w + WPR, ... IL at a time into
+// independent sums (IL * NR loads in flight per lane); the sums are added in
+// a fixed order, so the result does not depend on the rest of the batch.
 template <class VT, int NR>
-__global__ __launch_bounds__(256) void k_p1reduce(const SlotDev* __restrict__ slots, int nslots, int nreds,
-                                                  const int* __restrict__ slot_active, int nrr) {
-  __shared__ VT red[4][NR][64];
+constexpr int p1red_waves() {
+  return NR >= 4 ? 4 : 1;
+}
+
+template <class VT, int NR>
+__global__ __launch_bounds__(256) void k_p1reduce(const SlotDev* __restrict__ slots, const int* __restrict__ slot_of,
+                                                  int nreds, const int* __restrict__ slot_active, int nrr) {
+  constexpr int WPR = p1red_waves<VT, NR>();
+  constexpr int IL = NR == 1 ? 8 : (NR == 2 ? 4 : (NR == 4 ? 2 : 1));
+  __shared__ VT red[WPR > 1 ? WPR : 1][WPR > 1 ? NR : 1][64];
   const int lane = threadIdx.x & 63;
-  const int wv = threadIdx.x >> 6;
-  const int r = blockIdx.x;
-  if (r >= nreds) return;
-  const SlotDev S = uniform_load(slots + find_slot(slots, nslots, r, 1));
-  if (slot_active && !uniform_int(*gbl(slot_active + S.slot))) return;  // uniform over the workgroup
+  const int wv = uniform_int(threadIdx.x >> 6);  // wave index (uniform)
+  const int r = WPR > 1 ? blockIdx.x : blockIdx.x * 4 + wv;
+  const int w = WPR > 1 ? wv : 0;
+  if (r >= nreds) return;  // uniform over the workgroup when WPR > 1
+  const SlotDev S = uniform_load(slots + uniform_load(slot_of + r));
+  if (slot_active && !uniform_int(*gbl(slot_active + S.slot))) return;
   const P1Red R = uniform_load(S.p1red + (r - S.p1red_begin));
   const VT* P0 = (const VT*)S.part1 + (int64_t)R.part0 * P1_GW * NR;
-  VT acc[NR];
+  VT acc[IL][NR];
 #pragma unroll
-  for (int j = 0; j < NR; ++j) acc[j] = VT(0);
-  for (int p = wv; p < R.nparts; p += 4) {
-    const VT* Pp = P0 + (int64_t)p * NR * P1_GW;
+  for (int i = 0; i < IL; ++i)
 #pragma unroll
-    for (int j = 0; j < NR; ++j) acc[j] += gbl(Pp)[j * P1_GW + lane];
+    for (int j = 0; j < NR; ++j) acc[i][j] = VT(0);
+  for (int p = w * IL; p < R.nparts; p += WPR * IL) {
+#pragma unroll
+    for (int i = 0; i < IL; ++i) {
+      // past the last partial: re-read it and add nothing
+      const int pi = p + i < R.nparts ? p + i : R.nparts - 1;
+      const VT* Pp = P0 + (int64_t)pi * NR * P1_GW;
+#pragma unroll
+      for (int j = 0; j < NR; ++j) {
+        const VT v = gbl(Pp)[j * P1_GW + lane];
+        acc[i][j] += p + i < R.nparts ? v : VT(0);
+      }
+    }
   }
+  VT sum[NR];
 #pragma unroll
-  for (int j = 0; j < NR; ++j) red[wv][j][lane] = acc[j];
-  __syncthreads();
-  if (wv == 0 && lane < R.gw) {
+  for (int j = 0; j < NR; ++j) {
+    sum[j] = acc[0][j];
+#pragma unroll
+    for (int i = 1; i < IL; ++i) sum[j] += acc[i][j];
+  }
+  if constexpr (WPR > 1) {
+#pragma unroll
+    for (int j = 0; j < NR; ++j) red[wv][j][lane] = sum[j];
+    __syncthreads();
+    if (wv != 0) return;
+#pragma unroll
+    for (int j = 0; j < NR; ++j) {
+      VT t = red[0][j][lane];
+      for (int q = 1; q < WPR; ++q) t += red[q][j][lane];
+      sum[j] = t;
+    }
+  }
+  if (lane < R.gw) {
     VT* T = (VT*)S.t;
 #pragma unroll
     for (int j = 0; j < NR; ++j)
-      if (j < nrr) gbl_w(T)[R.trow + lane + j * S.ldt] = ((red[0][j][lane] + red[1][j][lane]) + red[2][j][lane]) + red[3][j][lane];
+      if (j < nrr) gbl_w(T)[R.trow + lane + j * S.ldt] = sum[j];
   }
 }
 
@@ -754,18 +823,17 @@ __device__ __forceinline__ f32x4 mfma16(float a, float b, f32x4 c) {
 // x rows of a 64-row chunk are staged in LDS (row-major, 16 values a row),
 // zero past the item's rows.
 template <class LT>
-__global__ __launch_bounds__(256) void k_phase1_mfma(const SlotDev* __restrict__ slots, int nslots, int ntasks,
+__global__ __launch_bounds__(256) void k_phase1_mfma(const SlotDev* __restrict__ slots, const int* __restrict__ slot_of, int ntasks,
                                                      const int* __restrict__ slot_active, int nrr,
                                                      const float* __restrict__ X, int64_t ldx) {
   constexpr int NR = 16;
   __shared__ float lds_x[4][64 * NR];
   const int lane = threadIdx.x & 63;
-  const int wv = threadIdx.x >> 6;
+  const int wv = uniform_int(threadIdx.x >> 6);  // wave index (uniform)
   const int li = lane & 15, lk = lane >> 4;
   const int task = blockIdx.x * 4 + wv;
   if (task >= ntasks) return;
-  const int si = find_slot(slots, nslots, task, 0);
-  const SlotDev S = uniform_load(slots + si);
+  const SlotDev S = uniform_load(slots + uniform_load(slot_of + task));
   if (slot_active && !uniform_int(*gbl(slot_active + S.slot))) return;
   const int lt = task - S.p1_task_begin;
   const int ib = uniform_int(gbl(S.p1_task)[lt]), ie = uniform_int(gbl(S.p1_task)[lt + 1]);
@@ -875,7 +943,7 @@ __device__ __forceinline__ void mfma_quads16(const Quad<MT> (&av)[4][4], const f
 // Phase 2, 16 right-hand sides: as k_phase2, with the row tile split into
 // four 16-row MFMA tiles; the waves' sums meet in LDS in wave order.
 template <class DT, class LT>
-__global__ __launch_bounds__(64 * P2_WAVES) void k_phase2_mfma(const SlotDev* __restrict__ slots, int nslots,
+__global__ __launch_bounds__(64 * P2_WAVES) void k_phase2_mfma(const SlotDev* __restrict__ slots, const int* __restrict__ slot_of,
                                                                const int* __restrict__ slot_active, int nrr,
                                                                const float* __restrict__ X, int64_t ldx,
                                                                float* __restrict__ Y, int64_t ldy, EpiDev<float> ep) {
@@ -884,11 +952,10 @@ __global__ __launch_bounds__(64 * P2_WAVES) void k_phase2_mfma(const SlotDev* __
   __shared__ float lds_in[P2_WAVES][CW * NR];  // reused for the wave sums [wave][rhs][row]
   __shared__ Seg lds_seg[P2_WAVES][P2_MAXSEG];
   const int lane = threadIdx.x & 63;
-  const int wv = threadIdx.x >> 6;
+  const int wv = uniform_int(threadIdx.x >> 6);  // wave index (uniform)
   const int li = lane & 15, lk = lane >> 4;
   const int tile = blockIdx.x;
-  const int si = find_slot(slots, nslots, tile, 2);
-  const SlotDev S = uniform_load(slots + si);
+  const SlotDev S = uniform_load(slots + uniform_load(slot_of + tile));
   if (slot_active && !uniform_int(*gbl(slot_active + S.slot))) return;  // uniform over the workgroup
   const P2Tile T = uniform_load(S.p2t + (tile - S.p2_tile_begin));
   const float* Xs = X + S.xoff;
@@ -906,24 +973,29 @@ __global__ __launch_bounds__(64 * P2_WAVES) void k_phase2_mfma(const SlotDev* __
     wave_lds_sync();
     const Seg lastseg = sg_lds[item.nseg - 1];
     const int wtrue = lastseg.col0 + lastseg.w;
-    // per chunk of 64 columns: the panel loads go out first, the input
-    // gathers overlap them, then 64 matrix-core steps
+    // per chunk of 64 columns: the input gathers and then the panel loads
+    // go out, the inputs are written to LDS while the panel loads are in
+    // flight, then 64 matrix-core steps
     if (item.kind == 0) {
       const DT* pa = (const DT*)S.dense + item.base;
       for (int c0 = 0; c0 < item.w; c0 += CW) {
         const int cw = min(CW, item.w - c0);
+        Staged<float, NR, CW> st;
+        stage_issue<float, NR, CW>(st, sg_lds, item.nseg, wtrue, c0, cw, lane, nrr, Xs, ldx, Ts, S.ldt);
         Quad<DT> av[4][4];
         load_quads16<DT>(av, pa, T.m, c0 >> 2, (c0 + cw) >> 2, li, lk);
-        stage_inputs<float, NR>(in, sg_lds, item.nseg, wtrue, c0, cw, lane, nrr, Xs, ldx, Ts, S.ldt);
+        stage_commit<float, NR, CW>(st, in, lane, cw);
         mfma_quads16<DT>(av, in, cw >> 2, li, lk, acc);
       }
     } else {
       const LT* pa = (const LT*)S.U + item.base;
       for (int c0 = 0; c0 < item.w; c0 += CW) {
         const int cw = min(CW, item.w - c0);
+        Staged<float, NR, CW> st;
+        stage_issue<float, NR, CW>(st, sg_lds, item.nseg, wtrue, c0, cw, lane, nrr, Xs, ldx, Ts, S.ldt);
         Quad<LT> av[4][4];
         load_quads16<LT>(av, pa, T.m, c0 >> 2, (c0 + cw) >> 2, li, lk);
-        stage_inputs<float, NR>(in, sg_lds, item.nseg, wtrue, c0, cw, lane, nrr, Xs, ldx, Ts, S.ldt);
+        stage_commit<float, NR, CW>(st, in, lane, cw);
         mfma_quads16<LT>(av, in, cw >> 2, li, lk, acc);
       }
     }
@@ -960,20 +1032,22 @@ void launch_typed(const Composition& C, int nrr, bool hi, const void* X, int64_t
                   const Epilogue& ep, const int* slot_active, hipStream_t s, hipEvent_t* ev) {
   constexpr int WPB = p1_waves_per_block<VT, NR>();
   const SlotDev* slots = (hi ? C.d_slots_hi : C.d_slots_lo).get<SlotDev>();
-  const int ns = (int)C.mats.size();
+  const int* sof = C.d_slot_of.get<int>();
   // 16 right-hand sides with FP32 sums of FP32/BF16 entries: matrix cores
   constexpr bool mfma = NR == 16 && std::is_same<VT, float>::value && sizeof(DT) == 4 && sizeof(LT) <= 4;
   if (ev) HM_HIP(hipEventRecord(ev[0], s));
   if (C.p1_tasks > 0) {
     if constexpr (mfma)
-      hipLaunchKernelGGL((k_phase1_mfma<LT>), dim3((C.p1_tasks + 3) / 4), dim3(256), 0, s, slots, ns, C.p1_tasks,
+      hipLaunchKernelGGL((k_phase1_mfma<LT>), dim3((C.p1_tasks + 3) / 4), dim3(256), 0, s, slots, sof, C.p1_tasks,
                          slot_active, nrr, (const float*)X, ldx);
     else
       hipLaunchKernelGGL((k_phase1<LT, VT, NR, WPB>), dim3((C.p1_tasks + WPB - 1) / WPB), dim3(64 * WPB), 0, s,
-                         slots, ns, C.p1_tasks, slot_active, nrr, (const VT*)X, ldx);
+                         slots, sof, C.p1_tasks, slot_active, nrr, (const VT*)X, ldx);
   }
   if (C.p1_reds > 0) {
-    hipLaunchKernelGGL((k_p1reduce<VT, NR>), dim3(C.p1_reds), dim3(256), 0, s, slots, ns, C.p1_reds,
+    constexpr int WPR = p1red_waves<VT, NR>();
+    const unsigned nb = WPR > 1 ? (unsigned)C.p1_reds : (unsigned)((C.p1_reds + 3) / 4);
+    hipLaunchKernelGGL((k_p1reduce<VT, NR>), dim3(nb), dim3(256), 0, s, slots, sof + C.p1_tasks, C.p1_reds,
                        slot_active, nrr);
   }
   if (ev) HM_HIP(hipEventRecord(ev[1], s));
@@ -986,11 +1060,11 @@ void launch_typed(const Composition& C, int nrr, bool hi, const void* X, int64_t
   e.ldz = ep.ldz;
   if (C.p2_tiles > 0) {
     if constexpr (mfma)
-      hipLaunchKernelGGL((k_phase2_mfma<DT, LT>), dim3(C.p2_tiles), dim3(64 * P2_WAVES), 0, s, slots, ns,
-                         slot_active, nrr, (const float*)X, ldx, (float*)Y, ldy, e);
+      hipLaunchKernelGGL((k_phase2_mfma<DT, LT>), dim3(C.p2_tiles), dim3(64 * P2_WAVES), 0, s, slots,
+                         sof + C.p1_tasks + C.p1_reds, slot_active, nrr, (const float*)X, ldx, (float*)Y, ldy, e);
     else
-      hipLaunchKernelGGL((k_phase2<DT, LT, VT, NR>), dim3(C.p2_tiles), dim3(64 * P2_WAVES), 0, s, slots, ns,
-                         slot_active, nrr, (const VT*)X, ldx, (VT*)Y, ldy, e);
+      hipLaunchKernelGGL((k_phase2<DT, LT, VT, NR>), dim3(C.p2_tiles), dim3(64 * P2_WAVES), 0, s, slots,
+                         sof + C.p1_tasks + C.p1_reds, slot_active, nrr, (const VT*)X, ldx, (VT*)Y, ldy, e);
   }
   if (ev) HM_HIP(hipEventRecord(ev[2], s));
   HM_HIP(hipGetLastError());

@@ -79,7 +79,7 @@ def c3(hm, ctx):
            for t, c in zip(trees, cavs)]
     eps = [dt(c.eps) for c in cavs]
     T = [dt(c.T[:, 0]) for c in cavs]
-    pmx = hm.solve_params(rtol=1e-7, restart=30, max_iter=400, mixed_precision=1, ir_inner_rtol=1e-3, want_q=1)
+    pmx = hm.solve_params(rtol=1e-7, restart=30, max_iter=400, mixed_precision=1, ir_inner_rtol=3e-3, want_q=1)
     Jx, qx, ix = hm.hm_solve_radiosity_batched(ctx, Mx, eps, T, SIGMA, pmx)
     p32 = hm.solve_params(rtol=1e-7, restart=30, max_iter=400, want_q=1, vec_dtype=hm.HM_F32)
     J3, q3, i3 = hm.hm_solve_radiosity_batched(ctx, M32, eps, T, SIGMA, p32)
