@@ -198,6 +198,8 @@ typedef struct {
   double ir_inner_rtol;    /* inner relative tolerance of each refinement step */
   int32_t want_q;          /* compute the facet flux of eq. (12) */
   int32_t vec_dtype;       /* Krylov vectors when not refining: HM_F64 or HM_F32 */
+  int32_t use_graphs;      /* 1: the Arnoldi steps run as HIP graphs captured once per workspace
+                              (fewer launches; same kernels and results); 0: direct launches */
 } hm_solve_params;
 
 typedef struct {

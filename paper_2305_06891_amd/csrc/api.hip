@@ -141,6 +141,7 @@ void check_params(const hm_solve_params* p) {
   HM_REQUIRE(!p->mixed_precision || (p->ir_inner_rtol > 0.0 && p->ir_inner_rtol < 1.0),
              "solve: ir_inner_rtol must be in (0, 1)");
   HM_REQUIRE(p->vec_dtype == HM_F64 || p->vec_dtype == HM_F32, "solve: vec_dtype must be HM_F64 or HM_F32");
+  HM_REQUIRE(p->use_graphs == 0 || p->use_graphs == 1, "solve: use_graphs must be 0 or 1");
 }
 
 }  // namespace

@@ -34,8 +34,20 @@ void SysSet::build(const Composition& C, const std::vector<std::vector<int>>& co
   upload(d_chunks, chunks, s);
 }
 
+void Krylov::drop_graphs() {
+  for (auto& g : graphs)
+    if (g.exec) (void)hipGraphExecDestroy(g.exec);
+  graphs.clear();
+}
+
+Krylov::~Krylov() {
+  drop_graphs();
+  if (cap) (void)hipStreamDestroy(cap);
+}
+
 void Krylov::init(const Composition& Cm, SysSet& Ss, int vec_bytes, int restart, hipStream_t s) {
   HM_REQUIRE(restart >= 1 && restart <= MAXM, "gmres: restart must be in 1..64");
+  drop_graphs();
   C = &Cm;
   S = &Ss;
   vb = vec_bytes;
@@ -317,9 +329,45 @@ void run_scale(Krylov& K, const double* div, const void* src, void* dst, hipStre
   HM_HIP(hipGetLastError());
 }
 
+// The graph of Arnoldi steps j0 .. j0 + nsteps - 1 for these arguments,
+// captured on the workspace's private stream at first use; nullptr when
+// capture is not possible (the caller then launches the steps directly).
+template <class F>
+hipGraphExec_t block_graph(Krylov& K, bool hi, const void* omeps, int nrr, int j0, int nsteps, F&& step) {
+  for (const auto& g : K.graphs)
+    if (g.hi == hi && g.omeps == omeps && g.nrr == nrr && g.j0 == j0 && g.nsteps == nsteps) return g.exec;
+  if (!K.cap && hipStreamCreateWithFlags(&K.cap, hipStreamNonBlocking) != hipSuccess) {
+    K.cap = nullptr;
+    return nullptr;
+  }
+  if (hipStreamBeginCapture(K.cap, hipStreamCaptureModeThreadLocal) != hipSuccess) return nullptr;
+  bool ok = true;
+  try {
+    for (int q = 0; q < nsteps; ++q) step(j0 + q, K.cap);
+  } catch (const Error&) {
+    ok = false;
+  }
+  hipGraph_t g = nullptr;
+  if (hipStreamEndCapture(K.cap, &g) != hipSuccess || !g) ok = false;
+  hipGraphExec_t ge = nullptr;
+  if (ok && hipGraphInstantiate(&ge, g, nullptr, nullptr, 0) != hipSuccess) ge = nullptr;
+  if (g) (void)hipGraphDestroy(g);
+  (void)hipGetLastError();
+  if (!ge) return nullptr;
+  StepGraph sg;
+  sg.hi = hi;
+  sg.omeps = omeps;
+  sg.nrr = nrr;
+  sg.j0 = j0;
+  sg.nsteps = nsteps;
+  sg.exec = ge;
+  K.graphs.push_back(sg);
+  return ge;
+}
+
 template <class VT>
 GmresStats gmres_t(Krylov& K, bool hi, const void* omeps, const void* b, void* x, double rtol, int max_iter,
-                   hipStream_t s) {
+                   hipStream_t s, bool use_graphs) {
   const Composition& C = *K.C;
   const int ns = K.S->size();
   const int nslots = (int)C.mats.size();
@@ -382,21 +430,33 @@ GmresStats gmres_t(Krylov& K, bool hi, const void* omeps, const void* b, void* x
     // (steps launched after every system has converged find nothing active
     // and return at once)
     constexpr int SYNC = 4;
-    for (int j = 0; j < K.m && iters + j < max_iter; ++j) {
+    // one Arnoldi step on stream st (kernels only)
+    auto step = [&](int j, hipStream_t st) {
       char* vj = K.basis.get<char>() + (size_t)j * K.blk * K.vb;
       char* vj1 = vj + (size_t)K.blk * K.vb;
-      launch_matvec(C, nrr, K.vb, hi, vj, K.ld, K.w.get(), K.ld, op_ep, K.slot_cnt.get<int>(), s);
-      run_gs<VT>(K, 0, j, K.w.get(), s);
-      run_gs<VT>(K, 1, j, K.w.get(), s);
-      run_gs<VT>(K, 2, j, K.w.get(), s);
-      run_scale<VT>(K, K.hn.get<double>(), K.w.get(), vj1, s);
-      if ((j + 1) % SYNC == 0 || j + 1 == K.m || iters + j + 1 >= max_iter) {
-        HM_HIP(hipMemcpyAsync(cnt.data(), K.slot_cnt.get(), nslots * 4, hipMemcpyDeviceToHost, s));
-        HM_HIP(hipStreamSynchronize(s));
-        int left = 0;
-        for (int v : cnt) left += v;
-        if (left == 0) break;
+      launch_matvec(C, nrr, K.vb, hi, vj, K.ld, K.w.get(), K.ld, op_ep, K.slot_cnt.get<int>(), st);
+      run_gs<VT>(K, 0, j, K.w.get(), st);
+      run_gs<VT>(K, 1, j, K.w.get(), st);
+      run_gs<VT>(K, 2, j, K.w.get(), st);
+      run_scale<VT>(K, K.hn.get<double>(), K.w.get(), vj1, st);
+    };
+    for (int j = 0; j < K.m && iters + j < max_iter;) {
+      // a block of up to SYNC steps, then the host looks at the active count
+      // (steps launched after every system has converged find nothing
+      // active and return at once)
+      const int nb = std::min(SYNC, std::min(K.m - j, max_iter - iters - j));
+      hipGraphExec_t ge = use_graphs ? block_graph(K, hi, omeps, nrr, j, nb, step) : nullptr;
+      if (ge) {
+        HM_HIP(hipGraphLaunch(ge, s));
+      } else {
+        for (int q = 0; q < nb; ++q) step(j + q, s);
       }
+      j += nb;
+      HM_HIP(hipMemcpyAsync(cnt.data(), K.slot_cnt.get(), nslots * 4, hipMemcpyDeviceToHost, s));
+      HM_HIP(hipStreamSynchronize(s));
+      int left = 0;
+      for (int v : cnt) left += v;
+      if (left == 0) break;
     }
     // steps taken in this cycle: the most any system took
     HM_HIP(hipMemcpyAsync(stp.data(), K.steps.get(), ns * 4, hipMemcpyDeviceToHost, s));
@@ -418,9 +478,9 @@ GmresStats gmres_t(Krylov& K, bool hi, const void* omeps, const void* b, void* x
 }  // namespace
 
 GmresStats gmres(Krylov& K, bool hi, const void* omeps, const void* b, void* x, double rtol, int max_iter,
-                 hipStream_t s) {
-  if (K.vb == 8) return gmres_t<double>(K, hi, omeps, b, x, rtol, max_iter, s);
-  return gmres_t<float>(K, hi, omeps, b, x, rtol, max_iter, s);
+                 hipStream_t s, bool graphs) {
+  if (K.vb == 8) return gmres_t<double>(K, hi, omeps, b, x, rtol, max_iter, s, graphs);
+  return gmres_t<float>(K, hi, omeps, b, x, rtol, max_iter, s, graphs);
 }
 
 void block_norms(Krylov& K, const void* v, std::vector<double>& out, hipStream_t s) {

@@ -41,7 +41,19 @@ struct GmresStats {
 };
 
 // Workspace of the Krylov iteration for one composition and vector type.
+// A captured block of Arnoldi steps (kernels only) and what it was captured for.
+struct StepGraph {
+  bool hi = false;
+  const void* omeps = nullptr;
+  int nrr = 0, j0 = 0, nsteps = 0;
+  hipGraphExec_t exec = nullptr;
+};
+
 struct Krylov {
+  Krylov() = default;
+  Krylov(const Krylov&) = delete;
+  Krylov& operator=(const Krylov&) = delete;
+  ~Krylov();
   const Composition* C = nullptr;
   SysSet* S = nullptr;
   int vb = 8;           // vector element bytes
@@ -50,6 +62,11 @@ struct Krylov {
   int64_t blk = 0;      // elements per vector block (ld * width)
   DevBuf basis, w, r;   // basis: (m+1) blocks
   DevBuf H, cs, sn, g, hA, hB, hn, beta, bnorm, tol, act, steps, slot_cnt, part, cnt;
+  // graphs of Arnoldi step blocks (valid while the buffers above and the
+  // composition stay as they are; init drops them)
+  std::vector<StepGraph> graphs;
+  hipStream_t cap = nullptr;  // private stream used only to capture
+  void drop_graphs();
   void init(const Composition& C, SysSet& S, int vec_bytes, int restart, hipStream_t s);
 };
 
@@ -57,7 +74,7 @@ struct Krylov {
 // the Krylov vector type; x holds the initial guess on entry.  omeps: per
 // row (1 - eps) in the vector type.  hi selects the FP32 factor copy.
 GmresStats gmres(Krylov& K, bool hi, const void* omeps, const void* b, void* x, double rtol, int max_iter,
-                 hipStream_t s);
+                 hipStream_t s, bool graphs = false);
 
 // Per-system 2-norms of a vector block (FP64 accumulation).
 void block_norms(Krylov& K, const void* v, std::vector<double>& out, hipStream_t s);

@@ -48,7 +48,7 @@ class hm_assembly_params(C.Structure):
 class hm_solve_params(C.Structure):
     _fields_ = [("rtol", C.c_double), ("restart", C.c_int32), ("max_iter", C.c_int32),
                 ("mixed_precision", C.c_int32), ("ir_inner_rtol", C.c_double), ("want_q", C.c_int32),
-                ("vec_dtype", C.c_int32)]
+                ("vec_dtype", C.c_int32), ("use_graphs", C.c_int32)]
 
 
 class hm_solve_info(C.Structure):
@@ -325,9 +325,9 @@ def hm_hmatvec_profile(ctx, M, nrhs=1, vec_dtype=HM_F32, use_f32_copy=False, rep
 
 
 def solve_params(rtol=1e-12, restart=30, max_iter=1000, mixed_precision=0, ir_inner_rtol=1e-4, want_q=1,
-                 vec_dtype=HM_F64):
+                 vec_dtype=HM_F64, use_graphs=1):
     return hm_solve_params(float(rtol), int(restart), int(max_iter), int(mixed_precision), float(ir_inner_rtol),
-                           int(want_q), int(vec_dtype))
+                           int(want_q), int(vec_dtype), int(use_graphs))
 
 
 def _info_dict(i: hm_solve_info):

@@ -230,3 +230,30 @@ def test_transient_matches_oracle(hm, ctx):
     log("transient e(T) = %.3e, newton total %d" % (e, info["newton_total"]))
     assert e <= 1e-9
     assert rel(to_np(T), ref[3]) <= 1e-9
+
+
+def test_graph_replays_match_direct_launches(hm, ctx):
+    """The Arnoldi steps captured as HIP graphs (use_graphs = 1) run the same
+    kernels in the same order as direct launches: every replay, with other
+    solves and eager work in between, gives the direct result bit for bit."""
+    import torch
+    v, f = meshes.cylinder(40, 24, 6, seed=8)
+    f = meshes.inward(f)
+    nf = f.shape[0]
+    log("case: cylinder %d facets, graph replays vs direct launches (FP32 and FP64 solves, refinement)" % nf)
+    tree, M = build(hm, ctx, v, f, 32, 1.5, 1e-6, hm.HM_F32, hm.HM_F32)
+    tree2, Mb = build(hm, ctx, v, f, 32, 1.5, 1e-6, hm.HM_BF16, hm.HM_F32, keep=1)
+    rng = np.random.default_rng(44)
+    eps = dt(rng.uniform(0.1, 0.9, nf))
+    Ts = [dt(rng.uniform(300, 1500, nf)) for _ in range(3)]
+    for Mx, kw in ((M, dict(rtol=1e-7, vec_dtype=hm.HM_F32)), (M, dict(rtol=1e-10)),
+                   (Mb, dict(rtol=1e-9, mixed_precision=1, ir_inner_rtol=3e-3))):
+        ref = [hm.hm_solve_radiosity(ctx, Mx, eps, T, SIGMA, hm.solve_params(use_graphs=0, **kw)) for T in Ts]
+        for rep in range(3):
+            for k, T in enumerate(Ts):
+                J, q, info = hm.hm_solve_radiosity(ctx, Mx, eps, T, SIGMA, hm.solve_params(use_graphs=1, **kw))
+                torch.cuda.synchronize()
+                assert torch.equal(J, ref[k][0]) and torch.equal(q, ref[k][1]), (kw, rep, k)
+                assert info["iters"] == ref[k][2]["iters"]
+                _ = (T * 2.0).sum().item()  # eager work between replays
+        log("%s: %d iterations, replays identical" % (kw, ref[0][2]["iters"]))
