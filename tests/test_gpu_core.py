@@ -257,3 +257,31 @@ def test_graph_replays_match_direct_launches(hm, ctx):
                 assert info["iters"] == ref[k][2]["iters"]
                 _ = (T * 2.0).sum().item()  # eager work between replays
         log("%s: %d iterations, replays identical" % (kw, ref[0][2]["iters"]))
+
+
+def test_closed_cavity_row_scaling(hm, ctx):
+    """Eqs. (32)-(34) at assembly (closed_row_scale = 1): rows of F_H whose
+    row sum is below 1 are divided by it, the others stay as they are.  The
+    jittered cylinder has row sums on both sides of 1; the scaled F_H
+    (expanded column by column) matches the oracle's scaling of the dense F
+    within the ACA tolerance, and rows with sum >= 1 equal the unscaled ones
+    exactly."""
+    v, f = meshes.cylinder(30, 16, 5, seed=2)
+    f = meshes.inward(f)
+    nf = f.shape[0]
+    log("case: cylinder %d facets, closed-cavity row scaling, FP64, ACA 1e-10" % nf)
+    _, M0 = build(hm, ctx, v, f, 32, 1.5, 1e-10)
+    _, M1 = build(hm, ctx, v, f, 32, 1.5, 1e-10, closed=1)
+    F0 = full_matrix(hm, ctx, M0, nf)
+    F1 = full_matrix(hm, ctx, M1, nf)
+    c, n, a, F = oracle_dense(v, f)
+    Fs = viewfactor.closed_cavity_scaling(F)
+    s = F.sum(axis=1)
+    low = s < 1.0 - 1e-6
+    high = s > 1.0 + 1e-6
+    e = rel(F1, Fs)
+    log("rows scaled %d, unscaled %d; |F1 - oracle| / |oracle| = %.2e" % (low.sum(), high.sum(), e))
+    assert low.sum() > 0 and high.sum() > 0
+    assert e <= 1e-8
+    assert np.array_equal(F1[high], F0[high])
+    assert np.allclose(F1[low].sum(axis=1), 1.0, rtol=1e-8)
