@@ -38,7 +38,7 @@ __device__ __forceinline__ double view_factor(const Geo& g, int i, int j) {
 
 struct AcaDev {
   int32_t rb, re, cb, ce;
-  int32_t kcap, pad;
+  int32_t kcap, out;            // rank cap; index of the block's rank/status outputs
   int64_t u_off, v_off, f_off;  // scratch offsets (doubles, doubles, ints)
 };
 
@@ -204,8 +204,146 @@ __global__ __launch_bounds__(ACA_T) void k_aca(const AcaDev* __restrict__ blocks
     i = nx.idx;
   }
   if (tid == 0) {
-    rank[blockIdx.x] = k;
-    status[blockIdx.x] = conv;
+    rank[b.out] = k;
+    status[b.out] = conv;
+  }
+}
+
+// ---- one wave per small block (m, n <= 64, rank cap <= ACAW_K): the same
+// steps as k_aca, lane = row for U and lane = column for V, the factors and
+// the geometry of the lane's row and column in registers, the pivot row's
+// and column's values handed to all lanes by broadcast.  For such blocks
+// k_aca's data lives in its first wave (thread = row / column index) and its
+// other waves add zeros, so both kernels take the same pivots and ranks and
+// produce the same factors bit for bit.
+constexpr int ACAW_K = 32;
+
+__device__ __forceinline__ double bcast_d(double v, int l) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), l);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+__device__ inline ArgMax wave_argmax(ArgMax v) {
+  for (int o = 32; o > 0; o >>= 1) {
+    ArgMax w;
+    w.mag = __shfl_xor(v.mag, o, 64);
+    w.val = __shfl_xor(v.val, o, 64);
+    w.idx = __shfl_xor(v.idx, o, 64);
+    v = better(v, w);
+  }
+  return v;
+}
+
+// view_factor's operations in its order, on geometry held in registers
+__device__ __forceinline__ double view_factor_r(double icx, double icy, double icz, double inx, double iny,
+                                                double inz, double jcx, double jcy, double jcz, double jnx,
+                                                double jny, double jnz, double jar, bool same) {
+  if (same) return 0.0;
+  const double dx = jcx - icx;
+  const double dy = jcy - icy;
+  const double dz = jcz - icz;
+  const double r2 = (dx * dx + dy * dy) + dz * dz;
+  const double ci = (inx * dx + iny * dy) + inz * dz;
+  const double cj = -((jnx * dx + jny * dy) + jnz * dz);
+  const double num = fmax(ci, 0.0) * fmax(cj, 0.0) * jar;
+  const double den = (3.141592653589793 * r2) * r2;
+  return r2 > 0.0 ? num / den : 0.0;
+}
+
+__global__ __launch_bounds__(256) void k_aca_wave(const AcaDev* __restrict__ blocks, int nblk, Geo g, double tol,
+                                                  double* __restrict__ scratch, int* __restrict__ rank,
+                                                  int* __restrict__ status) {
+  const int lane = threadIdx.x & 63;
+  const int bi = blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  if (bi >= nblk) return;
+  const AcaDev b = uniform_load(blocks + bi);
+  const int m = b.re - b.rb, n = b.ce - b.cb;
+  // geometry of the lane's row (rows past m repeat the last) and column
+  const int ri = b.rb + min(lane, m - 1), cj = b.cb + min(lane, n - 1);
+  const double rcx = g.cx[ri], rcy = g.cy[ri], rcz = g.cz[ri], rnx = g.nx[ri], rny = g.ny[ri], rnz = g.nz[ri];
+  const double ccx = g.cx[cj], ccy = g.cy[cj], ccz = g.cz[cj], cnx = g.nx[cj], cny = g.ny[cj], cnz = g.nz[cj];
+  const double car = g.ar[cj];
+  double U[ACAW_K], V[ACAW_K];
+#pragma unroll
+  for (int l = 0; l < ACAW_K; ++l) U[l] = V[l] = 0.0;
+  bool used = false;
+  int i = 0, k = 0, conv = 0;
+  double s2 = 0.0;
+  for (;;) {
+    // residual row i (lane = column j)
+    const double icx = bcast_d(rcx, i), icy = bcast_d(rcy, i), icz = bcast_d(rcz, i);
+    const double inx = bcast_d(rnx, i), iny = bcast_d(rny, i), inz = bcast_d(rnz, i);
+    double r = view_factor_r(icx, icy, icz, inx, iny, inz, ccx, ccy, ccz, cnx, cny, cnz, car, b.rb + i == cj);
+#pragma unroll
+    for (int l = 0; l < ACAW_K; ++l)
+      if (l < k) r = r - bcast_d(U[l], i) * V[l];
+    ArgMax am = lane < n ? ArgMax{fabs(r), r, lane} : ArgMax{-1.0, 0.0, 0x7fffffff};
+    am = wave_argmax(am);
+    const int jp = __builtin_amdgcn_readfirstlane(am.idx);
+    const double rj = am.val;
+    if (rj == 0.0) {
+      // zero residual row: mark it used and move to the smallest unused row
+      if (lane == i) used = true;
+      const unsigned long long bal = __ballot(lane < m && !used);
+      if (bal == 0ull) {
+        conv = 1;
+        break;
+      }
+      i = __ffsll((long long)bal) - 1;
+      continue;
+    }
+    const double v = lane < n ? r / rj : 0.0;
+    // residual column jp (lane = row)
+    const double jcx = bcast_d(ccx, jp), jcy = bcast_d(ccy, jp), jcz = bcast_d(ccz, jp);
+    const double jnx = bcast_d(cnx, jp), jny = bcast_d(cny, jp), jnz = bcast_d(cnz, jp), jar = bcast_d(car, jp);
+    double u = view_factor_r(rcx, rcy, rcz, rnx, rny, rnz, jcx, jcy, jcz, jnx, jny, jnz, jar, ri == b.cb + jp);
+#pragma unroll
+    for (int l = 0; l < ACAW_K; ++l)
+      if (l < k) u = u - bcast_d(V[l], jp) * U[l];
+    if (lane >= m) u = 0.0;
+    if (lane == i) used = true;
+    const double nu2 = wave_sum(u * u), nv2 = wave_sum(v * v);
+    double cross = 0.0;
+#pragma unroll
+    for (int l = 0; l < ACAW_K; ++l)
+      if (l < k) cross += wave_sum(U[l] * u) * wave_sum(V[l] * v);
+    s2 += nu2 * nv2 + 2.0 * cross;
+#pragma unroll
+    for (int l = 0; l < ACAW_K; ++l)
+      if (l == k) {
+        U[l] = u;
+        V[l] = v;
+      }
+    ++k;
+    if (sqrt(nu2 * nv2) <= tol * sqrt(fmax(s2, 0.0))) {
+      conv = 1;
+      break;
+    }
+    if (k >= b.kcap) {
+      conv = 0;
+      break;
+    }
+    ArgMax nx = (lane < m && !used) ? ArgMax{fabs(u), u, lane} : ArgMax{-1.0, 0.0, 0x7fffffff};
+    nx = wave_argmax(nx);
+    if (nx.idx == 0x7fffffff) {
+      conv = 1;
+      break;
+    }
+    i = __builtin_amdgcn_readfirstlane(nx.idx);
+  }
+  double* Us = scratch + b.u_off;
+  double* Vs = scratch + b.v_off;
+#pragma unroll
+  for (int l = 0; l < ACAW_K; ++l)
+    if (l < k) {
+      if (lane < m) Us[(int64_t)l * m + lane] = U[l];
+      if (lane < n) Vs[(int64_t)l * n + lane] = V[l];
+    }
+  if (lane == 0) {
+    rank[b.out] = k;
+    status[b.out] = conv;
   }
 }
 #pragma clang fp contract(on)
@@ -370,7 +508,7 @@ hm_matrix* assemble(hm_ctx& ctx, const hm_tree& t, const hm_assembly_params& p) 
   std::vector<LrInfo> lr;
   std::vector<BlockRef> dn(t.dense.begin(), t.dense.end());
   std::vector<DevBuf> stages;
-  DevBuf scratch, flags, d_blk, d_rank, d_status, d_cd;
+  DevBuf scratch, flags, d_blk, d_blk_small, d_rank, d_status, d_cd;
   size_t pos = 0;
   while (pos < t.lowrank.size()) {
     std::vector<AcaDev> batch;
@@ -387,18 +525,35 @@ hm_matrix* assemble(hm_ctx& ctx, const hm_tree& t, const hm_assembly_params& p) 
       batch.push_back(a);
       ++pos;
     }
-    // largest blocks first for the hardware dispatcher
-    std::stable_sort(batch.begin(), batch.end(), [](const AcaDev& x, const AcaDev& y) {
+    // blocks of at most 64 x 64 (rank cap <= 32): one wave each; larger ones:
+    // one workgroup each, largest first for the hardware dispatcher
+    std::vector<AcaDev> small, large;
+    for (size_t q = 0; q < batch.size(); ++q) {
+      batch[q].out = (int32_t)q;
+      const AcaDev& a = batch[q];
+      if (a.re - a.rb <= 64 && a.ce - a.cb <= 64 && a.kcap <= ACAW_K) small.push_back(a);
+      else large.push_back(a);
+    }
+    std::stable_sort(large.begin(), large.end(), [](const AcaDev& x, const AcaDev& y) {
       return (int64_t)(x.re - x.rb) * (x.ce - x.cb) > (int64_t)(y.re - y.rb) * (y.ce - y.cb);
     });
     if ((size_t)sd * 8 > scratch.bytes()) scratch.alloc((size_t)sd * 8);
     if ((size_t)sf * 4 > flags.bytes()) flags.alloc((size_t)sf * 4);
-    upload(d_blk, batch, s);
     d_rank.alloc(batch.size() * 4);
     d_status.alloc(batch.size() * 4);
-    hipLaunchKernelGGL(k_aca, dim3((unsigned)batch.size()), dim3(ACA_T), 0, s, d_blk.get<AcaDev>(), g, p.aca_tol,
-                       scratch.get<double>(), flags.get<int>(), d_rank.get<int>(), d_status.get<int>());
-    HM_HIP(hipGetLastError());
+    if (!large.empty()) {
+      upload(d_blk, large, s);
+      hipLaunchKernelGGL(k_aca, dim3((unsigned)large.size()), dim3(ACA_T), 0, s, d_blk.get<AcaDev>(), g, p.aca_tol,
+                         scratch.get<double>(), flags.get<int>(), d_rank.get<int>(), d_status.get<int>());
+      HM_HIP(hipGetLastError());
+    }
+    if (!small.empty()) {
+      upload(d_blk_small, small, s);
+      hipLaunchKernelGGL(k_aca_wave, dim3((unsigned)((small.size() + 3) / 4)), dim3(256), 0, s,
+                         d_blk_small.get<AcaDev>(), (int)small.size(), g, p.aca_tol, scratch.get<double>(),
+                         d_rank.get<int>(), d_status.get<int>());
+      HM_HIP(hipGetLastError());
+    }
     std::vector<int> rk(batch.size()), st(batch.size());
     HM_HIP(hipMemcpyAsync(rk.data(), d_rank.get(), rk.size() * 4, hipMemcpyDeviceToHost, s));
     HM_HIP(hipMemcpyAsync(st.data(), d_status.get(), st.size() * 4, hipMemcpyDeviceToHost, s));
