@@ -305,6 +305,189 @@ def run_kernels_only(args):
             "copy_bytes": 1 << 30, "fp64_muls": x.numel()}
 
 
+def run_c4(args):
+    """200,000-facet (4, 2, 1) ellipsoid, 16 scenarios: one step = one
+    backward-Euler step of all 16 (diagonal Newton on the lumped balance,
+    each iteration a 16-right-hand-side FP32 solve plus an FP64 flux)."""
+    import torch
+    from paper_2305_06891_amd import hm
+    from workloads import configs
+
+    cav = configs.c4_ellipsoid()
+    ctx = hm.Context(0)
+    t0 = time.perf_counter()
+    c, nrm, area = hm.hm_facets_from_triangles(cav.v, cav.tri, orient=1)
+    tree = hm.hm_build_cluster_tree(ctx, c, nrm, area, cav.leaf, cav.eta)
+    t_tree = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    M = hm.hm_assemble_hmatrix(ctx, tree, cav.aca_tol, 256, hm.HM_F32, hm.HM_F32, autotune=1)
+    torch.cuda.synchronize()
+    t_asm = time.perf_counter() - t0
+    st = M.stats()
+    log("c4: matrix", st, "tree %.2fs assembly %.2fs" % (t_tree, t_asm))
+    eps = torch.as_tensor(cav.eps, device="cuda")
+    T = torch.as_tensor(np.asfortranarray(cav.T), device="cuda")
+    src = torch.as_tensor(np.asfortranarray(cav.extra["source"]), device="cuda")
+    sp = hm.solve_params(rtol=RTOL, restart=30, max_iter=400, want_q=1, vec_dtype=hm.HM_F32)
+    kw = dict(mc=cav.extra["mc"], dt=cav.extra["dt"], newton_rtol=1e-9, params=sp)
+    hm.hm_transient_run(ctx, M, eps, T, src, steps=max(1, args.warmup), **kw)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, info = hm.hm_transient_run(ctx, M, eps, T, src, steps=args.steps, **kw)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    solves = info["newton_total"] * T.shape[1]
+    log("c4: %d steps in %.3f s: newton %d (max %d), matvecs %d, residual %.1e"
+        % (args.steps, dt, info["newton_total"], info["newton_max"], info["matvecs"], info["max_rel_residual"]))
+    prof = hm.hm_hmatvec_profile(ctx, M, 16, hm.HM_F32, reps=10, flush_bytes=0)
+    prof1 = hm.hm_hmatvec_profile(ctx, M, 1, hm.HM_F32, reps=10, flush_bytes=0)
+    log("profile 16 rhs", prof, "\nprofile 1 rhs", prof1)
+    out = base_record(args, solves / dt, 1e3 * dt / args.steps, "f32+f64", {
+        "workload": "c4_ellipsoid_200000_16_scenarios", "facets": cav.n, "scenarios": int(T.shape[1]),
+        "leaf": cav.leaf, "eta": cav.eta, "aca_tol": cav.aca_tol, "storage": "fp32",
+        "solver": "backward Euler, diagonal Newton; gmres(30) fp32 16 rhs per product (matrix cores), fp64 flux",
+        "rtol": RTOL, "newton_rtol": 1e-9, "mc": cav.extra["mc"], "dt": cav.extra["dt"]})
+    out["roofline"] = roofline(prof)
+    out["roofline_1rhs"] = roofline(prof1)
+    out["steps_per_s"] = args.steps / dt
+    out["transient"] = {k: info[k] for k in ("steps_done", "newton_total", "newton_max", "matvecs",
+                                             "max_rel_residual")}
+    out["matrix"] = {k: st[k] for k in ("bytes_device", "entries_dense", "entries_lowrank", "max_rank",
+                                        "n_dense_blocks", "n_lowrank_blocks", "n_fallback")}
+    out["assembly_s"] = t_asm
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline_transient(cav.n, info["newton_total"] / max(1, args.steps))
+    return out
+
+
+def cpu_baseline_transient(n, newton_per_step):
+    """The oracle's transient (dense F, LU, diagonal Newton, 16 scenarios)
+    timed on the 4,500-facet member of the same ellipsoid family, scaled to n
+    facets: assembly x(n/ns)^2 and LU x(n/ns)^3 once, each Newton iteration
+    (16-right-hand-side triangular solves and products, O(n^2)) x(n/ns)^2.
+    Returns radiosity solves (right-hand sides) per second over 10 steps."""
+    from oracle import geometry, radiosity, transient, viewfactor
+    from workloads import configs
+    cav = configs.c4_ellipsoid(nu=15, scenarios=16)
+    c, nrm, area = geometry.facets_from_triangles(cav.v, cav.tri)
+    ns = cav.n
+    t0 = time.perf_counter()
+    F = viewfactor.view_factor_matrix(c, nrm, area)
+    t_asm = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    rad = radiosity.DenseRadiosity(F, cav.eps)
+    t_lu = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    _, it, _ = transient.newton_step(rad, cav.T, cav.extra["source"], cav.extra["mc"], cav.extra["dt"], tol=1e-9)
+    t_step = time.perf_counter() - t0
+    per_it = t_step / max(1, it)
+    r2, r3 = (n / ns) ** 2, (n / ns) ** 3
+    steps = 10
+    total = t_asm * r2 + t_lu * r3 + steps * newton_per_step * per_it * r2
+    return {"value": steps * newton_per_step * 16 / total, "unit": "solves/s", "cores": _blas_threads(),
+            "kind": "oracle",
+            "sample": "dense FP64 oracle transient on the %d-facet ellipsoid (assembly %.2f s, LU + g %.2f s, "
+                      "one Newton iteration of 16 scenarios %.3f s) scaled to %d facets and 10 steps of %.1f "
+                      "Newton iterations" % (ns, t_asm, t_lu, per_it, n, newton_per_step),
+            "seconds_per_step": total / steps}
+
+
+def run_c5(args):
+    """Serving: a stream of radiosity-solve requests on 256 cavity ids
+    (1k-100k facets, Zipf 1.1 over ids, 1-8 right-hand sides), BF16 factors
+    + FP64 refinement to a residual of 1e-7, resident H-matrices admitted by
+    a 64 GB budget, continuous batching.  First a closed-loop burst (all
+    requests at once, after a warm-up that assembles the popular cavities)
+    measures the saturation rate; then Poisson arrivals at 0.5, 0.8 and 0.95
+    of it give the latency percentiles.  value = right-hand sides solved per
+    second at saturation."""
+    import torch
+    from paper_2305_06891_amd import hm
+    from workloads import configs
+
+    nreq = args.c5_requests
+    seed = 5999
+    ctx = hm.Context(0)
+    p = hm.solve_params(rtol=RTOL, restart=30, max_iter=400, mixed_precision=1, ir_inner_rtol=3e-3, want_q=1)
+    srv = hm.Server(ctx, hbm_budget_bytes=64 << 30, max_active=64, max_rhs_per_slot=8, params=p)
+    # the request streams (arrival order, ids, nrhs) of every phase
+    _, ids_all, nrhs_all = configs.c5_requests(nreq * 5, 1.0, seed=seed)
+    t0 = time.perf_counter()
+    sizes = {}
+    for cid in sorted(set(int(i) for i in ids_all)):
+        cav = configs.c5_cavity(cid)
+        c, nrm, area = hm.hm_facets_from_triangles(cav.v, cav.tri, orient=1)
+        tree = hm.hm_build_cluster_tree(ctx, c, nrm, area, cav.leaf, cav.eta)
+        srv.register_cavity(cid, tree, cav.eps, aca_tol=cav.aca_tol, lowrank_dtype=hm.HM_BF16,
+                            dense_dtype=hm.HM_F32, keep_f32_copy=1)
+        sizes[cid] = cav.n
+    log("c5: registered %d cavity ids (%d-%d facets) in %.1f s" % (len(sizes), min(sizes.values()),
+                                                                    max(sizes.values()), time.perf_counter() - t0))
+
+    def temps(k):
+        cid, nr = int(ids_all[k]), int(nrhs_all[k])
+        return cid, configs.request_temperatures(sizes[cid], nr, seed, k)
+
+    def run_phase(first, count, arrivals):
+        """Submit requests first..first+count-1 at the given arrival offsets
+        (None: all at once); returns (elapsed s, latencies s, rhs, statuses)."""
+        reqs = [temps(first + k) for k in range(count)]
+        lat, rhs, sts = [], 0, []
+        pending = {}
+        t_start = time.perf_counter()
+        i = 0
+        while i < count or pending:
+            now = time.perf_counter() - t_start
+            while i < count and (arrivals is None or arrivals[i] <= now):
+                cid, T = reqs[i]
+                tk, shape = srv.submit(cid, T)
+                pending[tk] = shape
+                i += 1
+            for tk in list(pending):
+                r = srv.poll(tk, pending[tk])
+                if r is not None:
+                    lat.append(r[2]["latency"])
+                    rhs += pending[tk][1]
+                    sts.append(r[2]["rel_residual"])
+                    del pending[tk]
+            time.sleep(0.0002)
+        return time.perf_counter() - t_start, np.array(lat), rhs, sts
+
+    # warm-up: assembles the cavities of the first requests
+    t_w, _, _, _ = run_phase(0, nreq // 2, None)
+    st0 = srv.stats()
+    log("c5: warm-up %d requests in %.1f s; %s" % (nreq // 2, t_w, st0))
+    el, lat, rhs, res = run_phase(nreq // 2, nreq, None)
+    sat_req = nreq / el
+    sat_rhs = rhs / el
+    log("c5: saturation %.1f requests/s, %.1f solves/s (p50 %.1f ms, p99 %.1f ms; worst residual %.1e)"
+        % (sat_req, sat_rhs, 1e3 * np.percentile(lat, 50), 1e3 * np.percentile(lat, 99), max(res)))
+    loads = []
+    first = nreq // 2 + nreq
+    for frac in (0.5, 0.8, 0.95):
+        rate = frac * sat_req
+        gaps = np.random.default_rng([seed, int(1000 * frac)]).exponential(1.0 / rate, nreq)
+        el, lat, rhs, res = run_phase(first, nreq, np.cumsum(gaps))
+        first += nreq
+        loads.append({"load": frac, "offered_req_per_s": rate, "achieved_req_per_s": nreq / el,
+                      "solves_per_s": rhs / el, "p50_ms": 1e3 * float(np.percentile(lat, 50)),
+                      "p99_ms": 1e3 * float(np.percentile(lat, 99)), "worst_rel_residual": float(max(res))})
+        log("c5: load %.2f: %s" % (frac, loads[-1]))
+    st = srv.stats()
+    srv.close()
+    out = base_record(args, sat_rhs, 1e3 / sat_req, "f32+f64", {
+        "workload": "c5_serving_256_ids", "cavity_ids": 256, "ids_used": len(sizes), "zipf_s": 1.1,
+        "facets_range": [min(sizes.values()), max(sizes.values())], "rhs_per_request": "1-8",
+        "hbm_budget_gb": 64, "storage": "bf16 low-rank factors, fp32 near field, fp32 factor copy",
+        "solver": "continuous batching, fp64 refinement rounds with batched fp32 gmres", "rtol": RTOL,
+        "requests_per_phase": nreq})
+    out["unit"] = "solves/s"
+    out["saturation"] = {"req_per_s": sat_req, "solves_per_s": sat_rhs}
+    out["latency"] = loads
+    out["server"] = st
+    return out
+
+
 def run_c2(args):
     import torch
     from paper_2305_06891_amd import hm

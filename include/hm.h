@@ -157,6 +157,14 @@ hm_status hm_matrix_info(const hm_matrix* M, int64_t* n, int64_t* n_dense_blocks
  * be NULL) receives the measured microseconds of the chosen split, or 0 when
  * nothing was timed.  Any pointer may be NULL. */
 hm_status hm_matrix_tuning(const hm_matrix* M, int32_t* p1_rows, int32_t* p1_task_bytes, double* timing_us);
+/* Sets the work split of the product's first kernel (the two values
+ * hm_matrix_tuning reports), e.g. a split found by timing a batch of
+ * matrices that are multiplied together.  p1_rows: rows per item, a positive
+ * multiple of 64; p1_task_bytes: minimum bytes per wave task, counted at 4
+ * bytes per stored entry, >= 0.  The product's result changes only by the
+ * order of partial sums.  Synchronises ctx's stream; must not overlap a
+ * product with M on another stream.  HM_EINVAL on bad values. */
+hm_status hm_matrix_set_tuning(hm_ctx* ctx, hm_matrix* M, int32_t p1_rows, int32_t p1_task_bytes);
 void hm_matrix_destroy(hm_matrix* M);
 
 /* Y = alpha * F_H * X + beta * Y (Sec. 5.2: the block-wise product adds no

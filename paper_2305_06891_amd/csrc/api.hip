@@ -254,6 +254,24 @@ hm_status hm_matrix_tuning(const hm_matrix* M, int32_t* rows, int32_t* task_byte
   return HM_OK;
 }
 
+hm_status hm_matrix_set_tuning(hm_ctx* ctx, hm_matrix* M, int32_t rows, int32_t task_bytes) {
+  if (!ctx) {
+    set_tl_error("hm_matrix_set_tuning: NULL ctx");
+    return HM_EINVAL;
+  }
+  return guarded(ctx, [&] {
+    HM_REQUIRE(M, "hm_matrix_set_tuning: NULL matrix");
+    HM_REQUIRE(M->device == ctx->device, "hm_matrix_set_tuning: matrix lives on another device");
+    HM_REQUIRE(rows >= 64 && rows % 64 == 0 && rows <= (1 << 20), "hm_matrix_set_tuning: p1_rows must be a positive multiple of 64");
+    HM_REQUIRE(task_bytes >= 0, "hm_matrix_set_tuning: p1_task_bytes must be >= 0");
+    P1Params pp;
+    pp.rows = rows;
+    pp.task_bytes = task_bytes;
+    replan_phase1(*M, pp, ctx->stream);
+    M->plan.p1_us = 0.0;
+  });
+}
+
 void hm_matrix_destroy(hm_matrix* M) {
   if (!M) return;
   (void)hipSetDevice(M->device);

@@ -367,7 +367,7 @@ hipGraphExec_t block_graph(Krylov& K, bool hi, const void* omeps, int nrr, int j
 
 template <class VT>
 GmresStats gmres_t(Krylov& K, bool hi, const void* omeps, const void* b, void* x, double rtol, int max_iter,
-                   hipStream_t s, bool use_graphs) {
+                   hipStream_t s, bool use_graphs, unsigned opts) {
   const Composition& C = *K.C;
   const int ns = K.S->size();
   const int nslots = (int)C.mats.size();
@@ -397,11 +397,17 @@ GmresStats gmres_t(Krylov& K, bool hi, const void* omeps, const void* b, void* x
   std::vector<int> act(ns), cnt(nslots), stp(ns);
   std::vector<double> g0((size_t)ns * (MAXM + 1), 0.0);
   int iters = 0;
+  bool first = true;
   for (;;) {
-    // true residual and its norm
-    launch_matvec(C, nrr, K.vb, hi, x, K.ld, K.basis.get(), K.ld, res_ep, nullptr, s);
-    st.matvecs++;
-    st.bytes += mbytes;
+    // true residual and its norm (b itself for a zero start)
+    if (first && (opts & GM_X0_ZERO)) {
+      HM_HIP(hipMemcpyAsync(K.basis.get(), b, (size_t)K.blk * K.vb, hipMemcpyDeviceToDevice, s));
+    } else {
+      launch_matvec(C, nrr, K.vb, hi, x, K.ld, K.basis.get(), K.ld, res_ep, nullptr, s);
+      st.matvecs++;
+      st.bytes += mbytes;
+    }
+    first = false;
     run_gs<VT>(K, 3, 0, K.basis.get(), s);
     HM_HIP(hipMemcpyAsync(beta.data(), K.beta.get(), ns * 8, hipMemcpyDeviceToHost, s));
     HM_HIP(hipStreamSynchronize(s));
@@ -440,6 +446,7 @@ GmresStats gmres_t(Krylov& K, bool hi, const void* omeps, const void* b, void* x
       run_gs<VT>(K, 2, j, K.w.get(), st);
       run_scale<VT>(K, K.hn.get<double>(), K.w.get(), vj1, st);
     };
+    int left = nact;
     for (int j = 0; j < K.m && iters + j < max_iter;) {
       // a block of up to SYNC steps, then the host looks at the active count
       // (steps launched after every system has converged find nothing
@@ -454,12 +461,14 @@ GmresStats gmres_t(Krylov& K, bool hi, const void* omeps, const void* b, void* x
       j += nb;
       HM_HIP(hipMemcpyAsync(cnt.data(), K.slot_cnt.get(), nslots * 4, hipMemcpyDeviceToHost, s));
       HM_HIP(hipStreamSynchronize(s));
-      int left = 0;
+      left = 0;
       for (int v : cnt) left += v;
       if (left == 0) break;
     }
     // steps taken in this cycle: the most any system took
+    const bool trusted = (opts & GM_TRUST_ESTIMATE) && left == 0;
     HM_HIP(hipMemcpyAsync(stp.data(), K.steps.get(), ns * 4, hipMemcpyDeviceToHost, s));
+    if (trusted) HM_HIP(hipMemcpyAsync(g0.data(), K.g.get(), g0.size() * 8, hipMemcpyDeviceToHost, s));
     HM_HIP(hipStreamSynchronize(s));
     const int cyc = *std::max_element(stp.begin(), stp.end());
     iters += cyc;
@@ -470,6 +479,12 @@ GmresStats gmres_t(Krylov& K, bool hi, const void* omeps, const void* b, void* x
                        K.S->d_chunks.get<ChunkDev>(), K.steps.get<int>(), K.H.get<double>(), K.g.get<double>(),
                        (const VT*)K.basis.get(), K.ld, K.blk, (VT*)x);
     HM_HIP(hipGetLastError());
+    if (trusted) {
+      // every system met the tolerance by its residual estimate
+      for (int q = 0; q < ns; ++q)
+        st.rel_res[q] = bn[q] > 0 ? std::fabs(g0[(size_t)q * (MAXM + 1) + stp[q]]) / bn[q] : 0.0;
+      break;
+    }
   }
   st.iters = iters;
   return st;
@@ -478,9 +493,9 @@ GmresStats gmres_t(Krylov& K, bool hi, const void* omeps, const void* b, void* x
 }  // namespace
 
 GmresStats gmres(Krylov& K, bool hi, const void* omeps, const void* b, void* x, double rtol, int max_iter,
-                 hipStream_t s, bool graphs) {
-  if (K.vb == 8) return gmres_t<double>(K, hi, omeps, b, x, rtol, max_iter, s, graphs);
-  return gmres_t<float>(K, hi, omeps, b, x, rtol, max_iter, s, graphs);
+                 hipStream_t s, bool graphs, unsigned opts) {
+  if (K.vb == 8) return gmres_t<double>(K, hi, omeps, b, x, rtol, max_iter, s, graphs, opts);
+  return gmres_t<float>(K, hi, omeps, b, x, rtol, max_iter, s, graphs, opts);
 }
 
 void block_norms(Krylov& K, const void* v, std::vector<double>& out, hipStream_t s) {

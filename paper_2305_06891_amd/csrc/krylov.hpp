@@ -70,11 +70,24 @@ struct Krylov {
   void init(const Composition& C, SysSet& S, int vec_bytes, int restart, hipStream_t s);
 };
 
+// Options of gmres().
+enum : unsigned {
+  // x is zero on entry: the first residual is b itself (no product).  For
+  // the same number of products this searches a Krylov space that contains
+  // the one of the start x = b, so it never ends with a larger residual.
+  GM_X0_ZERO = 1u,
+  // return as soon as every system's GMRES residual estimate (the last
+  // Givens-rotated entry) meets the tolerance, without the closing product
+  // for the true residual; rel_res then holds the estimates.  For inner
+  // solves whose result the caller checks with its own residual.
+  GM_TRUST_ESTIMATE = 2u,
+};
+
 // Solve C x = b for every system of S.  b, x: vector blocks (ld = C.N) of
 // the Krylov vector type; x holds the initial guess on entry.  omeps: per
 // row (1 - eps) in the vector type.  hi selects the FP32 factor copy.
 GmresStats gmres(Krylov& K, bool hi, const void* omeps, const void* b, void* x, double rtol, int max_iter,
-                 hipStream_t s, bool graphs = false);
+                 hipStream_t s, bool graphs = false, unsigned opts = 0);
 
 // Per-system 2-norms of a vector block (FP64 accumulation).
 void block_norms(Krylov& K, const void* v, std::vector<double>& out, hipStream_t s);

@@ -659,13 +659,57 @@ __device__ __forceinline__ double lane_bcast(double v, int l) {
 }
 
 // Phase 1: lane l owns rank column l of a group panel: t[trow + l] (+ j*ldt)
-// = sum_r V(r, l) x(xrow + r).  The x entries of 64 rows are read with one
-// coalesced load (lane = row) and handed to every lane by lane broadcast; the
-// V loads go out in predicated batches.
+// = sum_r V(r, l) x(xrow + r).  The rows of an item go in batches of UN
+// quads (about 8 KB per wave whatever the stored type): the x entries of a
+// batch come with one coalesced load (lane = row) and reach every lane by
+// lane broadcast.  The loads of the next batch are issued before the
+// current one is used, so each wave keeps two batches in flight; rows past
+// the item's end re-read its last quad and meet x = 0, so no load sits
+// behind a branch.
+template <class LT>
+constexpr int p1_batch_quads() {
+  return (int)(128 / sizeof(Quad<LT>));
+}
+
+template <class LT, class VT, int NR, int UN>
+struct P1Batch {
+  Quad<LT> v[UN];
+  VT x[NR];
+  bool ok;  // this lane's x row lies inside the item and the cavity
+};
+
+template <class LT, class VT, int NR, int UN>
+__device__ __forceinline__ void p1_issue(P1Batch<LT, VT, NR, UN>& b, const LT* a, int64_t step, int qb, int qe,
+                                         const VT* xr, int64_t ldx, int nrr, int nrows, int lane) {
+  const int row = qb * 4 + lane;
+  b.ok = lane < 4 * UN && row < 4 * qe && row < nrows;
+  const int rr = min(row, nrows - 1);
+#pragma unroll
+  for (int j = 0; j < NR; ++j) b.x[j] = gbl(xr)[rr + (int64_t)min(j, nrr - 1) * ldx];
+#pragma unroll
+  for (int u = 0; u < UN; ++u) b.v[u].load(a + (int64_t)min(qb + u, qe - 1) * step);
+}
+
+template <class LT, class VT, int NR, int UN>
+__device__ __forceinline__ void p1_use(const P1Batch<LT, VT, NR, UN>& b, int nrr, VT* acc) {
+  VT xm[NR];
+#pragma unroll
+  for (int j = 0; j < NR; ++j) xm[j] = (b.ok && j < nrr) ? b.x[j] : VT(0);
+#pragma unroll
+  for (int u = 0; u < UN; ++u)
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const VT w = b.v[u].template get<VT>(e);
+#pragma unroll
+      for (int j = 0; j < NR; ++j) acc[j] += w * lane_bcast(xm[j], u * 4 + e);
+    }
+}
+
 template <class LT, class VT, int NR, int WPB>
 __global__ __launch_bounds__(64 * WPB) void k_phase1(const SlotDev* __restrict__ slots, const int* __restrict__ slot_of, int ntasks,
                                                      const int* __restrict__ slot_active, int nrr,
                                                      const VT* __restrict__ X, int64_t ldx) {
+  constexpr int UN = p1_batch_quads<LT>();
   const int lane = threadIdx.x & 63;
   const int wv = uniform_int(threadIdx.x >> 6);  // wave index (uniform)
   const int task = blockIdx.x * WPB + wv;
@@ -676,9 +720,6 @@ __global__ __launch_bounds__(64 * WPB) void k_phase1(const SlotDev* __restrict__
   const int ib = uniform_int(gbl(S.p1_task)[lt]), ie = uniform_int(gbl(S.p1_task)[lt + 1]);
   const VT* Xs = X + S.xoff;
   VT* T = (VT*)S.t;
-  // one 64-row chunk per batch of loads (two batches when the entries or
-  // the sums are FP64, to stay within 128 VGPRs)
-  constexpr int UN = sizeof(LT) + sizeof(VT) > 8 ? 8 : 16;
   for (int it = ib; it < ie; ++it) {
     const P1Item item = uniform_load(S.p1 + it);
     const bool act = lane < item.gw;
@@ -690,33 +731,24 @@ __global__ __launch_bounds__(64 * WPB) void k_phase1(const SlotDev* __restrict__
     VT acc[NR];
 #pragma unroll
     for (int j = 0; j < NR; ++j) acc[j] = VT(0);
-    for (int q0 = item.q0; q0 < qe; q0 += 16) {
-      // rows 4*q0 .. 4*q0+63 of the panel; x beyond the group's rows reads as 0
-      const int r0 = q0 * 4;
-      const int q1 = q0 + 16 < qe ? q0 + 16 : qe;
-      VT xv[NR];
-      {
-        const int rr = min(r0 + lane, item.nrows - 1);
-#pragma unroll
-        for (int j = 0; j < NR; ++j) xv[j] = gbl(xr)[rr + (int64_t)min(j, nrr - 1) * ldx];
-#pragma unroll
-        for (int j = 0; j < NR; ++j) xv[j] = (j < nrr && r0 + lane < item.nrows) ? xv[j] : VT(0);
+    P1Batch<LT, VT, NR, UN> A, B;
+    int qb = item.q0;
+    p1_issue(A, a, step, qb, qe, xr, ldx, nrr, item.nrows, lane);
+    for (;;) {
+      if (qb + UN >= qe) {
+        p1_use(A, nrr, acc);
+        break;
       }
-      for (int h = 0; h < 16; h += UN) {
-        const int qb = q0 + h;
-        Quad<LT> v[UN];
-#pragma unroll
-        for (int u = 0; u < UN; ++u) v[u].load(a + (int64_t)(qb + u < q1 ? qb + u : q1 - 1) * step);
-#pragma unroll
-        for (int u = 0; u < UN; ++u)
-          if (qb + u < q1)
-#pragma unroll
-            for (int e = 0; e < 4; ++e) {
-              const VT w = v[u].template get<VT>(e);
-#pragma unroll
-              for (int j = 0; j < NR; ++j) acc[j] += w * lane_bcast(xv[j], (h + u) * 4 + e);
-            }
+      p1_issue(B, a, step, qb + UN, qe, xr, ldx, nrr, item.nrows, lane);
+      p1_use(A, nrr, acc);
+      qb += UN;
+      if (qb + UN >= qe) {
+        p1_use(B, nrr, acc);
+        break;
       }
+      p1_issue(A, a, step, qb + UN, qe, xr, ldx, nrr, item.nrows, lane);
+      p1_use(B, nrr, acc);
+      qb += UN;
     }
     if (item.part < 0) {
       if (act)

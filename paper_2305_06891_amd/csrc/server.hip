@@ -345,11 +345,14 @@ void hm_server::round(std::vector<SrvReq*>& act) {
         HM_HIP(hipMemsetAsync(b32.get<float>() + sd.col * N + sd.row0, 0, (size_t)sd.n * 4, s));
       }
     }
-    HM_HIP(hipMemcpyAsync(x32.get(), b32.get(), blk * 4, hipMemcpyDeviceToDevice, s));
+    // correction from zero, stopped on the GMRES residual estimate (the
+    // next round's FP64 residual checks it)
+    HM_HIP(hipMemsetAsync(x32.get(), 0, blk * 4, s));
     Krylov K4;
     K4.init(*C, S, 4, p.solve.restart, s);
     const double inner = p.solve.mixed_precision ? p.solve.ir_inner_rtol : std::min(p.solve.ir_inner_rtol, 1e-5);
-    GmresStats gs = gmres(K4, false, om32.get(), b32.get(), x32.get(), inner, p.solve.max_iter, s);
+    GmresStats gs = gmres(K4, false, om32.get(), b32.get(), x32.get(), inner, p.solve.max_iter, s, false,
+                          GM_X0_ZERO | GM_TRUST_ESTIMATE);
     hipLaunchKernelGGL(k_srv_acc, dim3((unsigned)((blk + 255) / 256)), dim3(256), 0, s, x32.get<float>(),
                        x64.get<double>(), (int64_t)blk);
     for (size_t q = 0; q < act.size(); ++q) {

@@ -96,6 +96,7 @@ _PROTOS = {
     "hm_matrix_info": (C.c_int, [_vp, C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.POINTER(C.c_int64),
                                  C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
     "hm_matrix_tuning": (C.c_int, [_vp, C.POINTER(C.c_int32), C.POINTER(C.c_int32), _dp]),
+    "hm_matrix_set_tuning": (C.c_int, [_vp, _vp, C.c_int32, C.c_int32]),
     "hm_matrix_destroy": (None, [_vp]),
     "hm_hmatvec": (C.c_int, [_vp, _vp, C.c_int32, C.c_int, _vp, C.c_int64, _vp, C.c_int64, C.c_double,
                              C.c_double]),
@@ -276,6 +277,11 @@ class HMatrix:
         r, tb, us = C.c_int32(), C.c_int32(), C.c_double()
         _check(lib.hm_matrix_tuning(self._h, C.byref(r), C.byref(tb), C.byref(us)))
         return {"p1_rows": r.value, "p1_task_bytes": tb.value, "p1_us": us.value}
+
+    def set_tuning(self, ctx, p1_rows, p1_task_bytes):
+        """Sets the work split of the product's first kernel (the values
+        ``tuning()`` reports)."""
+        _check(lib.hm_matrix_set_tuning(ctx._h, self._h, int(p1_rows), int(p1_task_bytes)))
 
     def close(self):
         if self._h:
