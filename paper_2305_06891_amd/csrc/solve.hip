@@ -277,9 +277,8 @@ SolveResult Batch::solve_prepared(const hm_solve_params& p, hipStream_t s, bool 
   const unsigned gb_ = (unsigned)((tot + 255) / 256);
   if (!p.mixed_precision && p.vec_dtype != HM_F32) {
     Krylov& K = krylov(8, p.restart, s);
-    if (!warm) HM_HIP(hipMemsetAsync(x64.get(), 0, tot * 8, s));
-    GmresStats st = gmres(K, false, omeps64.get(), b64.get(), x64.get(), p.rtol, p.max_iter, s, p.use_graphs != 0,
-                          warm ? 0u : GM_X0_ZERO);
+    if (!warm) HM_HIP(hipMemcpyAsync(x64.get(), b64.get(), tot * 8, hipMemcpyDeviceToDevice, s));
+    GmresStats st = gmres(K, false, omeps64.get(), b64.get(), x64.get(), p.rtol, p.max_iter, s, p.use_graphs != 0);
     R.iters = st.iters;
     R.matvecs = st.matvecs;
     R.bytes = st.bytes;
@@ -288,9 +287,8 @@ SolveResult Batch::solve_prepared(const hm_solve_params& p, hipStream_t s, bool 
   } else if (!p.mixed_precision) {
     Krylov& K = krylov(4, p.restart, s);
     if (warm) hipLaunchKernelGGL((k_cast<double, float>), dim3(gb_), dim3(256), 0, s, x64.get<double>(), x32.get<float>(), tot);
-    else HM_HIP(hipMemsetAsync(x32.get(), 0, tot * 4, s));
-    GmresStats st = gmres(K, false, omeps32.get(), b32.get(), x32.get(), p.rtol, p.max_iter, s, p.use_graphs != 0,
-                          warm ? 0u : GM_X0_ZERO);
+    else HM_HIP(hipMemcpyAsync(x32.get(), b32.get(), tot * 4, hipMemcpyDeviceToDevice, s));
+    GmresStats st = gmres(K, false, omeps32.get(), b32.get(), x32.get(), p.rtol, p.max_iter, s, p.use_graphs != 0);
     hipLaunchKernelGGL((k_cast<float, double>), dim3(gb_), dim3(256), 0, s, x32.get<float>(), x64.get<double>(), tot);
     R.iters = st.iters;
     R.matvecs = st.matvecs;
