@@ -58,6 +58,10 @@ template <class T> using gptr = T*;
 #endif
 template <class T> __device__ __forceinline__ gptr<const T> gbl(const T* p) { return (gptr<const T>)p; }
 template <class T> __device__ __forceinline__ gptr<T> gbl_w(T* p) { return (gptr<T>)p; }
+// Data read once per kernel and larger than the caches (factor panels):
+// non-temporal loads, which stream past the caches instead of displacing
+// the vectors that are reused.
+template <class T> __device__ __forceinline__ T ld_stream(const T* p) { return __builtin_nontemporal_load(gbl(p)); }
 
 // A descriptor that every lane of the wave reads at the same address,
 // loaded through the constant address space (scalar loads into SGPRs; the

@@ -406,6 +406,9 @@ struct EpiDev {
 // Four consecutive panel entries in their stored type (one 8-32 byte load);
 // they are converted to the vector type only when they are used, so a batch
 // of loads in flight costs the stored bytes in registers, not the widened ones.
+// The loads are non-temporal: each panel entry is read once per product
+// and the panels exceed the last-level cache, so caching them would only
+// displace the vectors and partial sums that are reused.
 using f32x4 = float __attribute__((ext_vector_type(4)));
 using f64x2 = double __attribute__((ext_vector_type(2)));
 using u32x2 = uint32_t __attribute__((ext_vector_type(2)));
@@ -413,20 +416,20 @@ using u32x2 = uint32_t __attribute__((ext_vector_type(2)));
 template <class MT> struct Quad;
 template <> struct Quad<float> {
   f32x4 v;
-  __device__ void load(const float* p) { v = *gbl(reinterpret_cast<const f32x4*>(p)); }
+  __device__ void load(const float* p) { v = ld_stream(reinterpret_cast<const f32x4*>(p)); }
   template <class VT> __device__ VT get(int e) const { return (VT)v[e]; }
 };
 template <> struct Quad<double> {
   f64x2 a, b;
   __device__ void load(const double* p) {
-    a = gbl(reinterpret_cast<const f64x2*>(p))[0];
-    b = gbl(reinterpret_cast<const f64x2*>(p))[1];
+    a = ld_stream(reinterpret_cast<const f64x2*>(p));
+    b = ld_stream(reinterpret_cast<const f64x2*>(p) + 1);
   }
   template <class VT> __device__ VT get(int e) const { return (VT)(e < 2 ? a[e] : b[e - 2]); }
 };
 template <> struct Quad<bf16_t> {
   u32x2 v;
-  __device__ void load(const bf16_t* p) { v = *gbl(reinterpret_cast<const u32x2*>(p)); }
+  __device__ void load(const bf16_t* p) { v = ld_stream(reinterpret_cast<const u32x2*>(p)); }
   template <class VT> __device__ VT get(int e) const {
     const uint32_t w = v[e >> 1];
     return (VT)bf16_to_f32((bf16_t)((e & 1) ? (w >> 16) : (w & 0xffffu)));
