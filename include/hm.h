@@ -143,6 +143,20 @@ typedef struct {
 hm_status hm_assemble_hmatrix(hm_ctx* ctx, const hm_tree* tree, const hm_assembly_params* params,
                               hm_matrix** out);
 
+/* Assembles count cavities as hm_assemble_hmatrix would one by one
+ * (trees[i] with params[i], matrix written to out[i]), with the admissible
+ * blocks of all cavities compressed in shared ACA launches, largest blocks
+ * first: the batching of Sec. 4.3's block-wise compression across cavities.
+ * Every matrix equals the one hm_assemble_hmatrix builds from the same tree
+ * and parameters (same ranks and factors), except that the cavities whose
+ * autotune flag is set share one work split of the product's first kernel,
+ * timed on their batched product (as hm_solve_radiosity_batched and
+ * hm_hmatvec_profile apply them together).  count >= 1; trees, params and out hold
+ * count entries.  On error no matrix is returned.  Runs on ctx's stream and
+ * synchronises it. */
+hm_status hm_assemble_hmatrix_batched(hm_ctx* ctx, int32_t count, const hm_tree* const* trees,
+                                      const hm_assembly_params* params, hm_matrix** out);
+
 /* bytes_device: device bytes held by the matrix; entries_dense: sum of m*n
  * over dense blocks; entries_lowrank: sum of k*(m+n) over low-rank blocks;
  * max_rank; any pointer may be NULL. */

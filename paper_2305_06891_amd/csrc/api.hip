@@ -20,6 +20,8 @@ const char* tl_error() { return g_tl_error.c_str(); }
 void set_tl_error(const std::string& m) { g_tl_error = m; }
 
 hm_matrix* assemble(hm_ctx& ctx, const hm_tree& t, const hm_assembly_params& p);
+std::vector<hm_matrix*> assemble_batch(hm_ctx& ctx, const std::vector<const hm_tree*>& trees,
+                                       const std::vector<hm_assembly_params>& ps, bool tune_jointly);
 
 // Per-matrix cache: compositions for plain products, permuted vector
 // buffers, and batched-solve state keyed by the ids of its matrices.
@@ -198,6 +200,18 @@ hm_status hm_ctx_synchronize(hm_ctx* ctx) {
   return guarded(ctx, [&] { HM_HIP(hipStreamSynchronize(ctx->stream)); });
 }
 
+namespace {
+void check_assembly_params(const hm_assembly_params* p, const char* fn) {
+  const std::string f(fn);
+  HM_REQUIRE(p->aca_tol > 0.0 && p->aca_tol < 1.0, f + ": aca_tol must be in (0, 1)");
+  HM_REQUIRE(p->k_max >= 1, f + ": k_max must be >= 1");
+  HM_REQUIRE(p->lowrank_dtype == HM_F64 || p->lowrank_dtype == HM_F32 || p->lowrank_dtype == HM_BF16,
+             f + ": bad lowrank_dtype");
+  HM_REQUIRE(p->dense_dtype == HM_F64 || p->dense_dtype == HM_F32, f + ": bad dense_dtype");
+  HM_REQUIRE(!(p->dense_dtype == HM_F64 && p->lowrank_dtype == HM_BF16), f + ": BF16 factors need FP32 near field");
+}
+}  // namespace
+
 hm_status hm_assemble_hmatrix(hm_ctx* ctx, const hm_tree* tree, const hm_assembly_params* p, hm_matrix** out) {
   if (!ctx) {
     set_tl_error("hm_assemble_hmatrix: NULL ctx");
@@ -205,16 +219,35 @@ hm_status hm_assemble_hmatrix(hm_ctx* ctx, const hm_tree* tree, const hm_assembl
   }
   return guarded(ctx, [&] {
     HM_REQUIRE(tree && p && out, "hm_assemble_hmatrix: NULL argument");
-    HM_REQUIRE(p->aca_tol > 0.0 && p->aca_tol < 1.0, "hm_assemble_hmatrix: aca_tol must be in (0, 1)");
-    HM_REQUIRE(p->k_max >= 1, "hm_assemble_hmatrix: k_max must be >= 1");
-    HM_REQUIRE(p->lowrank_dtype == HM_F64 || p->lowrank_dtype == HM_F32 || p->lowrank_dtype == HM_BF16,
-               "hm_assemble_hmatrix: bad lowrank_dtype");
-    HM_REQUIRE(p->dense_dtype == HM_F64 || p->dense_dtype == HM_F32, "hm_assemble_hmatrix: bad dense_dtype");
-    HM_REQUIRE(!(p->dense_dtype == HM_F64 && p->lowrank_dtype == HM_BF16),
-               "hm_assemble_hmatrix: BF16 factors need FP32 near field");
+    check_assembly_params(p, "hm_assemble_hmatrix");
     hm_matrix* M = assemble(*ctx, *tree, *p);
     M->id = g_next_id++;
     *out = M;
+  });
+}
+
+hm_status hm_assemble_hmatrix_batched(hm_ctx* ctx, int32_t count, const hm_tree* const* trees,
+                                      const hm_assembly_params* params, hm_matrix** out) {
+  if (!ctx) {
+    set_tl_error("hm_assemble_hmatrix_batched: NULL ctx");
+    return HM_EINVAL;
+  }
+  return guarded(ctx, [&] {
+    HM_REQUIRE(count >= 1, "hm_assemble_hmatrix_batched: count must be >= 1");
+    HM_REQUIRE(trees && params && out, "hm_assemble_hmatrix_batched: NULL argument");
+    std::vector<const hm_tree*> ts(count);
+    std::vector<hm_assembly_params> ps(count);
+    for (int32_t i = 0; i < count; ++i) {
+      HM_REQUIRE(trees[i], "hm_assemble_hmatrix_batched: NULL tree");
+      check_assembly_params(params + i, "hm_assemble_hmatrix_batched");
+      ts[i] = trees[i];
+      ps[i] = params[i];
+    }
+    std::vector<hm_matrix*> ms = assemble_batch(*ctx, ts, ps, true);
+    for (int32_t i = 0; i < count; ++i) {
+      ms[i]->id = g_next_id++;
+      out[i] = ms[i];
+    }
   });
 }
 

@@ -40,6 +40,7 @@ struct AcaDev {
   int32_t rb, re, cb, ce;
   int32_t kcap, out;            // rank cap; index of the block's rank/status outputs
   int64_t u_off, v_off, f_off;  // scratch offsets (doubles, doubles, ints)
+  double tol;                   // relative ACA tolerance of the block's cavity
 };
 
 constexpr int ACA_T = 256;
@@ -100,13 +101,14 @@ __device__ void block_sum(double* v, double* sh) {
 // holds k and status[b] is 1 when the stop test |u||v| <= tol |sum u v^T|_F
 // was met (0 when the rank cap was reached first).
 #pragma clang fp contract(off)
-__global__ __launch_bounds__(ACA_T) void k_aca(const AcaDev* __restrict__ blocks, Geo g, double tol,
+__global__ __launch_bounds__(ACA_T) void k_aca(const AcaDev* __restrict__ blocks, Geo g,
                                                double* __restrict__ scratch, int* __restrict__ flags,
                                                int* __restrict__ rank, int* __restrict__ status) {
   __shared__ double coef[ACA_KMAX];
   __shared__ ArgMax sh_am[ACA_W];
   __shared__ double sh_sum[ACA_W * 16];
   const AcaDev b = blocks[blockIdx.x];
+  const double tol = b.tol;
   const int m = b.re - b.rb, n = b.ce - b.cb;
   double* U = scratch + b.u_off;
   double* V = scratch + b.v_off;
@@ -252,13 +254,14 @@ __device__ __forceinline__ double view_factor_r(double icx, double icy, double i
   return r2 > 0.0 ? num / den : 0.0;
 }
 
-__global__ __launch_bounds__(256) void k_aca_wave(const AcaDev* __restrict__ blocks, int nblk, Geo g, double tol,
+__global__ __launch_bounds__(256) void k_aca_wave(const AcaDev* __restrict__ blocks, int nblk, Geo g,
                                                   double* __restrict__ scratch, int* __restrict__ rank,
                                                   int* __restrict__ status) {
   const int lane = threadIdx.x & 63;
   const int bi = blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   if (bi >= nblk) return;
   const AcaDev b = uniform_load(blocks + bi);
+  const double tol = b.tol;
   const int m = b.re - b.rb, n = b.ce - b.cb;
   // geometry of the lane's row (rows past m repeat the last) and column
   const int ri = b.rb + min(lane, m - 1), cj = b.cb + min(lane, n - 1);
@@ -471,133 +474,30 @@ void dispatch_dtype(hm_dtype t, F&& f) {
 
 void closed_row_scale(hm_matrix& M, hipStream_t s);
 
-hm_matrix* assemble(hm_ctx& ctx, const hm_tree& t, const hm_assembly_params& p) {
-  hipStream_t s = ctx.stream;
-  const int64_t n = t.n;
-  auto M = std::make_unique<hm_matrix>();
-  M->device = ctx.device;
-  M->n = n;
-  M->dense_dtype = p.dense_dtype;
-  M->lr_dtype = p.lowrank_dtype;
-  M->has_hi = p.lowrank_dtype == HM_BF16 && p.keep_f32_copy;
-  M->perm = t.perm;
-  upload(M->d_perm, M->perm, s);
+namespace {
 
-  // permuted geometry, SoA FP64
-  std::vector<double> geo(7 * n);
-  for (int64_t k = 0; k < n; ++k) {
-    const int64_t o = t.perm[k];
-    for (int a = 0; a < 3; ++a) {
-      geo[a * n + k] = t.c[3 * o + a];
-      geo[(3 + a) * n + k] = t.nrm[3 * o + a];
-    }
-    geo[6 * n + k] = t.area[o];
-  }
-  DevBuf d_geo;
-  upload(d_geo, geo, s);
-  const double* gp = d_geo.get<double>();
-  Geo g{gp, gp + n, gp + 2 * n, gp + 3 * n, gp + 4 * n, gp + 5 * n, gp + 6 * n};
-
-  // ---- ACA on the admissible blocks, in batches bounded by a scratch budget
-  const int kmax = std::min<int>(p.k_max, ACA_KMAX);
-  const bool st64 = p.lowrank_dtype == HM_F64;
-  const size_t ses = st64 ? 8 : 4;
-  size_t free_b = 0, total_b = 0;
-  HM_HIP(hipMemGetInfo(&free_b, &total_b));
-  const int64_t budget = std::max<int64_t>(256ll << 20, std::min<int64_t>(8ll << 30, (int64_t)free_b / 4));
+// One cavity of an assembly call.
+struct AsmJob {
+  const hm_tree* t = nullptr;
+  hm_assembly_params p{};
+  std::unique_ptr<hm_matrix> M;
+  int64_t goff = 0;  // first facet of the cavity in the shared geometry arrays
+  Geo g{};           // the cavity's geometry (pointers into the shared arrays)
   std::vector<LrInfo> lr;
-  std::vector<BlockRef> dn(t.dense.begin(), t.dense.end());
-  std::vector<DevBuf> stages;
-  DevBuf scratch, flags, d_blk, d_blk_small, d_rank, d_status, d_cd;
-  size_t pos = 0;
-  while (pos < t.lowrank.size()) {
-    std::vector<AcaDev> batch;
-    int64_t sd = 0, sf = 0;
-    while (pos < t.lowrank.size()) {
-      const BlockRef& b = t.lowrank[pos];
-      const int m = b.re - b.rb, nn = b.ce - b.cb;
-      const int64_t kc = rank_cap(m, nn, kmax);
-      const int64_t need = kc * (m + nn) * 8 + m * 4;
-      if (!batch.empty() && (sd * 8 + sf * 4 + need) > budget) break;
-      AcaDev a{b.rb, b.re, b.cb, b.ce, (int32_t)kc, 0, sd, sd + kc * m, sf};
-      sd += kc * (m + nn);
-      sf += m;
-      batch.push_back(a);
-      ++pos;
-    }
-    // blocks of at most 64 x 64 (rank cap <= 32): one wave each; larger ones:
-    // one workgroup each, largest first for the hardware dispatcher
-    std::vector<AcaDev> small, large;
-    for (size_t q = 0; q < batch.size(); ++q) {
-      batch[q].out = (int32_t)q;
-      const AcaDev& a = batch[q];
-      if (a.re - a.rb <= 64 && a.ce - a.cb <= 64 && a.kcap <= ACAW_K) small.push_back(a);
-      else large.push_back(a);
-    }
-    std::stable_sort(large.begin(), large.end(), [](const AcaDev& x, const AcaDev& y) {
-      return (int64_t)(x.re - x.rb) * (x.ce - x.cb) > (int64_t)(y.re - y.rb) * (y.ce - y.cb);
-    });
-    if ((size_t)sd * 8 > scratch.bytes()) scratch.alloc((size_t)sd * 8);
-    if ((size_t)sf * 4 > flags.bytes()) flags.alloc((size_t)sf * 4);
-    d_rank.alloc(batch.size() * 4);
-    d_status.alloc(batch.size() * 4);
-    if (!large.empty()) {
-      upload(d_blk, large, s);
-      hipLaunchKernelGGL(k_aca, dim3((unsigned)large.size()), dim3(ACA_T), 0, s, d_blk.get<AcaDev>(), g, p.aca_tol,
-                         scratch.get<double>(), flags.get<int>(), d_rank.get<int>(), d_status.get<int>());
-      HM_HIP(hipGetLastError());
-    }
-    if (!small.empty()) {
-      upload(d_blk_small, small, s);
-      hipLaunchKernelGGL(k_aca_wave, dim3((unsigned)((small.size() + 3) / 4)), dim3(256), 0, s,
-                         d_blk_small.get<AcaDev>(), (int)small.size(), g, p.aca_tol, scratch.get<double>(),
-                         d_rank.get<int>(), d_status.get<int>());
-      HM_HIP(hipGetLastError());
-    }
-    std::vector<int> rk(batch.size()), st(batch.size());
-    HM_HIP(hipMemcpyAsync(rk.data(), d_rank.get(), rk.size() * 4, hipMemcpyDeviceToHost, s));
-    HM_HIP(hipMemcpyAsync(st.data(), d_status.get(), st.size() * 4, hipMemcpyDeviceToHost, s));
-    HM_HIP(hipStreamSynchronize(s));
-    // classify: low rank (converged and k(m+n) < mn), rank zero (dropped), dense fallback
-    std::vector<CompactDev> cd;
-    int64_t off = 0;
-    for (size_t q = 0; q < batch.size(); ++q) {
-      const AcaDev& a = batch[q];
-      const int m = a.re - a.rb, nn = a.ce - a.cb;
-      const int k = rk[q];
-      BlockRef br{a.rb, a.re, a.cb, a.ce};
-      if (!st[q] || (int64_t)k * (m + nn) >= (int64_t)m * nn) {
-        dn.push_back(br);
-        M->n_fallback++;
-        continue;
-      }
-      if (k == 0) continue;  // exactly zero block
-      cd.push_back(CompactDev{a.u_off, a.v_off, off, off + (int64_t)m * k, m, nn, k, 0});
-      lr.push_back(LrInfo{br, k, (int32_t)stages.size(), off, off + (int64_t)m * k});
-      off += (int64_t)k * (m + nn);
-    }
-    DevBuf stg;
-    if (!cd.empty()) {
-      stg.alloc(off * ses);
-      upload(d_cd, cd, s);
-      if (st64)
-        hipLaunchKernelGGL(k_compact<double>, dim3((unsigned)cd.size()), dim3(256), 0, s, d_cd.get<CompactDev>(),
-                           scratch.get<double>(), stg.get<double>());
-      else
-        hipLaunchKernelGGL(k_compact<float>, dim3((unsigned)cd.size()), dim3(256), 0, s, d_cd.get<CompactDev>(),
-                           scratch.get<double>(), stg.get<float>());
-      HM_HIP(hipGetLastError());
-      HM_HIP(hipStreamSynchronize(s));  // scratch is reused by the next batch
-    }
-    stages.push_back(std::move(stg));
-  }
-  scratch.release();
-  flags.release();
+  std::vector<BlockRef> dn;
+  size_t lr_done = 0;  // admissible blocks of the cavity whose ACA has finished
+};
+
+// Near-field packing, panel packing of the compacted factors, statistics and
+// the product plan of a cavity whose ACA blocks are all done.
+void finish_job(AsmJob& J, const std::vector<DevBuf>& stages, hipStream_t s) {
+  hm_matrix* M = J.M.get();
+  const hm_assembly_params& p = J.p;
+  auto& dn = J.dn;
+  auto& lr = J.lr;
   std::sort(dn.begin(), dn.end(), [](const BlockRef& x, const BlockRef& y) {
     return x.rb != y.rb ? x.rb < y.rb : x.cb < y.cb;
   });
-
-  // ---- statistics
   for (const auto& d : dn) M->dense_entries += (int64_t)(d.re - d.rb) * (d.ce - d.cb);
   M->n_dense_blocks = (int64_t)dn.size();
   M->n_lr_blocks = (int64_t)lr.size();
@@ -611,7 +511,7 @@ hm_matrix* assemble(hm_ctx& ctx, const hm_tree& t, const hm_assembly_params& p) 
 
   // ---- plan, panel arenas, packing
   PackLists pk;
-  build_plan(*M, lr, dn, t, pk, s);
+  build_plan(*M, lr, dn, *J.t, pk, s);
   const Plan& P = M->plan;
   const size_t ds = dtype_size(p.dense_dtype), ls = dtype_size(p.lowrank_dtype);
   M->dense.alloc(std::max<int64_t>(1, P.dense_elems) * ds);
@@ -630,10 +530,10 @@ hm_matrix* assemble(hm_ctx& ctx, const hm_tree& t, const hm_assembly_params& p) 
     DevBuf d_nf;
     upload(d_nf, pk.nf, s);
     if (p.dense_dtype == HM_F64)
-      hipLaunchKernelGGL(k_nf_pack<double>, dim3((unsigned)pk.nf.size()), dim3(256), 0, s, d_nf.get<NfDev>(), g,
+      hipLaunchKernelGGL(k_nf_pack<double>, dim3((unsigned)pk.nf.size()), dim3(256), 0, s, d_nf.get<NfDev>(), J.g,
                          M->dense.get<double>());
     else
-      hipLaunchKernelGGL(k_nf_pack<float>, dim3((unsigned)pk.nf.size()), dim3(256), 0, s, d_nf.get<NfDev>(), g,
+      hipLaunchKernelGGL(k_nf_pack<float>, dim3((unsigned)pk.nf.size()), dim3(256), 0, s, d_nf.get<NfDev>(), J.g,
                          M->dense.get<float>());
     HM_HIP(hipGetLastError());
     HM_HIP(hipStreamSynchronize(s));
@@ -663,11 +563,207 @@ hm_matrix* assemble(hm_ctx& ctx, const hm_tree& t, const hm_assembly_params& p) 
     HM_HIP(hipGetLastError());
     HM_HIP(hipStreamSynchronize(s));
   }
-  stages.clear();
   if (p.closed_row_scale) closed_row_scale(*M, s);
-  if (p.autotune) autotune_phase1(*M, s);
+}
+
+}  // namespace
+
+// Assembles every cavity of `trees` (Sec. 4.3): the admissible blocks of all
+// of them go through shared ACA launches (largest blocks first, one wave per
+// small block), then each cavity is packed as soon as its blocks are done.
+// Each block's ACA depends only on the block, so a matrix is the same whether
+// its cavity is assembled alone or with others.  With tune_jointly, the
+// matrices whose autotune flag is set get one phase-1 split, timed on their
+// batched product; otherwise each such matrix is tuned alone.
+std::vector<hm_matrix*> assemble_batch(hm_ctx& ctx, const std::vector<const hm_tree*>& trees,
+                                       const std::vector<hm_assembly_params>& ps, bool tune_jointly) {
+  hipStream_t s = ctx.stream;
+  const size_t nj = trees.size();
+  std::vector<AsmJob> jobs(nj);
+  int64_t ntot = 0;
+  for (size_t j = 0; j < nj; ++j) {
+    AsmJob& J = jobs[j];
+    J.t = trees[j];
+    J.p = ps[j];
+    J.goff = ntot;
+    ntot += J.t->n;
+    HM_REQUIRE(ntot < ((int64_t)1 << 31), "assemble: more than 2^31 facets in one call");
+    J.M = std::make_unique<hm_matrix>();
+    hm_matrix* M = J.M.get();
+    M->device = ctx.device;
+    M->n = J.t->n;
+    M->dense_dtype = J.p.dense_dtype;
+    M->lr_dtype = J.p.lowrank_dtype;
+    M->has_hi = J.p.lowrank_dtype == HM_BF16 && J.p.keep_f32_copy;
+    M->perm = J.t->perm;
+    upload(M->d_perm, M->perm, s);
+    J.dn.assign(J.t->dense.begin(), J.t->dense.end());
+  }
+
+  // permuted geometry of all cavities, SoA FP64, one array per quantity
+  std::vector<double> geo(7 * std::max<int64_t>(1, ntot));
+  for (const AsmJob& J : jobs) {
+    const hm_tree& t = *J.t;
+    for (int64_t k = 0; k < t.n; ++k) {
+      const int64_t o = t.perm[k], d = J.goff + k;
+      for (int a = 0; a < 3; ++a) {
+        geo[a * ntot + d] = t.c[3 * o + a];
+        geo[(3 + a) * ntot + d] = t.nrm[3 * o + a];
+      }
+      geo[6 * ntot + d] = t.area[o];
+    }
+  }
+  DevBuf d_geo;
+  upload(d_geo, geo, s);
+  const double* gp = d_geo.get<double>();
+  const Geo g{gp, gp + ntot, gp + 2 * ntot, gp + 3 * ntot, gp + 4 * ntot, gp + 5 * ntot, gp + 6 * ntot};
+  for (AsmJob& J : jobs) {
+    const int64_t o = J.goff;
+    J.g = Geo{g.cx + o, g.cy + o, g.cz + o, g.nx + o, g.ny + o, g.nz + o, g.ar + o};
+  }
+
+  // ---- ACA on the admissible blocks of all cavities, in batches bounded by
+  // a scratch budget; block indices address the shared geometry
+  size_t free_b = 0, total_b = 0;
+  HM_HIP(hipMemGetInfo(&free_b, &total_b));
+  const int64_t budget = std::max<int64_t>(256ll << 20, std::min<int64_t>(8ll << 30, (int64_t)free_b / 4));
+  std::vector<DevBuf> stages;
+  std::vector<size_t> stage_last;  // last job with factors in each stage buffer
+  DevBuf scratch, flags, d_blk, d_blk_small, d_rank, d_status, d_cd;
+  size_t jpos = 0, bpos = 0, next_finish = 0;
+  auto finish_ready = [&]() {
+    while (next_finish < nj && jobs[next_finish].lr_done == jobs[next_finish].t->lowrank.size()) {
+      finish_job(jobs[next_finish], stages, s);
+      // stage buffers no later cavity reads
+      for (size_t q = 0; q < stages.size(); ++q)
+        if (stage_last[q] <= next_finish) stages[q].release();
+      ++next_finish;
+    }
+  };
+  finish_ready();
+  while (next_finish < nj) {
+    std::vector<AcaDev> batch;
+    std::vector<int32_t> bjob;  // job of each batch entry
+    int64_t sd = 0, sf = 0;
+    while (jpos < nj) {
+      const AsmJob& J = jobs[jpos];
+      if (bpos == J.t->lowrank.size()) {
+        ++jpos;
+        bpos = 0;
+        continue;
+      }
+      const BlockRef& b = J.t->lowrank[bpos];
+      const int m = b.re - b.rb, nn = b.ce - b.cb;
+      const int64_t kc = rank_cap(m, nn, std::min<int>(J.p.k_max, ACA_KMAX));
+      const int64_t need = kc * (m + nn) * 8 + m * 4;
+      if (!batch.empty() && (sd * 8 + sf * 4 + need) > budget) break;
+      const int32_t o = (int32_t)J.goff;
+      batch.push_back(AcaDev{b.rb + o, b.re + o, b.cb + o, b.ce + o, (int32_t)kc, 0, sd, sd + kc * m, sf, J.p.aca_tol});
+      bjob.push_back((int32_t)jpos);
+      sd += kc * (m + nn);
+      sf += m;
+      ++bpos;
+    }
+    HM_REQUIRE(!batch.empty(), "assemble: empty ACA batch");
+    // blocks of at most 64 x 64 (rank cap <= 32): one wave each; larger ones:
+    // one workgroup each, largest first for the hardware dispatcher
+    std::vector<AcaDev> small, large;
+    for (size_t q = 0; q < batch.size(); ++q) {
+      batch[q].out = (int32_t)q;
+      const AcaDev& a = batch[q];
+      if (a.re - a.rb <= 64 && a.ce - a.cb <= 64 && a.kcap <= ACAW_K) small.push_back(a);
+      else large.push_back(a);
+    }
+    std::stable_sort(large.begin(), large.end(), [](const AcaDev& x, const AcaDev& y) {
+      return (int64_t)(x.re - x.rb) * (x.ce - x.cb) > (int64_t)(y.re - y.rb) * (y.ce - y.cb);
+    });
+    if ((size_t)sd * 8 > scratch.bytes()) scratch.alloc((size_t)sd * 8);
+    if ((size_t)sf * 4 > flags.bytes()) flags.alloc((size_t)sf * 4);
+    d_rank.alloc(batch.size() * 4);
+    d_status.alloc(batch.size() * 4);
+    if (!large.empty()) {
+      upload(d_blk, large, s);
+      hipLaunchKernelGGL(k_aca, dim3((unsigned)large.size()), dim3(ACA_T), 0, s, d_blk.get<AcaDev>(), g,
+                         scratch.get<double>(), flags.get<int>(), d_rank.get<int>(), d_status.get<int>());
+      HM_HIP(hipGetLastError());
+    }
+    if (!small.empty()) {
+      upload(d_blk_small, small, s);
+      hipLaunchKernelGGL(k_aca_wave, dim3((unsigned)((small.size() + 3) / 4)), dim3(256), 0, s,
+                         d_blk_small.get<AcaDev>(), (int)small.size(), g, scratch.get<double>(),
+                         d_rank.get<int>(), d_status.get<int>());
+      HM_HIP(hipGetLastError());
+    }
+    std::vector<int> rk(batch.size()), st(batch.size());
+    HM_HIP(hipMemcpyAsync(rk.data(), d_rank.get(), rk.size() * 4, hipMemcpyDeviceToHost, s));
+    HM_HIP(hipMemcpyAsync(st.data(), d_status.get(), st.size() * 4, hipMemcpyDeviceToHost, s));
+    HM_HIP(hipStreamSynchronize(s));
+    // classify: low rank (converged and k(m+n) < mn), rank zero (dropped),
+    // dense fallback; factors compacted per stored precision (FP64 stage for
+    // FP64 factors, FP32 otherwise)
+    std::vector<CompactDev> cd[2];
+    int64_t off[2] = {0, 0};
+    int32_t sidx[2] = {-1, -1};
+    for (int w = 0; w < 2; ++w) {
+      sidx[w] = (int32_t)stages.size();
+      stages.emplace_back();
+      stage_last.push_back(0);
+    }
+    for (size_t q = 0; q < batch.size(); ++q) {
+      const AcaDev& a = batch[q];
+      AsmJob& J = jobs[bjob[q]];
+      const int32_t o = (int32_t)J.goff;
+      const int m = a.re - a.rb, nn = a.ce - a.cb;
+      const int k = rk[q];
+      BlockRef br{a.rb - o, a.re - o, a.cb - o, a.ce - o};
+      J.lr_done++;
+      if (!st[q] || (int64_t)k * (m + nn) >= (int64_t)m * nn) {
+        J.dn.push_back(br);
+        J.M->n_fallback++;
+        continue;
+      }
+      if (k == 0) continue;  // exactly zero block
+      const int w = J.p.lowrank_dtype == HM_F64 ? 1 : 0;
+      cd[w].push_back(CompactDev{a.u_off, a.v_off, off[w], off[w] + (int64_t)m * k, m, nn, k, 0});
+      J.lr.push_back(LrInfo{br, k, sidx[w], off[w], off[w] + (int64_t)m * k});
+      off[w] += (int64_t)k * (m + nn);
+      stage_last[sidx[w]] = std::max<size_t>(stage_last[sidx[w]], (size_t)bjob[q]);
+    }
+    for (int w = 0; w < 2; ++w) {
+      if (cd[w].empty()) continue;
+      DevBuf& stg = stages[sidx[w]];
+      stg.alloc(off[w] * (w ? 8 : 4));
+      upload(d_cd, cd[w], s);
+      if (w)
+        hipLaunchKernelGGL(k_compact<double>, dim3((unsigned)cd[w].size()), dim3(256), 0, s,
+                           d_cd.get<CompactDev>(), scratch.get<double>(), stg.get<double>());
+      else
+        hipLaunchKernelGGL(k_compact<float>, dim3((unsigned)cd[w].size()), dim3(256), 0, s,
+                           d_cd.get<CompactDev>(), scratch.get<double>(), stg.get<float>());
+      HM_HIP(hipGetLastError());
+      HM_HIP(hipStreamSynchronize(s));  // scratch is reused by the next batch
+    }
+    finish_ready();
+  }
+  scratch.release();
+  flags.release();
+  stages.clear();
+
+  // ---- phase-1 split
+  std::vector<hm_matrix*> tuned;
+  for (AsmJob& J : jobs)
+    if (J.p.autotune) tuned.push_back(J.M.get());
+  if (tune_jointly && tuned.size() > 1) autotune_phase1_joint(tuned, s);
+  else
+    for (hm_matrix* M : tuned) autotune_phase1(*M, s);
   HM_HIP(hipStreamSynchronize(s));
-  return M.release();
+  std::vector<hm_matrix*> out(nj);
+  for (size_t j = 0; j < nj; ++j) out[j] = jobs[j].M.release();
+  return out;
+}
+
+hm_matrix* assemble(hm_ctx& ctx, const hm_tree& t, const hm_assembly_params& p) {
+  return assemble_batch(ctx, {&t}, {p}, false)[0];
 }
 
 // Closed-cavity treatment (eqs. (32)-(34)): s = F_H 1 (the per-area row sum),

@@ -298,6 +298,9 @@ void replan_phase1(hm_matrix& M, const P1Params& pp, hipStream_t s);
 // Times the candidate phase-1 splits on M (FP32 vectors unless the factors
 // are FP64) and keeps the fastest.  Call before any composition of M exists.
 void autotune_phase1(hm_matrix& M, hipStream_t s);
+// The same for several matrices multiplied together: one split for all,
+// timed on their batched product.
+void autotune_phase1_joint(const std::vector<hm_matrix*>& mats, hipStream_t s);
 // The host part of build_plan (no device calls): items, tasks, arena sizes.
 void plan_host(hm_matrix& M, const std::vector<struct LrInfo>& lr, const std::vector<BlockRef>& dn,
                const hm_tree& t, PackLists& pk);

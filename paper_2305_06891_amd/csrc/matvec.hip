@@ -262,22 +262,31 @@ __global__ void k_tune_flush(const float4* __restrict__ p, int64_t n4, float* __
   if (acc != acc) sink[0] = acc;
 }
 
-void autotune_phase1(hm_matrix& M, hipStream_t s) {
-  if (M.plan.taus.empty()) return;
-  const int vb = M.lr_dtype == HM_F64 ? 8 : 4;
-  const int64_t n = M.n;
-  const int64_t vbytes = M.v_entries * (int64_t)dtype_size(M.lr_dtype);
-  // matrices whose factors could stay in the last-level cache are timed
-  // after a read of 512 MB, as in the solve where phase 2 runs in between
+void autotune_phase1_joint(const std::vector<hm_matrix*>& mats, hipStream_t s) {
+  std::vector<hm_matrix*> ms;
+  for (hm_matrix* M : mats)
+    if (!M->plan.taus.empty()) ms.push_back(M);
+  if (ms.empty()) return;
+  // FP64 vectors only when every matrix stores FP64 factors
+  const bool all64 = std::all_of(ms.begin(), ms.end(), [](const hm_matrix* M) { return M->lr_dtype == HM_F64; });
+  const int vb = all64 ? 8 : 4;
+  int64_t n = 0, vbytes = 0;
+  for (const hm_matrix* M : ms) {
+    n += M->n;
+    vbytes += M->v_entries * (int64_t)dtype_size(M->lr_dtype);
+  }
+  // factors that could stay in the last-level cache are timed after a read
+  // of 512 MB, as in the solve where phase 2 runs in between
   const int64_t flush_bytes = vbytes > (16 << 20) ? (int64_t)512 << 20 : 0;
   DevBuf X((size_t)n * vb), Y((size_t)n * vb), flush(flush_bytes), sink(16);
   HM_HIP(hipMemsetAsync(X.get(), 0, (size_t)n * vb, s));
   if (flush_bytes) HM_HIP(hipMemsetAsync(flush.get(), 0, (size_t)flush_bytes, s));
+  const std::vector<const hm_matrix*> cms(ms.begin(), ms.end());
   hipEvent_t ev[3];
   for (auto& e : ev) HM_HIP(hipEventCreate(&e));
   const int rows[] = {64, 128, 256};
   const int task[] = {0, 8 << 10, 16 << 10, 32 << 10, 64 << 10};
-  P1Params best = M.plan.p1p;
+  P1Params best = ms[0]->plan.p1p;
   double best_us = 1e30;
   try {
     for (int r : rows)
@@ -285,8 +294,8 @@ void autotune_phase1(hm_matrix& M, hipStream_t s) {
         P1Params pp;
         pp.rows = r;
         pp.task_bytes = tb;
-        replan_phase1(M, pp, s);
-        auto comp = make_composition({&M}, 1, vb, s);
+        for (hm_matrix* M : ms) replan_phase1(*M, pp, s);
+        auto comp = make_composition(cms, 1, vb, s);
         double tot = 0;
         const int reps = 6;
         for (int k = 0; k < reps + 1; ++k) {
@@ -310,9 +319,13 @@ void autotune_phase1(hm_matrix& M, hipStream_t s) {
     throw;
   }
   for (auto& e : ev) HM_HIP(hipEventDestroy(e));
-  replan_phase1(M, best, s);
-  M.plan.p1_us = best_us;
+  for (hm_matrix* M : ms) {
+    replan_phase1(*M, best, s);
+    M->plan.p1_us = best_us;
+  }
 }
+
+void autotune_phase1(hm_matrix& M, hipStream_t s) { autotune_phase1_joint({&M}, s); }
 
 int64_t matrix_bytes(const hm_matrix& M, bool hi) {
   const size_t dsz = dtype_size(M.dense_dtype);

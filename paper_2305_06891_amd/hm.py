@@ -91,6 +91,8 @@ _PROTOS = {
     "hm_tree_blocks": (C.c_int, [_vp, _ip, _ip]),
     "hm_tree_destroy": (None, [_vp]),
     "hm_assemble_hmatrix": (C.c_int, [_vp, _vp, C.POINTER(hm_assembly_params), C.POINTER(_vp)]),
+    "hm_assemble_hmatrix_batched": (C.c_int, [_vp, C.c_int32, C.POINTER(_vp), C.POINTER(hm_assembly_params),
+                                              C.POINTER(_vp)]),
     "hm_matrix_stats": (C.c_int, [_vp, C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.POINTER(C.c_int64),
                                   C.POINTER(C.c_int32)]),
     "hm_matrix_info": (C.c_int, [_vp, C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.POINTER(C.c_int64),
@@ -302,6 +304,30 @@ def hm_assemble_hmatrix(ctx, tree: Tree, aca_tol=1e-6, k_max=256, lowrank_dtype=
     h = _vp()
     _check(lib.hm_assemble_hmatrix(ctx.handle, tree._h, C.byref(p), C.byref(h)), ctx.handle)
     return HMatrix(h, ctx)
+
+
+def hm_assemble_hmatrix_batched(ctx, trees, aca_tol=1e-6, k_max=256, lowrank_dtype=HM_F32, dense_dtype=HM_F32,
+                                keep_f32_copy=0, closed_row_scale=0, autotune=0):
+    """Matrices of several cavities assembled together (shared ACA launches;
+    with autotune, one product split tuned on their batched product).  Every
+    parameter is a scalar for all cavities or a sequence with one entry per
+    tree."""
+    trees = list(trees)
+    k = len(trees)
+
+    def each(v):
+        return list(v) if isinstance(v, (list, tuple)) else [v] * k
+
+    cols = [each(aca_tol), each(k_max), each(lowrank_dtype), each(dense_dtype), each(keep_f32_copy),
+            each(closed_row_scale), each(autotune)]
+    if any(len(c) != k for c in cols):
+        raise ValueError("one parameter value per tree expected")
+    ps = (hm_assembly_params * k)(*[hm_assembly_params(float(a), int(b), int(c), int(d), int(e), int(f), int(g))
+                                    for a, b, c, d, e, f, g in zip(*cols)])
+    ts = (_vp * k)(*[t._h for t in trees])
+    hs = (_vp * k)()
+    _check(lib.hm_assemble_hmatrix_batched(ctx.handle, k, ts, ps, hs), ctx.handle)
+    return [HMatrix(_vp(h), ctx) for h in hs]
 
 
 def hm_hmatvec(ctx, M: HMatrix, X, Y, alpha=1.0, beta=0.0, use_f32_copy=False):
