@@ -96,11 +96,28 @@ __device__ void block_sum(double* v, double* sh) {
   }
 }
 
+#pragma clang fp contract(off)
+// r - sum_{l < k} c[l] P[l ld + j], subtracted one term at a time in the order
+// of l; the loads go out eight at a time so their latencies overlap (the
+// same operations as the plain loop, so the same result bit for bit).
+__device__ __forceinline__ double sub_terms(double r, const double* c, const double* __restrict__ P, int64_t ld,
+                                            int j, int k) {
+  int l = 0;
+  for (; l + 8 <= k; l += 8) {
+    double v[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) v[q] = P[(int64_t)(l + q) * ld + j];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) r = r - c[l + q] * v[q];
+  }
+  for (; l < k; ++l) r = r - c[l] * P[(int64_t)l * ld + j];
+  return r;
+}
+
 // Partial-pivoting ACA of one admissible block per workgroup, in FP64.
 // U (m x kcap) and V (n x kcap) are column-major scratch; on exit rank[b]
 // holds k and status[b] is 1 when the stop test |u||v| <= tol |sum u v^T|_F
 // was met (0 when the rank cap was reached first).
-#pragma clang fp contract(off)
 __global__ __launch_bounds__(ACA_T) void k_aca(const AcaDev* __restrict__ blocks, Geo g,
                                                double* __restrict__ scratch, int* __restrict__ flags,
                                                int* __restrict__ rank, int* __restrict__ status) {
@@ -127,8 +144,7 @@ __global__ __launch_bounds__(ACA_T) void k_aca(const AcaDev* __restrict__ blocks
     ArgMax am{-1.0, 0.0, 0x7fffffff};
     double* vk = V + (int64_t)k * n;
     for (int j = tid; j < n; j += ACA_T) {
-      double r = view_factor(g, b.rb + i, b.cb + j);
-      for (int l = 0; l < k; ++l) r = r - coef[l] * V[(int64_t)l * n + j];
+      const double r = sub_terms(view_factor(g, b.rb + i, b.cb + j), coef, V, n, j, k);
       vk[j] = r;
       const double a = fabs(r);
       if (a > am.mag || (a == am.mag && j < am.idx)) am = ArgMax{a, r, j};
@@ -159,8 +175,7 @@ __global__ __launch_bounds__(ACA_T) void k_aca(const AcaDev* __restrict__ blocks
     ArgMax nx{-1.0, 0.0, 0x7fffffff};
     double nu2 = 0.0, nv2 = 0.0;
     for (int ii = tid; ii < m; ii += ACA_T) {
-      double u = view_factor(g, b.rb + ii, b.cb + jp);
-      for (int l = 0; l < k; ++l) u = u - coef[l] * U[(int64_t)l * m + ii];
+      const double u = sub_terms(view_factor(g, b.rb + ii, b.cb + jp), coef, U, m, ii, k);
       uk[ii] = u;
       nu2 += u * u;
       if (!used[ii]) {
