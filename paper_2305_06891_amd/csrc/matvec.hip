@@ -429,11 +429,13 @@ using u32x2 = uint32_t __attribute__((ext_vector_type(2)));
 template <class MT> struct Quad;
 template <> struct Quad<float> {
   f32x4 v;
+  __device__ void zero() { v = f32x4{0.f, 0.f, 0.f, 0.f}; }
   __device__ void load(const float* p) { v = ld_stream(reinterpret_cast<const f32x4*>(p)); }
   template <class VT> __device__ VT get(int e) const { return (VT)v[e]; }
 };
 template <> struct Quad<double> {
   f64x2 a, b;
+  __device__ void zero() { a = b = f64x2{0.0, 0.0}; }
   __device__ void load(const double* p) {
     a = ld_stream(reinterpret_cast<const f64x2*>(p));
     b = ld_stream(reinterpret_cast<const f64x2*>(p) + 1);
@@ -442,6 +444,7 @@ template <> struct Quad<double> {
 };
 template <> struct Quad<bf16_t> {
   u32x2 v;
+  __device__ void zero() { v = u32x2{0u, 0u}; }
   __device__ void load(const bf16_t* p) { v = ld_stream(reinterpret_cast<const u32x2*>(p)); }
   template <class VT> __device__ VT get(int e) const {
     const uint32_t w = v[e >> 1];
@@ -678,10 +681,10 @@ __device__ __forceinline__ double lane_bcast(double v, int l) {
 // = sum_r V(r, l) x(xrow + r).  The rows of an item go in batches of UN
 // quads (about 8 KB per wave whatever the stored type): the x entries of a
 // batch come with one coalesced load (lane = row) and reach every lane by
-// lane broadcast.  The loads of the next batch are issued before the
-// current one is used, so each wave keeps two batches in flight; rows past
-// the item's end re-read its last quad and meet x = 0, so no load sits
-// behind a branch.
+// lane broadcast.  The loads of the next full batch are issued before the
+// current one is used, so each wave keeps two batches in flight (no load of
+// a full batch sits behind a branch); an item's last, partial batch loads
+// its quads in groups of four, and rows past the item meet x = 0.
 template <class LT>
 constexpr int p1_batch_quads() {
   return (int)(128 / sizeof(Quad<LT>));
@@ -704,6 +707,28 @@ __device__ __forceinline__ void p1_issue(P1Batch<LT, VT, NR, UN>& b, const LT* a
   for (int j = 0; j < NR; ++j) b.x[j] = gbl(xr)[rr + (int64_t)min(j, nrr - 1) * ldx];
 #pragma unroll
   for (int u = 0; u < UN; ++u) b.v[u].load(a + (int64_t)min(qb + u, qe - 1) * step);
+}
+
+// The last, partial batch of an item: its quads are loaded in groups of
+// four (uniform branches), so at most three quads past the item are read.
+template <class LT, class VT, int NR, int UN>
+__device__ __forceinline__ void p1_issue_tail(P1Batch<LT, VT, NR, UN>& b, const LT* a, int64_t step, int qb, int qe,
+                                              const VT* xr, int64_t ldx, int nrr, int nrows, int lane) {
+  const int row = qb * 4 + lane;
+  b.ok = lane < 4 * UN && row < 4 * qe && row < nrows;
+  const int rr = min(row, nrows - 1);
+#pragma unroll
+  for (int j = 0; j < NR; ++j) b.x[j] = gbl(xr)[rr + (int64_t)min(j, nrr - 1) * ldx];
+#pragma unroll
+  for (int g = 0; g < UN; g += 4) {
+    if (qb + g < qe) {
+#pragma unroll
+      for (int u = g; u < g + 4; ++u) b.v[u].load(a + (int64_t)min(qb + u, qe - 1) * step);
+    } else {
+#pragma unroll
+      for (int u = g; u < g + 4; ++u) b.v[u].zero();
+    }
+  }
 }
 
 template <class LT, class VT, int NR, int UN>
@@ -747,24 +772,34 @@ __global__ __launch_bounds__(64 * WPB) void k_phase1(const SlotDev* __restrict__
     VT acc[NR];
 #pragma unroll
     for (int j = 0; j < NR; ++j) acc[j] = VT(0);
-    P1Batch<LT, VT, NR, UN> A, B;
+    // full batches, the next one in flight while the current one is used
+    const int qf = item.q0 + (item.nq / UN) * UN;  // end of the full batches
     int qb = item.q0;
-    p1_issue(A, a, step, qb, qe, xr, ldx, nrr, item.nrows, lane);
-    for (;;) {
-      if (qb + UN >= qe) {
+    if (qb < qf) {
+      P1Batch<LT, VT, NR, UN> A, B;
+      p1_issue(A, a, step, qb, qe, xr, ldx, nrr, item.nrows, lane);
+      for (;;) {
+        if (qb + UN >= qf) {
+          p1_use(A, nrr, acc);
+          break;
+        }
+        p1_issue(B, a, step, qb + UN, qe, xr, ldx, nrr, item.nrows, lane);
         p1_use(A, nrr, acc);
-        break;
-      }
-      p1_issue(B, a, step, qb + UN, qe, xr, ldx, nrr, item.nrows, lane);
-      p1_use(A, nrr, acc);
-      qb += UN;
-      if (qb + UN >= qe) {
+        qb += UN;
+        if (qb + UN >= qf) {
+          p1_use(B, nrr, acc);
+          break;
+        }
+        p1_issue(A, a, step, qb + UN, qe, xr, ldx, nrr, item.nrows, lane);
         p1_use(B, nrr, acc);
-        break;
+        qb += UN;
       }
-      p1_issue(A, a, step, qb + UN, qe, xr, ldx, nrr, item.nrows, lane);
-      p1_use(B, nrr, acc);
-      qb += UN;
+      qb = qf;
+    }
+    if (qb < qe) {
+      P1Batch<LT, VT, NR, UN> T;
+      p1_issue_tail(T, a, step, qb, qe, xr, ldx, nrr, item.nrows, lane);
+      p1_use(T, nrr, acc);
     }
     if (item.part < 0) {
       if (act)

@@ -117,3 +117,24 @@ def test_invalid_arguments_are_rejected():
         hm.hm_facets_from_triangles(v, np.array([[0, 1, 2]]))   # degenerate triangle
     with pytest.raises(hm.HMError):
         hm.hm_facets_from_triangles(v, np.array([[0, 1, 5]]))   # index out of range
+
+
+def test_entry_points_reject_missing_handles():
+    # no GPU needed: every entry point checks its handles before any device call
+    hm = _hm()
+    tree = hm.hm_build_cluster_tree(None, *_small_cloud(), 2, 1.0)
+    params = (hm.hm_assembly_params * 1)(hm.hm_assembly_params(1e-6, 16, hm.HM_F32, hm.HM_F32, 0, 0, 0))
+    trees = (C.c_void_p * 1)(tree._h)
+    out = (C.c_void_p * 1)()
+    assert hm.lib.hm_assemble_hmatrix_batched(None, 1, trees, params, out) == hm.HM_EINVAL
+    assert hm.lib.hm_matrix_set_tuning(None, None, 64, 0) == hm.HM_EINVAL
+    assert hm.lib.hm_matrix_tuning(None, None, None, None) == hm.HM_EINVAL
+    assert hm.lib.hm_matrix_stats(None, None, None, None, None) == hm.HM_EINVAL
+    assert out[0] is None
+
+
+def _small_cloud():
+    c = np.zeros((8, 3))
+    c[:, 0] = np.arange(8)
+    n = np.tile([0.0, 0.0, 1.0], (8, 1))
+    return c, n, np.ones(8)
