@@ -1,7 +1,8 @@
 // Serving loop: radiosity solves of registered cavities, continuously
-// batched.  A background host thread owns the device work.  Requests are
-// admitted while the resident H-matrices and the solve buffers fit the HBM
-// budget; all admitted requests advance together, one refinement round at a
+// batched.  A background host thread owns the solves; a second one
+// assembles cavities that are not resident, on its own stream, while the
+// admitted requests keep their rounds.  Requests are admitted while the
+// resident H-matrices and the solve buffers fit the HBM budget; all admitted requests advance together, one refinement round at a
 // time (FP64 residual with the most accurate stored factors, then an inner
 // FP32 GMRES with the stored factors), sharing every H-matrix product and
 // every Krylov kernel launch; requests that arrive meanwhile join at the
@@ -94,6 +95,9 @@ struct SrvCavity {
   int64_t bytes = 0;     // device bytes while resident
   uint64_t last_use = 0;
   int refs = 0;
+  bool building = false;  // queued for or in assembly on the assembler thread
+  int waiting = 0;        // parked requests not yet admitted (the cavity is not evicted)
+  int64_t reserved = 0;   // budget bytes held while building
   ~SrvCavity() { delete M; }
 };
 
@@ -110,6 +114,7 @@ struct SrvReq {
   int rounds = 0, inner = 0, matvecs = 0;
   int64_t bytes = 0;
   double rel_res = 0;
+  bool waited = false;  // parked while its cavity was assembled
 };
 
 }  // namespace hm
@@ -124,14 +129,22 @@ struct hm_server {
   std::map<uint64_t, std::unique_ptr<hm::SrvReq>> req;
   std::deque<uint64_t> queue;
   std::vector<uint64_t> active;
+  std::vector<uint64_t> parked;       // requests waiting for their cavity's assembly
+  std::vector<uint64_t> ready;        // parked requests whose cavity is built (the worker
+                                      // moves them to the queue front: only it pops the queue)
+  std::deque<uint64_t> build_queue;   // cavities to assemble, in order
+  std::condition_variable acv;
   uint64_t next_ticket = 1, clock = 0;
   bool stop = false;
   hm_server_stats st{};
-  std::thread worker;
-  hm_ctx ctx;  // the worker's own context (device + private stream)
+  std::thread worker, assembler;
+  hm_ctx ctx;   // the worker's own context (device + private stream)
+  hm_ctx actx;  // the assembler's (device + its own stream)
+  enum Admit { ADMITTED, PARKED, WAIT };
   void run();
+  void build_loop();
   void round(std::vector<hm::SrvReq*>& act);
-  bool admit_one(hm::SrvReq& r);
+  Admit admit_one(hm::SrvReq& r);
   int64_t resident() const;
 };
 
@@ -139,26 +152,34 @@ using namespace hm;
 
 int64_t hm_server::resident() const {
   int64_t b = 0;
-  for (auto& kv : cav)
+  for (auto& kv : cav) {
     if (kv.second->M) b += kv.second->bytes;
+    else if (kv.second->building) b += kv.second->reserved;
+  }
   return b;
 }
 
-// Make the request's cavity resident (evicting idle cavities, least recently
-// used first, while over budget) and allocate its vectors.  Called without
-// the lock held; the worker thread is the only one touching device state.
-bool hm_server::admit_one(SrvReq& r) {
+// Admit a request whose cavity is resident (allocate its vectors); for a
+// cavity that is not, make room in the budget (evicting idle cavities, least
+// recently used first) and hand it to the assembler thread, parking the
+// request until the cavity is built, so that the requests already running
+// keep their rounds meanwhile.  Called without the lock held; device state
+// of resident cavities is touched only by the worker thread.
+hm_server::Admit hm_server::admit_one(SrvReq& r) {
   SrvCavity* c;
+  bool res;
   {
     std::lock_guard<std::mutex> lk(mu);
     c = cav.at(r.cid).get();
+    if (c->building) return PARKED;
+    res = c->M != nullptr;
   }
   const int64_t vec_bytes = r.n * r.nrhs * 8 * 3;
   auto resident_locked = [&] {
     std::lock_guard<std::mutex> lk(mu);
     return resident();
   };
-  if (!c->M) {
+  if (!res) {
     // evict idle cavities until the estimate fits
     const int64_t est = c->bytes > 0 ? c->bytes : r.n * 2500 * 4;
     for (;;) {
@@ -167,58 +188,41 @@ bool hm_server::admit_one(SrvReq& r) {
       {
         std::lock_guard<std::mutex> lk(mu);
         for (auto& kv : cav)
-          if (kv.second->M && kv.second->refs == 0 && (!lru || kv.second->last_use < lru->last_use))
+          if (kv.second->M && kv.second->refs == 0 && kv.second->waiting == 0 &&
+              (!lru || kv.second->last_use < lru->last_use))
             lru = kv.second.get();
       }
       if (!lru) break;
       HM_HIP(hipStreamSynchronize(stream));
-      delete lru->M;
-      lru->M = nullptr;
+      hm_matrix* dead;
+      {
+        std::lock_guard<std::mutex> lk(mu);
+        dead = lru->M;
+        lru->M = nullptr;
+        st.evictions++;
+      }
+      delete dead;
       lru->epsp.release();
       lru->om64.release();
       lru->om32.release();
       lru->g.release();
-      std::lock_guard<std::mutex> lk(mu);
-      st.evictions++;
     }
-    bool busy;
-    {
-      std::lock_guard<std::mutex> lk(mu);
-      busy = !active.empty();
-    }
-    if (resident_locked() + est + vec_bytes > p.hbm_budget_bytes && busy) return false;  // wait
-    c->M = assemble(ctx, *c->tree, c->ap);
-    c->M->id = 0x8000000000000000ull | c->id;
-    const int64_t n = c->M->n;
-    // permuted emissivities and g = F C^-1 eps for the flux (eq. (12))
-    c->eps_d.alloc(n * 8);
-    HM_HIP(hipMemcpyAsync(c->eps_d.get(), c->eps.data(), n * 8, hipMemcpyHostToDevice, stream));
-    c->epsp.alloc(n * 8);
-    hipLaunchKernelGGL(k_srv_gather<double>, g2(n, 1), dim3(256), 0, stream, c->M->d_perm.get<int32_t>(),
-                       c->eps_d.get<double>(), n, c->epsp.get<double>(), n, n);
-    std::vector<double> om(n);
-    for (int64_t i = 0; i < n; ++i) om[i] = 1.0 - c->eps[c->M->perm[i]];
-    std::vector<float> om32(om.begin(), om.end());
-    upload(c->om64, om, stream);
-    upload(c->om32, om32, stream);
-    {
-      Batch B({c->M}, 1, stream);
-      B.io({c->eps_d.get<double>()}, {}, 0, nullptr, stream);
-      B.gather(B.epsp.get<double>(), 1, 1, stream);
-      B.ensure_g({c->eps_d.get<double>()}, stream);
-      c->g.alloc(n * 8);
-      HM_HIP(hipMemcpyAsync(c->g.get(), B.g.get(), n * 8, hipMemcpyDeviceToDevice, stream));
-      HM_HIP(hipStreamSynchronize(stream));
-    }
-    c->bytes = c->M->bytes_device() + n * 8 * 4;
     std::lock_guard<std::mutex> lk(mu);
-    st.assemblies++;
-  } else {
-    std::lock_guard<std::mutex> lk(mu);
-    st.cache_hits++;
+    const bool busy = !active.empty() || !build_queue.empty();
+    if (resident() + est + vec_bytes > p.hbm_budget_bytes && busy) return WAIT;
+    c->building = true;
+    c->reserved = est;
+    build_queue.push_back(c->id);
+    acv.notify_all();
+    return PARKED;
   }
-  c->refs++;
-  c->last_use = ++clock;
+  {
+    std::lock_guard<std::mutex> lk(mu);
+    if (!r.waited) st.cache_hits++;
+    else c->waiting--;
+    c->refs++;
+    c->last_use = ++clock;
+  }
   // request vectors (permuted)
   const int64_t n = r.n;
   DevBuf Th(n * r.nrhs * 8);
@@ -232,7 +236,84 @@ bool hm_server::admit_one(SrvReq& r) {
                      r.b64.get<double>(), n, p.sigma);
   HM_HIP(hipMemsetAsync(r.J64.get(), 0, n * r.nrhs * 8, stream));
   HM_HIP(hipStreamSynchronize(stream));
-  return true;
+  return ADMITTED;
+}
+
+// The assembler thread: H-matrix, permuted emissivities and g = F C^-1 eps
+// (eq. (12)) of each queued cavity, on its own stream; then the requests
+// parked for the cavity are handed back (the worker puts them at the front
+// of the queue in their order).
+void hm_server::build_loop() {
+  (void)hipSetDevice(device);
+  for (;;) {
+    SrvCavity* c;
+    {
+      std::unique_lock<std::mutex> lk(mu);
+      acv.wait(lk, [&] { return stop || !build_queue.empty(); });
+      if (stop) return;
+      c = cav.at(build_queue.front()).get();
+    }
+    hipStream_t as = actx.stream;
+    hm_matrix* M = nullptr;
+    bool ok = true;
+    try {
+      M = assemble(actx, *c->tree, c->ap);
+      M->id = 0x8000000000000000ull | c->id;
+      const int64_t n = M->n;
+      c->eps_d.alloc(n * 8);
+      HM_HIP(hipMemcpyAsync(c->eps_d.get(), c->eps.data(), n * 8, hipMemcpyHostToDevice, as));
+      c->epsp.alloc(n * 8);
+      hipLaunchKernelGGL(k_srv_gather<double>, g2(n, 1), dim3(256), 0, as, M->d_perm.get<int32_t>(),
+                         c->eps_d.get<double>(), n, c->epsp.get<double>(), n, n);
+      std::vector<double> om(n);
+      for (int64_t i = 0; i < n; ++i) om[i] = 1.0 - c->eps[M->perm[i]];
+      std::vector<float> om32(om.begin(), om.end());
+      upload(c->om64, om, as);
+      upload(c->om32, om32, as);
+      {
+        Batch B({M}, 1, as);
+        B.io({c->eps_d.get<double>()}, {}, 0, nullptr, as);
+        B.gather(B.epsp.get<double>(), 1, 1, as);
+        B.ensure_g({c->eps_d.get<double>()}, as);
+        c->g.alloc(n * 8);
+        HM_HIP(hipMemcpyAsync(c->g.get(), B.g.get(), n * 8, hipMemcpyDeviceToDevice, as));
+        HM_HIP(hipStreamSynchronize(as));
+      }
+    } catch (const std::exception& e) {
+      (void)hipGetLastError();
+      delete M;
+      M = nullptr;
+      ok = false;
+      actx.last_error = e.what();
+    }
+    std::lock_guard<std::mutex> lk(mu);
+    build_queue.pop_front();
+    c->building = false;
+    c->reserved = 0;
+    if (ok) {
+      c->M = M;
+      c->bytes = M->bytes_device() + M->n * 8 * 4;
+      st.assemblies++;
+    }
+    // the cavity's parked requests: back to the queue front, or failed
+    std::vector<uint64_t> back, keep;
+    for (uint64_t tk : parked) {
+      SrvReq& r = *req.at(tk);
+      if (r.cid != c->id) {
+        keep.push_back(tk);
+      } else if (ok) {
+        back.push_back(tk);
+      } else {
+        c->waiting--;
+        r.status = HM_EDEVICE;
+        r.t_done = now_s();
+        r.done = true;
+      }
+    }
+    parked.swap(keep);
+    ready.insert(ready.end(), back.begin(), back.end());
+    cv.notify_all();
+  }
 }
 
 // One refinement round for every active request.
@@ -394,7 +475,7 @@ void hm_server::run() {
     std::vector<uint64_t> pending;
     {
       std::unique_lock<std::mutex> lk(mu);
-      cv.wait(lk, [&] { return stop || !queue.empty() || !active.empty(); });
+      cv.wait(lk, [&] { return stop || !queue.empty() || !active.empty() || !ready.empty(); });
       if (stop && active.empty()) return;
     }
     const double t0 = now_s();
@@ -404,6 +485,9 @@ void hm_server::run() {
         uint64_t tk = 0;
         {
           std::lock_guard<std::mutex> lk(mu);
+          // requests whose cavity the assembler has built go first, in order
+          queue.insert(queue.begin(), ready.begin(), ready.end());
+          ready.clear();
           if (stop || queue.empty() || (int)active.size() >= p.max_active) break;
           tk = queue.front();
         }
@@ -412,16 +496,17 @@ void hm_server::run() {
           std::lock_guard<std::mutex> lk(mu);
           r = req.at(tk).get();
         }
-        bool ok = false;
+        Admit a = WAIT;
         try {
-          ok = admit_one(*r);
+          a = admit_one(*r);
         } catch (const std::exception& e) {
           // this request cannot be admitted (assembly or allocation failed):
           // fail it alone and keep serving the others
           (void)hipGetLastError();
           const Error* he = dynamic_cast<const Error*>(&e);
           std::lock_guard<std::mutex> lk(mu);
-          queue.pop_front();
+          if (!queue.empty() && queue.front() == tk) queue.pop_front();
+          if (r->waited) cav.at(r->cid)->waiting--;
           r->status = he ? he->code : HM_EDEVICE;
           r->t_done = now_s();
           r->done = true;
@@ -429,8 +514,15 @@ void hm_server::run() {
           continue;
         }
         std::lock_guard<std::mutex> lk(mu);
-        if (!ok) break;
+        if (a == WAIT) break;
+        if (queue.empty() || queue.front() != tk) break;  // the queue was cleared (shutdown)
         queue.pop_front();
+        if (a == PARKED) {
+          if (!r->waited) cav.at(r->cid)->waiting++;
+          r->waited = true;
+          parked.push_back(tk);
+          continue;
+        }
         active.push_back(tk);
       }
       std::vector<SrvReq*> act;
@@ -485,8 +577,11 @@ hm_status hm_server_create(hm_ctx* ctx, const hm_server_params* p, hm_server** o
     HM_HIP(hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking));
     s->ctx.device = ctx->device;
     s->ctx.stream = s->stream;
+    s->actx.device = ctx->device;
+    HM_HIP(hipStreamCreateWithFlags(&s->actx.stream, hipStreamNonBlocking));
     hm_server* raw = s.get();
     s->worker = std::thread([raw] { raw->run(); });
+    s->assembler = std::thread([raw] { raw->build_loop(); });
     *out = s.release();
     return HM_OK;
   } catch (const Error& e) {
@@ -610,12 +705,16 @@ void hm_server_destroy(hm_server* s) {
     s->queue.clear();
   }
   s->cv.notify_all();
+  s->acv.notify_all();
   if (s->worker.joinable()) s->worker.join();
+  if (s->assembler.joinable()) s->assembler.join();
   (void)hipSetDevice(s->device);
   (void)hipStreamSynchronize(s->stream);
+  if (s->actx.stream) (void)hipStreamSynchronize(s->actx.stream);
   s->cav.clear();
   s->req.clear();
   (void)hipStreamDestroy(s->stream);
+  if (s->actx.stream) (void)hipStreamDestroy(s->actx.stream);
   delete s;
 }
 

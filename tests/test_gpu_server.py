@@ -8,6 +8,10 @@
   refinement to a residual of 1e-9, ACA 1e-8).
 * A budget too small for all cavities forces evictions and re-assembly, and
   results stay the same.
+* Cold start: requests on cavities that are not resident, all submitted at
+  once, are assembled on the server's assembler thread while the requests
+  whose cavity is ready already run; every result equals the one of the same
+  request served alone (bit for bit up to 1e-12).
 """
 import time
 
@@ -127,3 +131,28 @@ def test_server_evicts_under_a_small_budget(hm, ctx):
     for (rnd, cid), r in out.items():
         want = ref[tks[cid][0]]
         assert rel(r[0], want[0]) <= 1e-12 and rel(r[1], want[1]) <= 1e-12
+
+
+def test_server_cold_mix_assembles_while_serving(hm, ctx):
+    cavs = _cavities()
+    log("case: server cold start, 3 cavities submitted at once")
+    rng = np.random.default_rng(13)
+    reqs = []
+    for cid, nr in ((2, 2), (0, 1), (1, 3), (2, 1), (0, 4), (1, 1), (2, 2)):
+        reqs.append((cid, rng.uniform(300.0, 1500.0, (cavs[cid][1].shape[0], nr))))
+    warm = _server(hm, ctx, cavs, 8 << 30)
+    alone = []
+    for cid, T in reqs:
+        tk = warm.submit(cid, T)
+        alone.append(_wait(warm, [tk])[tk[0]])
+    warm.close()
+    cold = _server(hm, ctx, cavs, 8 << 30)
+    tks = [cold.submit(cid, T) for cid, T in reqs]
+    mix = _wait(cold, tks)
+    st = cold.stats()
+    cold.close()
+    log("stats", st)
+    assert st["completed"] == len(reqs) and st["assemblies"] == 3
+    for (cid, T), a, tk in zip(reqs, alone, tks):
+        m = mix[tk[0]]
+        assert rel(m[0], a[0]) <= 1e-12 and rel(m[1], a[1]) <= 1e-12, cid
