@@ -307,12 +307,16 @@ typedef struct {
   int64_t resident_bytes;
 } hm_server_stats;
 
-/* A serving loop owned by a background host thread: requests (radiosity
+/* A serving loop owned by two background host threads: requests (radiosity
  * solves of registered cavities) are admitted while the resident H-matrices
  * and the solve buffers fit hbm_budget_bytes, advanced together in shared
  * products, and retired as they converge; new requests join at the next
  * round.  H-matrices stay resident across requests (least-recently-used
- * eviction).  Thread-safe. */
+ * eviction of cavities with no running or waiting request).  A cavity that
+ * is not resident is assembled by the second thread on its own stream while
+ * the admitted requests keep running; the requests that need it wait for it
+ * (its budget share reserved) and then go first.  cache_hits counts
+ * requests whose cavity was resident when they were admitted.  Thread-safe. */
 hm_status hm_server_create(hm_ctx* ctx, const hm_server_params* p, hm_server** out);
 /* Register a cavity: the tree is copied; eps_host (HOST, n) is copied;
  * assembly happens lazily on first use. */

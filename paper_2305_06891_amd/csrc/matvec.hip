@@ -2,10 +2,11 @@
 //   phase 1:  t_b = V_b^T x_tau          for every low-rank block b
 //   phase 2:  y_sigma += D_b x_tau  and  y_sigma += U_b t_b, row tile by row tile.
 // Both phases are bandwidth kernels: every stored entry is read once per
-// product, from panels packed so that each lane loads 16 contiguous bytes and
-// each wave load is one contiguous run (see the layouts in hm_internal.hpp).
-// Phase 2 runs one workgroup per row tile whose waves share the tile's
-// byte-balanced items and add their sums in LDS in a fixed order; phase-1
+// product (non-temporal loads), from panels packed so that each lane loads
+// four consecutive entries (8-32 bytes) and each wave load is one contiguous
+// run (see the layouts in hm_internal.hpp).  Phase 2 runs one workgroup per
+// row tile whose waves share the tile's items (cut to nearly equal column
+// counts) and add their sums in LDS in a fixed order; phase-1
 // groups whose rows are split over several items write partials that a
 // separate kernel adds in item order.  No kernel communicates across
 // workgroups, so results do not depend on scheduling.  Several matrices can
