@@ -136,7 +136,8 @@ constexpr int P2_MAXW = 256;   // padded columns per phase-2 item
 constexpr int P1_GW = 64;      // rank columns per phase-1 group (one per lane)
 constexpr int P1_XST = 256;    // rows of x staged in LDS at a time
 constexpr int TILE = 64;       // rows per phase-2 tile (lane = row)
-constexpr int P2_WAVES = 8;    // waves per phase-2 workgroup (one tile each)
+constexpr int P2_WAVES = 8;    // items per phase-2 tile; waves per phase-2 workgroup
+constexpr int P2_MANY_TILES = 4096;  // from this many tiles, four waves per workgroup
 constexpr int P2_MAXSEG = 64;  // input runs per phase-2 item
 
 // Phase 1 item: t (or a partial of it) for the gw columns of one group over

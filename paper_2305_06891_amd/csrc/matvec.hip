@@ -598,17 +598,25 @@ __device__ __forceinline__ void panel_item(const MT* __restrict__ a, int m, int 
   }
 }
 
-// Phase 2: one workgroup per row tile, lane = row of the tile; the waves
-// share the tile's items and add their sums in LDS in wave order.
-template <class DT, class LT, class VT, int NR>
-__global__ __launch_bounds__(64 * P2_WAVES) void k_phase2(const SlotDev* __restrict__ slots, const int* __restrict__ slot_of,
+// Phase 2: one workgroup of WG waves per row tile, lane = row of the tile;
+// the waves share the tile's items (each takes every WG-th) and add their
+// sums in LDS in wave order.  Compositions with many tiles run with four
+// waves per workgroup (a workgroup's slots are released only when its last
+// wave ends, and there are tiles enough to fill the GPU); small ones with
+// eight, one item per wave, for parallelism within each tile.
+template <class DT, class LT, class VT, int NR, int WG>
+__global__ __launch_bounds__(64 * WG) void k_phase2(const SlotDev* __restrict__ slots, const int* __restrict__ slot_of,
                                                           const int* __restrict__ slot_active, int nrr,
                                                           const VT* __restrict__ X, int64_t ldx,
                                                           VT* __restrict__ Y, int64_t ldy, EpiDev<VT> ep) {
   constexpr int CW = p2_chunk<VT, NR>();
   constexpr int RJ = NR < 4 ? NR : 4;
-  __shared__ VT lds_in[P2_WAVES][CW * NR];
-  __shared__ Seg lds_seg[P2_WAVES][P2_MAXSEG];
+  // item k is summed in slot k % P2_WAVES whatever WG is, and the slots are
+  // added in slot order, so every workgroup shape gives the same bits
+  constexpr int SL = P2_WAVES / WG;  // slots per wave
+  static_assert(P2_WAVES % WG == 0, "phase 2: WG must divide P2_WAVES");
+  __shared__ VT lds_in[WG][CW * NR];
+  __shared__ Seg lds_seg[WG][P2_MAXSEG];
   __shared__ VT lds_red[P2_WAVES][RJ][TILE];
   const int lane = threadIdx.x & 63;
   const int wv = uniform_int(threadIdx.x >> 6);  // wave index (uniform)
@@ -623,10 +631,13 @@ __global__ __launch_bounds__(64 * P2_WAVES) void k_phase2(const SlotDev* __restr
   Seg* sg_lds = lds_seg[wv];
   // lanes past the tile's rows repeat its last row; their sums are not stored
   const int prow = lane < T.m ? lane : T.m - 1;
-  VT acc[NR];
+  VT accs[SL][NR];
 #pragma unroll
-  for (int j = 0; j < NR; ++j) acc[j] = VT(0);
-  for (int k = wv; k < T.nit; k += P2_WAVES) {
+  for (int q = 0; q < SL; ++q)
+#pragma unroll
+    for (int j = 0; j < NR; ++j) accs[q][j] = VT(0);
+  for (int k = wv; k < T.nit; k += WG) {
+    VT* acc = accs[SL > 1 ? (k / WG) % SL : 0];
     const P2Item item = uniform_load(S.p2 + (T.it0 + k));
     wave_lds_sync();
     for (int q = lane; q < item.nseg; q += 64) sg_lds[q] = gbl(S.segs)[item.seg0 + q];
@@ -640,7 +651,7 @@ __global__ __launch_bounds__(64 * P2_WAVES) void k_phase2(const SlotDev* __restr
       panel_item<LT, VT, NR>((const LT*)S.U + item.base + prow * 4, T.m, item.w, in, sg_lds, item.nseg, wtrue, lane,
                              nrr, Xs, ldx, Ts, S.ldt, acc);
   }
-  // combine the waves in order and finish the tile
+  // combine the slots in order and finish the tile
   VT sum[NR];
 #pragma unroll
   for (int j = 0; j < NR; ++j) sum[j] = VT(0);
@@ -648,7 +659,9 @@ __global__ __launch_bounds__(64 * P2_WAVES) void k_phase2(const SlotDev* __restr
   for (int j0 = 0; j0 < NR; j0 += RJ) {
     __syncthreads();
 #pragma unroll
-    for (int j = 0; j < RJ; ++j) lds_red[wv][j][lane] = acc[j0 + j];
+    for (int q = 0; q < SL; ++q)
+#pragma unroll
+      for (int j = 0; j < RJ; ++j) lds_red[wv + WG * q][j][lane] = accs[q][j0 + j];
     __syncthreads();
     if (wv == 0) {
 #pragma unroll
@@ -1146,8 +1159,11 @@ void launch_typed(const Composition& C, int nrr, bool hi, const void* X, int64_t
     if constexpr (mfma)
       hipLaunchKernelGGL((k_phase2_mfma<DT, LT>), dim3(C.p2_tiles), dim3(64 * P2_WAVES), 0, s, slots,
                          sof + C.p1_tasks + C.p1_reds, slot_active, nrr, (const float*)X, ldx, (float*)Y, ldy, e);
+    else if (C.p2_tiles >= P2_MANY_TILES)
+      hipLaunchKernelGGL((k_phase2<DT, LT, VT, NR, 4>), dim3(C.p2_tiles), dim3(64 * 4), 0, s, slots,
+                         sof + C.p1_tasks + C.p1_reds, slot_active, nrr, (const VT*)X, ldx, (VT*)Y, ldy, e);
     else
-      hipLaunchKernelGGL((k_phase2<DT, LT, VT, NR>), dim3(C.p2_tiles), dim3(64 * P2_WAVES), 0, s, slots,
+      hipLaunchKernelGGL((k_phase2<DT, LT, VT, NR, P2_WAVES>), dim3(C.p2_tiles), dim3(64 * P2_WAVES), 0, s, slots,
                          sof + C.p1_tasks + C.p1_reds, slot_active, nrr, (const VT*)X, ldx, (VT*)Y, ldy, e);
   }
   if (ev) HM_HIP(hipEventRecord(ev[2], s));

@@ -19,6 +19,10 @@ times (autotuned matrices, the same solve parameters).
   operator; the ACA error breaks reciprocity at the 1e-6 level).
 * Autotuned and fixed phase-1 splits give the same product up to the order
   of partial sums (FP64: 1e-13).
+* The smallest and the largest cavity of the batch, solved alone with the
+  same matrices and parameters, give the batch's radiosity and flux bit for
+  bit (the batch's products run four-wave workgroups, a single cavity's
+  eight; every row sum has the same order in both).
 """
 import os
 
@@ -85,11 +89,19 @@ def c3(hm, ctx):
     p32 = hm.solve_params(rtol=1e-7, restart=30, max_iter=400, want_q=1, vec_dtype=hm.HM_F32)
     J3, q3, i3 = hm.hm_solve_radiosity_batched(ctx, M32, eps, T, SIGMA, p32)
     torch.cuda.synchronize()
-    return cavs, [to_np(j) for j in Jx], [to_np(q) for q in qx], ix, [to_np(j) for j in J3], [to_np(q) for q in q3]
+    # two cavities solved alone with the same matrices and parameters: the
+    # batch's products run four-wave workgroups, a single cavity's eight
+    alone = {}
+    for k in (min(range(len(cavs)), key=lambda i: cavs[i].n), max(range(len(cavs)), key=lambda i: cavs[i].n)):
+        Ja, qa, _ = hm.hm_solve_radiosity(ctx, Mx[k], eps[k], T[k], SIGMA, pmx)
+        alone[k] = (to_np(Ja), to_np(qa))
+    torch.cuda.synchronize()
+    return (cavs, [to_np(j) for j in Jx], [to_np(q) for q in qx], ix, [to_np(j) for j in J3], [to_np(q) for q in q3],
+            alone)
 
 
 def test_c3_batch_smallest_of_each_type_match_oracle(c3):
-    cavs, Jx, qx, ix, _, _ = c3
+    cavs, Jx, qx, ix, _, _, _ = c3
     assert all(i["status"] == 0 for i in ix)
     picked = {}
     for k, c in enumerate(cavs):
@@ -109,7 +121,7 @@ def test_c3_batch_smallest_of_each_type_match_oracle(c3):
 
 
 def test_c3_batch_mixed_agrees_with_fp32_and_conserves_energy(c3):
-    cavs, Jx, qx, ix, J3, q3 = c3
+    cavs, Jx, qx, ix, J3, q3, _ = c3
     worst_J = worst_q = worst_e = 0.0
     for k, c in enumerate(cavs):
         worst_J = max(worst_J, rel(Jx[k], J3[k]))
@@ -122,7 +134,7 @@ def test_c3_batch_mixed_agrees_with_fp32_and_conserves_energy(c3):
 
 
 def test_c3_largest_cavity_sampled_rows_satisfy_radiosity_balance(c3):
-    cavs, Jx, _, _, _, _ = c3
+    cavs, Jx, _, _, _, _, _ = c3
     k = max(range(len(cavs)), key=lambda i: cavs[i].n)
     c = cavs[k]
     cc, nn, a = geometry.facets_from_triangles(c.v, c.tri)
@@ -134,6 +146,13 @@ def test_c3_largest_cavity_sampled_rows_satisfy_radiosity_balance(c3):
     e = float(np.linalg.norm(r) / np.linalg.norm(b))
     log("%s (%d facets): sampled-row residual of the exact balance %.2e" % (c.name, c.n, e))
     assert e <= 1e-5
+
+
+def test_c3_batch_members_equal_their_alone_solves(c3):
+    cavs, Jx, qx, _, _, _, alone = c3
+    for k, (Ja, qa) in alone.items():
+        log("%s (%d facets): batched vs alone max |dJ| %.1e" % (cavs[k].name, cavs[k].n, float(np.max(np.abs(Jx[k] - Ja)))))
+        assert np.array_equal(Jx[k], Ja) and np.array_equal(qx[k], qa)
 
 
 def test_autotuned_and_fixed_splits_give_the_same_product(hm, ctx):
