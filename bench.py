@@ -220,7 +220,7 @@ def run_c3(args):
     prof_hi = hm.hm_hmatvec_profile(ctx, Mx, 1, hm.HM_F64, use_f32_copy=True, reps=10, flush_bytes=0)
     prof32 = hm.hm_hmatvec_profile(ctx, M32, 1, hm.HM_F32, reps=10, flush_bytes=0)
     rf = roofline(prof)
-    rf["traffic"] = measured_traffic("k_phase2<float, bf16, float, 1>" if rf["kernel"] == "k_phase2"
+    rf["traffic"] = measured_traffic("k_phase2<float, bf16, float, 1, 4>" if rf["kernel"] == "k_phase2"
                                      else "k_phase1<bf16, float, 1, 4>")
     ceil = copy_ceiling_gbps()
     rf["copy_ceiling_GBps"] = ceil
