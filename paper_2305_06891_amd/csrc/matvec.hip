@@ -600,10 +600,10 @@ __device__ __forceinline__ void panel_item(const MT* __restrict__ a, int m, int 
 
 // Phase 2: one workgroup of WG waves per row tile, lane = row of the tile;
 // the waves share the tile's items (each takes every WG-th) and add their
-// sums in LDS in wave order.  Compositions with many tiles run with four
-// waves per workgroup (a workgroup's slots are released only when its last
-// wave ends, and there are tiles enough to fill the GPU); small ones with
-// eight, one item per wave, for parallelism within each tile.
+// sums in LDS in wave order.  Compositions with many tiles and one or two
+// right-hand sides run with four waves per workgroup (a workgroup's slots
+// are released only when its last wave ends, and there are tiles enough to
+// fill the GPU); the others with eight, one item per wave.
 template <class DT, class LT, class VT, int NR, int WG>
 __global__ __launch_bounds__(64 * WG) void k_phase2(const SlotDev* __restrict__ slots, const int* __restrict__ slot_of,
                                                           const int* __restrict__ slot_active, int nrr,
@@ -695,10 +695,11 @@ __device__ __forceinline__ double lane_bcast(double v, int l) {
 // = sum_r V(r, l) x(xrow + r).  The rows of an item go in batches of UN
 // quads (about 8 KB per wave whatever the stored type): the x entries of a
 // batch come with one coalesced load (lane = row) and reach every lane by
-// lane broadcast.  The loads of the next full batch are issued before the
+// lane broadcast.  The loads of the next batch are issued before the
 // current one is used, so each wave keeps two batches in flight (no load of
-// a full batch sits behind a branch); an item's last, partial batch loads
-// its quads in groups of four, and rows past the item meet x = 0.
+// a pipelined batch sits behind a branch); with one right-hand side an
+// item's last, partial batch loads its quads in groups of four instead of
+// re-reading its last quad; rows past the item meet x = 0.
 template <class LT>
 constexpr int p1_batch_quads() {
   return (int)(128 / sizeof(Quad<LT>));
@@ -786,8 +787,10 @@ __global__ __launch_bounds__(64 * WPB) void k_phase1(const SlotDev* __restrict__
     VT acc[NR];
 #pragma unroll
     for (int j = 0; j < NR; ++j) acc[j] = VT(0);
-    // full batches, the next one in flight while the current one is used
-    const int qf = item.q0 + (item.nq / UN) * UN;  // end of the full batches
+    // full batches, the next one in flight while the current one is used;
+    // with one right-hand side a partial last batch loads only its quads
+    // (with more, its loads are better kept in the pipeline: clamped quads)
+    const int qf = NR == 1 ? item.q0 + (item.nq / UN) * UN : qe;  // end of the pipelined batches
     int qb = item.q0;
     if (qb < qf) {
       P1Batch<LT, VT, NR, UN> A, B;
@@ -810,10 +813,12 @@ __global__ __launch_bounds__(64 * WPB) void k_phase1(const SlotDev* __restrict__
       }
       qb = qf;
     }
-    if (qb < qe) {
-      P1Batch<LT, VT, NR, UN> T;
-      p1_issue_tail(T, a, step, qb, qe, xr, ldx, nrr, item.nrows, lane);
-      p1_use(T, nrr, acc);
+    if constexpr (NR == 1) {
+      if (qb < qe) {
+        P1Batch<LT, VT, NR, UN> T;
+        p1_issue_tail(T, a, step, qb, qe, xr, ldx, nrr, item.nrows, lane);
+        p1_use(T, nrr, acc);
+      }
     }
     if (item.part < 0) {
       if (act)
@@ -1159,12 +1164,20 @@ void launch_typed(const Composition& C, int nrr, bool hi, const void* X, int64_t
     if constexpr (mfma)
       hipLaunchKernelGGL((k_phase2_mfma<DT, LT>), dim3(C.p2_tiles), dim3(64 * P2_WAVES), 0, s, slots,
                          sof + C.p1_tasks + C.p1_reds, slot_active, nrr, (const float*)X, ldx, (float*)Y, ldy, e);
-    else if (C.p2_tiles >= P2_MANY_TILES)
-      hipLaunchKernelGGL((k_phase2<DT, LT, VT, NR, 4>), dim3(C.p2_tiles), dim3(64 * 4), 0, s, slots,
-                         sof + C.p1_tasks + C.p1_reds, slot_active, nrr, (const VT*)X, ldx, (VT*)Y, ldy, e);
-    else
-      hipLaunchKernelGGL((k_phase2<DT, LT, VT, NR, P2_WAVES>), dim3(C.p2_tiles), dim3(64 * P2_WAVES), 0, s, slots,
-                         sof + C.p1_tasks + C.p1_reds, slot_active, nrr, (const VT*)X, ldx, (VT*)Y, ldy, e);
+    else {
+      // four waves per workgroup on many tiles, for one or two right-hand
+      // sides (wider products would spill the second set of sums)
+      bool four = false;
+      if constexpr (NR <= 2) four = C.p2_tiles >= P2_MANY_TILES;
+      if constexpr (NR <= 2) {
+        if (four)
+          hipLaunchKernelGGL((k_phase2<DT, LT, VT, NR, 4>), dim3(C.p2_tiles), dim3(64 * 4), 0, s, slots,
+                             sof + C.p1_tasks + C.p1_reds, slot_active, nrr, (const VT*)X, ldx, (VT*)Y, ldy, e);
+      }
+      if (!four)
+        hipLaunchKernelGGL((k_phase2<DT, LT, VT, NR, P2_WAVES>), dim3(C.p2_tiles), dim3(64 * P2_WAVES), 0, s,
+                           slots, sof + C.p1_tasks + C.p1_reds, slot_active, nrr, (const VT*)X, ldx, (VT*)Y, ldy, e);
+    }
   }
   if (ev) HM_HIP(hipEventRecord(ev[2], s));
   HM_HIP(hipGetLastError());
