@@ -260,7 +260,8 @@ def run_kernels_only(args):
     and 5 FP64 elementwise products of 2^26 entries (c = a * b: a kernel of
     known FP64 operation count that calibrates the VALU flop counters).
     c4: the 200,000-facet ellipsoid (FP32), 10 products with 16 right-hand
-    sides (matrix cores) and 10 with one."""
+    sides and FP32 vectors (matrix cores), 10 with 16 and FP64 vectors
+    (matrix cores, FP64 sums) and 10 with one."""
     import torch
     from paper_2305_06891_amd import hm
     from workloads import configs
@@ -274,9 +275,12 @@ def run_kernels_only(args):
         torch.cuda.synchronize()
         p16 = hm.hm_hmatvec_profile(ctx, M, 16, hm.HM_F32, reps=10, flush_bytes=0)
         log("16-rhs product x10:", p16)
+        p16d = hm.hm_hmatvec_profile(ctx, M, 16, hm.HM_F64, reps=10, flush_bytes=0)
+        log("16-rhs fp64 product x10:", p16d)
         p1 = hm.hm_hmatvec_profile(ctx, M, 1, hm.HM_F32, reps=10, flush_bytes=0)
         log("1-rhs product x10:", p1)
-        return {"kernels_only": True, "roofline": roofline(p16), "roofline_1rhs": roofline(p1)}
+        return {"kernels_only": True, "roofline": roofline(p16), "roofline_fp64_16rhs": roofline(p16d),
+                "roofline_1rhs": roofline(p1)}
     cavs = configs.c3_batch()
     trees = []
     for cav in cavs:
@@ -345,13 +349,15 @@ def run_c4(args):
         % (args.steps, dt, info["newton_total"], info["newton_max"], info["matvecs"], info["max_rel_residual"]))
     prof = hm.hm_hmatvec_profile(ctx, M, 16, hm.HM_F32, reps=10, flush_bytes=0)
     prof1 = hm.hm_hmatvec_profile(ctx, M, 1, hm.HM_F32, reps=10, flush_bytes=0)
-    log("profile 16 rhs", prof, "\nprofile 1 rhs", prof1)
+    profd = hm.hm_hmatvec_profile(ctx, M, 16, hm.HM_F64, reps=10, flush_bytes=0)
+    log("profile 16 rhs", prof, "\nprofile 16 rhs fp64", profd, "\nprofile 1 rhs", prof1)
     out = base_record(args, solves / dt, 1e3 * dt / args.steps, "f32+f64", {
         "workload": "c4_ellipsoid_200000_16_scenarios", "facets": cav.n, "scenarios": int(T.shape[1]),
         "leaf": cav.leaf, "eta": cav.eta, "aca_tol": cav.aca_tol, "storage": "fp32",
-        "solver": "backward Euler, diagonal Newton; gmres(30) fp32 16 rhs per product (matrix cores), fp64 flux",
+        "solver": "backward Euler, diagonal Newton; 16-rhs products on the matrix cores: gmres(30) fp32, flux fp64",
         "rtol": RTOL, "newton_rtol": 1e-9, "mc": cav.extra["mc"], "dt": cav.extra["dt"]})
     out["roofline"] = roofline(prof)
+    out["roofline_fp64_16rhs"] = roofline(profd)
     out["roofline_1rhs"] = roofline(prof1)
     out["steps_per_s"] = args.steps / dt
     out["transient"] = {k: info[k] for k in ("steps_done", "newton_total", "newton_max", "matvecs",

@@ -287,6 +287,9 @@ struct Composition {
   std::vector<int32_t> slot_of;
   DevBuf d_slot_of;
   DevBuf t, part1;
+  // 16-column products on the matrix cores: the input rows copied to
+  // row-major order (16 values a row, FP32 or FP64); t is then row-major too
+  DevBuf xr;
   int64_t bytes_lo = 0, bytes_hi = 0;     // algorithmic matrix bytes per product
 };
 

@@ -351,6 +351,7 @@ std::unique_ptr<Composition> make_composition(const std::vector<const hm_matrix*
   const int64_t eb = 8;  // buffers sized for FP64 so one composition serves both vector types
   C->t.alloc(std::max<int64_t>(1, tsz * nr) * eb);
   C->part1.alloc(std::max<int64_t>(1, p1 * P1_GW * nr) * eb);
+  if (nr == 16) C->xr.alloc(std::max<int64_t>(1, C->N) * 16 * eb);
   int64_t to = 0;
   p1 = 0;
   int32_t t1 = 0, r1 = 0, t2 = 0;
@@ -843,9 +844,12 @@ constexpr int p1red_waves() {
   return NR >= 4 ? 4 : 1;
 }
 
-template <class VT, int NR>
+// ROWS: t is row-major (16 values a row, the matrix-core products), each
+// lane storing its row in four 16-byte stores.
+template <class VT, int NR, bool ROWS = false>
 __global__ __launch_bounds__(256) void k_p1reduce(const SlotDev* __restrict__ slots, const int* __restrict__ slot_of,
                                                   int nreds, const int* __restrict__ slot_active, int nrr) {
+  static_assert(!ROWS || NR == 16, "row-major t: 16 columns");
   constexpr int WPR = p1red_waves<VT, NR>();
   constexpr int IL = NR == 1 ? 8 : (NR == 2 ? 4 : (NR == 4 ? 2 : 1));
   __shared__ VT red[WPR > 1 ? WPR : 1][WPR > 1 ? NR : 1][64];
@@ -897,9 +901,23 @@ __global__ __launch_bounds__(256) void k_p1reduce(const SlotDev* __restrict__ sl
   }
   if (lane < R.gw) {
     VT* T = (VT*)S.t;
+    if constexpr (ROWS) {
+      // columns past nrr hold zero sums (their inputs are zero)
+      VT* o = T + (int64_t)(R.trow + lane) * NR;
+      if constexpr (std::is_same<VT, float>::value) {
+        const gptr<f32x4> q = (gptr<f32x4>)gbl_w(o);
 #pragma unroll
-    for (int j = 0; j < NR; ++j)
-      if (j < nrr) gbl_w(T)[R.trow + lane + j * S.ldt] = sum[j];
+        for (int k = 0; k < NR / 4; ++k) q[k] = f32x4{sum[4 * k], sum[4 * k + 1], sum[4 * k + 2], sum[4 * k + 3]};
+      } else {
+        const gptr<f64x2> q = (gptr<f64x2>)gbl_w(o);
+#pragma unroll
+        for (int k = 0; k < NR / 2; ++k) q[k] = f64x2{sum[2 * k], sum[2 * k + 1]};
+      }
+    } else {
+#pragma unroll
+      for (int j = 0; j < NR; ++j)
+        if (j < nrr) gbl_w(T)[R.trow + lane + j * S.ldt] = sum[j];
+    }
   }
 }
 
@@ -908,28 +926,114 @@ namespace {
 
 // ---- 16 right-hand sides: the products are dense contractions (16 rank
 // columns or rows x 16 right-hand sides per 4-deep step) and run on the
-// matrix cores with v_mfma_f32_16x16x4f32.  Operand layout of that
-// instruction for lane l (li = l % 16, lk = l / 16): A[li][lk], B[lk][li];
-// the result holds D[4 lk + v][li] in element v.  The depth index of a step
-// may stand for any four panel columns as long as A and B agree, so each
-// lane loads one 16-byte quad of its panel row (lane group lk taking the
-// next quad) and element e of the four quads feeds step e: one 16-byte load
-// per lane serves four steps, as in the one-right-hand-side kernels.
+// matrix cores, with v_mfma_f32_16x16x4f32 for FP32 vectors and
+// v_mfma_f64_16x16x4f64 for FP64 vectors (the stored FP32/BF16 entries are
+// widened exactly).  Operand layout of both for lane l (li = l % 16,
+// lk = l / 16): A[li][lk], B[lk][li]; element v of the result holds
+// D[4 lk + v][li] (FP32) or D[lk + 4 v][li] (FP64, rows interleaved).  The
+// depth index of a step may stand for any four panel
+// columns (or rows) as long as A and B agree, so each lane loads one
+// 16-byte quad of its panel row and element e of the quad feeds step e: in
+// step st lane group lk takes quad st + 4 lk of a 16-quad chunk, whose
+// element e is chunk column (or row) 16 lk + 4 st + e.  One 16-byte load per
+// lane serves four steps, as in the one-right-hand-side kernels.
+//
+// The vectors are read row-major (16 values a row): the input rows are
+// copied to that order first, and t is written in it.  The rows of a chunk
+// are staged in LDS with an odd row stride of 17 values: each lane's stores
+// of its row, and the operand reads (lane groups 16 rows apart), then fall
+// in distinct banks.
+
+using f64x4 = double __attribute__((ext_vector_type(4)));
+template <class VT> struct Acc16;
+template <> struct Acc16<float> { using type = f32x4; };
+template <> struct Acc16<double> { using type = f64x4; };
+template <class VT> using acc16_t = typename Acc16<VT>::type;
+
+// Row of the 16 x 16 result held in element v by lane group lk.
+template <class VT> __device__ __forceinline__ int acc_row(int lk, int v) {
+  return std::is_same<VT, double>::value ? lk + 4 * v : 4 * lk + v;
+}
 
 __device__ __forceinline__ f32x4 mfma16(float a, float b, f32x4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
+__device__ __forceinline__ f64x4 mfma16(double a, double b, f64x4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
 
-// Phase 1, 16 right-hand sides: t[trow + col][j] = sum_r V(r, col) x(xrow + r, j)
+constexpr int IN16_LD = 17;  // LDS row stride of staged vector rows (values)
+
+// Input rows of a 16-column product in row-major order: xr(r, j) = X(r, j)
+// for j < nrr and 0 past it, so that a row's values come with 16-byte loads
+// instead of a gather over 16 columns.
+template <class VT>
+__global__ __launch_bounds__(256) void k_rows16(const VT* __restrict__ X, int64_t ldx, int nrr, int64_t n,
+                                               VT* __restrict__ xr) {
+  const int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (r >= n) return;
+  VT v[16];
+#pragma unroll
+  for (int j = 0; j < 16; ++j) v[j] = j < nrr ? X[r + j * ldx] : VT(0);
+  VT* o = xr + r * 16;
+#pragma unroll
+  for (int j = 0; j < 16; ++j) o[j] = v[j];
+}
+
+// A vector row of 16 values in registers (four or eight 16-byte loads).
+template <class VT> struct Row16;
+template <> struct Row16<float> {
+  f32x4 v[4];
+  __device__ void load(const float* p) {
+    const gptr<const f32x4> q = (gptr<const f32x4>)gbl(p);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) v[k] = q[k];
+  }
+  __device__ float get(int j) const { return v[j >> 2][j & 3]; }
+};
+template <> struct Row16<double> {
+  f64x2 v[8];
+  __device__ void load(const double* p) {
+    const gptr<const f64x2> q = (gptr<const f64x2>)gbl(p);
+#pragma unroll
+    for (int k = 0; k < 8; ++k) v[k] = q[k];
+  }
+  __device__ double get(int j) const { return v[j >> 1][j & 1]; }
+};
+
+// Row `lane` of the chunk's staging area: the loaded row, or zero.
+template <class VT>
+__device__ __forceinline__ void stage_row16(const Row16<VT>& r, bool valid, VT* in, int lane) {
+#pragma unroll
+  for (int j = 0; j < 16; ++j) in[lane * IN16_LD + j] = valid ? r.get(j) : VT(0);
+}
+
+// acc[t] += the loaded quads times the staged rows of the chunk (zero past
+// the item, so the clamped quads that meet them add nothing).
+template <class MT, class VT>
+__device__ __forceinline__ void mfma_quads16(const Quad<MT> (&av)[4][4], const VT* __restrict__ in, int li, int lk,
+                                             acc16_t<VT>* acc) {
+#pragma unroll
+  for (int st = 0; st < 4; ++st) {
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const VT b = in[((st + 4 * lk) * 4 + e) * IN16_LD + li];
+#pragma unroll
+      for (int t = 0; t < 4; ++t) acc[t] = mfma16(av[st][t].template get<VT>(e), b, acc[t]);
+    }
+  }
+}
+
+// Phase 1, 16 right-hand sides: t(trow + col, j) = sum_r V(r, col) x(xrow + r, j)
 // for the <= 64 rank columns of a group panel (four 16-column tiles).  The
-// x rows of a 64-row chunk are staged in LDS (row-major, 16 values a row),
-// zero past the item's rows.
-template <class LT>
-__global__ __launch_bounds__(256) void k_phase1_mfma(const SlotDev* __restrict__ slots, const int* __restrict__ slot_of, int ntasks,
-                                                     const int* __restrict__ slot_active, int nrr,
-                                                     const float* __restrict__ X, int64_t ldx) {
+// x rows of a 64-row chunk are staged in LDS, zero past the item's rows.
+template <class LT, class VT>
+__global__ __launch_bounds__(256, sizeof(VT) == 4 ? 4 : 3) void k_phase1_mfma(const SlotDev* __restrict__ slots, const int* __restrict__ slot_of,
+                                                        int ntasks, const int* __restrict__ slot_active,
+                                                        const VT* __restrict__ Xr) {
   constexpr int NR = 16;
-  __shared__ float lds_x[4][64 * NR];
+  using AT = acc16_t<VT>;
+  __shared__ VT lds_x[4][64 * IN16_LD];
   const int lane = threadIdx.x & 63;
   const int wv = uniform_int(threadIdx.x >> 6);  // wave index (uniform)
   const int li = lane & 15, lk = lane >> 4;
@@ -939,119 +1043,120 @@ __global__ __launch_bounds__(256) void k_phase1_mfma(const SlotDev* __restrict__
   if (slot_active && !uniform_int(*gbl(slot_active + S.slot))) return;
   const int lt = task - S.p1_task_begin;
   const int ib = uniform_int(gbl(S.p1_task)[lt]), ie = uniform_int(gbl(S.p1_task)[lt + 1]);
-  const float* Xs = X + S.xoff;
-  float* T = (float*)S.t;
-  float* xs = lds_x[wv];
+  VT* T = (VT*)S.t;
+  VT* xs = lds_x[wv];
   for (int it = ib; it < ie; ++it) {
     const P1Item item = uniform_load(S.p1 + it);
     const int ntile = (item.gw + 15) >> 4;
-    const LT* vb = (const LT*)S.V + item.base;
-    const int64_t step = (int64_t)item.gw * 4;
+    // 32-bit byte offsets from the chunk's wave-uniform base (a chunk spans
+    // 16 quads of at most 64 columns): one address register per load
+    const char* vb = reinterpret_cast<const char*>((const LT*)S.V + item.base);
+    const uint32_t step = (uint32_t)item.gw * 4u * (uint32_t)sizeof(LT);
     // lanes past the group's columns repeat its last column (not stored)
-    int coff[4];
+    uint32_t coff[4];
 #pragma unroll
-    for (int t = 0; t < 4; ++t) coff[t] = min(16 * t + li, item.gw - 1) * 4;
-    const float* xr = Xs + item.xrow;
+    for (int t = 0; t < 4; ++t) coff[t] = (uint32_t)min(16 * t + li, item.gw - 1) * 4u * (uint32_t)sizeof(LT);
+    const VT* xr = Xr + (S.xoff + item.xrow) * NR;
     const int qe = item.q0 + item.nq;
     const int rend = min(item.nrows, qe * 4);
-    f32x4 acc[4];
+    AT acc[4];
 #pragma unroll
-    for (int t = 0; t < 4; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int t = 0; t < 4; ++t) acc[t] = AT{0, 0, 0, 0};
     for (int q0 = item.q0; q0 < qe; q0 += 16) {
       const int r0 = q0 * 4;
-      // x rows of the chunk (clamped into the item and the caller's columns;
-      // values past them become zero below), then the chunk's panel quads:
-      // one round trip covers both
-      const int rr = min(r0 + lane, rend - 1);
-      float xv[NR];
-#pragma unroll
-      for (int j = 0; j < NR; ++j) xv[j] = gbl(xr)[rr + (int64_t)min(j, nrr - 1) * ldx];
-      // four steps of four quads: lane group lk takes quad q0 + 4 st + lk;
+      // the chunk's x rows (clamped into the item; rows past it become
+      // zero below), then its panel quads: one round trip covers both
+      Row16<VT> xv;
+      xv.load(xr + (int64_t)min(r0 + lane, rend - 1) * NR);
       // all four column tiles are computed (past the group's width they
       // repeat its last column and are not stored)
       Quad<LT> a[4][4];
+      const char* vc = vb + (int64_t)q0 * step;
 #pragma unroll
       for (int st = 0; st < 4; ++st) {
-        const int q = q0 + 4 * st + lk;
-        const int64_t qo = (int64_t)(q < qe ? q : qe - 1) * step;
+        const int q = q0 + st + 4 * lk;
+        const uint32_t qo = (uint32_t)((q < qe ? q : qe - 1) - q0) * step;
 #pragma unroll
-        for (int t = 0; t < 4; ++t) a[st][t].load(vb + qo + coff[t]);
+        for (int t = 0; t < 4; ++t) a[st][t].load(reinterpret_cast<const LT*>(vc + (qo + coff[t])));
       }
       wave_lds_sync();
-#pragma unroll
-      for (int j = 0; j < NR; ++j) xs[lane * NR + j] = (j < nrr && r0 + lane < rend) ? xv[j] : 0.f;
+      stage_row16<VT>(xv, r0 + lane < rend, xs, lane);
       wave_lds_sync();
-      // rows past the item are zero in xs, so the clamped quads add nothing
-#pragma unroll
-      for (int st = 0; st < 4; ++st)
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          const float b = xs[((4 * st + lk) * 4 + e) * NR + li];
-#pragma unroll
-          for (int t = 0; t < 4; ++t) acc[t] = mfma16(a[st][t].template get<float>(e), b, acc[t]);
-        }
+      mfma_quads16<LT, VT>(a, xs, li, lk, acc);
     }
     if (item.part < 0) {
-      if (li < nrr)
+      // t row-major; columns past nrr hold zero (their inputs are zero)
 #pragma unroll
-        for (int t = 0; t < 4; ++t)
+      for (int t = 0; t < 4; ++t)
 #pragma unroll
-          for (int v = 0; v < 4; ++v) {
-            const int col = 16 * t + 4 * lk + v;
-            if (t < ntile && col < item.gw) gbl_w(T)[item.trow + col + li * S.ldt] = acc[t][v];
-          }
+        for (int v = 0; v < 4; ++v) {
+          const int col = 16 * t + acc_row<VT>(lk, v);
+          if (t < ntile && col < item.gw) gbl_w(T)[(int64_t)(item.trow + col) * NR + li] = acc[t][v];
+        }
     } else {
-      float* P = (float*)S.part1 + (int64_t)item.part * P1_GW * NR;
+      VT* P = (VT*)S.part1 + (int64_t)item.part * P1_GW * NR;
 #pragma unroll
       for (int t = 0; t < 4; ++t)
 #pragma unroll
         for (int v = 0; v < 4; ++v)
-          if (t < ntile) gbl_w(P)[li * P1_GW + 16 * t + 4 * lk + v] = acc[t][v];
+          if (t < ntile) gbl_w(P)[li * P1_GW + 16 * t + acc_row<VT>(lk, v)] = acc[t][v];
     }
   }
 }
 
 // The 16 quads [g, g + 16) of an item panel of m rows, for the four 16-row
-// tiles (lanes past m repeat row m - 1; quads past g1 repeat quad g1 - 1).
+// tiles: lane group lk takes quad g + st + 4 lk in step st (lanes past m
+// repeat row m - 1; quads past g1 repeat quad g1 - 1).  32-bit element
+// offsets from the wave-uniform panel base (an item panel holds far fewer
+// than 2^32 entries) keep one address register per load.
 template <class MT>
 __device__ __forceinline__ void load_quads16(Quad<MT> (&av)[4][4], const MT* __restrict__ a, int m, int g, int g1,
                                              int li, int lk) {
+  const char* base = reinterpret_cast<const char*>(a);
 #pragma unroll
   for (int st = 0; st < 4; ++st) {
-    const int q = g + 4 * st + lk;
-    const int64_t go = (int64_t)(q < g1 ? q : g1 - 1) * m * 4;
+    const int q = g + st + 4 * lk;
+    const uint32_t go = (uint32_t)(q < g1 ? q : g1 - 1) * (uint32_t)m * 4u;
 #pragma unroll
-    for (int rt = 0; rt < 4; ++rt) av[st][rt].load(a + go + min(16 * rt + li, m - 1) * 4);
-  }
-}
-
-// acc[rt] += the loaded quads times the staged inputs in[col][rhs] of the
-// chunk's columns (lane groups whose quad lies past the chunk add zero).
-template <class MT>
-__device__ __forceinline__ void mfma_quads16(const Quad<MT> (&av)[4][4], const float* __restrict__ in, int nq, int li,
-                                             int lk, f32x4* acc) {
-#pragma unroll
-  for (int st = 0; st < 4; ++st) {
-    const bool in_item = 4 * st + lk < nq;
-#pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      const float b = in_item ? in[((4 * st + lk) * 4 + e) * 16 + li] : 0.f;
-#pragma unroll
-      for (int rt = 0; rt < 4; ++rt) acc[rt] = mfma16(av[st][rt].template get<float>(e), b, acc[rt]);
+    for (int rt = 0; rt < 4; ++rt) {
+      const uint32_t off = (go + (uint32_t)min(16 * rt + li, m - 1) * 4u) * (uint32_t)sizeof(MT);
+      av[st][rt].load(reinterpret_cast<const MT*>(base + off));
     }
   }
 }
 
+// Phase-2 inputs of chunk column c0 + lane: its row-major input row (x or
+// t, found in the item's runs), or nothing past the chunk or the item.
+template <class VT>
+__device__ __forceinline__ bool stage16_issue(Row16<VT>& r, const Seg* sg_lds, int nseg, int wtrue, int c0, int cw,
+                                              int lane, const VT* Xr, const VT* Tr) {
+  const int c = c0 + lane;
+  const int cs = min(c, wtrue - 1);
+  int lo = 0, hi = nseg - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (sg_lds[mid].col0 <= cs) lo = mid;
+    else hi = mid - 1;
+  }
+  const Seg sg = sg_lds[lo];
+  const int kk = cs - sg.col0;
+  r.load(sg.src >= 0 ? Xr + (int64_t)(sg.src + kk) * 16 : Tr + (int64_t)(~sg.src + kk) * 16);
+  return lane < cw && c < wtrue;
+}
+
 // Phase 2, 16 right-hand sides: as k_phase2, with the row tile split into
 // four 16-row MFMA tiles; the waves' sums meet in LDS in wave order.
-template <class DT, class LT>
-__global__ __launch_bounds__(64 * P2_WAVES) void k_phase2_mfma(const SlotDev* __restrict__ slots, const int* __restrict__ slot_of,
-                                                               const int* __restrict__ slot_active, int nrr,
-                                                               const float* __restrict__ X, int64_t ldx,
-                                                               float* __restrict__ Y, int64_t ldy, EpiDev<float> ep) {
+template <class DT, class LT, class VT>
+__global__ __launch_bounds__(64 * P2_WAVES, sizeof(VT) == 4 ? 4 : 2) void k_phase2_mfma(const SlotDev* __restrict__ slots, const int* __restrict__ slot_of,
+                                                                  const int* __restrict__ slot_active, int nrr,
+                                                                  const VT* __restrict__ X, int64_t ldx,
+                                                                  const VT* __restrict__ Xr,
+                                                                  VT* __restrict__ Y, int64_t ldy, EpiDev<VT> ep) {
   constexpr int NR = 16;
-  constexpr int CW = 64;  // staged columns per chunk (4 KB per wave)
-  __shared__ float lds_in[P2_WAVES][CW * NR];  // reused for the wave sums [wave][rhs][row]
+  constexpr int CW = 64;  // staged columns per chunk
+  using AT = acc16_t<VT>;
+  static_assert(CW * IN16_LD >= NR * TILE, "the wave sums reuse the staging area");
+  __shared__ VT lds_in[P2_WAVES][CW * IN16_LD];  // reused for the wave sums [wave][rhs][row]
   __shared__ Seg lds_seg[P2_WAVES][P2_MAXSEG];
   const int lane = threadIdx.x & 63;
   const int wv = uniform_int(threadIdx.x >> 6);  // wave index (uniform)
@@ -1060,14 +1165,15 @@ __global__ __launch_bounds__(64 * P2_WAVES) void k_phase2_mfma(const SlotDev* __
   const SlotDev S = uniform_load(slots + uniform_load(slot_of + tile));
   if (slot_active && !uniform_int(*gbl(slot_active + S.slot))) return;  // uniform over the workgroup
   const P2Tile T = uniform_load(S.p2t + (tile - S.p2_tile_begin));
-  const float* Xs = X + S.xoff;
-  float* Ys = Y + S.xoff;
-  const float* Ts = (const float*)S.t;
-  float* in = lds_in[wv];
+  const VT* Xs = X + S.xoff;
+  VT* Ys = Y + S.xoff;
+  const VT* Xrs = Xr + S.xoff * NR;
+  const VT* Ts = (const VT*)S.t;
+  VT* in = lds_in[wv];
   Seg* sg_lds = lds_seg[wv];
-  f32x4 acc[4];
+  AT acc[4];
 #pragma unroll
-  for (int rt = 0; rt < 4; ++rt) acc[rt] = f32x4{0.f, 0.f, 0.f, 0.f};
+  for (int rt = 0; rt < 4; ++rt) acc[rt] = AT{0, 0, 0, 0};
   for (int k = wv; k < T.nit; k += P2_WAVES) {
     const P2Item item = uniform_load(S.p2 + (T.it0 + k));
     wave_lds_sync();
@@ -1075,52 +1181,55 @@ __global__ __launch_bounds__(64 * P2_WAVES) void k_phase2_mfma(const SlotDev* __
     wave_lds_sync();
     const Seg lastseg = sg_lds[item.nseg - 1];
     const int wtrue = lastseg.col0 + lastseg.w;
-    // per chunk of 64 columns: the input gathers and then the panel loads
+    // per chunk of 64 columns: the input loads and then the panel loads
     // go out, the inputs are written to LDS while the panel loads are in
     // flight, then 64 matrix-core steps
     if (item.kind == 0) {
       const DT* pa = (const DT*)S.dense + item.base;
       for (int c0 = 0; c0 < item.w; c0 += CW) {
         const int cw = min(CW, item.w - c0);
-        Staged<float, NR, CW> st;
-        stage_issue<float, NR, CW>(st, sg_lds, item.nseg, wtrue, c0, cw, lane, nrr, Xs, ldx, Ts, S.ldt);
+        Row16<VT> xin;
+        const bool valid = stage16_issue<VT>(xin, sg_lds, item.nseg, wtrue, c0, cw, lane, Xrs, Ts);
         Quad<DT> av[4][4];
         load_quads16<DT>(av, pa, T.m, c0 >> 2, (c0 + cw) >> 2, li, lk);
-        stage_commit<float, NR, CW>(st, in, lane, cw);
-        mfma_quads16<DT>(av, in, cw >> 2, li, lk, acc);
+        wave_lds_sync();
+        stage_row16<VT>(xin, valid, in, lane);
+        wave_lds_sync();
+        mfma_quads16<DT, VT>(av, in, li, lk, acc);
       }
     } else {
       const LT* pa = (const LT*)S.U + item.base;
       for (int c0 = 0; c0 < item.w; c0 += CW) {
         const int cw = min(CW, item.w - c0);
-        Staged<float, NR, CW> st;
-        stage_issue<float, NR, CW>(st, sg_lds, item.nseg, wtrue, c0, cw, lane, nrr, Xs, ldx, Ts, S.ldt);
+        Row16<VT> xin;
+        const bool valid = stage16_issue<VT>(xin, sg_lds, item.nseg, wtrue, c0, cw, lane, Xrs, Ts);
         Quad<LT> av[4][4];
         load_quads16<LT>(av, pa, T.m, c0 >> 2, (c0 + cw) >> 2, li, lk);
-        stage_commit<float, NR, CW>(st, in, lane, cw);
-        mfma_quads16<LT>(av, in, cw >> 2, li, lk, acc);
+        wave_lds_sync();
+        stage_row16<VT>(xin, valid, in, lane);
+        wave_lds_sync();
+        mfma_quads16<LT, VT>(av, in, li, lk, acc);
       }
     }
   }
   __syncthreads();
-  float* red = &lds_in[0][0];
+  VT* red = &lds_in[0][0];
 #pragma unroll
   for (int rt = 0; rt < 4; ++rt)
 #pragma unroll
-    for (int v = 0; v < 4; ++v) red[(wv * NR + li) * TILE + 16 * rt + 4 * lk + v] = acc[rt][v];
+    for (int v = 0; v < 4; ++v) red[(wv * NR + li) * TILE + 16 * rt + acc_row<VT>(lk, v)] = acc[rt][v];
   __syncthreads();
   if (wv == 0) {
-    float sum[NR];
+    VT sum[NR];
 #pragma unroll
-    for (int j = 0; j < NR; ++j) {
-      float t = red[j * TILE + lane];
-      for (int w = 1; w < P2_WAVES; ++w) t += red[(w * NR + j) * TILE + lane];
-      sum[j] = t;
-    }
-    EpiDev<float> e = ep;
+    for (int j = 0; j < NR; ++j) sum[j] = red[j * TILE + lane];
+    for (int w = 1; w < P2_WAVES; ++w)
+#pragma unroll
+      for (int j = 0; j < NR; ++j) sum[j] += red[(w * NR + j) * TILE + lane];
+    EpiDev<VT> e = ep;
     if (e.rowscale) e.rowscale += S.xoff;
     if (e.z) e.z += S.xoff;
-    epilogue_store<float, NR>(T.row0 + lane, lane, T.m, nrr, sum, Xs, ldx, Ys, ldy, e);
+    epilogue_store<VT, NR>(T.row0 + lane, lane, T.m, nrr, sum, Xs, ldx, Ys, ldy, e);
   }
 }
 
@@ -1135,13 +1244,19 @@ void launch_typed(const Composition& C, int nrr, bool hi, const void* X, int64_t
   constexpr int WPB = p1_waves_per_block<VT, NR>();
   const SlotDev* slots = (hi ? C.d_slots_hi : C.d_slots_lo).get<SlotDev>();
   const int* sof = C.d_slot_of.get<int>();
-  // 16 right-hand sides with FP32 sums of FP32/BF16 entries: matrix cores
-  constexpr bool mfma = NR == 16 && std::is_same<VT, float>::value && sizeof(DT) == 4 && sizeof(LT) <= 4;
+  // 16 right-hand sides of FP32/BF16 entries: matrix cores (FP32 or FP64 sums)
+  constexpr bool mfma = NR == 16 && sizeof(DT) == 4 && sizeof(LT) <= 4;
   if (ev) HM_HIP(hipEventRecord(ev[0], s));
+  if constexpr (mfma) {
+    HM_REQUIRE(C.xr.get() != nullptr, "matvec: 16-column composition without its row-major input buffer");
+    if (C.N > 0)
+      hipLaunchKernelGGL(k_rows16<VT>, dim3((unsigned)((C.N + 255) / 256)), dim3(256), 0, s, (const VT*)X, ldx, nrr,
+                         C.N, C.xr.get<VT>());
+  }
   if (C.p1_tasks > 0) {
     if constexpr (mfma)
-      hipLaunchKernelGGL((k_phase1_mfma<LT>), dim3((C.p1_tasks + 3) / 4), dim3(256), 0, s, slots, sof, C.p1_tasks,
-                         slot_active, nrr, (const float*)X, ldx);
+      hipLaunchKernelGGL((k_phase1_mfma<LT, VT>), dim3((C.p1_tasks + 3) / 4), dim3(256), 0, s, slots, sof,
+                         C.p1_tasks, slot_active, (const VT*)C.xr.get<VT>());
     else
       hipLaunchKernelGGL((k_phase1<LT, VT, NR, WPB>), dim3((C.p1_tasks + WPB - 1) / WPB), dim3(64 * WPB), 0, s,
                          slots, sof, C.p1_tasks, slot_active, nrr, (const VT*)X, ldx);
@@ -1149,7 +1264,7 @@ void launch_typed(const Composition& C, int nrr, bool hi, const void* X, int64_t
   if (C.p1_reds > 0) {
     constexpr int WPR = p1red_waves<VT, NR>();
     const unsigned nb = WPR > 1 ? (unsigned)C.p1_reds : (unsigned)((C.p1_reds + 3) / 4);
-    hipLaunchKernelGGL((k_p1reduce<VT, NR>), dim3(nb), dim3(256), 0, s, slots, sof + C.p1_tasks, C.p1_reds,
+    hipLaunchKernelGGL((k_p1reduce<VT, NR, mfma>), dim3(nb), dim3(256), 0, s, slots, sof + C.p1_tasks, C.p1_reds,
                        slot_active, nrr);
   }
   if (ev) HM_HIP(hipEventRecord(ev[1], s));
@@ -1162,8 +1277,9 @@ void launch_typed(const Composition& C, int nrr, bool hi, const void* X, int64_t
   e.ldz = ep.ldz;
   if (C.p2_tiles > 0) {
     if constexpr (mfma)
-      hipLaunchKernelGGL((k_phase2_mfma<DT, LT>), dim3(C.p2_tiles), dim3(64 * P2_WAVES), 0, s, slots,
-                         sof + C.p1_tasks + C.p1_reds, slot_active, nrr, (const float*)X, ldx, (float*)Y, ldy, e);
+      hipLaunchKernelGGL((k_phase2_mfma<DT, LT, VT>), dim3(C.p2_tiles), dim3(64 * P2_WAVES), 0, s, slots,
+                         sof + C.p1_tasks + C.p1_reds, slot_active, nrr, (const VT*)X, ldx,
+                         (const VT*)C.xr.get<VT>(), (VT*)Y, ldy, e);
     else {
       // four waves per workgroup on many tiles, for one or two right-hand
       // sides (wider products would spill the second set of sums)
