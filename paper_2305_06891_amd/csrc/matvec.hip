@@ -963,6 +963,7 @@ __device__ __forceinline__ f64x4 mfma16(double a, double b, f64x4 c) {
 }
 
 constexpr int IN16_LD = 17;  // LDS row stride of staged vector rows (values)
+constexpr int P2M_WAVES = 4;  // waves per phase-2 workgroup (one row tile)
 
 // Input rows of a 16-column product in row-major order: xr(r, j) = X(r, j)
 // for j < nrr and 0 past it, so that a row's values come with 16-byte loads
@@ -1009,8 +1010,9 @@ __device__ __forceinline__ void stage_row16(const Row16<VT>& r, bool valid, VT* 
 }
 
 // acc[t] += the loaded quads times the staged rows of the chunk (zero past
-// the item, so the clamped quads that meet them add nothing).
-template <class MT, class VT>
+// the item, so the clamped quads that meet them add nothing), for the NT
+// 16-wide tiles that hold columns (phase 1) or rows (phase 2) of the item.
+template <class MT, class VT, int NT>
 __device__ __forceinline__ void mfma_quads16(const Quad<MT> (&av)[4][4], const VT* __restrict__ in, int li, int lk,
                                              acc16_t<VT>* acc) {
 #pragma unroll
@@ -1019,8 +1021,35 @@ __device__ __forceinline__ void mfma_quads16(const Quad<MT> (&av)[4][4], const V
     for (int e = 0; e < 4; ++e) {
       const VT b = in[((st + 4 * lk) * 4 + e) * IN16_LD + li];
 #pragma unroll
-      for (int t = 0; t < 4; ++t) acc[t] = mfma16(av[st][t].template get<VT>(e), b, acc[t]);
+      for (int t = 0; t < NT; ++t) acc[t] = mfma16(av[st][t].template get<VT>(e), b, acc[t]);
     }
+  }
+}
+
+// Phase 1, one item with NT column tiles: its 64-row chunks in turn.
+template <class LT, class VT, int NT>
+__device__ __forceinline__ void p1_item16(const char* vb, uint32_t step, const uint32_t (&coff)[4], const VT* xr,
+                                          int q0b, int qe, int rend, VT* xs, int lane, int li, int lk,
+                                          acc16_t<VT>* acc) {
+  for (int q0 = q0b; q0 < qe; q0 += 16) {
+    const int r0 = q0 * 4;
+    // the chunk's x rows (clamped into the item; rows past it become zero
+    // below), then its panel quads: one round trip covers both
+    Row16<VT> xv;
+    xv.load(xr + (int64_t)min(r0 + lane, rend - 1) * 16);
+    Quad<LT> a[4][4];
+    const char* vc = vb + (int64_t)q0 * step;
+#pragma unroll
+    for (int st = 0; st < 4; ++st) {
+      const int q = q0 + st + 4 * lk;
+      const uint32_t qo = (uint32_t)((q < qe ? q : qe - 1) - q0) * step;
+#pragma unroll
+      for (int t = 0; t < NT; ++t) a[st][t].load(reinterpret_cast<const LT*>(vc + (qo + coff[t])));
+    }
+    wave_lds_sync();
+    stage_row16<VT>(xv, r0 + lane < rend, xs, lane);
+    wave_lds_sync();
+    mfma_quads16<LT, VT, NT>(a, xs, li, lk, acc);
   }
 }
 
@@ -1062,27 +1091,13 @@ __global__ __launch_bounds__(256, sizeof(VT) == 4 ? 4 : 3) void k_phase1_mfma(co
     AT acc[4];
 #pragma unroll
     for (int t = 0; t < 4; ++t) acc[t] = AT{0, 0, 0, 0};
-    for (int q0 = item.q0; q0 < qe; q0 += 16) {
-      const int r0 = q0 * 4;
-      // the chunk's x rows (clamped into the item; rows past it become
-      // zero below), then its panel quads: one round trip covers both
-      Row16<VT> xv;
-      xv.load(xr + (int64_t)min(r0 + lane, rend - 1) * NR);
-      // all four column tiles are computed (past the group's width they
-      // repeat its last column and are not stored)
-      Quad<LT> a[4][4];
-      const char* vc = vb + (int64_t)q0 * step;
-#pragma unroll
-      for (int st = 0; st < 4; ++st) {
-        const int q = q0 + st + 4 * lk;
-        const uint32_t qo = (uint32_t)((q < qe ? q : qe - 1) - q0) * step;
-#pragma unroll
-        for (int t = 0; t < 4; ++t) a[st][t].load(reinterpret_cast<const LT*>(vc + (qo + coff[t])));
-      }
-      wave_lds_sync();
-      stage_row16<VT>(xv, r0 + lane < rend, xs, lane);
-      wave_lds_sync();
-      mfma_quads16<LT, VT>(a, xs, li, lk, acc);
+    // only the column tiles that hold group columns are computed (in the
+    // last one, lanes past the width repeat its last column, not stored)
+    switch (ntile) {
+      case 1: p1_item16<LT, VT, 1>(vb, step, coff, xr, item.q0, qe, rend, xs, lane, li, lk, acc); break;
+      case 2: p1_item16<LT, VT, 2>(vb, step, coff, xr, item.q0, qe, rend, xs, lane, li, lk, acc); break;
+      case 3: p1_item16<LT, VT, 3>(vb, step, coff, xr, item.q0, qe, rend, xs, lane, li, lk, acc); break;
+      default: p1_item16<LT, VT, 4>(vb, step, coff, xr, item.q0, qe, rend, xs, lane, li, lk, acc); break;
     }
     if (item.part < 0) {
       // t row-major; columns past nrr hold zero (their inputs are zero)
@@ -1109,7 +1124,7 @@ __global__ __launch_bounds__(256, sizeof(VT) == 4 ? 4 : 3) void k_phase1_mfma(co
 // repeat row m - 1; quads past g1 repeat quad g1 - 1).  32-bit element
 // offsets from the wave-uniform panel base (an item panel holds far fewer
 // than 2^32 entries) keep one address register per load.
-template <class MT>
+template <class MT, int NT>
 __device__ __forceinline__ void load_quads16(Quad<MT> (&av)[4][4], const MT* __restrict__ a, int m, int g, int g1,
                                              int li, int lk) {
   const char* base = reinterpret_cast<const char*>(a);
@@ -1118,7 +1133,7 @@ __device__ __forceinline__ void load_quads16(Quad<MT> (&av)[4][4], const MT* __r
     const int q = g + st + 4 * lk;
     const uint32_t go = (uint32_t)(q < g1 ? q : g1 - 1) * (uint32_t)m * 4u;
 #pragma unroll
-    for (int rt = 0; rt < 4; ++rt) {
+    for (int rt = 0; rt < NT; ++rt) {
       const uint32_t off = (go + (uint32_t)min(16 * rt + li, m - 1) * 4u) * (uint32_t)sizeof(MT);
       av[st][rt].load(reinterpret_cast<const MT*>(base + off));
     }
@@ -1144,10 +1159,33 @@ __device__ __forceinline__ bool stage16_issue(Row16<VT>& r, const Seg* sg_lds, i
   return lane < cw && c < wtrue;
 }
 
+// Phase 2, one item of a row tile with NT 16-row tiles: per chunk of 64
+// columns the input loads and then the panel loads go out, the inputs are
+// written to LDS while the panel loads are in flight, then 16 NT
+// matrix-core steps.
+template <class MT, class VT, int NT>
+__device__ __forceinline__ void p2_item16(const MT* pa, int m, int w, const Seg* sg_lds, int nseg, int wtrue,
+                                          int lane, int li, int lk, const VT* Xrs, const VT* Ts, VT* in,
+                                          acc16_t<VT>* acc) {
+  constexpr int CW = 64;  // staged columns per chunk
+  for (int c0 = 0; c0 < w; c0 += CW) {
+    const int cw = min(CW, w - c0);
+    Row16<VT> xin;
+    const bool valid = stage16_issue<VT>(xin, sg_lds, nseg, wtrue, c0, cw, lane, Xrs, Ts);
+    Quad<MT> av[4][4];
+    load_quads16<MT, NT>(av, pa, m, c0 >> 2, (c0 + cw) >> 2, li, lk);
+    wave_lds_sync();
+    stage_row16<VT>(xin, valid, in, lane);
+    wave_lds_sync();
+    mfma_quads16<MT, VT, NT>(av, in, li, lk, acc);
+  }
+}
+
 // Phase 2, 16 right-hand sides: as k_phase2, with the row tile split into
-// four 16-row MFMA tiles; the waves' sums meet in LDS in wave order.
-template <class DT, class LT, class VT>
-__global__ __launch_bounds__(64 * P2_WAVES, sizeof(VT) == 4 ? 4 : 2) void k_phase2_mfma(const SlotDev* __restrict__ slots, const int* __restrict__ slot_of,
+// 16-row MFMA tiles (only those that hold rows are computed); WG waves share a tile's items (each takes every
+// WG-th) and their sums meet in LDS in wave order.
+template <class DT, class LT, class VT, int WG>
+__global__ __launch_bounds__(64 * WG, sizeof(VT) == 4 ? 4 : 3) void k_phase2_mfma(const SlotDev* __restrict__ slots, const int* __restrict__ slot_of,
                                                                   const int* __restrict__ slot_active, int nrr,
                                                                   const VT* __restrict__ X, int64_t ldx,
                                                                   const VT* __restrict__ Xr,
@@ -1156,8 +1194,8 @@ __global__ __launch_bounds__(64 * P2_WAVES, sizeof(VT) == 4 ? 4 : 2) void k_phas
   constexpr int CW = 64;  // staged columns per chunk
   using AT = acc16_t<VT>;
   static_assert(CW * IN16_LD >= NR * TILE, "the wave sums reuse the staging area");
-  __shared__ VT lds_in[P2_WAVES][CW * IN16_LD];  // reused for the wave sums [wave][rhs][row]
-  __shared__ Seg lds_seg[P2_WAVES][P2_MAXSEG];
+  __shared__ VT lds_in[WG][CW * IN16_LD];  // reused for the wave sums [wave][rhs][row]
+  __shared__ Seg lds_seg[WG][P2_MAXSEG];
   const int lane = threadIdx.x & 63;
   const int wv = uniform_int(threadIdx.x >> 6);  // wave index (uniform)
   const int li = lane & 15, lk = lane >> 4;
@@ -1171,44 +1209,32 @@ __global__ __launch_bounds__(64 * P2_WAVES, sizeof(VT) == 4 ? 4 : 2) void k_phas
   const VT* Ts = (const VT*)S.t;
   VT* in = lds_in[wv];
   Seg* sg_lds = lds_seg[wv];
+  const int ntile = (T.m + 15) >> 4;  // 16-row tiles holding rows (uniform)
   AT acc[4];
 #pragma unroll
   for (int rt = 0; rt < 4; ++rt) acc[rt] = AT{0, 0, 0, 0};
-  for (int k = wv; k < T.nit; k += P2_WAVES) {
+  for (int k = wv; k < T.nit; k += WG) {
     const P2Item item = uniform_load(S.p2 + (T.it0 + k));
     wave_lds_sync();
     for (int q = lane; q < item.nseg; q += 64) sg_lds[q] = gbl(S.segs)[item.seg0 + q];
     wave_lds_sync();
     const Seg lastseg = sg_lds[item.nseg - 1];
     const int wtrue = lastseg.col0 + lastseg.w;
-    // per chunk of 64 columns: the input loads and then the panel loads
-    // go out, the inputs are written to LDS while the panel loads are in
-    // flight, then 64 matrix-core steps
     if (item.kind == 0) {
       const DT* pa = (const DT*)S.dense + item.base;
-      for (int c0 = 0; c0 < item.w; c0 += CW) {
-        const int cw = min(CW, item.w - c0);
-        Row16<VT> xin;
-        const bool valid = stage16_issue<VT>(xin, sg_lds, item.nseg, wtrue, c0, cw, lane, Xrs, Ts);
-        Quad<DT> av[4][4];
-        load_quads16<DT>(av, pa, T.m, c0 >> 2, (c0 + cw) >> 2, li, lk);
-        wave_lds_sync();
-        stage_row16<VT>(xin, valid, in, lane);
-        wave_lds_sync();
-        mfma_quads16<DT, VT>(av, in, li, lk, acc);
+      switch (ntile) {
+        case 1: p2_item16<DT, VT, 1>(pa, T.m, item.w, sg_lds, item.nseg, wtrue, lane, li, lk, Xrs, Ts, in, acc); break;
+        case 2: p2_item16<DT, VT, 2>(pa, T.m, item.w, sg_lds, item.nseg, wtrue, lane, li, lk, Xrs, Ts, in, acc); break;
+        case 3: p2_item16<DT, VT, 3>(pa, T.m, item.w, sg_lds, item.nseg, wtrue, lane, li, lk, Xrs, Ts, in, acc); break;
+        default: p2_item16<DT, VT, 4>(pa, T.m, item.w, sg_lds, item.nseg, wtrue, lane, li, lk, Xrs, Ts, in, acc); break;
       }
     } else {
       const LT* pa = (const LT*)S.U + item.base;
-      for (int c0 = 0; c0 < item.w; c0 += CW) {
-        const int cw = min(CW, item.w - c0);
-        Row16<VT> xin;
-        const bool valid = stage16_issue<VT>(xin, sg_lds, item.nseg, wtrue, c0, cw, lane, Xrs, Ts);
-        Quad<LT> av[4][4];
-        load_quads16<LT>(av, pa, T.m, c0 >> 2, (c0 + cw) >> 2, li, lk);
-        wave_lds_sync();
-        stage_row16<VT>(xin, valid, in, lane);
-        wave_lds_sync();
-        mfma_quads16<LT, VT>(av, in, li, lk, acc);
+      switch (ntile) {
+        case 1: p2_item16<LT, VT, 1>(pa, T.m, item.w, sg_lds, item.nseg, wtrue, lane, li, lk, Xrs, Ts, in, acc); break;
+        case 2: p2_item16<LT, VT, 2>(pa, T.m, item.w, sg_lds, item.nseg, wtrue, lane, li, lk, Xrs, Ts, in, acc); break;
+        case 3: p2_item16<LT, VT, 3>(pa, T.m, item.w, sg_lds, item.nseg, wtrue, lane, li, lk, Xrs, Ts, in, acc); break;
+        default: p2_item16<LT, VT, 4>(pa, T.m, item.w, sg_lds, item.nseg, wtrue, lane, li, lk, Xrs, Ts, in, acc); break;
       }
     }
   }
@@ -1223,7 +1249,7 @@ __global__ __launch_bounds__(64 * P2_WAVES, sizeof(VT) == 4 ? 4 : 2) void k_phas
     VT sum[NR];
 #pragma unroll
     for (int j = 0; j < NR; ++j) sum[j] = red[j * TILE + lane];
-    for (int w = 1; w < P2_WAVES; ++w)
+    for (int w = 1; w < WG; ++w)
 #pragma unroll
       for (int j = 0; j < NR; ++j) sum[j] += red[(w * NR + j) * TILE + lane];
     EpiDev<VT> e = ep;
@@ -1277,7 +1303,7 @@ void launch_typed(const Composition& C, int nrr, bool hi, const void* X, int64_t
   e.ldz = ep.ldz;
   if (C.p2_tiles > 0) {
     if constexpr (mfma)
-      hipLaunchKernelGGL((k_phase2_mfma<DT, LT, VT>), dim3(C.p2_tiles), dim3(64 * P2_WAVES), 0, s, slots,
+      hipLaunchKernelGGL((k_phase2_mfma<DT, LT, VT, P2M_WAVES>), dim3(C.p2_tiles), dim3(64 * P2M_WAVES), 0, s, slots,
                          sof + C.p1_tasks + C.p1_reds, slot_active, nrr, (const VT*)X, ldx,
                          (const VT*)C.xr.get<VT>(), (VT*)Y, ldy, e);
     else {
