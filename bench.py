@@ -438,11 +438,15 @@ def run_c5(args):
         cid, nr = int(ids_all[k]), int(nrhs_all[k])
         return cid, configs.request_temperatures(sizes[cid], nr, seed, k)
 
+    seen = set()  # cavity ids requested so far (the budget holds them all: no evictions)
+
     def run_phase(first, count, arrivals):
         """Submit requests first..first+count-1 at the given arrival offsets
-        (None: all at once); returns (elapsed s, latencies s, rhs, statuses)."""
+        (None: all at once); returns (elapsed s, latencies s, rhs, statuses,
+        cold flags: the request was the first on its cavity id, whose
+        H-matrix is assembled on arrival)."""
         reqs = [temps(first + k) for k in range(count)]
-        lat, rhs, sts = [], 0, []
+        lat, rhs, sts, cold = [], 0, [], []
         pending = {}
         t_start = time.perf_counter()
         i = 0
@@ -451,23 +455,26 @@ def run_c5(args):
             while i < count and (arrivals is None or arrivals[i] <= now):
                 cid, T = reqs[i]
                 tk, shape = srv.submit(cid, T)
-                pending[tk] = shape
+                pending[tk] = (shape, cid not in seen)
+                seen.add(cid)
                 i += 1
             for tk in list(pending):
-                r = srv.poll(tk, pending[tk])
+                shape, c = pending[tk]
+                r = srv.poll(tk, shape)
                 if r is not None:
                     lat.append(r[2]["latency"])
-                    rhs += pending[tk][1]
+                    rhs += shape[1]
                     sts.append(r[2]["rel_residual"])
+                    cold.append(c)
                     del pending[tk]
             time.sleep(0.0002)
-        return time.perf_counter() - t_start, np.array(lat), rhs, sts
+        return time.perf_counter() - t_start, np.array(lat), rhs, sts, np.array(cold, dtype=bool)
 
     # warm-up: assembles the cavities of the first requests
-    t_w, _, _, _ = run_phase(0, nreq // 2, None)
+    t_w, _, _, _, _ = run_phase(0, nreq // 2, None)
     st0 = srv.stats()
     log("c5: warm-up %d requests in %.1f s; %s" % (nreq // 2, t_w, st0))
-    el, lat, rhs, res = run_phase(nreq // 2, nreq, None)
+    el, lat, rhs, res, _ = run_phase(nreq // 2, nreq, None)
     sat_req = nreq / el
     sat_rhs = rhs / el
     log("c5: saturation %.1f requests/s, %.1f solves/s (p50 %.1f ms, p99 %.1f ms; worst residual %.1e)"
@@ -477,11 +484,17 @@ def run_c5(args):
     for frac in (0.5, 0.8, 0.95):
         rate = frac * sat_req
         gaps = np.random.default_rng([seed, int(1000 * frac)]).exponential(1.0 / rate, nreq)
-        el, lat, rhs, res = run_phase(first, nreq, np.cumsum(gaps))
+        el, lat, rhs, res, cold = run_phase(first, nreq, np.cumsum(gaps))
         first += nreq
+        warm = lat[~cold]
         loads.append({"load": frac, "offered_req_per_s": rate, "achieved_req_per_s": nreq / el,
                       "solves_per_s": rhs / el, "p50_ms": 1e3 * float(np.percentile(lat, 50)),
-                      "p99_ms": 1e3 * float(np.percentile(lat, 99)), "worst_rel_residual": float(max(res))})
+                      "p99_ms": 1e3 * float(np.percentile(lat, 99)), "worst_rel_residual": float(max(res)),
+                      # requests on cavities already requested (resident) and first requests on a new id
+                      "resident_p50_ms": 1e3 * float(np.percentile(warm, 50)) if warm.size else None,
+                      "resident_p99_ms": 1e3 * float(np.percentile(warm, 99)) if warm.size else None,
+                      "cold_requests": int(cold.sum()),
+                      "cold_p50_ms": 1e3 * float(np.percentile(lat[cold], 50)) if cold.any() else None})
         log("c5: load %.2f: %s" % (frac, loads[-1]))
     st = srv.stats()
     srv.close()

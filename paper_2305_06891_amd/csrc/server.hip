@@ -145,6 +145,7 @@ struct hm_server {
   void build_loop();
   void round(std::vector<hm::SrvReq*>& act);
   Admit admit_one(hm::SrvReq& r);
+  void park_locked(hm::SrvReq& r);
   int64_t resident() const;
 };
 
@@ -159,19 +160,35 @@ int64_t hm_server::resident() const {
   return b;
 }
 
+// Moves the request at the queue front to the parked list (caller holds the
+// lock).  Parking happens in the same critical section that sees its cavity
+// queued for or in assembly: the assembler hands back the parked requests of
+// a cavity when its build ends, so a request parked after that would wait
+// forever.
+void hm_server::park_locked(SrvReq& r) {
+  if (!queue.empty() && queue.front() == r.ticket) queue.pop_front();
+  if (!r.waited) cav.at(r.cid)->waiting++;
+  r.waited = true;
+  parked.push_back(r.ticket);
+}
+
 // Admit a request whose cavity is resident (allocate its vectors); for a
 // cavity that is not, make room in the budget (evicting idle cavities, least
 // recently used first) and hand it to the assembler thread, parking the
 // request until the cavity is built, so that the requests already running
-// keep their rounds meanwhile.  Called without the lock held; device state
-// of resident cavities is touched only by the worker thread.
+// keep their rounds meanwhile.  Called without the lock held, for the
+// request at the queue front; device state of resident cavities is touched
+// only by the worker thread.
 hm_server::Admit hm_server::admit_one(SrvReq& r) {
   SrvCavity* c;
   bool res;
   {
     std::lock_guard<std::mutex> lk(mu);
     c = cav.at(r.cid).get();
-    if (c->building) return PARKED;
+    if (c->building) {
+      park_locked(r);
+      return PARKED;
+    }
     res = c->M != nullptr;
   }
   const int64_t vec_bytes = r.n * r.nrhs * 8 * 3;
@@ -213,6 +230,7 @@ hm_server::Admit hm_server::admit_one(SrvReq& r) {
     c->building = true;
     c->reserved = est;
     build_queue.push_back(c->id);
+    park_locked(r);
     acv.notify_all();
     return PARKED;
   }
@@ -515,14 +533,9 @@ void hm_server::run() {
         }
         std::lock_guard<std::mutex> lk(mu);
         if (a == WAIT) break;
+        if (a == PARKED) continue;  // admit_one has moved it to the parked list
         if (queue.empty() || queue.front() != tk) break;  // the queue was cleared (shutdown)
         queue.pop_front();
-        if (a == PARKED) {
-          if (!r->waited) cav.at(r->cid)->waiting++;
-          r->waited = true;
-          parked.push_back(tk);
-          continue;
-        }
         active.push_back(tk);
       }
       std::vector<SrvReq*> act;

@@ -86,11 +86,11 @@ def test_hmatvec_alpha_beta_and_widths(hm, ctx):
     import torch
     v, f = meshes.cylinder(36, 20, 5, seed=5)
     f = meshes.inward(f)
-    log("case: cylinder %d facets, FP32 storage, alpha/beta, nrhs 1/3/16" % f.shape[0])
+    log("case: cylinder %d facets, FP32 storage, alpha/beta, nrhs 1/3/9/16" % f.shape[0])
     tree, M = build(hm, ctx, v, f, 32, 1.5, 1e-6, hm.HM_F32, hm.HM_F32)
     c, n, a, F = oracle_dense(v, f)
     rng = np.random.default_rng(3)
-    for nr in (1, 3, 16):
+    for nr in (1, 3, 9, 16):  # 9 and 16: matrix-core products (9 padded to 16 columns)
         X = rng.uniform(-1, 1, (f.shape[0], nr))
         Y0 = rng.uniform(-1, 1, (f.shape[0], nr))
         for tdt, tol in ((torch.float64, 5e-6), (torch.float32, 5e-6)):
