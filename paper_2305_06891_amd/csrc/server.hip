@@ -431,7 +431,12 @@ void hm_server::round(std::vector<SrvReq*>& act) {
       r.bytes += matrix_bytes(*mats[q], true);
     }
   }
-  // continuing requests: inner FP32 GMRES with the stored factors on C d = r
+  // continuing requests: inner FP32 GMRES with the stored factors on C d = r.
+  // The Krylov workspace lives until the round's closing synchronisation:
+  // GMRES returns with its last update still queued, and the allocator hands
+  // freed blocks to the assembler thread, whose stream does not wait for
+  // this one.
+  Krylov K4;
   bool any_cont = false;
   for (size_t q = 0; q < act.size(); ++q) any_cont |= !fin[q];
   if (any_cont) {
@@ -447,7 +452,6 @@ void hm_server::round(std::vector<SrvReq*>& act) {
     // correction from zero, stopped on the GMRES residual estimate (the
     // next round's FP64 residual checks it)
     HM_HIP(hipMemsetAsync(x32.get(), 0, blk * 4, s));
-    Krylov K4;
     K4.init(*C, S, 4, p.solve.restart, s);
     const double inner = p.solve.mixed_precision ? p.solve.ir_inner_rtol : std::min(p.solve.ir_inner_rtol, 1e-5);
     GmresStats gs = gmres(K4, false, om32.get(), b32.get(), x32.get(), inner, p.solve.max_iter, s, false,
