@@ -1,6 +1,15 @@
 // Caching device allocator behind DevBuf.
+//
+// A freed block is handed out again only to the host thread that freed it.
+// Blocks go back to the cache when their owner is destroyed, which may be
+// before the work queued on the owner's stream has run; each thread orders
+// its work on its own stream, so reuse within the thread is ordered after
+// that work, but another thread's stream would not wait for it (the serving
+// loop runs a worker and an assembler thread, each with its own stream).
 #include <map>
 #include <mutex>
+#include <thread>
+#include <tuple>
 
 #include "hm_internal.hpp"
 
@@ -10,8 +19,9 @@ namespace {
 
 struct Pool {
   std::mutex mu;
-  std::multimap<std::pair<int, size_t>, void*> free_;  // (device, size class) -> block
-  std::map<void*, int> owner;                          // block -> device
+  // (device, freeing thread, size class) -> block
+  std::multimap<std::tuple<int, std::thread::id, size_t>, void*> free_;
+  std::map<void*, int> owner;  // block -> device
   int64_t cached = 0;
 };
 
@@ -37,7 +47,7 @@ void* pool_alloc(size_t bytes, size_t* granted) {
   Pool& P = pool();
   {
     std::lock_guard<std::mutex> lk(P.mu);
-    auto it = P.free_.find({dev, g});
+    auto it = P.free_.find(std::make_tuple(dev, std::this_thread::get_id(), g));
     if (it != P.free_.end()) {
       void* p = it->second;
       P.free_.erase(it);
@@ -67,7 +77,7 @@ void pool_free(void* p, size_t granted) {
   std::lock_guard<std::mutex> lk(P.mu);
   auto it = P.owner.find(p);
   const int dev = it != P.owner.end() ? it->second : 0;
-  P.free_.emplace(std::make_pair(dev, granted), p);
+  P.free_.emplace(std::make_tuple(dev, std::this_thread::get_id(), granted), p);
   P.cached += (int64_t)granted;
 }
 
@@ -83,7 +93,7 @@ void pool_trim() {
   int cur = 0;
   (void)hipGetDevice(&cur);
   for (auto& kv : P.free_) {
-    (void)hipSetDevice(kv.first.first);
+    (void)hipSetDevice(std::get<0>(kv.first));
     (void)hipDeviceSynchronize();
     (void)hipFree(kv.second);
     P.owner.erase(kv.second);
