@@ -501,6 +501,7 @@ void hm_server::run() {
       if (stop && active.empty()) return;
     }
     const double t0 = now_s();
+    bool no_room = false;  // the queue front waits for budget held by a build or by running requests
     try {
       // admission: FIFO while slots are free and the budget allows
       for (;;) {
@@ -536,7 +537,10 @@ void hm_server::run() {
           continue;
         }
         std::lock_guard<std::mutex> lk(mu);
-        if (a == WAIT) break;
+        if (a == WAIT) {
+          no_room = true;
+          break;
+        }
         if (a == PARKED) continue;  // admit_one has moved it to the parked list
         if (queue.empty() || queue.front() != tk) break;  // the queue was cleared (shutdown)
         queue.pop_front();
@@ -548,9 +552,14 @@ void hm_server::run() {
         for (uint64_t tk : active) act.push_back(req.at(tk).get());
       }
       if (!act.empty()) round(act);  // retires finished requests from active
-      std::lock_guard<std::mutex> lk(mu);
+      std::unique_lock<std::mutex> lk(mu);
       st.busy_seconds += now_s() - t0;
       st.resident_bytes = resident();
+      // nothing running and the queue front waits for a build to release
+      // budget: sleep until the assembler reports (bounded, no busy loop)
+      if (no_room && act.empty())
+        cv.wait_for(lk, std::chrono::milliseconds(2),
+                    [&] { return stop || !ready.empty() || build_queue.empty(); });
     } catch (const std::exception& e) {
       // fail every active request with the error; keep serving
       (void)hipGetLastError();
