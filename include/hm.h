@@ -123,8 +123,12 @@ typedef struct {
   double aca_tol;          /* eps_rel of eq. (31), in (0, 1) */
   int32_t k_max;           /* rank cap of ACA; a block reaching it is stored dense (>= 1) */
   hm_dtype lowrank_dtype;  /* storage of U, V: HM_F64, HM_F32 or HM_BF16 */
-  hm_dtype dense_dtype;    /* storage of near-field blocks: HM_F64 or HM_F32 */
-  int32_t keep_f32_copy;   /* with HM_BF16 factors: also keep FP32 factors (refinement residual) */
+  hm_dtype dense_dtype;    /* storage of near-field blocks: HM_F64, HM_F32 or HM_BF16; HM_BF16
+                              needs HM_BF16 factors and keep_f32_copy, and no closed_row_scale
+                              (HM_EINVAL otherwise) */
+  int32_t keep_f32_copy;   /* with HM_BF16 factors: also keep FP32 factors (and an FP32 copy of a
+                              BF16 near field); products with FP64 vectors use the copies
+                              (refinement residual), products with FP32 vectors the BF16 arrays */
   int32_t closed_row_scale;/* 1: closed-cavity row scaling of eqs. (32)-(34) (clamp the row sum
                               to [0,1], divide rows with non-zero clamped sum by it); default 0 */
   int32_t autotune;        /* 1: time the candidate work splits of the product's first kernel

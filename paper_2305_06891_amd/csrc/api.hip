@@ -104,7 +104,8 @@ void check_device_range(hm_ctx& c, const double* v, int64_t n, int64_t ld, int n
 }  // namespace hm
 
 int64_t hm_matrix::bytes_device() const {
-  int64_t b = (int64_t)(dense.bytes() + U.bytes() + V.bytes() + U_hi.bytes() + V_hi.bytes() + d_perm.bytes());
+  int64_t b = (int64_t)(dense.bytes() + dense_hi.bytes() + U.bytes() + V.bytes() + U_hi.bytes() + V_hi.bytes() +
+                        d_perm.bytes());
   b += (int64_t)(plan.d_p1.bytes() + plan.d_p1_task.bytes() + plan.d_p1red.bytes() + plan.d_p2t.bytes() + plan.d_p2.bytes() +
                  plan.d_segs.bytes());
   return b;
@@ -207,8 +208,12 @@ void check_assembly_params(const hm_assembly_params* p, const char* fn) {
   HM_REQUIRE(p->k_max >= 1, f + ": k_max must be >= 1");
   HM_REQUIRE(p->lowrank_dtype == HM_F64 || p->lowrank_dtype == HM_F32 || p->lowrank_dtype == HM_BF16,
              f + ": bad lowrank_dtype");
-  HM_REQUIRE(p->dense_dtype == HM_F64 || p->dense_dtype == HM_F32, f + ": bad dense_dtype");
+  HM_REQUIRE(p->dense_dtype == HM_F64 || p->dense_dtype == HM_F32 || p->dense_dtype == HM_BF16,
+             f + ": bad dense_dtype");
   HM_REQUIRE(!(p->dense_dtype == HM_F64 && p->lowrank_dtype == HM_BF16), f + ": BF16 factors need FP32 near field");
+  HM_REQUIRE(p->dense_dtype != HM_BF16 || (p->lowrank_dtype == HM_BF16 && p->keep_f32_copy),
+             f + ": a BF16 near field needs BF16 factors and keep_f32_copy (FP32 copies for FP64-vector products)");
+  HM_REQUIRE(p->dense_dtype != HM_BF16 || !p->closed_row_scale, f + ": closed_row_scale needs an FP32 or FP64 near field");
 }
 }  // namespace
 
@@ -435,7 +440,7 @@ hm_status hm_hmatvec_profile(hm_ctx* ctx, int32_t count, const hm_matrix* const*
     for (const hm_matrix* M : mats) {
       const bool use_f32 = hi && M->has_hi;
       const int64_t sl = use_f32 ? 4 : (int64_t)dtype_size(M->lr_dtype);
-      const int64_t sd = (int64_t)dtype_size(M->dense_dtype);
+      const int64_t sd = use_f32 && M->dense_dtype == HM_BF16 ? 4 : (int64_t)dtype_size(M->dense_dtype);
       by1 += M->v_entries * sl + vecs * (M->n + M->Ktot);
       by2 += M->dense_entries * sd + M->u_entries * sl + vecs * (2 * M->n + M->Ktot);
     }

@@ -397,6 +397,13 @@ __global__ __launch_bounds__(256) void k_nf_pack(const NfDev* __restrict__ nf, G
   }
 }
 
+// BF16 near field from its FP32 copy (round to nearest even), so that the
+// two hold the same rounding of each view factor as the low-rank factors.
+__global__ __launch_bounds__(256) void k_to_bf16(const float* __restrict__ in, bf16_t* __restrict__ out, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < n) out[i] = f32_to_bf16(in[i]);
+}
+
 // U factor rows of one tile into a phase-2 panel (storage type and FP32 copy).
 template <class ST, class OT>
 __global__ __launch_bounds__(256) void k_u_pack(const URepack* __restrict__ ur, const void* const* __restrict__ stages,
@@ -533,6 +540,10 @@ void finish_job(AsmJob& J, const std::vector<DevBuf>& stages, hipStream_t s) {
   M->U.alloc(std::max<int64_t>(1, P.u_elems) * ls);
   M->V.alloc(std::max<int64_t>(1, P.v_elems) * ls);
   HM_HIP(hipMemsetAsync(M->dense.get(), 0, M->dense.bytes(), s));
+  if (p.dense_dtype == HM_BF16) {
+    M->dense_hi.alloc(std::max<int64_t>(1, P.dense_elems) * 4);
+    HM_HIP(hipMemsetAsync(M->dense_hi.get(), 0, M->dense_hi.bytes(), s));
+  }
   HM_HIP(hipMemsetAsync(M->U.get(), 0, M->U.bytes(), s));
   HM_HIP(hipMemsetAsync(M->V.get(), 0, M->V.bytes(), s));
   if (M->has_hi) {
@@ -547,9 +558,17 @@ void finish_job(AsmJob& J, const std::vector<DevBuf>& stages, hipStream_t s) {
     if (p.dense_dtype == HM_F64)
       hipLaunchKernelGGL(k_nf_pack<double>, dim3((unsigned)pk.nf.size()), dim3(256), 0, s, d_nf.get<NfDev>(), J.g,
                          M->dense.get<double>());
-    else
+    else if (p.dense_dtype == HM_F32)
       hipLaunchKernelGGL(k_nf_pack<float>, dim3((unsigned)pk.nf.size()), dim3(256), 0, s, d_nf.get<NfDev>(), J.g,
                          M->dense.get<float>());
+    else {
+      // FP32 copy first (also the padding zeros), then its BF16 rounding
+      const int64_t ne = std::max<int64_t>(1, P.dense_elems);
+      hipLaunchKernelGGL(k_nf_pack<float>, dim3((unsigned)pk.nf.size()), dim3(256), 0, s, d_nf.get<NfDev>(), J.g,
+                         M->dense_hi.get<float>());
+      hipLaunchKernelGGL(k_to_bf16, dim3((unsigned)((ne + 255) / 256)), dim3(256), 0, s, M->dense_hi.get<float>(),
+                         M->dense.get<bf16_t>(), ne);
+    }
     HM_HIP(hipGetLastError());
     HM_HIP(hipStreamSynchronize(s));
   }

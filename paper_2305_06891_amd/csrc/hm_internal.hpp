@@ -255,10 +255,11 @@ struct hm_matrix {
   int device = 0;
   int64_t n = 0;
   hm_dtype dense_dtype = HM_F32, lr_dtype = HM_F32;
-  bool has_hi = false;  // FP32 copies of BF16 factors
+  bool has_hi = false;  // FP32 copies of BF16 factors (and of a BF16 near field)
   std::vector<int32_t> perm;
   hm::DevBuf d_perm;                         // int32 perm
   hm::DevBuf dense, U, V, U_hi, V_hi;        // arenas
+  hm::DevBuf dense_hi;                       // FP32 copy of a BF16 near field
   int64_t dense_entries = 0, lr_entries = 0, Ktot = 0;
   int64_t u_entries = 0, v_entries = 0;  // sum k*m and sum k*n over low-rank blocks
   int64_t n_dense_blocks = 0, n_lr_blocks = 0, n_fallback = 0, rank_sum = 0;

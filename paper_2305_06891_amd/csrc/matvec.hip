@@ -329,7 +329,7 @@ void autotune_phase1_joint(const std::vector<hm_matrix*>& mats, hipStream_t s) {
 void autotune_phase1(hm_matrix& M, hipStream_t s) { autotune_phase1_joint({&M}, s); }
 
 int64_t matrix_bytes(const hm_matrix& M, bool hi) {
-  const size_t dsz = dtype_size(M.dense_dtype);
+  const size_t dsz = hi && M.has_hi && M.dense_dtype == HM_BF16 ? 4 : dtype_size(M.dense_dtype);
   const size_t lsz = hi && M.has_hi ? 4 : dtype_size(M.lr_dtype);
   return M.dense_entries * (int64_t)dsz + M.lr_entries * (int64_t)lsz;
 }
@@ -386,6 +386,7 @@ std::unique_ptr<Composition> make_composition(const std::vector<const hm_matrix*
     if (M.has_hi) {
       h.U = M.U_hi.get();
       h.V = M.V_hi.get();
+      if (M.dense_dtype == HM_BF16) h.dense = M.dense_hi.get();
     }
     C->slots_hi.push_back(h);
     C->bytes_lo += matrix_bytes(M, false);
@@ -1271,7 +1272,7 @@ void launch_typed(const Composition& C, int nrr, bool hi, const void* X, int64_t
   const SlotDev* slots = (hi ? C.d_slots_hi : C.d_slots_lo).get<SlotDev>();
   const int* sof = C.d_slot_of.get<int>();
   // 16 right-hand sides of FP32/BF16 entries: matrix cores (FP32 or FP64 sums)
-  constexpr bool mfma = NR == 16 && sizeof(DT) == 4 && sizeof(LT) <= 4;
+  constexpr bool mfma = NR == 16 && sizeof(DT) <= 4 && sizeof(LT) <= 4;
   if (ev) HM_HIP(hipEventRecord(ev[0], s));
   if constexpr (mfma) {
     HM_REQUIRE(C.xr.get() != nullptr, "matvec: 16-column composition without its row-major input buffer");
@@ -1350,15 +1351,17 @@ void launch_matvec(const Composition& C, int nrr, int vb, bool hi, const void* X
                "matvec: matrices of one batch must share storage types");
   const bool use_hi = hi && M0.has_hi;
   const hm_dtype lt = use_hi ? HM_F32 : M0.lr_dtype;
-  const hm_dtype dt = M0.dense_dtype;
+  const hm_dtype dt = use_hi && M0.dense_dtype == HM_BF16 ? HM_F32 : M0.dense_dtype;
   if (vb == 8) {
     if (dt == HM_F64 && lt == HM_F64) return launch_nr<double, double, double>(C, nrr, use_hi, X, ldx, Y, ldy, ep, slot_active, s, ev);
     if (dt == HM_F32 && lt == HM_F32) return launch_nr<float, float, double>(C, nrr, use_hi, X, ldx, Y, ldy, ep, slot_active, s, ev);
     if (dt == HM_F32 && lt == HM_BF16) return launch_nr<float, bf16_t, double>(C, nrr, use_hi, X, ldx, Y, ldy, ep, slot_active, s, ev);
     if (dt == HM_F64 && lt == HM_F32) return launch_nr<double, float, double>(C, nrr, use_hi, X, ldx, Y, ldy, ep, slot_active, s, ev);
+    if (dt == HM_BF16 && lt == HM_BF16) return launch_nr<bf16_t, bf16_t, double>(C, nrr, use_hi, X, ldx, Y, ldy, ep, slot_active, s, ev);
   } else {
     if (dt == HM_F32 && lt == HM_F32) return launch_nr<float, float, float>(C, nrr, use_hi, X, ldx, Y, ldy, ep, slot_active, s, ev);
     if (dt == HM_F32 && lt == HM_BF16) return launch_nr<float, bf16_t, float>(C, nrr, use_hi, X, ldx, Y, ldy, ep, slot_active, s, ev);
+    if (dt == HM_BF16 && lt == HM_BF16) return launch_nr<bf16_t, bf16_t, float>(C, nrr, use_hi, X, ldx, Y, ldy, ep, slot_active, s, ev);
     if (dt == HM_F64 && lt == HM_F64) return launch_nr<double, double, float>(C, nrr, use_hi, X, ldx, Y, ldy, ep, slot_active, s, ev);
   }
   fail(HM_EINVAL, "matvec: unsupported combination of storage and vector types");

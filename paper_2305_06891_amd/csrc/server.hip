@@ -627,6 +627,8 @@ hm_status hm_server_register_cavity(hm_server* s, uint64_t cid, const hm_tree* t
     for (int64_t i = 0; i < tree->n; ++i)
       HM_REQUIRE(eps_host[i] > 0.0 && eps_host[i] <= 1.0, "hm_server_register_cavity: eps must be in (0, 1]");
     HM_REQUIRE(ap->aca_tol > 0 && ap->aca_tol < 1 && ap->k_max >= 1, "hm_server_register_cavity: bad assembly parameters");
+    HM_REQUIRE(ap->dense_dtype != HM_BF16 || (ap->lowrank_dtype == HM_BF16 && ap->keep_f32_copy),
+               "hm_server_register_cavity: a BF16 near field needs BF16 factors and keep_f32_copy");
     auto c = std::make_unique<SrvCavity>();
     c->id = cid;
     c->tree = std::make_unique<hm_tree>(*tree);

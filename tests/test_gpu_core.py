@@ -185,15 +185,19 @@ def test_batched_equals_single_and_oracle(hm, ctx):
         assert eJ <= 1e-8 and eq <= 1e-8
 
 
-def test_mixed_precision_refinement(hm, ctx):
+@pytest.mark.parametrize("near", ["f32", "bf16"])
+def test_mixed_precision_refinement(hm, ctx, near):
     v, f = meshes.ellipsoid(14, (3.0, 2.0, 1.5))
     f = meshes.inward(f)
     nf = f.shape[0]
     rng = np.random.default_rng(21)
     eps = rng.uniform(0.1, 0.9, nf)
     T = rng.uniform(300, 1500, nf)
-    log("case: ellipsoid %d facets, BF16 factors + FP32 copy, refinement" % nf)
-    tree, M = build(hm, ctx, v, f, 64, 1.5, 1e-6, hm.HM_BF16, hm.HM_F32, keep=1)
+    # a BF16 near field keeps an FP32 copy too: FP32-vector products (the
+    # inner solves) read the BF16 arrays, FP64-vector ones (residuals) the copies
+    dense = hm.HM_F32 if near == "f32" else hm.HM_BF16
+    log("case: ellipsoid %d facets, BF16 factors + FP32 copy, %s near field, refinement" % (nf, near))
+    tree, M = build(hm, ctx, v, f, 64, 1.5, 1e-6, hm.HM_BF16, dense, keep=1)
     c, n, a, F = oracle_dense(v, f)
     rad = radiosity.DenseRadiosity(F, eps)
     p = hm.solve_params(rtol=1e-7, mixed_precision=1, ir_inner_rtol=1e-3)
@@ -203,6 +207,21 @@ def test_mixed_precision_refinement(hm, ctx):
                                                                info["rel_residual"], eJ, eq))
     assert info["status"] == hm.HM_OK
     assert eJ <= 1e-6 and eq <= 1e-6
+    if near == "bf16":
+        # products: FP32 vectors on the BF16 arrays within BF16 rounding of the
+        # FP32-copy product; FP64 vectors on the copies equal an all-FP32 matrix's
+        import torch
+        _, M32 = build(hm, ctx, v, f, 64, 1.5, 1e-6, hm.HM_F32, hm.HM_F32)
+        x = rng.uniform(0.5, 1.5, nf)
+        y_lo = to_np(hm.hm_hmatvec(ctx, M, dt(x).float(), torch.zeros(nf, dtype=torch.float32, device="cuda")))
+        y64 = to_np(hm.hm_hmatvec(ctx, M, dt(x), dt(np.zeros(nf)), use_f32_copy=True))
+        y32 = to_np(hm.hm_hmatvec(ctx, M32, dt(x), dt(np.zeros(nf))))
+        e_lo, e_hi = rel(y_lo, y64), rel(y64, y32)
+        log("BF16 near field: FP32-vector product vs FP64 one %.2e; FP64 product vs all-FP32 matrix %.2e"
+            % (e_lo, e_hi))
+        assert e_lo <= 4e-3 and e_hi <= 1e-12
+        with pytest.raises(Exception):
+            build(hm, ctx, v, f, 64, 1.5, 1e-6, hm.HM_BF16, hm.HM_BF16, keep=0)
 
 
 def test_transient_matches_oracle(hm, ctx):
