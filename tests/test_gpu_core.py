@@ -220,6 +220,23 @@ def test_mixed_precision_refinement(hm, ctx, near):
         log("BF16 near field: FP32-vector product vs FP64 one %.2e; FP64 product vs all-FP32 matrix %.2e"
             % (e_lo, e_hi))
         assert e_lo <= 4e-3 and e_hi <= 1e-12
+        # FP64 vectors on the BF16 arrays themselves: the FP32-vector product
+        # up to FP32 rounding
+        y64lo = to_np(hm.hm_hmatvec(ctx, M, dt(x), dt(np.zeros(nf))))
+        assert rel(y_lo, y64lo) <= 2e-6
+        # 16 columns (matrix cores, BF16 near-field panels; FP64 ones on the
+        # copies): every column equals the one-column product
+        X = rng.uniform(0.5, 1.5, (nf, 16))
+        for tdt, copy, tol in ((torch.float32, False, 2e-6), (torch.float64, True, 1e-13)):
+            Xt = torch.as_tensor(np.asfortranarray(X), dtype=tdt, device="cuda")
+            Y = to_np(hm.hm_hmatvec(ctx, M, Xt, torch.zeros_like(Xt), use_f32_copy=copy))
+            worst = 0.0
+            for j in range(16):
+                yj = to_np(hm.hm_hmatvec(ctx, M, Xt[:, j].contiguous(), torch.zeros(nf, dtype=tdt, device="cuda"),
+                                         use_f32_copy=copy))
+                worst = max(worst, rel(Y[:, j], yj))
+            log("BF16 near field, 16 columns %s (copies %d): worst column vs one-column %.2e" % (tdt, copy, worst))
+            assert worst <= tol
         with pytest.raises(Exception):
             build(hm, ctx, v, f, 64, 1.5, 1e-6, hm.HM_BF16, hm.HM_BF16, keep=0)
 
