@@ -188,8 +188,11 @@ void hm_matrix_destroy(hm_matrix* M);
 /* Y = alpha * F_H * X + beta * Y (Sec. 5.2: the block-wise product adds no
  * approximation beyond the stored blocks).  X, Y: DEVICE, n x nrhs
  * column-major, leading dims ldx, ldy, of type vec_dtype (HM_F64 or HM_F32).
- * 1 <= nrhs <= 16.  use_f32_copy = 1 reads the FP32 copy of BF16 factors.
- * Accumulation is in vec_dtype.  X and Y must not overlap. */
+ * 1 <= nrhs <= 16 (widths 3, 5-7 and 9-15 run in the kernels of the next
+ * width of 2, 4, 8 or 16, whose extra columns are neither read from X nor
+ * written to Y; 9-16 columns of FP32/BF16 entries run on the matrix cores).  use_f32_copy = 1 reads the FP32 copies of BF16 factors (and of a
+ * BF16 near field).  Accumulation is in vec_dtype.  X and Y must not
+ * overlap. */
 hm_status hm_hmatvec(hm_ctx* ctx, const hm_matrix* M, int32_t nrhs, hm_dtype vec_dtype, const void* X,
                      int64_t ldx, void* Y, int64_t ldy, double alpha, double beta);
 hm_status hm_hmatvec_ex(hm_ctx* ctx, const hm_matrix* M, int32_t nrhs, hm_dtype vec_dtype,
