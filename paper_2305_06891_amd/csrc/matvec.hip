@@ -600,6 +600,21 @@ __device__ __forceinline__ void panel_item(const MT* __restrict__ a, int m, int 
   }
 }
 
+// Row tile of phase-2 workgroup i among G.  Workgroups go to the eight
+// XCDs in turn (i to XCD i % 8), each XCD with its own L2; neighbouring row
+// tiles read many of the same input entries (x columns of shared near-field
+// blocks, t rows of shared low-rank blocks), so each XCD takes runs of
+// XCD_RUN consecutive tiles, the runs dealt out in turn (balanced like the
+// plain order at run granularity).  Tiles past the last full round keep
+// their index.  A renumbering only: every tile's result is the same.
+constexpr int XCD_COUNT = 8, XCD_RUN = 8;
+__device__ __forceinline__ int xcd_tile(int i, int G) {
+  constexpr int R = XCD_COUNT * XCD_RUN;
+  if (i >= (G / R) * R) return i;
+  const int x = i % XCD_COUNT, k = i / XCD_COUNT;
+  return ((k / XCD_RUN) * XCD_COUNT + x) * XCD_RUN + k % XCD_RUN;
+}
+
 // Phase 2: one workgroup of WG waves per row tile, lane = row of the tile;
 // the waves share the tile's items (each takes every WG-th) and add their
 // sums in LDS in wave order.  Compositions with many tiles and one or two
@@ -622,7 +637,7 @@ __global__ __launch_bounds__(64 * WG) void k_phase2(const SlotDev* __restrict__ 
   __shared__ VT lds_red[P2_WAVES][RJ][TILE];
   const int lane = threadIdx.x & 63;
   const int wv = uniform_int(threadIdx.x >> 6);  // wave index (uniform)
-  const int tile = blockIdx.x;
+  const int tile = xcd_tile(blockIdx.x, gridDim.x);  // uniform
   const SlotDev S = uniform_load(slots + uniform_load(slot_of + tile));
   if (slot_active && !uniform_int(*gbl(slot_active + S.slot))) return;  // uniform over the workgroup
   const P2Tile T = uniform_load(S.p2t + (tile - S.p2_tile_begin));
@@ -1200,7 +1215,7 @@ __global__ __launch_bounds__(64 * WG, sizeof(VT) == 4 ? 4 : 3) void k_phase2_mfm
   const int lane = threadIdx.x & 63;
   const int wv = uniform_int(threadIdx.x >> 6);  // wave index (uniform)
   const int li = lane & 15, lk = lane >> 4;
-  const int tile = blockIdx.x;
+  const int tile = xcd_tile(blockIdx.x, gridDim.x);  // uniform
   const SlotDev S = uniform_load(slots + uniform_load(slot_of + tile));
   if (slot_active && !uniform_int(*gbl(slot_active + S.slot))) return;  // uniform over the workgroup
   const P2Tile T = uniform_load(S.p2t + (tile - S.p2_tile_begin));
