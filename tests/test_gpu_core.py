@@ -76,6 +76,12 @@ def test_hmatvec_c1_fp64_matches_oracle_hmatrix(hm, ctx, c1):
     log("rel err vs oracle H-matrix %.3e, vs dense %.3e" % (e_h, e_d))
     assert e_h <= cav.aca_tol
     assert e_d <= 2e-8
+    # 16 columns of FP64 storage (vector-unit kernels, FP64 sums)
+    X16 = rng.uniform(0.5, 1.5, (cav.n, 16))
+    Y16 = to_np(hm.hm_hmatvec(ctx, M, dt(X16), dt(np.zeros_like(X16))))
+    e16 = rel(Y16, H.matvec(X16))
+    log("16 columns: rel err vs oracle H-matrix %.3e" % e16)
+    assert e16 <= cav.aca_tol
     FH = full_matrix(hm, ctx, M, cav.n)
     g = np.linalg.norm(FH - F) / np.linalg.norm(F)
     log("global |F_H - F|_F / |F|_F = %.3e (ACA tol 1e-8)" % g)
