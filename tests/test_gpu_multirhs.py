@@ -55,3 +55,27 @@ def test_sixteen_rhs_product_matches_single_rhs(hm, ctx, lr, vec):
             worst = max(worst, rel(to_np(Y[:, j]), to_np(y1)))
         log("nr=%d: worst column rel diff vs single-rhs %.2e" % (nr, worst))
         assert worst <= tol
+
+
+def test_sixteen_rhs_on_small_tiles(hm, ctx):
+    """Leaf 16: phase-2 row tiles of at most 16 rows and narrow phase-1
+    groups, so the matrix-core kernels run with one or two 16-wide tiles
+    (the other tile counts of the same kernels); each column against the
+    one-column product."""
+    import torch
+    v, f = meshes.ellipsoid(9, (3.0, 2.0, 1.0))
+    f = meshes.inward(f)
+    n = f.shape[0]
+    tree, M = build(hm, ctx, v, f, 16, 1.5, 1e-6, hm.HM_F32, hm.HM_F32, keep=0)
+    log("case: ellipsoid %d facets, leaf 16, FP32 storage, 16 columns" % n)
+    rng = np.random.default_rng(23)
+    X = rng.uniform(0.5, 1.5, (n, 16))
+    for tdt, tol in ((torch.float32, 2e-6), (torch.float64, 1e-13)):
+        Xt = torch.as_tensor(np.asfortranarray(X), dtype=tdt, device="cuda")
+        Y = to_np(hm.hm_hmatvec(ctx, M, Xt, torch.zeros_like(Xt)))
+        worst = 0.0
+        for j in range(16):
+            yj = to_np(hm.hm_hmatvec(ctx, M, Xt[:, j].contiguous(), torch.zeros(n, dtype=tdt, device="cuda")))
+            worst = max(worst, rel(Y[:, j], yj))
+        log("%s: worst column rel diff vs one-column %.2e" % (tdt, worst))
+        assert worst <= tol
