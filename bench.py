@@ -271,7 +271,8 @@ def run_kernels_only(args):
         cav = configs.c4_ellipsoid()
         c, nrm, area = hm.hm_facets_from_triangles(cav.v, cav.tri, orient=1)
         t = hm.hm_build_cluster_tree(ctx, c, nrm, area, cav.leaf, cav.eta)
-        M = hm.hm_assemble_hmatrix(ctx, t, cav.aca_tol, 256, hm.HM_F32, hm.HM_F32, autotune=1)
+        # the product's work split tuned on 16-column products (the transient's width)
+        M = hm.hm_assemble_hmatrix(ctx, t, cav.aca_tol, 256, hm.HM_F32, hm.HM_F32, autotune=16)
         torch.cuda.synchronize()
         p16 = hm.hm_hmatvec_profile(ctx, M, 16, hm.HM_F32, reps=10, flush_bytes=0)
         log("16-rhs product x10:", p16)
@@ -328,7 +329,8 @@ def run_c4(args):
     tree = hm.hm_build_cluster_tree(ctx, c, nrm, area, cav.leaf, cav.eta)
     t_tree = time.perf_counter() - t0
     t0 = time.perf_counter()
-    M = hm.hm_assemble_hmatrix(ctx, tree, cav.aca_tol, 256, hm.HM_F32, hm.HM_F32, autotune=1)
+    # the product's work split tuned on 16-column products (the transient's width)
+    M = hm.hm_assemble_hmatrix(ctx, tree, cav.aca_tol, 256, hm.HM_F32, hm.HM_F32, autotune=16)
     torch.cuda.synchronize()
     t_asm = time.perf_counter() - t0
     st = M.stats()

@@ -131,10 +131,14 @@ typedef struct {
                               (refinement residual), products with FP32 vectors the BF16 arrays */
   int32_t closed_row_scale;/* 1: closed-cavity row scaling of eqs. (32)-(34) (clamp the row sum
                               to [0,1], divide rows with non-zero clamped sum by it); default 0 */
-  int32_t autotune;        /* 1: time the candidate work splits of the product's first kernel
-                              (rows per item, bytes per wave task) on this matrix and keep the
-                              fastest; 0: fixed defaults (128 rows, 16 KB).  Results are the same
-                              bit for bit either way except for the order of partial sums. */
+  int32_t autotune;        /* k >= 1: time the candidate work splits of the product's first
+                              kernel (rows per item, bytes per wave task) on this matrix with
+                              products of k columns (1..16: the width it will mostly be applied
+                              to; with many columns longer items are candidates too, their
+                              partial sums costing k times more) and keep the fastest; 0: fixed
+                              defaults (128 rows, 16 KB).  Results are the same bit for bit
+                              either way except for the order of partial sums.  HM_EINVAL
+                              outside 0..16. */
 } hm_assembly_params;
 
 /* Evaluate the near field (every inadmissible leaf block, FP64 evaluation

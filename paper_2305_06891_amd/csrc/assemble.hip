@@ -785,11 +785,16 @@ std::vector<hm_matrix*> assemble_batch(hm_ctx& ctx, const std::vector<const hm_t
 
   // ---- phase-1 split
   std::vector<hm_matrix*> tuned;
+  int width = 1;  // the widest product the tuned matrices ask for
   for (AsmJob& J : jobs)
-    if (J.p.autotune) tuned.push_back(J.M.get());
-  if (tune_jointly && tuned.size() > 1) autotune_phase1_joint(tuned, s);
+    if (J.p.autotune) {
+      tuned.push_back(J.M.get());
+      width = std::max(width, (int)J.p.autotune);
+    }
+  if (tune_jointly && tuned.size() > 1) autotune_phase1_joint(tuned, s, width);
   else
-    for (hm_matrix* M : tuned) autotune_phase1(*M, s);
+    for (size_t j = 0, t = 0; j < jobs.size(); ++j)
+      if (jobs[j].p.autotune) autotune_phase1(*tuned[t++], s, (int)jobs[j].p.autotune);
   HM_HIP(hipStreamSynchronize(s));
   std::vector<hm_matrix*> out(nj);
   for (size_t j = 0; j < nj; ++j) out[j] = jobs[j].M.release();

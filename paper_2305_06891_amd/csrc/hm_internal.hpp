@@ -301,11 +301,12 @@ void plan_phase1(Plan& P, const P1Params& pp);
 // Re-split phase 1 and upload its lists (the matrix must not be in use).
 void replan_phase1(hm_matrix& M, const P1Params& pp, hipStream_t s);
 // Times the candidate phase-1 splits on M (FP32 vectors unless the factors
-// are FP64) and keeps the fastest.  Call before any composition of M exists.
-void autotune_phase1(hm_matrix& M, hipStream_t s);
+// are FP64; products of `width` columns, 1..16) and keeps the fastest.  Call
+// before any composition of M exists.
+void autotune_phase1(hm_matrix& M, hipStream_t s, int width = 1);
 // The same for several matrices multiplied together: one split for all,
 // timed on their batched product.
-void autotune_phase1_joint(const std::vector<hm_matrix*>& mats, hipStream_t s);
+void autotune_phase1_joint(const std::vector<hm_matrix*>& mats, hipStream_t s, int width = 1);
 // The host part of build_plan (no device calls): items, tasks, arena sizes.
 void plan_host(hm_matrix& M, const std::vector<struct LrInfo>& lr, const std::vector<BlockRef>& dn,
                const hm_tree& t, PackLists& pk);

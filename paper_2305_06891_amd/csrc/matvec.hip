@@ -263,7 +263,8 @@ __global__ void k_tune_flush(const float4* __restrict__ p, int64_t n4, float* __
   if (acc != acc) sink[0] = acc;
 }
 
-void autotune_phase1_joint(const std::vector<hm_matrix*>& mats, hipStream_t s) {
+void autotune_phase1_joint(const std::vector<hm_matrix*>& mats, hipStream_t s, int width) {
+  HM_REQUIRE(width >= 1 && width <= 16, "autotune: product width must be in 1..16");
   std::vector<hm_matrix*> ms;
   for (hm_matrix* M : mats)
     if (!M->plan.taus.empty()) ms.push_back(M);
@@ -279,13 +280,17 @@ void autotune_phase1_joint(const std::vector<hm_matrix*>& mats, hipStream_t s) {
   // factors that could stay in the last-level cache are timed after a read
   // of 512 MB, as in the solve where phase 2 runs in between
   const int64_t flush_bytes = vbytes > (16 << 20) ? (int64_t)512 << 20 : 0;
-  DevBuf X((size_t)n * vb), Y((size_t)n * vb), flush(flush_bytes), sink(16);
-  HM_HIP(hipMemsetAsync(X.get(), 0, (size_t)n * vb, s));
+  // products of the width the matrices will mostly see: with many columns
+  // the partial sums of split column clusters cost as many times more, so
+  // longer items are candidates too
+  const int W = pad_width(width);
+  DevBuf X((size_t)n * W * vb), Y((size_t)n * W * vb), flush(flush_bytes), sink(16);
+  HM_HIP(hipMemsetAsync(X.get(), 0, (size_t)n * W * vb, s));
   if (flush_bytes) HM_HIP(hipMemsetAsync(flush.get(), 0, (size_t)flush_bytes, s));
   const std::vector<const hm_matrix*> cms(ms.begin(), ms.end());
   hipEvent_t ev[3];
   for (auto& e : ev) HM_HIP(hipEventCreate(&e));
-  const int rows[] = {64, 128, 256};
+  const std::vector<int> rows = width > 1 ? std::vector<int>{128, 256, 512, 1024} : std::vector<int>{64, 128, 256};
   const int task[] = {0, 8 << 10, 16 << 10, 32 << 10, 64 << 10};
   P1Params best = ms[0]->plan.p1p;
   double best_us = 1e30;
@@ -296,14 +301,14 @@ void autotune_phase1_joint(const std::vector<hm_matrix*>& mats, hipStream_t s) {
         pp.rows = r;
         pp.task_bytes = tb;
         for (hm_matrix* M : ms) replan_phase1(*M, pp, s);
-        auto comp = make_composition(cms, 1, vb, s);
+        auto comp = make_composition(cms, W, vb, s);
         double tot = 0;
         const int reps = 6;
         for (int k = 0; k < reps + 1; ++k) {
           if (flush_bytes)
             hipLaunchKernelGGL(k_tune_flush, dim3(1024), dim3(256), 0, s, flush.get<float4>(), flush_bytes / 16,
                                sink.get<float>());
-          launch_matvec(*comp, 1, vb, false, X.get(), n, Y.get(), n, Epilogue{}, nullptr, s, ev);
+          launch_matvec(*comp, width, vb, false, X.get(), n, Y.get(), n, Epilogue{}, nullptr, s, ev);
           HM_HIP(hipEventSynchronize(ev[2]));
           float a = 0;
           HM_HIP(hipEventElapsedTime(&a, ev[0], ev[1]));
@@ -326,7 +331,7 @@ void autotune_phase1_joint(const std::vector<hm_matrix*>& mats, hipStream_t s) {
   }
 }
 
-void autotune_phase1(hm_matrix& M, hipStream_t s) { autotune_phase1_joint({&M}, s); }
+void autotune_phase1(hm_matrix& M, hipStream_t s, int width) { autotune_phase1_joint({&M}, s, width); }
 
 int64_t matrix_bytes(const hm_matrix& M, bool hi) {
   const size_t dsz = hi && M.has_hi && M.dense_dtype == HM_BF16 ? 4 : dtype_size(M.dense_dtype);

@@ -155,22 +155,29 @@ def test_c3_batch_members_equal_their_alone_solves(c3):
         assert np.array_equal(Jx[k], Ja) and np.array_equal(qx[k], qa)
 
 
-def test_autotuned_and_fixed_splits_give_the_same_product(hm, ctx):
+@pytest.mark.parametrize("width", [1, 16])
+def test_autotuned_and_fixed_splits_give_the_same_product(hm, ctx, width):
+    """The split tuned on products of 1 or 16 columns changes only the order
+    of partial sums (16: FP32 storage, so the tuning times matrix-core
+    products; compared with FP64 vectors on the FP32 entries)."""
     import torch
     cav = configs.c2_cylinder()
     t = _tree(hm, ctx, cav)
-    log("case: c2 FP64 product, fixed vs autotuned phase-1 split")
-    Ma = hm.hm_assemble_hmatrix(ctx, t, cav.aca_tol, 256, hm.HM_F64, hm.HM_F64, autotune=1)
-    Mf = hm.hm_assemble_hmatrix(ctx, t, cav.aca_tol, 256, hm.HM_F64, hm.HM_F64, autotune=0)
-    x = torch.as_tensor(np.random.default_rng(3).uniform(0.5, 1.5, (cav.n, 3)), device="cuda").T.contiguous().T
+    st = hm.HM_F64 if width == 1 else hm.HM_F32
+    log("case: c2 product, fixed vs phase-1 split autotuned on %d-column products" % width)
+    Ma = hm.hm_assemble_hmatrix(ctx, t, cav.aca_tol, 256, st, st, autotune=width)
+    Mf = hm.hm_assemble_hmatrix(ctx, t, cav.aca_tol, 256, st, st, autotune=0)
+    x = torch.as_tensor(np.random.default_rng(3).uniform(0.5, 1.5, (cav.n, 16)), device="cuda").T.contiguous().T
     ya = torch.zeros_like(x)
     yf = torch.zeros_like(x)
     hm.hm_hmatvec(ctx, Ma, x, ya)
     hm.hm_hmatvec(ctx, Mf, x, yf)
     e = rel(to_np(ya), to_np(yf))
     log("tuning %s vs %s: rel diff %.2e" % (Ma.tuning(), Mf.tuning(), e))
-    assert Mf.tuning()["p1_us"] == 0.0
+    assert Mf.tuning()["p1_us"] == 0.0 and Ma.tuning()["p1_us"] > 0.0
     assert e <= 1e-13
+    with pytest.raises(Exception):
+        hm.hm_assemble_hmatrix(ctx, t, cav.aca_tol, 256, st, st, autotune=17)
 
 
 def test_batched_profile_counts_the_bytes_of_every_matrix(hm, ctx):
