@@ -244,6 +244,30 @@ def run_c3(args):
                      "bytes_device_mixed": sum(s["bytes_device"] for s in stx),
                      "n_fallback": sum(s["n_fallback"] for s in stx), "max_rank": max(s["max_rank"] for s in stx)}
     out["assembly_s"] = {"mixed_batched": t_asm, "fp32_one_by_one": t_asm32, "trees": t_tree}
+
+    # --- the same batch with a BF16 near field too (FP32 copies for the
+    # residual): fewer bytes per inner product, at a lower share of HBM peak
+    del M32
+    Mb = hm.hm_assemble_hmatrix_batched(ctx, trees, [cav.aca_tol for cav in cavs], 256, hm.HM_BF16, hm.HM_BF16,
+                                        keep_f32_copy=1, autotune=1)
+    for _ in range(args.warmup):
+        hm.hm_solve_radiosity_batched(ctx, Mb, eps, T, hm.SIGMA, pmx, J, q)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        _, _, infm = hm.hm_solve_radiosity_batched(ctx, Mb, eps, T, hm.SIGMA, pmx, J, q)
+    torch.cuda.synchronize()
+    rate_bn = len(cavs) * args.steps / (time.perf_counter() - t0)
+    profb = hm.hm_hmatvec_profile(ctx, Mb, 1, hm.HM_F32, reps=20, flush_bytes=0)
+    rb = roofline(profb)
+    log("batched mixed, bf16 near field: %.1f solves/s; outer %d inner %d; product %s"
+        % (rate_bn, infm[0]["outer_iters"], infm[0]["iters"], profb))
+    out["bf16_near_field"] = {"value": rate_bn, "unit": "solves/s", "outer_iters": infm[0]["outer_iters"],
+                              "inner_iters": infm[0]["iters"],
+                              "worst_rel_residual": max(i["rel_residual"] for i in infm),
+                              "matvec_ms": rb["matvec_ms"], "matvec_GBps": rb["matvec_GBps"],
+                              "matvec_frac": rb["matvec_frac"]}
+    del Mb
     if not args.no_cpu_baseline:
         sample = min(cavs, key=lambda c: abs(c.n - 5000))
         out["cpu_baseline"] = cpu_baseline_dense(sample, sizes)
