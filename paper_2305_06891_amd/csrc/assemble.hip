@@ -43,8 +43,9 @@ struct AcaDev {
   double tol;                   // relative ACA tolerance of the block's cavity
 };
 
-constexpr int ACA_T = 256;
-constexpr int ACA_W = ACA_T / 64;
+constexpr int ACA_T = 256;        // threads per workgroup of k_aca
+constexpr int ACA_T_HUGE = 512;   // ... for blocks with m + n >= ACA_HUGE
+constexpr int ACA_HUGE = 4096;
 constexpr int ACA_KMAX = 1024;
 
 // (|value|, index) maximum over the workgroup: larger magnitude wins, the
@@ -60,6 +61,7 @@ __device__ inline ArgMax better(ArgMax a, ArgMax b) {
   return a;
 }
 
+template <int W>
 __device__ ArgMax block_argmax(ArgMax v, ArgMax* sh) {
   for (int o = 32; o > 0; o >>= 1) {
     ArgMax w;
@@ -73,12 +75,12 @@ __device__ ArgMax block_argmax(ArgMax v, ArgMax* sh) {
   if ((threadIdx.x & 63) == 0) sh[wid] = v;
   __syncthreads();
   ArgMax r = sh[0];
-  for (int w = 1; w < ACA_W; ++w) r = better(r, sh[w]);
+  for (int w = 1; w < W; ++w) r = better(r, sh[w]);
   return r;
 }
 
-// Sum of NV values over the workgroup, fixed order (waves 0..3).
-template <int NV>
+// Sum of NV values over the W waves of the workgroup, fixed order.
+template <int W, int NV>
 __device__ void block_sum(double* v, double* sh) {
 #pragma unroll
   for (int q = 0; q < NV; ++q) v[q] = wave_sum(v[q]);
@@ -91,7 +93,7 @@ __device__ void block_sum(double* v, double* sh) {
 #pragma unroll
   for (int q = 0; q < NV; ++q) {
     double s = sh[q];
-    for (int w = 1; w < ACA_W; ++w) s += sh[w * NV + q];
+    for (int w = 1; w < W; ++w) s += sh[w * NV + q];
     v[q] = s;
   }
 }
@@ -114,13 +116,19 @@ __device__ __forceinline__ double sub_terms(double r, const double* c, const dou
   return r;
 }
 
-// Partial-pivoting ACA of one admissible block per workgroup, in FP64.
-// U (m x kcap) and V (n x kcap) are column-major scratch; on exit rank[b]
-// holds k and status[b] is 1 when the stop test |u||v| <= tol |sum u v^T|_F
-// was met (0 when the rank cap was reached first).
-__global__ __launch_bounds__(ACA_T) void k_aca(const AcaDev* __restrict__ blocks, Geo g,
-                                               double* __restrict__ scratch, int* __restrict__ flags,
-                                               int* __restrict__ rank, int* __restrict__ status) {
+// Partial-pivoting ACA of one admissible block per workgroup of T threads,
+// in FP64.  U (m x kcap) and V (n x kcap) are column-major scratch; on exit
+// rank[b] holds k and status[b] is 1 when the stop test |u||v| <= tol
+// |sum u v^T|_F was met (0 when the rank cap was reached first).  The
+// crosses of a block are sequential, so a launch lasts as long as its
+// largest blocks: those get T = 512 (8 waves, two per SIMD; each cross's row
+// and column work spread twice as wide; 1024 threads would spill at the
+// 128 registers they leave a thread), the others T = 256.
+template <int T>
+__global__ __launch_bounds__(T) void k_aca(const AcaDev* __restrict__ blocks, Geo g,
+                                           double* __restrict__ scratch, int* __restrict__ flags,
+                                           int* __restrict__ rank, int* __restrict__ status) {
+  constexpr int ACA_T = T, ACA_W = T / 64;
   __shared__ double coef[ACA_KMAX];
   __shared__ ArgMax sh_am[ACA_W];
   __shared__ double sh_sum[ACA_W * 16];
@@ -149,7 +157,7 @@ __global__ __launch_bounds__(ACA_T) void k_aca(const AcaDev* __restrict__ blocks
       const double a = fabs(r);
       if (a > am.mag || (a == am.mag && j < am.idx)) am = ArgMax{a, r, j};
     }
-    am = block_argmax(am, sh_am);
+    am = block_argmax<ACA_W>(am, sh_am);
     const int jp = am.idx;
     const double rj = am.val;
     if (rj == 0.0) {
@@ -159,7 +167,7 @@ __global__ __launch_bounds__(ACA_T) void k_aca(const AcaDev* __restrict__ blocks
       ArgMax nx{-1.0, 0.0, 0x7fffffff};
       for (int ii = tid; ii < m; ii += ACA_T)
         if (!used[ii] && ii < nx.idx) nx = ArgMax{0.0, 0.0, ii};
-      nx = block_argmax(nx, sh_am);
+      nx = block_argmax<ACA_W>(nx, sh_am);
       if (nx.idx == 0x7fffffff) { conv = 1; break; }
       i = nx.idx;
       continue;
@@ -186,7 +194,7 @@ __global__ __launch_bounds__(ACA_T) void k_aca(const AcaDev* __restrict__ blocks
     for (int j = tid; j < n; j += ACA_T) nv2 += vk[j] * vk[j];
     {
       double t2[2] = {nu2, nv2};
-      block_sum<2>(t2, sh_sum);
+      block_sum<ACA_W, 2>(t2, sh_sum);
       nu2 = t2[0];
       nv2 = t2[1];
     }
@@ -209,14 +217,14 @@ __global__ __launch_bounds__(ACA_T) void k_aca(const AcaDev* __restrict__ blocks
         for (int q = 0; q < 8; ++q)
           if (q < nl) d[8 + q] += V[(int64_t)(l0 + q) * n + j] * v;
       }
-      block_sum<16>(d, sh_sum);
+      block_sum<ACA_W, 16>(d, sh_sum);
       for (int q = 0; q < nl; ++q) cross += d[q] * d[8 + q];
     }
     s2 += nu2 * nv2 + 2.0 * cross;
     ++k;
     if (sqrt(nu2 * nv2) <= tol * sqrt(fmax(s2, 0.0))) { conv = 1; break; }
     if (k >= b.kcap) { conv = 0; break; }
-    nx = block_argmax(nx, sh_am);
+    nx = block_argmax<ACA_W>(nx, sh_am);
     if (nx.idx == 0x7fffffff) { conv = 1; break; }
     i = nx.idx;
   }
@@ -609,9 +617,31 @@ void finish_job(AsmJob& J, const std::vector<DevBuf>& stages, hipStream_t s) {
 // its cavity is assembled alone or with others.  With tune_jointly, the
 // matrices whose autotune flag is set get one phase-1 split, timed on their
 // batched product; otherwise each such matrix is tuned alone.
+// A second stream (default priority) and the events that fork it from and
+// join it to the caller's stream, for the launch of the largest ACA blocks,
+// which then runs beside the launch of the others.
+struct SideStream {
+  hipStream_t st = nullptr;
+  hipEvent_t fork = nullptr, join = nullptr;
+  SideStream() {
+    HM_HIP(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+    HM_HIP(hipEventCreateWithFlags(&fork, hipEventDisableTiming));
+    HM_HIP(hipEventCreateWithFlags(&join, hipEventDisableTiming));
+  }
+  ~SideStream() {
+    if (st) (void)hipStreamSynchronize(st);
+    if (fork) (void)hipEventDestroy(fork);
+    if (join) (void)hipEventDestroy(join);
+    if (st) (void)hipStreamDestroy(st);
+  }
+  SideStream(const SideStream&) = delete;
+  SideStream& operator=(const SideStream&) = delete;
+};
+
 std::vector<hm_matrix*> assemble_batch(hm_ctx& ctx, const std::vector<const hm_tree*>& trees,
                                        const std::vector<hm_assembly_params>& ps, bool tune_jointly) {
   hipStream_t s = ctx.stream;
+  std::unique_ptr<SideStream> side;  // created with the first launch of the largest blocks
   const size_t nj = trees.size();
   std::vector<AsmJob> jobs(nj);
   int64_t ntot = 0;
@@ -663,7 +693,7 @@ std::vector<hm_matrix*> assemble_batch(hm_ctx& ctx, const std::vector<const hm_t
   const int64_t budget = std::max<int64_t>(256ll << 20, std::min<int64_t>(8ll << 30, (int64_t)free_b / 4));
   std::vector<DevBuf> stages;
   std::vector<size_t> stage_last;  // last job with factors in each stage buffer
-  DevBuf scratch, flags, d_blk, d_blk_small, d_rank, d_status, d_cd;
+  DevBuf scratch, flags, d_blk, d_blk_small, d_blk_huge, d_rank, d_status, d_cd;
   size_t jpos = 0, bpos = 0, next_finish = 0;
   auto finish_ready = [&]() {
     while (next_finish < nj && jobs[next_finish].lr_done == jobs[next_finish].t->lowrank.size()) {
@@ -700,24 +730,41 @@ std::vector<hm_matrix*> assemble_batch(hm_ctx& ctx, const std::vector<const hm_t
     }
     HM_REQUIRE(!batch.empty(), "assemble: empty ACA batch");
     // blocks of at most 64 x 64 (rank cap <= 32): one wave each; larger ones:
-    // one workgroup each, largest first for the hardware dispatcher
-    std::vector<AcaDev> small, large;
+    // one workgroup each (512 threads from m + n >= ACA_HUGE), largest
+    // first for the hardware dispatcher
+    std::vector<AcaDev> small, large, huge;
     for (size_t q = 0; q < batch.size(); ++q) {
       batch[q].out = (int32_t)q;
       const AcaDev& a = batch[q];
       if (a.re - a.rb <= 64 && a.ce - a.cb <= 64 && a.kcap <= ACAW_K) small.push_back(a);
+      else if ((a.re - a.rb) + (a.ce - a.cb) >= ACA_HUGE) huge.push_back(a);
       else large.push_back(a);
     }
-    std::stable_sort(large.begin(), large.end(), [](const AcaDev& x, const AcaDev& y) {
+    auto by_size = [](const AcaDev& x, const AcaDev& y) {
       return (int64_t)(x.re - x.rb) * (x.ce - x.cb) > (int64_t)(y.re - y.rb) * (y.ce - y.cb);
-    });
+    };
+    std::stable_sort(large.begin(), large.end(), by_size);
+    std::stable_sort(huge.begin(), huge.end(), by_size);
     if ((size_t)sd * 8 > scratch.bytes()) scratch.alloc((size_t)sd * 8);
     if ((size_t)sf * 4 > flags.bytes()) flags.alloc((size_t)sf * 4);
     d_rank.alloc(batch.size() * 4);
     d_status.alloc(batch.size() * 4);
+    if (!huge.empty()) {
+      // on the side stream, after everything queued so far on s (uploads,
+      // scratch), joined back into s before the ranks are read
+      upload(d_blk_huge, huge, s);
+      if (!side) side = std::make_unique<SideStream>();
+      HM_HIP(hipEventRecord(side->fork, s));
+      HM_HIP(hipStreamWaitEvent(side->st, side->fork, 0));
+      hipLaunchKernelGGL(k_aca<ACA_T_HUGE>, dim3((unsigned)huge.size()), dim3(ACA_T_HUGE), 0, side->st,
+                         d_blk_huge.get<AcaDev>(), g, scratch.get<double>(), flags.get<int>(), d_rank.get<int>(),
+                         d_status.get<int>());
+      HM_HIP(hipGetLastError());
+      HM_HIP(hipEventRecord(side->join, side->st));
+    }
     if (!large.empty()) {
       upload(d_blk, large, s);
-      hipLaunchKernelGGL(k_aca, dim3((unsigned)large.size()), dim3(ACA_T), 0, s, d_blk.get<AcaDev>(), g,
+      hipLaunchKernelGGL(k_aca<ACA_T>, dim3((unsigned)large.size()), dim3(ACA_T), 0, s, d_blk.get<AcaDev>(), g,
                          scratch.get<double>(), flags.get<int>(), d_rank.get<int>(), d_status.get<int>());
       HM_HIP(hipGetLastError());
     }
@@ -728,6 +775,7 @@ std::vector<hm_matrix*> assemble_batch(hm_ctx& ctx, const std::vector<const hm_t
                          d_rank.get<int>(), d_status.get<int>());
       HM_HIP(hipGetLastError());
     }
+    if (!huge.empty()) HM_HIP(hipStreamWaitEvent(s, side->join, 0));
     std::vector<int> rk(batch.size()), st(batch.size());
     HM_HIP(hipMemcpyAsync(rk.data(), d_rank.get(), rk.size() * 4, hipMemcpyDeviceToHost, s));
     HM_HIP(hipMemcpyAsync(st.data(), d_status.get(), st.size() * 4, hipMemcpyDeviceToHost, s));
