@@ -52,7 +52,9 @@ struct Batch {
   void scatter(const double* src, int ncol, hipStream_t s);
   void ensure_g(const std::vector<const double*>& eps_user, hipStream_t s);
   void prepare_rhs(double sigma, const hm_solve_params& p, hipStream_t s);
-  SolveResult solve_prepared(const hm_solve_params& p, hipStream_t s, bool warm = false);
+  // report: with FP32 vectors, measure the final residual with FP64 vectors
+  // (one more product; callers that check their own residual skip it)
+  SolveResult solve_prepared(const hm_solve_params& p, hipStream_t s, bool warm = false, bool report = true);
   void residual64(bool hi, hipStream_t s);
   void flux(double sigma, hipStream_t s);
   SolveResult solve(const std::vector<const double*>& eps, const std::vector<const double*>& T,
