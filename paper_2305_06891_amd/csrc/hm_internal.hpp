@@ -322,6 +322,8 @@ struct Epilogue {
   double a_acc = 1.0, a_x = 0.0, a_z = 0.0;
   const void* z = nullptr;
   int64_t ldz = 0;
+  void* acc_out = nullptr;  // optional: the plain product F x as well (leading dim ld_acc)
+  int64_t ld_acc = 0;
 };
 
 // nrr: right-hand sides actually present (<= C.nr, the padded width).

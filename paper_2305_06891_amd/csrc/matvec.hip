@@ -422,6 +422,8 @@ struct EpiDev {
   VT a_acc, a_x, a_z;
   const VT* z;
   int64_t ldz;
+  VT* acc_out;  // optional second output: the plain product
+  int64_t ld_acc;
 };
 
 // Four consecutive panel entries in their stored type (one 8-32 byte load);
@@ -483,6 +485,7 @@ __device__ __forceinline__ void epilogue_store(int row, int lane, int m, int nrr
     if (ep.a_x != VT(0)) o += ep.a_x * gbl(X)[row + j * ldx];
     if (ep.a_z != VT(0)) o += ep.a_z * gbl(ep.z)[row + j * ep.ldz];
     gbl_w(Y)[row + j * ldy] = o;
+    if (ep.acc_out) gbl_w(ep.acc_out)[row + j * ep.ld_acc] = acc[j];
   }
 }
 
@@ -698,6 +701,7 @@ __global__ __launch_bounds__(64 * WG) void k_phase2(const SlotDev* __restrict__ 
     EpiDev<VT> e = ep;
     if (e.rowscale) e.rowscale += S.xoff;
     if (e.z) e.z += S.xoff;
+    if (e.acc_out) e.acc_out += S.xoff;
     epilogue_store<VT, NR>(T.row0 + lane, lane, T.m, nrr, sum, Xs, ldx, Ys, ldy, e);
   }
 }
@@ -1276,6 +1280,7 @@ __global__ __launch_bounds__(64 * WG, sizeof(VT) == 4 ? 4 : 3) void k_phase2_mfm
     EpiDev<VT> e = ep;
     if (e.rowscale) e.rowscale += S.xoff;
     if (e.z) e.z += S.xoff;
+    if (e.acc_out) e.acc_out += S.xoff;
     epilogue_store<VT, NR>(T.row0 + lane, lane, T.m, nrr, sum, Xs, ldx, Ys, ldy, e);
   }
 }
@@ -1322,6 +1327,8 @@ void launch_typed(const Composition& C, int nrr, bool hi, const void* X, int64_t
   e.a_z = (VT)ep.a_z;
   e.z = (const VT*)ep.z;
   e.ldz = ep.ldz;
+  e.acc_out = (VT*)ep.acc_out;
+  e.ld_acc = ep.ld_acc;
   if (C.p2_tiles > 0) {
     if constexpr (mfma)
       hipLaunchKernelGGL((k_phase2_mfma<DT, LT, VT, P2M_WAVES>), dim3(C.p2_tiles), dim3(64 * P2M_WAVES), 0, s, slots,

@@ -246,10 +246,10 @@ SolveResult Batch::solve(const std::vector<const double*>& eps_user, const std::
   io(T_user, {}, 0, &ldT, s);
   gather(Tp.get<double>(), nrhs, W, s);
   prepare_rhs(sigma, p, s);
-  R = solve_prepared(p, s);
+  R = solve_prepared(p, s, false, true, want_q);
   if (want_q) {
     ensure_g(eps_user, s);
-    flux(sigma, s);
+    flux(sigma, s, R.fx);
   }
   io({}, J_user, 0, &ldJ, s);
   scatter(x64.get<double>(), nrhs, s);
@@ -271,7 +271,7 @@ void Batch::prepare_rhs(double sigma, const hm_solve_params& p, hipStream_t s) {
   HM_HIP(hipGetLastError());
 }
 
-SolveResult Batch::solve_prepared(const hm_solve_params& p, hipStream_t s, bool warm, bool report) {
+SolveResult Batch::solve_prepared(const hm_solve_params& p, hipStream_t s, bool warm, bool report, bool keep_fx) {
   SolveResult R;
   const int64_t tot = N * W;
   const unsigned gb_ = (unsigned)((tot + 255) / 256);
@@ -321,8 +321,12 @@ SolveResult Batch::solve_prepared(const hm_solve_params& p, hipStream_t s, bool 
       if (outer == 0 && !warm) {
         // x = 0: the residual is b itself, no product needed
         HM_HIP(hipMemcpyAsync(r64.get(), b64.get(), tot * 8, hipMemcpyDeviceToDevice, s));
+        R.fx = false;
       } else {
-        residual64(true, s);
+        // with the flux wanted, the product also leaves F x in H64: the last
+        // residual is taken at the final iterate, with the flux's operator
+        residual64(true, s, keep_fx);
+        R.fx = keep_fx;
         R.matvecs++;
         R.bytes += C->bytes_hi;
       }
@@ -352,6 +356,7 @@ SolveResult Batch::solve_prepared(const hm_solve_params& p, hipStream_t s, bool 
       GmresStats st = gmres(K4, false, omeps32.get(), b32.get(), x32.get(), p.ir_inner_rtol, p.max_iter, s,
                             p.use_graphs != 0, GM_X0_ZERO | GM_TRUST_ESTIMATE);
       hipLaunchKernelGGL(k_acc<float>, dim3(gb_), dim3(256), 0, s, x32.get<float>(), x64.get<double>(), tot);
+      R.fx = false;  // x changed
       R.iters += st.iters;
       R.matvecs += st.matvecs;
       R.bytes += st.bytes;
@@ -364,7 +369,7 @@ SolveResult Batch::solve_prepared(const hm_solve_params& p, hipStream_t s, bool 
 }
 
 // r64 = b64 - C x64 with FP64 vectors (hi: FP32 copy of BF16 factors)
-void Batch::residual64(bool hi, hipStream_t s) {
+void Batch::residual64(bool hi, hipStream_t s, bool keep_fx) {
   Epilogue ep;
   ep.rowscale = omeps64.get();
   ep.a_acc = 1.0;
@@ -372,12 +377,16 @@ void Batch::residual64(bool hi, hipStream_t s) {
   ep.a_z = 1.0;
   ep.z = b64.get();
   ep.ldz = N;
+  if (keep_fx) {
+    ep.acc_out = H64.get();
+    ep.ld_acc = N;
+  }
   launch_matvec(*C, nrhs, 8, hi, x64.get(), N, r64.get(), N, ep, nullptr, s);
 }
 
 // H64 <- q = eps (F J - sigma T^4 g), J = x64
-void Batch::flux(double sigma, hipStream_t s) {
-  launch_matvec(*C, nrhs, 8, true, x64.get(), N, H64.get(), N, Epilogue{}, nullptr, s);
+void Batch::flux(double sigma, hipStream_t s, bool have_fx) {
+  if (!have_fx) launch_matvec(*C, nrhs, 8, true, x64.get(), N, H64.get(), N, Epilogue{}, nullptr, s);
   hipLaunchKernelGGL(k_flux, grid_rows(N, nrhs), dim3(256), 0, s, epsp.get<double>(), Tp.get<double>(),
                      H64.get<double>(), g.get<double>(), N, nrhs, sigma, H64.get<double>());
   HM_HIP(hipGetLastError());

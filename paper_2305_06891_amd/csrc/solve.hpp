@@ -19,6 +19,7 @@ struct SolveResult {
   int iters = 0, outer = 0, matvecs = 0;
   int64_t bytes = 0;
   bool converged = true;
+  bool fx = false;              // the plain product F x of the final iterate is in H64
   std::vector<double> rel_res;  // per system (slot-major, then column)
 };
 
@@ -54,9 +55,12 @@ struct Batch {
   void prepare_rhs(double sigma, const hm_solve_params& p, hipStream_t s);
   // report: with FP32 vectors, measure the final residual with FP64 vectors
   // (one more product; callers that check their own residual skip it)
-  SolveResult solve_prepared(const hm_solve_params& p, hipStream_t s, bool warm = false, bool report = true);
-  void residual64(bool hi, hipStream_t s);
-  void flux(double sigma, hipStream_t s);
+  // keep_fx: with refinement, let the residual products leave F x in H64 too
+  // (the flux then needs no product of its own)
+  SolveResult solve_prepared(const hm_solve_params& p, hipStream_t s, bool warm = false, bool report = true,
+                             bool keep_fx = false);
+  void residual64(bool hi, hipStream_t s, bool keep_fx = false);
+  void flux(double sigma, hipStream_t s, bool have_fx = false);
   SolveResult solve(const std::vector<const double*>& eps, const std::vector<const double*>& T,
                     const std::vector<int64_t>& ldT, double sigma, const hm_solve_params& p,
                     const std::vector<double*>& J, const std::vector<int64_t>& ldJ, const std::vector<double*>& q,
