@@ -370,7 +370,9 @@ void hm_server::round(std::vector<SrvReq*>& act) {
     HM_HIP(hipMemcpyAsync(om64.get<double>() + off, cs[q]->om64.get(), n * 8, hipMemcpyDeviceToDevice, s));
     HM_HIP(hipMemcpyAsync(om32.get<float>() + off, cs[q]->om32.get(), n * 4, hipMemcpyDeviceToDevice, s));
   }
-  // FP64 residual r = b - C J with the most accurate stored factors
+  // FP64 residual r = b - C J with the most accurate stored factors; the
+  // product also leaves H = F J, the flux of the requests that finish now
+  DevBuf H(blk * 8);
   Epilogue ep;
   ep.rowscale = om64.get();
   ep.a_acc = 1.0;
@@ -378,6 +380,8 @@ void hm_server::round(std::vector<SrvReq*>& act) {
   ep.a_z = 1.0;
   ep.z = b64.get();
   ep.ldz = N;
+  ep.acc_out = H.get();
+  ep.ld_acc = N;
   launch_matvec(*C, W, 8, true, x64.get(), N, r64.get(), N, ep, nullptr, s);
   Krylov K8;
   K8.init(*C, S, 8, 1, s);
@@ -385,7 +389,7 @@ void hm_server::round(std::vector<SrvReq*>& act) {
   block_norms(K8, r64.get(), rn, s);
   block_norms(K8, b64.get(), bn, s);
   // per request: converged?
-  std::vector<int> fin(act.size(), 1), slot_active(act.size(), 0);
+  std::vector<int> fin(act.size(), 1);
   std::vector<double> worst(act.size(), 0.0);
   for (int k = 0; k < S.size(); ++k) {
     const int q = S.sys[k].slot;
@@ -401,14 +405,8 @@ void hm_server::round(std::vector<SrvReq*>& act) {
   }
   // finishing requests: flux and results
   bool any_fin = false;
-  for (size_t q = 0; q < act.size(); ++q) {
-    slot_active[q] = fin[q];
-    any_fin |= fin[q] != 0;
-  }
+  for (size_t q = 0; q < act.size(); ++q) any_fin |= fin[q] != 0;
   if (any_fin) {
-    DevBuf H(blk * 8), d_sa(act.size() * 4);
-    HM_HIP(hipMemcpyAsync(d_sa.get(), slot_active.data(), act.size() * 4, hipMemcpyHostToDevice, s));
-    launch_matvec(*C, W, 8, true, x64.get(), N, H.get(), N, Epilogue{}, d_sa.get<int>(), s);
     for (size_t q = 0; q < act.size(); ++q) {
       if (!fin[q]) continue;
       SrvReq& r = *act[q];
@@ -427,8 +425,6 @@ void hm_server::round(std::vector<SrvReq*>& act) {
       HM_HIP(hipMemcpyAsync(r.J.data(), Jo.get(), n * r.nrhs * 8, hipMemcpyDeviceToHost, s));
       HM_HIP(hipMemcpyAsync(r.q.data(), qo.get(), n * r.nrhs * 8, hipMemcpyDeviceToHost, s));
       HM_HIP(hipStreamSynchronize(s));
-      r.matvecs++;
-      r.bytes += matrix_bytes(*mats[q], true);
     }
   }
   // continuing requests: inner FP32 GMRES with the stored factors on C d = r.
