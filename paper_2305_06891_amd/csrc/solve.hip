@@ -296,9 +296,13 @@ SolveResult Batch::solve_prepared(const hm_solve_params& p, hipStream_t s, bool 
     R.converged = st.converged;
     R.rel_res = st.rel_res;  // FP32 GMRES's own residuals
     if (report) {
-      // the residual in FP64 against the same stored operator
+      // the residual in FP64 against the same stored operator; without FP32
+      // copies that is also the flux's operator, so the product can leave
+      // F x for it
+      const bool fx = keep_fx && !C->mats[0]->has_hi;
       Krylov& K8 = krylov(8, p.restart, s);
-      residual64(false, s);
+      residual64(false, s, fx);
+      R.fx = fx;
       R.matvecs++;
       R.bytes += C->bytes_lo;
       std::vector<double> rn, bn;
