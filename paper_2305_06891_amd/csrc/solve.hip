@@ -420,6 +420,10 @@ TransientResult Batch::transient(const std::vector<const double*>& eps_user, dou
   Krylov& K8 = krylov(8, sp.restart, s);
   std::vector<int> upd(W, 0);
   bool have_J = false;
+  // every step's Newton loop ends on an evaluation at the accepted
+  // temperatures with no update after it, so J (x64) and q (H64) already hold
+  // the next step's first evaluation, which is at the same temperatures
+  bool have_q = false;
   for (int step = 0; step < tp.steps; ++step) {
     HM_HIP(hipMemcpyAsync(Tn.get(), Tp.get(), N * W * 8, hipMemcpyDeviceToDevice, s));
     std::vector<double> scale;
@@ -427,13 +431,17 @@ TransientResult Batch::transient(const std::vector<const double*>& eps_user, dou
     for (auto& v : scale) v *= tp.mc / tp.dt;
     int it = 0;
     for (;;) {
-      // q(T): radiosity solve (warm start from the previous iterate) and flux
-      prepare_rhs(sigma, sp, s);
-      // the Newton residual below checks the step: no FP64 report of the solve
-      SolveResult R = solve_prepared(sp, s, have_J, false);
-      have_J = true;
-      TR.matvecs += R.matvecs + 1;
-      flux(sigma, s);  // H64 = q
+      if (have_q) {
+        have_q = false;
+      } else {
+        // q(T): radiosity solve (warm start from the previous iterate) and flux
+        prepare_rhs(sigma, sp, s);
+        // the Newton residual below checks the step: no FP64 report of the solve
+        SolveResult R = solve_prepared(sp, s, have_J, false);
+        have_J = true;
+        TR.matvecs += R.matvecs + 1;
+        flux(sigma, s);  // H64 = q
+      }
       std::fill(upd.begin(), upd.end(), 0);
       hipLaunchKernelGGL(k_newton, grid_rows(N, nrhs), dim3(256), 0, s, epsp.get<double>(), g.get<double>(),
                          H64.get<double>(), srcp.get<double>(), Tn.get<double>(), Tp.get<double>(), Rv.get<double>(),
@@ -463,6 +471,7 @@ TransientResult Batch::transient(const std::vector<const double*>& eps_user, dou
     TR.newton_total += it;
     TR.newton_max = std::max(TR.newton_max, it);
     TR.steps_done = step + 1;
+    have_q = true;
     if (history) {
       io({}, {history + (int64_t)(step + 1) * ldT * nrhs}, 0, &ldh, s);
       scatter(Tp.get<double>(), nrhs, s);
