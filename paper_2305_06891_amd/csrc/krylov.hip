@@ -174,8 +174,10 @@ __global__ __launch_bounds__(GS_T) void k_gs(GsArgs a) {
   }
 }
 
-// One block per system: the chunk partials of k_gs added in chunk order,
-// then the step's bookkeeping (Hessenberg entries, norm, Givens rotation).
+// One wave per system: the chunk partials of k_gs added in a fixed order
+// (lane i sums partials i, i + 64, ..., then a fixed butterfly over the
+// lanes; the order depends only on the system's own partial count), then the
+// step's bookkeeping (Hessenberg entries, norm, Givens rotation).
 __global__ __launch_bounds__(64) void k_gs_final(GsArgs a, int nsys) {
   __shared__ double red[MAXM + 1];
   const int s = blockIdx.x;
@@ -186,10 +188,11 @@ __global__ __launch_bounds__(64) void k_gs_final(GsArgs a, int nsys) {
   const int L = (a.mode <= 1) ? a.j + 1 : 0;
   const int nv = L > 0 ? L : 1;
   const double* P0 = a.part + (int64_t)c0.part * (MAXM + 1);
-  for (int l = threadIdx.x; l < nv; l += 64) {
+  for (int l = 0; l < nv; ++l) {
     double t = 0.0;
-    for (int p = 0; p < c0.nparts; ++p) t += P0[(int64_t)p * (MAXM + 1) + l];
-    red[l] = t;
+    for (int p = threadIdx.x; p < c0.nparts; p += 64) t += P0[(int64_t)p * (MAXM + 1) + l];
+    t = wave_sum(t);
+    if (threadIdx.x == 0) red[l] = t;
   }
   __syncthreads();
   if (threadIdx.x != 0) return;
