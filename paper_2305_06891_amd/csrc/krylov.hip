@@ -6,6 +6,9 @@
 // accumulated in FP64 and reduced in a fixed order.
 #include <algorithm>
 #include <cmath>
+#include <cstring>
+#include <exception>
+#include <mutex>
 
 #include "dev_common.hpp"
 #include "krylov.hpp"
@@ -368,6 +371,50 @@ hipGraphExec_t block_graph(Krylov& K, bool hi, const void* omeps, int nrr, int j
   return ge;
 }
 
+// Pinned host buffers for the scalars gmres exchanges with the device every
+// cycle (norms, active flags, counts, the Givens right-hand side): copies
+// from pageable memory go through a bounce buffer and took tens of
+// microseconds each.  A call leases one buffer and returns it when it ends,
+// when every copy from or to it has completed (each cycle ends with a
+// stream synchronisation); a call left by an exception keeps its buffer.
+// Buffers are never freed: a few per thread that runs solves.
+struct StageLease {
+  void* p = nullptr;
+  size_t bytes = 0;
+  static std::mutex& mu() {
+    static std::mutex* m = new std::mutex();
+    return *m;
+  }
+  static std::vector<std::pair<void*, size_t>>& free_list() {
+    static auto* v = new std::vector<std::pair<void*, size_t>>();
+    return *v;
+  }
+  explicit StageLease(size_t need) {
+    {
+      std::lock_guard<std::mutex> lk(mu());
+      auto& fl = free_list();
+      for (size_t i = 0; i < fl.size(); ++i)
+        if (fl[i].second >= need) {
+          p = fl[i].first;
+          bytes = fl[i].second;
+          fl.erase(fl.begin() + (std::ptrdiff_t)i);
+          return;
+        }
+    }
+    size_t b = 4096;
+    while (b < need) b <<= 1;
+    HM_HIP(hipHostMalloc(&p, b, hipHostMallocDefault));
+    bytes = b;
+  }
+  ~StageLease() {
+    if (std::uncaught_exceptions() > 0) return;
+    std::lock_guard<std::mutex> lk(mu());
+    free_list().emplace_back(p, bytes);
+  }
+  StageLease(const StageLease&) = delete;
+  StageLease& operator=(const StageLease&) = delete;
+};
+
 template <class VT>
 GmresStats gmres_t(Krylov& K, bool hi, const void* omeps, const void* b, void* x, double rtol, int max_iter,
                    hipStream_t s, bool use_graphs, unsigned opts) {
@@ -377,14 +424,24 @@ GmresStats gmres_t(Krylov& K, bool hi, const void* omeps, const void* b, void* x
   GmresStats st;
   st.rel_res.assign(ns, 0.0);
   const int64_t mbytes = hi ? C.bytes_hi : C.bytes_lo;
+  // host side of the per-cycle scalars, in pinned memory
+  const size_t g0n = (size_t)ns * (MAXM + 1);
+  StageLease lease((g0n + 3 * (size_t)ns) * 8 + (2 * (size_t)ns + nslots) * 4);
+  double* g0 = (double*)lease.p;
+  double* bn = g0 + g0n;
+  double* tolv = bn + ns;
+  double* beta = tolv + ns;
+  int* act = (int*)(beta + ns);
+  int* stp = act + ns;
+  int* cnt = stp + ns;
+  std::memset(g0, 0, g0n * 8);
   // |b| per system
-  std::vector<double> bn(ns), beta(ns), tolv(ns);
   run_gs<VT>(K, 3, 0, const_cast<void*>(b), s);
-  HM_HIP(hipMemcpyAsync(bn.data(), K.beta.get(), ns * 8, hipMemcpyDeviceToHost, s));
+  HM_HIP(hipMemcpyAsync(bn, K.beta.get(), ns * 8, hipMemcpyDeviceToHost, s));
   HM_HIP(hipStreamSynchronize(s));
   for (int q = 0; q < ns; ++q) tolv[q] = rtol * bn[q];
-  HM_HIP(hipMemcpyAsync(K.tol.get(), tolv.data(), ns * 8, hipMemcpyHostToDevice, s));
-  HM_HIP(hipMemcpyAsync(K.bnorm.get(), bn.data(), ns * 8, hipMemcpyHostToDevice, s));
+  HM_HIP(hipMemcpyAsync(K.tol.get(), tolv, ns * 8, hipMemcpyHostToDevice, s));
+  HM_HIP(hipMemcpyAsync(K.bnorm.get(), bn, ns * 8, hipMemcpyHostToDevice, s));
   Epilogue res_ep;  // r = b - (x - (1-eps) F x) = b - x + (1-eps) F x
   res_ep.rowscale = omeps;
   res_ep.a_acc = 1.0;
@@ -397,8 +454,6 @@ GmresStats gmres_t(Krylov& K, bool hi, const void* omeps, const void* b, void* x
   op_ep.a_acc = -1.0;
   op_ep.a_x = 1.0;
   const int nrr = C.nr;
-  std::vector<int> act(ns), cnt(nslots), stp(ns);
-  std::vector<double> g0((size_t)ns * (MAXM + 1), 0.0);
   int iters = 0;
   bool first = true;
   for (;;) {
@@ -412,10 +467,10 @@ GmresStats gmres_t(Krylov& K, bool hi, const void* omeps, const void* b, void* x
     }
     first = false;
     run_gs<VT>(K, 3, 0, K.basis.get(), s);
-    HM_HIP(hipMemcpyAsync(beta.data(), K.beta.get(), ns * 8, hipMemcpyDeviceToHost, s));
+    HM_HIP(hipMemcpyAsync(beta, K.beta.get(), ns * 8, hipMemcpyDeviceToHost, s));
     HM_HIP(hipStreamSynchronize(s));
     int nact = 0;
-    std::fill(cnt.begin(), cnt.end(), 0);
+    std::fill(cnt, cnt + nslots, 0);
     for (int q = 0; q < ns; ++q) {
       st.rel_res[q] = bn[q] > 0 ? beta[q] / bn[q] : 0.0;
       act[q] = beta[q] > tolv[q] && std::isfinite(beta[q]) ? 1 : 0;
@@ -430,9 +485,9 @@ GmresStats gmres_t(Krylov& K, bool hi, const void* omeps, const void* b, void* x
       st.converged = false;
       break;
     }
-    HM_HIP(hipMemcpyAsync(K.act.get(), act.data(), ns * 4, hipMemcpyHostToDevice, s));
-    HM_HIP(hipMemcpyAsync(K.slot_cnt.get(), cnt.data(), nslots * 4, hipMemcpyHostToDevice, s));
-    HM_HIP(hipMemcpyAsync(K.g.get(), g0.data(), g0.size() * 8, hipMemcpyHostToDevice, s));
+    HM_HIP(hipMemcpyAsync(K.act.get(), act, ns * 4, hipMemcpyHostToDevice, s));
+    HM_HIP(hipMemcpyAsync(K.slot_cnt.get(), cnt, nslots * 4, hipMemcpyHostToDevice, s));
+    HM_HIP(hipMemcpyAsync(K.g.get(), g0, g0n * 8, hipMemcpyHostToDevice, s));
     HM_HIP(hipMemsetAsync(K.steps.get(), 0, ns * 4, s));
     run_scale<VT>(K, K.beta.get<double>(), K.basis.get(), K.basis.get(), s);
     // Arnoldi steps; the host looks at the active count every SYNC steps
@@ -462,18 +517,18 @@ GmresStats gmres_t(Krylov& K, bool hi, const void* omeps, const void* b, void* x
         for (int q = 0; q < nb; ++q) step(j + q, s);
       }
       j += nb;
-      HM_HIP(hipMemcpyAsync(cnt.data(), K.slot_cnt.get(), nslots * 4, hipMemcpyDeviceToHost, s));
+      HM_HIP(hipMemcpyAsync(cnt, K.slot_cnt.get(), nslots * 4, hipMemcpyDeviceToHost, s));
       HM_HIP(hipStreamSynchronize(s));
       left = 0;
-      for (int v : cnt) left += v;
+      for (int q = 0; q < nslots; ++q) left += cnt[q];
       if (left == 0) break;
     }
     // steps taken in this cycle: the most any system took
     const bool trusted = (opts & GM_TRUST_ESTIMATE) && left == 0;
-    HM_HIP(hipMemcpyAsync(stp.data(), K.steps.get(), ns * 4, hipMemcpyDeviceToHost, s));
-    if (trusted) HM_HIP(hipMemcpyAsync(g0.data(), K.g.get(), g0.size() * 8, hipMemcpyDeviceToHost, s));
+    HM_HIP(hipMemcpyAsync(stp, K.steps.get(), ns * 4, hipMemcpyDeviceToHost, s));
+    if (trusted) HM_HIP(hipMemcpyAsync(g0, K.g.get(), g0n * 8, hipMemcpyDeviceToHost, s));
     HM_HIP(hipStreamSynchronize(s));
-    const int cyc = *std::max_element(stp.begin(), stp.end());
+    const int cyc = *std::max_element(stp, stp + ns);
     iters += cyc;
     st.matvecs += cyc;
     st.bytes += (int64_t)cyc * mbytes;
