@@ -559,9 +559,12 @@ GmresStats gmres(Krylov& K, bool hi, const void* omeps, const void* b, void* x, 
 void block_norms(Krylov& K, const void* v, std::vector<double>& out, hipStream_t s) {
   if (K.vb == 8) run_gs<double>(K, 3, 0, const_cast<void*>(v), s);
   else run_gs<float>(K, 3, 0, const_cast<void*>(v), s);
-  out.resize(K.S->size());
-  HM_HIP(hipMemcpyAsync(out.data(), K.beta.get(), out.size() * 8, hipMemcpyDeviceToHost, s));
+  const int ns = K.S->size();
+  StageLease lease((size_t)ns * 8);
+  HM_HIP(hipMemcpyAsync(lease.p, K.beta.get(), (size_t)ns * 8, hipMemcpyDeviceToHost, s));
   HM_HIP(hipStreamSynchronize(s));
+  const double* nr = (const double*)lease.p;
+  out.assign(nr, nr + ns);
 }
 
 }  // namespace hm
