@@ -71,3 +71,38 @@ def test_literal_flux_pin_rejects_flux_without_g():
     q_bad = eps * (F @ J - radiosity.SIGMA * T**4)   # mutant: g replaced by 1
     assert np.linalg.norm(q_bad - ql) / np.linalg.norm(ql) > 1e-4
     assert np.linalg.norm(rad.flux(T) - ql) / np.linalg.norm(ql) < 1e-12
+
+
+def _newton_step_plus_q(rad, Tn, src, mc, dt, tol=1e-15, max_newton=80):
+    """Mutant of the implicit Euler step with the exchange term's sign
+    flipped (``R = mc (T - T^n)/dt + q - s``, with the matching local
+    Jacobian).  It conserves energy exactly like the oracle, so the energy
+    invariant and the isothermal rest state both accept it."""
+    T = np.array(Tn, dtype=np.float64, copy=True)
+    scale = np.linalg.norm(mc * Tn / dt, axis=0)
+    eps = rad.eps[:, None]
+    g = rad.g[:, None]
+    for _ in range(max_newton):
+        R = mc * (T - Tn) / dt + rad.flux(T) - src
+        if np.all(np.linalg.norm(R, axis=0) <= tol * scale):
+            break
+        T = T - R / (mc / dt - 4.0 * rad.sigma * eps * g * T**3)
+    return T
+
+
+def test_two_plate_transient_pin_rejects_flipped_exchange_sign():
+    from tests.test_oracle_pins import _two_plate_step_exact
+
+    F = np.array([[0.0, 1.0], [1.0, 0.0]])
+    e1, e2, T1, T2, mc, dt = 0.8, 0.8, 400.0, 1200.0, 1.0e4, 1.0
+    rad = radiosity.DenseRadiosity(F, np.array([e1, e2]))
+    Tn = np.array([[T1], [T2]])
+    x1, _ = _two_plate_step_exact(e1, e2, T1, T2, mc, dt)
+    Tm = _newton_step_plus_q(rad, Tn, np.zeros_like(Tn), mc, dt)
+    # the mutant passes the energy invariant ...
+    assert abs((Tm[0, 0] + Tm[1, 0]) - (T1 + T2)) <= 1e-9 * (T1 + T2)
+    # ... but heats the hot plate: the two-plate pin rejects it
+    assert abs(Tm[0, 0] - x1) > 1.0
+    from oracle import transient
+    To, _, _ = transient.newton_step(rad, Tn, np.zeros_like(Tn), mc, dt, tol=1e-15, max_newton=80)
+    assert abs(To[0, 0] - x1) <= 1e-12 * x1

@@ -328,3 +328,42 @@ def test_transient_energy_invariant_and_isothermal_rest():
     Tiso = np.full((a.size, 1), 600.0)
     T2, it2, _ = transient.newton_step(rad, Tiso, np.zeros_like(Tiso), mc, dt)
     assert np.max(np.abs(T2 - 600.0)) < 1e-9
+
+
+def _two_plate_step_exact(e1, e2, T1, T2, mc, dt, sigma=SIGMA):
+    """One implicit Euler step of two facing infinite gray plates (equal
+    areas and heat capacities, no source), solved as a scalar equation.
+
+    The plates exchange only with each other, so energy is conserved and the
+    new temperatures satisfy T1' + T2' = T1 + T2.  The net flux into plate 1
+    is the Sec. 2.2 closed form, so the step reduces to
+    ``mc (T1' - T1)/dt = q1(T1', T1 + T2 - T1')``, whose left side increases
+    and right side decreases with T1': one root, bracketed by the two
+    initial temperatures."""
+    from scipy.optimize import brentq
+
+    S = T1 + T2
+
+    def f(x):
+        return mc * (x - T1) / dt - closed_forms.two_plates_flux(e1, e2, x, S - x, sigma)
+
+    lo, hi = min(T1, T2), max(T1, T2)
+    x = brentq(f, lo, hi, xtol=1e-14, rtol=4 * np.finfo(float).eps, maxiter=400)
+    return x, S - x
+
+
+@pytest.mark.parametrize("e1,e2,T1,T2,dt", [(0.8, 0.8, 400.0, 1200.0, 1.0), (0.3, 0.9, 1500.0, 350.0, 5.0),
+                                            (1.0, 0.5, 700.0, 710.0, 0.5)])
+def test_transient_two_plates_direction_of_exchange(e1, e2, T1, T2, dt):
+    """Fixes the sign of the exchange term: heat flows from the hotter plate
+    to the colder one at the two-plate rate of Sec. 2.2."""
+    F = np.array([[0.0, 1.0], [1.0, 0.0]])
+    rad = radiosity.DenseRadiosity(F, np.array([e1, e2]))
+    mc = 1.0e4
+    Tn = np.array([[T1], [T2]])
+    T, it, _ = transient.newton_step(rad, Tn, np.zeros_like(Tn), mc, dt, tol=1e-15, max_newton=80)
+    x1, x2 = _two_plate_step_exact(e1, e2, T1, T2, mc, dt)
+    assert abs(T[0, 0] - x1) <= 1e-12 * x1
+    assert abs(T[1, 0] - x2) <= 1e-12 * x2
+    # the hotter plate cooled, the colder one warmed
+    assert (T[0, 0] - T1) * (T2 - T1) > 0
