@@ -6,6 +6,7 @@
 #include <cmath>
 #include <map>
 
+#include "convergence.hpp"
 #include "dev_common.hpp"
 #include "solve.hpp"
 
@@ -25,10 +26,20 @@ std::vector<hm_matrix*> assemble_batch(hm_ctx& ctx, const std::vector<const hm_t
 
 // Per-matrix cache: compositions for plain products, permuted vector
 // buffers, and batched-solve state keyed by the ids of its matrices.
+// Products leave their work queued when they return; `done` marks the end of
+// the last product's work on `last`, and a product on another stream waits
+// for it before it touches the shared buffers (xp, yp and the composition's
+// scratch).
 struct MatCache {
   std::map<int, std::unique_ptr<Composition>> comps;
   DevBuf xp, yp;
   std::map<std::vector<uint64_t>, std::unique_ptr<Batch>> batches;
+  hipEvent_t done = nullptr;
+  hipStream_t last = nullptr;
+  bool pending = false;
+  ~MatCache() {
+    if (done) (void)hipEventDestroy(done);
+  }
 };
 
 MatCache& cache_of(const hm_matrix& M) {
@@ -119,6 +130,7 @@ template <class F>
 hm_status guarded(hm_ctx* ctx, F&& f) {
   try {
     if (ctx) HM_HIP(hipSetDevice(ctx->device));
+    StreamScope scope(ctx ? ctx->stream : current_stream());
     f();
     return HM_OK;
   } catch (const Error& e) {
@@ -306,8 +318,17 @@ hm_status hm_matrix_set_tuning(hm_ctx* ctx, hm_matrix* M, int32_t rows, int32_t 
     P1Params pp;
     pp.rows = rows;
     pp.task_bytes = task_bytes;
+    std::lock_guard<std::mutex> lk(M->mu);
+    // every composition, batch and captured graph built on M copied the old
+    // phase-1 lists and counts: wait for all work that may use them, drop
+    // M's caches, and give M a new id so that batches cached under other
+    // matrices (keyed by the ids of their members) no longer match it
+    HM_HIP(hipDeviceSynchronize());
+    M->cache.reset();
     replan_phase1(*M, pp, ctx->stream);
+    HM_HIP(hipStreamSynchronize(ctx->stream));
     M->plan.p1_us = 0.0;
+    M->id = g_next_id++;
   });
 }
 
@@ -333,6 +354,7 @@ hm_status hm_hmatvec_ex(hm_ctx* ctx, const hm_matrix* M, int32_t nrhs, hm_dtype 
     std::lock_guard<std::mutex> lk(const_cast<hm_matrix*>(M)->mu);
     hipStream_t s = ctx->stream;
     MatCache& mc = cache_of(*M);
+    if (mc.pending && mc.last != s) HM_HIP(hipStreamWaitEvent(s, mc.done, 0));
     const int W = pad_width(nrhs);
     auto& comp = mc.comps[W];
     if (!comp) comp = make_composition({M}, W, 8, s);
@@ -370,6 +392,10 @@ hm_status hm_hmatvec_ex(hm_ctx* ctx, const hm_matrix* M, int32_t nrhs, hm_dtype 
     else
       hipLaunchKernelGGL(k_perm_scatter<float>, grid, dim3(256), 0, s, perm, mc.yp.get<float>(), n, (float*)Y, ldy, n);
     HM_HIP(hipGetLastError());
+    if (!mc.done) HM_HIP(hipEventCreateWithFlags(&mc.done, hipEventDisableTiming));
+    HM_HIP(hipEventRecord(mc.done, s));
+    mc.last = s;
+    mc.pending = true;
   });
 }
 
@@ -461,7 +487,7 @@ static void fill_info(hm_solve_info* info, const SolveResult& R, double secs, in
   info->bytes_moved = R.bytes;
   info->seconds = secs;
   double rr = 0.0;
-  for (int q = sys_begin; q < sys_end && q < (int)R.rel_res.size(); ++q) rr = std::max(rr, R.rel_res[q]);
+  for (int q = sys_begin; q < sys_end && q < (int)R.rel_res.size(); ++q) rr = max_keep_nan(rr, R.rel_res[q]);
   info->rel_residual = rr;
 }
 
@@ -543,7 +569,8 @@ hm_status hm_transient_run(hm_ctx* ctx, const hm_matrix* M, const double* eps, i
     set_tl_error("hm_transient_run: NULL ctx");
     return HM_EINVAL;
   }
-  return guarded(ctx, [&] {
+  bool nonfinite = false;
+  hm_status st = guarded(ctx, [&] {
     const auto t0 = std::chrono::steady_clock::now();
     HM_REQUIRE(M && eps && T && src && tp, "hm_transient_run: NULL argument");
     HM_REQUIRE(nrhs >= 1 && nrhs <= 16, "hm_transient_run: nrhs must be in 1..16");
@@ -565,7 +592,13 @@ hm_status hm_transient_run(hm_ctx* ctx, const hm_matrix* M, const double* eps, i
       info->max_rel_residual = R.max_rel_residual;
       info->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     }
+    nonfinite = R.nonfinite;
   });
+  if (st == HM_OK && nonfinite) {
+    ctx->last_error = "hm_transient_run: a Newton residual was not finite (the run stopped at that step)";
+    return HM_ENOTCONV;
+  }
+  return st;
 }
 
 }  // extern "C"

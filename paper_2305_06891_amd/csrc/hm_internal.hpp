@@ -39,7 +39,21 @@ struct Error : std::runtime_error {
 // ---------------------------------------------------------------- device memory
 // Caching device allocator: freed blocks are kept per (device, size class)
 // and handed out again, so per-call workspaces do not pay hipMalloc/hipFree.
+// Reuse is stream-ordered: a block freed while this thread's current stream
+// is s is handed to an allocation on another stream only after that stream
+// has been made to wait for the work queued on s before the free.
 void* pool_alloc(size_t bytes, size_t* granted);
+hipStream_t current_stream();
+void set_current_stream(hipStream_t s);
+// Sets the calling thread's current stream for its lifetime (restores the
+// previous one at the end).
+struct StreamScope {
+  hipStream_t prev;
+  explicit StreamScope(hipStream_t s) : prev(current_stream()) { set_current_stream(s); }
+  ~StreamScope() { set_current_stream(prev); }
+  StreamScope(const StreamScope&) = delete;
+  StreamScope& operator=(const StreamScope&) = delete;
+};
 void pool_free(void* p, size_t granted);
 int64_t pool_cached_bytes();
 void pool_trim();

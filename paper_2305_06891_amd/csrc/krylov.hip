@@ -11,6 +11,7 @@
 #include <mutex>
 
 #include "dev_common.hpp"
+#include "convergence.hpp"
 #include "krylov.hpp"
 
 namespace hm {
@@ -472,13 +473,16 @@ GmresStats gmres_t(Krylov& K, bool hi, const void* omeps, const void* b, void* x
     int nact = 0;
     std::fill(cnt, cnt + nslots, 0);
     for (int q = 0; q < ns; ++q) {
-      st.rel_res[q] = bn[q] > 0 ? beta[q] / bn[q] : 0.0;
-      act[q] = beta[q] > tolv[q] && std::isfinite(beta[q]) ? 1 : 0;
+      st.rel_res[q] = rel_residual(beta[q], bn[q]);
+      // a system whose residual is not finite stops (and fails the solve)
+      const bool finite = std::isfinite(beta[q]) && std::isfinite(bn[q]);
+      if (!finite) st.converged = false;
+      act[q] = finite && beta[q] > tolv[q] ? 1 : 0;
       if (act[q]) {
         ++nact;
         cnt[K.S->sys[q].slot]++;
       }
-      g0[(size_t)q * (MAXM + 1)] = beta[q];
+      g0[(size_t)q * (MAXM + 1)] = finite ? beta[q] : 0.0;
     }
     if (nact == 0) break;
     if (iters >= max_iter) {
@@ -539,8 +543,10 @@ GmresStats gmres_t(Krylov& K, bool hi, const void* omeps, const void* b, void* x
     HM_HIP(hipGetLastError());
     if (trusted) {
       // every system met the tolerance by its residual estimate
-      for (int q = 0; q < ns; ++q)
-        st.rel_res[q] = bn[q] > 0 ? std::fabs(g0[(size_t)q * (MAXM + 1) + stp[q]]) / bn[q] : 0.0;
+      for (int q = 0; q < ns; ++q) {
+        st.rel_res[q] = rel_residual(std::fabs(g0[(size_t)q * (MAXM + 1) + stp[q]]), bn[q]);
+        if (std::isnan(st.rel_res[q])) st.converged = false;
+      }
       break;
     }
   }

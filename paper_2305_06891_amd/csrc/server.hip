@@ -15,6 +15,7 @@
 #include <map>
 #include <thread>
 
+#include "convergence.hpp"
 #include "dev_common.hpp"
 #include "solve.hpp"
 
@@ -140,13 +141,19 @@ struct hm_server {
   std::thread worker, assembler;
   hm_ctx ctx;   // the worker's own context (device + private stream)
   hm_ctx actx;  // the assembler's (device + its own stream)
-  enum Admit { ADMITTED, PARKED, WAIT };
+  // storage types shared by every cavity (set by the first registration):
+  // a round composes all active cavities into one product
+  bool have_types = false;
+  hm_dtype lr_type = HM_F32, dense_type = HM_F32;
+  int32_t keep_copy = 0;
+  enum Admit { ADMITTED, PARKED, WAIT, REJECTED };
   void run();
   void build_loop();
   void round(std::vector<hm::SrvReq*>& act);
   Admit admit_one(hm::SrvReq& r);
   void park_locked(hm::SrvReq& r);
   int64_t resident() const;
+  int64_t active_need_locked(const hm::SrvReq* extra, int64_t extra_ktot) const;
 };
 
 using namespace hm;
@@ -158,6 +165,58 @@ int64_t hm_server::resident() const {
     else if (kv.second->building) b += kv.second->reserved;
   }
   return b;
+}
+
+namespace hm {
+namespace {
+// Device bytes of one request's own vectors (temperatures, right-hand side,
+// radiosity; FP64, permuted).
+int64_t req_bytes(int64_t n, int nrhs) { return 3 * 8 * n * (int64_t)nrhs; }
+
+// Device bytes of one round over requests with `rows` rows in total, padded
+// width W and sum_ktot rank columns: the round's FP64 and FP32 vectors (b, x,
+// r, F x; b, x), the FP64 Krylov workspace of the residual norms (restart 1)
+// and the FP32 one of the inner GMRES (restart + 1 basis blocks, w, r), the
+// product's rank-column intermediates and row-major inputs, the flux
+// buffers of finishing requests and the per-row emissivity factors.
+int64_t round_bytes(int64_t rows, int W, int restart, int64_t sum_ktot, int64_t nsys) {
+  const int64_t blk = rows * W;
+  int64_t b = blk * (4 * 8 + 2 * 4);           // b64 x64 r64 H, b32 x32
+  b += blk * 8 * 4;                             // K8: 2 basis blocks, w, r
+  b += blk * 4 * (int64_t)(restart + 3);        // K4: restart + 1 basis blocks, w, r
+  b += blk * 8 * 5;                             // flux and result buffers of finishing requests
+  b += sum_ktot * W * 8;                        // t
+  if (W == 16) b += blk * 8;                    // row-major inputs of 16-column products
+  b += rows * 12;                               // 1 - eps, FP64 and FP32
+  b += nsys * (80 << 10);                       // Hessenberg data and rotations of each system
+  return b + (64 << 10);                        // descriptors and reduction partials
+}
+}  // namespace
+}  // namespace hm
+
+// Bytes the active requests need (their own vectors and one shared round),
+// with `extra` added (may be NULL) whose cavity has extra_ktot rank columns.
+// Caller holds the lock.
+int64_t hm_server::active_need_locked(const SrvReq* extra, int64_t extra_ktot) const {
+  int64_t rows = 0, kt = 0, own = 0, nsys = 0;
+  int maxr = 1;
+  auto add = [&](const SrvReq& r, int64_t ktot) {
+    rows += r.n;
+    kt += ktot;
+    own += req_bytes(r.n, r.nrhs);
+    nsys += r.nrhs;
+    maxr = std::max(maxr, r.nrhs);
+  };
+  for (uint64_t tk : active) {
+    auto it = req.find(tk);
+    if (it == req.end()) continue;
+    const SrvReq& r = *it->second;
+    auto ci = cav.find(r.cid);
+    add(r, ci != cav.end() && ci->second->M ? ci->second->M->Ktot : 4 * r.n);
+  }
+  if (extra) add(*extra, extra_ktot);
+  if (rows == 0) return 0;
+  return own + round_bytes(rows, pad_width(maxr), p.solve.restart, kt, nsys);
 }
 
 // Moves the request at the queue front to the parked list (caller holds the
@@ -182,6 +241,7 @@ void hm_server::park_locked(SrvReq& r) {
 hm_server::Admit hm_server::admit_one(SrvReq& r) {
   SrvCavity* c;
   bool res;
+  int64_t built_bytes;
   {
     std::lock_guard<std::mutex> lk(mu);
     c = cav.at(r.cid).get();
@@ -190,22 +250,32 @@ hm_server::Admit hm_server::admit_one(SrvReq& r) {
       return PARKED;
     }
     res = c->M != nullptr;
+    built_bytes = c->bytes;
   }
-  const int64_t vec_bytes = r.n * r.nrhs * 8 * 3;
-  auto resident_locked = [&] {
+  // the cavity (when it is not resident: its size when it was last built,
+  // else an estimate), this request's vectors and the round it joins must
+  // fit beside what is resident or being built
+  const int64_t cav_bytes = built_bytes > 0 ? built_bytes : r.n * 2500 * 4;
+  const int64_t est = res ? 0 : cav_bytes;
+  const int64_t ktot = res ? c->M->Ktot : 4 * r.n;
+  // a request that cannot fit even alone fails (the cavity's size is known
+  // once it has been built; before that only the request's own bytes count)
+  const int64_t alone = (built_bytes > 0 ? built_bytes : 0) + req_bytes(r.n, r.nrhs) +
+                        round_bytes(r.n, pad_width(r.nrhs), p.solve.restart, ktot, r.nrhs);
+  if (alone > p.hbm_budget_bytes) return REJECTED;
+  auto over_locked = [&] {
     std::lock_guard<std::mutex> lk(mu);
-    return resident();
+    return resident() + est + active_need_locked(&r, ktot) > p.hbm_budget_bytes;
   };
-  if (!res) {
-    // evict idle cavities until the estimate fits
-    const int64_t est = c->bytes > 0 ? c->bytes : r.n * 2500 * 4;
+  {
+    // evict idle cavities (least recently used first) until it fits
     for (;;) {
-      if (resident_locked() + est + vec_bytes <= p.hbm_budget_bytes) break;
+      if (!over_locked()) break;
       SrvCavity* lru = nullptr;
       {
         std::lock_guard<std::mutex> lk(mu);
         for (auto& kv : cav)
-          if (kv.second->M && kv.second->refs == 0 && kv.second->waiting == 0 &&
+          if (kv.second.get() != c && kv.second->M && kv.second->refs == 0 && kv.second->waiting == 0 &&
               (!lru || kv.second->last_use < lru->last_use))
             lru = kv.second.get();
       }
@@ -224,15 +294,24 @@ hm_server::Admit hm_server::admit_one(SrvReq& r) {
       lru->om32.release();
       lru->g.release();
     }
+  }
+  {
     std::lock_guard<std::mutex> lk(mu);
-    const bool busy = !active.empty() || !build_queue.empty();
-    if (resident() + est + vec_bytes > p.hbm_budget_bytes && busy) return WAIT;
-    c->building = true;
-    c->reserved = est;
-    build_queue.push_back(c->id);
-    park_locked(r);
-    acv.notify_all();
-    return PARKED;
+    if (resident() + est + active_need_locked(&r, ktot) > p.hbm_budget_bytes) {
+      // running requests or builds hold the budget: wait for them (with
+      // nothing running or building, every idle cavity has been evicted and
+      // the request fits alone, so this cannot wait forever)
+      const bool busy = !active.empty() || !build_queue.empty();
+      if (busy) return WAIT;
+    }
+    if (!res) {
+      c->building = true;
+      c->reserved = est;
+      build_queue.push_back(c->id);
+      park_locked(r);
+      acv.notify_all();
+      return PARKED;
+    }
   }
   {
     std::lock_guard<std::mutex> lk(mu);
@@ -263,6 +342,7 @@ hm_server::Admit hm_server::admit_one(SrvReq& r) {
 // of the queue in their order).
 void hm_server::build_loop() {
   (void)hipSetDevice(device);
+  set_current_stream(actx.stream);
   for (;;) {
     SrvCavity* c;
     {
@@ -393,15 +473,16 @@ void hm_server::round(std::vector<SrvReq*>& act) {
   std::vector<double> worst(act.size(), 0.0);
   for (int k = 0; k < S.size(); ++k) {
     const int q = S.sys[k].slot;
-    const double rel = bn[k] > 0 ? rn[k] / bn[k] : 0.0;
-    worst[q] = std::max(worst[q], rel);
-    if (rn[k] > p.solve.rtol * bn[k]) fin[q] = 0;
+    worst[q] = max_keep_nan(worst[q], rel_residual(rn[k], bn[k]));
+    if (!residual_met(rn[k], bn[k], p.solve.rtol)) fin[q] = 0;
   }
   for (size_t q = 0; q < act.size(); ++q) {
     act[q]->matvecs++;
     act[q]->bytes += matrix_bytes(*mats[q], true);
     act[q]->rel_res = worst[q];
-    if (!fin[q] && act[q]->rounds >= 40) fin[q] = 1;  // give up: reported as not converged
+    // give up after 40 rounds, or at once on a residual that is not finite:
+    // reported as not converged
+    if (!fin[q] && (act[q]->rounds >= 40 || std::isnan(worst[q]))) fin[q] = 1;
   }
   // finishing requests: flux and results
   bool any_fin = false;
@@ -440,7 +521,7 @@ void hm_server::round(std::vector<SrvReq*>& act) {
                        r64.get<double>(), b32.get<float>(), (int64_t)blk);
     for (int k = 0; k < S.size(); ++k) {
       const int q = S.sys[k].slot;
-      if (fin[q] || rn[k] <= p.solve.rtol * bn[k]) {
+      if (fin[q] || residual_met(rn[k], bn[k], p.solve.rtol)) {
         const SysDev& sd = S.sys[k];
         HM_HIP(hipMemsetAsync(b32.get<float>() + sd.col * N + sd.row0, 0, (size_t)sd.n * 4, s));
       }
@@ -483,12 +564,13 @@ void hm_server::round(std::vector<SrvReq*>& act) {
     active.erase(std::find(active.begin(), active.end(), r.ticket));
     r.done = true;
     r.t_done = t;
-    r.status = worst[q] <= p.solve.rtol ? HM_OK : HM_ENOTCONV;
+    r.status = rel_met(worst[q], p.solve.rtol) ? HM_OK : HM_ENOTCONV;
   }
 }
 
 void hm_server::run() {
   (void)hipSetDevice(device);
+  set_current_stream(stream);
   for (;;) {
     std::vector<uint64_t> pending;
     {
@@ -533,6 +615,17 @@ void hm_server::run() {
           continue;
         }
         std::lock_guard<std::mutex> lk(mu);
+        if (a == REJECTED) {
+          // needs more device memory than the whole budget: fail it alone
+          if (!queue.empty() && queue.front() == tk) queue.pop_front();
+          if (r->waited) cav.at(r->cid)->waiting--;
+          r->status = HM_ENOMEM;
+          r->t_done = now_s();
+          r->done = true;
+          st.rejected++;
+          ctx.last_error = "request needs more device memory than the server's budget";
+          continue;
+        }
         if (a == WAIT) {
           no_room = true;
           break;
@@ -625,6 +718,10 @@ hm_status hm_server_register_cavity(hm_server* s, uint64_t cid, const hm_tree* t
     HM_REQUIRE(ap->aca_tol > 0 && ap->aca_tol < 1 && ap->k_max >= 1, "hm_server_register_cavity: bad assembly parameters");
     HM_REQUIRE(ap->dense_dtype != HM_BF16 || (ap->lowrank_dtype == HM_BF16 && ap->keep_f32_copy),
                "hm_server_register_cavity: a BF16 near field needs BF16 factors and keep_f32_copy");
+    HM_REQUIRE(ap->lowrank_dtype != HM_BF16 || ap->keep_f32_copy,
+               "hm_server_register_cavity: BF16 factors need keep_f32_copy (the FP64 residual reads the FP32 copies)");
+    HM_REQUIRE(!(ap->dense_dtype == HM_F64 && ap->lowrank_dtype == HM_BF16),
+               "hm_server_register_cavity: BF16 factors need an FP32 or BF16 near field");
     auto c = std::make_unique<SrvCavity>();
     c->id = cid;
     c->tree = std::make_unique<hm_tree>(*tree);
@@ -633,6 +730,15 @@ hm_status hm_server_register_cavity(hm_server* s, uint64_t cid, const hm_tree* t
     c->ap.closed_row_scale = 0;
     std::lock_guard<std::mutex> lk(s->mu);
     HM_REQUIRE(s->cav.find(cid) == s->cav.end(), "hm_server_register_cavity: id already registered");
+    const int32_t keep = ap->lowrank_dtype == HM_BF16 ? 1 : 0;
+    if (s->have_types)
+      HM_REQUIRE(ap->lowrank_dtype == s->lr_type && ap->dense_dtype == s->dense_type && keep == s->keep_copy,
+                 "hm_server_register_cavity: every cavity of a server must use the storage types of the first "
+                 "registered one (lowrank_dtype, dense_dtype, keep_f32_copy)");
+    s->have_types = true;
+    s->lr_type = ap->lowrank_dtype;
+    s->dense_type = ap->dense_dtype;
+    s->keep_copy = keep;
     s->cav[cid] = std::move(c);
     return HM_OK;
   } catch (const Error& e) {

@@ -8,6 +8,7 @@
 #include <cstring>
 #include <map>
 
+#include "convergence.hpp"
 #include "dev_common.hpp"
 #include "krylov.hpp"
 #include "solve.hpp"
@@ -309,7 +310,10 @@ SolveResult Batch::solve_prepared(const hm_solve_params& p, hipStream_t s, bool 
       block_norms(K8, r64.get(), rn, s);
       block_norms(K8, b64.get(), bn, s);
       R.rel_res.resize(rn.size());
-      for (size_t q = 0; q < rn.size(); ++q) R.rel_res[q] = bn[q] > 0 ? rn[q] / bn[q] : 0.0;
+      for (size_t q = 0; q < rn.size(); ++q) {
+        R.rel_res[q] = rel_residual(rn[q], bn[q]);
+        if (std::isnan(R.rel_res[q])) R.converged = false;
+      }
     }
   } else {
     // iterative refinement: FP64 residual with the FP32 (hi) factors, inner
@@ -335,21 +339,23 @@ SolveResult Batch::solve_prepared(const hm_solve_params& p, hipStream_t s, bool 
         R.bytes += C->bytes_hi;
       }
       block_norms(K8, r64.get(), rn, s);
-      bool done = true;
+      bool done = true, nonfinite = false;
       R.rel_res.resize(rn.size());
       for (size_t q = 0; q < rn.size(); ++q) {
-        R.rel_res[q] = bn[q] > 0 ? rn[q] / bn[q] : 0.0;
-        if (rn[q] > p.rtol * bn[q]) done = false;
+        R.rel_res[q] = rel_residual(rn[q], bn[q]);
+        if (!residual_met(rn[q], bn[q], p.rtol)) done = false;
+        if (std::isnan(R.rel_res[q])) nonfinite = true;
       }
       if (done) {
         R.converged = true;
         break;
       }
-      if (outer >= 30 || inner_total >= p.max_iter) break;
+      // a residual that is not finite cannot be refined: stop, not converged
+      if (nonfinite || outer >= 30 || inner_total >= p.max_iter) break;
       // systems already converged get a zero right-hand side (no inner work)
       hipLaunchKernelGGL((k_cast<double, float>), dim3(gb_), dim3(256), 0, s, r64.get<double>(), b32.get<float>(), tot);
       for (size_t q = 0; q < rn.size(); ++q) {
-        if (rn[q] <= p.rtol * bn[q]) {
+        if (residual_met(rn[q], bn[q], p.rtol)) {
           const SysDev& sd = S.sys[q];
           HM_HIP(hipMemsetAsync(b32.get<float>() + sd.col * N + sd.row0, 0, (size_t)sd.n * 4, s));
         }
@@ -449,16 +455,18 @@ TransientResult Batch::transient(const std::vector<const double*>& eps_user, dou
       HM_HIP(hipGetLastError());
       std::vector<double> rn;
       block_norms(K8, Rv.get(), rn, s);
-      bool done = true;
+      bool done = true, nonfinite = false;
       double worst = 0.0;
       for (int j = 0; j < nrhs; ++j) {
-        const double rel = scale[j] > 0 ? rn[j] / scale[j] : 0.0;
-        worst = std::max(worst, rel);
-        upd[j] = rel > tp.newton_rtol ? 1 : 0;
+        const double rel = rel_residual(rn[j], scale[j]);
+        worst = max_keep_nan(worst, rel);
+        if (std::isnan(rel)) nonfinite = true;
+        upd[j] = !rel_met(rel, tp.newton_rtol) && !std::isnan(rel) ? 1 : 0;
         if (upd[j]) done = false;
       }
-      if (done || it >= tp.max_newton) {
-        TR.max_rel_residual = std::max(TR.max_rel_residual, worst);
+      if (done || nonfinite || it >= tp.max_newton) {
+        TR.max_rel_residual = max_keep_nan(TR.max_rel_residual, worst);
+        if (nonfinite) TR.nonfinite = true;
         break;
       }
       HM_HIP(hipMemcpyAsync(d_upd.get(), upd.data(), W * 4, hipMemcpyHostToDevice, s));
@@ -471,6 +479,7 @@ TransientResult Batch::transient(const std::vector<const double*>& eps_user, dou
     TR.newton_total += it;
     TR.newton_max = std::max(TR.newton_max, it);
     TR.steps_done = step + 1;
+    if (TR.nonfinite) break;
     have_q = true;
     if (history) {
       io({}, {history + (int64_t)(step + 1) * ldT * nrhs}, 0, &ldh, s);

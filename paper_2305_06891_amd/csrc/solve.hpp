@@ -26,6 +26,7 @@ struct SolveResult {
 struct TransientResult {
   int steps_done = 0, newton_total = 0, newton_max = 0, matvecs = 0;
   double max_rel_residual = 0.0;
+  bool nonfinite = false;  // a Newton residual was not finite: the run stopped there
 };
 
 // Everything one batched solve needs, kept between calls on the same set of

@@ -114,16 +114,31 @@ def test_server_alone_vs_mix_and_oracle(hm, ctx, wide):
         assert eJ <= 1e-6 and eq <= 1e-6
 
 
+def _cavity_bytes(hm, ctx, cavs):
+    """Device bytes of each cavity's H-matrix as the server assembles it."""
+    out = []
+    for v, f, eps in cavs:
+        c, n, a = hm.hm_facets_from_triangles(v, f, orient=1)
+        tree = hm.hm_build_cluster_tree(ctx, c, n, a, 32, 1.5)
+        M = hm.hm_assemble_hmatrix(ctx, tree, 1e-8, 256, hm.HM_BF16, hm.HM_F32, 1, 0)
+        out.append(M.stats()["bytes_device"] + 32 * f.shape[0])
+    return out
+
+
 def test_server_evicts_under_a_small_budget(hm, ctx):
     cavs = _cavities()
-    log("case: server with a budget that holds one cavity")
+    sizes = _cavity_bytes(hm, ctx, cavs)
+    # room for the largest cavity and one round of it, not for all three
+    budget = max(sizes) + (2 << 20)
+    log("case: server with a budget that holds the largest cavity: sizes", sizes, "budget", budget)
+    assert sum(sizes) > budget
     rng = np.random.default_rng(12)
     T = [rng.uniform(300.0, 1500.0, (c[1].shape[0], 1)) for c in cavs]
     big = _server(hm, ctx, cavs, 8 << 30)
     tks = [big.submit(cid, T[cid]) for cid in range(3)]
     ref = _wait(big, tks)
     big.close()
-    small = _server(hm, ctx, cavs, 6 << 20)
+    small = _server(hm, ctx, cavs, budget)
     out = {}
     for rnd in range(2):
         for cid in range(3):
@@ -132,7 +147,7 @@ def test_server_evicts_under_a_small_budget(hm, ctx):
     st = small.stats()
     small.close()
     log("stats", st)
-    assert st["evictions"] >= 3 and st["assemblies"] >= 4
+    assert st["evictions"] >= 1 and st["assemblies"] >= 4 and st["rejected"] == 0
     for (rnd, cid), r in out.items():
         want = ref[tks[cid][0]]
         assert rel(r[0], want[0]) <= 1e-12 and rel(r[1], want[1]) <= 1e-12
@@ -161,3 +176,49 @@ def test_server_cold_mix_assembles_while_serving(hm, ctx):
     for (cid, T), a, tk in zip(reqs, alone, tks):
         m = mix[tk[0]]
         assert rel(m[0], a[0]) <= 1e-12 and rel(m[1], a[1]) <= 1e-12, cid
+
+
+def test_server_rejects_a_request_larger_than_its_budget(hm, ctx):
+    """A cavity whose H-matrix alone exceeds the budget is built once (its
+    size is unknown before), then its request fails with HM_ENOMEM and is
+    counted as rejected; the server keeps serving."""
+    cavs = _cavities()
+    sizes = _cavity_bytes(hm, ctx, cavs)
+    budget = sizes[2] // 2
+    log("case: server budget %d below the cylinder's %d bytes" % (budget, sizes[2]))
+    srv = _server(hm, ctx, cavs, budget)
+    T = np.full((cavs[2][1].shape[0], 1), 600.0)
+    tk = srv.submit(2, T)
+    with pytest.raises(hm.HMError) as ei:
+        _wait(srv, [tk])
+    assert ei.value.status == hm.HM_ENOMEM
+    st = srv.stats()
+    srv.close()
+    log("stats", st)
+    assert st["rejected"] == 1 and st["completed"] == 0
+
+
+def test_server_requires_one_set_of_storage_types(hm, ctx):
+    """A round composes every active cavity into one product, so all cavities
+    of a server share their storage types; BF16 factors need their FP32 copy
+    (the FP64 residual reads it)."""
+    cavs = _cavities()
+    p = hm.solve_params(rtol=1e-9, mixed_precision=1, ir_inner_rtol=1e-3)
+    srv = hm.Server(ctx, hbm_budget_bytes=1 << 30, max_active=4, params=p)
+    trees = []
+    for v, f, eps in cavs:
+        c, n, a = hm.hm_facets_from_triangles(v, f, orient=1)
+        trees.append(hm.hm_build_cluster_tree(ctx, c, n, a, 32, 1.5))
+    with pytest.raises(hm.HMError) as e0:
+        srv.register_cavity(0, trees[0], cavs[0][2], lowrank_dtype=hm.HM_BF16, keep_f32_copy=0)
+    assert e0.value.status == hm.HM_EINVAL
+    srv.register_cavity(0, trees[0], cavs[0][2], lowrank_dtype=hm.HM_BF16, keep_f32_copy=1)
+    with pytest.raises(hm.HMError) as e1:
+        srv.register_cavity(1, trees[1], cavs[1][2], lowrank_dtype=hm.HM_F32, keep_f32_copy=0)
+    assert e1.value.status == hm.HM_EINVAL
+    with pytest.raises(hm.HMError) as e2:
+        srv.register_cavity(1, trees[1], cavs[1][2], lowrank_dtype=hm.HM_BF16, dense_dtype=hm.HM_BF16,
+                            keep_f32_copy=1)
+    assert e2.value.status == hm.HM_EINVAL
+    srv.register_cavity(1, trees[1], cavs[1][2], lowrank_dtype=hm.HM_BF16, keep_f32_copy=1)
+    srv.close()
