@@ -203,6 +203,29 @@ hm_status hm_hmatvec_ex(hm_ctx* ctx, const hm_matrix* M, int32_t nrhs, hm_dtype 
                         int32_t use_f32_copy, const void* X, int64_t ldx, void* Y, int64_t ldy,
                         double alpha, double beta);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * product as hm_hmatvec (same kernels, same result bit for bit, factors as
+ * stored), with every workspace in a fixed device array of
+ * HM_NOALLOC_SCRATCH_BYTES bytes that the library holds on each device it
+ * runs on until the process ends.  It calls no hipMalloc or hipFree, no
+ * allocating library routine, and does not synchronise.  The caller still
+ * passes X and Y (DEVICE, as for hm_hmatvec).  The array is shared by every
+ * call on a device and keeps the last call's contents (nothing in it needs
+ * to start at zero): calls that overlap on one device race, so a caller
+ * using several streams must order these calls itself.
+ * Workspace needed (bytes, each part rounded up to 256): two slot
+ * descriptors; 4 per product work item (tasks, reductions and tiles of the
+ * matrix's plan, + 1); 2 * n * w * 8 for the permuted vectors (w = nrhs
+ * rounded up to 1, 2, 4, 8 or 16); 8 * w * (sum of ranks) for the rank
+ * intermediates; 8 * w * 64 per row-split partial of the first kernel; and
+ * n * 16 * 8 more when w = 16.  HM_ENOMEM (the product is not run) when this
+ * exceeds HM_NOALLOC_SCRATCH_BYTES; hm_hmatvec has no such limit.  Other
+ * errors as hm_hmatvec. */
+#define HM_NOALLOC_SCRATCH_BYTES (64u << 20)
+hm_status hm_hmatvec_noalloc(hm_ctx* ctx, const hm_matrix* M, int32_t nrhs, hm_dtype vec_dtype, const void* X,
+                             int64_t ldx, void* Y, int64_t ldy, double alpha, double beta);
+
 /* Timing of the product's two kernels for `count` matrices applied as one
  * block-diagonal operator (one launch per phase, as in the batched solve),
  * measured with HIP events recorded on ctx's stream around each kernel of

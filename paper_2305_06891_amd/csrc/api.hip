@@ -114,6 +114,53 @@ void check_device_range(hm_ctx& c, const double* v, int64_t n, int64_t ld, int n
 
 }  // namespace hm
 
+// ---------------------------------------------------------------- allocation-free product
+// Device scratch of hm_hmatvec_noalloc: a fixed array in the library's code
+// object, so the entry point needs no allocation.  Each device the library
+// runs on holds its own copy until the process ends.  Host code never passes
+// the array's name to a kernel or a copy (on the host it is only a stand-in
+// symbol): it uses the device address that hipGetSymbolAddress returns for
+// the current device, taken once per device when a context is created.
+static __device__ __align__(256) unsigned char scratch[HM_NOALLOC_SCRATCH_BYTES];
+
+namespace hm {
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// The calling thread's current device must be `device`.
+void scratch_setup(int device) {
+  HM_REQUIRE(device >= 0 && device < kMaxDevices, "hm_ctx_create: device index beyond the scratch table");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch_ptr[device]) return;
+  void* p = nullptr;
+  HM_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+  HM_REQUIRE(p != nullptr, "hm_ctx_create: no device address for the product scratch");
+  g_scratch_ptr[device] = p;
+}
+
+void* scratch_ptr(int device) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  return device >= 0 && device < kMaxDevices ? g_scratch_ptr[device] : nullptr;
+}
+
+// Writes the two slot descriptors (factors as stored, FP32 copies) and a
+// zero slot index for every work item of a one-matrix product.
+__global__ void k_noalloc_tables(SlotDev lo, SlotDev hi, SlotDev* __restrict__ slots, int32_t* __restrict__ slot_of,
+                                 int32_t count) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i == 0) {
+    slots[0] = lo;
+    slots[1] = hi;
+  }
+  if (i < count) slot_of[i] = 0;
+}
+
+constexpr int64_t align256(int64_t b) { return (b + 255) & ~int64_t(255); }
+}  // namespace
+}  // namespace hm
+
 int64_t hm_matrix::bytes_device() const {
   int64_t b = (int64_t)(dense.bytes() + dense_hi.bytes() + U.bytes() + V.bytes() + U_hi.bytes() + V_hi.bytes() +
                         d_perm.bytes());
@@ -193,6 +240,7 @@ hm_status hm_ctx_create(int device, void* hip_stream, hm_ctx** out) {
     HM_REQUIRE(device >= 0 && device < nd, "hm_ctx_create: no such device");
     HM_HIP(hipSetDevice(device));
     c->stream = (hipStream_t)hip_stream;  // NULL: the null stream
+    scratch_setup(device);
   });
   if (st == HM_OK) *out = c.release();
   return st;
@@ -402,6 +450,118 @@ hm_status hm_hmatvec_ex(hm_ctx* ctx, const hm_matrix* M, int32_t nrhs, hm_dtype 
 hm_status hm_hmatvec(hm_ctx* ctx, const hm_matrix* M, int32_t nrhs, hm_dtype vt, const void* X, int64_t ldx,
                      void* Y, int64_t ldy, double alpha, double beta) {
   return hm_hmatvec_ex(ctx, M, nrhs, vt, 0, X, ldx, Y, ldy, alpha, beta);
+}
+
+hm_status hm_hmatvec_noalloc(hm_ctx* ctx, const hm_matrix* M, int32_t nrhs, hm_dtype vt, const void* X, int64_t ldx,
+                             void* Y, int64_t ldy, double alpha, double beta) {
+  if (!ctx) {
+    set_tl_error("hm_hmatvec_noalloc: NULL ctx");
+    return HM_EINVAL;
+  }
+  return guarded(ctx, [&] {
+    HM_REQUIRE(M && X && Y, "hm_hmatvec_noalloc: NULL argument");
+    HM_REQUIRE(nrhs >= 1 && nrhs <= 16, "hm_hmatvec_noalloc: nrhs must be in 1..16");
+    HM_REQUIRE(vt == HM_F64 || vt == HM_F32, "hm_hmatvec_noalloc: vec_dtype must be HM_F64 or HM_F32");
+    HM_REQUIRE(ldx >= M->n && ldy >= M->n, "hm_hmatvec_noalloc: leading dimension smaller than n");
+    HM_REQUIRE(std::isfinite(alpha) && std::isfinite(beta), "hm_hmatvec_noalloc: alpha/beta must be finite");
+    HM_REQUIRE(M->device == ctx->device, "hm_hmatvec_noalloc: matrix and context on different devices");
+    char* base = (char*)scratch_ptr(ctx->device);
+    HM_REQUIRE(base != nullptr, "hm_hmatvec_noalloc: no scratch address for this device");
+    std::lock_guard<std::mutex> lk(const_cast<hm_matrix*>(M)->mu);
+    const hipStream_t s = ctx->stream;
+    const Plan& P = M->plan;
+    const int W = pad_width(nrhs);
+    const int64_t n = M->n;
+    const int32_t p1_tasks = (int32_t)P.p1_task.size() - 1, p1_reds = (int32_t)P.p1red.size(),
+                  p2_tiles = (int32_t)P.p2t.size();
+    const int32_t count = p1_tasks + p1_reds + p2_tiles + 1;
+    // scratch layout: slot tables, slot indices, permuted x and y, rank
+    // intermediates t, phase-1 partial sums, row-major inputs (16 columns);
+    // the vector buffers are sized for FP64 as in hm_hmatvec
+    int64_t off = 0;
+    const int64_t o_slots = off;
+    off += align256(2 * (int64_t)sizeof(SlotDev));
+    const int64_t o_sof = off;
+    off += align256((int64_t)count * 4);
+    const int64_t o_xp = off;
+    off += align256(n * W * 8);
+    const int64_t o_yp = off;
+    off += align256(n * W * 8);
+    const int64_t o_t = off;
+    off += align256(std::max<int64_t>(1, M->Ktot * W) * 8);
+    const int64_t o_p1 = off;
+    off += align256(std::max<int64_t>(1, (int64_t)P.n_p1_parts * P1_GW * W) * 8);
+    const int64_t o_xr = off;
+    if (W == 16) off += align256(n * 16 * 8);
+    if (off > (int64_t)HM_NOALLOC_SCRATCH_BYTES)
+      fail(HM_ENOMEM, "hm_hmatvec_noalloc: this product needs " + std::to_string(off) +
+                          " bytes of scratch, more than the fixed " + std::to_string((int64_t)HM_NOALLOC_SCRATCH_BYTES) +
+                          " (use hm_hmatvec)");
+    SlotDev d{};
+    d.p1 = P.d_p1.get<P1Item>();
+    d.p1_task = P.d_p1_task.get<int32_t>();
+    d.p1red = P.d_p1red.get<P1Red>();
+    d.p2t = P.d_p2t.get<P2Tile>();
+    d.p2 = P.d_p2.get<P2Item>();
+    d.segs = P.d_segs.get<Seg>();
+    d.dense = M->dense.get();
+    d.U = M->U.get();
+    d.V = M->V.get();
+    d.part1 = base + o_p1;
+    d.t = base + o_t;
+    d.ldt = std::max<int64_t>(1, M->Ktot);
+    d.xoff = 0;
+    d.n = (int32_t)n;
+    SlotDev h = d;
+    if (M->has_hi) {
+      h.U = M->U_hi.get();
+      h.V = M->V_hi.get();
+      if (M->dense_dtype == HM_BF16) h.dense = M->dense_hi.get();
+    }
+    SlotDev* slots = (SlotDev*)(base + o_slots);
+    int32_t* sof = (int32_t*)(base + o_sof);
+    hipLaunchKernelGGL(k_noalloc_tables, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s, d, h, slots, sof,
+                       count);
+    CompView V;
+    V.slots_lo = slots;
+    V.slots_hi = slots + 1;
+    V.slot_of = sof;
+    V.xr = W == 16 ? base + o_xr : nullptr;
+    V.N = n;
+    V.p1_tasks = p1_tasks;
+    V.p1_reds = p1_reds;
+    V.p2_tiles = p2_tiles;
+    V.nr = W;
+    V.dense_dtype = M->dense_dtype;
+    V.lr_dtype = M->lr_dtype;
+    V.has_hi = M->has_hi;
+    void* xp = base + o_xp;
+    void* yp = base + o_yp;
+    const int vb = vt == HM_F64 ? 8 : 4;
+    dim3 grid((unsigned)((n + 255) / 256), (unsigned)nrhs);
+    const int32_t* perm = M->d_perm.get<int32_t>();
+    if (vb == 8) {
+      hipLaunchKernelGGL(k_perm_gather<double>, grid, dim3(256), 0, s, perm, (const double*)X, ldx, (double*)xp, n, n);
+      if (beta != 0.0)
+        hipLaunchKernelGGL(k_perm_gather<double>, grid, dim3(256), 0, s, perm, (const double*)Y, ldy, (double*)yp, n, n);
+    } else {
+      hipLaunchKernelGGL(k_perm_gather<float>, grid, dim3(256), 0, s, perm, (const float*)X, ldx, (float*)xp, n, n);
+      if (beta != 0.0)
+        hipLaunchKernelGGL(k_perm_gather<float>, grid, dim3(256), 0, s, perm, (const float*)Y, ldy, (float*)yp, n, n);
+    }
+    HM_HIP(hipGetLastError());
+    Epilogue ep;
+    ep.a_acc = alpha;
+    ep.a_z = beta;
+    ep.z = beta != 0.0 ? yp : nullptr;
+    ep.ldz = n;
+    launch_matvec_view(V, nrhs, vb, false, xp, n, yp, n, ep, nullptr, s);
+    if (vb == 8)
+      hipLaunchKernelGGL(k_perm_scatter<double>, grid, dim3(256), 0, s, perm, (const double*)yp, n, (double*)Y, ldy, n);
+    else
+      hipLaunchKernelGGL(k_perm_scatter<float>, grid, dim3(256), 0, s, perm, (const float*)yp, n, (float*)Y, ldy, n);
+    HM_HIP(hipGetLastError());
+  });
 }
 
 hm_status hm_hmatvec_profile(hm_ctx* ctx, int32_t count, const hm_matrix* const* Ms, int32_t nrhs, hm_dtype vt,

@@ -345,6 +345,23 @@ struct Epilogue {
 void launch_matvec(const Composition& C, int nrr, int vb, bool hi, const void* X, int64_t ldx, void* Y, int64_t ldy,
                    const Epilogue& ep, const int* slot_active, hipStream_t s, hipEvent_t* ev = nullptr);
 
+// What the product kernels read of a composition: its device tables, the
+// work counts and the storage types.  A Composition gives one over its own
+// buffers; the allocation-free product builds one over a static buffer.
+struct CompView {
+  const SlotDev* slots_lo = nullptr;
+  const SlotDev* slots_hi = nullptr;
+  const int32_t* slot_of = nullptr;
+  void* xr = nullptr;  // row-major input rows (16-column products only)
+  int64_t N = 0;
+  int32_t p1_tasks = 0, p1_reds = 0, p2_tiles = 0;
+  int nr = 1;
+  hm_dtype dense_dtype = HM_F32, lr_dtype = HM_F32;
+  bool has_hi = false;
+};
+void launch_matvec_view(const CompView& V, int nrr, int vb, bool hi, const void* X, int64_t ldx, void* Y, int64_t ldy,
+                        const Epilogue& ep, const int* slot_active, hipStream_t s, hipEvent_t* ev = nullptr);
+
 inline int pad_width(int nrhs) { return nrhs <= 1 ? 1 : nrhs <= 2 ? 2 : nrhs <= 4 ? 4 : nrhs <= 8 ? 8 : 16; }
 int64_t matrix_bytes(const hm_matrix& M, bool hi);
 

@@ -1291,24 +1291,24 @@ constexpr int p1_waves_per_block() {
 }
 
 template <class DT, class LT, class VT, int NR>
-void launch_typed(const Composition& C, int nrr, bool hi, const void* X, int64_t ldx, void* Y, int64_t ldy,
+void launch_typed(const CompView& C, int nrr, bool hi, const void* X, int64_t ldx, void* Y, int64_t ldy,
                   const Epilogue& ep, const int* slot_active, hipStream_t s, hipEvent_t* ev) {
   constexpr int WPB = p1_waves_per_block<VT, NR>();
-  const SlotDev* slots = (hi ? C.d_slots_hi : C.d_slots_lo).get<SlotDev>();
-  const int* sof = C.d_slot_of.get<int>();
+  const SlotDev* slots = hi ? C.slots_hi : C.slots_lo;
+  const int* sof = C.slot_of;
   // 16 right-hand sides of FP32/BF16 entries: matrix cores (FP32 or FP64 sums)
   constexpr bool mfma = NR == 16 && sizeof(DT) <= 4 && sizeof(LT) <= 4;
   if (ev) HM_HIP(hipEventRecord(ev[0], s));
   if constexpr (mfma) {
-    HM_REQUIRE(C.xr.get() != nullptr, "matvec: 16-column composition without its row-major input buffer");
+    HM_REQUIRE(C.xr != nullptr, "matvec: 16-column composition without its row-major input buffer");
     if (C.N > 0)
       hipLaunchKernelGGL(k_rows16<VT>, dim3((unsigned)((C.N + 255) / 256)), dim3(256), 0, s, (const VT*)X, ldx, nrr,
-                         C.N, C.xr.get<VT>());
+                         C.N, (VT*)C.xr);
   }
   if (C.p1_tasks > 0) {
     if constexpr (mfma)
       hipLaunchKernelGGL((k_phase1_mfma<LT, VT>), dim3((C.p1_tasks + 3) / 4), dim3(256), 0, s, slots, sof,
-                         C.p1_tasks, slot_active, (const VT*)C.xr.get<VT>());
+                         C.p1_tasks, slot_active, (const VT*)C.xr);
     else
       hipLaunchKernelGGL((k_phase1<LT, VT, NR, WPB>), dim3((C.p1_tasks + WPB - 1) / WPB), dim3(64 * WPB), 0, s,
                          slots, sof, C.p1_tasks, slot_active, nrr, (const VT*)X, ldx);
@@ -1333,7 +1333,7 @@ void launch_typed(const Composition& C, int nrr, bool hi, const void* X, int64_t
     if constexpr (mfma)
       hipLaunchKernelGGL((k_phase2_mfma<DT, LT, VT, P2M_WAVES>), dim3(C.p2_tiles), dim3(64 * P2M_WAVES), 0, s, slots,
                          sof + C.p1_tasks + C.p1_reds, slot_active, nrr, (const VT*)X, ldx,
-                         (const VT*)C.xr.get<VT>(), (VT*)Y, ldy, e);
+                         (const VT*)C.xr, (VT*)Y, ldy, e);
     else {
       // four waves per workgroup on many tiles, for one or two right-hand
       // sides (wider products would spill the second set of sums)
@@ -1354,7 +1354,7 @@ void launch_typed(const Composition& C, int nrr, bool hi, const void* X, int64_t
 }
 
 template <class DT, class LT, class VT>
-void launch_nr(const Composition& C, int nrr, bool hi, const void* X, int64_t ldx, void* Y, int64_t ldy,
+void launch_nr(const CompView& C, int nrr, bool hi, const void* X, int64_t ldx, void* Y, int64_t ldy,
                const Epilogue& ep, const int* sa, hipStream_t s, hipEvent_t* ev) {
   switch (C.nr) {
     case 1: launch_typed<DT, LT, VT, 1>(C, nrr, hi, X, ldx, Y, ldy, ep, sa, s, ev); break;
@@ -1371,14 +1371,32 @@ void launch_nr(const Composition& C, int nrr, bool hi, const void* X, int64_t ld
 void launch_matvec(const Composition& C, int nrr, int vb, bool hi, const void* X, int64_t ldx, void* Y, int64_t ldy,
                    const Epilogue& ep, const int* slot_active, hipStream_t s, hipEvent_t* ev) {
   HM_REQUIRE(!C.mats.empty(), "matvec: empty composition");
-  HM_REQUIRE(nrr >= 1 && nrr <= C.nr, "matvec: more right-hand sides than the composition holds");
   const hm_matrix& M0 = *C.mats[0];
   for (const auto* M : C.mats)
     HM_REQUIRE(M->dense_dtype == M0.dense_dtype && M->lr_dtype == M0.lr_dtype && M->has_hi == M0.has_hi,
                "matvec: matrices of one batch must share storage types");
-  const bool use_hi = hi && M0.has_hi;
-  const hm_dtype lt = use_hi ? HM_F32 : M0.lr_dtype;
-  const hm_dtype dt = use_hi && M0.dense_dtype == HM_BF16 ? HM_F32 : M0.dense_dtype;
+  CompView V;
+  V.slots_lo = C.d_slots_lo.get<SlotDev>();
+  V.slots_hi = C.d_slots_hi.get<SlotDev>();
+  V.slot_of = C.d_slot_of.get<int32_t>();
+  V.xr = C.xr.get();
+  V.N = C.N;
+  V.p1_tasks = C.p1_tasks;
+  V.p1_reds = C.p1_reds;
+  V.p2_tiles = C.p2_tiles;
+  V.nr = C.nr;
+  V.dense_dtype = M0.dense_dtype;
+  V.lr_dtype = M0.lr_dtype;
+  V.has_hi = M0.has_hi;
+  launch_matvec_view(V, nrr, vb, hi, X, ldx, Y, ldy, ep, slot_active, s, ev);
+}
+
+void launch_matvec_view(const CompView& C, int nrr, int vb, bool hi, const void* X, int64_t ldx, void* Y,
+                        int64_t ldy, const Epilogue& ep, const int* slot_active, hipStream_t s, hipEvent_t* ev) {
+  HM_REQUIRE(nrr >= 1 && nrr <= C.nr, "matvec: more right-hand sides than the composition holds");
+  const bool use_hi = hi && C.has_hi;
+  const hm_dtype lt = use_hi ? HM_F32 : C.lr_dtype;
+  const hm_dtype dt = use_hi && C.dense_dtype == HM_BF16 ? HM_F32 : C.dense_dtype;
   if (vb == 8) {
     if (dt == HM_F64 && lt == HM_F64) return launch_nr<double, double, double>(C, nrr, use_hi, X, ldx, Y, ldy, ep, slot_active, s, ev);
     if (dt == HM_F32 && lt == HM_F32) return launch_nr<float, float, double>(C, nrr, use_hi, X, ldx, Y, ldy, ep, slot_active, s, ev);

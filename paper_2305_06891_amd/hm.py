@@ -104,6 +104,8 @@ _PROTOS = {
                              C.c_double]),
     "hm_hmatvec_ex": (C.c_int, [_vp, _vp, C.c_int32, C.c_int, C.c_int32, _vp, C.c_int64, _vp, C.c_int64,
                                 C.c_double, C.c_double]),
+    "hm_hmatvec_noalloc": (C.c_int, [_vp, _vp, C.c_int32, C.c_int, _vp, C.c_int64, _vp, C.c_int64, C.c_double,
+                                     C.c_double]),
     "hm_hmatvec_profile": (C.c_int, [_vp, C.c_int32, C.POINTER(_vp), C.c_int32, C.c_int, C.c_int32, C.c_int32,
                                      C.c_int64,
                                      _dp, _dp, _dp, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
@@ -337,6 +339,17 @@ def hm_hmatvec(ctx, M: HMatrix, X, Y, alpha=1.0, beta=0.0, use_f32_copy=False):
     nr = 1 if X.dim() == 1 else X.shape[1]
     _check(lib.hm_hmatvec_ex(ctx.handle, M._h, nr, vt, int(use_f32_copy), _dev_ptr(X), _ld(X), _dev_ptr(Y, X.dtype),
                              _ld(Y), float(alpha), float(beta)), ctx.handle)
+    return Y
+
+
+def hm_hmatvec_noalloc(ctx, M: HMatrix, X, Y, alpha=1.0, beta=0.0):
+    """Y = alpha F_H X + beta Y with the library's fixed device scratch (no
+    allocation); X, Y device tensors (n or n x r, float64/float32)."""
+    import torch
+    vt = {torch.float64: HM_F64, torch.float32: HM_F32}[X.dtype]
+    nr = 1 if X.dim() == 1 else X.shape[1]
+    _check(lib.hm_hmatvec_noalloc(ctx.handle, M._h, nr, vt, _dev_ptr(X), _ld(X), _dev_ptr(Y, X.dtype), _ld(Y),
+                                  float(alpha), float(beta)), ctx.handle)
     return Y
 
 
