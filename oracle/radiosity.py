@@ -22,9 +22,13 @@ SIGMA = 5.670374e-8
 
 
 def reflection_matrix(F, eps):
-    """``C = I - diag(1 - eps) F`` (eq. (11) in the per-area convention)."""
+    """``C = I - diag(1 - eps) F`` (eq. (11) in the per-area convention).
+    Built as ``-(1 - eps) F`` plus 1 on the diagonal, the same values as
+    ``I - (1 - eps) F`` without an n x n identity."""
     n = F.shape[0]
-    return np.eye(n) - (1.0 - eps)[:, None] * F
+    C = (eps - 1.0)[:, None] * F
+    C[np.diag_indices(n)] += 1.0
+    return C
 
 
 def emission(eps, T, sigma=SIGMA):
@@ -38,12 +42,15 @@ class DenseRadiosity:
     """Dense LU of the reflection matrix of one cavity, reused for every
     right-hand side (as the paper reuses its factorisation)."""
 
-    def __init__(self, F, eps, sigma=SIGMA):
+    def __init__(self, F, eps, sigma=SIGMA, keep_c=True):
         self.F = F
         self.eps = np.asarray(eps, dtype=np.float64)
         self.sigma = sigma
-        self.C = reflection_matrix(F, self.eps)
-        self.lu = sla.lu_factor(self.C)
+        C = reflection_matrix(F, self.eps)
+        # keep_c=False factorises C in place (large cavities: one n x n array
+        # fewer); the factors are the same either way
+        self.C = C if keep_c else None
+        self.lu = sla.lu_factor(C, overwrite_a=not keep_c)
         # w = C^-1 eps and g = F w, used by the O(n) evaluation of eq. (12)
         self.w = sla.lu_solve(self.lu, self.eps)
         self.g = F @ self.w

@@ -9,7 +9,9 @@ times (autotuned matrices, the same solve parameters).
 * 64-cavity batch (696,072 facets) assembled in one batched call, BF16
   factors + FP64 refinement to a residual of 1e-7, all cavities in one
   batched solve: the smallest cavity of
-  each type against the dense oracle computed here (relative L2 <= 1e-6);
+  each type against the dense oracle computed here, and the largest
+  ellipsoid (35,280 facets) with an 18k-facet cavity of each type against the
+  stored dense oracle solution (relative L2 <= 1e-6);
   every cavity against the batched FP32 solve of the same cavities (both
   within 1e-6 of the exact solution: <= 2e-6 apart); the largest cavity
   (35,280 facets) through the exact radiosity balance on 64 sampled rows
@@ -115,6 +117,24 @@ def test_c3_batch_smallest_of_each_type_match_oracle(c3):
         Jo = rad.radiosity(c.T[:, 0])
         qo = rad.flux(c.T[:, 0], Jo)
         eJ, eq = rel(Jx[k], Jo), rel(qx[k], qo)
+        log("%s (%d facets): outer %d inner %d e(J) %.3e e(q) %.3e" % (c.name, c.n, ix[k]["outer_iters"],
+                                                                       ix[k]["iters"], eJ, eq))
+        assert eJ <= 1e-6 and eq <= 1e-6
+
+
+def test_c3_batch_large_and_mid_cavities_match_golden(c3):
+    """The largest ellipsoid (35,280 facets) and an 18,000-18,400-facet
+    icosphere, ellipsoid and cylinder of the batch against the oracle's dense
+    FP64 LU solution (``tests/golden/c3_reference.npz``, written by
+    ``tests/golden/make_c3_reference.py`` from ``oracle/`` only): relative L2
+    of J and q <= 1e-6."""
+    cavs, Jx, qx, ix, _, _, _ = c3
+    ref = np.load(os.path.join(HERE, "golden", "c3_reference.npz"))
+    for k in ref["indices"]:
+        k = int(k)
+        c = cavs[k]
+        assert int(ref["n_%d" % k]) == c.n
+        eJ, eq = rel(Jx[k], ref["J_%d" % k]), rel(qx[k], ref["q_%d" % k])
         log("%s (%d facets): outer %d inner %d e(J) %.3e e(q) %.3e" % (c.name, c.n, ix[k]["outer_iters"],
                                                                        ix[k]["iters"], eJ, eq))
         assert eJ <= 1e-6 and eq <= 1e-6

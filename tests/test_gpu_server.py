@@ -222,3 +222,41 @@ def test_server_requires_one_set_of_storage_types(hm, ctx):
     assert e2.value.status == hm.HM_EINVAL
     srv.register_cavity(1, trees[1], cavs[1][2], lowrank_dtype=hm.HM_BF16, keep_f32_copy=1)
     srv.close()
+
+
+def test_server_bench_configuration_matches_dense_oracle(hm, ctx):
+    """Three cavity ids of the serving workload (one of each type, 5,120 to
+    11,534 facets) served with the bench's parameters: leaf 64, eta 1.5,
+    ACA 1e-6, BF16 factors + FP32 near field + FP32 copy, FP64 refinement to
+    a residual of 1e-7 (inner FP32 GMRES to 3e-3), all three requests
+    submitted together.  J and q against the oracle's dense FP64 LU solution
+    of the same requests (``tests/golden/c5_reference.npz``, written by
+    ``tests/golden/make_c5_reference.py`` from ``oracle/`` only): relative
+    L2 <= 1e-6 per right-hand side."""
+    import os
+
+    from workloads import configs
+    ref = np.load(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "c5_reference.npz"))
+    seed = int(ref["seed"])
+    p = hm.solve_params(rtol=1e-7, restart=30, max_iter=400, mixed_precision=1, ir_inner_rtol=3e-3, want_q=1)
+    srv = hm.Server(ctx, hbm_budget_bytes=64 << 30, max_active=64, max_rhs_per_slot=8, params=p)
+    reqs = []
+    for cid, nrhs, idx in ref["requests"]:
+        cav = configs.c5_cavity(int(cid))
+        c, n, a = hm.hm_facets_from_triangles(cav.v, cav.tri, orient=1)
+        tree = hm.hm_build_cluster_tree(ctx, c, n, a, cav.leaf, cav.eta)
+        srv.register_cavity(int(cid), tree, cav.eps, aca_tol=cav.aca_tol, lowrank_dtype=hm.HM_BF16,
+                            dense_dtype=hm.HM_F32, keep_f32_copy=1)
+        reqs.append((int(cid), configs.request_temperatures(cav.n, int(nrhs), seed, int(idx))))
+    log("case: serving configuration, ids %s" % [(cid, T.shape) for cid, T in reqs])
+    tks = [srv.submit(cid, T) for cid, T in reqs]
+    res = _wait(srv, tks, timeout=120.0)
+    srv.close()
+    for (cid, T), tk in zip(reqs, tks):
+        J, q, info = res[tk[0]]
+        eJ = radiosity.relative_l2(J, ref["J_%d" % cid])
+        eq = radiosity.relative_l2(q, ref["q_%d" % cid])
+        log("id %d (%d facets, %d columns): residual %.1e, e(J) max %.2e, e(q) max %.2e" %
+            (cid, T.shape[0], T.shape[1], info["rel_residual"], eJ.max(), eq.max()))
+        assert info["rel_residual"] <= 1e-7
+        assert np.all(eJ <= 1e-6) and np.all(eq <= 1e-6)

@@ -106,3 +106,49 @@ def test_two_plate_transient_pin_rejects_flipped_exchange_sign():
     from oracle import transient
     To, _, _ = transient.newton_step(rad, Tn, np.zeros_like(Tn), mc, dt, tol=1e-15, max_newton=80)
     assert abs(To[0, 0] - x1) <= 1e-12 * x1
+
+
+def _mutant_matfree(tmp_path, name, old, new):
+    """Builds ``oracle/vf_matfree.c`` with one planted change."""
+    import os
+    import subprocess
+
+    from oracle import matfree
+    src = open(os.path.join(os.path.dirname(matfree.__file__), "vf_matfree.c")).read()
+    assert old in src
+    path = tmp_path / ("%s.c" % name)
+    path.write_text(src.replace(old, new, 1))
+    so = tmp_path / ("%s.so" % name)
+    subprocess.run(["gcc", "-O2", "-fopenmp", "-ffp-contract=off", "-fPIC", "-shared", "-o", str(so), str(path)],
+                   check=True)
+    return matfree.load(str(so))
+
+
+def test_matrix_free_pins_reject_planted_kernel_mistakes(tmp_path):
+    """The large-n oracle's C product is pinned by the dense oracle and the
+    projected-sphere closed form; a dropped area factor, a flipped cosine
+    sign and a skipped last column each fail them."""
+    from oracle import geometry, matfree
+    v, f = meshes.ellipsoid(6, (3.0, 2.0, 1.0))
+    f = meshes.inward(f)
+    c, n, a = geometry.facets_from_triangles(v, f)
+    F = viewfactor.view_factor_matrix(c, n, a)
+    X = np.random.default_rng(4).uniform(0.5, 1.5, (a.size, 2))
+    ref = F @ X
+    p, nr, w = meshes.projected_sphere_points(2, radius=1.3, seed=3)
+    sref = closed_forms.sphere_points_F(w, 1.3) @ np.ones(w.size)
+
+    def errors(lib):
+        mf = matfree.MatrixFreeF(c, n, a, lib=lib)
+        e1 = np.max(np.abs(mf @ X - ref)) / np.max(np.abs(ref))
+        ms = matfree.MatrixFreeF(p, nr, w, lib=lib)
+        e2 = np.max(np.abs(ms @ np.ones(w.size) - sref)) / np.max(np.abs(sref))
+        return e1, e2
+
+    good = errors(None)
+    assert max(good) < 1e-13
+    for name, old, new in (("drop_area", "* aj;", ";"),
+                           ("sign_flip", "const double cj = -((mx", "const double cj = ((mx"),
+                           ("skip_last", "for (int64_t j = 0; j < n; ++j)", "for (int64_t j = 0; j < n - 1; ++j)")):
+        e1, e2 = errors(_mutant_matfree(tmp_path, name, old, new))
+        assert max(e1, e2) > 1e-3, name
