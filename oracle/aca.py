@@ -22,6 +22,10 @@ This oracle follows the deterministic partial-pivoting reading:
 4. stop when ``|u| |v| <= eps_rel sqrt(S2)`` or the rank cap is reached;
    otherwise the next row is ``argmax |u(i)|`` over unused rows (first on ties).
 
+Recompression (optional): the crosses of a block stored low-rank are
+truncated to the smallest rank that keeps the discarded singular values of
+``U V^T`` within the tolerance (``recompress``).
+
 Storage rule: the block is kept dense when the cap
 ``min(k_max, ceil(mn/(m+n)))`` is reached without meeting the stop test, or
 when ``k (m + n) >= m n`` (low-rank storage would not be smaller).
@@ -105,6 +109,29 @@ def rank_cap(m: int, n: int, k_max: int) -> int:
     return max(1, min(k_max, -(-(m * n) // (m + n))))
 
 
+def recompress(U, V, tol: float):
+    """Post-processing of a cross approximation into truncated-SVD form
+    (Sec. 4.3: the crosses are brought to standard form ``U V^T``; Sec. 5.1:
+    ranks are set from the singular value decay at a fixed relative
+    accuracy).  Householder QR of both factors (LAPACK), SVD of the small
+    core ``R_u R_v^T = W S Z^T``, and the smallest rank ``r >= 1`` whose
+    discarded singular values satisfy ``sqrt(sum_{i>r} s_i^2) <= tol *
+    sqrt(sum_i s_i^2)`` (the Frobenius form of eq. (31)).  Returns
+    ``U' = Q_u W_r S_r`` (m x r) and ``V' = Q_v Z_r`` (n x r, orthonormal
+    columns)."""
+    Qu, Ru = np.linalg.qr(U)
+    Qv, Rv = np.linalg.qr(V)
+    W, S, Zt = np.linalg.svd(Ru @ Rv.T)
+    tail = np.sqrt(np.cumsum((S**2)[::-1]))[::-1]  # tail[r] = sqrt(sum_{i >= r} s_i^2)
+    limit = tol * math.sqrt(float(np.sum(S**2)))
+    r = S.size
+    for q in range(1, S.size):
+        if tail[q] <= limit:
+            r = q
+            break
+    return Qu @ (W[:, :r] * S[:r]), Qv @ Zt[:r].T
+
+
 @dataclass
 class HMatrix:
     n: int
@@ -143,9 +170,12 @@ class HMatrix:
         return d, lr
 
 
-def build_hmatrix(c, nrm, area, n_min: int, eta: float, tol: float, k_max: int = 256) -> HMatrix:
+def build_hmatrix(c, nrm, area, n_min: int, eta: float, tol: float, k_max: int = 256,
+                  recompress_tol: float | None = None) -> HMatrix:
     """Cluster tree (Alg. 1), block tree (Alg. 2), dense near field, ACA
-    (eqs. (30)-(31)) on every admissible block, with the storage rule."""
+    (eqs. (30)-(31)) on every admissible block, with the storage rule; with
+    ``recompress_tol``, every block stored low-rank is then truncated by
+    ``recompress`` (the storage rule is decided on the ACA rank)."""
     root, perm = clustering.build_index_tree(c, n_min)
     dense_blocks, lr_blocks = clustering.build_block_tree(root, eta)
     cp, np_, ap = c[perm], nrm[perm], area[perm]
@@ -166,6 +196,9 @@ def build_hmatrix(c, nrm, area, n_min: int, eta: float, tol: float, k_max: int =
         if (not res.converged) or k * (m + nn) >= m * nn:
             dense.append((r0, r1, c0, c1, view_factor_block(cp, np_, ap, rows, cols)))
             fallback += 1
+        elif recompress_tol is not None:
+            U2, V2 = recompress(res.U, res.V, recompress_tol)
+            lowrank.append((r0, r1, c0, c1, U2, V2))
         else:
             lowrank.append((r0, r1, c0, c1, res.U, res.V))
     return HMatrix(c.shape[0], perm, dense, lowrank, fallback)

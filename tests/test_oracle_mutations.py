@@ -152,3 +152,51 @@ def test_matrix_free_pins_reject_planted_kernel_mistakes(tmp_path):
                            ("skip_last", "for (int64_t j = 0; j < n; ++j)", "for (int64_t j = 0; j < n - 1; ++j)")):
         e1, e2 = errors(_mutant_matfree(tmp_path, name, old, new))
         assert max(e1, e2) > 1e-3, name
+
+
+def test_recompression_pins_reject_planted_mistakes():
+    """A truncation on the largest discarded singular value instead of the
+    Frobenius tail, a core without its singular values, and factors whose
+    QR is taken on the wrong side each fail the Eckart-Young pin."""
+    from oracle import aca
+
+    # one dominant value and a flat tail: the Frobenius and the largest-value
+    # criteria keep different ranks
+    s = np.array([1.0] + [1e-2] * 10 + [1e-3])
+    rng = np.random.default_rng(22)
+    k = s.size
+    Q1, _ = np.linalg.qr(rng.standard_normal((60, k)))
+    Q2, _ = np.linalg.qr(rng.standard_normal((50, k)))
+    Mx = np.eye(k) + 0.3 * rng.standard_normal((k, k))
+    U, V = Q1 @ np.diag(s) @ Mx, Q2 @ np.linalg.inv(Mx).T
+    X = U @ V.T
+    tol = 2e-2
+    tail = np.sqrt(np.cumsum((s**2)[::-1]))[::-1]
+    r_exp = next(q for q in range(1, k) if tail[q] <= tol * np.linalg.norm(s))
+
+    def pin_ok(fn):
+        U2, V2 = fn(U, V, tol)
+        err = np.linalg.norm(X - U2 @ V2.T)
+        return U2.shape[1] == r_exp and abs(err - tail[r_exp]) <= 1e-10 * tail[r_exp]
+
+    def spectral(U, V, tol):
+        Qu, Ru = np.linalg.qr(U)
+        Qv, Rv = np.linalg.qr(V)
+        W, S, Zt = np.linalg.svd(Ru @ Rv.T)
+        r = next((q for q in range(1, S.size) if S[q] <= tol * S[0]), S.size)
+        return Qu @ (W[:, :r] * S[:r]), Qv @ Zt[:r].T
+
+    def no_sigma(U, V, tol):
+        U2, V2 = aca.recompress(U, V, tol)
+        return U2 / np.linalg.norm(U2, axis=0), V2
+
+    def wrong_side(U, V, tol):
+        Qu, Ru = np.linalg.qr(U)
+        Qv, Rv = np.linalg.qr(V)
+        W, S, Zt = np.linalg.svd(Ru.T @ Rv)
+        r = aca.recompress(U, V, tol)[0].shape[1]
+        return Qu @ (W[:, :r] * S[:r]), Qv @ Zt[:r].T
+
+    assert pin_ok(aca.recompress)
+    for fn in (spectral, no_sigma, wrong_side):
+        assert not pin_ok(fn), fn.__name__

@@ -367,3 +367,61 @@ def test_transient_two_plates_direction_of_exchange(e1, e2, T1, T2, dt):
     assert abs(T[1, 0] - x2) <= 1e-12 * x2
     # the hotter plate cooled, the colder one warmed
     assert (T[0, 0] - T1) * (T2 - T1) > 0
+
+
+# ---------------------------------------------------------------- recompression (Sec. 4.3 post-processing)
+def _planted(m, n, svals, seed):
+    """U V^T = Q1 diag(s) Q2^T with known singular values s, spread over a
+    random (well-conditioned) non-orthogonal factor pair."""
+    rng = np.random.default_rng(seed)
+    k = len(svals)
+    Q1, _ = np.linalg.qr(rng.standard_normal((m, k)))
+    Q2, _ = np.linalg.qr(rng.standard_normal((n, k)))
+    Mx = np.eye(k) + 0.3 * rng.standard_normal((k, k))
+    U = Q1 @ np.diag(svals) @ Mx
+    V = Q2 @ np.linalg.inv(Mx).T
+    return U, V, Q1 @ np.diag(svals) @ Q2.T
+
+
+def test_recompress_recovers_a_planted_rank():
+    rng = np.random.default_rng(21)
+    m, n, r, k = 90, 70, 5, 14
+    U = rng.standard_normal((m, r)) @ rng.standard_normal((r, k))
+    V = rng.standard_normal((n, r)) @ rng.standard_normal((r, k))
+    U2, V2 = aca.recompress(U, V, 1e-10)
+    X = U @ V.T
+    assert U2.shape == (m, r) and V2.shape == (n, r)
+    assert np.linalg.norm(U2 @ V2.T - X) <= 1e-13 * np.linalg.norm(X)
+    assert np.allclose(V2.T @ V2, np.eye(r), atol=1e-13)
+
+
+def test_recompress_truncates_at_the_eckart_young_error():
+    """Known singular values (s_i = 10^(-i/2), and one dominant value over a
+    flat tail): the kept rank is the smallest r with
+    sqrt(sum_{i>=r} s_i^2) <= tol |s|, and the error of the truncated factors
+    equals that tail (the best rank-r error, Eckart-Young)."""
+    spectra = ((10.0 ** (-0.5 * np.arange(12)), (3e-1, 2e-2, 1e-3, 5e-5)),
+               (np.array([1.0] + [1e-2] * 10 + [1e-3]), (2e-2, 5e-3)))
+    for s, tols in spectra:
+        U, V, X = _planted(60, 50, s, 22)
+        tail = np.sqrt(np.cumsum((s**2)[::-1]))[::-1]
+        for tol in tols:
+            r_exp = next(q for q in range(1, s.size) if tail[q] <= tol * np.linalg.norm(s))
+            U2, V2 = aca.recompress(U, V, tol)
+            assert U2.shape[1] == r_exp
+            err = np.linalg.norm(X - U2 @ V2.T)
+            assert abs(err - tail[r_exp]) <= 1e-10 * tail[r_exp]
+            assert err <= tol * np.linalg.norm(X)
+
+
+def test_recompressed_hmatrix_meets_tolerance_with_fewer_entries():
+    v, f = meshes.ellipsoid(9, (3.0, 2.0, 1.0))
+    f = meshes.inward(f)
+    c, n, a = geometry.facets_from_triangles(v, f)
+    F = viewfactor.view_factor_matrix(c, n, a)
+    H = aca.build_hmatrix(c, n, a, 32, 1.5, 1e-6)
+    Hr = aca.build_hmatrix(c, n, a, 32, 1.5, 1e-6, recompress_tol=1e-6)
+    e, er = (np.linalg.norm(h.to_dense() - F) / np.linalg.norm(F) for h in (H, Hr))
+    assert er <= 1e-6 and e <= 1e-6
+    assert Hr.stored_entries()[1] < 0.9 * H.stored_entries()[1]
+    assert all(B[4].shape[1] <= A[4].shape[1] for A, B in zip(H.lowrank, Hr.lowrank))
