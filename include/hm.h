@@ -139,6 +139,14 @@ typedef struct {
                               defaults (128 rows, 16 KB).  Results are the same bit for bit
                               either way except for the order of partial sums.  HM_EINVAL
                               outside 0..16. */
+  int32_t recompress;      /* 1: truncate every block stored low-rank to its smallest rank r whose
+                              discarded singular values satisfy sqrt(sum_{i>r} s_i^2) <= aca_tol *
+                              |s|_2 (Sec. 4.3 post-processing into U V^T; Sec. 5.1 truncation at
+                              eps_rel): FP64 QR-free SVD of the crosses on the GPU, V' with
+                              orthonormal columns.  The dense/low-rank decision is taken on the
+                              ACA rank; blocks of ACA rank above 256 keep their crosses.  0: the
+                              ACA crosses are stored as they are (default).  HM_EINVAL outside
+                              0..1. */
 } hm_assembly_params;
 
 /* Evaluate the near field (every inadmissible leaf block, FP64 evaluation

@@ -275,6 +275,7 @@ void check_assembly_params(const hm_assembly_params* p, const char* fn) {
              f + ": a BF16 near field needs BF16 factors and keep_f32_copy (FP32 copies for FP64-vector products)");
   HM_REQUIRE(p->dense_dtype != HM_BF16 || !p->closed_row_scale, f + ": closed_row_scale needs an FP32 or FP64 near field");
   HM_REQUIRE(p->autotune >= 0 && p->autotune <= 16, f + ": autotune must be in 0..16");
+  HM_REQUIRE(p->recompress == 0 || p->recompress == 1, f + ": recompress must be 0 or 1");
 }
 }  // namespace
 

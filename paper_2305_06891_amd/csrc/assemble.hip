@@ -8,6 +8,7 @@
 
 #include "dev_common.hpp"
 #include "hm_internal.hpp"
+#include "recompress.hpp"
 
 namespace hm {
 
@@ -525,6 +526,8 @@ void finish_job(AsmJob& J, const std::vector<DevBuf>& stages, hipStream_t s) {
   const hm_assembly_params& p = J.p;
   auto& dn = J.dn;
   auto& lr = J.lr;
+  // blocks whose recompressed factors are all zero hold nothing
+  lr.erase(std::remove_if(lr.begin(), lr.end(), [](const LrInfo& l) { return l.k == 0; }), lr.end());
   std::sort(dn.begin(), dn.end(), [](const BlockRef& x, const BlockRef& y) {
     return x.rb != y.rb ? x.rb < y.rb : x.cb < y.cb;
   });
@@ -784,6 +787,10 @@ std::vector<hm_matrix*> assemble_batch(hm_ctx& ctx, const std::vector<const hm_t
     // dense fallback; factors compacted per stored precision (FP64 stage for
     // FP64 factors, FP32 otherwise)
     std::vector<CompactDev> cd[2];
+    // blocks truncated by recompression instead of compacted as they are,
+    // with the job and the position in its low-rank list of each
+    std::vector<RcDev> rc[2];
+    std::vector<std::pair<AsmJob*, size_t>> rc_lr[2];
     int64_t off[2] = {0, 0};
     int32_t sidx[2] = {-1, -1};
     for (int w = 0; w < 2; ++w) {
@@ -806,23 +813,45 @@ std::vector<hm_matrix*> assemble_batch(hm_ctx& ctx, const std::vector<const hm_t
       }
       if (k == 0) continue;  // exactly zero block
       const int w = J.p.lowrank_dtype == HM_F64 ? 1 : 0;
-      cd[w].push_back(CompactDev{a.u_off, a.v_off, off[w], off[w] + (int64_t)m * k, m, nn, k, 0});
+      if (J.p.recompress && k >= 2 && k <= RC_KMAX) {
+        // the stage keeps room for the ACA rank; the truncated factors
+        // (rank r <= k) are written at the same offsets
+        rc[w].push_back(RcDev{a.u_off, a.v_off, 0, off[w], off[w] + (int64_t)m * k, m, nn, k,
+                              (int32_t)rc[w].size(), a.tol});
+        rc_lr[w].emplace_back(&J, J.lr.size());
+      } else {
+        cd[w].push_back(CompactDev{a.u_off, a.v_off, off[w], off[w] + (int64_t)m * k, m, nn, k, 0});
+      }
       J.lr.push_back(LrInfo{br, k, sidx[w], off[w], off[w] + (int64_t)m * k});
       off[w] += (int64_t)k * (m + nn);
       stage_last[sidx[w]] = std::max<size_t>(stage_last[sidx[w]], (size_t)bjob[q]);
     }
     for (int w = 0; w < 2; ++w) {
-      if (cd[w].empty()) continue;
+      if (cd[w].empty() && rc[w].empty()) continue;
       DevBuf& stg = stages[sidx[w]];
       stg.alloc(off[w] * (w ? 8 : 4));
-      upload(d_cd, cd[w], s);
-      if (w)
-        hipLaunchKernelGGL(k_compact<double>, dim3((unsigned)cd[w].size()), dim3(256), 0, s,
-                           d_cd.get<CompactDev>(), scratch.get<double>(), stg.get<double>());
-      else
-        hipLaunchKernelGGL(k_compact<float>, dim3((unsigned)cd[w].size()), dim3(256), 0, s,
-                           d_cd.get<CompactDev>(), scratch.get<double>(), stg.get<float>());
-      HM_HIP(hipGetLastError());
+      if (!cd[w].empty()) {
+        upload(d_cd, cd[w], s);
+        if (w)
+          hipLaunchKernelGGL(k_compact<double>, dim3((unsigned)cd[w].size()), dim3(256), 0, s,
+                             d_cd.get<CompactDev>(), scratch.get<double>(), stg.get<double>());
+        else
+          hipLaunchKernelGGL(k_compact<float>, dim3((unsigned)cd[w].size()), dim3(256), 0, s,
+                             d_cd.get<CompactDev>(), scratch.get<double>(), stg.get<float>());
+        HM_HIP(hipGetLastError());
+      }
+      if (!rc[w].empty()) {
+        DevBuf d_nr(rc[w].size() * 4);
+        recompress_blocks(rc[w], scratch.get<double>(), stg.get(), w == 1, d_nr.get<int>(), s);
+        std::vector<int> nr(rc[w].size());
+        HM_HIP(hipMemcpyAsync(nr.data(), d_nr.get(), nr.size() * 4, hipMemcpyDeviceToHost, s));
+        HM_HIP(hipStreamSynchronize(s));
+        for (size_t q = 0; q < nr.size(); ++q) {
+          LrInfo& l = rc_lr[w][q].first->lr[rc_lr[w][q].second];
+          HM_REQUIRE(nr[q] >= 0 && nr[q] <= l.k, "assemble: recompression raised a rank");
+          l.k = nr[q];
+        }
+      }
       HM_HIP(hipStreamSynchronize(s));  // scratch is reused by the next batch
     }
     finish_ready();

@@ -1,0 +1,453 @@
+// Recompression of ACA crosses into truncated-SVD form on gfx950 (Sec. 4.3:
+// the cross approximation is post-processed into standard low-rank factors;
+// Sec. 5.1: ranks follow the singular value decay at the relative accuracy
+// eps_rel).  One workgroup per block, FP64 throughout:
+//
+//  1. column scaling: U = Uh diag(a), V = Vh diag(b) with unit columns
+//     (a_l = |u_l|, b_l = |v_l|), so U V^T = Uh D Vh^T, D = diag(a b);
+//  2. Gram matrices Gu = Uh^T Uh, Gv = Vh^T Vh (k x k);
+//  3. pivoted Cholesky Gu ~ Ru^T Ru (largest remaining diagonal first,
+//     stopped when it falls below RC_DROP: columns within 1e-8 of the span
+//     of the selected ones add nothing), so Uh ~ Qu Ru with
+//     Qu = Uh_sel Ru11^-1 orthonormal; the same for V;
+//  4. core K = Ru D Rv^T (ru x rv), SVD by one-sided Jacobi (cyclic
+//     round-robin pairs, rotations accumulated in Z): K Z = W S;
+//  5. the smallest rank r >= 1 with sqrt(sum_{i>r} s_i^2) <= tol |s|_2
+//     (Frobenius form of eq. (31));
+//  6. U' = U Tu, V' = V Tv with Tu = diag(1/a) [Ru11^-1 (K Z)_r] on the
+//     selected rows and Tv = diag(1/b) [Rv11^-1 Z_r], so that U' = Qu W_r S_r
+//     and V' = Qv Z_r (orthonormal columns); a second kernel forms them
+//     straight into the staging buffer of the compacted factors.
+//
+// Untruncated, the factors reproduce U V^T whatever the accuracy of the
+// Cholesky factors (the same Ru, Rv are used on both sides), so rounding in
+// the Gram matrices only perturbs the directions that are cut.
+#include <algorithm>
+#include <cmath>
+#include <climits>
+
+#include "dev_common.hpp"
+#include "hm_internal.hpp"
+#include "recompress.hpp"
+
+namespace hm {
+
+namespace {
+
+constexpr int RC_T = 256;                 // threads per workgroup
+constexpr int RC_W = RC_T / 64;           // waves
+constexpr int RC_LP = 16;                 // lanes per Jacobi pair
+constexpr int RC_GROUPS = RC_T / RC_LP;   // Jacobi pairs in flight
+constexpr int RC_ROWS = 16;               // panel rows staged per Gram pass
+constexpr int RC_SWEEPS = 40;             // Jacobi sweep limit
+constexpr double RC_DROP = 1e-16;         // pivoted Cholesky stop (unit diagonal)
+constexpr double RC_JTOL = 1e-13;         // Jacobi: |g| <= RC_JTOL sqrt(a b) counts as orthogonal
+
+struct RcMax {
+  double mag;
+  int idx;
+};
+
+__device__ inline RcMax rc_better(RcMax a, RcMax b) {
+  if (b.mag > a.mag || (b.mag == a.mag && b.idx < a.idx)) return b;
+  return a;
+}
+
+__device__ RcMax rc_block_max(RcMax v, RcMax* sh) {
+  for (int o = 32; o > 0; o >>= 1) {
+    RcMax w;
+    w.mag = __shfl_xor(v.mag, o, 64);
+    w.idx = __shfl_xor(v.idx, o, 64);
+    v = rc_better(v, w);
+  }
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+  __syncthreads();
+  RcMax r = sh[0];
+  for (int w = 1; w < RC_W; ++w) r = rc_better(r, sh[w]);
+  return r;
+}
+
+__device__ double rc_block_sum(double v, double* sh) {
+  v = wave_sum(v);
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double s = sh[0];
+  for (int w = 1; w < RC_W; ++w) s += sh[w];
+  return s;
+}
+
+__device__ inline double grp_sum(double v) {
+#pragma unroll
+  for (int o = RC_LP / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, RC_LP);
+  return v;
+}
+
+// Column 2-norms of a len x k column-major panel (one wave per column).
+__device__ void rc_colnorms(const double* __restrict__ P, int len, int k, double* __restrict__ nrm) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  for (int l = wid; l < k; l += RC_W) {
+    double s = 0.0;
+    for (int i = lane; i < len; i += 64) {
+      const double v = P[(int64_t)l * len + i];
+      s += v * v;
+    }
+    s = wave_sum(s);
+    if (lane == 0) nrm[l] = sqrt(s);
+  }
+}
+
+// G = S^T S for S = P diag(inv) (len x k, column-major): 4 x 4 tiles of the
+// upper triangle, one per thread per pass, over rows staged RC_ROWS at a
+// time in LDS; both triangles of G (ld k) are written.
+__device__ void rc_gram(const double* __restrict__ P, int len, int k, const double* __restrict__ inv,
+                        double* __restrict__ G, double* __restrict__ stage) {
+  const int nt = (k + 3) / 4, kc = 4 * nt;
+  const int ntiles = nt * (nt + 1) / 2;
+  for (int t0 = 0; t0 < ntiles; t0 += RC_T) {
+    const int t = t0 + (int)threadIdx.x;
+    const bool have = t < ntiles;
+    int tp = 0, tq = 0;
+    if (have) {
+      int rem = t;
+      while (rem >= nt - tp) {
+        rem -= nt - tp;
+        ++tp;
+      }
+      tq = tp + rem;
+    }
+    double acc[4][4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = 0; b < 4; ++b) acc[a][b] = 0.0;
+    for (int i0 = 0; i0 < len; i0 += RC_ROWS) {
+      const int rows = min(RC_ROWS, len - i0);
+      __syncthreads();
+      for (int e = threadIdx.x; e < RC_ROWS * kc; e += RC_T) {
+        const int c = e / RC_ROWS, r = e % RC_ROWS;
+        stage[r * RC_KMAX + c] = (r < rows && c < k) ? P[(int64_t)c * len + i0 + r] * inv[c] : 0.0;
+      }
+      __syncthreads();
+      if (have)
+        for (int r = 0; r < rows; ++r) {
+          const double* row = stage + r * RC_KMAX;
+          double x[4], y[4];
+#pragma unroll
+          for (int a = 0; a < 4; ++a) {
+            x[a] = row[4 * tp + a];
+            y[a] = row[4 * tq + a];
+          }
+#pragma unroll
+          for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int b = 0; b < 4; ++b) acc[a][b] += x[a] * y[b];
+        }
+    }
+    if (have)
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+          const int p = 4 * tp + a, q = 4 * tq + b;
+          if (p < k && q < k) {
+            G[(int64_t)p * k + q] = acc[a][b];
+            G[(int64_t)q * k + p] = acc[a][b];
+          }
+        }
+  }
+  __syncthreads();
+}
+
+// Pivoted Cholesky of the k x k Gram matrix G: rows s of R (ld k, all k
+// columns; zero at the columns selected before step s), sel[s] = column of
+// step s.  Returns the number of steps (the numerical rank).
+__device__ int rc_pchol(const double* __restrict__ G, int k, double* __restrict__ R, int* __restrict__ sel,
+                        double* __restrict__ d, int* __restrict__ taken, RcMax* sh) {
+  for (int j = threadIdx.x; j < k; j += RC_T) {
+    d[j] = G[(int64_t)j * k + j];
+    taken[j] = 0;
+  }
+  __syncthreads();
+  int rr = 0;
+  for (int s = 0; s < k; ++s) {
+    RcMax am{-1.0, INT_MAX};
+    for (int j = threadIdx.x; j < k; j += RC_T)
+      if (!taken[j]) am = rc_better(am, RcMax{d[j], j});
+    am = rc_block_max(am, sh);
+    if (am.idx == INT_MAX || !(am.mag > RC_DROP)) break;
+    const int p = am.idx;
+    const double rpp = sqrt(am.mag);
+    for (int j = threadIdx.x; j < k; j += RC_T) {
+      double v;
+      if (j == p) {
+        v = rpp;
+      } else if (taken[j]) {
+        v = 0.0;
+      } else {
+        double x = G[(int64_t)p * k + j];
+        for (int t = 0; t < s; ++t) x -= R[(int64_t)t * k + p] * R[(int64_t)t * k + j];
+        v = x / rpp;
+      }
+      R[(int64_t)s * k + j] = v;
+    }
+    __syncthreads();
+    for (int j = threadIdx.x; j < k; j += RC_T)
+      if (!taken[j] && j != p) d[j] -= R[(int64_t)s * k + j] * R[(int64_t)s * k + j];
+    if (threadIdx.x == 0) {
+      taken[p] = 1;
+      sel[s] = p;
+    }
+    __syncthreads();
+    rr = s + 1;
+  }
+  return rr;
+}
+
+// Back substitution R11 y = b for the upper-triangular ru x ru matrix
+// R11(s, s') = R(s, sel[s']) (one thread per right-hand side).
+__device__ void rc_backsub(const double* __restrict__ R, int k, const int* __restrict__ sel, int ru,
+                           double* __restrict__ y) {
+  for (int s = ru - 1; s >= 0; --s) {
+    double x = y[s];
+    for (int s2 = s + 1; s2 < ru; ++s2) x -= R[(int64_t)s * k + sel[s2]] * y[s2];
+    y[s] = x / R[(int64_t)s * k + sel[s]];
+  }
+}
+
+}  // namespace
+
+int64_t recompress_work_doubles(int k) { return 8 * (int64_t)k * k; }
+
+// Ranks and transforms of one chunk of blocks.  Workspace per block
+// (doubles, ld k): Gu | Ru | Gv | Rv | K | Z | Tu | Tv.
+__global__ __launch_bounds__(RC_T) void k_recompress(const RcDev* __restrict__ blocks, const double* __restrict__ scratch,
+                                                     double* __restrict__ work, int* __restrict__ newrank) {
+  __shared__ double stage[RC_ROWS * RC_KMAX];
+  __shared__ double ia[RC_KMAX], ib[RC_KMAX], dd[RC_KMAX], sig[RC_KMAX];
+  __shared__ int selu[RC_KMAX], selv[RC_KMAX], taken[RC_KMAX], order[RC_KMAX];
+  __shared__ RcMax sh_max[RC_W];
+  __shared__ double sh_sum[RC_W];
+  __shared__ int sh_rot;
+  const RcDev b = blocks[blockIdx.x];
+  const int m = b.m, n = b.n, k = b.k;
+  const double* U = scratch + b.u_off;
+  const double* V = scratch + b.v_off;
+  double* W = work + b.w_off;
+  double *Gu = W, *Ru = W + k * k, *Gv = W + 2 * k * k, *Rv = W + 3 * k * k;
+  double *K = W + 4 * k * k, *Z = W + 5 * k * k, *Tu = W + 6 * k * k, *Tv = W + 7 * k * k;
+  const int tid = threadIdx.x;
+
+  // 1. column scales (a zero column gets scale 0 and drops out)
+  rc_colnorms(U, m, k, ia);
+  rc_colnorms(V, n, k, ib);
+  __syncthreads();
+  for (int l = tid; l < k; l += RC_T) {
+    const double a = ia[l], c = ib[l];
+    dd[l] = a * c;  // D = diag(a b)
+    ia[l] = a > 0.0 ? 1.0 / a : 0.0;
+    ib[l] = c > 0.0 ? 1.0 / c : 0.0;
+  }
+  __syncthreads();
+  // 2-3. Gram matrices and their pivoted Cholesky factors
+  rc_gram(U, m, k, ia, Gu, stage);
+  rc_gram(V, n, k, ib, Gv, stage);
+  const int ru = rc_pchol(Gu, k, Ru, selu, sig, taken, sh_max);
+  const int rv = rc_pchol(Gv, k, Rv, selv, sig, taken, sh_max);
+  // 4. K = Ru D Rv^T (ru x rv, column t at K + t k), Z = I (rv x rv)
+  for (int e = tid; e < ru * rv; e += RC_T) {
+    const int s = e % ru, t = e / ru;
+    double x = 0.0;
+    for (int l = 0; l < k; ++l) x += Ru[(int64_t)s * k + l] * dd[l] * Rv[(int64_t)t * k + l];
+    K[(int64_t)t * k + s] = x;
+  }
+  for (int e = tid; e < rv * rv; e += RC_T) Z[(int64_t)(e / rv) * k + e % rv] = (e / rv == e % rv) ? 1.0 : 0.0;
+  __syncthreads();
+  // one-sided Jacobi on the columns of K: round-robin pairs over np
+  // positions (np = rv rounded up to even; position rv is a dummy)
+  const int np = (rv + 1) & ~1;
+  const int g = tid / RC_LP, gl = tid % RC_LP;
+  for (int sweep = 0; sweep < RC_SWEEPS && np >= 2; ++sweep) {
+    if (tid == 0) sh_rot = 0;
+    __syncthreads();
+    int rotated = 0;
+    for (int step = 0; step < np - 1; ++step) {
+      for (int pi = g; pi < np / 2; pi += RC_GROUPS) {
+        auto pos = [&](int j) { return j == 0 ? 0 : ((j - 1 + step) % (np - 1)) + 1; };
+        int p = pos(pi), q = pos(np - 1 - pi);
+        if (p > q) {
+          const int t = p;
+          p = q;
+          q = t;
+        }
+        if (q >= rv) continue;
+        double* kp = K + (int64_t)p * k;
+        double* kq = K + (int64_t)q * k;
+        double al = 0.0, be = 0.0, ga = 0.0;
+        for (int i = gl; i < ru; i += RC_LP) {
+          const double x = kp[i], y = kq[i];
+          al += x * x;
+          be += y * y;
+          ga += x * y;
+        }
+        al = grp_sum(al);
+        be = grp_sum(be);
+        ga = grp_sum(ga);
+        if (ga != 0.0 && fabs(ga) > RC_JTOL * sqrt(al * be)) {
+          const double zeta = (be - al) / (2.0 * ga);
+          const double tt = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+          const double c = 1.0 / sqrt(1.0 + tt * tt), sn = c * tt;
+          for (int i = gl; i < ru; i += RC_LP) {
+            const double x = kp[i], y = kq[i];
+            kp[i] = c * x - sn * y;
+            kq[i] = sn * x + c * y;
+          }
+          double* zp = Z + (int64_t)p * k;
+          double* zq = Z + (int64_t)q * k;
+          for (int i = gl; i < rv; i += RC_LP) {
+            const double x = zp[i], y = zq[i];
+            zp[i] = c * x - sn * y;
+            zq[i] = sn * x + c * y;
+          }
+          rotated = 1;
+        }
+      }
+      __syncthreads();
+    }
+    if (rotated) atomicOr(&sh_rot, 1);
+    __syncthreads();
+    const int any = sh_rot;
+    __syncthreads();
+    if (!any) break;
+  }
+  // 5. singular values (column norms of K Z), their descending order and the rank
+  for (int t = tid; t < rv; t += RC_T) {
+    double s2 = 0.0;
+    for (int i = 0; i < ru; ++i) s2 += K[(int64_t)t * k + i] * K[(int64_t)t * k + i];
+    sig[t] = sqrt(s2);
+  }
+  __syncthreads();
+  for (int t = tid; t < rv; t += RC_T) {
+    int rank = 0;
+    for (int u = 0; u < rv; ++u) rank += (sig[u] > sig[t] || (sig[u] == sig[t] && u < t)) ? 1 : 0;
+    order[rank] = t;
+  }
+  __syncthreads();
+  double tot = 0.0;
+  for (int t = tid; t < rv; t += RC_T) tot += sig[t] * sig[t];
+  tot = rc_block_sum(tot, sh_sum);
+  int r = 0;
+  if (tid == 0 && tot > 0.0) {
+    const double lim = b.tol * sqrt(tot);
+    double tail2 = 0.0;  // sum of the discarded squares, from the smallest up
+    r = rv;
+    for (int c = rv - 1; c >= 1; --c) {
+      const double s = sig[order[c]];
+      tail2 += s * s;
+      if (sqrt(tail2) <= lim) r = c;
+      else break;
+    }
+    newrank[b.out] = r;
+  } else if (tid == 0) {
+    newrank[b.out] = 0;
+  }
+  if (tid == 0) sh_rot = r;
+  __syncthreads();
+  r = sh_rot;
+  // 6. Tu (k x r) and Tv (k x r): back substitutions on the selected rows
+  for (int c = tid; c < r; c += RC_T) {
+    const int t = order[c];
+    double* tu = Tu + (int64_t)c * k;
+    double* tv = Tv + (int64_t)c * k;
+    for (int l = 0; l < k; ++l) tu[l] = tv[l] = 0.0;
+    // y (in the first ru entries of the column, then moved to the rows sel)
+    double* y = Gu + (int64_t)c * k;  // Gu is free now: scratch column per rank
+    for (int s = 0; s < ru; ++s) y[s] = K[(int64_t)t * k + s];
+    rc_backsub(Ru, k, selu, ru, y);
+    for (int s = 0; s < ru; ++s) tu[selu[s]] = y[s] * ia[selu[s]];
+    double* z = Gv + (int64_t)c * k;
+    for (int s = 0; s < rv; ++s) z[s] = Z[(int64_t)t * k + s];
+    rc_backsub(Rv, k, selv, rv, z);
+    for (int s = 0; s < rv; ++s) tv[selv[s]] = z[s] * ib[selv[s]];
+  }
+}
+
+// U' = U Tu and V' = V Tv into the staging buffer (m x r and n x r,
+// column-major at du and dv), 16 output columns at a time with the
+// transform columns in LDS.
+template <class ST>
+__global__ __launch_bounds__(RC_T) void k_recompress_apply(const RcDev* __restrict__ blocks,
+                                                           const double* __restrict__ scratch,
+                                                           const double* __restrict__ work,
+                                                           const int* __restrict__ newrank, ST* __restrict__ stage) {
+  __shared__ double T[RC_KMAX * 16];
+  const RcDev b = blocks[blockIdx.x];
+  const int k = b.k;
+  const int r = newrank[b.out];
+  const double* Wk = work + b.w_off;
+  for (int side = 0; side < 2; ++side) {
+    const int len = side ? b.n : b.m;
+    const double* P = scratch + (side ? b.v_off : b.u_off);
+    const double* Tm = Wk + (int64_t)(side ? 7 : 6) * k * k;
+    ST* out = stage + (side ? b.dv : b.du);
+    for (int c0 = 0; c0 < r; c0 += 16) {
+      const int nc = min(16, r - c0);
+      __syncthreads();
+      for (int e = threadIdx.x; e < k * 16; e += RC_T) {
+        const int l = e % k, c = e / k;
+        T[l * 16 + c] = c < nc ? Tm[(int64_t)(c0 + c) * k + l] : 0.0;
+      }
+      __syncthreads();
+      for (int i = threadIdx.x; i < len; i += RC_T) {
+        double acc[16];
+#pragma unroll
+        for (int c = 0; c < 16; ++c) acc[c] = 0.0;
+        for (int l = 0; l < k; ++l) {
+          const double x = P[(int64_t)l * len + i];
+#pragma unroll
+          for (int c = 0; c < 16; ++c) acc[c] += x * T[l * 16 + c];
+        }
+        for (int c = 0; c < nc; ++c) out[(int64_t)(c0 + c) * len + i] = (ST)acc[c];
+      }
+    }
+  }
+}
+
+void recompress_blocks(std::vector<RcDev>& blocks, const double* scratch, void* stage, bool stage_f64,
+                       int* d_newrank, hipStream_t s) {
+  if (blocks.empty()) return;
+  // chunks bounded by a workspace budget (a block needs 8 k^2 doubles)
+  const int64_t budget = (int64_t)256 << 20;
+  std::vector<size_t> starts;
+  int64_t used = budget;
+  for (size_t q = 0; q < blocks.size(); ++q) {
+    const int64_t need = recompress_work_doubles(blocks[q].k) * 8;
+    if (used + need > budget) {
+      starts.push_back(q);
+      used = 0;
+    }
+    blocks[q].w_off = used / 8;
+    used += need;
+  }
+  starts.push_back(blocks.size());
+  DevBuf d_blocks, work;
+  upload(d_blocks, blocks, s);
+  work.alloc((size_t)budget);
+  for (size_t c = 0; c + 1 < starts.size(); ++c) {
+    const unsigned cnt = (unsigned)(starts[c + 1] - starts[c]);
+    const RcDev* bp = d_blocks.get<RcDev>() + starts[c];
+    hipLaunchKernelGGL(k_recompress, dim3(cnt), dim3(RC_T), 0, s, bp, scratch, work.get<double>(), d_newrank);
+    if (stage_f64)
+      hipLaunchKernelGGL(k_recompress_apply<double>, dim3(cnt), dim3(RC_T), 0, s, bp, scratch, work.get<double>(),
+                         (const int*)d_newrank, (double*)stage);
+    else
+      hipLaunchKernelGGL(k_recompress_apply<float>, dim3(cnt), dim3(RC_T), 0, s, bp, scratch, work.get<double>(),
+                         (const int*)d_newrank, (float*)stage);
+    HM_HIP(hipGetLastError());
+  }
+  // the workspace and the descriptors are released when the work is done
+  HM_HIP(hipStreamSynchronize(s));
+}
+
+}  // namespace hm
