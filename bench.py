@@ -16,7 +16,12 @@ Workload ``c2``: the 20,176-facet jittered cylinder, plain FP32 H-solve.
 
 Prints ONE JSON line on stdout (progress goes to stderr).
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c3|c2|c4|c5]
+Default (``--workload all``): the ``c3`` record is the headline; the ``c4``
+transient and ``c5`` serving records ride along on the same JSON line
+(keys ``c4_transient`` and ``c5_serving``), each with its own value,
+roofline or latency figures and oracle baseline.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload all|c3|c2|c4|c5]
 """
 import argparse
 import json
@@ -46,28 +51,46 @@ def _blas_threads():
         return os.cpu_count()
 
 
-def cpu_baseline_dense(sample, sizes):
-    """The oracle (numpy/scipy FP64: dense centroid-rule F, LU of the
-    radiosity system, g = F C^-1 eps) timed on one sample cavity, then scaled
-    to each cavity of the workload: assembly by (n/n_s)^2, factorisation by
-    (n/n_s)^3.  Returns solves per second for one right-hand side per cavity."""
+def _best_of(fn, reps=3):
+    """Runs fn once as a warm-up, then `reps` times; the shortest time and the
+    last result."""
+    fn()
+    best, out = 1e30, None
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        out = fn()
+        best = min(best, time.perf_counter() - t0)
+    return best, out
+
+
+def cpu_baseline_dense(samples, sizes):
+    """The oracle (numpy/scipy FP64) timed on sample cavities of the workload,
+    each component after a warm-up as the best of three: dense centroid-rule
+    F (eq. (10)), LU of the reflection system with g = F C^-1 eps, and J and
+    q of eq. (12) for one right-hand side.  Each component of the largest
+    sample is scaled to every cavity by its order (assembly and the
+    triangular solves by n^2, the factorisation by n^3).  Returns solves per
+    second for one right-hand side per cavity of the whole workload."""
     from oracle import geometry, radiosity, viewfactor
-    c, nrm, area = geometry.facets_from_triangles(sample.v, sample.tri)
-    ns = area.size
-    t0 = time.perf_counter()
-    F = viewfactor.view_factor_matrix(c, nrm, area)
-    t_asm = time.perf_counter() - t0
-    t0 = time.perf_counter()
-    rad = radiosity.DenseRadiosity(F, sample.eps)
-    rad.radiosity(sample.T[:, 0])
-    rad.flux(sample.T[:, 0])
-    t_lu = time.perf_counter() - t0
-    total = sum(t_asm * (n / ns) ** 2 + t_lu * (n / ns) ** 3 for n in sizes)
-    return {"value": len(sizes) / total, "unit": "solves/s", "cores": _blas_threads(), "kind": "oracle",
-            "sample": "dense FP64 oracle on %s (%d facets): assembly %.2f s, LU + g + J + q %.2f s; scaled to "
-                      "the %d cavities (assembly x(n/%d)^2, LU x(n/%d)^3)"
-                      % (sample.name, ns, t_asm, t_lu, len(sizes), ns, ns),
-            "seconds_per_step": total}
+    parts = []
+    for cav in samples:
+        c, nrm, area = geometry.facets_from_triangles(cav.v, cav.tri)
+        t_asm, F = _best_of(lambda: viewfactor.view_factor_matrix(c, nrm, area))
+        t_lu, rad = _best_of(lambda: radiosity.DenseRadiosity(F, cav.eps))
+        t_sol, _ = _best_of(lambda: rad.flux(cav.T[:, 0], rad.radiosity(cav.T[:, 0])))
+        parts.append({"cavity": cav.name, "n": int(area.size), "assembly_s": t_asm, "lu_and_g_s": t_lu,
+                      "solve_and_flux_s": t_sol, "solves_per_s": 1.0 / (t_asm + t_lu + t_sol)})
+        del F, rad
+    ref = max(parts, key=lambda p: p["n"])
+    ns = ref["n"]
+    total = sum(ref["assembly_s"] * (n / ns) ** 2 + ref["lu_and_g_s"] * (n / ns) ** 3
+                + ref["solve_and_flux_s"] * (n / ns) ** 2 for n in sizes)
+    return {"value": len(sizes) / total if total > 0 else None, "unit": "solves/s", "cores": _blas_threads(),
+            "kind": "oracle",
+            "sample": "dense FP64 oracle on %s (warm-up, then best of 3 per component: assembly, LU + g, J + q); "
+                      "the %d-facet cavity's components scaled to the %d cavities (assembly and solves "
+                      "x(n/%d)^2, LU x(n/%d)^3)" % (", ".join(p["cavity"] for p in parts), ns, len(sizes), ns, ns),
+            "components": parts, "seconds_per_step": total}
 
 
 def roofline(prof, bytes_total_lim=1 << 30):
@@ -150,13 +173,15 @@ def run_c3(args):
     t0 = time.perf_counter()
     # the batched configuration: all cavities in one assembly call (shared ACA
     # launches, one product split tuned on the batch)
+    rc = args.recompress
     Mx = hm.hm_assemble_hmatrix_batched(ctx, trees, [cav.aca_tol for cav in cavs], 256, hm.HM_BF16, hm.HM_F32,
-                                        keep_f32_copy=1, autotune=1)
+                                        keep_f32_copy=1, autotune=1, recompress=rc)
     torch.cuda.synchronize()
     t_asm = time.perf_counter() - t0
-    # the plain configuration: one cavity per call, each tuned alone
+    # the plain configuration: one cavity per call, each tuned alone (the
+    # same H-matrix approximation: recompressed as well)
     t0 = time.perf_counter()
-    M32 = [hm.hm_assemble_hmatrix(ctx, t, cav.aca_tol, 256, hm.HM_F32, hm.HM_F32, autotune=1)
+    M32 = [hm.hm_assemble_hmatrix(ctx, t, cav.aca_tol, 256, hm.HM_F32, hm.HM_F32, autotune=1, recompress=rc)
            for t, cav in zip(trees, cavs)]
     torch.cuda.synchronize()
     t_asm32 = time.perf_counter() - t0
@@ -178,17 +203,22 @@ def run_c3(args):
     for _ in range(args.warmup):
         hm.hm_solve_radiosity_batched(ctx, Mx, eps, T, hm.SIGMA, pmx, J, q)
     torch.cuda.synchronize()
+    step_s = []
     t0 = time.perf_counter()
     for _ in range(args.steps):
+        ts = time.perf_counter()
         _, _, infos = hm.hm_solve_radiosity_batched(ctx, Mx, eps, T, hm.SIGMA, pmx, J, q)
+        torch.cuda.synchronize()
+        step_s.append(time.perf_counter() - ts)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     ms = 1e3 * dt / args.steps
     value = len(cavs) * args.steps / dt
     i0 = infos[0]
     worst = max(i["rel_residual"] for i in infos)
-    log("batched mixed: %.2f ms/step = %.1f solves/s; outer %d inner %d matvecs %d worst residual %.2e"
-        % (ms, value, i0["outer_iters"], i0["iters"], i0["matvecs"], worst))
+    log("batched mixed: %.2f ms/step = %.1f solves/s (median %.2f ms, p90 %.2f ms over %d); outer %d inner %d "
+        "matvecs %d worst residual %.2e" % (ms, value, 1e3 * np.median(step_s), 1e3 * np.percentile(step_s, 90),
+                                            len(step_s), i0["outer_iters"], i0["iters"], i0["matvecs"], worst))
 
     # --- batched FP32 (batching gain without the precision gain)
     p32 = hm.solve_params(rtol=RTOL, restart=30, max_iter=400, want_q=1, vec_dtype=hm.HM_F32)
@@ -229,8 +259,12 @@ def run_c3(args):
     out = base_record(args, value, ms, "f32+f64", {
         "workload": "c3_64_cavities_%d_facets" % sum(sizes), "cavities": len(cavs), "facets": sum(sizes),
         "facets_min": min(sizes), "facets_max": max(sizes), "leaf": 64, "eta": 1.5, "aca_tol": 1e-6,
+        "recompression": "truncated svd at aca_tol" if rc else "none",
         "storage": "bf16 low-rank factors, fp32 near field, fp32 factor copy for the residual",
         "solver": "batched gmres(30) fp32 inside fp64 iterative refinement", "rtol": RTOL, "nrhs": 1})
+    out["timing"] = {"reps": len(step_s), "median_ms": 1e3 * float(np.median(step_s)),
+                     "p90_ms": 1e3 * float(np.percentile(step_s, 90)), "min_ms": 1e3 * float(np.min(step_s)),
+                     "median_solves_per_s": len(cavs) / float(np.median(step_s))}
     out["roofline"] = rf
     out["roofline_fp64_residual_product"] = roofline(prof_hi)
     out["roofline_fp32_product"] = roofline(prof32)
@@ -249,7 +283,7 @@ def run_c3(args):
     # residual): fewer bytes per inner product, at a lower share of HBM peak
     del M32
     Mb = hm.hm_assemble_hmatrix_batched(ctx, trees, [cav.aca_tol for cav in cavs], 256, hm.HM_BF16, hm.HM_BF16,
-                                        keep_f32_copy=1, autotune=1)
+                                        keep_f32_copy=1, autotune=1, recompress=rc)
     for _ in range(args.warmup):
         hm.hm_solve_radiosity_batched(ctx, Mb, eps, T, hm.SIGMA, pmx, J, q)
     torch.cuda.synchronize()
@@ -268,9 +302,31 @@ def run_c3(args):
                               "matvec_ms": rb["matvec_ms"], "matvec_GBps": rb["matvec_GBps"],
                               "matvec_frac": rb["matvec_frac"]}
     del Mb
+    if rc:
+        # context: the same batch with the ACA crosses as they are
+        del Mx
+        Mn = hm.hm_assemble_hmatrix_batched(ctx, trees, [cav.aca_tol for cav in cavs], 256, hm.HM_BF16,
+                                            hm.HM_F32, keep_f32_copy=1, autotune=1, recompress=0)
+        for _ in range(args.warmup):
+            hm.hm_solve_radiosity_batched(ctx, Mn, eps, T, hm.SIGMA, pmx, J, q)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        nn = max(1, args.steps // 2)
+        for _ in range(nn):
+            hm.hm_solve_radiosity_batched(ctx, Mn, eps, T, hm.SIGMA, pmx, J, q)
+        torch.cuda.synchronize()
+        rate_n = len(cavs) * nn / (time.perf_counter() - t0)
+        profn = roofline(hm.hm_hmatvec_profile(ctx, Mn, 1, hm.HM_F32, reps=10, flush_bytes=0))
+        stn = [m.stats() for m in Mn]
+        out["without_recompression"] = {"value": rate_n, "unit": "solves/s",
+                                        "entries_lowrank": sum(x["entries_lowrank"] for x in stn),
+                                        "bytes_device_mixed": sum(x["bytes_device"] for x in stn),
+                                        "matvec_ms": profn["matvec_ms"], "matvec_frac": profn["matvec_frac"]}
+        log("batched mixed without recompression: %.1f solves/s, product %.3f ms" % (rate_n, profn["matvec_ms"]))
+        del Mn
     if not args.no_cpu_baseline:
-        sample = min(cavs, key=lambda c: abs(c.n - 5000))
-        out["cpu_baseline"] = cpu_baseline_dense(sample, sizes)
+        samples = [min(cavs, key=lambda c: abs(c.n - t)) for t in (2000, 5000)]
+        out["cpu_baseline"] = cpu_baseline_dense(samples, sizes)
     return out
 
 
@@ -354,11 +410,13 @@ def run_c4(args):
     t_tree = time.perf_counter() - t0
     t0 = time.perf_counter()
     # the product's work split tuned on 16-column products (the transient's width)
-    M = hm.hm_assemble_hmatrix(ctx, tree, cav.aca_tol, 256, hm.HM_F32, hm.HM_F32, autotune=16)
+    M = hm.hm_assemble_hmatrix(ctx, tree, cav.aca_tol, 256, hm.HM_F32, hm.HM_F32, autotune=16,
+                               recompress=args.recompress)
     torch.cuda.synchronize()
     t_asm = time.perf_counter() - t0
     st = M.stats()
     log("c4: matrix", st, "tree %.2fs assembly %.2fs" % (t_tree, t_asm))
+    steps = args.c4_steps
     eps = torch.as_tensor(cav.eps, device="cuda")
     T = torch.as_tensor(np.asfortranarray(cav.T), device="cuda")
     src = torch.as_tensor(np.asfortranarray(cav.extra["source"]), device="cuda")
@@ -367,33 +425,56 @@ def run_c4(args):
     hm.hm_transient_run(ctx, M, eps, T, src, steps=max(1, args.warmup), **kw)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    _, info = hm.hm_transient_run(ctx, M, eps, T, src, steps=args.steps, **kw)
+    _, info = hm.hm_transient_run(ctx, M, eps, T, src, steps=steps, **kw)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     solves = info["newton_total"] * T.shape[1]
     log("c4: %d steps in %.3f s: newton %d (max %d), matvecs %d, residual %.1e"
-        % (args.steps, dt, info["newton_total"], info["newton_max"], info["matvecs"], info["max_rel_residual"]))
+        % (steps, dt, info["newton_total"], info["newton_max"], info["matvecs"], info["max_rel_residual"]))
     prof = hm.hm_hmatvec_profile(ctx, M, 16, hm.HM_F32, reps=10, flush_bytes=0)
     prof1 = hm.hm_hmatvec_profile(ctx, M, 1, hm.HM_F32, reps=10, flush_bytes=0)
     profd = hm.hm_hmatvec_profile(ctx, M, 16, hm.HM_F64, reps=10, flush_bytes=0)
     log("profile 16 rhs", prof, "\nprofile 16 rhs fp64", profd, "\nprofile 1 rhs", prof1)
-    out = base_record(args, solves / dt, 1e3 * dt / args.steps, "f32+f64", {
+    out = base_record(args, solves / dt, 1e3 * dt / steps, "f32+f64", {
         "workload": "c4_ellipsoid_200000_16_scenarios", "facets": cav.n, "scenarios": int(T.shape[1]),
         "leaf": cav.leaf, "eta": cav.eta, "aca_tol": cav.aca_tol, "storage": "fp32",
+        "recompression": "truncated svd at aca_tol" if args.recompress else "none",
         "solver": "backward Euler, diagonal Newton; 16-rhs products on the matrix cores: gmres(30) fp32, flux fp64",
         "rtol": RTOL, "newton_rtol": 1e-9, "mc": cav.extra["mc"], "dt": cav.extra["dt"]})
     out["roofline"] = roofline(prof)
     out["roofline_fp64_16rhs"] = roofline(profd)
     out["roofline_1rhs"] = roofline(prof1)
-    out["steps_per_s"] = args.steps / dt
+    out["steps"] = steps
+    out["steps_per_s"] = steps / dt
     out["transient"] = {k: info[k] for k in ("steps_done", "newton_total", "newton_max", "matvecs",
                                              "max_rel_residual")}
     out["matrix"] = {k: st[k] for k in ("bytes_device", "entries_dense", "entries_lowrank", "max_rank",
                                         "n_dense_blocks", "n_lowrank_blocks", "n_fallback")}
     out["assembly_s"] = t_asm
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline_transient(cav.n, info["newton_total"] / max(1, args.steps))
+        out["cpu_baseline"] = cpu_baseline_transient(cav.n, info["newton_total"] / max(1, steps))
     return out
+
+
+def cpu_baseline_serving(samples, cavity_sizes, request_sizes):
+    """The oracle serving the same request stream: per cavity id, dense F and
+    LU once (then kept, as the server keeps its H-matrices); per right-hand
+    side, J and q.  Components timed as in cpu_baseline_dense on sample
+    cavities and scaled from the largest by n^2 / n^3.  cavity_sizes: facets
+    of every id the stream uses; request_sizes: (facets, right-hand sides) of
+    every request.  Returns right-hand sides solved per second."""
+    base = cpu_baseline_dense(samples, [])
+    ref = max(base["components"], key=lambda p: p["n"])
+    ns = ref["n"]
+    t_setup = sum(ref["assembly_s"] * (n / ns) ** 2 + ref["lu_and_g_s"] * (n / ns) ** 3 for n in cavity_sizes)
+    t_solve = sum(r * ref["solve_and_flux_s"] * (n / ns) ** 2 for n, r in request_sizes)
+    rhs = sum(r for _, r in request_sizes)
+    return {"value": rhs / (t_setup + t_solve), "unit": "solves/s", "cores": base["cores"], "kind": "oracle",
+            "sample": "dense FP64 oracle on %s (warm-up, then best of 3 per component); the %d-facet cavity's "
+                      "assembly + LU scaled to each of the %d cavity ids the stream uses (x(n/%d)^2, x(n/%d)^3) "
+                      "and its J + q to each of the %d right-hand sides (x(n/%d)^2)"
+                      % (", ".join(p["cavity"] for p in base["components"]), ns, len(cavity_sizes), ns, ns, rhs, ns),
+            "components": base["components"], "seconds": t_setup + t_solve}
 
 
 def cpu_baseline_transient(n, newton_per_step):
@@ -443,14 +524,15 @@ def run_c5(args):
 
     nreq = args.c5_requests
     seed = 5999
+    budget_gb = args.c5_budget_gb
     ctx = hm.Context(0)
     p = hm.solve_params(rtol=RTOL, restart=30, max_iter=400, mixed_precision=1, ir_inner_rtol=3e-3, want_q=1)
-    srv = hm.Server(ctx, hbm_budget_bytes=64 << 30, max_active=64, max_rhs_per_slot=8, params=p)
+    srv = hm.Server(ctx, hbm_budget_bytes=int(budget_gb * (1 << 30)), max_active=64, max_rhs_per_slot=8, params=p)
     # the request streams (arrival order, ids, nrhs) of every phase
     _, ids_all, nrhs_all = configs.c5_requests(nreq * 5, 1.0, seed=seed)
     t0 = time.perf_counter()
     sizes = {}
-    for cid in sorted(set(int(i) for i in ids_all)):
+    for cid in range(256):
         cav = configs.c5_cavity(cid)
         c, nrm, area = hm.hm_facets_from_triangles(cav.v, cav.tri, orient=1)
         tree = hm.hm_build_cluster_tree(ctx, c, nrm, area, cav.leaf, cav.eta)
@@ -464,7 +546,7 @@ def run_c5(args):
         cid, nr = int(ids_all[k]), int(nrhs_all[k])
         return cid, configs.request_temperatures(sizes[cid], nr, seed, k)
 
-    seen = set()  # cavity ids requested so far (the budget holds them all: no evictions)
+    seen = set()  # cavity ids requested so far (first requests on an id find it cold)
 
     def run_phase(first, count, arrivals):
         """Submit requests first..first+count-1 at the given arrival offsets
@@ -524,16 +606,24 @@ def run_c5(args):
         log("c5: load %.2f: %s" % (frac, loads[-1]))
     st = srv.stats()
     srv.close()
+    log("c5: server stats %s" % st)
     out = base_record(args, sat_rhs, 1e3 / sat_req, "f32+f64", {
         "workload": "c5_serving_256_ids", "cavity_ids": 256, "ids_used": len(sizes), "zipf_s": 1.1,
         "facets_range": [min(sizes.values()), max(sizes.values())], "rhs_per_request": "1-8",
-        "hbm_budget_gb": 64, "storage": "bf16 low-rank factors, fp32 near field, fp32 factor copy",
+        "hbm_budget_gb": budget_gb, "storage": "bf16 low-rank factors, fp32 near field, fp32 factor copy",
         "solver": "continuous batching, fp64 refinement rounds with batched fp32 gmres", "rtol": RTOL,
         "requests_per_phase": nreq})
     out["unit"] = "solves/s"
     out["saturation"] = {"req_per_s": sat_req, "solves_per_s": sat_rhs}
     out["latency"] = loads
     out["server"] = st
+    if not args.no_cpu_baseline:
+        reqs = [(sizes[int(ids_all[k])], int(nrhs_all[k])) for k in range(len(ids_all))]
+        used = sorted(set(int(i) for i in ids_all))
+        samples = [configs.c5_cavity(c) for c in (3, 0)]  # 2,000 and 5,120 facets
+        for cav in samples:
+            cav.T = configs.request_temperatures(cav.n, 1, seed, 0)
+        out["cpu_baseline"] = cpu_baseline_serving(samples, [sizes[c] for c in used], reqs)
     return out
 
 
@@ -600,10 +690,17 @@ def run_c2(args):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="c3", choices=["c3", "c2", "c4", "c5"])
-    ap.add_argument("--c5-requests", type=int, default=600, help="requests per serving phase")
+    ap.add_argument("--steps", type=int, default=50, help="timed batched solves of the 64-cavity workload")
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="all", choices=["all", "c3", "c2", "c4", "c5"],
+                    help="all: the 64-cavity batch (the headline record) with the transient and serving "
+                         "records attached to the same line")
+    ap.add_argument("--recompress", type=int, default=1, choices=[0, 1],
+                    help="truncated-SVD recompression of the ACA crosses (c3, c4)")
+    ap.add_argument("--c4-steps", type=int, default=20, help="timed backward-Euler steps of the transient")
+    ap.add_argument("--c5-requests", type=int, default=1500, help="requests per serving phase")
+    ap.add_argument("--c5-budget-gb", type=float, default=48.0,
+                    help="device budget of the server (resident H-matrices + solve buffers)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--kernels-only", action="store_true",
                     help="profiling aid: only the batched product kernels and a calibration copy, no solves")
@@ -615,6 +712,13 @@ def main():
         sys.exit(2)
     if args.kernels_only:
         out = run_kernels_only(args)
+    elif args.workload == "all":
+        out = run_c3(args)
+        import gc
+        gc.collect()
+        out["c4_transient"] = run_c4(args)
+        gc.collect()
+        out["c5_serving"] = run_c5(args)
     else:
         out = {"c3": run_c3, "c2": run_c2, "c4": run_c4, "c5": run_c5}[args.workload](args)
     print(json.dumps(out), flush=True)
