@@ -6,7 +6,8 @@ times (autotuned matrices, the same solve parameters).
   ``tests/golden/c2_reference.npz`` (written by
   ``tests/golden/make_c2_reference.py`` from ``oracle/`` only): relative L2
   <= 1e-6 (FP32 Krylov floor ~ cond * 1e-7 plus the ACA error ~3e-7).
-* 64-cavity batch (696,072 facets) assembled in one batched call, BF16
+* 64-cavity batch (696,072 facets) assembled in one batched call (ACA
+  crosses recompressed by truncated SVD at the ACA tolerance), BF16
   factors + FP64 refinement to a residual of 1e-7, all cavities in one
   batched solve: the smallest cavity of
   each type against the dense oracle computed here, and the largest
@@ -81,8 +82,8 @@ def c3(hm, ctx):
     log("case: c3 batch of %d cavities, %d facets" % (len(cavs), sum(c.n for c in cavs)))
     trees = [_tree(hm, ctx, c) for c in cavs]
     Mx = hm.hm_assemble_hmatrix_batched(ctx, trees, [c.aca_tol for c in cavs], 256, hm.HM_BF16, hm.HM_F32,
-                                        keep_f32_copy=1, autotune=1)
-    M32 = [hm.hm_assemble_hmatrix(ctx, t, c.aca_tol, 256, hm.HM_F32, hm.HM_F32, autotune=1)
+                                        keep_f32_copy=1, autotune=1, recompress=1)
+    M32 = [hm.hm_assemble_hmatrix(ctx, t, c.aca_tol, 256, hm.HM_F32, hm.HM_F32, autotune=1, recompress=1)
            for t, c in zip(trees, cavs)]
     eps = [dt(c.eps) for c in cavs]
     T = [dt(c.T[:, 0]) for c in cavs]

@@ -1,6 +1,7 @@
 """GPU tests of the lumped transient (analogue of Sec. 3.3) with 16
 scenarios per product (the matrix-core path), in the configuration the
-bench times: FP32 factors and FP32 Krylov vectors (rtol 1e-7), FP64 flux and
+bench times: FP32 factors (recompressed ACA crosses, product split tuned on
+16-column products) and FP32 Krylov vectors (rtol 1e-7), FP64 flux and
 Newton update, Newton tolerance 1e-9.
 
 * 18,000-facet member (geodesic frequency 30) of the (4, 2, 1) ellipsoid
@@ -14,7 +15,11 @@ Newton update, Newton tolerance 1e-9.
   scenario, sum_i A_i (m_c (T_i^{n+1} - T_i^n) / dt - s_i) = sum_i A_i q_i,
   vanishes for the dense operator (reciprocity) and up to the ACA error
   (1e-6) and the Newton tolerance here: relative to sum_i A_i |m_c dT_i/dt|
-  it stays <= 1e-5.
+  it stays <= 1e-5.  Step 1 of scenarios 0-1 against the oracle's large-n
+  mode (matrix-free FP64 products, GMRES to 1e-12; stored as the FP32
+  increments T^1 - T^0 in ``tests/golden/c4_fullsize_reference.npz``,
+  written by ``tests/golden/make_c4_fullsize_reference.py`` from
+  ``oracle/`` only): e(T) <= 1e-6.
 """
 import os
 
@@ -46,7 +51,7 @@ def _setup(hm, ctx, cav):
     import torch
     c, n, a = hm.hm_facets_from_triangles(cav.v, cav.tri, orient=1)
     tree = hm.hm_build_cluster_tree(ctx, c, n, a, cav.leaf, cav.eta)
-    M = hm.hm_assemble_hmatrix(ctx, tree, cav.aca_tol, 256, hm.HM_F32, hm.HM_F32, autotune=1)
+    M = hm.hm_assemble_hmatrix(ctx, tree, cav.aca_tol, 256, hm.HM_F32, hm.HM_F32, autotune=16, recompress=1)
     eps = torch.as_tensor(cav.eps, device="cuda")
     T = torch.as_tensor(np.asfortranarray(cav.T), device="cuda")
     src = torch.as_tensor(np.asfortranarray(cav.extra["source"]), device="cuda")
@@ -101,3 +106,12 @@ def test_transient_full_size_energy_balance(hm, ctx):
                                                                       max(i1["max_rel_residual"],
                                                                           i2["max_rel_residual"]), worst))
     assert worst <= 1e-5
+    ref_path = os.path.join(HERE, "golden", "c4_fullsize_reference.npz")
+    ref = np.load(ref_path)
+    assert int(ref["n"]) == cav.n
+    for sc in range(int(ref["scenarios"])):
+        T1o = T0[:, sc] + ref["dT1"][:, sc].astype(np.float64)
+        e = np.linalg.norm(T1[:, sc] - T1o) / np.linalg.norm(T1o)
+        ed = np.linalg.norm((T1[:, sc] - T0[:, sc]) - ref["dT1"][:, sc]) / np.linalg.norm(ref["dT1"][:, sc])
+        log("scenario %d: e(T) step 1 %.2e (increment %.2e)" % (sc, e, ed))
+        assert e <= 1e-6
