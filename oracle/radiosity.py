@@ -8,7 +8,9 @@
 * radiosity: ``J = C^-1 (sigma eps eta)``, the balance
   ``J_i = eps_i sigma eta_i + (1 - eps_i) sum_j F_ij J_j``;
 * facet flux, eq. (12):
-  ``q_i = (sigma eps_i / A_i) sum_j eps_j sum_k F_paper_ik C^-1_kj (eta_j - eta_i)``.
+  ``q_i = (sigma eps_i / A_i) sum_j eps_j sum_k F_paper_ik C^-1_kj (eta_j - eta_i)``;
+* open cavities, eq. (35): the view fraction ``1 - c_i`` (clamped row sum
+  c_i, eqs. (32)-(33)) exchanges with an ambient at ``T_amb``.
 
 The dense system is solved by LU with partial pivoting (LAPACK getrf/getrs
 through scipy), in FP64.
@@ -38,6 +40,24 @@ def emission(eps, T, sigma=SIGMA):
     return sigma * e * T**4
 
 
+def clamped_row_sums(F):
+    """``c_i = clamp(s_i, 0, 1)`` with the row sum ``s_i = sum_j F_ij``
+    (eqs. (32)-(33); the ``1/A_i`` of eq. (32) is inside the per-area F)."""
+    return np.clip(F.sum(axis=1), 0.0, 1.0)
+
+
+def ambient_flux(c, T, T_amb, sigma=SIGMA):
+    """Open-cavity exchange with the ambient, eq. (35): the fraction
+    ``1 - c_i`` of facet i's view that leaves the cavity carries
+    ``sigma (1 - c_i) (T_i^4 - T_amb^4)`` away from the facet (the printed
+    term omits sigma; it is restored for units).  Returned as the flux INTO
+    the facet (the sign convention of eq. (12)): ``-sigma (1 - c)(T^4 - T_amb^4)``.
+    ``c`` are the clamped row sums; T may be n or n x r."""
+    T = np.asarray(T, dtype=np.float64)
+    w = (1.0 - c) if T.ndim == 1 else (1.0 - c)[:, None]
+    return -sigma * w * (T**4 - T_amb**4)
+
+
 class DenseRadiosity:
     """Dense LU of the reflection matrix of one cavity, reused for every
     right-hand side (as the paper reuses its factorisation)."""
@@ -61,17 +81,22 @@ class DenseRadiosity:
     def radiosity(self, T):
         return self.solve(emission(self.eps, T, self.sigma))
 
-    def flux(self, T, J=None):
+    def flux(self, T, J=None, T_amb=None):
         """Eq. (12) rewritten with the radiosity J:
         ``q_i = sigma eps_i [ (F C^-1 (eps eta))_i - eta_i (F C^-1 eps)_i ]``
-        ``    = eps_i [ (F J)_i - sigma eta_i g_i ]``,  ``g = F C^-1 eps``."""
+        ``    = eps_i [ (F J)_i - sigma eta_i g_i ]``,  ``g = F C^-1 eps``;
+        with ``T_amb`` (open cavity) plus the ambient exchange of eq. (35)."""
         T = np.asarray(T, dtype=np.float64)
         if J is None:
             J = self.radiosity(T)
         eta = T**4
         if T.ndim == 1:
-            return self.eps * (self.F @ J - self.sigma * eta * self.g)
-        return self.eps[:, None] * (self.F @ J - self.sigma * eta * self.g[:, None])
+            q = self.eps * (self.F @ J - self.sigma * eta * self.g)
+        else:
+            q = self.eps[:, None] * (self.F @ J - self.sigma * eta * self.g[:, None])
+        if T_amb is not None:
+            q = q + ambient_flux(clamped_row_sums(self.F), T, T_amb, self.sigma)
+        return q
 
 
 def flux_eq12_literal(F, eps, area, T, sigma=SIGMA):

@@ -22,21 +22,26 @@ import numpy as np
 from .radiosity import SIGMA, DenseRadiosity
 
 
-def newton_step(rad: DenseRadiosity, Tn, src, mc, dt, tol=1e-12, max_newton=60):
+def newton_step(rad: DenseRadiosity, Tn, src, mc, dt, tol=1e-12, max_newton=60, T_amb=None):
     """One implicit Euler step from ``Tn`` (n x r).  Returns (T, iterations,
-    final residual norms)."""
+    final residual norms).  With ``T_amb`` the cavity is open: the flux gains
+    the ambient exchange of eq. (35), and the local Jacobian its derivative
+    ``4 sigma (1 - c_i) T_i^3``."""
     T = np.array(Tn, dtype=np.float64, copy=True)
     scale = np.linalg.norm(mc * Tn / dt, axis=0)
     eps = rad.eps[:, None]
     g = rad.g[:, None]
+    amb = 0.0
+    if T_amb is not None:
+        amb = (1.0 - np.clip(rad.F.sum(axis=1), 0.0, 1.0))[:, None]
     it = 0
     while True:
-        q = rad.flux(T)
+        q = rad.flux(T) if T_amb is None else rad.flux(T, T_amb=T_amb)
         R = mc * (T - Tn) / dt - q - src
         rn = np.linalg.norm(R, axis=0)
         if np.all(rn <= tol * scale) or it >= max_newton:
             return T, it, rn
-        D = mc / dt + 4.0 * rad.sigma * eps * g * T**3
+        D = mc / dt + 4.0 * rad.sigma * (eps * g + amb) * T**3
         T = T - R / D
         it += 1
 

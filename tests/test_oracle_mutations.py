@@ -200,3 +200,37 @@ def test_recompression_pins_reject_planted_mistakes():
     assert pin_ok(aca.recompress)
     for fn in (spectral, no_sigma, wrong_side):
         assert not pin_ok(fn), fn.__name__
+
+
+def test_ambient_pins_reject_planted_mistakes():
+    """The spherical-cap closed form rejects a flipped ambient sign and a
+    dropped view fraction (1 - c); the closed icosphere rejects a row sum
+    used without the clamp of eq. (33)."""
+    R = 1.4
+    p, nr, w = meshes.projected_sphere_points(3, radius=R, seed=31)
+    cap = p[:, 2] > 0.25 * R
+    p, nr, w = p[cap], nr[cap], w[cap]
+    rng = np.random.default_rng(32)
+    eps = rng.uniform(0.1, 0.9, w.size)
+    T = rng.uniform(300.0, 1500.0, w.size)
+    T_amb = 350.0
+    F = viewfactor.view_factor_matrix(p, nr, w)
+    rad = radiosity.DenseRadiosity(F, eps)
+    q12 = rad.flux(T)
+    s_exact = (w.sum() - w) / (4.0 * math.pi * R**2)
+    q_exact = closed_forms.sphere_points_flux(w, eps, T, R)[0] - radiosity.SIGMA * (1.0 - s_exact) * (T**4 - T_amb**4)
+
+    def cap_ok(q):
+        return np.linalg.norm(q - q_exact) <= 1e-12 * np.linalg.norm(q_exact)
+
+    c = radiosity.clamped_row_sums(F)
+    assert cap_ok(q12 + radiosity.ambient_flux(c, T, T_amb))
+    assert not cap_ok(q12 - radiosity.ambient_flux(c, T, T_amb))                       # sign
+    assert not cap_ok(q12 - radiosity.SIGMA * (T**4 - T_amb**4))                       # no (1 - c)
+    v, f = meshes.icosphere(2)
+    f = meshes.inward(f)
+    cc, nn, aa = __import__("oracle.geometry", fromlist=["x"]).facets_from_triangles(v, f)
+    Fi = viewfactor.view_factor_matrix(cc, nn, aa)
+    Ti = np.random.default_rng(33).uniform(300.0, 1500.0, aa.size)
+    assert np.all(radiosity.ambient_flux(radiosity.clamped_row_sums(Fi), Ti, 400.0) == 0.0)
+    assert np.any(radiosity.ambient_flux(Fi.sum(axis=1), Ti, 400.0) != 0.0)            # unclamped

@@ -425,3 +425,96 @@ def test_recompressed_hmatrix_meets_tolerance_with_fewer_entries():
     assert er <= 1e-6 and e <= 1e-6
     assert Hr.stored_entries()[1] < 0.9 * H.stored_entries()[1]
     assert all(B[4].shape[1] <= A[4].shape[1] for A, B in zip(H.lowrank, Hr.lowrank))
+
+
+# ---------------------------------------------------------------- open cavities (eqs. (32)-(35))
+def test_open_cavity_flux_on_a_spherical_cap_matches_closed_form():
+    """Sphere points with radial normals restricted to a cap: every entry is
+    still w_j / (4 pi R^2), so the row sums are (W - w_i) / A_s < 1 in closed
+    form, the eq. (12) flux follows the projected-sphere closed form over the
+    cap's weights, and the ambient term of eq. (35) adds
+    -sigma (1 - s_i)(T_i^4 - T_amb^4)."""
+    R = 1.4
+    p, nr, w = meshes.projected_sphere_points(3, radius=R, seed=31)
+    cap = p[:, 2] > 0.25 * R
+    p, nr, w = p[cap], nr[cap], w[cap]
+    rng = np.random.default_rng(32)
+    eps = rng.uniform(0.1, 0.9, w.size)
+    T = rng.uniform(300.0, 1500.0, w.size)
+    T_amb = 350.0
+    F = viewfactor.view_factor_matrix(p, nr, w)
+    As = 4.0 * math.pi * R**2
+    s_exact = (w.sum() - w) / As
+    assert np.max(np.abs(radiosity.clamped_row_sums(F) - s_exact)) <= 1e-13
+    rad = radiosity.DenseRadiosity(F, eps)
+    q = rad.flux(T, T_amb=T_amb)
+    q12, _ = closed_forms.sphere_points_flux(w, eps, T, R)
+    q_exact = q12 - radiosity.SIGMA * (1.0 - s_exact) * (T**4 - T_amb**4)
+    assert np.linalg.norm(q - q_exact) <= 1e-12 * np.linalg.norm(q_exact)
+
+
+def test_isolated_facet_exchanges_only_with_the_ambient():
+    """A facet that sees nothing (its F row is zero, Sec. 6.1's isolated
+    facets) has J = eps sigma T^4 and q = -sigma (T^4 - T_amb^4); one implicit
+    Euler step of it is the scalar equation
+    mc (T' - T)/dt = -sigma (T'^4 - T_amb^4) + s, solved here by bracketing."""
+    from scipy.optimize import brentq
+    # two facing pairs (0-1 and 2-3) and facet 4, which faces away from all
+    c = np.array([[0.0, 0.0, 0.0], [0.0, 0.0, -1.0], [5.0, 0.0, 0.0], [5.0, 0.0, 1.0], [10.0, 0.0, 0.0]])
+    nrm = np.array([[0.0, 0.0, -1.0], [0.0, 0.0, 1.0], [0.0, 0.0, 1.0], [0.0, 0.0, -1.0], [1.0, 0.0, 0.0]])
+    A = np.full(5, 0.1)
+    F = viewfactor.view_factor_matrix(c, nrm, A)
+    iso = np.where(~np.any(F != 0.0, axis=1))[0]
+    assert list(iso) == [4]
+    eps = np.array([0.7, 0.6, 0.5, 0.4, 0.3])
+    T = np.array([900.0, 700.0, 500.0, 800.0, 650.0])
+    T_amb = 300.0
+    rad = radiosity.DenseRadiosity(F, eps)
+    J = rad.radiosity(T)
+    q = rad.flux(T, J, T_amb=T_amb)
+    sig = radiosity.SIGMA
+    assert J[4] == pytest.approx(eps[4] * sig * T[4] ** 4, rel=1e-15)
+    assert q[4] == pytest.approx(-sig * (T[4] ** 4 - T_amb**4), rel=1e-13)
+    mc, dt, s = 1e4, 1.0, 250.0
+    Tn = T[:, None]
+    src = np.full((5, 1), s)
+    T1, _, _ = transient.newton_step(rad, Tn, src, mc, dt, tol=1e-14, T_amb=T_amb)
+    root = brentq(lambda x: mc * (x - T[4]) / dt + sig * (x**4 - T_amb**4) - s, 300.0, 900.0, xtol=1e-13)
+    assert T1[4, 0] == pytest.approx(root, rel=1e-12)
+
+
+def test_ambient_term_vanishes_in_a_closed_convex_cavity():
+    """On a recursive icosphere every centroid-rule row sum exceeds 1, so the
+    clamp of eq. (33) gives c = 1 and the open-cavity flux equals eq. (12)."""
+    v, f = meshes.icosphere(2)
+    f = meshes.inward(f)
+    c, n, a = geometry.facets_from_triangles(v, f)
+    F = viewfactor.view_factor_matrix(c, n, a)
+    assert np.all(F.sum(axis=1) > 1.0)
+    rng = np.random.default_rng(33)
+    eps = rng.uniform(0.1, 0.9, a.size)
+    T = rng.uniform(300.0, 1500.0, a.size)
+    rad = radiosity.DenseRadiosity(F, eps)
+    assert np.array_equal(rad.flux(T, T_amb=400.0), rad.flux(T))
+
+
+def test_fibonacci_spiral_is_an_open_cavity_with_isolated_facets():
+    """The 13-sphere spiral (Sec. 6): centres follow the Fibonacci offsets
+    (spheres 1-2 and 2-3 a diagonal of the unit square apart), every row sum
+    is below 1 (open), facets of one sphere never see each other (convex
+    spheres, back-face rule), and some 7-9% of the facets see no other facet
+    at all (the paper reports about 7%)."""
+    c = meshes.fibonacci_centers()
+    assert np.allclose(c[1, :2], [1.0, 1.0]) and np.allclose(c[2, :2], [0.0, 2.0])
+    assert np.allclose(c[12, :2], [-15.0, -3.0])
+    v, f, sid = meshes.fibonacci_spheres(3)
+    cc, nn, aa = geometry.facets_from_triangles(v, f)
+    F = viewfactor.view_factor_matrix(cc, nn, aa)
+    s = F.sum(axis=1)
+    assert np.all(s < 1.0)
+    same = sid[:, None] == sid[None, :]
+    assert np.all(F[same] == 0.0)
+    iso = ~np.any(F != 0.0, axis=1)
+    assert 0.06 <= iso.mean() <= 0.10
+    G = aa[:, None] * F
+    assert np.max(np.abs(G - G.T)) <= 1e-15 * np.max(G)

@@ -146,3 +146,18 @@ def c5_requests(count: int, rate_hz: float, n_ids: int = 256, zipf_s: float = 1.
 
 def request_temperatures(n: int, nrhs: int, seed: int, index: int) -> np.ndarray:
     return np.random.default_rng([seed, index]).uniform(300.0, 1500.0, (n, nrhs))
+
+
+def fibonacci_spiral(nu: int = 5, radius: float = 0.5, eps: float = 0.8, T_amb: float = 300.0) -> Cavity:
+    """The 13-sphere spiral of the paper's experiments (Sec. 6) as a
+    non-convex, open radiation surface: geodesic spheres of frequency ``nu``
+    (20 nu^2 facets each; nu = 2, 3, 5, 6, 8, 10, 12 give 1,040-37,440 facets
+    in all, spanning the paper's mesh levels) with outward normals;
+    emissivity ``eps`` uniform; the central sphere at 1000 K and the others at
+    300 K (the paper's initial state); ambient at ``T_amb``.  About 8% of the
+    facets see no other facet (zero rows of F)."""
+    v, tri, sid = meshes.fibonacci_spheres(nu, radius)
+    n = tri.shape[0]
+    T = np.where(sid == 0, 1000.0, 300.0)
+    return Cavity(f"fibonacci_spiral_{n}", v, tri, np.full(n, eps), T[:, None],
+                  extra={"sphere": sid, "T_amb": T_amb})

@@ -284,3 +284,51 @@ def projected_sphere_points(n_level: int = 3, radius: float = 1.0, seed: int = 7
     n = d.shape[0]
     w = np.random.default_rng(seed).uniform(0.5, 1.5, n) * (4.0 * math.pi * radius**2 / n)
     return radius * d, -d, w
+
+
+def fibonacci_centers():
+    """Centres (x, y, 0) of the 13 spheres of the spiral arrangement described
+    in Sec. 6 (unit = the first Fibonacci offset), in sphere order 1..13.
+
+    Sphere 1 sits at the origin; spheres 2, 3, 5, 7, 9, 11, 13 follow, each
+    offset from the previous one of them by (+-a_n, +-a_n) with a_n the n-th
+    Fibonacci number (1, 1, 2, 3, 5, 8, 13), the sign pairs turning by a
+    quarter turn each time, (+,+), (-,+), (-,-), (+,-), ..., which winds the
+    spiral counter-clockwise.  Consecutive ones of these are joined by
+    quarter circles of radius a_n (the centre on the side that turns the arc
+    counter-clockwise); spheres 4, 6, 8, 10, 12 sit at the midpoints of the
+    arcs 3-5, 5-7, 7-9, 9-11, 11-13."""
+    fib = [1, 1, 2, 3, 5, 8, 13]
+    signs = [(1, 1), (-1, 1), (-1, -1), (1, -1)]
+    main = [np.zeros(2)]
+    arcs = []
+    for k, a in enumerate(fib):
+        sx, sy = signs[k % 4]
+        prev = main[-1]
+        nxt = prev + np.array([sx * a, sy * a], dtype=np.float64)
+        for cen in (prev + np.array([sx * a, 0.0]), prev + np.array([0.0, sy * a])):
+            u, w = prev - cen, nxt - cen
+            if u[0] * w[1] - u[1] * w[0] > 0.0:  # counter-clockwise quarter turn
+                mid = u + w
+                arcs.append(cen + a * mid / np.linalg.norm(mid))
+                break
+        main.append(nxt)
+    # main[0..7] are spheres 1, 2, 3, 5, 7, 9, 11, 13; arcs[k] joins main[k] and main[k+1]
+    order = [main[0], main[1], main[2], arcs[2], main[3], arcs[3], main[4], arcs[4], main[5], arcs[5],
+             main[6], arcs[6], main[7]]
+    return np.array([[p[0], p[1], 0.0] for p in order])
+
+
+def fibonacci_spheres(nu: int, radius: float = 0.5):
+    """The 13-sphere spiral of Sec. 6 as one radiation surface: a geodesic
+    sphere of frequency ``nu`` (20 nu^2 facets) at every centre of
+    ``fibonacci_centers``, triangles wound outward (the cavity is the space
+    between the spheres, so these normals already point into it).  Returns
+    (vertices, triangles, sphere index of every triangle)."""
+    vs, fs, ids = [], [], []
+    sv, sf = geodesic(nu, radius)
+    for k, cen in enumerate(fibonacci_centers()):
+        fs.append(sf + sum(x.shape[0] for x in vs))
+        vs.append(sv + cen[None, :])
+        ids.append(np.full(sf.shape[0], k, dtype=np.int32))
+    return np.concatenate(vs), np.concatenate(fs).astype(np.int32), np.concatenate(ids)
