@@ -22,6 +22,12 @@ This oracle follows the deterministic partial-pivoting reading:
 4. stop when ``|u| |v| <= eps_rel sqrt(S2)`` or the rank cap is reached;
    otherwise the next row is ``argmax |u(i)|`` over unused rows (first on ties).
 
+Full pivoting (the paper's choice): ``aca_full`` takes each pivot as the
+largest entry of the whole residual and stops on the exact residual norm of
+eq. (31); it needs the evaluated block but cannot miss parts of it, which
+partial pivoting does on blocks whose back-facing pairs leave whole groups of
+rows or columns zero (the 13-sphere spiral of Sec. 6).
+
 Recompression (optional): the crosses of a block stored low-rank are
 truncated to the smallest rank that keeps the discarded singular values of
 ``U V^T`` within the tolerance (``recompress``).
@@ -104,6 +110,44 @@ def aca_partial(row_fn, col_fn, m: int, n: int, tol: float, k_cap: int) -> ACARe
     return ACAResult(U, V, R, C, converged)
 
 
+def aca_full(X, tol: float, k_cap: int) -> ACAResult:
+    """Fully pivoted ACA of an explicit m x n block (the paper's choice,
+    Sec. 1; Sec. 4.3): each cross takes the entry of largest magnitude of the
+    whole residual R (first in row-major order on ties) as pivot,
+    ``u = R(:, j)``, ``v = R(i, :) / R(i, j)``, and ``R <- R - u v^T``
+    (eq. (30) built one cross at a time).  The residual is known exactly, so
+    the stop test is eq. (31) itself: ``|R|_F <= tol |X|_F``, or a zero
+    residual, or the rank cap."""
+    R = np.array(X, dtype=np.float64, copy=True)
+    m, n = R.shape
+    nx = float(np.linalg.norm(X))
+    us, vs, rows, cols = [], [], [], []
+    converged = False
+    while True:
+        flat = int(np.argmax(np.abs(R)))
+        i, j = divmod(flat, n)
+        piv = R[i, j]
+        if piv == 0.0:
+            converged = True
+            break
+        u = R[:, j].copy()
+        v = R[i, :] / piv
+        R = R - np.outer(u, v)
+        us.append(u)
+        vs.append(v)
+        rows.append(i)
+        cols.append(j)
+        if float(np.linalg.norm(R)) <= tol * nx:
+            converged = True
+            break
+        if len(us) >= k_cap:
+            break
+    k = len(us)
+    U = np.stack(us, axis=1) if k else np.zeros((m, 0))
+    V = np.stack(vs, axis=1) if k else np.zeros((n, 0))
+    return ACAResult(U, V, rows, cols, converged)
+
+
 def rank_cap(m: int, n: int, k_max: int) -> int:
     """Smallest k at which ``k (m + n) >= m n``, limited by ``k_max``."""
     return max(1, min(k_max, -(-(m * n) // (m + n))))
@@ -171,11 +215,13 @@ class HMatrix:
 
 
 def build_hmatrix(c, nrm, area, n_min: int, eta: float, tol: float, k_max: int = 256,
-                  recompress_tol: float | None = None) -> HMatrix:
+                  recompress_tol: float | None = None, pivot: str = "partial") -> HMatrix:
     """Cluster tree (Alg. 1), block tree (Alg. 2), dense near field, ACA
     (eqs. (30)-(31)) on every admissible block, with the storage rule; with
     ``recompress_tol``, every block stored low-rank is then truncated by
-    ``recompress`` (the storage rule is decided on the ACA rank)."""
+    ``recompress`` (the storage rule is decided on the ACA rank).
+    ``pivot``: "partial" (``aca_partial``, entries evaluated by rows and
+    columns) or "full" (``aca_full`` on the evaluated block)."""
     root, perm = clustering.build_index_tree(c, n_min)
     dense_blocks, lr_blocks = clustering.build_block_tree(root, eta)
     cp, np_, ap = c[perm], nrm[perm], area[perm]
@@ -187,11 +233,14 @@ def build_hmatrix(c, nrm, area, n_min: int, eta: float, tol: float, k_max: int =
         m, nn = r1 - r0, c1 - c0
         cols = np.arange(c0, c1)
         rows = np.arange(r0, r1)
-        res = aca_partial(
-            lambda i: view_factor_block(cp, np_, ap, [r0 + i], cols)[0],
-            lambda j: view_factor_block(cp, np_, ap, rows, [c0 + j])[:, 0],
-            m, nn, tol, rank_cap(m, nn, k_max),
-        )
+        if pivot == "full":
+            res = aca_full(view_factor_block(cp, np_, ap, rows, cols), tol, rank_cap(m, nn, k_max))
+        else:
+            res = aca_partial(
+                lambda i: view_factor_block(cp, np_, ap, [r0 + i], cols)[0],
+                lambda j: view_factor_block(cp, np_, ap, rows, [c0 + j])[:, 0],
+                m, nn, tol, rank_cap(m, nn, k_max),
+            )
         k = res.U.shape[1]
         if (not res.converged) or k * (m + nn) >= m * nn:
             dense.append((r0, r1, c0, c1, view_factor_block(cp, np_, ap, rows, cols)))

@@ -234,3 +234,38 @@ def test_ambient_pins_reject_planted_mistakes():
     Ti = np.random.default_rng(33).uniform(300.0, 1500.0, aa.size)
     assert np.all(radiosity.ambient_flux(radiosity.clamped_row_sums(Fi), Ti, 400.0) == 0.0)
     assert np.any(radiosity.ambient_flux(Fi.sum(axis=1), Ti, 400.0) != 0.0)            # unclamped
+
+
+def test_full_pivot_pins_reject_planted_mistakes():
+    """A cross whose row is not divided by the pivot, and a pivot searched
+    only in the first row of the residual, each fail the planted-rank pin or
+    the skeleton identity of eq. (30)."""
+    from oracle import aca
+
+    rng = np.random.default_rng(41)
+    X = rng.standard_normal((40, 5)) @ rng.standard_normal((5, 30))
+
+    def run(undivided=False, row_only=False):
+        R = X.copy()
+        us, vs = [], []
+        for _ in range(30):
+            if row_only:
+                i = 0
+                j = int(np.argmax(np.abs(R[0])))
+            else:
+                i, j = divmod(int(np.argmax(np.abs(R))), R.shape[1])
+            if R[i, j] == 0.0:
+                break
+            u = R[:, j].copy()
+            v = R[i, :] if undivided else R[i, :] / R[i, j]
+            R = R - np.outer(u, v)
+            us.append(u)
+            vs.append(v)
+            if np.linalg.norm(R) <= 1e-13 * np.linalg.norm(X):
+                break
+        U, V = np.stack(us, axis=1), np.stack(vs, axis=1)
+        return U.shape[1] == 5 and np.linalg.norm(X - U @ V.T) <= 1e-12 * np.linalg.norm(X)
+
+    assert run()
+    assert not run(undivided=True)
+    assert not run(row_only=True)

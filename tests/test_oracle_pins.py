@@ -518,3 +518,39 @@ def test_fibonacci_spiral_is_an_open_cavity_with_isolated_facets():
     assert 0.06 <= iso.mean() <= 0.10
     G = aa[:, None] * F
     assert np.max(np.abs(G - G.T)) <= 1e-15 * np.max(G)
+
+
+# ---------------------------------------------------------------- fully pivoted ACA (Sec. 1, Sec. 4.3)
+def test_full_pivot_aca_recovers_planted_rank_and_pivots_on_the_largest_entry():
+    rng = np.random.default_rng(41)
+    X = rng.standard_normal((40, 5)) @ rng.standard_normal((5, 30))
+    res = aca.aca_full(X, 1e-13, 30)
+    assert res.converged and res.U.shape[1] == 5
+    assert np.linalg.norm(X - res.U @ res.V.T) <= 1e-12 * np.linalg.norm(X)
+    i, j = np.unravel_index(np.argmax(np.abs(X)), X.shape)
+    assert (res.rows[0], res.cols[0]) == (i, j)
+    # cross = skeleton formula eq. (30) over the chosen rows and columns
+    R, Cc = res.rows, res.cols
+    S = X[:, Cc] @ np.linalg.solve(X[np.ix_(R, Cc)], X[R, :])
+    assert np.linalg.norm(S - res.U @ res.V.T) <= 1e-10 * np.linalg.norm(X)
+
+
+def test_full_pivot_aca_meets_eq31_on_every_block_where_partial_pivoting_fails():
+    """The 13-sphere spiral: partial pivoting leaves whole zero-structured
+    parts of some admissible blocks out (per-block errors of several percent),
+    while full pivoting meets |X - U V^T|_F <= tol |X|_F on every block."""
+    from workloads import configs
+    cav = configs.fibonacci_spiral(nu=2)
+    c, n, a = geometry.facets_from_triangles(cav.v, cav.tri)
+    F = viewfactor.view_factor_matrix(c, n, a)
+    tol = 1e-8
+    Hf = aca.build_hmatrix(c, n, a, 16, 1.5, tol, pivot="full")
+    Hp = aca.build_hmatrix(c, n, a, 16, 1.5, tol, pivot="partial")
+    Fp = F[np.ix_(Hf.perm, Hf.perm)]
+    worst = 0.0
+    for r0, r1, c0, c1, U, V in Hf.lowrank:
+        X = Fp[r0:r1, c0:c1]
+        worst = max(worst, np.linalg.norm(X - U @ V.T) / max(np.linalg.norm(X), 1e-300))
+    assert worst <= tol
+    assert np.linalg.norm(Hf.to_dense() - F) <= tol * np.linalg.norm(F)
+    assert np.linalg.norm(Hp.to_dense() - F) > 100 * tol * np.linalg.norm(F)
