@@ -147,6 +147,14 @@ typedef struct {
                               ACA rank; blocks of ACA rank above 256 keep their crosses.  0: the
                               ACA crosses are stored as they are (default).  HM_EINVAL outside
                               0..1. */
+  int32_t aca_pivot;       /* 0: partial (row/column) pivoting: each cross evaluates one row and
+                              one column, stop when |u_k||v_k| <= aca_tol |sum u_l v_l^T|_F
+                              (default); 1: full pivoting (the paper's choice): the block is
+                              evaluated whole, each pivot is the largest entry of the residual
+                              (first in row-major order on ties) and the stop test is eq. (31)
+                              itself, |X - U V^T|_F <= aca_tol |X|_F, so no block can miss it;
+                              needs m n doubles of scratch per block being compressed and
+                              O(m n k) work.  HM_EINVAL outside 0..1. */
 } hm_assembly_params;
 
 /* Evaluate the near field (every inadmissible leaf block, FP64 evaluation
@@ -264,6 +272,14 @@ typedef struct {
   int32_t vec_dtype;       /* Krylov vectors when not refining: HM_F64 or HM_F32 */
   int32_t use_graphs;      /* 1: the Arnoldi steps run as HIP graphs captured once per workspace
                               (fewer launches; same kernels and results); 0: direct launches */
+  int32_t open_cavity;     /* 1: open cavity (eq. (35)): the flux gains the exchange with an
+                              ambient at ambient_temperature, -sigma (1 - c_i)(T_i^4 - T_amb^4) into
+                              facet i, c_i = clamp(sum_j F_ij, 0, 1) (eqs. (32)-(33), the row sum of
+                              the stored H-matrix); the transient's Newton update takes its
+                              derivative 4 sigma (1 - c_i) T_i^3.  The server takes closed cavities
+                              only: hm_server_create returns HM_EINVAL for 1.  0: closed
+                              cavity (default) */
+  double ambient_temperature; /* T_amb in K (> 0) when open_cavity = 1; ignored otherwise */
 } hm_solve_params;
 
 typedef struct {

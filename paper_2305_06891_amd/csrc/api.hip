@@ -204,6 +204,9 @@ void check_params(const hm_solve_params* p) {
              "solve: ir_inner_rtol must be in (0, 1)");
   HM_REQUIRE(p->vec_dtype == HM_F64 || p->vec_dtype == HM_F32, "solve: vec_dtype must be HM_F64 or HM_F32");
   HM_REQUIRE(p->use_graphs == 0 || p->use_graphs == 1, "solve: use_graphs must be 0 or 1");
+  HM_REQUIRE(p->open_cavity == 0 || p->open_cavity == 1, "solve: open_cavity must be 0 or 1");
+  HM_REQUIRE(!p->open_cavity || (std::isfinite(p->ambient_temperature) && p->ambient_temperature > 0.0),
+             "solve: ambient_temperature must be positive and finite for an open cavity");
 }
 
 }  // namespace
@@ -276,6 +279,7 @@ void check_assembly_params(const hm_assembly_params* p, const char* fn) {
   HM_REQUIRE(p->dense_dtype != HM_BF16 || !p->closed_row_scale, f + ": closed_row_scale needs an FP32 or FP64 near field");
   HM_REQUIRE(p->autotune >= 0 && p->autotune <= 16, f + ": autotune must be in 0..16");
   HM_REQUIRE(p->recompress == 0 || p->recompress == 1, f + ": recompress must be 0 or 1");
+  HM_REQUIRE(p->aca_pivot == 0 || p->aca_pivot == 1, f + ": aca_pivot must be 0 or 1");
 }
 }  // namespace
 

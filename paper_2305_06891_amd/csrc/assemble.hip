@@ -41,6 +41,7 @@ struct AcaDev {
   int32_t rb, re, cb, ce;
   int32_t kcap, out;            // rank cap; index of the block's rank/status outputs
   int64_t u_off, v_off, f_off;  // scratch offsets (doubles, doubles, ints)
+  int64_t r_off;                // full pivoting: scratch offset of the m x n residual (doubles)
   double tol;                   // relative ACA tolerance of the block's cavity
 };
 
@@ -375,6 +376,94 @@ __global__ __launch_bounds__(256) void k_aca_wave(const AcaDev* __restrict__ blo
 }
 #pragma clang fp contract(on)
 
+// ---- fully pivoted ACA (the paper's pivoting), one workgroup per block:
+// the block is evaluated into a column-major m x n residual R in scratch;
+// each cross takes the entry of largest |R| (smallest row-major index i n + j
+// on ties) as pivot, u = R(:, j), v = R(i, :) / R(i, j), and R <- R - u v^T
+// entry by entry (one product and one subtraction, no contraction, as the
+// oracle's R - outer(u, v)), while the same pass finds the next pivot and
+// |R|_F^2.  The stop test is eq. (31) on the exact residual:
+// |R|_F <= tol |X|_F (or a zero residual, or the rank cap).
+#pragma clang fp contract(off)
+template <int T>
+__global__ __launch_bounds__(T) void k_aca_full(const AcaDev* __restrict__ blocks, Geo g,
+                                                double* __restrict__ scratch, int* __restrict__ rank,
+                                                int* __restrict__ status) {
+  constexpr int W = T / 64;
+  __shared__ ArgMax sh_am[W];
+  __shared__ double sh_sum[W];
+  const AcaDev b = blocks[blockIdx.x];
+  const int m = b.re - b.rb, n = b.ce - b.cb;
+  const int64_t mn = (int64_t)m * n;
+  double* R = scratch + b.r_off;
+  double* U = scratch + b.u_off;
+  double* V = scratch + b.v_off;
+  const int tid = threadIdx.x;
+  ArgMax am{-1.0, 0.0, 0x7fffffff};
+  double s2 = 0.0;
+  for (int64_t e = tid; e < mn; e += T) {
+    const int i = (int)(e % m), j = (int)(e / m);
+    const double x = view_factor(g, b.rb + i, b.cb + j);
+    R[e] = x;
+    s2 += x * x;
+    const double a = fabs(x);
+    const int key = i * n + j;
+    if (a > am.mag || (a == am.mag && key < am.idx)) am = ArgMax{a, x, key};
+  }
+  {
+    double t[1] = {s2};
+    block_sum<W, 1>(t, sh_sum);
+    s2 = t[0];
+  }
+  am = block_argmax<W>(am, sh_am);
+  const double limit = b.tol * sqrt(s2);
+  int k = 0, conv = 0;
+  for (;;) {
+    if (am.idx == 0x7fffffff || am.val == 0.0) {
+      conv = 1;  // zero residual: the crosses so far are exact
+      break;
+    }
+    const int ip = am.idx / n, jp = am.idx % n;
+    const double piv = am.val;
+    double* uk = U + (int64_t)k * m;
+    double* vk = V + (int64_t)k * n;
+    for (int i = tid; i < m; i += T) uk[i] = R[(int64_t)jp * m + i];
+    for (int j = tid; j < n; j += T) vk[j] = R[(int64_t)j * m + ip] / piv;
+    __syncthreads();
+    am = ArgMax{-1.0, 0.0, 0x7fffffff};
+    double r2 = 0.0;
+    for (int64_t e = tid; e < mn; e += T) {
+      const int i = (int)(e % m), j = (int)(e / m);
+      const double r = R[e] - uk[i] * vk[j];
+      R[e] = r;
+      r2 += r * r;
+      const double a = fabs(r);
+      const int key = i * n + j;
+      if (a > am.mag || (a == am.mag && key < am.idx)) am = ArgMax{a, r, key};
+    }
+    {
+      double t[1] = {r2};
+      block_sum<W, 1>(t, sh_sum);
+      r2 = t[0];
+    }
+    am = block_argmax<W>(am, sh_am);
+    ++k;
+    if (sqrt(r2) <= limit) {
+      conv = 1;
+      break;
+    }
+    if (k >= b.kcap) {
+      conv = 0;
+      break;
+    }
+  }
+  if (tid == 0) {
+    rank[b.out] = k;
+    status[b.out] = conv;
+  }
+}
+#pragma clang fp contract(on)
+
 struct CompactDev {
   int64_t su, sv;   // scratch offsets of U, V (doubles)
   int64_t du, dv;   // destination offsets (elements) in the stage buffer
@@ -696,7 +785,7 @@ std::vector<hm_matrix*> assemble_batch(hm_ctx& ctx, const std::vector<const hm_t
   const int64_t budget = std::max<int64_t>(256ll << 20, std::min<int64_t>(8ll << 30, (int64_t)free_b / 4));
   std::vector<DevBuf> stages;
   std::vector<size_t> stage_last;  // last job with factors in each stage buffer
-  DevBuf scratch, flags, d_blk, d_blk_small, d_blk_huge, d_rank, d_status, d_cd;
+  DevBuf scratch, flags, d_blk, d_blk_small, d_blk_huge, d_blk_full, d_rank, d_status, d_cd;
   size_t jpos = 0, bpos = 0, next_finish = 0;
   auto finish_ready = [&]() {
     while (next_finish < nj && jobs[next_finish].lr_done == jobs[next_finish].t->lowrank.size()) {
@@ -711,6 +800,7 @@ std::vector<hm_matrix*> assemble_batch(hm_ctx& ctx, const std::vector<const hm_t
   while (next_finish < nj) {
     std::vector<AcaDev> batch;
     std::vector<int32_t> bjob;  // job of each batch entry
+    std::vector<uint8_t> bfull;  // 1: fully pivoted ACA
     int64_t sd = 0, sf = 0;
     while (jpos < nj) {
       const AsmJob& J = jobs[jpos];
@@ -722,12 +812,17 @@ std::vector<hm_matrix*> assemble_batch(hm_ctx& ctx, const std::vector<const hm_t
       const BlockRef& b = J.t->lowrank[bpos];
       const int m = b.re - b.rb, nn = b.ce - b.cb;
       const int64_t kc = rank_cap(m, nn, std::min<int>(J.p.k_max, ACA_KMAX));
-      const int64_t need = kc * (m + nn) * 8 + m * 4;
+      const bool full = J.p.aca_pivot == 1;
+      const int64_t rsz = full ? (int64_t)m * nn : 0;  // residual of full pivoting
+      HM_REQUIRE(rsz < ((int64_t)1 << 31), "assemble: full pivoting needs admissible blocks of fewer than 2^31 entries");
+      const int64_t need = (kc * (m + nn) + rsz) * 8 + m * 4;
       if (!batch.empty() && (sd * 8 + sf * 4 + need) > budget) break;
       const int32_t o = (int32_t)J.goff;
-      batch.push_back(AcaDev{b.rb + o, b.re + o, b.cb + o, b.ce + o, (int32_t)kc, 0, sd, sd + kc * m, sf, J.p.aca_tol});
+      batch.push_back(AcaDev{b.rb + o, b.re + o, b.cb + o, b.ce + o, (int32_t)kc, 0, sd, sd + kc * m, sf,
+                             sd + kc * (m + nn), J.p.aca_tol});
       bjob.push_back((int32_t)jpos);
-      sd += kc * (m + nn);
+      bfull.push_back(full ? 1 : 0);
+      sd += kc * (m + nn) + rsz;
       sf += m;
       ++bpos;
     }
@@ -735,11 +830,12 @@ std::vector<hm_matrix*> assemble_batch(hm_ctx& ctx, const std::vector<const hm_t
     // blocks of at most 64 x 64 (rank cap <= 32): one wave each; larger ones:
     // one workgroup each (512 threads from m + n >= ACA_HUGE), largest
     // first for the hardware dispatcher
-    std::vector<AcaDev> small, large, huge;
+    std::vector<AcaDev> small, large, huge, full;
     for (size_t q = 0; q < batch.size(); ++q) {
       batch[q].out = (int32_t)q;
       const AcaDev& a = batch[q];
-      if (a.re - a.rb <= 64 && a.ce - a.cb <= 64 && a.kcap <= ACAW_K) small.push_back(a);
+      if (bfull[q]) full.push_back(a);
+      else if (a.re - a.rb <= 64 && a.ce - a.cb <= 64 && a.kcap <= ACAW_K) small.push_back(a);
       else if ((a.re - a.rb) + (a.ce - a.cb) >= ACA_HUGE) huge.push_back(a);
       else large.push_back(a);
     }
@@ -748,6 +844,7 @@ std::vector<hm_matrix*> assemble_batch(hm_ctx& ctx, const std::vector<const hm_t
     };
     std::stable_sort(large.begin(), large.end(), by_size);
     std::stable_sort(huge.begin(), huge.end(), by_size);
+    std::stable_sort(full.begin(), full.end(), by_size);
     if ((size_t)sd * 8 > scratch.bytes()) scratch.alloc((size_t)sd * 8);
     if ((size_t)sf * 4 > flags.bytes()) flags.alloc((size_t)sf * 4);
     d_rank.alloc(batch.size() * 4);
@@ -769,6 +866,12 @@ std::vector<hm_matrix*> assemble_batch(hm_ctx& ctx, const std::vector<const hm_t
       upload(d_blk, large, s);
       hipLaunchKernelGGL(k_aca<ACA_T>, dim3((unsigned)large.size()), dim3(ACA_T), 0, s, d_blk.get<AcaDev>(), g,
                          scratch.get<double>(), flags.get<int>(), d_rank.get<int>(), d_status.get<int>());
+      HM_HIP(hipGetLastError());
+    }
+    if (!full.empty()) {
+      upload(d_blk_full, full, s);
+      hipLaunchKernelGGL(k_aca_full<ACA_T>, dim3((unsigned)full.size()), dim3(ACA_T), 0, s, d_blk_full.get<AcaDev>(),
+                         g, scratch.get<double>(), d_rank.get<int>(), d_status.get<int>());
       HM_HIP(hipGetLastError());
     }
     if (!small.empty()) {

@@ -682,6 +682,7 @@ hm_status hm_server_create(hm_ctx* ctx, const hm_server_params* p, hm_server** o
     HM_REQUIRE(p->hbm_budget_bytes > 0 && p->max_active >= 1, "hm_server_create: bad budget or max_active");
     HM_REQUIRE(p->max_rhs_per_slot >= 1 && p->max_rhs_per_slot <= 16, "hm_server_create: max_rhs_per_slot in 1..16");
     HM_REQUIRE(p->sigma > 0.0, "hm_server_create: sigma must be > 0");
+    HM_REQUIRE(p->solve.open_cavity == 0, "hm_server_create: open cavities are not served (closed cavities only)");
     HM_REQUIRE(p->solve.rtol > 0 && p->solve.rtol < 1 && p->solve.restart >= 1 && p->solve.restart <= MAXM &&
                    p->solve.max_iter >= 1 && p->solve.ir_inner_rtol > 0 && p->solve.ir_inner_rtol < 1,
                "hm_server_create: bad solve parameters");

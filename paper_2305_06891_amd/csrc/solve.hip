@@ -83,24 +83,43 @@ __global__ void k_acc(const VT* __restrict__ x, double* __restrict__ y, int64_t 
   if (k < n) y[k] += (double)x[k];
 }
 
-// q = eps (H - sigma T^4 g)  (eq. (12) through J and g = F C^-1 eps)
+// q = eps (H - sigma T^4 g)  (eq. (12) through J and g = F C^-1 eps); for an
+// open cavity (amb != NULL) plus the ambient exchange of eq. (35),
+// -sigma (1 - c) (T^4 - T_amb^4) with amb = 1 - c
 __global__ void k_flux(const double* __restrict__ eps, const double* __restrict__ T, const double* __restrict__ H,
-                       const double* __restrict__ g, int64_t N, int ncol, double sigma, double* __restrict__ q) {
+                       const double* __restrict__ g, int64_t N, int ncol, double sigma, double* __restrict__ q,
+                       const double* __restrict__ amb, double tamb4) {
   const int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int j = blockIdx.y;
   if (row >= N || j >= ncol) return;
   const int64_t k = row + j * N;
   const double t = T[k];
   const double t2 = t * t;
-  q[k] = eps[row] * (H[k] - sigma * (t2 * t2) * g[row]);
+  double v = eps[row] * (H[k] - sigma * (t2 * t2) * g[row]);
+  if (amb) v = v - sigma * amb[row] * (t2 * t2 - tamb4);
+  q[k] = v;
+}
+
+// amb = 1 - clamp(s, 0, 1) for the row sums s = F 1 (eqs. (32)-(33))
+__global__ void k_ambient(const double* __restrict__ rowsum, int64_t N, double* __restrict__ amb) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  const double c = fmin(fmax(rowsum[i], 0.0), 1.0);
+  amb[i] = 1.0 - c;
+}
+
+__global__ void k_fill(double* __restrict__ x, int64_t n, double v) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) x[i] = v;
 }
 
 // Newton residual R = mc (T - Tn)/dt - q - s, and the update T <- T - R / D
 // with D = mc/dt + 4 sigma eps g T^3 (mode 1), or only R (mode 0).
+// (open cavity: D also holds the ambient term's 4 sigma (1 - c) T^3)
 __global__ void k_newton(const double* __restrict__ eps, const double* __restrict__ g, const double* __restrict__ q,
                          const double* __restrict__ src, const double* __restrict__ Tn, double* __restrict__ T,
                          double* __restrict__ R, int64_t N, int ncol, double mc, double dt, double sigma,
-                         const int* __restrict__ upd) {
+                         const int* __restrict__ upd, const double* __restrict__ amb) {
   const int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int j = blockIdx.y;
   if (row >= N || j >= ncol) return;
@@ -109,7 +128,8 @@ __global__ void k_newton(const double* __restrict__ eps, const double* __restric
   const double r = mc * (t - Tn[k]) / dt - q[k] - src[k];
   R[k] = r;
   if (upd && upd[j]) {
-    const double D = mc / dt + 4.0 * sigma * eps[row] * g[row] * (t * t * t);
+    const double a = eps[row] * g[row] + (amb ? amb[row] : 0.0);
+    const double D = mc / dt + 4.0 * sigma * a * (t * t * t);
     T[k] = t - r / D;
   }
 }
@@ -234,6 +254,26 @@ void Batch::ensure_g(const std::vector<const double*>& eps_user, hipStream_t s) 
   g_ready = true;
 }
 
+void Batch::set_ambient(const hm_solve_params& p, hipStream_t s) {
+  open = p.open_cavity != 0;
+  if (!open) return;
+  const double t2 = p.ambient_temperature * p.ambient_temperature;
+  tamb4 = t2 * t2;
+  if (amb_ready) return;
+  // row sums of the stored operator: one FP64 product with the most
+  // accurate factors on a vector of ones
+  if (!gb) gb = std::make_unique<Batch>(mats, 1, s);
+  Batch& B = *gb;
+  DevBuf ones(N * 8), rs(N * 8);
+  hipLaunchKernelGGL(k_fill, grid_rows(N), dim3(256), 0, s, ones.get<double>(), N, 1.0);
+  launch_matvec(*B.C, 1, 8, true, ones.get(), N, rs.get(), N, Epilogue{}, nullptr, s);
+  amb.alloc(N * 8);
+  hipLaunchKernelGGL(k_ambient, grid_rows(N), dim3(256), 0, s, rs.get<double>(), N, amb.get<double>());
+  HM_HIP(hipGetLastError());
+  HM_HIP(hipStreamSynchronize(s));
+  amb_ready = true;
+}
+
 SolveResult Batch::solve(const std::vector<const double*>& eps_user, const std::vector<const double*>& T_user,
                          const std::vector<int64_t>& ldT, double sigma, const hm_solve_params& p,
                          const std::vector<double*>& J_user, const std::vector<int64_t>& ldJ,
@@ -250,6 +290,7 @@ SolveResult Batch::solve(const std::vector<const double*>& eps_user, const std::
   R = solve_prepared(p, s, false, true, want_q);
   if (want_q) {
     ensure_g(eps_user, s);
+    set_ambient(p, s);
     flux(sigma, s, R.fx);
   }
   io({}, J_user, 0, &ldJ, s);
@@ -398,7 +439,8 @@ void Batch::residual64(bool hi, hipStream_t s, bool keep_fx) {
 void Batch::flux(double sigma, hipStream_t s, bool have_fx) {
   if (!have_fx) launch_matvec(*C, nrhs, 8, true, x64.get(), N, H64.get(), N, Epilogue{}, nullptr, s);
   hipLaunchKernelGGL(k_flux, grid_rows(N, nrhs), dim3(256), 0, s, epsp.get<double>(), Tp.get<double>(),
-                     H64.get<double>(), g.get<double>(), N, nrhs, sigma, H64.get<double>());
+                     H64.get<double>(), g.get<double>(), N, nrhs, sigma, H64.get<double>(),
+                     open ? (const double*)amb.get<double>() : (const double*)nullptr, tamb4);
   HM_HIP(hipGetLastError());
 }
 
@@ -411,6 +453,8 @@ TransientResult Batch::transient(const std::vector<const double*>& eps_user, dou
   gather(epsp.get<double>(), 1, 1, s);
   hipLaunchKernelGGL(k_omeps<double>, grid_rows(N), dim3(256), 0, s, epsp.get<double>(), N, omeps64.get<double>());
   ensure_g(eps_user, s);
+  set_ambient(sp, s);
+  const double* ambp = open ? amb.get<double>() : nullptr;
   std::vector<int64_t> ldv{ldT};
   io({T_user}, {}, 0, &ldv, s);
   gather(Tp.get<double>(), nrhs, W, s);
@@ -451,7 +495,7 @@ TransientResult Batch::transient(const std::vector<const double*>& eps_user, dou
       std::fill(upd.begin(), upd.end(), 0);
       hipLaunchKernelGGL(k_newton, grid_rows(N, nrhs), dim3(256), 0, s, epsp.get<double>(), g.get<double>(),
                          H64.get<double>(), srcp.get<double>(), Tn.get<double>(), Tp.get<double>(), Rv.get<double>(),
-                         N, nrhs, tp.mc, tp.dt, sigma, (const int*)nullptr);
+                         N, nrhs, tp.mc, tp.dt, sigma, (const int*)nullptr, ambp);
       HM_HIP(hipGetLastError());
       std::vector<double> rn;
       block_norms(K8, Rv.get(), rn, s);
@@ -472,7 +516,7 @@ TransientResult Batch::transient(const std::vector<const double*>& eps_user, dou
       HM_HIP(hipMemcpyAsync(d_upd.get(), upd.data(), W * 4, hipMemcpyHostToDevice, s));
       hipLaunchKernelGGL(k_newton, grid_rows(N, nrhs), dim3(256), 0, s, epsp.get<double>(), g.get<double>(),
                          H64.get<double>(), srcp.get<double>(), Tn.get<double>(), Tp.get<double>(), Rv.get<double>(),
-                         N, nrhs, tp.mc, tp.dt, sigma, d_upd.get<int>());
+                         N, nrhs, tp.mc, tp.dt, sigma, d_upd.get<int>(), ambp);
       HM_HIP(hipGetLastError());
       ++it;
     }

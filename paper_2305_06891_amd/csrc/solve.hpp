@@ -45,6 +45,11 @@ struct Batch {
   DevBuf d_ios;
   std::unique_ptr<Batch> gb;  // width-1 batch for g = F C^-1 eps
   bool g_ready = false;
+  // open cavities (eq. (35)): amb = 1 - clamp(F 1, 0, 1) per permuted row,
+  // and the ambient's T^4 of the current call (open = false: closed cavity)
+  DevBuf amb;
+  bool amb_ready = false, open = false;
+  double tamb4 = 0.0;
 
   Batch(const std::vector<const hm_matrix*>& mats, int nrhs, hipStream_t s);
   Krylov& krylov(int vb, int restart, hipStream_t s);
@@ -53,6 +58,8 @@ struct Batch {
   void gather(double* dst, int ncol, int dst_cols, hipStream_t s);
   void scatter(const double* src, int ncol, hipStream_t s);
   void ensure_g(const std::vector<const double*>& eps_user, hipStream_t s);
+  // sets open / tamb4 from p and, for an open cavity, computes amb once
+  void set_ambient(const hm_solve_params& p, hipStream_t s);
   void prepare_rhs(double sigma, const hm_solve_params& p, hipStream_t s);
   // report: with FP32 vectors, measure the final residual with FP64 vectors
   // (one more product; callers that check their own residual skip it)

@@ -42,13 +42,14 @@ class hm_tree_params(C.Structure):
 class hm_assembly_params(C.Structure):
     _fields_ = [("aca_tol", C.c_double), ("k_max", C.c_int32), ("lowrank_dtype", C.c_int),
                 ("dense_dtype", C.c_int), ("keep_f32_copy", C.c_int32), ("closed_row_scale", C.c_int32),
-                ("autotune", C.c_int32), ("recompress", C.c_int32)]
+                ("autotune", C.c_int32), ("recompress", C.c_int32), ("aca_pivot", C.c_int32)]
 
 
 class hm_solve_params(C.Structure):
     _fields_ = [("rtol", C.c_double), ("restart", C.c_int32), ("max_iter", C.c_int32),
                 ("mixed_precision", C.c_int32), ("ir_inner_rtol", C.c_double), ("want_q", C.c_int32),
-                ("vec_dtype", C.c_int32), ("use_graphs", C.c_int32)]
+                ("vec_dtype", C.c_int32), ("use_graphs", C.c_int32), ("open_cavity", C.c_int32),
+                ("ambient_temperature", C.c_double)]
 
 
 class hm_solve_info(C.Structure):
@@ -300,16 +301,16 @@ class HMatrix:
 
 
 def hm_assemble_hmatrix(ctx, tree: Tree, aca_tol=1e-6, k_max=256, lowrank_dtype=HM_F32, dense_dtype=HM_F32,
-                        keep_f32_copy=0, closed_row_scale=0, autotune=0, recompress=0) -> HMatrix:
+                        keep_f32_copy=0, closed_row_scale=0, autotune=0, recompress=0, aca_pivot=0) -> HMatrix:
     p = hm_assembly_params(float(aca_tol), int(k_max), int(lowrank_dtype), int(dense_dtype), int(keep_f32_copy),
-                           int(closed_row_scale), int(autotune), int(recompress))
+                           int(closed_row_scale), int(autotune), int(recompress), int(aca_pivot))
     h = _vp()
     _check(lib.hm_assemble_hmatrix(ctx.handle, tree._h, C.byref(p), C.byref(h)), ctx.handle)
     return HMatrix(h, ctx)
 
 
 def hm_assemble_hmatrix_batched(ctx, trees, aca_tol=1e-6, k_max=256, lowrank_dtype=HM_F32, dense_dtype=HM_F32,
-                                keep_f32_copy=0, closed_row_scale=0, autotune=0, recompress=0):
+                                keep_f32_copy=0, closed_row_scale=0, autotune=0, recompress=0, aca_pivot=0):
     """Matrices of several cavities assembled together (shared ACA launches;
     with autotune, one product split tuned on their batched product).  Every
     parameter is a scalar for all cavities or a sequence with one entry per
@@ -321,12 +322,12 @@ def hm_assemble_hmatrix_batched(ctx, trees, aca_tol=1e-6, k_max=256, lowrank_dty
         return list(v) if isinstance(v, (list, tuple)) else [v] * k
 
     cols = [each(aca_tol), each(k_max), each(lowrank_dtype), each(dense_dtype), each(keep_f32_copy),
-            each(closed_row_scale), each(autotune), each(recompress)]
+            each(closed_row_scale), each(autotune), each(recompress), each(aca_pivot)]
     if any(len(c) != k for c in cols):
         raise ValueError("one parameter value per tree expected")
     ps = (hm_assembly_params * k)(*[hm_assembly_params(float(a), int(b), int(c), int(d), int(e), int(f), int(g),
-                                                       int(h))
-                                    for a, b, c, d, e, f, g, h in zip(*cols)])
+                                                       int(h), int(i))
+                                    for a, b, c, d, e, f, g, h, i in zip(*cols)])
     ts = (_vp * k)(*[t._h for t in trees])
     hs = (_vp * k)()
     _check(lib.hm_assemble_hmatrix_batched(ctx.handle, k, ts, ps, hs), ctx.handle)
@@ -371,9 +372,10 @@ def hm_hmatvec_profile(ctx, M, nrhs=1, vec_dtype=HM_F32, use_f32_copy=False, rep
 
 
 def solve_params(rtol=1e-12, restart=30, max_iter=1000, mixed_precision=0, ir_inner_rtol=1e-4, want_q=1,
-                 vec_dtype=HM_F64, use_graphs=1):
+                 vec_dtype=HM_F64, use_graphs=1, open_cavity=0, ambient_temperature=0.0):
     return hm_solve_params(float(rtol), int(restart), int(max_iter), int(mixed_precision), float(ir_inner_rtol),
-                           int(want_q), int(vec_dtype), int(use_graphs))
+                           int(want_q), int(vec_dtype), int(use_graphs), int(open_cavity),
+                           float(ambient_temperature))
 
 
 def _info_dict(i: hm_solve_info):
@@ -451,10 +453,10 @@ class Server:
         self._n = {}
 
     def register_cavity(self, cavity_id, tree: Tree, eps_host, aca_tol=1e-6, k_max=256, lowrank_dtype=HM_BF16,
-                        dense_dtype=HM_F32, keep_f32_copy=1, autotune=0, recompress=0):
+                        dense_dtype=HM_F32, keep_f32_copy=1, autotune=0, recompress=0, aca_pivot=0):
         e = _f64(eps_host)
         ap = hm_assembly_params(float(aca_tol), int(k_max), int(lowrank_dtype), int(dense_dtype),
-                                int(keep_f32_copy), 0, int(autotune), int(recompress))
+                                int(keep_f32_copy), 0, int(autotune), int(recompress), int(aca_pivot))
         _check(lib.hm_server_register_cavity(self._h, C.c_uint64(cavity_id), tree._h, _ptr(e), C.byref(ap)))
         self._n[cavity_id] = tree.n
 
