@@ -21,6 +21,11 @@ Contents (each function cites the passage of the paper it follows):
 * ``closed_forms`` two infinite gray plates (Sec. 2.2), projected-sphere and
                    aligned-parallel-squares closed forms
 * ``transient``    lumped backward-Euler radiative exchange (analogue of Sec. 3.3)
+* ``matfree``      the dense definition at large n: products with the
+                   centroid-rule entries evaluated on the fly (plain C,
+                   ``vf_matfree.c``) and GMRES in place of LU
+* ``hlu``          hierarchical block LU of the reflection matrix (Sec. 5.1)
+                   and its forward / backward substitution (Sec. 5.2)
 
 Where the paper is silent the readings are fixed in the module docstrings.
 """
