@@ -352,7 +352,8 @@ def run_kernels_only(args):
         c, nrm, area = hm.hm_facets_from_triangles(cav.v, cav.tri, orient=1)
         t = hm.hm_build_cluster_tree(ctx, c, nrm, area, cav.leaf, cav.eta)
         # the product's work split tuned on 16-column products (the transient's width)
-        M = hm.hm_assemble_hmatrix(ctx, t, cav.aca_tol, 256, hm.HM_F32, hm.HM_F32, autotune=16)
+        M = hm.hm_assemble_hmatrix(ctx, t, cav.aca_tol, 256, hm.HM_F32, hm.HM_F32, autotune=16,
+                                   recompress=args.recompress)
         torch.cuda.synchronize()
         p16 = hm.hm_hmatvec_profile(ctx, M, 16, hm.HM_F32, reps=10, flush_bytes=0)
         log("16-rhs product x10:", p16)
@@ -368,7 +369,7 @@ def run_kernels_only(args):
         c, nrm, area = hm.hm_facets_from_triangles(cav.v, cav.tri, orient=1)
         trees.append(hm.hm_build_cluster_tree(ctx, c, nrm, area, cav.leaf, cav.eta))
     Mx = hm.hm_assemble_hmatrix_batched(ctx, trees, [cav.aca_tol for cav in cavs], 256, hm.HM_BF16, hm.HM_F32,
-                                        keep_f32_copy=1, autotune=1)
+                                        keep_f32_copy=1, autotune=1, recompress=args.recompress)
     torch.cuda.synchronize()
     ev = sum(m.stats()["entries_dense"] for m in Mx)
     log("assembled %d cavities (%d near-field entries)" % (len(Mx), ev))

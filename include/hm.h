@@ -347,6 +347,36 @@ hm_status hm_transient_run(hm_ctx* ctx, const hm_matrix* M, const double* eps, i
                            const hm_transient_params* tp, const hm_solve_params* sp, double* history,
                            hm_transient_info* info);
 
+/* --------------------------------------------------- hierarchical block LU */
+
+/* Sec. 5.1: the reflection matrix C = I - diag(1 - eps) F (eq. (11)) in the
+ * block structure of the tree (Algorithm 2), its admissible blocks
+ * compressed by ACA (params->aca_pivot) and truncated at params->aca_tol,
+ * factorised C ~ L U by the paper's four recursive steps (dense LU without
+ * row exchanges in the leaf blocks; forward substitution for the blocks
+ * right of the diagonal, backward substitution for those below it, the
+ * Schur complement update) with every addition into a low-rank block
+ * truncated at the relative accuracy aca_tol from its singular values.  All
+ * in FP64: params->lowrank_dtype and dense_dtype must be HM_F64
+ * (HM_EINVAL otherwise); keep_f32_copy, closed_row_scale, autotune and
+ * recompress are not used.  eps: DEVICE FP64 n, caller order, in (0, 1].
+ * Runs on ctx's stream and synchronises it; the tree may be destroyed
+ * afterwards. */
+typedef struct hm_hlu hm_hlu;
+hm_status hm_hlu_factor(hm_ctx* ctx, const hm_tree* tree, const double* eps, const hm_assembly_params* params,
+                        hm_hlu** out);
+/* Sec. 5.2: X = U^-1 (L^-1 B) ~ C^-1 B for nrhs right-hand sides (DEVICE
+ * FP64 n x nrhs, caller order, leading dimensions ldb, ldx >= n; X may be
+ * B).  No further approximation beyond the factors.  Synchronises ctx's
+ * stream. */
+hm_status hm_hlu_solve(hm_ctx* ctx, const hm_hlu* lu, int32_t nrhs, const double* B, int64_t ldb, double* X,
+                       int64_t ldx);
+/* Device bytes and stored entries of the factors, their largest rank and the
+ * factorisation's wall time in seconds (any pointer may be NULL). */
+hm_status hm_hlu_stats(const hm_hlu* lu, int64_t* bytes_device, int64_t* entries, int32_t* max_rank,
+                       double* factor_seconds);
+void hm_hlu_destroy(hm_hlu* lu);
+
 /* ------------------------------------------------------------- serving */
 
 typedef struct {

@@ -727,6 +727,52 @@ hm_status hm_solve_radiosity_batched(hm_ctx* ctx, int32_t count, const hm_matrix
   return st;
 }
 
+hm_status hm_hlu_factor(hm_ctx* ctx, const hm_tree* tree, const double* eps, const hm_assembly_params* p,
+                        hm_hlu** out) {
+  if (!ctx) {
+    set_tl_error("hm_hlu_factor: NULL ctx");
+    return HM_EINVAL;
+  }
+  return guarded(ctx, [&] {
+    HM_REQUIRE(tree && eps && p && out, "hm_hlu_factor: NULL argument");
+    check_assembly_params(p, "hm_hlu_factor");
+    HM_REQUIRE(p->lowrank_dtype == HM_F64 && p->dense_dtype == HM_F64,
+               "hm_hlu_factor: the block LU runs in FP64 (lowrank_dtype and dense_dtype HM_F64)");
+    check_device_range(*ctx, eps, tree->n, tree->n, 1, 0.0, 1.0, true, "hm_hlu_factor: eps");
+    *out = hlu_factor(*ctx, *tree, eps, *p);
+  });
+}
+
+hm_status hm_hlu_solve(hm_ctx* ctx, const hm_hlu* lu, int32_t nrhs, const double* B, int64_t ldb, double* X,
+                       int64_t ldx) {
+  if (!ctx) {
+    set_tl_error("hm_hlu_solve: NULL ctx");
+    return HM_EINVAL;
+  }
+  return guarded(ctx, [&] {
+    HM_REQUIRE(lu && B && X, "hm_hlu_solve: NULL argument");
+    HM_REQUIRE(nrhs >= 1 && nrhs <= 65535, "hm_hlu_solve: nrhs must be in 1..65535");
+    HM_REQUIRE(ldb >= hlu_rows(*lu) && ldx >= hlu_rows(*lu), "hm_hlu_solve: leading dimension smaller than n");
+    HM_REQUIRE(hlu_device(*lu) == ctx->device, "hm_hlu_solve: factors and context on different devices");
+    hlu_solve(*ctx, *lu, nrhs, B, ldb, X, ldx);
+  });
+}
+
+hm_status hm_hlu_stats(const hm_hlu* lu, int64_t* bytes_device, int64_t* entries, int32_t* max_rank,
+                       double* factor_seconds) {
+  if (!lu) {
+    set_tl_error("hm_hlu_stats: NULL factors");
+    return HM_EINVAL;
+  }
+  hlu_stats(*lu, bytes_device, entries, max_rank, factor_seconds);
+  return HM_OK;
+}
+
+void hm_hlu_destroy(hm_hlu* lu) {
+  if (!lu) return;
+  hlu_destroy(lu);
+}
+
 hm_status hm_transient_run(hm_ctx* ctx, const hm_matrix* M, const double* eps, int32_t nrhs, double* T, int64_t ldT,
                            const double* src, int64_t ldS, double sigma, const hm_transient_params* tp,
                            const hm_solve_params* sp, double* history, hm_transient_info* info) {

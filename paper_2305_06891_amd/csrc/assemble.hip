@@ -1022,4 +1022,189 @@ void closed_row_scale(hm_matrix& M, hipStream_t s) {
   HM_HIP(hipStreamSynchronize(s));
 }
 
+
+// ------------------------------------------------------------------ per-block factors for the block LU
+namespace {
+// Dense block of the reflection matrix C = I - diag(1 - eps) F (eq. (11)):
+// D(i, j) = -om_i F(r0 + i, c0 + j), plus 1 on the diagonal of a diagonal
+// block (F_ii = 0); column-major m x n.
+__global__ void k_reflect_dense(Geo g, int32_t r0, int32_t c0, int32_t m, int32_t n, const double* __restrict__ om,
+                                int diag, double* __restrict__ D) {
+  const int64_t mn = (int64_t)m * n;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < mn; e += (int64_t)gridDim.x * blockDim.x) {
+    const int i = (int)(e % m), j = (int)(e / m);
+    double v = -om[r0 + i] * view_factor(g, r0 + i, c0 + j);
+    if (diag && i == j) v += 1.0;
+    D[e] = v;
+  }
+}
+
+// U(i, l) <- -om[r0 + i] U(i, l): the row scaling of C applied to a low-rank factor
+__global__ void k_reflect_rows(double* __restrict__ U, int32_t m, int32_t k, const double* __restrict__ om,
+                               int32_t r0) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < (int64_t)m * k) U[e] = -om[r0 + (int)(e % m)] * U[e];
+}
+}  // namespace
+
+// Blocks of the reflection matrix for the block LU (Sec. 5.1): every listed
+// block (permuted positions) is either a dense block of C (dense[i] = 1 on
+// input: evaluated in full) or an admissible block compressed by ACA with
+// the parameters' pivoting and recompressed at aca_tol, its U rows scaled by
+// -(1 - eps); an admissible block that ACA stores dense (cap reached, or
+// k (m + n) >= m n) comes back dense.  om = 1 - eps in the permuted order
+// (DEVICE).  FP64 throughout.
+void reflection_blocks(hm_ctx& ctx, const hm_tree& t, const double* om, const std::vector<BlockRef>& blocks,
+                       std::vector<uint8_t>& dense, const hm_assembly_params& p, std::vector<BlockFactor>& out) {
+  hipStream_t s = ctx.stream;
+  const int64_t n = t.n;
+  std::vector<double> geo(7 * std::max<int64_t>(1, n));
+  for (int64_t k = 0; k < n; ++k) {
+    const int64_t o = t.perm[k];
+    for (int a = 0; a < 3; ++a) {
+      geo[a * n + k] = t.c[3 * o + a];
+      geo[(3 + a) * n + k] = t.nrm[3 * o + a];
+    }
+    geo[6 * n + k] = t.area[o];
+  }
+  DevBuf d_geo;
+  upload(d_geo, geo, s);
+  const double* gp = d_geo.get<double>();
+  const Geo g{gp, gp + n, gp + 2 * n, gp + 3 * n, gp + 4 * n, gp + 5 * n, gp + 6 * n};
+  out.clear();
+  out.resize(blocks.size());
+  // ACA of the admissible blocks, in batches bounded by a scratch budget
+  std::vector<size_t> adm;
+  for (size_t q = 0; q < blocks.size(); ++q)
+    if (!dense[q]) adm.push_back(q);
+  const int64_t budget = (int64_t)1 << 30;
+  size_t pos = 0;
+  DevBuf scratch, flags, d_blk, d_rank, d_status, d_nr, d_cd;
+  while (pos < adm.size()) {
+    std::vector<AcaDev> batch;
+    std::vector<size_t> who;
+    int64_t sd = 0, sf = 0;
+    while (pos < adm.size()) {
+      const BlockRef& b = blocks[adm[pos]];
+      const int m = b.re - b.rb, nn = b.ce - b.cb;
+      const int64_t kc = rank_cap(m, nn, std::min<int>(p.k_max, ACA_KMAX));
+      const int64_t rsz = p.aca_pivot == 1 ? (int64_t)m * nn : 0;
+      HM_REQUIRE(rsz < ((int64_t)1 << 31), "block LU: full pivoting needs blocks of fewer than 2^31 entries");
+      const int64_t need = (kc * (m + nn) + rsz) * 8 + m * 4;
+      if (!batch.empty() && sd * 8 + sf * 4 + need > budget) break;
+      batch.push_back(AcaDev{b.rb, b.re, b.cb, b.ce, (int32_t)kc, (int32_t)batch.size(), sd, sd + kc * m, sf,
+                             sd + kc * (m + nn), p.aca_tol});
+      who.push_back(adm[pos]);
+      sd += kc * (m + nn) + rsz;
+      sf += m;
+      ++pos;
+    }
+    if ((size_t)sd * 8 > scratch.bytes()) scratch.alloc((size_t)sd * 8);
+    if ((size_t)sf * 4 > flags.bytes()) flags.alloc((size_t)sf * 4);
+    d_rank.alloc(batch.size() * 4);
+    d_status.alloc(batch.size() * 4);
+    std::vector<AcaDev> small, large;
+    for (const AcaDev& a : batch) {
+      if (p.aca_pivot != 1 && a.re - a.rb <= 64 && a.ce - a.cb <= 64 && a.kcap <= ACAW_K) small.push_back(a);
+      else large.push_back(a);
+    }
+    DevBuf d_small;
+    if (!large.empty()) {
+      upload(d_blk, large, s);
+      if (p.aca_pivot == 1)
+        hipLaunchKernelGGL(k_aca_full<ACA_T>, dim3((unsigned)large.size()), dim3(ACA_T), 0, s, d_blk.get<AcaDev>(),
+                           g, scratch.get<double>(), d_rank.get<int>(), d_status.get<int>());
+      else
+        hipLaunchKernelGGL(k_aca<ACA_T>, dim3((unsigned)large.size()), dim3(ACA_T), 0, s, d_blk.get<AcaDev>(), g,
+                           scratch.get<double>(), flags.get<int>(), d_rank.get<int>(), d_status.get<int>());
+      HM_HIP(hipGetLastError());
+    }
+    if (!small.empty()) {
+      upload(d_small, small, s);
+      hipLaunchKernelGGL(k_aca_wave, dim3((unsigned)((small.size() + 3) / 4)), dim3(256), 0, s,
+                         d_small.get<AcaDev>(), (int)small.size(), g, scratch.get<double>(), d_rank.get<int>(),
+                         d_status.get<int>());
+      HM_HIP(hipGetLastError());
+    }
+    std::vector<int> rk(batch.size()), st(batch.size());
+    HM_HIP(hipMemcpyAsync(rk.data(), d_rank.get(), rk.size() * 4, hipMemcpyDeviceToHost, s));
+    HM_HIP(hipMemcpyAsync(st.data(), d_status.get(), st.size() * 4, hipMemcpyDeviceToHost, s));
+    HM_HIP(hipStreamSynchronize(s));
+    // low-rank blocks: recompressed (rank >= 2) or copied (rank 1) into an FP64 stage
+    std::vector<RcDev> rc;
+    std::vector<CompactDev> cd;
+    std::vector<size_t> rc_q, cd_q;
+    int64_t off = 0;
+    for (size_t q = 0; q < batch.size(); ++q) {
+      const AcaDev& a = batch[q];
+      const int m = a.re - a.rb, nn = a.ce - a.cb, k = rk[q];
+      if (!st[q] || (int64_t)k * (m + nn) >= (int64_t)m * nn) {
+        dense[who[q]] = 1;
+        continue;
+      }
+      out[who[q]].lowrank = true;
+      out[who[q]].k = k;
+      if (k >= 2 && k <= RC_KMAX) {
+        rc.push_back(RcDev{a.u_off, a.v_off, 0, off, off + (int64_t)m * k, m, nn, k, (int32_t)rc.size(), a.tol});
+        rc_q.push_back(q);
+      } else if (k >= 1) {
+        cd.push_back(CompactDev{a.u_off, a.v_off, off, off + (int64_t)m * k, m, nn, k, 0});
+        cd_q.push_back(q);
+      }
+      out[who[q]].su = off;
+      out[who[q]].sv = off + (int64_t)m * k;
+      off += (int64_t)k * (m + nn);
+    }
+    DevBuf stage(std::max<int64_t>(1, off) * 8);
+    if (!cd.empty()) {
+      upload(d_cd, cd, s);
+      hipLaunchKernelGGL(k_compact<double>, dim3((unsigned)cd.size()), dim3(256), 0, s, d_cd.get<CompactDev>(),
+                         scratch.get<double>(), stage.get<double>());
+      HM_HIP(hipGetLastError());
+    }
+    if (!rc.empty()) {
+      d_nr.alloc(rc.size() * 4);
+      recompress_blocks(rc, scratch.get<double>(), stage.get(), true, d_nr.get<int>(), s);
+      std::vector<int> nr(rc.size());
+      HM_HIP(hipMemcpyAsync(nr.data(), d_nr.get(), nr.size() * 4, hipMemcpyDeviceToHost, s));
+      HM_HIP(hipStreamSynchronize(s));
+      for (size_t q = 0; q < rc.size(); ++q) out[who[rc_q[q]]].k = nr[q];
+    }
+    // each block's factors into buffers of its own (U m x k, V n x k, the
+    // row scaling of C on U)
+    for (size_t q = 0; q < batch.size(); ++q) {
+      BlockFactor& f = out[who[q]];
+      if (!f.lowrank || dense[who[q]]) continue;
+      const AcaDev& a = batch[q];
+      const int m = a.re - a.rb, nn = a.ce - a.cb;
+      f.U.alloc(std::max<int64_t>(1, (int64_t)m * f.k) * 8);
+      f.V.alloc(std::max<int64_t>(1, (int64_t)nn * f.k) * 8);
+      if (f.k > 0) {
+        HM_HIP(hipMemcpyAsync(f.U.get(), stage.get<double>() + f.su, (size_t)m * f.k * 8, hipMemcpyDeviceToDevice, s));
+        HM_HIP(hipMemcpyAsync(f.V.get(), stage.get<double>() + f.sv, (size_t)nn * f.k * 8, hipMemcpyDeviceToDevice, s));
+        const int64_t e = (int64_t)m * f.k;
+        hipLaunchKernelGGL(k_reflect_rows, dim3((unsigned)((e + 255) / 256)), dim3(256), 0, s, f.U.get<double>(), m,
+                           f.k, om, a.rb);
+        HM_HIP(hipGetLastError());
+      }
+    }
+    HM_HIP(hipStreamSynchronize(s));
+  }
+  // dense blocks of C
+  for (size_t q = 0; q < blocks.size(); ++q) {
+    if (!dense[q]) continue;
+    const BlockRef& b = blocks[q];
+    const int m = b.re - b.rb, nn = b.ce - b.cb;
+    BlockFactor& f = out[q];
+    f.lowrank = false;
+    f.D.alloc((size_t)m * nn * 8);
+    const int64_t e = (int64_t)m * nn;
+    const unsigned gr = (unsigned)std::min<int64_t>(4096, (e + 255) / 256);
+    hipLaunchKernelGGL(k_reflect_dense, dim3(gr), dim3(256), 0, s, g, b.rb, b.cb, m, nn, om,
+                       b.rb == b.cb && b.re == b.ce ? 1 : 0, f.D.get<double>());
+    HM_HIP(hipGetLastError());
+  }
+  HM_HIP(hipStreamSynchronize(s));
+}
+
 }  // namespace hm

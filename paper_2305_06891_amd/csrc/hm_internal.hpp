@@ -136,6 +136,8 @@ struct hm_tree {
 namespace hm {
 
 void build_tree(hm_tree& t);  // fills perm, nodes, leaves, dense, lowrank from c, params
+// The admissibility condition of Algorithm 2 (eq. (28) on the bounding boxes).
+bool tree_admissible(const ClusterNode& s, const ClusterNode& t, double eta);
 
 // ---------------------------------------------------------------- matvec plan
 // Both phases stream panels laid out so that every lane loads 16 contiguous
@@ -371,6 +373,25 @@ struct LrInfo {
   int32_t stage;         // stage buffer holding the FP32/FP64 factors
   int64_t su, sv;        // element offsets of U_b (m x k) and V_b (n x k), column-major
 };
+
+// ---------------------------------------------------------------- block LU support
+// One block of the reflection matrix for the block LU: dense (D, m x n) or
+// low-rank (U m x k, V n x k), FP64, column-major.
+struct BlockFactor {
+  bool lowrank = false;
+  int32_t k = 0;
+  int64_t su = 0, sv = 0;  // staging offsets (internal to reflection_blocks)
+  DevBuf D, U, V;
+};
+void reflection_blocks(hm_ctx& ctx, const hm_tree& t, const double* om, const std::vector<BlockRef>& blocks,
+                       std::vector<uint8_t>& dense, const hm_assembly_params& p, std::vector<BlockFactor>& out);
+
+hm_hlu* hlu_factor(hm_ctx& ctx, const hm_tree& t, const double* eps, const hm_assembly_params& p);
+void hlu_solve(hm_ctx& ctx, const hm_hlu& H, int nrhs, const double* B, int64_t ldb, double* X, int64_t ldx);
+void hlu_stats(const hm_hlu& H, int64_t* bytes, int64_t* entries, int32_t* max_rank, double* seconds);
+int64_t hlu_rows(const hm_hlu& H);
+int hlu_device(const hm_hlu& H);
+void hlu_destroy(hm_hlu* H);  // waits for the device, then frees
 
 // ---------------------------------------------------------------- misc helpers
 const char* tl_error();

@@ -82,6 +82,8 @@ bool admissible(const ClusterNode& s, const ClusterNode& t, double eta) {
 
 }  // namespace
 
+bool tree_admissible(const ClusterNode& s, const ClusterNode& t, double eta) { return admissible(s, t, eta); }
+
 void build_tree(hm_tree& t) {
   const int64_t n = t.n;
   t.nodes.clear();

@@ -42,6 +42,7 @@ constexpr int RC_ROWS = 16;               // panel rows staged per Gram pass
 constexpr int RC_SWEEPS = 40;             // Jacobi sweep limit
 constexpr double RC_DROP = 1e-16;         // pivoted Cholesky stop (unit diagonal)
 constexpr double RC_JTOL = 1e-13;         // Jacobi: |g| <= RC_JTOL sqrt(a b) counts as orthogonal
+constexpr double RC_JNOISE = 1e-15;       // ... and so does |g| <= RC_JNOISE max(a, b)
 
 struct RcMax {
   double mag;
@@ -102,7 +103,7 @@ __device__ void rc_colnorms(const double* __restrict__ P, int len, int k, double
 // upper triangle, one per thread per pass, over rows staged RC_ROWS at a
 // time in LDS; both triangles of G (ld k) are written.
 __device__ void rc_gram(const double* __restrict__ P, int len, int k, const double* __restrict__ inv,
-                        double* __restrict__ G, double* __restrict__ stage) {
+                        double* __restrict__ G, double* __restrict__ stage, int sst) {
   const int nt = (k + 3) / 4, kc = 4 * nt;
   const int ntiles = nt * (nt + 1) / 2;
   for (int t0 = 0; t0 < ntiles; t0 += RC_T) {
@@ -127,12 +128,12 @@ __device__ void rc_gram(const double* __restrict__ P, int len, int k, const doub
       __syncthreads();
       for (int e = threadIdx.x; e < RC_ROWS * kc; e += RC_T) {
         const int c = e / RC_ROWS, r = e % RC_ROWS;
-        stage[r * RC_KMAX + c] = (r < rows && c < k) ? P[(int64_t)c * len + i0 + r] * inv[c] : 0.0;
+        stage[r * sst + c] = (r < rows && c < k) ? P[(int64_t)c * len + i0 + r] * inv[c] : 0.0;
       }
       __syncthreads();
       if (have)
         for (int r = 0; r < rows; ++r) {
-          const double* row = stage + r * RC_KMAX;
+          const double* row = stage + r * sst;
           double x[4], y[4];
 #pragma unroll
           for (int a = 0; a < 4; ++a) {
@@ -163,8 +164,12 @@ __device__ void rc_gram(const double* __restrict__ P, int len, int k, const doub
 // Pivoted Cholesky of the k x k Gram matrix G: rows s of R (ld k, all k
 // columns; zero at the columns selected before step s), sel[s] = column of
 // step s.  Returns the number of steps (the numerical rank).
+// With weights w (the early mode), the step takes the column of largest
+// w_j^2 d_j and the steps stop once sum_j w_j sqrt(d_j) over the columns not
+// taken is at most lim.
 __device__ int rc_pchol(const double* __restrict__ G, int k, double* __restrict__ R, int* __restrict__ sel,
-                        double* __restrict__ d, int* __restrict__ taken, RcMax* sh) {
+                        double* __restrict__ d, int* __restrict__ taken, RcMax* sh, const double* __restrict__ w,
+                        double lim, double* sh_sum) {
   for (int j = threadIdx.x; j < k; j += RC_T) {
     d[j] = G[(int64_t)j * k + j];
     taken[j] = 0;
@@ -173,12 +178,18 @@ __device__ int rc_pchol(const double* __restrict__ G, int k, double* __restrict_
   int rr = 0;
   for (int s = 0; s < k; ++s) {
     RcMax am{-1.0, INT_MAX};
+    double rest = 0.0;
     for (int j = threadIdx.x; j < k; j += RC_T)
-      if (!taken[j]) am = rc_better(am, RcMax{d[j], j});
+      if (!taken[j]) {
+        am = rc_better(am, RcMax{w ? w[j] * w[j] * d[j] : d[j], j});
+        if (w) rest += w[j] * sqrt(fmax(d[j], 0.0));
+      }
     am = rc_block_max(am, sh);
-    if (am.idx == INT_MAX || !(am.mag > RC_DROP)) break;
+    if (w && rc_block_sum(rest, sh_sum) <= lim) break;
+    if (am.idx == INT_MAX) break;
     const int p = am.idx;
-    const double rpp = sqrt(am.mag);
+    if (!(d[p] > RC_DROP)) break;
+    const double rpp = sqrt(d[p]);
     for (int j = threadIdx.x; j < k; j += RC_T) {
       double v;
       if (j == p) {
@@ -220,23 +231,21 @@ __device__ void rc_backsub(const double* __restrict__ R, int k, const int* __res
 
 int64_t recompress_work_doubles(int k) { return 8 * (int64_t)k * k; }
 
-// Ranks and transforms of one chunk of blocks.  Workspace per block
-// (doubles, ld k): Gu | Ru | Gv | Rv | K | Z | Tu | Tv.
-__global__ __launch_bounds__(RC_T) void k_recompress(const RcDev* __restrict__ blocks, const double* __restrict__ scratch,
-                                                     double* __restrict__ work, int* __restrict__ newrank) {
-  __shared__ double stage[RC_ROWS * RC_KMAX];
-  __shared__ double ia[RC_KMAX], ib[RC_KMAX], dd[RC_KMAX], sig[RC_KMAX];
-  __shared__ int selu[RC_KMAX], selv[RC_KMAX], taken[RC_KMAX], order[RC_KMAX];
-  __shared__ RcMax sh_max[RC_W];
-  __shared__ double sh_sum[RC_W];
-  __shared__ int sh_rot;
-  const RcDev b = blocks[blockIdx.x];
+namespace {
+
+// The steps 1-6 for one block.  Work arrays (k x k, ld k) may be in LDS or
+// in the global workspace: Gu and Gv (Gram matrices), Ru and Rv (Cholesky
+// rows), K (core, rotated in place), Z (rotations); Gv may share Gu's
+// storage and K Gu's, Z may share Ru's when Ru_keep is a copy of its own;
+// ytmp, ztmp, Tu, Tv are global.
+__device__ void rc_core(const RcDev& b, const double* __restrict__ scratch, int* __restrict__ newrank,
+                        double* stage, int sst, double* Gu, double* Ru, double* Gv, double* Rv, double* K, double* Z,
+                        double* Ru_keep, double* ytmp, double* ztmp, double* Tu, double* Tv, double* ia, double* ib,
+                        double* dd, double* sig, int* selu, int* selv, int* taken, int* order, RcMax* sh_max,
+                        double* sh_sum, int* sh_rot) {
   const int m = b.m, n = b.n, k = b.k;
   const double* U = scratch + b.u_off;
   const double* V = scratch + b.v_off;
-  double* W = work + b.w_off;
-  double *Gu = W, *Ru = W + k * k, *Gv = W + 2 * k * k, *Rv = W + 3 * k * k;
-  double *K = W + 4 * k * k, *Z = W + 5 * k * k, *Tu = W + 6 * k * k, *Tv = W + 7 * k * k;
   const int tid = threadIdx.x;
 
   // 1. column scales (a zero column gets scale 0 and drops out)
@@ -251,10 +260,22 @@ __global__ __launch_bounds__(RC_T) void k_recompress(const RcDev* __restrict__ b
   }
   __syncthreads();
   // 2-3. Gram matrices and their pivoted Cholesky factors
-  rc_gram(U, m, k, ia, Gu, stage);
-  rc_gram(V, n, k, ib, Gv, stage);
-  const int ru = rc_pchol(Gu, k, Ru, selu, sig, taken, sh_max);
-  const int rv = rc_pchol(Gv, k, Rv, selv, sig, taken, sh_max);
+  rc_gram(U, m, k, ia, Gu, stage, sst);
+  double lim = 0.0;
+  if (b.early) {
+    // |U V^T|_F^2 = sum_{l,l'} d_l d_l' Gu(l,l') Gv(l,l') (Gu, Gv of the unit columns)
+    rc_gram(V, n, k, ib, Gv, stage, sst);
+    double x2 = 0.0;
+    for (int e = tid; e < k * k; e += RC_T) {
+      const int l = e % k, l2 = e / k;
+      x2 += dd[l] * dd[l2] * Gu[e] * Gv[e];
+    }
+    x2 = rc_block_sum(x2, sh_sum);
+    lim = RC_EARLY * b.tol * sqrt(fmax(x2, 0.0));
+  }
+  const int ru = rc_pchol(Gu, k, Ru, selu, sig, taken, sh_max, b.early ? dd : nullptr, lim, sh_sum);
+  if (!b.early) rc_gram(V, n, k, ib, Gv, stage, sst);
+  const int rv = rc_pchol(Gv, k, Rv, selv, sig, taken, sh_max, b.early ? dd : nullptr, lim, sh_sum);
   // 4. K = Ru D Rv^T (ru x rv, column t at K + t k), Z = I (rv x rv)
   for (int e = tid; e < ru * rv; e += RC_T) {
     const int s = e % ru, t = e / ru;
@@ -262,6 +283,11 @@ __global__ __launch_bounds__(RC_T) void k_recompress(const RcDev* __restrict__ b
     for (int l = 0; l < k; ++l) x += Ru[(int64_t)s * k + l] * dd[l] * Rv[(int64_t)t * k + l];
     K[(int64_t)t * k + s] = x;
   }
+  __syncthreads();
+  // Ru is kept where the back substitutions read it (Z may take its place)
+  if (Ru_keep != Ru)
+    for (int e = tid; e < ru * k; e += RC_T) Ru_keep[e] = Ru[e];
+  __syncthreads();
   for (int e = tid; e < rv * rv; e += RC_T) Z[(int64_t)(e / rv) * k + e % rv] = (e / rv == e % rv) ? 1.0 : 0.0;
   __syncthreads();
   // one-sided Jacobi on the columns of K: round-robin pairs over np
@@ -269,7 +295,7 @@ __global__ __launch_bounds__(RC_T) void k_recompress(const RcDev* __restrict__ b
   const int np = (rv + 1) & ~1;
   const int g = tid / RC_LP, gl = tid % RC_LP;
   for (int sweep = 0; sweep < RC_SWEEPS && np >= 2; ++sweep) {
-    if (tid == 0) sh_rot = 0;
+    if (tid == 0) *sh_rot = 0;
     __syncthreads();
     int rotated = 0;
     for (int step = 0; step < np - 1; ++step) {
@@ -294,7 +320,10 @@ __global__ __launch_bounds__(RC_T) void k_recompress(const RcDev* __restrict__ b
         al = grp_sum(al);
         be = grp_sum(be);
         ga = grp_sum(ga);
-        if (ga != 0.0 && fabs(ga) > RC_JTOL * sqrt(al * be)) {
+        // a pair counts as orthogonal when |g| is below RC_JTOL of sqrt(a b),
+        // or at rounding level of the larger column (a column of negligible
+        // norm against a large one would otherwise keep rotating on noise)
+        if (ga != 0.0 && fabs(ga) > RC_JTOL * sqrt(al * be) && fabs(ga) > RC_JNOISE * fmax(al, be)) {
           const double zeta = (be - al) / (2.0 * ga);
           const double tt = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
           const double c = 1.0 / sqrt(1.0 + tt * tt), sn = c * tt;
@@ -315,9 +344,9 @@ __global__ __launch_bounds__(RC_T) void k_recompress(const RcDev* __restrict__ b
       }
       __syncthreads();
     }
-    if (rotated) atomicOr(&sh_rot, 1);
+    if (rotated) atomicOr(sh_rot, 1);
     __syncthreads();
-    const int any = sh_rot;
+    const int any = *sh_rot;
     __syncthreads();
     if (!any) break;
   }
@@ -352,9 +381,9 @@ __global__ __launch_bounds__(RC_T) void k_recompress(const RcDev* __restrict__ b
   } else if (tid == 0) {
     newrank[b.out] = 0;
   }
-  if (tid == 0) sh_rot = r;
+  if (tid == 0) *sh_rot = r;
   __syncthreads();
-  r = sh_rot;
+  r = *sh_rot;
   // 6. Tu (k x r) and Tv (k x r): back substitutions on the selected rows
   for (int c = tid; c < r; c += RC_T) {
     const int t = order[c];
@@ -362,15 +391,57 @@ __global__ __launch_bounds__(RC_T) void k_recompress(const RcDev* __restrict__ b
     double* tv = Tv + (int64_t)c * k;
     for (int l = 0; l < k; ++l) tu[l] = tv[l] = 0.0;
     // y (in the first ru entries of the column, then moved to the rows sel)
-    double* y = Gu + (int64_t)c * k;  // Gu is free now: scratch column per rank
+    double* y = ytmp + (int64_t)c * k;  // one scratch column per rank
     for (int s = 0; s < ru; ++s) y[s] = K[(int64_t)t * k + s];
-    rc_backsub(Ru, k, selu, ru, y);
+    rc_backsub(Ru_keep, k, selu, ru, y);
     for (int s = 0; s < ru; ++s) tu[selu[s]] = y[s] * ia[selu[s]];
-    double* z = Gv + (int64_t)c * k;
+    double* z = ztmp + (int64_t)c * k;
     for (int s = 0; s < rv; ++s) z[s] = Z[(int64_t)t * k + s];
     rc_backsub(Rv, k, selv, rv, z);
     for (int s = 0; s < rv; ++s) tv[selv[s]] = z[s] * ib[selv[s]];
   }
+}
+
+}  // namespace
+
+// Ranks and transforms of one chunk of blocks, work arrays in the global
+// workspace (any rank up to RC_KMAX).  Workspace per block (doubles, ld k):
+// Gu | Ru | Gv | Rv | K | Z | Tu | Tv.
+__global__ __launch_bounds__(RC_T) void k_recompress(const RcDev* __restrict__ blocks, const double* __restrict__ scratch,
+                                                     double* __restrict__ work, int* __restrict__ newrank) {
+  __shared__ double stage[RC_ROWS * RC_KMAX];
+  __shared__ double ia[RC_KMAX], ib[RC_KMAX], dd[RC_KMAX], sig[RC_KMAX];
+  __shared__ int selu[RC_KMAX], selv[RC_KMAX], taken[RC_KMAX], order[RC_KMAX];
+  __shared__ RcMax sh_max[RC_W];
+  __shared__ double sh_sum[RC_W];
+  __shared__ int sh_rot;
+  const RcDev b = blocks[blockIdx.x];
+  const int64_t kk = (int64_t)b.k * b.k;
+  double* W = work + b.w_off;
+  rc_core(b, scratch, newrank, stage, RC_KMAX, W, W + kk, W + 2 * kk, W + 3 * kk, W + 4 * kk, W + 5 * kk, W + kk, W,
+          W + 2 * kk, W + 6 * kk, W + 7 * kk, ia, ib, dd, sig, selu, selv, taken, order, sh_max, sh_sum, &sh_rot);
+}
+
+// The same for blocks of rank up to KM with the k x k arrays in LDS (three
+// KM x KM areas: A holds Gu, then Gv, then K; B holds Ru, then Z; C holds
+// Rv); Ru is copied to the workspace before Z overwrites it.  The steps and
+// their order are those of k_recompress, so both give the same results.
+template <int KM>
+__global__ __launch_bounds__(RC_T) void k_recompress_lds(const RcDev* __restrict__ blocks,
+                                                         const double* __restrict__ scratch, double* __restrict__ work,
+                                                         int* __restrict__ newrank) {
+  __shared__ double stage[RC_ROWS * KM];
+  __shared__ double A[KM * KM], B[KM * KM], Cm[KM * KM];
+  __shared__ double ia[KM], ib[KM], dd[KM], sig[KM];
+  __shared__ int selu[KM], selv[KM], taken[KM], order[KM];
+  __shared__ RcMax sh_max[RC_W];
+  __shared__ double sh_sum[RC_W];
+  __shared__ int sh_rot;
+  const RcDev b = blocks[blockIdx.x];
+  const int64_t kk = (int64_t)b.k * b.k;
+  double* W = work + b.w_off;
+  rc_core(b, scratch, newrank, stage, KM, A, B, A, Cm, A, B, W + kk, W, W + 2 * kk, W + 6 * kk, W + 7 * kk, ia, ib,
+          dd, sig, selu, selv, taken, order, sh_max, sh_sum, &sh_rot);
 }
 
 // U' = U Tu and V' = V Tv into the staging buffer (m x r and n x r,
@@ -417,34 +488,51 @@ __global__ __launch_bounds__(RC_T) void k_recompress_apply(const RcDev* __restri
 void recompress_blocks(std::vector<RcDev>& blocks, const double* scratch, void* stage, bool stage_f64,
                        int* d_newrank, hipStream_t s) {
   if (blocks.empty()) return;
+  // blocks by rank: the LDS variants for ranks up to 16, 32 and 64, the
+  // global-workspace kernel above
+  std::vector<RcDev> bucket[4];
+  for (const RcDev& b : blocks) bucket[b.k <= 16 ? 0 : b.k <= 32 ? 1 : b.k <= 64 ? 2 : 3].push_back(b);
   // chunks bounded by a workspace budget (a block needs 8 k^2 doubles)
   const int64_t budget = (int64_t)256 << 20;
-  std::vector<size_t> starts;
-  int64_t used = budget;
-  for (size_t q = 0; q < blocks.size(); ++q) {
-    const int64_t need = recompress_work_doubles(blocks[q].k) * 8;
-    if (used + need > budget) {
-      starts.push_back(q);
-      used = 0;
-    }
-    blocks[q].w_off = used / 8;
-    used += need;
-  }
-  starts.push_back(blocks.size());
-  DevBuf d_blocks, work;
-  upload(d_blocks, blocks, s);
+  DevBuf work;
   work.alloc((size_t)budget);
-  for (size_t c = 0; c + 1 < starts.size(); ++c) {
-    const unsigned cnt = (unsigned)(starts[c + 1] - starts[c]);
-    const RcDev* bp = d_blocks.get<RcDev>() + starts[c];
-    hipLaunchKernelGGL(k_recompress, dim3(cnt), dim3(RC_T), 0, s, bp, scratch, work.get<double>(), d_newrank);
-    if (stage_f64)
-      hipLaunchKernelGGL(k_recompress_apply<double>, dim3(cnt), dim3(RC_T), 0, s, bp, scratch, work.get<double>(),
-                         (const int*)d_newrank, (double*)stage);
-    else
-      hipLaunchKernelGGL(k_recompress_apply<float>, dim3(cnt), dim3(RC_T), 0, s, bp, scratch, work.get<double>(),
-                         (const int*)d_newrank, (float*)stage);
-    HM_HIP(hipGetLastError());
+  std::vector<DevBuf> descs;
+  for (int v = 0; v < 4; ++v) {
+    std::vector<RcDev>& bl = bucket[v];
+    if (bl.empty()) continue;
+    std::vector<size_t> starts;
+    int64_t used = budget;
+    for (size_t q = 0; q < bl.size(); ++q) {
+      const int64_t need = recompress_work_doubles(bl[q].k) * 8;
+      if (used + need > budget) {
+        starts.push_back(q);
+        used = 0;
+      }
+      bl[q].w_off = used / 8;
+      used += need;
+    }
+    starts.push_back(bl.size());
+    descs.emplace_back();
+    upload(descs.back(), bl, s);
+    for (size_t c = 0; c + 1 < starts.size(); ++c) {
+      const unsigned cnt = (unsigned)(starts[c + 1] - starts[c]);
+      const RcDev* bp = descs.back().get<RcDev>() + starts[c];
+      if (v == 0)
+        hipLaunchKernelGGL(k_recompress_lds<16>, dim3(cnt), dim3(RC_T), 0, s, bp, scratch, work.get<double>(), d_newrank);
+      else if (v == 1)
+        hipLaunchKernelGGL(k_recompress_lds<32>, dim3(cnt), dim3(RC_T), 0, s, bp, scratch, work.get<double>(), d_newrank);
+      else if (v == 2)
+        hipLaunchKernelGGL(k_recompress_lds<64>, dim3(cnt), dim3(RC_T), 0, s, bp, scratch, work.get<double>(), d_newrank);
+      else
+        hipLaunchKernelGGL(k_recompress, dim3(cnt), dim3(RC_T), 0, s, bp, scratch, work.get<double>(), d_newrank);
+      if (stage_f64)
+        hipLaunchKernelGGL(k_recompress_apply<double>, dim3(cnt), dim3(RC_T), 0, s, bp, scratch, work.get<double>(),
+                           (const int*)d_newrank, (double*)stage);
+      else
+        hipLaunchKernelGGL(k_recompress_apply<float>, dim3(cnt), dim3(RC_T), 0, s, bp, scratch, work.get<double>(),
+                           (const int*)d_newrank, (float*)stage);
+      HM_HIP(hipGetLastError());
+    }
   }
   // the workspace and the descriptors are released when the work is done
   HM_HIP(hipStreamSynchronize(s));

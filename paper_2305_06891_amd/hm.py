@@ -119,6 +119,11 @@ _PROTOS = {
     "hm_transient_run": (C.c_int, [_vp, _vp, _vp, C.c_int32, _vp, C.c_int64, _vp, C.c_int64, C.c_double,
                                    C.POINTER(hm_transient_params), C.POINTER(hm_solve_params), _vp,
                                    C.POINTER(hm_transient_info)]),
+    "hm_hlu_factor": (C.c_int, [_vp, _vp, _vp, C.POINTER(hm_assembly_params), C.POINTER(_vp)]),
+    "hm_hlu_solve": (C.c_int, [_vp, _vp, C.c_int32, _vp, C.c_int64, _vp, C.c_int64]),
+    "hm_hlu_stats": (C.c_int, [_vp, C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.POINTER(C.c_int32),
+                               C.POINTER(C.c_double)]),
+    "hm_hlu_destroy": (None, [_vp]),
     "hm_server_create": (C.c_int, [_vp, C.POINTER(hm_server_params), C.POINTER(_vp)]),
     "hm_server_register_cavity": (C.c_int, [_vp, C.c_uint64, _vp, _dp, C.POINTER(hm_assembly_params)]),
     "hm_submit": (C.c_int, [_vp, C.c_uint64, C.c_int32, _dp, C.POINTER(C.c_uint64)]),
@@ -438,6 +443,51 @@ def hm_transient_run(ctx, M: HMatrix, eps, T, src, sigma=SIGMA, mc=1.0e4, dt=1.0
                                 C.byref(info)), ctx.handle)
     return T, {"steps_done": info.steps_done, "newton_total": info.newton_total, "newton_max": info.newton_max,
                "matvecs": info.matvecs, "seconds": info.seconds, "max_rel_residual": info.max_rel_residual}
+
+
+class HLU:
+    """Factors C ~ L U of the reflection matrix (``hm_hlu_factor``)."""
+
+    def __init__(self, h, ctx, n):
+        self._h = h
+        self.ctx = ctx
+        self.n = n
+
+    def solve(self, B, X=None):
+        """X = U^-1 (L^-1 B) for a device float64 tensor B (n or n x r)."""
+        import torch
+        if X is None:
+            X = torch.empty_like(B)
+        nr = 1 if B.dim() == 1 else B.shape[1]
+        _check(lib.hm_hlu_solve(self.ctx.handle, self._h, nr, _dev_ptr(B, torch.float64), _ld(B),
+                                _dev_ptr(X, torch.float64), _ld(X)), self.ctx.handle)
+        return X
+
+    def stats(self):
+        b, e, mr, sec = C.c_int64(), C.c_int64(), C.c_int32(), C.c_double()
+        _check(lib.hm_hlu_stats(self._h, C.byref(b), C.byref(e), C.byref(mr), C.byref(sec)))
+        return {"bytes_device": b.value, "entries": e.value, "max_rank": mr.value, "factor_seconds": sec.value}
+
+    def close(self):
+        if self._h:
+            lib.hm_hlu_destroy(self._h)
+            self._h = _vp()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def hm_hlu_factor(ctx, tree: Tree, eps, aca_tol=1e-6, k_max=256, aca_pivot=0) -> HLU:
+    """Hierarchical block LU of C = I - diag(1 - eps) F (eps: device float64,
+    caller order)."""
+    import torch
+    p = hm_assembly_params(float(aca_tol), int(k_max), HM_F64, HM_F64, 0, 0, 0, 0, int(aca_pivot))
+    h = _vp()
+    _check(lib.hm_hlu_factor(ctx.handle, tree._h, _dev_ptr(eps, torch.float64), C.byref(p), C.byref(h)), ctx.handle)
+    return HLU(h, ctx, tree.n)
 
 
 class Server:
