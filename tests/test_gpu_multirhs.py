@@ -8,7 +8,8 @@ column with FP32 vectors, 1e-13 with FP64 vectors (the stored entries widen
 exactly, so only the summation order differs).  The matrices are large
 enough for column clusters split into row chunks (partial sums), and the
 cases cover FP32 and BF16 factors, 16 and 12 columns, and a fused epilogue
-(alpha, beta).
+(alpha, beta).  The 16-column product is also compared with the oracle's
+H-matrix whose entries are rounded to the same storage types.
 """
 import numpy as np
 import pytest
@@ -78,4 +79,49 @@ def test_sixteen_rhs_on_small_tiles(hm, ctx):
             yj = to_np(hm.hm_hmatvec(ctx, M, Xt[:, j].contiguous(), torch.zeros(n, dtype=tdt, device="cuda")))
             worst = max(worst, rel(Y[:, j], yj))
         log("%s: worst column rel diff vs one-column %.2e" % (tdt, worst))
+        assert worst <= tol
+
+
+def _stored_oracle_product(v, f, lr, X):
+    """The oracle's H-matrix (same tree, partial-pivot ACA at 1e-6) with its
+    entries rounded as the library stores them (near field FP64 -> FP32;
+    factors FP64 -> FP32, then -> BF16 by round-to-nearest-even for BF16
+    storage), applied to X in FP64."""
+    import torch
+    from oracle import aca, geometry
+    c, nr, a = geometry.facets_from_triangles(v, f)
+    H = aca.build_hmatrix(c, nr, a, 64, 1.5, 1e-6)
+
+    def st(A):
+        A32 = np.asarray(A, dtype=np.float32)
+        if lr == "bf16":
+            return torch.from_numpy(A32).to(torch.bfloat16).to(torch.float64).numpy()
+        return A32.astype(np.float64)
+
+    H.dense = [(r0, r1, c0, c1, np.asarray(B, dtype=np.float32).astype(np.float64)) for r0, r1, c0, c1, B in H.dense]
+    H.lowrank = [(r0, r1, c0, c1, st(U), st(V)) for r0, r1, c0, c1, U, V in H.lowrank]
+    return H.matvec(X)
+
+
+@pytest.mark.parametrize("lr", ["f32", "bf16"])
+def test_sixteen_rhs_product_matches_the_oracle(hm, ctx, lr):
+    """The 16-column matrix-core product against the oracle's H-matrix with
+    the same storage rounding: the library's ACA takes the oracle's steps in
+    FP64 and rounds its entries the same way, so with FP64 vectors only the
+    summation order differs (relative 1e-12 per column); with FP32 vectors
+    the FP32 sums add 2e-6."""
+    import torch
+    v, f = meshes.ellipsoid(18, (4.0, 2.0, 1.0))
+    f = meshes.inward(f)
+    n = f.shape[0]
+    lrt = hm.HM_F32 if lr == "f32" else hm.HM_BF16
+    tree, M = build(hm, ctx, v, f, 64, 1.5, 1e-6, lrt, hm.HM_F32, keep=0)
+    log("case: ellipsoid %d facets, %s factors, 16 columns against the oracle's stored H-matrix" % (n, lr))
+    X = np.random.default_rng(29).uniform(0.5, 1.5, (n, 16))
+    Yo = _stored_oracle_product(v, f, lr, X)
+    for tdt, tol in ((torch.float64, 1e-12), (torch.float32, 2e-6)):
+        Xt = torch.as_tensor(np.asfortranarray(X), dtype=tdt, device="cuda")
+        Y = to_np(hm.hm_hmatvec(ctx, M, Xt, torch.zeros_like(Xt)))
+        worst = max(rel(Y[:, j], Yo[:, j]) for j in range(16))
+        log("%s vectors: worst column rel diff vs the oracle %.2e" % (tdt, worst))
         assert worst <= tol
