@@ -37,6 +37,7 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 METRIC = "H-matvec % HBM peak; radiosity solves/s vs plain FP32 H-solve at 1e-6 rel err"
 RTOL = 1e-7            # residual target; with cond(C) ~ 5 a solve error below 1e-6
+IR_INNER = 2e-4        # inner tolerance of each refinement step (2 outer steps on the 64-cavity batch)
 
 
 def log(*a):
@@ -175,7 +176,7 @@ def run_c3(args):
     # launches, one product split tuned on the batch)
     rc = args.recompress
     Mx = hm.hm_assemble_hmatrix_batched(ctx, trees, [cav.aca_tol for cav in cavs], 256, hm.HM_BF16, hm.HM_F32,
-                                        keep_f32_copy=1, autotune=1, recompress=rc)
+                                        keep_f32_copy=1, autotune=1, recompress=rc, lowrank_rounding=1)
     torch.cuda.synchronize()
     t_asm = time.perf_counter() - t0
     # the plain configuration: one cavity per call, each tuned alone (the
@@ -199,7 +200,7 @@ def run_c3(args):
     q = [torch.empty_like(t) for t in T]
 
     # --- headline: batched mixed-precision solve (BF16 factors + FP64 refinement)
-    pmx = hm.solve_params(rtol=RTOL, restart=30, max_iter=400, mixed_precision=1, ir_inner_rtol=3e-3, want_q=1)
+    pmx = hm.solve_params(rtol=RTOL, restart=30, max_iter=400, mixed_precision=1, ir_inner_rtol=IR_INNER, want_q=1)
     for _ in range(args.warmup):
         hm.hm_solve_radiosity_batched(ctx, Mx, eps, T, hm.SIGMA, pmx, J, q)
     torch.cuda.synchronize()
@@ -260,7 +261,8 @@ def run_c3(args):
         "workload": "c3_64_cavities_%d_facets" % sum(sizes), "cavities": len(cavs), "facets": sum(sizes),
         "facets_min": min(sizes), "facets_max": max(sizes), "leaf": 64, "eta": 1.5, "aca_tol": 1e-6,
         "recompression": "truncated svd at aca_tol" if rc else "none",
-        "storage": "bf16 low-rank factors, fp32 near field, fp32 factor copy for the residual",
+        "storage": "bf16 low-rank factors (dithered rounding), fp32 near field, fp32 factor copy for the residual",
+        "ir_inner_rtol": IR_INNER,
         "solver": "batched gmres(30) fp32 inside fp64 iterative refinement", "rtol": RTOL, "nrhs": 1})
     out["timing"] = {"reps": len(step_s), "median_ms": 1e3 * float(np.median(step_s)),
                      "p90_ms": 1e3 * float(np.percentile(step_s, 90)), "min_ms": 1e3 * float(np.min(step_s)),
@@ -272,6 +274,7 @@ def run_c3(args):
                          "iters_max": max(it_plain)}
     out["batched_fp32"] = {"value": rate_b32, "unit": "solves/s", "iters": infb[0]["iters"]}
     out["speedup_vs_plain_fp32"] = value / rate_plain
+    out["speedup_vs_batched_fp32"] = value / rate_b32
     out["solve"] = {"outer_iters": i0["outer_iters"], "inner_iters": i0["iters"], "matvecs": i0["matvecs"],
                     "worst_rel_residual": worst}
     out["matrix"] = {"entries_dense": ent_d, "entries_lowrank": ent_l,
@@ -283,7 +286,7 @@ def run_c3(args):
     # residual): fewer bytes per inner product, at a lower share of HBM peak
     del M32
     Mb = hm.hm_assemble_hmatrix_batched(ctx, trees, [cav.aca_tol for cav in cavs], 256, hm.HM_BF16, hm.HM_BF16,
-                                        keep_f32_copy=1, autotune=1, recompress=rc)
+                                        keep_f32_copy=1, autotune=1, recompress=rc, lowrank_rounding=1)
     for _ in range(args.warmup):
         hm.hm_solve_radiosity_batched(ctx, Mb, eps, T, hm.SIGMA, pmx, J, q)
     torch.cuda.synchronize()
@@ -302,11 +305,30 @@ def run_c3(args):
                               "matvec_ms": rb["matvec_ms"], "matvec_GBps": rb["matvec_GBps"],
                               "matvec_frac": rb["matvec_frac"]}
     del Mb
+    # context: BF16 factors rounded to nearest even (errors of near-equal
+    # entries add up coherently; refinement needs a third outer step)
+    Me = hm.hm_assemble_hmatrix_batched(ctx, trees, [cav.aca_tol for cav in cavs], 256, hm.HM_BF16, hm.HM_F32,
+                                        keep_f32_copy=1, autotune=1, recompress=rc, lowrank_rounding=0)
+    for _ in range(args.warmup):
+        hm.hm_solve_radiosity_batched(ctx, Me, eps, T, hm.SIGMA, pmx, J, q)
+    torch.cuda.synchronize()
+    ne = max(1, args.steps // 2)
+    t0 = time.perf_counter()
+    for _ in range(ne):
+        _, _, infe = hm.hm_solve_radiosity_batched(ctx, Me, eps, T, hm.SIGMA, pmx, J, q)
+    torch.cuda.synchronize()
+    rate_e = len(cavs) * ne / (time.perf_counter() - t0)
+    out["nearest_even_rounding"] = {"value": rate_e, "unit": "solves/s",
+                                    "outer_iters": max(i["outer_iters"] for i in infe),
+                                    "worst_rel_residual": max(i["rel_residual"] for i in infe)}
+    log("batched mixed, nearest-even bf16 rounding: %.1f solves/s, outer %d"
+        % (rate_e, out["nearest_even_rounding"]["outer_iters"]))
+    del Me
     if rc:
         # context: the same batch with the ACA crosses as they are
         del Mx
         Mn = hm.hm_assemble_hmatrix_batched(ctx, trees, [cav.aca_tol for cav in cavs], 256, hm.HM_BF16,
-                                            hm.HM_F32, keep_f32_copy=1, autotune=1, recompress=0)
+                                            hm.HM_F32, keep_f32_copy=1, autotune=1, recompress=0, lowrank_rounding=1)
         for _ in range(args.warmup):
             hm.hm_solve_radiosity_batched(ctx, Mn, eps, T, hm.SIGMA, pmx, J, q)
         torch.cuda.synchronize()
@@ -369,7 +391,7 @@ def run_kernels_only(args):
         c, nrm, area = hm.hm_facets_from_triangles(cav.v, cav.tri, orient=1)
         trees.append(hm.hm_build_cluster_tree(ctx, c, nrm, area, cav.leaf, cav.eta))
     Mx = hm.hm_assemble_hmatrix_batched(ctx, trees, [cav.aca_tol for cav in cavs], 256, hm.HM_BF16, hm.HM_F32,
-                                        keep_f32_copy=1, autotune=1, recompress=args.recompress)
+                                        keep_f32_copy=1, autotune=1, recompress=args.recompress, lowrank_rounding=1)
     torch.cuda.synchronize()
     ev = sum(m.stats()["entries_dense"] for m in Mx)
     log("assembled %d cavities (%d near-field entries)" % (len(Mx), ev))
@@ -527,7 +549,7 @@ def run_c5(args):
     seed = 5999
     budget_gb = args.c5_budget_gb
     ctx = hm.Context(0)
-    p = hm.solve_params(rtol=RTOL, restart=30, max_iter=400, mixed_precision=1, ir_inner_rtol=3e-3, want_q=1)
+    p = hm.solve_params(rtol=RTOL, restart=30, max_iter=400, mixed_precision=1, ir_inner_rtol=IR_INNER, want_q=1)
     srv = hm.Server(ctx, hbm_budget_bytes=int(budget_gb * (1 << 30)), max_active=64, max_rhs_per_slot=8, params=p)
     # the request streams (arrival order, ids, nrhs) of every phase
     _, ids_all, nrhs_all = configs.c5_requests(nreq * 5, 1.0, seed=seed)
@@ -538,7 +560,7 @@ def run_c5(args):
         c, nrm, area = hm.hm_facets_from_triangles(cav.v, cav.tri, orient=1)
         tree = hm.hm_build_cluster_tree(ctx, c, nrm, area, cav.leaf, cav.eta)
         srv.register_cavity(cid, tree, cav.eps, aca_tol=cav.aca_tol, lowrank_dtype=hm.HM_BF16,
-                            dense_dtype=hm.HM_F32, keep_f32_copy=1)
+                            dense_dtype=hm.HM_F32, keep_f32_copy=1, lowrank_rounding=1)
         sizes[cid] = cav.n
     log("c5: registered %d cavity ids (%d-%d facets) in %.1f s" % (len(sizes), min(sizes.values()),
                                                                     max(sizes.values()), time.perf_counter() - t0))

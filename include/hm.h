@@ -155,6 +155,15 @@ typedef struct {
                               itself, |X - U V^T|_F <= aca_tol |X|_F, so no block can miss it;
                               needs m n doubles of scratch per block being compressed and
                               O(m n k) work.  HM_EINVAL outside 0..1. */
+  int32_t lowrank_rounding; /* rounding of FP32 factor entries to HM_BF16 storage: 0 nearest even
+                              (default); 1 dithered: up or down to the two BF16 neighbours with
+                              the probabilities that make the error's mean zero, drawn by a
+                              counter-based generator (SplitMix64 output function) keyed by the
+                              entry's factor side, permuted row or column, block and rank index,
+                              so the result is deterministic and the same alone or batched.
+                              Errors of near-equal entries then do not add up coherently, which
+                              lets iterative refinement converge in fewer outer steps.  1 needs
+                              HM_BF16 factors and closed_row_scale 0.  HM_EINVAL otherwise. */
 } hm_assembly_params;
 
 /* Evaluate the near field (every inadmissible leaf block, FP64 evaluation

@@ -280,6 +280,9 @@ void check_assembly_params(const hm_assembly_params* p, const char* fn) {
   HM_REQUIRE(p->autotune >= 0 && p->autotune <= 16, f + ": autotune must be in 0..16");
   HM_REQUIRE(p->recompress == 0 || p->recompress == 1, f + ": recompress must be 0 or 1");
   HM_REQUIRE(p->aca_pivot == 0 || p->aca_pivot == 1, f + ": aca_pivot must be 0 or 1");
+  HM_REQUIRE(p->lowrank_rounding == 0 || p->lowrank_rounding == 1, f + ": lowrank_rounding must be 0 or 1");
+  HM_REQUIRE(p->lowrank_rounding == 0 || (p->lowrank_dtype == HM_BF16 && !p->closed_row_scale),
+             f + ": dithered rounding needs BF16 factors and no closed_row_scale");
 }
 }  // namespace
 

@@ -503,9 +503,20 @@ __global__ __launch_bounds__(256) void k_to_bf16(const float* __restrict__ in, b
 }
 
 // U factor rows of one tile into a phase-2 panel (storage type and FP32 copy).
+// Storage rounding of a factor entry: nearest even, or dithered (BF16
+// storage only) with the draw keyed by the entry.
+template <class OT>
+__device__ __forceinline__ OT round_factor(double x, bool dither, uint32_t side, uint32_t idx, uint32_t other,
+                                           uint32_t l) {
+  if constexpr (std::is_same<OT, bf16_t>::value) {
+    if (dither) return f32_to_bf16_dither((float)x, dither_draw16(side, idx, other, l));
+  }
+  return Cvt<OT>::from_f64(x);
+}
+
 template <class ST, class OT>
 __global__ __launch_bounds__(256) void k_u_pack(const URepack* __restrict__ ur, const void* const* __restrict__ stages,
-                                                OT* __restrict__ out, float* __restrict__ out_hi) {
+                                                OT* __restrict__ out, float* __restrict__ out_hi, int dither) {
   const URepack d = ur[blockIdx.x];
   const ST* src = (const ST*)stages[d.stage] + d.src;
   const int64_t tot = (int64_t)d.m * d.k;
@@ -514,7 +525,7 @@ __global__ __launch_bounds__(256) void k_u_pack(const URepack* __restrict__ ur, 
     const int col = d.col0 + c;
     const double x = (double)src[(int64_t)c * d.ld + r];
     const int64_t o = d.base + ((int64_t)(col >> 2) * d.m + r) * 4 + (col & 3);
-    out[o] = Cvt<OT>::from_f64(x);
+    out[o] = round_factor<OT>(x, dither != 0, 1u, (uint32_t)(d.row0 + r), (uint32_t)d.cb, (uint32_t)(d.l0 + c));
     if (out_hi) out_hi[o] = (float)x;
   }
 }
@@ -524,7 +535,7 @@ __global__ __launch_bounds__(256) void k_u_pack(const URepack* __restrict__ ur, 
 // ((r / 4) * gw + pc % 64) * 4 + r % 4 inside the group.
 template <class ST, class OT>
 __global__ __launch_bounds__(256) void k_v_pack(const VRepack* __restrict__ vr, const void* const* __restrict__ stages,
-                                                OT* __restrict__ out, float* __restrict__ out_hi) {
+                                                OT* __restrict__ out, float* __restrict__ out_hi, int dither) {
   const VRepack d = vr[blockIdx.x];
   const ST* src = (const ST*)stages[d.stage] + d.src;
   const int64_t tot = (int64_t)d.n * d.k;
@@ -535,7 +546,7 @@ __global__ __launch_bounds__(256) void k_v_pack(const VRepack* __restrict__ vr, 
     const int gw = min(P1_GW, d.ktau - g * P1_GW);
     const int64_t o = d.tau_base + (int64_t)g * P1_GW * d.np + ((int64_t)(r >> 2) * gw + lp) * 4 + (r & 3);
     const double x = (double)src[e];
-    out[o] = Cvt<OT>::from_f64(x);
+    out[o] = round_factor<OT>(x, dither != 0, 2u, (uint32_t)(d.cb + r), (uint32_t)d.rb, (uint32_t)l);
     if (out_hi) out_hi[o] = (float)x;
   }
 }
@@ -686,10 +697,10 @@ void finish_job(AsmJob& J, const std::vector<DevBuf>& stages, hipStream_t s) {
       using OT = std::remove_pointer_t<decltype(otag)>;
       if (!pk.ur.empty())
         hipLaunchKernelGGL((k_u_pack<ST, OT>), dim3((unsigned)pk.ur.size()), dim3(256), 0, s, d_ur.get<URepack>(),
-                           d_sp.get<const void*>(), M->U.get<OT>(), uh);
+                           d_sp.get<const void*>(), M->U.get<OT>(), uh, (int)p.lowrank_rounding);
       if (!pk.vr.empty())
         hipLaunchKernelGGL((k_v_pack<ST, OT>), dim3((unsigned)pk.vr.size()), dim3(256), 0, s, d_vr.get<VRepack>(),
-                           d_sp.get<const void*>(), M->V.get<OT>(), vh);
+                           d_sp.get<const void*>(), M->V.get<OT>(), vh, (int)p.lowrank_rounding);
     };
     if (p.lowrank_dtype == HM_F64) go((double*)0, (double*)0);
     else if (p.lowrank_dtype == HM_F32) go((float*)0, (float*)0);

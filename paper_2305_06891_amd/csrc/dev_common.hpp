@@ -25,6 +25,38 @@ __host__ __device__ inline bf16_t f32_to_bf16(float f) {
   return (bf16_t)(c.u >> 16);
 }
 
+// Dithered rounding of factor entries to BF16: an entry goes to its BF16
+// neighbour away from zero with probability equal to its distance from the
+// neighbour toward zero (in units of their spacing), so the rounding error
+// has mean zero and no correlation between entries.  Round-to-nearest-even
+// instead gives near-equal entries (the factors of blocks seen from nearly
+// the same direction) errors of one sign, which add up coherently in a
+// product.  The draw is a 16-bit value from the SplitMix64 output function
+// (Steele, Lea and Flood, OOPSLA 2014) applied twice to a key of the entry:
+// factor side (1 for U, 2 for V), the entry's permuted row (U) or column (V)
+// in its cavity, the block's first column (U) or row (V), and the rank
+// index.  The key does not depend on the batch, so a cavity's factors are
+// the same assembled alone or with others.
+__host__ __device__ inline uint64_t splitmix64_mix(uint64_t z) {
+  z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+  z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+  return z ^ (z >> 31);
+}
+__host__ __device__ inline uint32_t dither_draw16(uint32_t side, uint32_t idx, uint32_t other, uint32_t l) {
+  constexpr uint64_t gamma = 0x9e3779b97f4a7c15ull;
+  const uint64_t z = splitmix64_mix((((uint64_t)side << 32) | idx) + gamma);
+  return (uint32_t)(splitmix64_mix(z + ((((uint64_t)other << 32) | l) + gamma)) >> 48);
+}
+// FP32 -> BF16, dithered by the 16-bit draw r (non-finite values round to
+// nearest even)
+__host__ __device__ inline bf16_t f32_to_bf16_dither(float f, uint32_t r) {
+  union { uint32_t u; float f; } c;
+  c.f = f;
+  if ((c.u & 0x7f800000u) == 0x7f800000u) return f32_to_bf16(f);
+  const uint32_t low = c.u & 0xffffu;
+  return (bf16_t)((c.u >> 16) + (r < low ? 1u : 0u));
+}
+
 template <class T> struct Cvt;
 template <> struct Cvt<double> {
   __device__ static double to_f64(double v) { return v; }

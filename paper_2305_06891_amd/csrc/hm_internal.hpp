@@ -249,14 +249,16 @@ struct NfDev {     // dense segment: F(row0 + r, cb + c) -> item panel
   int32_t row0, m, cb, w, col0, pad;
 };
 struct URepack {   // U_b rows of a tile -> item panel
-  int64_t src;     // stage element offset of U_b(row0 - rb, 0)
+  int64_t src;     // stage element offset of U_b(row0 - rb, l0)
   int64_t base;
-  int32_t stage, ld, m, k, col0, pad;
+  int32_t stage, ld, m, k, col0;
+  int32_t row0, cb, l0;  // first (permuted) row and rank index taken, first column of the block
 };
 struct VRepack {   // V_b -> group panels of its column cluster
   int64_t src;     // stage element offset of V_b
   int64_t tau_base;
   int32_t stage, n, k, lc0, ktau, np;
+  int32_t cb, rb;  // first (permuted) column and row of the block
 };
 struct PackLists {
   std::vector<NfDev> nf;

@@ -69,7 +69,7 @@ void plan_host(hm_matrix& M, const std::vector<LrInfo>& lr, const std::vector<Bl
     for (size_t z = q; z < e; ++z) {
       const LrInfo& L = lr[ord[z]];
       tidx[ord[z]] = (int32_t)(tcur + lc);
-      pk.vr.push_back(VRepack{L.sv, tau_base, L.stage, n, L.k, lc, ktau, np});
+      pk.vr.push_back(VRepack{L.sv, tau_base, L.stage, n, L.k, lc, ktau, np, L.b.cb, L.b.rb});
       lc += L.k;
     }
     P.taus.push_back(P1Tau{tau_base, tcur, b0.cb, n, np, ktau});
@@ -155,7 +155,8 @@ void plan_host(hm_matrix& M, const std::vector<LrInfo>& lr, const std::vector<Bl
             } else {
               const LrInfo& L = lr[R.blk];
               const int32_t ld = L.b.re - L.b.rb;
-              pk.ur.push_back(URepack{L.su + (row0 - L.b.rb) + (int64_t)roff * ld, 0, L.stage, ld, m, take, col, 0});
+              pk.ur.push_back(URepack{L.su + (row0 - L.b.rb) + (int64_t)roff * ld, 0, L.stage, ld, m, take, col, row0,
+                                      L.b.cb, roff});
             }
             col += take;
             want -= take;

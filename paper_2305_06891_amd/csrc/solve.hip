@@ -366,6 +366,9 @@ SolveResult Batch::solve_prepared(const hm_solve_params& p, hipStream_t s, bool 
     block_norms(K8, b64.get(), bn, s);
     R.converged = false;
     int outer = 0, inner_total = 0;
+    const size_t nslots = mats.size();
+    bool masked = false;  // the last refinement step left some slots untouched
+    int64_t masked_bytes = 0;
     for (;;) {
       if (outer == 0 && !warm) {
         // x = 0: the residual is b itself, no product needed
@@ -373,11 +376,14 @@ SolveResult Batch::solve_prepared(const hm_solve_params& p, hipStream_t s, bool 
         R.fx = false;
       } else {
         // with the flux wanted, the product also leaves F x in H64: the last
-        // residual is taken at the final iterate, with the flux's operator
-        residual64(true, s, keep_fx);
+        // residual is taken at the final iterate, with the flux's operator.
+        // Slots whose systems had all met the tolerance took a zero
+        // correction (x unchanged), so their residual and F x from the
+        // previous product stand and the product skips them.
+        residual64(true, s, keep_fx, masked ? res_mask.get<int>() : nullptr);
         R.fx = keep_fx;
         R.matvecs++;
-        R.bytes += C->bytes_hi;
+        R.bytes += masked ? masked_bytes : C->bytes_hi;
       }
       block_norms(K8, r64.get(), rn, s);
       bool done = true, nonfinite = false;
@@ -395,11 +401,22 @@ SolveResult Batch::solve_prepared(const hm_solve_params& p, hipStream_t s, bool 
       if (nonfinite || outer >= 30 || inner_total >= p.max_iter) break;
       // systems already converged get a zero right-hand side (no inner work)
       hipLaunchKernelGGL((k_cast<double, float>), dim3(gb_), dim3(256), 0, s, r64.get<double>(), b32.get<float>(), tot);
+      res_mask_h.assign(nslots, 0);
       for (size_t q = 0; q < rn.size(); ++q) {
         if (residual_met(rn[q], bn[q], p.rtol)) {
           const SysDev& sd = S.sys[q];
           HM_HIP(hipMemsetAsync(b32.get<float>() + sd.col * N + sd.row0, 0, (size_t)sd.n * 4, s));
+        } else {
+          res_mask_h[S.sys[q].slot] = 1;
         }
+      }
+      masked_bytes = 0;
+      for (size_t q = 0; q < nslots; ++q)
+        if (res_mask_h[q]) masked_bytes += matrix_bytes(*mats[q], true);
+      masked = masked_bytes < C->bytes_hi;
+      if (masked) {
+        if (!res_mask.get()) res_mask.alloc(nslots * 4);
+        HM_HIP(hipMemcpyAsync(res_mask.get(), res_mask_h.data(), nslots * 4, hipMemcpyHostToDevice, s));
       }
       // correction from zero; the FP64 residual above checks its progress,
       // so the inner solve stops on its own residual estimate
@@ -420,7 +437,7 @@ SolveResult Batch::solve_prepared(const hm_solve_params& p, hipStream_t s, bool 
 }
 
 // r64 = b64 - C x64 with FP64 vectors (hi: FP32 copy of BF16 factors)
-void Batch::residual64(bool hi, hipStream_t s, bool keep_fx) {
+void Batch::residual64(bool hi, hipStream_t s, bool keep_fx, const int* slot_active) {
   Epilogue ep;
   ep.rowscale = omeps64.get();
   ep.a_acc = 1.0;
@@ -432,7 +449,7 @@ void Batch::residual64(bool hi, hipStream_t s, bool keep_fx) {
     ep.acc_out = H64.get();
     ep.ld_acc = N;
   }
-  launch_matvec(*C, nrhs, 8, hi, x64.get(), N, r64.get(), N, ep, nullptr, s);
+  launch_matvec(*C, nrhs, 8, hi, x64.get(), N, r64.get(), N, ep, slot_active, s);
 }
 
 // H64 <- q = eps (F J - sigma T^4 g), J = x64

@@ -41,6 +41,10 @@ struct Batch {
   Krylov K64, K32;
   bool k64 = false, k32 = false;
   DevBuf Tp, epsp, omeps64, omeps32, b64, b32, x64, x32, r64, H64, g, g_eps, d_flag;
+  // refinement: slots (matrices) that still hold a system above the
+  // tolerance; the next residual product runs on those only
+  DevBuf res_mask;
+  std::vector<int> res_mask_h;
   std::vector<SlotIO> ios;
   DevBuf d_ios;
   std::unique_ptr<Batch> gb;  // width-1 batch for g = F C^-1 eps
@@ -67,7 +71,8 @@ struct Batch {
   // (the flux then needs no product of its own)
   SolveResult solve_prepared(const hm_solve_params& p, hipStream_t s, bool warm = false, bool report = true,
                              bool keep_fx = false);
-  void residual64(bool hi, hipStream_t s, bool keep_fx = false);
+  // slot_active: NULL for every slot, else a device flag per slot
+  void residual64(bool hi, hipStream_t s, bool keep_fx = false, const int* slot_active = nullptr);
   void flux(double sigma, hipStream_t s, bool have_fx = false);
   SolveResult solve(const std::vector<const double*>& eps, const std::vector<const double*>& T,
                     const std::vector<int64_t>& ldT, double sigma, const hm_solve_params& p,

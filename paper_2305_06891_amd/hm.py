@@ -42,7 +42,8 @@ class hm_tree_params(C.Structure):
 class hm_assembly_params(C.Structure):
     _fields_ = [("aca_tol", C.c_double), ("k_max", C.c_int32), ("lowrank_dtype", C.c_int),
                 ("dense_dtype", C.c_int), ("keep_f32_copy", C.c_int32), ("closed_row_scale", C.c_int32),
-                ("autotune", C.c_int32), ("recompress", C.c_int32), ("aca_pivot", C.c_int32)]
+                ("autotune", C.c_int32), ("recompress", C.c_int32), ("aca_pivot", C.c_int32),
+                ("lowrank_rounding", C.c_int32)]
 
 
 class hm_solve_params(C.Structure):
@@ -306,16 +307,19 @@ class HMatrix:
 
 
 def hm_assemble_hmatrix(ctx, tree: Tree, aca_tol=1e-6, k_max=256, lowrank_dtype=HM_F32, dense_dtype=HM_F32,
-                        keep_f32_copy=0, closed_row_scale=0, autotune=0, recompress=0, aca_pivot=0) -> HMatrix:
+                        keep_f32_copy=0, closed_row_scale=0, autotune=0, recompress=0, aca_pivot=0,
+                        lowrank_rounding=0) -> HMatrix:
     p = hm_assembly_params(float(aca_tol), int(k_max), int(lowrank_dtype), int(dense_dtype), int(keep_f32_copy),
-                           int(closed_row_scale), int(autotune), int(recompress), int(aca_pivot))
+                           int(closed_row_scale), int(autotune), int(recompress), int(aca_pivot),
+                           int(lowrank_rounding))
     h = _vp()
     _check(lib.hm_assemble_hmatrix(ctx.handle, tree._h, C.byref(p), C.byref(h)), ctx.handle)
     return HMatrix(h, ctx)
 
 
 def hm_assemble_hmatrix_batched(ctx, trees, aca_tol=1e-6, k_max=256, lowrank_dtype=HM_F32, dense_dtype=HM_F32,
-                                keep_f32_copy=0, closed_row_scale=0, autotune=0, recompress=0, aca_pivot=0):
+                                keep_f32_copy=0, closed_row_scale=0, autotune=0, recompress=0, aca_pivot=0,
+                                lowrank_rounding=0):
     """Matrices of several cavities assembled together (shared ACA launches;
     with autotune, one product split tuned on their batched product).  Every
     parameter is a scalar for all cavities or a sequence with one entry per
@@ -327,12 +331,12 @@ def hm_assemble_hmatrix_batched(ctx, trees, aca_tol=1e-6, k_max=256, lowrank_dty
         return list(v) if isinstance(v, (list, tuple)) else [v] * k
 
     cols = [each(aca_tol), each(k_max), each(lowrank_dtype), each(dense_dtype), each(keep_f32_copy),
-            each(closed_row_scale), each(autotune), each(recompress), each(aca_pivot)]
+            each(closed_row_scale), each(autotune), each(recompress), each(aca_pivot), each(lowrank_rounding)]
     if any(len(c) != k for c in cols):
         raise ValueError("one parameter value per tree expected")
     ps = (hm_assembly_params * k)(*[hm_assembly_params(float(a), int(b), int(c), int(d), int(e), int(f), int(g),
-                                                       int(h), int(i))
-                                    for a, b, c, d, e, f, g, h, i in zip(*cols)])
+                                                       int(h), int(i), int(j))
+                                    for a, b, c, d, e, f, g, h, i, j in zip(*cols)])
     ts = (_vp * k)(*[t._h for t in trees])
     hs = (_vp * k)()
     _check(lib.hm_assemble_hmatrix_batched(ctx.handle, k, ts, ps, hs), ctx.handle)
@@ -484,7 +488,7 @@ def hm_hlu_factor(ctx, tree: Tree, eps, aca_tol=1e-6, k_max=256, aca_pivot=0) ->
     """Hierarchical block LU of C = I - diag(1 - eps) F (eps: device float64,
     caller order)."""
     import torch
-    p = hm_assembly_params(float(aca_tol), int(k_max), HM_F64, HM_F64, 0, 0, 0, 0, int(aca_pivot))
+    p = hm_assembly_params(float(aca_tol), int(k_max), HM_F64, HM_F64, 0, 0, 0, 0, int(aca_pivot), 0)
     h = _vp()
     _check(lib.hm_hlu_factor(ctx.handle, tree._h, _dev_ptr(eps, torch.float64), C.byref(p), C.byref(h)), ctx.handle)
     return HLU(h, ctx, tree.n)
@@ -503,10 +507,12 @@ class Server:
         self._n = {}
 
     def register_cavity(self, cavity_id, tree: Tree, eps_host, aca_tol=1e-6, k_max=256, lowrank_dtype=HM_BF16,
-                        dense_dtype=HM_F32, keep_f32_copy=1, autotune=0, recompress=0, aca_pivot=0):
+                        dense_dtype=HM_F32, keep_f32_copy=1, autotune=0, recompress=0, aca_pivot=0,
+                        lowrank_rounding=0):
         e = _f64(eps_host)
         ap = hm_assembly_params(float(aca_tol), int(k_max), int(lowrank_dtype), int(dense_dtype),
-                                int(keep_f32_copy), 0, int(autotune), int(recompress), int(aca_pivot))
+                                int(keep_f32_copy), 0, int(autotune), int(recompress), int(aca_pivot),
+                                int(lowrank_rounding))
         _check(lib.hm_server_register_cavity(self._h, C.c_uint64(cavity_id), tree._h, _ptr(e), C.byref(ap)))
         self._n[cavity_id] = tree.n
 

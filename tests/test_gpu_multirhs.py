@@ -9,7 +9,9 @@ exactly, so only the summation order differs).  The matrices are large
 enough for column clusters split into row chunks (partial sums), and the
 cases cover FP32 and BF16 factors, 16 and 12 columns, and a fused epilogue
 (alpha, beta).  The 16-column product is also compared with the oracle's
-H-matrix whose entries are rounded to the same storage types.
+H-matrix whose entries are rounded to the same storage types (BF16 by
+nearest even, or dithered by the keyed draws, emulated here from the
+generator's published definition).
 """
 import numpy as np
 import pytest
@@ -82,11 +84,40 @@ def test_sixteen_rhs_on_small_tiles(hm, ctx):
         assert worst <= tol
 
 
+def _splitmix64_mix(z):
+    """SplitMix64 output function (Steele, Lea and Flood, OOPSLA 2014) on
+    uint64 arrays (wrap-around arithmetic)."""
+    with np.errstate(over="ignore"):
+        z = (z ^ (z >> np.uint64(30))) * np.uint64(0xBF58476D1CE4E5B9)
+        z = (z ^ (z >> np.uint64(27))) * np.uint64(0x94D049BB133111EB)
+        return z ^ (z >> np.uint64(31))
+
+
+def _draw16(side, idx, other, rank):
+    g = np.uint64(0x9E3779B97F4A7C15)
+    u = lambda x: np.asarray(x, dtype=np.uint64)
+    with np.errstate(over="ignore"):
+        z = _splitmix64_mix(((u(side) << np.uint64(32)) | u(idx)) + g)
+        return _splitmix64_mix(z + (((u(other) << np.uint64(32)) | u(rank)) + g)) >> np.uint64(48)
+
+
+def _bf16_dither(A, side, idx0, other):
+    """FP64 -> FP32 (nearest) -> BF16, away from zero when the 16-bit draw
+    of entry (i, l) is below the FP32 value's low 16 bits (its position
+    between the two BF16 neighbours)."""
+    bits = np.ascontiguousarray(A, dtype=np.float32).view(np.uint32)
+    i = np.arange(A.shape[0])[:, None] + idx0
+    l = np.arange(A.shape[1])[None, :]
+    r = _draw16(side, i, other, l)
+    hi = (bits >> np.uint32(16)).astype(np.uint32) + (r < (bits & np.uint32(0xFFFF))).astype(np.uint32)
+    return (hi << np.uint32(16)).view(np.float32).astype(np.float64)
+
+
 def _stored_oracle_product(v, f, lr, X):
     """The oracle's H-matrix (same tree, partial-pivot ACA at 1e-6) with its
     entries rounded as the library stores them (near field FP64 -> FP32;
-    factors FP64 -> FP32, then -> BF16 by round-to-nearest-even for BF16
-    storage), applied to X in FP64."""
+    factors FP64 -> FP32, then -> BF16 by round-to-nearest-even, or dithered
+    with the keyed draws), applied to X in FP64."""
     import torch
     from oracle import aca, geometry
     c, nr, a = geometry.facets_from_triangles(v, f)
@@ -99,11 +130,15 @@ def _stored_oracle_product(v, f, lr, X):
         return A32.astype(np.float64)
 
     H.dense = [(r0, r1, c0, c1, np.asarray(B, dtype=np.float32).astype(np.float64)) for r0, r1, c0, c1, B in H.dense]
-    H.lowrank = [(r0, r1, c0, c1, st(U), st(V)) for r0, r1, c0, c1, U, V in H.lowrank]
+    if lr == "bf16_dither":
+        H.lowrank = [(r0, r1, c0, c1, _bf16_dither(U, 1, r0, c0), _bf16_dither(V, 2, c0, r0))
+                     for r0, r1, c0, c1, U, V in H.lowrank]
+    else:
+        H.lowrank = [(r0, r1, c0, c1, st(U), st(V)) for r0, r1, c0, c1, U, V in H.lowrank]
     return H.matvec(X)
 
 
-@pytest.mark.parametrize("lr", ["f32", "bf16"])
+@pytest.mark.parametrize("lr", ["f32", "bf16", "bf16_dither"])
 def test_sixteen_rhs_product_matches_the_oracle(hm, ctx, lr):
     """The 16-column matrix-core product against the oracle's H-matrix with
     the same storage rounding: the library's ACA takes the oracle's steps in
@@ -115,7 +150,9 @@ def test_sixteen_rhs_product_matches_the_oracle(hm, ctx, lr):
     f = meshes.inward(f)
     n = f.shape[0]
     lrt = hm.HM_F32 if lr == "f32" else hm.HM_BF16
-    tree, M = build(hm, ctx, v, f, 64, 1.5, 1e-6, lrt, hm.HM_F32, keep=0)
+    c, nr, a = hm.hm_facets_from_triangles(v, f, orient=1)
+    tree = hm.hm_build_cluster_tree(ctx, c, nr, a, 64, 1.5)
+    M = hm.hm_assemble_hmatrix(ctx, tree, 1e-6, 256, lrt, hm.HM_F32, lowrank_rounding=int(lr == "bf16_dither"))
     log("case: ellipsoid %d facets, %s factors, 16 columns against the oracle's stored H-matrix" % (n, lr))
     X = np.random.default_rng(29).uniform(0.5, 1.5, (n, 16))
     Yo = _stored_oracle_product(v, f, lr, X)
