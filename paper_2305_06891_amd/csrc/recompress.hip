@@ -10,14 +10,19 @@
 //     stopped when it falls below RC_DROP: columns within 1e-8 of the span
 //     of the selected ones add nothing), so Uh ~ Qu Ru with
 //     Qu = Uh_sel Ru11^-1 orthonormal; the same for V;
-//  4. core K = Ru D Rv^T (ru x rv), SVD by one-sided Jacobi (cyclic
-//     round-robin pairs, rotations accumulated in Z): K Z = W S;
-//  5. the smallest rank r >= 1 with sqrt(sum_{i>r} s_i^2) <= tol |s|_2
-//     (Frobenius form of eq. (31));
-//  6. U' = U Tu, V' = V Tv with Tu = diag(1/a) [Ru11^-1 (K Z)_r] on the
-//     selected rows and Tv = diag(1/b) [Rv11^-1 Z_r], so that U' = Qu W_r S_r
-//     and V' = Qv Z_r (orthonormal columns); a second kernel forms them
-//     straight into the staging buffer of the compacted factors.
+//  4. core K = Ru D Rv^T (ru x rv);
+//  5. its SVD: Householder QR with column pivoting K P = Q R, then
+//     one-sided Jacobi on the columns of R^T (cyclic round-robin pairs):
+//     R^T Z = W, whose column norms are the singular values s and whose
+//     normalised columns, permuted back, the right singular vectors
+//     x = P W S^-1 (Z and Q are never formed); the smallest rank r >= 1 with
+//     sqrt(sum_{i>r} s_i^2) <= tol |s|_2 (Frobenius form of eq. (31));
+//  6. the kept right vectors x_r and the left ones times s, K x_r;
+//  7. U' = U Tu, V' = V Tv with Tu = diag(1/a) [Ru11^-1 K x_r] and
+//     Tv = diag(1/b) [Rv11^-1 x_r] on the selected rows, so that
+//     U' = (left vectors) S_r and V' has orthonormal columns; a second
+//     kernel forms them straight into the staging buffer of the compacted
+//     factors.
 //
 // Untruncated, the factors reproduce U V^T whatever the accuracy of the
 // Cholesky factors (the same Ru, Rv are used on both sides), so rounding in
@@ -42,7 +47,7 @@ constexpr int RC_ROWS = 16;               // panel rows staged per Gram pass
 constexpr int RC_SWEEPS = 40;             // Jacobi sweep limit
 constexpr double RC_DROP = 1e-16;         // pivoted Cholesky stop (unit diagonal)
 constexpr double RC_JTOL = 1e-13;         // Jacobi: |g| <= RC_JTOL sqrt(a b) counts as orthogonal
-constexpr double RC_JNOISE = 1e-15;       // ... and so does |g| <= RC_JNOISE max(a, b)
+constexpr double RC_JFLOOR = 1e-30;       // ... and so does a pair of columns below RC_JFLOOR |K|_F^2
 
 struct RcMax {
   double mag;
@@ -216,14 +221,21 @@ __device__ int rc_pchol(const double* __restrict__ G, int k, double* __restrict_
   return rr;
 }
 
-// Back substitution R11 y = b for the upper-triangular ru x ru matrix
-// R11(s, s') = R(s, sel[s']) (one thread per right-hand side).
-__device__ void rc_backsub(const double* __restrict__ R, int k, const int* __restrict__ sel, int ru,
-                           double* __restrict__ y) {
-  for (int s = ru - 1; s >= 0; --s) {
-    double x = y[s];
-    for (int s2 = s + 1; s2 < ru; ++s2) x -= R[(int64_t)s * k + sel[s2]] * y[s2];
-    y[s] = x / R[(int64_t)s * k + sel[s]];
+// Back substitution R11 Y = B in place for r right-hand sides (Y column c
+// at Y + c k), R11(s, s') = R(s, sel[s']) upper triangular (n x n): row by
+// row from the last, each row's values then removed from the rows above it,
+// all columns at once.
+__device__ void rc_trsm(const double* __restrict__ R, int k, const int* __restrict__ sel, int n,
+                        double* __restrict__ Y, int r) {
+  for (int s = n - 1; s >= 0; --s) {
+    const double piv = R[(int64_t)s * k + sel[s]];
+    for (int c = threadIdx.x; c < r; c += RC_T) Y[(int64_t)c * k + s] /= piv;
+    __syncthreads();
+    for (int e = threadIdx.x; e < s * r; e += RC_T) {
+      const int s2 = e % s, c = e / s;
+      Y[(int64_t)c * k + s2] -= R[(int64_t)s2 * k + sel[s]] * Y[(int64_t)c * k + s];
+    }
+    __syncthreads();
   }
 }
 
@@ -233,13 +245,13 @@ int64_t recompress_work_doubles(int k) { return 8 * (int64_t)k * k; }
 
 namespace {
 
-// The steps 1-6 for one block.  Work arrays (k x k, ld k) may be in LDS or
+// The steps 1-7 for one block.  Work arrays (k x k, ld k) may be in LDS or
 // in the global workspace: Gu and Gv (Gram matrices), Ru and Rv (Cholesky
-// rows), K (core, rotated in place), Z (rotations); Gv may share Gu's
-// storage and K Gu's, Z may share Ru's when Ru_keep is a copy of its own;
-// ytmp, ztmp, Tu, Tv are global.
+// rows), K (core, then its QR, then Rv^T z products), W (R^T, rotated in
+// place); Gv may share Gu's storage and K Gu's, W may share Ru's when
+// Ru_keep is a copy of its own; ytmp, ztmp, Tu, Tv are global.
 __device__ void rc_core(const RcDev& b, const double* __restrict__ scratch, int* __restrict__ newrank,
-                        double* stage, int sst, double* Gu, double* Ru, double* Gv, double* Rv, double* K, double* Z,
+                        double* stage, int sst, double* Gu, double* Ru, double* Gv, double* Rv, double* K, double* W,
                         double* Ru_keep, double* ytmp, double* ztmp, double* Tu, double* Tv, double* ia, double* ib,
                         double* dd, double* sig, int* selu, int* selv, int* taken, int* order, RcMax* sh_max,
                         double* sh_sum, int* sh_rot) {
@@ -276,7 +288,7 @@ __device__ void rc_core(const RcDev& b, const double* __restrict__ scratch, int*
   const int ru = rc_pchol(Gu, k, Ru, selu, sig, taken, sh_max, b.early ? dd : nullptr, lim, sh_sum);
   if (!b.early) rc_gram(V, n, k, ib, Gv, stage, sst);
   const int rv = rc_pchol(Gv, k, Rv, selv, sig, taken, sh_max, b.early ? dd : nullptr, lim, sh_sum);
-  // 4. K = Ru D Rv^T (ru x rv, column t at K + t k), Z = I (rv x rv)
+  // 4. K = Ru D Rv^T (ru x rv, column t at K + t k)
   for (int e = tid; e < ru * rv; e += RC_T) {
     const int s = e % ru, t = e / ru;
     double x = 0.0;
@@ -284,15 +296,95 @@ __device__ void rc_core(const RcDev& b, const double* __restrict__ scratch, int*
     K[(int64_t)t * k + s] = x;
   }
   __syncthreads();
-  // Ru is kept where the back substitutions read it (Z may take its place)
+  // Ru is kept where the last steps read it (W may take its place)
   if (Ru_keep != Ru)
     for (int e = tid; e < ru * k; e += RC_T) Ru_keep[e] = Ru[e];
   __syncthreads();
-  for (int e = tid; e < rv * rv; e += RC_T) Z[(int64_t)(e / rv) * k + e % rv] = (e / rv == e % rv) ? 1.0 : 0.0;
+  // 5. Householder QR of K with column pivoting (largest remaining column
+  // first, the first index on ties): R in the upper triangle of K, the
+  // column order in perm; W = R^T.  One-sided Jacobi on the columns of R^T
+  // (the preconditioning of Drmac and Veselic, SIAM J. Matrix Anal. Appl.
+  // 29 (2008)) converges in about half the sweeps it takes on K itself, and
+  // the rotations need not be kept: with R^T Z = W S', the right singular
+  // vectors of K are P W, the left ones times s come from K (P W).
+  int* perm = taken;  // free after the Cholesky steps
+  const int lane = tid & 63, wid = tid >> 6;
+  for (int j = tid; j < rv; j += RC_T) perm[j] = j;
+  for (int j = wid; j < rv; j += RC_W) {  // column norms^2 (sig holds them during the QR)
+    double s2 = 0.0;
+    for (int i = lane; i < ru; i += 64) {
+      const double x = K[(int64_t)j * k + i];
+      s2 += x * x;
+    }
+    s2 = wave_sum(s2);
+    if (lane == 0) sig[j] = s2;
+  }
   __syncthreads();
-  // one-sided Jacobi on the columns of K: round-robin pairs over np
-  // positions (np = rv rounded up to even; position rv is a dummy)
-  const int np = (rv + 1) & ~1;
+  const int qmax = min(ru, rv);
+  int kq = 0;
+  for (int s = 0; s < qmax; ++s) {
+    RcMax am{-1.0, INT_MAX};
+    for (int j = s + tid; j < rv; j += RC_T) am = rc_better(am, RcMax{sig[j], j});
+    am = rc_block_max(am, sh_max);
+    if (!(am.mag > 0.0)) break;
+    const int p = am.idx;
+    double* ks = K + (int64_t)s * k;
+    if (p != s) {
+      double* kp = K + (int64_t)p * k;
+      for (int i = tid; i < ru; i += RC_T) {
+        const double x = ks[i];
+        ks[i] = kp[i];
+        kp[i] = x;
+      }
+      if (tid == 0) {
+        const int t = perm[s];
+        perm[s] = perm[p];
+        perm[p] = t;
+        sig[p] = sig[s];
+      }
+    }
+    __syncthreads();
+    // reflector I - beta v v^T with v = x - alpha e_1 (x: rows s.. of the
+    // column, |x|^2 = am.mag), stored in place of the column
+    const double x0 = ks[s];
+    const double nx = sqrt(am.mag);
+    const double alpha = x0 >= 0.0 ? -nx : nx;
+    const double beta = 1.0 / (nx * (nx + fabs(x0)));  // 2 / |v|^2
+    __syncthreads();
+    if (tid == 0) ks[s] = x0 - alpha;
+    __syncthreads();
+    for (int j = s + 1 + wid; j < rv; j += RC_W) {
+      double* kj = K + (int64_t)j * k;
+      double dot = 0.0;
+      for (int i = s + lane; i < ru; i += 64) dot += ks[i] * kj[i];
+      dot = wave_sum(dot) * beta;
+      double s2 = 0.0;
+      for (int i = s + lane; i < ru; i += 64) {
+        const double x = kj[i] - dot * ks[i];
+        kj[i] = x;
+        if (i > s) s2 += x * x;
+      }
+      s2 = wave_sum(s2);
+      if (lane == 0) sig[j] = s2;  // the next step's norms (rows s+1..)
+    }
+    __syncthreads();
+    if (tid == 0) ks[s] = alpha;
+    __syncthreads();
+    kq = s + 1;
+  }
+  // W = R^T (rv x kq): column i holds row i of R
+  double fro2 = 0.0;  // |K|_F^2 = |R|_F^2, which the rotations keep
+  for (int e = tid; e < kq * rv; e += RC_T) {
+    const int j = e % rv, i = e / rv;
+    const double x = j >= i ? K[(int64_t)j * k + i] : 0.0;
+    W[(int64_t)i * k + j] = x;
+    fro2 += x * x;
+  }
+  fro2 = rc_block_sum(fro2, sh_sum);
+  const double floor2 = RC_JFLOOR * fro2;
+  // one-sided Jacobi on the columns of W: round-robin pairs over np
+  // positions (np = kq rounded up to even; position kq is a dummy)
+  const int np = (kq + 1) & ~1;
   const int g = tid / RC_LP, gl = tid % RC_LP;
   for (int sweep = 0; sweep < RC_SWEEPS && np >= 2; ++sweep) {
     if (tid == 0) *sh_rot = 0;
@@ -307,12 +399,12 @@ __device__ void rc_core(const RcDev& b, const double* __restrict__ scratch, int*
           p = q;
           q = t;
         }
-        if (q >= rv) continue;
-        double* kp = K + (int64_t)p * k;
-        double* kq = K + (int64_t)q * k;
+        if (q >= kq) continue;
+        double* wp = W + (int64_t)p * k;
+        double* wq = W + (int64_t)q * k;
         double al = 0.0, be = 0.0, ga = 0.0;
-        for (int i = gl; i < ru; i += RC_LP) {
-          const double x = kp[i], y = kq[i];
+        for (int i = gl; i < rv; i += RC_LP) {
+          const double x = wp[i], y = wq[i];
           al += x * x;
           be += y * y;
           ga += x * y;
@@ -321,23 +413,20 @@ __device__ void rc_core(const RcDev& b, const double* __restrict__ scratch, int*
         be = grp_sum(be);
         ga = grp_sum(ga);
         // a pair counts as orthogonal when |g| is below RC_JTOL of sqrt(a b),
-        // or at rounding level of the larger column (a column of negligible
-        // norm against a large one would otherwise keep rotating on noise)
-        if (ga != 0.0 && fabs(ga) > RC_JTOL * sqrt(al * be) && fabs(ga) > RC_JNOISE * fmax(al, be)) {
+        // or when both columns are rounding noise (such pairs would keep
+        // rotating on it).  Every column above that floor is made
+        // orthogonal to the others to RC_JTOL relative to the two norms:
+        // the right vectors are the normalised columns, and a kept column
+        // of norm s_t leaning toward one of norm s_1 by d would bring
+        // d s_1 of the larger direction into K x_t.
+        if (ga != 0.0 && fabs(ga) > RC_JTOL * sqrt(al * be) && fmax(al, be) > floor2) {
           const double zeta = (be - al) / (2.0 * ga);
           const double tt = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
           const double c = 1.0 / sqrt(1.0 + tt * tt), sn = c * tt;
-          for (int i = gl; i < ru; i += RC_LP) {
-            const double x = kp[i], y = kq[i];
-            kp[i] = c * x - sn * y;
-            kq[i] = sn * x + c * y;
-          }
-          double* zp = Z + (int64_t)p * k;
-          double* zq = Z + (int64_t)q * k;
           for (int i = gl; i < rv; i += RC_LP) {
-            const double x = zp[i], y = zq[i];
-            zp[i] = c * x - sn * y;
-            zq[i] = sn * x + c * y;
+            const double x = wp[i], y = wq[i];
+            wp[i] = c * x - sn * y;
+            wq[i] = sn * x + c * y;
           }
           rotated = 1;
         }
@@ -350,28 +439,28 @@ __device__ void rc_core(const RcDev& b, const double* __restrict__ scratch, int*
     __syncthreads();
     if (!any) break;
   }
-  // 5. singular values (column norms of K Z), their descending order and the rank
-  for (int t = tid; t < rv; t += RC_T) {
+  // singular values (column norms of W), their descending order and the rank
+  for (int t = tid; t < kq; t += RC_T) {
     double s2 = 0.0;
-    for (int i = 0; i < ru; ++i) s2 += K[(int64_t)t * k + i] * K[(int64_t)t * k + i];
+    for (int i = 0; i < rv; ++i) s2 += W[(int64_t)t * k + i] * W[(int64_t)t * k + i];
     sig[t] = sqrt(s2);
   }
   __syncthreads();
-  for (int t = tid; t < rv; t += RC_T) {
+  for (int t = tid; t < kq; t += RC_T) {
     int rank = 0;
-    for (int u = 0; u < rv; ++u) rank += (sig[u] > sig[t] || (sig[u] == sig[t] && u < t)) ? 1 : 0;
+    for (int u = 0; u < kq; ++u) rank += (sig[u] > sig[t] || (sig[u] == sig[t] && u < t)) ? 1 : 0;
     order[rank] = t;
   }
   __syncthreads();
   double tot = 0.0;
-  for (int t = tid; t < rv; t += RC_T) tot += sig[t] * sig[t];
+  for (int t = tid; t < kq; t += RC_T) tot += sig[t] * sig[t];
   tot = rc_block_sum(tot, sh_sum);
   int r = 0;
   if (tid == 0 && tot > 0.0) {
     const double lim = b.tol * sqrt(tot);
     double tail2 = 0.0;  // sum of the discarded squares, from the smallest up
-    r = rv;
-    for (int c = rv - 1; c >= 1; --c) {
+    r = kq;
+    for (int c = kq - 1; c >= 1; --c) {
       const double s = sig[order[c]];
       tail2 += s * s;
       if (sqrt(tail2) <= lim) r = c;
@@ -384,21 +473,46 @@ __device__ void rc_core(const RcDev& b, const double* __restrict__ scratch, int*
   if (tid == 0) *sh_rot = r;
   __syncthreads();
   r = *sh_rot;
-  // 6. Tu (k x r) and Tv (k x r): back substitutions on the selected rows
-  for (int c = tid; c < r; c += RC_T) {
+  // 6. kept right singular vectors in Rv coordinates, z_c = P w_t / s_t
+  // (t = order[c]), and left ones times s in Ru coordinates,
+  // y_c = K z_c = Ru D (Rv^T z_c); then the triangular solves on the
+  // selected rows, all kept columns together
+  for (int e = tid; e < r * rv; e += RC_T) {
+    const int j = e % rv, c = e / rv;
     const int t = order[c];
-    double* tu = Tu + (int64_t)c * k;
-    double* tv = Tv + (int64_t)c * k;
-    for (int l = 0; l < k; ++l) tu[l] = tv[l] = 0.0;
-    // y (in the first ru entries of the column, then moved to the rows sel)
-    double* y = ytmp + (int64_t)c * k;  // one scratch column per rank
-    for (int s = 0; s < ru; ++s) y[s] = K[(int64_t)t * k + s];
-    rc_backsub(Ru_keep, k, selu, ru, y);
-    for (int s = 0; s < ru; ++s) tu[selu[s]] = y[s] * ia[selu[s]];
-    double* z = ztmp + (int64_t)c * k;
-    for (int s = 0; s < rv; ++s) z[s] = Z[(int64_t)t * k + s];
-    rc_backsub(Rv, k, selv, rv, z);
-    for (int s = 0; s < rv; ++s) tv[selv[s]] = z[s] * ib[selv[s]];
+    ztmp[(int64_t)c * k + perm[j]] = W[(int64_t)t * k + j] / sig[t];
+  }
+  __syncthreads();
+  double* Ab = K;  // k x r: K is free once its R went to W
+  for (int e = tid; e < k * r; e += RC_T) {
+    const int l = e % k, c = e / k;
+    double x = 0.0;
+    for (int t = 0; t < rv; ++t) x += Rv[(int64_t)t * k + l] * ztmp[(int64_t)c * k + t];
+    Ab[(int64_t)c * k + l] = x * dd[l];
+  }
+  __syncthreads();
+  for (int e = tid; e < ru * r; e += RC_T) {
+    const int s = e % ru, c = e / ru;
+    double x = 0.0;
+    for (int l = 0; l < k; ++l) x += Ru_keep[(int64_t)s * k + l] * Ab[(int64_t)c * k + l];
+    ytmp[(int64_t)c * k + s] = x;
+  }
+  __syncthreads();
+  rc_trsm(Ru_keep, k, selu, ru, ytmp, r);
+  rc_trsm(Rv, k, selv, rv, ztmp, r);
+  // 7. Tu (k x r) and Tv (k x r)
+  for (int e = tid; e < r * k; e += RC_T) {
+    Tu[e % k + (int64_t)(e / k) * k] = 0.0;
+    Tv[e % k + (int64_t)(e / k) * k] = 0.0;
+  }
+  __syncthreads();
+  for (int e = tid; e < r * ru; e += RC_T) {
+    const int s = e % ru, c = e / ru;
+    Tu[(int64_t)c * k + selu[s]] = ytmp[(int64_t)c * k + s] * ia[selu[s]];
+  }
+  for (int e = tid; e < r * rv; e += RC_T) {
+    const int s = e % rv, c = e / rv;
+    Tv[(int64_t)c * k + selv[s]] = ztmp[(int64_t)c * k + s] * ib[selv[s]];
   }
 }
 
@@ -406,7 +520,7 @@ __device__ void rc_core(const RcDev& b, const double* __restrict__ scratch, int*
 
 // Ranks and transforms of one chunk of blocks, work arrays in the global
 // workspace (any rank up to RC_KMAX).  Workspace per block (doubles, ld k):
-// Gu | Ru | Gv | Rv | K | Z | Tu | Tv.
+// Gu (then y) | Ru | Gv (then z) | Rv | K | W | Tu | Tv.
 __global__ __launch_bounds__(RC_T) void k_recompress(const RcDev* __restrict__ blocks, const double* __restrict__ scratch,
                                                      double* __restrict__ work, int* __restrict__ newrank) {
   __shared__ double stage[RC_ROWS * RC_KMAX];
@@ -423,8 +537,8 @@ __global__ __launch_bounds__(RC_T) void k_recompress(const RcDev* __restrict__ b
 }
 
 // The same for blocks of rank up to KM with the k x k arrays in LDS (three
-// KM x KM areas: A holds Gu, then Gv, then K; B holds Ru, then Z; C holds
-// Rv); Ru is copied to the workspace before Z overwrites it.  The steps and
+// KM x KM areas: A holds Gu, then Gv, then K; B holds Ru, then W; C holds
+// Rv); Ru is copied to the workspace before W overwrites it.  The steps and
 // their order are those of k_recompress, so both give the same results.
 template <int KM>
 __global__ __launch_bounds__(RC_T) void k_recompress_lds(const RcDev* __restrict__ blocks,
