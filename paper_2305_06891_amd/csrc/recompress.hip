@@ -43,6 +43,7 @@ constexpr int RC_T = 256;                 // threads per workgroup
 constexpr int RC_W = RC_T / 64;           // waves
 constexpr int RC_LP = 16;                 // lanes per Jacobi pair
 constexpr int RC_GROUPS = RC_T / RC_LP;   // Jacobi pairs in flight
+constexpr int RC_PL = (RC_KMAX + RC_LP - 1) / RC_LP;  // column entries per lane
 constexpr int RC_ROWS = 16;               // panel rows staged per Gram pass
 constexpr int RC_SWEEPS = 40;             // Jacobi sweep limit
 constexpr double RC_DROP = 1e-16;         // pivoted Cholesky stop (unit diagonal)
@@ -231,9 +232,22 @@ __device__ void rc_trsm(const double* __restrict__ R, int k, const int* __restri
     const double piv = R[(int64_t)s * k + sel[s]];
     for (int c = threadIdx.x; c < r; c += RC_T) Y[(int64_t)c * k + s] /= piv;
     __syncthreads();
-    for (int e = threadIdx.x; e < s * r; e += RC_T) {
-      const int s2 = e % s, c = e / s;
-      Y[(int64_t)c * k + s2] -= R[(int64_t)s2 * k + sel[s]] * Y[(int64_t)c * k + s];
+    // eight updates per thread at a time, all loads before the stores
+    for (int e0 = threadIdx.x; e0 < s * r; e0 += 8 * RC_T) {
+      double v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int e = e0 + u * RC_T;
+        if (e < s * r) {
+          const int s2 = e % s, c = e / s;
+          v[u] = Y[(int64_t)c * k + s2] - R[(int64_t)s2 * k + sel[s]] * Y[(int64_t)c * k + s];
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int e = e0 + u * RC_T;
+        if (e < s * r) Y[(int64_t)(e / s) * k + e % s] = v[u];
+      }
     }
     __syncthreads();
   }
@@ -374,11 +388,28 @@ __device__ void rc_core(const RcDev& b, const double* __restrict__ scratch, int*
   }
   // W = R^T (rv x kq): column i holds row i of R
   double fro2 = 0.0;  // |K|_F^2 = |R|_F^2, which the rotations keep
-  for (int e = tid; e < kq * rv; e += RC_T) {
-    const int j = e % rv, i = e / rv;
-    const double x = j >= i ? K[(int64_t)j * k + i] : 0.0;
-    W[(int64_t)i * k + j] = x;
-    fro2 += x * x;
+  if (W != K) {
+    for (int e = tid; e < kq * rv; e += RC_T) {
+      const int j = e % rv, i = e / rv;
+      const double x = j >= i ? K[(int64_t)j * k + i] : 0.0;
+      W[(int64_t)i * k + j] = x;
+      fro2 += x * x;
+    }
+  } else {
+    // in place: R(i, j), j > i, sits at K[j k + i] and goes to K[i k + j]
+    // (below the diagonal of K: the Householder vectors, no longer needed);
+    // then the places it came from are cleared
+    for (int e = tid; e < kq * rv; e += RC_T) {
+      const int j = e % rv, i = e / rv;
+      if (j > i) W[(int64_t)i * k + j] = K[(int64_t)j * k + i];
+    }
+    __syncthreads();
+    for (int e = tid; e < kq * rv; e += RC_T) {
+      const int j = e % rv, i = e / rv;
+      if (j < i) W[(int64_t)i * k + j] = 0.0;  // R(j, i) read above (j < i < kq)
+      const double x = W[(int64_t)i * k + j];
+      fro2 += x * x;
+    }
   }
   fro2 = rc_block_sum(fro2, sh_sum);
   const double floor2 = RC_JFLOOR * fro2;
@@ -402,12 +433,22 @@ __device__ void rc_core(const RcDev& b, const double* __restrict__ scratch, int*
         if (q >= kq) continue;
         double* wp = W + (int64_t)p * k;
         double* wq = W + (int64_t)q * k;
+        // the lane's slices of both columns in registers: every load is
+        // issued before any store (the stores of a rotation would otherwise
+        // hold up the next loads by a memory latency each)
+        double xp[RC_PL], xq[RC_PL];
+#pragma unroll
+        for (int u = 0; u < RC_PL; ++u) {
+          const int i = gl + u * RC_LP;
+          xp[u] = i < rv ? wp[i] : 0.0;
+          xq[u] = i < rv ? wq[i] : 0.0;
+        }
         double al = 0.0, be = 0.0, ga = 0.0;
-        for (int i = gl; i < rv; i += RC_LP) {
-          const double x = wp[i], y = wq[i];
-          al += x * x;
-          be += y * y;
-          ga += x * y;
+#pragma unroll
+        for (int u = 0; u < RC_PL; ++u) {
+          al += xp[u] * xp[u];
+          be += xq[u] * xq[u];
+          ga += xp[u] * xq[u];
         }
         al = grp_sum(al);
         be = grp_sum(be);
@@ -423,10 +464,13 @@ __device__ void rc_core(const RcDev& b, const double* __restrict__ scratch, int*
           const double zeta = (be - al) / (2.0 * ga);
           const double tt = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
           const double c = 1.0 / sqrt(1.0 + tt * tt), sn = c * tt;
-          for (int i = gl; i < rv; i += RC_LP) {
-            const double x = wp[i], y = wq[i];
-            wp[i] = c * x - sn * y;
-            wq[i] = sn * x + c * y;
+#pragma unroll
+          for (int u = 0; u < RC_PL; ++u) {
+            const int i = gl + u * RC_LP;
+            if (i < rv) {
+              wp[i] = c * xp[u] - sn * xq[u];
+              wq[i] = sn * xp[u] + c * xq[u];
+            }
           }
           rotated = 1;
         }
@@ -606,8 +650,13 @@ void recompress_blocks(std::vector<RcDev>& blocks, const double* scratch, void* 
   // global-workspace kernel above
   std::vector<RcDev> bucket[4];
   for (const RcDev& b : blocks) bucket[b.k <= 16 ? 0 : b.k <= 32 ? 1 : b.k <= 64 ? 2 : 3].push_back(b);
-  // chunks bounded by a workspace budget (a block needs 8 k^2 doubles)
-  const int64_t budget = (int64_t)256 << 20;
+  // chunks bounded by a workspace budget (a block needs 8 k^2 doubles): one
+  // launch should hold enough blocks for several workgroups per compute
+  // unit, since each block's steps are latency-bound
+  int64_t need_all = 0;
+  for (const RcDev& b : blocks) need_all += recompress_work_doubles(b.k) * 8;
+  const int64_t budget = std::max<int64_t>(recompress_work_doubles(RC_KMAX) * 8,
+                                           std::min<int64_t>(need_all, (int64_t)2 << 30));
   DevBuf work;
   work.alloc((size_t)budget);
   std::vector<DevBuf> descs;
