@@ -26,6 +26,9 @@ Contents (each function cites the passage of the paper it follows):
                    ``vf_matfree.c``) and GMRES in place of LU
 * ``hlu``          hierarchical block LU of the reflection matrix (Sec. 5.1)
                    and its forward / backward substitution (Sec. 5.2)
+* ``fe``           finite-element coupling (Sec. 3.1-3.4): P1 surface
+                   elements, P, R_bar, S = P^T R_bar P, implicit Euler with
+                   Newton on the nodal residual
 
 Where the paper is silent the readings are fixed in the module docstrings.
 """
