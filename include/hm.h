@@ -386,6 +386,71 @@ hm_status hm_hlu_stats(const hm_hlu* lu, int64_t* bytes_device, int64_t* entries
                        double* factor_seconds);
 void hm_hlu_destroy(hm_hlu* lu);
 
+/* ------------------------------------------------------------- finite-element coupling */
+
+/* Sec. 3.1-3.4: nodal temperatures of a conducting shell whose P1 triangles
+ * are the cavity's facets, coupled to the radiation through
+ *   eta_M = T_M^4, eta_i = sum_M P_iM eta_M (P_iM = 1/3 for the vertices of
+ *   facet i: the facet average of the linear basis function),
+ *   R = sigma diag(eps A) F C^-1 diag(eps)  (eq. (Rdef) with this library's
+ *   normalised F), R_bar = R - diag(R 1)  (eq. (Rbardef)),
+ *   S = P^T R_bar P  (eq. (S_def_matrix)),  Q = S eta;
+ * implicit Euler on the Galerkin equations (eq. (SVF_Galerkin_time)):
+ *   Res(T) = M (T - T^n)/dt + K T - Q(T) - f,
+ * M the consistent mass (rho c_p h A/12 [[2,1,1],[1,2,1],[1,1,2]] per
+ * element), K the stiffness (k h (e_a . e_b)/(4A) per element, e_a the edge
+ * opposite vertex a), f_N = sum over the facets around N of f_i A_i / 3.
+ * Each Newton correction solves (M/dt + K - 4 S diag(T^3)) d = -Res by
+ * GMRES on the system preconditioned from the left with (M/dt + K)^-1
+ * (eq. (Jprec)), that inverse applied by conjugate gradients; every action
+ * of S costs one cavity solve (C^-1 by the H-matrix's Krylov solve). */
+typedef struct hm_fe hm_fe;
+typedef struct {
+  double conductance;      /* k h: conductivity times shell thickness (W/K), >= 0 */
+  double capacity;         /* rho c_p h: heat capacity per unit area (J/(m^2 K)), > 0 */
+  double dt;               /* implicit Euler step (s), > 0 */
+  double newton_rtol;      /* stop when |Res|_2 <= newton_rtol |M T^n / dt|_2 */
+  int32_t max_newton;      /* Newton corrections per step (>= 1) */
+  int32_t krylov_restart;  /* GMRES restart length (1..64) */
+  double krylov_rtol;      /* relative tolerance of each correction's preconditioned solve */
+  int32_t max_krylov;      /* Krylov iterations per correction (>= 1) */
+  double pc_rtol;          /* conjugate gradients for (M/dt + K)^-1 to this relative residual */
+  hm_solve_params solve;   /* the cavity solves (want_q and open_cavity ignored: closed cavity) */
+  double sigma;            /* Stefan-Boltzmann constant */
+} hm_fe_params;
+
+typedef struct {
+  int32_t newton;          /* Newton corrections taken */
+  int32_t krylov;          /* GMRES iterations over all corrections */
+  int32_t cavity_solves;   /* actions of S (each one solve with C) */
+  int32_t pc_iterations;   /* conjugate-gradient iterations over all preconditioner applications */
+  double residual;         /* final |Res|_2 / |M T^n / dt|_2 */
+  int32_t status;          /* HM_OK, or HM_ENOTCONV when max_newton was reached first */
+} hm_fe_info;
+
+/* F: the assembled H-matrix of the same facets (triangles in the same
+ * order; not copied: it must outlive the object).  vertices: HOST n_nodes x
+ * 3 (row-major); triangles: HOST n_facets x 3 vertex indices, oriented as
+ * for hm_facets_from_triangles; eps: DEVICE n_facets.  The mesh and
+ * eps are copied; the mass, stiffness and projection are built here.
+ * HM_EINVAL for sizes that do not match F, bad indices, degenerate
+ * triangles or parameters out of range. */
+hm_status hm_fe_create(hm_ctx* ctx, const hm_matrix* F, int64_t n_nodes, const double* vertices,
+                       int64_t n_facets, const int32_t* triangles, const double* eps, const hm_fe_params* p,
+                       hm_fe** out);
+/* Q = S T^4 for nodal temperatures T (DEVICE n_nodes in, DEVICE n_nodes
+ * out): the radiation load of eq. (flux_residual_3).  One cavity solve on
+ * ctx's stream (ctx on the object's device), which it synchronises. */
+hm_status hm_fe_cavity_load(hm_ctx* ctx, hm_fe* fe, const double* T, double* Q);
+/* One implicit Euler step: T_out (DEVICE n_nodes) from T_n (DEVICE
+ * n_nodes) with facet sources f_facet (DEVICE n_facets, W/m^2, or NULL for
+ * none); T_out may be T_n.  info may be NULL.  Returns HM_ENOTCONV (with the
+ * last iterate in T_out) when Newton did not reach newton_rtol.  Runs on
+ * ctx's stream and synchronises it.  Calls on one object must not overlap. */
+hm_status hm_fe_step(hm_ctx* ctx, hm_fe* fe, const double* T_n, const double* f_facet, double* T_out,
+                     hm_fe_info* info);
+void hm_fe_destroy(hm_fe* fe);
+
 /* ------------------------------------------------------------- serving */
 
 typedef struct {

@@ -776,6 +776,77 @@ void hm_hlu_destroy(hm_hlu* lu) {
   hlu_destroy(lu);
 }
 
+// ---- finite-element coupling
+hm_status hm_fe_create(hm_ctx* ctx, const hm_matrix* F, int64_t n_nodes, const double* vertices,
+                       int64_t n_facets, const int32_t* triangles, const double* eps, const hm_fe_params* p,
+                       hm_fe** out) {
+  if (!ctx) {
+    set_tl_error("hm_fe_create: NULL ctx");
+    return HM_EINVAL;
+  }
+  return guarded(ctx, [&] {
+    HM_REQUIRE(F && vertices && triangles && eps && p && out, "hm_fe_create: NULL argument");
+    HM_REQUIRE(p->conductance >= 0.0 && std::isfinite(p->conductance), "hm_fe_create: conductance must be >= 0");
+    HM_REQUIRE(p->capacity > 0.0 && std::isfinite(p->capacity), "hm_fe_create: capacity must be > 0");
+    HM_REQUIRE(p->dt > 0.0 && std::isfinite(p->dt), "hm_fe_create: dt must be > 0");
+    HM_REQUIRE(p->newton_rtol > 0.0 && p->max_newton >= 1, "hm_fe_create: bad Newton parameters");
+    HM_REQUIRE(p->krylov_restart >= 1 && p->krylov_restart <= 64 && p->max_krylov >= 1 && p->krylov_rtol > 0.0,
+               "hm_fe_create: bad Krylov parameters");
+    HM_REQUIRE(p->pc_rtol > 0.0 && p->pc_rtol < 1.0, "hm_fe_create: pc_rtol must be in (0, 1)");
+    HM_REQUIRE(p->sigma > 0.0 && std::isfinite(p->sigma), "hm_fe_create: sigma must be > 0");
+    check_params(&p->solve);
+    HM_REQUIRE(F->device == ctx->device, "hm_fe_create: matrix and context on different devices");
+    check_device_range(*ctx, eps, n_facets, n_facets, 1, 0.0, 1.0, true, "hm_fe_create: eps");
+    *out = fe_create(*ctx, *F, n_nodes, vertices, n_facets, triangles, eps, *p);
+  });
+}
+
+hm_status hm_fe_cavity_load(hm_ctx* c, hm_fe* fe, const double* T, double* Q) {
+  if (!c) {
+    set_tl_error("hm_fe_cavity_load: NULL ctx");
+    return HM_EINVAL;
+  }
+  hm_ctx& ctx = *c;
+  return guarded(c, [&] {
+    HM_REQUIRE(fe && T && Q, "hm_fe_cavity_load: NULL argument");
+    HM_REQUIRE(fe_device(*fe) == ctx.device, "hm_fe_cavity_load: object and context on different devices");
+    check_device_range(ctx, T, fe_nodes(*fe), fe_nodes(*fe), 1, 0.0, INFINITY, true, "hm_fe_cavity_load: T");
+    std::lock_guard<std::mutex> lk(const_cast<hm_matrix*>(fe_matrix(*fe))->mu);
+    fe_cavity_load(ctx, *fe, T, Q);
+  });
+}
+
+hm_status hm_fe_step(hm_ctx* c, hm_fe* fe, const double* T_n, const double* f_facet, double* T_out,
+                     hm_fe_info* info) {
+  if (!c) {
+    set_tl_error("hm_fe_step: NULL ctx");
+    return HM_EINVAL;
+  }
+  hm_ctx& ctx = *c;
+  hm_fe_info r{};
+  hm_status st = guarded(c, [&] {
+    HM_REQUIRE(fe && T_n && T_out, "hm_fe_step: NULL argument");
+    HM_REQUIRE(fe_device(*fe) == ctx.device, "hm_fe_step: object and context on different devices");
+    check_device_range(ctx, T_n, fe_nodes(*fe), fe_nodes(*fe), 1, 0.0, INFINITY, true, "hm_fe_step: T_n");
+    if (f_facet)
+      check_device_range(ctx, f_facet, fe_facets(*fe), fe_facets(*fe), 1, -INFINITY, INFINITY, false,
+                         "hm_fe_step: f_facet");
+    std::lock_guard<std::mutex> lk(const_cast<hm_matrix*>(fe_matrix(*fe))->mu);
+    r = fe_step(ctx, *fe, T_n, f_facet, T_out);
+  });
+  if (info) *info = r;
+  if (st == HM_OK && r.status != HM_OK) {
+    ctx.last_error = "hm_fe_step: Newton did not reach newton_rtol";
+    return HM_ENOTCONV;
+  }
+  return st;
+}
+
+void hm_fe_destroy(hm_fe* fe) {
+  if (!fe) return;
+  fe_destroy(fe);
+}
+
 hm_status hm_transient_run(hm_ctx* ctx, const hm_matrix* M, const double* eps, int32_t nrhs, double* T, int64_t ldT,
                            const double* src, int64_t ldS, double sigma, const hm_transient_params* tp,
                            const hm_solve_params* sp, double* history, hm_transient_info* info) {

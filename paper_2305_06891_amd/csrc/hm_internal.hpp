@@ -369,6 +369,17 @@ void launch_matvec_view(const CompView& V, int nrr, int vb, bool hi, const void*
 inline int pad_width(int nrhs) { return nrhs <= 1 ? 1 : nrhs <= 2 ? 2 : nrhs <= 4 ? 4 : nrhs <= 8 ? 8 : 16; }
 int64_t matrix_bytes(const hm_matrix& M, bool hi);
 
+// ---------------------------------------------------------------- finite-element coupling
+hm_fe* fe_create(hm_ctx& ctx, const hm_matrix& F, int64_t nn, const double* vtx, int64_t nf, const int32_t* tri,
+                 const double* eps, const hm_fe_params& p);
+void fe_cavity_load(hm_ctx& ctx, hm_fe& fe, const double* T, double* Q);
+hm_fe_info fe_step(hm_ctx& ctx, hm_fe& fe, const double* Tn, const double* f_facet, double* T_out);
+void fe_destroy(hm_fe* fe);
+int fe_device(const hm_fe& fe);
+const hm_matrix* fe_matrix(const hm_fe& fe);
+int64_t fe_nodes(const hm_fe& fe);
+int64_t fe_facets(const hm_fe& fe);
+
 struct LrInfo {
   BlockRef b;
   int32_t k;

@@ -49,7 +49,7 @@ __global__ void k_scatter(const SlotIO* __restrict__ io, int ns, int64_t N, int 
 // b = sigma eps T^4 and its cast; zero in padded columns
 template <class VT>
 __global__ void k_rhs(const double* __restrict__ eps, const double* __restrict__ T, int64_t N, int ncol,
-                      double sigma, double* __restrict__ b64, VT* __restrict__ bv) {
+                      double sigma, double* __restrict__ b64, VT* __restrict__ bv, int power) {
   const int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int j = blockIdx.y;
   if (row >= N) return;
@@ -58,7 +58,7 @@ __global__ void k_rhs(const double* __restrict__ eps, const double* __restrict__
   if (j < ncol) {
     const double t = T[k];
     const double t2 = t * t;
-    v = sigma * eps[row] * (t2 * t2);
+    v = sigma * eps[row] * (power ? t : t2 * t2);
   }
   if (b64) b64[k] = v;
   if (bv) bv[k] = (VT)v;
@@ -88,15 +88,16 @@ __global__ void k_acc(const VT* __restrict__ x, double* __restrict__ y, int64_t 
 // -sigma (1 - c) (T^4 - T_amb^4) with amb = 1 - c
 __global__ void k_flux(const double* __restrict__ eps, const double* __restrict__ T, const double* __restrict__ H,
                        const double* __restrict__ g, int64_t N, int ncol, double sigma, double* __restrict__ q,
-                       const double* __restrict__ amb, double tamb4) {
+                       const double* __restrict__ amb, double tamb4, int power) {
   const int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int j = blockIdx.y;
   if (row >= N || j >= ncol) return;
   const int64_t k = row + j * N;
   const double t = T[k];
   const double t2 = t * t;
-  double v = eps[row] * (H[k] - sigma * (t2 * t2) * g[row]);
-  if (amb) v = v - sigma * amb[row] * (t2 * t2 - tamb4);
+  const double e = power ? t : t2 * t2;  // radiation power eta
+  double v = eps[row] * (H[k] - sigma * e * g[row]);
+  if (amb) v = v - sigma * amb[row] * (e - tamb4);
   q[k] = v;
 }
 
@@ -309,7 +310,7 @@ void Batch::prepare_rhs(double sigma, const hm_solve_params& p, hipStream_t s) {
     hipLaunchKernelGGL(k_omeps<float>, grid_rows(N), dim3(256), 0, s, epsp.get<double>(), N, omeps32.get<float>());
   }
   hipLaunchKernelGGL(k_rhs<float>, grid_rows(N, W), dim3(256), 0, s, epsp.get<double>(), Tp.get<double>(), N, nrhs,
-                     sigma, b64.get<double>(), f32 ? b32.get<float>() : (float*)nullptr);
+                     sigma, b64.get<double>(), f32 ? b32.get<float>() : (float*)nullptr, power_in ? 1 : 0);
   HM_HIP(hipGetLastError());
 }
 
@@ -457,7 +458,7 @@ void Batch::flux(double sigma, hipStream_t s, bool have_fx) {
   if (!have_fx) launch_matvec(*C, nrhs, 8, true, x64.get(), N, H64.get(), N, Epilogue{}, nullptr, s);
   hipLaunchKernelGGL(k_flux, grid_rows(N, nrhs), dim3(256), 0, s, epsp.get<double>(), Tp.get<double>(),
                      H64.get<double>(), g.get<double>(), N, nrhs, sigma, H64.get<double>(),
-                     open ? (const double*)amb.get<double>() : (const double*)nullptr, tamb4);
+                     open ? (const double*)amb.get<double>() : (const double*)nullptr, tamb4, power_in ? 1 : 0);
   HM_HIP(hipGetLastError());
 }
 

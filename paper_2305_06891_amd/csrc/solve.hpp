@@ -54,6 +54,10 @@ struct Batch {
   DevBuf amb;
   bool amb_ready = false, open = false;
   double tamb4 = 0.0;
+  // the inputs T are radiation powers eta (any sign) instead of
+  // temperatures: the right-hand side is sigma eps eta, the flux
+  // eps (F J - sigma eta g) (the finite-element coupling's facet powers)
+  bool power_in = false;
 
   Batch(const std::vector<const hm_matrix*>& mats, int nrhs, hipStream_t s);
   Krylov& krylov(int vb, int restart, hipStream_t s);

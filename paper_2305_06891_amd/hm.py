@@ -53,6 +53,18 @@ class hm_solve_params(C.Structure):
                 ("ambient_temperature", C.c_double)]
 
 
+class hm_fe_params(C.Structure):
+    _fields_ = [("conductance", C.c_double), ("capacity", C.c_double), ("dt", C.c_double),
+                ("newton_rtol", C.c_double), ("max_newton", C.c_int32), ("krylov_restart", C.c_int32),
+                ("krylov_rtol", C.c_double), ("max_krylov", C.c_int32), ("pc_rtol", C.c_double),
+                ("solve", hm_solve_params), ("sigma", C.c_double)]
+
+
+class hm_fe_info(C.Structure):
+    _fields_ = [("newton", C.c_int32), ("krylov", C.c_int32), ("cavity_solves", C.c_int32),
+                ("pc_iterations", C.c_int32), ("residual", C.c_double), ("status", C.c_int32)]
+
+
 class hm_solve_info(C.Structure):
     _fields_ = [("iters", C.c_int32), ("outer_iters", C.c_int32), ("matvecs", C.c_int32),
                 ("rel_residual", C.c_double), ("seconds", C.c_double), ("bytes_moved", C.c_int64)]
@@ -125,6 +137,11 @@ _PROTOS = {
     "hm_hlu_stats": (C.c_int, [_vp, C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.POINTER(C.c_int32),
                                C.POINTER(C.c_double)]),
     "hm_hlu_destroy": (None, [_vp]),
+    "hm_fe_create": (C.c_int, [_vp, _vp, C.c_int64, _dp, C.c_int64, C.POINTER(C.c_int32), _vp,
+                               C.POINTER(hm_fe_params), C.POINTER(_vp)]),
+    "hm_fe_cavity_load": (C.c_int, [_vp, _vp, _vp, _vp]),
+    "hm_fe_step": (C.c_int, [_vp, _vp, _vp, _vp, _vp, C.POINTER(hm_fe_info)]),
+    "hm_fe_destroy": (None, [_vp]),
     "hm_server_create": (C.c_int, [_vp, C.POINTER(hm_server_params), C.POINTER(_vp)]),
     "hm_server_register_cavity": (C.c_int, [_vp, C.c_uint64, _vp, _dp, C.POINTER(hm_assembly_params)]),
     "hm_submit": (C.c_int, [_vp, C.c_uint64, C.c_int32, _dp, C.POINTER(C.c_uint64)]),
@@ -482,6 +499,73 @@ class HLU:
             self.close()
         except Exception:
             pass
+
+
+class FE:
+    """Finite-element coupling of a conducting shell with the cavity
+    (``hm_fe_create``): nodal temperatures, radiation load and implicit
+    Euler steps."""
+
+    def __init__(self, h, ctx, n_nodes, n_facets):
+        self._h = h
+        self.ctx = ctx
+        self.n_nodes = n_nodes
+        self.n_facets = n_facets
+
+    def cavity_load(self, T, Q=None):
+        """Q = S T^4 for device float64 nodal temperatures T."""
+        import torch
+        if Q is None:
+            Q = torch.empty_like(T)
+        _check(lib.hm_fe_cavity_load(self.ctx.handle, self._h, _dev_ptr(T, torch.float64),
+                                     _dev_ptr(Q, torch.float64)), self.ctx.handle)
+        return Q
+
+    def step(self, T_n, f_facet=None, T_out=None, check=True):
+        """One implicit Euler step; returns (T_out, info dict)."""
+        import torch
+        if T_out is None:
+            T_out = torch.empty_like(T_n)
+        info = hm_fe_info()
+        fp = _dev_ptr(f_facet, torch.float64) if f_facet is not None else None
+        st = lib.hm_fe_step(self.ctx.handle, self._h, _dev_ptr(T_n, torch.float64), fp,
+                            _dev_ptr(T_out, torch.float64), C.byref(info))
+        if check:
+            _check(st, self.ctx.handle)
+        return T_out, {"newton": info.newton, "krylov": info.krylov, "cavity_solves": info.cavity_solves,
+                       "pc_iterations": info.pc_iterations, "residual": info.residual, "status": info.status}
+
+    def close(self):
+        if self._h:
+            lib.hm_fe_destroy(self._h)
+            self._h = _vp()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def fe_params(conductance, capacity, dt, newton_rtol=1e-12, max_newton=20, krylov_restart=30, krylov_rtol=1e-10,
+              max_krylov=200, pc_rtol=1e-12, solve=None, sigma=None) -> hm_fe_params:
+    return hm_fe_params(float(conductance), float(capacity), float(dt), float(newton_rtol), int(max_newton),
+                        int(krylov_restart), float(krylov_rtol), int(max_krylov), float(pc_rtol),
+                        solve if solve is not None else solve_params(rtol=1e-12),
+                        float(SIGMA if sigma is None else sigma))
+
+
+def hm_fe_create(ctx, M: "HMatrix", vertices, triangles, eps, params: hm_fe_params) -> FE:
+    """vertices (n_nodes x 3) and triangles (n_facets x 3) on the host, eps a
+    device float64 vector in facet order; M the H-matrix of those facets."""
+    import torch
+    v = np.ascontiguousarray(vertices, dtype=np.float64)
+    t = np.ascontiguousarray(triangles, dtype=np.int32)
+    h = _vp()
+    _check(lib.hm_fe_create(ctx.handle, M._h, v.shape[0], v.ctypes.data_as(_dp), t.shape[0],
+                            t.ctypes.data_as(C.POINTER(C.c_int32)), _dev_ptr(eps, torch.float64),
+                            C.byref(params), C.byref(h)), ctx.handle)
+    return FE(h, ctx, v.shape[0], t.shape[0])
 
 
 def hm_hlu_factor(ctx, tree: Tree, eps, aca_tol=1e-6, k_max=256, aca_pivot=0) -> HLU:
