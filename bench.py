@@ -16,12 +16,15 @@ Workload ``c2``: the 20,176-facet jittered cylinder, plain FP32 H-solve.
 
 Prints ONE JSON line on stdout (progress goes to stderr).
 
-Default (``--workload all``): the ``c3`` record is the headline; the ``c4``
-transient and ``c5`` serving records ride along on the same JSON line
-(keys ``c4_transient`` and ``c5_serving``), each with its own value,
-roofline or latency figures and oracle baseline.
+Workload ``fe``: the finite-element coupling (Sec. 3.1-3.4), implicit Euler
+steps of a conducting 20,480-facet ellipsoid shell with cavity radiation.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload all|c3|c2|c4|c5]
+Default (``--workload all``): the ``c3`` record is the headline; the ``c4``
+transient, ``c5`` serving and ``fe`` coupling records ride along on the same
+JSON line (keys ``c4_transient``, ``c5_serving`` and ``fe_coupling``), each
+with its own value, roofline or latency figures and oracle baseline.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload all|c3|c2|c4|c5|fe]
 """
 import argparse
 import json
@@ -532,6 +535,86 @@ def cpu_baseline_transient(n, newton_per_step):
             "seconds_per_step": total / steps}
 
 
+def cpu_baseline_fe(n_facets, n_nodes):
+    """The oracle's finite-element step (dense F, R_bar from a dense solve
+    with C, dense S, Newton with the exact dense Jacobian) on the 2,000-facet
+    member of the same shell family, each part after a warm-up as the best of
+    three, scaled to the workload: F x(n/ns)^2, R_bar x(n/ns)^3, S and the
+    Newton solves x(nn/nns)^3."""
+    from oracle import fe, geometry, viewfactor
+    from workloads import configs
+    cav = configs.fe_shell(nu=10)
+    c, nrm, area = geometry.facets_from_triangles(cav.v, cav.tri)
+    ns, nns = cav.n, cav.v.shape[0]
+    x = cav.extra
+    t_f, F = _best_of(lambda: viewfactor.view_factor_matrix(c, nrm, area))
+    t_r, Rb = _best_of(lambda: fe.exchange_matrix(F, cav.eps, area))
+    M, K, P = fe.surface_p1(cav.v, cav.tri, x["conductance"], x["capacity"])
+    fN = fe.nodal_load(cav.tri, area, x["source"], nns)
+
+    def step():
+        S = fe.cavity_operator(P, Rb)
+        return fe.newton_step(cav.T[:, 0], x["dt"], M, K, S, fN, tol=1e-10)
+
+    t_s, _ = _best_of(step)
+    total = t_f * (n_facets / ns) ** 2 + t_r * (n_facets / ns) ** 3 + t_s * (n_nodes / nns) ** 3
+    return {"value": 1.0 / total, "unit": "steps/s", "cores": _blas_threads(), "kind": "oracle",
+            "sample": "dense FP64 oracle finite-element step on the %d-facet shell (F %.2f s, R_bar %.2f s, S and "
+                      "Newton %.2f s) scaled to %d facets and %d nodes" % (ns, t_f, t_r, t_s, n_facets, n_nodes)}
+
+
+def run_fe(args):
+    """Finite-element coupling (Sec. 3.1-3.4): implicit Euler steps of the
+    conducting ellipsoid shell (20,480 facets, 10,242 nodes) with cavity
+    radiation, FP64 H-matrix (leaf 64, eta 1.5, ACA 1e-6), Newton-Krylov with
+    the sparse part as preconditioner; every step starts from the seeded
+    temperatures (the same work each time)."""
+    import torch
+    from paper_2305_06891_amd import hm
+    from workloads import configs
+
+    cav = configs.fe_shell()
+    x = cav.extra
+    ctx = hm.Context(0)
+    c, nrm, area = hm.hm_facets_from_triangles(cav.v, cav.tri, orient=1)
+    tree = hm.hm_build_cluster_tree(ctx, c, nrm, area, cav.leaf, cav.eta)
+    M = hm.hm_assemble_hmatrix(ctx, tree, cav.aca_tol, 256, hm.HM_F64, hm.HM_F64, recompress=args.recompress)
+    dev = torch.device("cuda:0")
+    eps = torch.as_tensor(cav.eps, device=dev)
+    p = hm.fe_params(x["conductance"], x["capacity"], x["dt"], newton_rtol=1e-10, krylov_rtol=1e-8, pc_rtol=1e-10,
+                     solve=hm.solve_params(rtol=1e-12, restart=30, max_iter=600))
+    obj = hm.hm_fe_create(ctx, M, cav.v, cav.tri, eps, p)
+    T0 = torch.as_tensor(np.ascontiguousarray(cav.T[:, 0]), device=dev)
+    src = torch.as_tensor(x["source"], device=dev)
+    T1, info = obj.step(T0, src)  # warm-up
+    torch.cuda.synchronize()
+    steps = 3
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        T1, info = obj.step(T0, src)
+    torch.cuda.synchronize()
+    sec = (time.perf_counter() - t0) / steps
+    # the heat content changes only by the sources (any size): sum_N (M (T1 - T0))_N / dt = sum_i A_i f_i
+    q_load = obj.cavity_load(T1)
+    torch.cuda.synchronize()
+    a = np.asarray(area)
+    nodes = cav.v.shape[0]
+    out = {"metric": "finite-element implicit Euler steps/s (conduction + cavity radiation)", "value": 1.0 / sec,
+           "unit": "steps/s", "ms_per_step": 1e3 * sec, "steps": steps, "dtype": "f64",
+           "config": {"workload": cav.name, "facets": cav.n, "nodes": nodes, "leaf": cav.leaf, "eta": cav.eta,
+                      "aca_tol": cav.aca_tol, "conductance": x["conductance"], "capacity": x["capacity"],
+                      "dt": x["dt"], "newton_rtol": 1e-10, "cavity_solve_rtol": 1e-12},
+           "step": info,
+           "ms_per_cavity_solve_upper_bound": 1e3 * sec / max(1, info["cavity_solves"]),
+           "radiation_load_sum_rel": float(abs(q_load.sum().item()) / torch.linalg.norm(q_load).item()),
+           "source_power_W": float((a * x["source"]).sum())}
+    log("fe: %.1f ms/step; %s" % (1e3 * sec, info))
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline_fe(cav.n, nodes)
+    obj.close()
+    return out
+
+
 def run_c5(args):
     """Serving: a stream of radiosity-solve requests on 256 cavity ids
     (1k-100k facets, Zipf 1.1 over ids, 1-8 right-hand sides), BF16 factors
@@ -715,7 +798,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50, help="timed batched solves of the 64-cavity workload")
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="all", choices=["all", "c3", "c2", "c4", "c5"],
+    ap.add_argument("--workload", default="all", choices=["all", "c3", "c2", "c4", "c5", "fe"],
                     help="all: the 64-cavity batch (the headline record) with the transient and serving "
                          "records attached to the same line")
     ap.add_argument("--recompress", type=int, default=1, choices=[0, 1],
@@ -742,8 +825,10 @@ def main():
         out["c4_transient"] = run_c4(args)
         gc.collect()
         out["c5_serving"] = run_c5(args)
+        gc.collect()
+        out["fe_coupling"] = run_fe(args)
     else:
-        out = {"c3": run_c3, "c2": run_c2, "c4": run_c4, "c5": run_c5}[args.workload](args)
+        out = {"c3": run_c3, "c2": run_c2, "c4": run_c4, "c5": run_c5, "fe": run_fe}[args.workload](args)
     print(json.dumps(out), flush=True)
 
 

@@ -10,14 +10,14 @@ oracle's dense definition (oracle/fe.py), FP64 H-matrix (ACA 1e-10).
   and 1^T S = 0): to 1e-8 of the source power.
 * A uniform temperature without sources stays at rest.
 
-Geometries: an icosphere shell (level 3) and an ellipsoid shell (axes
-3, 2, 1), 1,280 facets each.
+Geometries: an icosphere shell (level 3) and the bench's ellipsoid shell
+family (axes 4, 2, 1) at 1,280 facets, 642 nodes each.
 """
 import numpy as np
 import pytest
 
 from oracle import fe, geometry, viewfactor
-from workloads import meshes
+from workloads import configs, meshes
 
 from gpu_common import dt, log, rel, to_np
 
@@ -37,8 +37,12 @@ def ctx(hm):
 
 @pytest.fixture(scope="module", params=["icosphere", "ellipsoid"])
 def shell(hm, ctx, request):
-    v, f = meshes.icosphere(3) if request.param == "icosphere" else meshes.ellipsoid(8, (3.0, 2.0, 1.0))
-    f = meshes.inward(f)
+    if request.param == "icosphere":
+        v, f = meshes.icosphere(3)
+        f = meshes.inward(f)
+    else:
+        cav = configs.fe_shell(nu=8)
+        v, f = cav.v, cav.tri
     c, n, a = geometry.facets_from_triangles(v, f)
     F = viewfactor.view_factor_matrix(c, n, a)
     eps = np.random.default_rng(21).uniform(0.2, 0.9, a.size)

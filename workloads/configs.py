@@ -112,6 +112,26 @@ def c4_ellipsoid(nu: int = 100, scenarios: int = 16) -> Cavity:
                   extra={"source": src, "mc": 1.0e4, "dt": 1.0})
 
 
+def fe_shell(nu: int = 32) -> Cavity:
+    """Conducting ellipsoid shell (semi-axes 4, 2, 1; frequency ``nu``:
+    20 nu^2 facets, 10 nu^2 + 2 nodes, watertight) for the finite-element
+    coupling: eps ~ U[0.2, 0.9] per facet, nodal T0 ~ U[300, 1000] K and facet
+    sources ~ U[0, 500] W m^-2 from seed 600; shell conductance k h = 5 W/K,
+    capacity rho c h = 2e3 J m^-2 K^-1, implicit Euler with dt = 1 s.  The
+    cavity's T field holds the nodal temperatures (one column)."""
+    v, f = meshes.ellipsoid(nu, (4.0, 2.0, 1.0))
+    # one node per position: the mesh generator repeats the vertices on the
+    # seams between its patches, which would cut the conducting shell there
+    uniq, inv = np.unique(np.round(v, 12), axis=0, return_inverse=True)
+    v, f = uniq, inv.reshape(-1)[f].astype(f.dtype)
+    rng = np.random.default_rng(600)
+    eps = rng.uniform(0.2, 0.9, f.shape[0])
+    T0 = rng.uniform(300.0, 1000.0, v.shape[0])
+    src = rng.uniform(0.0, 500.0, f.shape[0])
+    return Cavity(f"fe_shell_{f.shape[0]}", v, meshes.inward(f), eps, T0[:, None],
+                  extra={"source": src, "conductance": 5.0, "capacity": 2.0e3, "dt": 1.0})
+
+
 def c5_cavity(cid: int, n_lo: int = 1000, n_hi: int = 100000) -> Cavity:
     """Cavity id ``cid`` of the serving workload: type, facet count
     (log-uniform in [n_lo, n_hi]), axes and per-facet eps ~ U[0.1, 0.9] are
