@@ -458,18 +458,20 @@ GmresStats gmres_t(Krylov& K, bool hi, const void* omeps, const void* b, void* x
   int iters = 0;
   bool first = true;
   for (;;) {
-    // true residual and its norm (b itself for a zero start)
+    // true residual and its norm (b itself for a zero start: its norms are
+    // the ones just taken, in K.beta and bn)
     if (first && (opts & GM_X0_ZERO)) {
       HM_HIP(hipMemcpyAsync(K.basis.get(), b, (size_t)K.blk * K.vb, hipMemcpyDeviceToDevice, s));
+      std::copy(bn, bn + ns, beta);
     } else {
       launch_matvec(C, nrr, K.vb, hi, x, K.ld, K.basis.get(), K.ld, res_ep, nullptr, s);
       st.matvecs++;
       st.bytes += mbytes;
+      run_gs<VT>(K, 3, 0, K.basis.get(), s);
+      HM_HIP(hipMemcpyAsync(beta, K.beta.get(), ns * 8, hipMemcpyDeviceToHost, s));
+      HM_HIP(hipStreamSynchronize(s));
     }
     first = false;
-    run_gs<VT>(K, 3, 0, K.basis.get(), s);
-    HM_HIP(hipMemcpyAsync(beta, K.beta.get(), ns * 8, hipMemcpyDeviceToHost, s));
-    HM_HIP(hipStreamSynchronize(s));
     int nact = 0;
     std::fill(cnt, cnt + nslots, 0);
     for (int q = 0; q < ns; ++q) {

@@ -386,7 +386,10 @@ SolveResult Batch::solve_prepared(const hm_solve_params& p, hipStream_t s, bool 
         R.matvecs++;
         R.bytes += masked ? masked_bytes : C->bytes_hi;
       }
-      block_norms(K8, r64.get(), rn, s);
+      if (outer == 0 && !warm)
+        rn = bn;  // r = b
+      else
+        block_norms(K8, r64.get(), rn, s);
       bool done = true, nonfinite = false;
       R.rel_res.resize(rn.size());
       for (size_t q = 0; q < rn.size(); ++q) {
