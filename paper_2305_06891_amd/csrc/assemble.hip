@@ -544,7 +544,8 @@ __global__ __launch_bounds__(256) void k_v_pack(const VRepack* __restrict__ vr, 
     const int pc = d.lc0 + l;
     const int g = pc / P1_GW, lp = pc % P1_GW;
     const int gw = min(P1_GW, d.ktau - g * P1_GW);
-    const int64_t o = d.tau_base + (int64_t)g * P1_GW * d.np + ((int64_t)(r >> 2) * gw + lp) * 4 + (r & 3);
+    const int gs = gw + (gw & 1);  // stored columns (an odd panel carries a zero column)
+    const int64_t o = d.tau_base + (int64_t)g * P1_GW * d.np + ((int64_t)(r >> 2) * gs + lp) * 4 + (r & 3);
     const double x = (double)src[e];
     out[o] = round_factor<OT>(x, dither != 0, 2u, (uint32_t)(d.cb + r), (uint32_t)d.rb, (uint32_t)l);
     if (out_hi) out_hi[o] = (float)x;

@@ -166,7 +166,7 @@ struct P1Item {
   int32_t xrow;     // permuted x row of the cluster's first row
   int32_t trow;     // t index of the group's first column
   int32_t part;     // partial slot of this item; -1: write t directly
-  int32_t pad;
+  int32_t gs;       // stored columns of the group panel: gw rounded up to even
 };
 
 // Groups whose rows are split over several items: t = sum of their partials
@@ -196,7 +196,9 @@ struct Seg {
 };
 
 // One column cluster tau of the low-rank blocks: its V factors form
-// ceil(ktau / P1_GW) group panels of np rows (n rounded up to 4).
+// ceil(ktau / P1_GW) group panels of np rows (n rounded up to 4); a panel
+// of odd width carries one zero column, so every panel row of two adjacent
+// columns starts on a 16-byte boundary.
 struct P1Tau {
   int64_t vbase;    // element offset of the first group panel
   int64_t trow;     // t index of rank column 0

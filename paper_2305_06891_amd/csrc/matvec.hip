@@ -73,7 +73,7 @@ void plan_host(hm_matrix& M, const std::vector<LrInfo>& lr, const std::vector<Bl
       lc += L.k;
     }
     P.taus.push_back(P1Tau{tau_base, tcur, b0.cb, n, np, ktau});
-    vcur += (int64_t)np * ktau;
+    vcur += (int64_t)np * (ktau + (ktau & 1));
     tcur += ktau;
     q = e;
   }
@@ -210,6 +210,7 @@ void plan_phase1(Plan& P, const P1Params& pp) {
         P1Item it{};
         it.base = T.vbase + (int64_t)g * P1_GW * T.np;
         it.gw = gw;
+        it.gs = gw + (gw & 1);
         it.q0 = c * qch;
         it.nq = std::min(qch, nq - c * qch);
         it.nrows = T.n;
@@ -718,74 +719,189 @@ __device__ __forceinline__ double lane_bcast(double v, int l) {
   return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
-// Phase 1: lane l owns rank column l of a group panel: t[trow + l] (+ j*ldt)
-// = sum_r V(r, l) x(xrow + r).  The rows of an item go in batches of UN
-// quads (about 8 KB per wave whatever the stored type): the x entries of a
-// batch come with one coalesced load (lane = row) and reach every lane by
-// lane broadcast.  The loads of the next batch are issued before the
-// current one is used, so each wave keeps two batches in flight (no load of
-// a pipelined batch sits behind a branch); with one right-hand side an
+// Phase 1: t[trow + c] (+ j*ldt) = sum_r V(r, c) x(xrow + r) for the rank
+// columns c of a group panel.  The rows of an item go in batches of UN
+// quads (64 rows with BF16 entries); the x entries of a batch come with one
+// coalesced load (lane = row).  The loads of the next batch are issued before
+// the current one is used, so each wave keeps two batches in flight (no load
+// of a pipelined batch sits behind a branch); with one right-hand side an
 // item's last, partial batch loads its quads in groups of four instead of
 // re-reading its last quad; rows past the item meet x = 0.
+//
+// FP32 and FP64 entries: lane l owns column l, reads one quad (16 or 32
+// bytes) per row quad and takes x by lane broadcast.
+// BF16 entries (8-byte quads): lane l owns the column pair 2 (l mod 32),
+// 2 (l mod 32) + 1 and reads the pair's two quads of a row quad with one
+// 16-byte load (panel rows of two columns start on 16-byte boundaries);
+// lanes 0-31 take the even row quads of a batch and lanes 32-63 the odd
+// ones, so a wave moves 1 KB per load instruction instead of 512 bytes.
+// The halves need different x entries, which they read from the wave's LDS
+// copy of the batch's x (one read per row quad), and they add their sums
+// across halves at the end of the item.
 template <class LT>
 constexpr int p1_batch_quads() {
   return (int)(128 / sizeof(Quad<LT>));
 }
 
+template <class VT, int NR>
+__device__ __forceinline__ void p1_load_x(VT (&x)[NR], bool& ok, const VT* xr, int64_t ldx, int nrr, int nrows, int qb,
+                                          int qe, int nq_batch, int lane) {
+  const int row = qb * 4 + lane;
+  ok = lane < 4 * nq_batch && row < 4 * qe && row < nrows;
+  const int rr = min(row, nrows - 1);
+#pragma unroll
+  for (int j = 0; j < NR; ++j) x[j] = gbl(xr)[rr + (int64_t)min(j, nrr - 1) * ldx];
+}
+
+// lane = column: UN quads of one column
 template <class LT, class VT, int NR, int UN>
 struct P1Batch {
   Quad<LT> v[UN];
   VT x[NR];
   bool ok;  // this lane's x row lies inside the item and the cavity
-};
 
-template <class LT, class VT, int NR, int UN>
-__device__ __forceinline__ void p1_issue(P1Batch<LT, VT, NR, UN>& b, const LT* a, int64_t step, int qb, int qe,
-                                         const VT* xr, int64_t ldx, int nrr, int nrows, int lane) {
-  const int row = qb * 4 + lane;
-  b.ok = lane < 4 * UN && row < 4 * qe && row < nrows;
-  const int rr = min(row, nrows - 1);
+  // TAIL: the last, partial batch of an item: its quads are loaded in
+  // groups of four (uniform branches), so at most three quads past the item
+  // are read.  Otherwise quads past the item re-read its last quad.
+  template <bool TAIL>
+  __device__ __forceinline__ void issue(const LT* a, int64_t step, int qb, int qe, const VT* xr, int64_t ldx, int nrr,
+                                        int nrows, int lane) {
+    p1_load_x<VT, NR>(x, ok, xr, ldx, nrr, nrows, qb, qe, UN, lane);
 #pragma unroll
-  for (int j = 0; j < NR; ++j) b.x[j] = gbl(xr)[rr + (int64_t)min(j, nrr - 1) * ldx];
+    for (int g = 0; g < UN; g += 4) {
+      if (!TAIL || qb + g < qe) {
 #pragma unroll
-  for (int u = 0; u < UN; ++u) b.v[u].load(a + (int64_t)min(qb + u, qe - 1) * step);
-}
-
-// The last, partial batch of an item: its quads are loaded in groups of
-// four (uniform branches), so at most three quads past the item are read.
-template <class LT, class VT, int NR, int UN>
-__device__ __forceinline__ void p1_issue_tail(P1Batch<LT, VT, NR, UN>& b, const LT* a, int64_t step, int qb, int qe,
-                                              const VT* xr, int64_t ldx, int nrr, int nrows, int lane) {
-  const int row = qb * 4 + lane;
-  b.ok = lane < 4 * UN && row < 4 * qe && row < nrows;
-  const int rr = min(row, nrows - 1);
+        for (int u = g; u < g + 4; ++u) v[u].load(a + (int64_t)min(qb + u, qe - 1) * step);
+      } else {
 #pragma unroll
-  for (int j = 0; j < NR; ++j) b.x[j] = gbl(xr)[rr + (int64_t)min(j, nrr - 1) * ldx];
-#pragma unroll
-  for (int g = 0; g < UN; g += 4) {
-    if (qb + g < qe) {
-#pragma unroll
-      for (int u = g; u < g + 4; ++u) b.v[u].load(a + (int64_t)min(qb + u, qe - 1) * step);
-    } else {
-#pragma unroll
-      for (int u = g; u < g + 4; ++u) b.v[u].zero();
+        for (int u = g; u < g + 4; ++u) v[u].zero();
+      }
     }
   }
+
+  __device__ __forceinline__ void use(int nrr, VT* acc) const {
+    VT xm[NR];
+#pragma unroll
+    for (int j = 0; j < NR; ++j) xm[j] = (ok && j < nrr) ? x[j] : VT(0);
+#pragma unroll
+    for (int u = 0; u < UN; ++u)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const VT w = v[u].template get<VT>(e);
+#pragma unroll
+        for (int j = 0; j < NR; ++j) acc[j] += w * lane_bcast(xm[j], u * 4 + e);
+      }
+  }
+};
+
+using u32x4 = uint32_t __attribute__((ext_vector_type(4)));
+
+// The four x entries of a row quad from LDS (16-byte aligned).
+__device__ __forceinline__ void lds_quad(const float* p, float (&q)[4]) {
+  const f32x4 v = *reinterpret_cast<const f32x4*>(p);
+#pragma unroll
+  for (int e = 0; e < 4; ++e) q[e] = v[e];
+}
+__device__ __forceinline__ void lds_quad(const double* p, double (&q)[4]) {
+  const f64x2 a = reinterpret_cast<const f64x2*>(p)[0], b = reinterpret_cast<const f64x2*>(p)[1];
+  q[0] = a[0];
+  q[1] = a[1];
+  q[2] = b[0];
+  q[3] = b[1];
 }
 
-template <class LT, class VT, int NR, int UN>
-__device__ __forceinline__ void p1_use(const P1Batch<LT, VT, NR, UN>& b, int nrr, VT* acc) {
-  VT xm[NR];
+// lane = column pair (BF16 entries): UN / 2 row quads of two columns, row
+// quad qb + 2u + h (h = lane / 32) in v[u]; quad words 0-1 hold the first
+// column, 2-3 the second.
+template <class VT, int NR, int UN>
+struct P1Pair {
+  u32x4 v[UN / 2];
+  VT x[NR];
+  bool ok;
+
+  template <bool TAIL>
+  __device__ __forceinline__ void issue(const bf16_t* a, int64_t step, int h, int qb, int qe, const VT* xr, int64_t ldx,
+                                        int nrr, int nrows, int lane) {
+    p1_load_x<VT, NR>(x, ok, xr, ldx, nrr, nrows, qb, qe, UN, lane);
 #pragma unroll
-  for (int j = 0; j < NR; ++j) xm[j] = (b.ok && j < nrr) ? b.x[j] : VT(0);
+    for (int g = 0; g < UN / 2; g += 2) {
+      if (!TAIL || qb + 2 * g < qe) {
 #pragma unroll
-  for (int u = 0; u < UN; ++u)
+        for (int u = g; u < g + 2; ++u)
+          v[u] = ld_stream(reinterpret_cast<const u32x4*>(a + (int64_t)min(qb + 2 * u + h, qe - 1) * step));
+      } else {
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      const VT w = b.v[u].template get<VT>(e);
-#pragma unroll
-      for (int j = 0; j < NR; ++j) acc[j] += w * lane_bcast(xm[j], u * 4 + e);
+        for (int u = g; u < g + 2; ++u) v[u] = u32x4{0u, 0u, 0u, 0u};
+      }
     }
+  }
+
+  // xl: the wave's LDS copy of the batch's x (64 * NR entries)
+  __device__ __forceinline__ void use(int nrr, int lane, int h, VT* xl, VT* acc0, VT* acc1) const {
+#pragma unroll
+    for (int j = 0; j < NR; ++j) xl[j * 64 + lane] = (ok && j < nrr) ? x[j] : VT(0);
+    wave_lds_sync();
+#pragma unroll
+    for (int u = 0; u < UN / 2; ++u) {
+      VT w0[4], w1[4];
+#pragma unroll
+      for (int k = 0; k < 2; ++k) {
+        w0[2 * k] = (VT)__uint_as_float(v[u][k] << 16);
+        w0[2 * k + 1] = (VT)__uint_as_float(v[u][k] & 0xffff0000u);
+        w1[2 * k] = (VT)__uint_as_float(v[u][2 + k] << 16);
+        w1[2 * k + 1] = (VT)__uint_as_float(v[u][2 + k] & 0xffff0000u);
+      }
+#pragma unroll
+      for (int j = 0; j < NR; ++j) {
+        VT xq[4];
+        lds_quad(xl + j * 64 + (2 * u + h) * 4, xq);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          acc0[j] += w0[e] * xq[e];
+          acc1[j] += w1[e] * xq[e];
+        }
+      }
+    }
+    wave_lds_sync();  // the reads are done before the next batch is written
+  }
+};
+
+// The batches of one item [q0, q0 + nq): full batches with the next one in
+// flight; with one right-hand side a partial last batch loads only its quads
+// (with more, its loads are better kept in the pipeline: clamped quads).
+template <class B, int UN, int NR, class Issue, class Use>
+__device__ __forceinline__ void p1_batches(int q0, int nq, Issue issue, Use use) {
+  const int qe = q0 + nq;
+  const int qf = NR == 1 ? q0 + (nq / UN) * UN : qe;  // end of the pipelined batches
+  int qb = q0;
+  if (qb < qf) {
+    B A, C;
+    issue(A, qb, false);
+    for (;;) {
+      if (qb + UN >= qf) {
+        use(A);
+        break;
+      }
+      issue(C, qb + UN, false);
+      use(A);
+      qb += UN;
+      if (qb + UN >= qf) {
+        use(C);
+        break;
+      }
+      issue(A, qb + UN, false);
+      use(C);
+      qb += UN;
+    }
+    qb = qf;
+  }
+  if constexpr (NR == 1) {
+    if (qb < qe) {
+      B T;
+      issue(T, qb, true);
+      use(T);
+    }
+  }
 }
 
 template <class LT, class VT, int NR, int WPB>
@@ -793,6 +909,8 @@ __global__ __launch_bounds__(64 * WPB) void k_phase1(const SlotDev* __restrict__
                                                      const int* __restrict__ slot_active, int nrr,
                                                      const VT* __restrict__ X, int64_t ldx) {
   constexpr int UN = p1_batch_quads<LT>();
+  constexpr bool PAIR = sizeof(LT) == 2;
+  __shared__ __align__(16) VT p1x[PAIR ? WPB : 1][PAIR ? 64 * NR : 1];
   const int lane = threadIdx.x & 63;
   const int wv = uniform_int(threadIdx.x >> 6);  // wave index (uniform)
   const int task = blockIdx.x * WPB + wv;
@@ -805,57 +923,65 @@ __global__ __launch_bounds__(64 * WPB) void k_phase1(const SlotDev* __restrict__
   VT* T = (VT*)S.t;
   for (int it = ib; it < ie; ++it) {
     const P1Item item = uniform_load(S.p1 + it);
-    const bool act = lane < item.gw;
-    // lanes past the group's columns repeat its last column (not stored)
-    const LT* a = (const LT*)S.V + item.base + (int64_t)(act ? lane : item.gw - 1) * 4;
-    const int64_t step = (int64_t)item.gw * 4;
+    const int64_t step = (int64_t)item.gs * 4;
     const VT* xr = Xs + item.xrow;
     const int qe = item.q0 + item.nq;
-    VT acc[NR];
+    VT res[NR];
+    int col;  // the column whose sums this lane stores
+    if constexpr (PAIR) {
+      const int h = lane >> 5;
+      // lanes past the group's columns repeat its last pair (not stored)
+      const int pc = min(lane & 31, (item.gs >> 1) - 1);
+      const bf16_t* a = (const bf16_t*)S.V + item.base + (int64_t)pc * 8;
+      VT* xl = p1x[wv];
+      VT acc0[NR], acc1[NR];
 #pragma unroll
-    for (int j = 0; j < NR; ++j) acc[j] = VT(0);
-    // full batches, the next one in flight while the current one is used;
-    // with one right-hand side a partial last batch loads only its quads
-    // (with more, its loads are better kept in the pipeline: clamped quads)
-    const int qf = NR == 1 ? item.q0 + (item.nq / UN) * UN : qe;  // end of the pipelined batches
-    int qb = item.q0;
-    if (qb < qf) {
-      P1Batch<LT, VT, NR, UN> A, B;
-      p1_issue(A, a, step, qb, qe, xr, ldx, nrr, item.nrows, lane);
-      for (;;) {
-        if (qb + UN >= qf) {
-          p1_use(A, nrr, acc);
-          break;
-        }
-        p1_issue(B, a, step, qb + UN, qe, xr, ldx, nrr, item.nrows, lane);
-        p1_use(A, nrr, acc);
-        qb += UN;
-        if (qb + UN >= qf) {
-          p1_use(B, nrr, acc);
-          break;
-        }
-        p1_issue(A, a, step, qb + UN, qe, xr, ldx, nrr, item.nrows, lane);
-        p1_use(B, nrr, acc);
-        qb += UN;
+      for (int j = 0; j < NR; ++j) acc0[j] = acc1[j] = VT(0);
+      using B = P1Pair<VT, NR, UN>;
+      p1_batches<B, UN, NR>(
+          item.q0, item.nq,
+          [&](B& b, int qb, bool tail) {
+            if (tail)
+              b.template issue<true>(a, step, h, qb, qe, xr, ldx, nrr, item.nrows, lane);
+            else
+              b.template issue<false>(a, step, h, qb, qe, xr, ldx, nrr, item.nrows, lane);
+          },
+          [&](const B& b) { b.use(nrr, lane, h, xl, acc0, acc1); });
+      // each half summed half of the row quads: add the other half's sums
+      // (the same two terms in both halves, so both hold the same bits)
+#pragma unroll
+      for (int j = 0; j < NR; ++j) {
+        acc0[j] += __shfl_xor(acc0[j], 32, 64);
+        acc1[j] += __shfl_xor(acc1[j], 32, 64);
+        res[j] = h ? acc1[j] : acc0[j];
       }
-      qb = qf;
-    }
-    if constexpr (NR == 1) {
-      if (qb < qe) {
-        P1Batch<LT, VT, NR, UN> T;
-        p1_issue_tail(T, a, step, qb, qe, xr, ldx, nrr, item.nrows, lane);
-        p1_use(T, nrr, acc);
-      }
+      col = 2 * (lane & 31) + h;
+    } else {
+      // lanes past the group's columns repeat its last column (not stored)
+      const LT* a = (const LT*)S.V + item.base + (int64_t)min(lane, item.gw - 1) * 4;
+#pragma unroll
+      for (int j = 0; j < NR; ++j) res[j] = VT(0);
+      using B = P1Batch<LT, VT, NR, UN>;
+      p1_batches<B, UN, NR>(
+          item.q0, item.nq,
+          [&](B& b, int qb, bool tail) {
+            if (tail)
+              b.template issue<true>(a, step, qb, qe, xr, ldx, nrr, item.nrows, lane);
+            else
+              b.template issue<false>(a, step, qb, qe, xr, ldx, nrr, item.nrows, lane);
+          },
+          [&](const B& b) { b.use(nrr, res); });
+      col = lane;
     }
     if (item.part < 0) {
-      if (act)
+      if (col < item.gw)
 #pragma unroll
         for (int j = 0; j < NR; ++j)
-          if (j < nrr) gbl_w(T)[item.trow + lane + j * S.ldt] = acc[j];
+          if (j < nrr) gbl_w(T)[item.trow + col + j * S.ldt] = res[j];
     } else {
       VT* P = (VT*)S.part1 + (int64_t)item.part * P1_GW * NR;
 #pragma unroll
-      for (int j = 0; j < NR; ++j) gbl_w(P)[j * P1_GW + lane] = acc[j];
+      for (int j = 0; j < NR; ++j) gbl_w(P)[j * P1_GW + col] = res[j];
     }
   }
 }
@@ -1106,7 +1232,7 @@ __global__ __launch_bounds__(256, sizeof(VT) == 4 ? 4 : 3) void k_phase1_mfma(co
     // 32-bit byte offsets from the chunk's wave-uniform base (a chunk spans
     // 16 quads of at most 64 columns): one address register per load
     const char* vb = reinterpret_cast<const char*>((const LT*)S.V + item.base);
-    const uint32_t step = (uint32_t)item.gw * 4u * (uint32_t)sizeof(LT);
+    const uint32_t step = (uint32_t)item.gs * 4u * (uint32_t)sizeof(LT);
     // lanes past the group's columns repeat its last column (not stored)
     uint32_t coff[4];
 #pragma unroll
