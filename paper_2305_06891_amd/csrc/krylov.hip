@@ -47,6 +47,7 @@ void Krylov::drop_graphs() {
 Krylov::~Krylov() {
   drop_graphs();
   if (cap) (void)hipStreamDestroy(cap);
+  if (xch_h) (void)hipHostFree(xch_h);
 }
 
 void Krylov::init(const Composition& Cm, SysSet& Ss, int vec_bytes, int restart, hipStream_t s) {
@@ -65,16 +66,21 @@ void Krylov::init(const Composition& Cm, SysSet& Ss, int vec_bytes, int restart,
   H.alloc((size_t)ns * MAXM * (MAXM + 1) * 8);
   cs.alloc((size_t)ns * MAXM * 8);
   sn.alloc((size_t)ns * MAXM * 8);
-  g.alloc((size_t)ns * (MAXM + 1) * 8);
   hA.alloc((size_t)ns * (MAXM + 1) * 8);
   hB.alloc((size_t)ns * (MAXM + 1) * 8);
   hn.alloc((size_t)ns * 8);
   beta.alloc((size_t)ns * 8);
-  bnorm.alloc((size_t)ns * 8);
-  tol.alloc((size_t)ns * 8);
-  act.alloc((size_t)ns * 4);
-  steps.alloc((size_t)ns * 4);
-  slot_cnt.alloc(std::max<size_t>(1, Cm.mats.size()) * 4);
+  const size_t nslots = std::max<size_t>(1, Cm.mats.size());
+  xch_bytes = ((size_t)ns * (MAXM + 3)) * 8 + (((2 * (size_t)ns + nslots) * 4 + 7) & ~(size_t)7);
+  xch.alloc(xch_bytes);
+  if (xch_h) (void)hipHostFree(xch_h);
+  xch_h = pinned_alloc(xch_bytes + (size_t)ns * 8, &xch_hd);
+  g = xch.get<double>();
+  tol = g + (size_t)ns * (MAXM + 1);
+  bnorm = tol + ns;
+  act = (int*)(bnorm + ns);
+  steps = act + ns;
+  slot_cnt = steps + ns;
   part.alloc((size_t)std::max(1, Ss.nparts) * (MAXM + 1) * 8);
   cnt.alloc((size_t)ns * 4);
   HM_HIP(hipMemsetAsync(cnt.get(), 0, cnt.bytes(), s));
@@ -288,6 +294,70 @@ __global__ __launch_bounds__(GS_T) void k_xupdate(const SysDev* __restrict__ sys
   }
 }
 
+// ------------------------------------------------------------------ pinned leases
+namespace {
+std::mutex& lease_mu() {
+  static std::mutex* m = new std::mutex();
+  return *m;
+}
+struct FreeLease {
+  void* p;
+  void* dev;
+  size_t bytes;
+};
+std::vector<FreeLease>& lease_free() {
+  static auto* v = new std::vector<FreeLease>();
+  return *v;
+}
+}  // namespace
+
+PinnedLease::PinnedLease(size_t need) {
+  {
+    std::lock_guard<std::mutex> lk(lease_mu());
+    auto& fl = lease_free();
+    for (size_t i = 0; i < fl.size(); ++i)
+      if (fl[i].bytes >= need) {
+        p = fl[i].p;
+        dev = fl[i].dev;
+        bytes = fl[i].bytes;
+        fl.erase(fl.begin() + (std::ptrdiff_t)i);
+        return;
+      }
+  }
+  size_t b = 4096;
+  while (b < need) b <<= 1;
+  p = pinned_alloc(b, &dev);
+  bytes = b;
+}
+
+void* pinned_alloc(size_t bytes, void** dev) {
+  void* p = nullptr;
+  HM_HIP(hipHostMalloc(&p, bytes, hipHostMallocMapped | hipHostMallocCoherent));
+  std::memset(p, 0, bytes);
+  if (dev) HM_HIP(hipHostGetDevicePointer(dev, p, 0));
+  return p;
+}
+
+__global__ void k_words(const uint64_t* __restrict__ src, uint64_t* __restrict__ dst, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    dst[i] = src[i];
+}
+
+void copy_small(const void* src, void* dst, size_t bytes, hipStream_t s) {
+  HM_REQUIRE(bytes % 8 == 0 && (uintptr_t)src % 8 == 0 && (uintptr_t)dst % 8 == 0, "copy_small: misaligned copy");
+  const int64_t n = (int64_t)(bytes / 8);
+  if (n == 0) return;
+  const unsigned nb = (unsigned)std::min<int64_t>((n + 255) / 256, 64);
+  hipLaunchKernelGGL(k_words, dim3(nb), dim3(256), 0, s, (const uint64_t*)src, (uint64_t*)dst, n);
+  HM_HIP(hipGetLastError());
+}
+
+PinnedLease::~PinnedLease() {
+  if (std::uncaught_exceptions() > 0) return;
+  std::lock_guard<std::mutex> lk(lease_mu());
+  lease_free().push_back(FreeLease{p, dev, bytes});
+}
+
 // ------------------------------------------------------------------ driver
 namespace {
 
@@ -306,13 +376,13 @@ GsArgs gs_args(Krylov& K, int mode, int j, void* wvec) {
   a.H = K.H.get<double>();
   a.cs = K.cs.get<double>();
   a.sn = K.sn.get<double>();
-  a.g = K.g.get<double>();
+  a.g = K.g;
   a.hn = K.hn.get<double>();
   a.beta = K.beta.get<double>();
-  a.tol = K.tol.get<double>();
-  a.act = K.act.get<int>();
-  a.steps = K.steps.get<int>();
-  a.slot_cnt = K.slot_cnt.get<int>();
+  a.tol = K.tol;
+  a.act = K.act;
+  a.steps = K.steps;
+  a.slot_cnt = K.slot_cnt;
   a.part = K.part.get<double>();
   a.cnt = K.cnt.get<unsigned>();
   return a;
@@ -332,15 +402,16 @@ template <class VT>
 void run_scale(Krylov& K, const double* div, const void* src, void* dst, hipStream_t s) {
   const unsigned nb = (unsigned)K.S->chunks.size();
   hipLaunchKernelGGL(k_scale<VT>, dim3(nb), dim3(GS_T), 0, s, K.S->d_sys.get<SysDev>(),
-                     K.S->d_chunks.get<ChunkDev>(), K.act.get<int>(), div, (const VT*)src, (VT*)dst, K.ld);
+                     K.S->d_chunks.get<ChunkDev>(), K.act, div, (const VT*)src, (VT*)dst, K.ld);
   HM_HIP(hipGetLastError());
 }
 
-// The graph of Arnoldi steps j0 .. j0 + nsteps - 1 for these arguments,
-// captured on the workspace's private stream at first use; nullptr when
-// capture is not possible (the caller then launches the steps directly).
+// The graph of a block of Arnoldi steps j0 .. j0 + nsteps - 1 for these
+// arguments (body(j0, nsteps, stream) launches it), captured on the
+// workspace's private stream at first use; nullptr when capture is not
+// possible (the caller then launches the block directly).
 template <class F>
-hipGraphExec_t block_graph(Krylov& K, bool hi, const void* omeps, int nrr, int j0, int nsteps, F&& step) {
+hipGraphExec_t block_graph(Krylov& K, bool hi, const void* omeps, int nrr, int j0, int nsteps, F&& body) {
   for (const auto& g : K.graphs)
     if (g.hi == hi && g.omeps == omeps && g.nrr == nrr && g.j0 == j0 && g.nsteps == nsteps) return g.exec;
   if (!K.cap && hipStreamCreateWithFlags(&K.cap, hipStreamNonBlocking) != hipSuccess) {
@@ -350,7 +421,7 @@ hipGraphExec_t block_graph(Krylov& K, bool hi, const void* omeps, int nrr, int j
   if (hipStreamBeginCapture(K.cap, hipStreamCaptureModeThreadLocal) != hipSuccess) return nullptr;
   bool ok = true;
   try {
-    for (int q = 0; q < nsteps; ++q) step(j0 + q, K.cap);
+    body(j0, nsteps, K.cap);
   } catch (const Error&) {
     ok = false;
   }
@@ -372,77 +443,37 @@ hipGraphExec_t block_graph(Krylov& K, bool hi, const void* omeps, int nrr, int j
   return ge;
 }
 
-// Pinned host buffers for the scalars gmres exchanges with the device every
-// cycle (norms, active flags, counts, the Givens right-hand side): copies
-// from pageable memory go through a bounce buffer and took tens of
-// microseconds each.  A call leases one buffer and returns it when it ends,
-// when every copy from or to it has completed (each cycle ends with a
-// stream synchronisation); a call left by an exception keeps its buffer.
-// Buffers are never freed: a few per thread that runs solves.
-struct StageLease {
-  void* p = nullptr;
-  size_t bytes = 0;
-  static std::mutex& mu() {
-    static std::mutex* m = new std::mutex();
-    return *m;
-  }
-  static std::vector<std::pair<void*, size_t>>& free_list() {
-    static auto* v = new std::vector<std::pair<void*, size_t>>();
-    return *v;
-  }
-  explicit StageLease(size_t need) {
-    {
-      std::lock_guard<std::mutex> lk(mu());
-      auto& fl = free_list();
-      for (size_t i = 0; i < fl.size(); ++i)
-        if (fl[i].second >= need) {
-          p = fl[i].first;
-          bytes = fl[i].second;
-          fl.erase(fl.begin() + (std::ptrdiff_t)i);
-          return;
-        }
-    }
-    size_t b = 4096;
-    while (b < need) b <<= 1;
-    HM_HIP(hipHostMalloc(&p, b, hipHostMallocDefault));
-    bytes = b;
-  }
-  ~StageLease() {
-    if (std::uncaught_exceptions() > 0) return;
-    std::lock_guard<std::mutex> lk(mu());
-    free_list().emplace_back(p, bytes);
-  }
-  StageLease(const StageLease&) = delete;
-  StageLease& operator=(const StageLease&) = delete;
-};
-
 template <class VT>
 GmresStats gmres_t(Krylov& K, bool hi, const void* omeps, const void* b, void* x, double rtol, int max_iter,
-                   hipStream_t s, bool use_graphs, unsigned opts) {
+                   hipStream_t s, bool use_graphs, unsigned opts, const double* bnorm_in) {
   const Composition& C = *K.C;
   const int ns = K.S->size();
   const int nslots = (int)C.mats.size();
   GmresStats st;
   st.rel_res.assign(ns, 0.0);
   const int64_t mbytes = hi ? C.bytes_hi : C.bytes_lo;
-  // host side of the per-cycle scalars, in pinned memory
+  // host side of the exchange block (same layout as K.xch), then the
+  // residual norms read back after a product
   const size_t g0n = (size_t)ns * (MAXM + 1);
-  StageLease lease((g0n + 3 * (size_t)ns) * 8 + (2 * (size_t)ns + nslots) * 4);
-  double* g0 = (double*)lease.p;
-  double* bn = g0 + g0n;
-  double* tolv = bn + ns;
-  double* beta = tolv + ns;
-  int* act = (int*)(beta + ns);
+  double* g0 = (double*)K.xch_h;
+  double* tolv = g0 + g0n;
+  double* bn = tolv + ns;
+  int* act = (int*)(bn + ns);
   int* stp = act + ns;
   int* cnt = stp + ns;
-  std::memset(g0, 0, g0n * 8);
+  double* beta = (double*)((char*)K.xch_h + K.xch_bytes);
+  void* beta_d = (char*)K.xch_hd + K.xch_bytes;  // its device view
+  std::memset(K.xch_h, 0, K.xch_bytes);
   // |b| per system
-  run_gs<VT>(K, 3, 0, const_cast<void*>(b), s);
-  HM_HIP(hipMemcpyAsync(bn, K.beta.get(), ns * 8, hipMemcpyDeviceToHost, s));
-  HM_HIP(hipStreamSynchronize(s));
+  if (bnorm_in) {
+    std::copy(bnorm_in, bnorm_in + ns, bn);
+  } else {
+    run_gs<VT>(K, 3, 0, const_cast<void*>(b), s);
+    copy_small(K.beta.get(), beta_d, (size_t)ns * 8, s);
+    HM_HIP(hipStreamSynchronize(s));
+    std::copy(beta, beta + ns, bn);
+  }
   for (int q = 0; q < ns; ++q) tolv[q] = rtol * bn[q];
-  HM_HIP(hipMemcpyAsync(K.tol.get(), tolv, ns * 8, hipMemcpyHostToDevice, s));
-  HM_HIP(hipMemcpyAsync(K.bnorm.get(), bn, ns * 8, hipMemcpyHostToDevice, s));
   Epilogue res_ep;  // r = b - (x - (1-eps) F x) = b - x + (1-eps) F x
   res_ep.rowscale = omeps;
   res_ep.a_acc = 1.0;
@@ -459,16 +490,16 @@ GmresStats gmres_t(Krylov& K, bool hi, const void* omeps, const void* b, void* x
   bool first = true;
   for (;;) {
     // true residual and its norm (b itself for a zero start: its norms are
-    // the ones just taken, in K.beta and bn)
-    if (first && (opts & GM_X0_ZERO)) {
-      HM_HIP(hipMemcpyAsync(K.basis.get(), b, (size_t)K.blk * K.vb, hipMemcpyDeviceToDevice, s));
+    // bn, and the first basis vector is b / bn)
+    const bool from_b = first && (opts & GM_X0_ZERO);
+    if (from_b) {
       std::copy(bn, bn + ns, beta);
     } else {
       launch_matvec(C, nrr, K.vb, hi, x, K.ld, K.basis.get(), K.ld, res_ep, nullptr, s);
       st.matvecs++;
       st.bytes += mbytes;
       run_gs<VT>(K, 3, 0, K.basis.get(), s);
-      HM_HIP(hipMemcpyAsync(beta, K.beta.get(), ns * 8, hipMemcpyDeviceToHost, s));
+      copy_small(K.beta.get(), beta_d, (size_t)ns * 8, s);
       HM_HIP(hipStreamSynchronize(s));
     }
     first = false;
@@ -485,45 +516,48 @@ GmresStats gmres_t(Krylov& K, bool hi, const void* omeps, const void* b, void* x
         cnt[K.S->sys[q].slot]++;
       }
       g0[(size_t)q * (MAXM + 1)] = finite ? beta[q] : 0.0;
+      stp[q] = 0;
     }
     if (nact == 0) break;
     if (iters >= max_iter) {
       st.converged = false;
       break;
     }
-    HM_HIP(hipMemcpyAsync(K.act.get(), act, ns * 4, hipMemcpyHostToDevice, s));
-    HM_HIP(hipMemcpyAsync(K.slot_cnt.get(), cnt, nslots * 4, hipMemcpyHostToDevice, s));
-    HM_HIP(hipMemcpyAsync(K.g.get(), g0, g0n * 8, hipMemcpyHostToDevice, s));
-    HM_HIP(hipMemsetAsync(K.steps.get(), 0, ns * 4, s));
-    run_scale<VT>(K, K.beta.get<double>(), K.basis.get(), K.basis.get(), s);
-    // Arnoldi steps; the host looks at the active count every SYNC steps
-    // (steps launched after every system has converged find nothing active
-    // and return at once)
-    constexpr int SYNC = 4;
+    // one copy: g (first entries), tol, |b|, active flags, step counts, slot counts
+    copy_small(K.xch_hd, K.xch.get(), K.xch_bytes, s);
+    if (from_b)
+      run_scale<VT>(K, K.bnorm, b, K.basis.get(), s);
+    else
+      run_scale<VT>(K, K.beta.get<double>(), K.basis.get(), K.basis.get(), s);
     // one Arnoldi step on stream st (kernels only)
     auto step = [&](int j, hipStream_t st) {
       char* vj = K.basis.get<char>() + (size_t)j * K.blk * K.vb;
       char* vj1 = vj + (size_t)K.blk * K.vb;
-      launch_matvec(C, nrr, K.vb, hi, vj, K.ld, K.w.get(), K.ld, op_ep, K.slot_cnt.get<int>(), st);
+      launch_matvec(C, nrr, K.vb, hi, vj, K.ld, K.w.get(), K.ld, op_ep, K.slot_cnt, st);
       run_gs<VT>(K, 0, j, K.w.get(), st);
       run_gs<VT>(K, 1, j, K.w.get(), st);
       run_gs<VT>(K, 2, j, K.w.get(), st);
       run_scale<VT>(K, K.hn.get<double>(), K.w.get(), vj1, st);
     };
+    // blocks of up to SYNC Arnoldi steps; after each the host reads the
+    // whole exchange block back (the active counts decide whether to go on;
+    // the step counts and the rotated right-hand sides are then at hand for
+    // the update).  Steps launched after every system has converged find
+    // nothing active and return at once.
+    constexpr int SYNC = 4;
+    auto block = [&](int j0, int nsteps, hipStream_t st) {
+      for (int q = 0; q < nsteps; ++q) step(j0 + q, st);
+      copy_small(K.xch.get(), K.xch_hd, K.xch_bytes, st);
+    };
     int left = nact;
     for (int j = 0; j < K.m && iters + j < max_iter;) {
-      // a block of up to SYNC steps, then the host looks at the active count
-      // (steps launched after every system has converged find nothing
-      // active and return at once)
       const int nb = std::min(SYNC, std::min(K.m - j, max_iter - iters - j));
-      hipGraphExec_t ge = use_graphs ? block_graph(K, hi, omeps, nrr, j, nb, step) : nullptr;
-      if (ge) {
+      hipGraphExec_t ge = use_graphs ? block_graph(K, hi, omeps, nrr, j, nb, block) : nullptr;
+      if (ge)
         HM_HIP(hipGraphLaunch(ge, s));
-      } else {
-        for (int q = 0; q < nb; ++q) step(j + q, s);
-      }
+      else
+        block(j, nb, s);
       j += nb;
-      HM_HIP(hipMemcpyAsync(cnt, K.slot_cnt.get(), nslots * 4, hipMemcpyDeviceToHost, s));
       HM_HIP(hipStreamSynchronize(s));
       left = 0;
       for (int q = 0; q < nslots; ++q) left += cnt[q];
@@ -531,16 +565,13 @@ GmresStats gmres_t(Krylov& K, bool hi, const void* omeps, const void* b, void* x
     }
     // steps taken in this cycle: the most any system took
     const bool trusted = (opts & GM_TRUST_ESTIMATE) && left == 0;
-    HM_HIP(hipMemcpyAsync(stp, K.steps.get(), ns * 4, hipMemcpyDeviceToHost, s));
-    if (trusted) HM_HIP(hipMemcpyAsync(g0, K.g.get(), g0n * 8, hipMemcpyDeviceToHost, s));
-    HM_HIP(hipStreamSynchronize(s));
     const int cyc = *std::max_element(stp, stp + ns);
     iters += cyc;
     st.matvecs += cyc;
     st.bytes += (int64_t)cyc * mbytes;
     const unsigned nb = (unsigned)K.S->chunks.size();
     hipLaunchKernelGGL(k_xupdate<VT>, dim3(nb), dim3(GS_T), 0, s, K.S->d_sys.get<SysDev>(),
-                       K.S->d_chunks.get<ChunkDev>(), K.steps.get<int>(), K.H.get<double>(), K.g.get<double>(),
+                       K.S->d_chunks.get<ChunkDev>(), K.steps, K.H.get<double>(), K.g,
                        (const VT*)K.basis.get(), K.ld, K.blk, (VT*)x);
     HM_HIP(hipGetLastError());
     if (trusted) {
@@ -559,19 +590,20 @@ GmresStats gmres_t(Krylov& K, bool hi, const void* omeps, const void* b, void* x
 }  // namespace
 
 GmresStats gmres(Krylov& K, bool hi, const void* omeps, const void* b, void* x, double rtol, int max_iter,
-                 hipStream_t s, bool graphs, unsigned opts) {
-  if (K.vb == 8) return gmres_t<double>(K, hi, omeps, b, x, rtol, max_iter, s, graphs, opts);
-  return gmres_t<float>(K, hi, omeps, b, x, rtol, max_iter, s, graphs, opts);
+                 hipStream_t s, bool graphs, unsigned opts, const double* bnorm) {
+  if (K.vb == 8) return gmres_t<double>(K, hi, omeps, b, x, rtol, max_iter, s, graphs, opts, bnorm);
+  return gmres_t<float>(K, hi, omeps, b, x, rtol, max_iter, s, graphs, opts, bnorm);
 }
 
 void block_norms(Krylov& K, const void* v, std::vector<double>& out, hipStream_t s) {
   if (K.vb == 8) run_gs<double>(K, 3, 0, const_cast<void*>(v), s);
   else run_gs<float>(K, 3, 0, const_cast<void*>(v), s);
   const int ns = K.S->size();
-  StageLease lease((size_t)ns * 8);
-  HM_HIP(hipMemcpyAsync(lease.p, K.beta.get(), (size_t)ns * 8, hipMemcpyDeviceToHost, s));
+  // the norms come back through the workspace's pinned block (no gmres is
+  // running on this workspace meanwhile)
+  copy_small(K.beta.get(), (char*)K.xch_hd + K.xch_bytes, (size_t)ns * 8, s);
   HM_HIP(hipStreamSynchronize(s));
-  const double* nr = (const double*)lease.p;
+  const double* nr = (const double*)((const char*)K.xch_h + K.xch_bytes);
   out.assign(nr, nr + ns);
 }
 

@@ -61,7 +61,19 @@ struct Krylov {
   int64_t ld = 0;       // leading dimension of vector blocks (= C->N)
   int64_t blk = 0;      // elements per vector block (ld * width)
   DevBuf basis, w, r;   // basis: (m+1) blocks
-  DevBuf H, cs, sn, g, hA, hB, hn, beta, bnorm, tol, act, steps, slot_cnt, part, cnt;
+  DevBuf H, cs, sn, hA, hB, hn, beta, part, cnt;
+  // The scalars the host exchanges with the device every cycle, packed in
+  // one buffer (the host's pinned staging has the same layout, so each
+  // exchange is one copy):
+  //   g[ns (MAXM+1)] tol[ns] bnorm[ns] (doubles), act[ns] steps[ns] slot_cnt[nslots] (ints)
+  DevBuf xch;
+  double *g = nullptr, *tol = nullptr, *bnorm = nullptr;
+  int *act = nullptr, *steps = nullptr, *slot_cnt = nullptr;
+  size_t xch_bytes = 0;  // a multiple of 8
+  // pinned host side: the exchange block, then ns doubles of norms; the
+  // kernels use its device view xch_hd
+  void* xch_h = nullptr;
+  void* xch_hd = nullptr;
   // graphs of Arnoldi step blocks (valid while the buffers above and the
   // composition stay as they are; init drops them)
   std::vector<StepGraph> graphs;
@@ -86,8 +98,35 @@ enum : unsigned {
 // Solve C x = b for every system of S.  b, x: vector blocks (ld = C.N) of
 // the Krylov vector type; x holds the initial guess on entry.  omeps: per
 // row (1 - eps) in the vector type.  hi selects the FP32 factor copy.
+// bnorm: the per-system 2-norms of b when the caller has them (host array),
+// else NULL (they are computed here, one host round trip).
 GmresStats gmres(Krylov& K, bool hi, const void* omeps, const void* b, void* x, double rtol, int max_iter,
-                 hipStream_t s, bool graphs = false, unsigned opts = 0);
+                 hipStream_t s, bool graphs = false, unsigned opts = 0, const double* bnorm = nullptr);
+
+// Copies a few kilobytes between pinned host memory (its device view) and
+// device memory with a kernel on stream s: unlike a runtime copy it needs no
+// DMA engine, whose hand-over to the next kernel costs tens of
+// microseconds.  bytes and both addresses: multiples of 8.
+void copy_small(const void* src, void* dst, size_t bytes, hipStream_t s);
+
+// Pinned host memory, mapped for kernels and coherent, for small exchanges.
+void* pinned_alloc(size_t bytes, void** dev);
+
+// Pinned host memory for small host <-> device exchanges (copies from
+// pageable memory go through a bounce buffer and take tens of microseconds
+// each).  A lease takes a buffer of at least `need` bytes from a process-wide
+// free list and returns it when it ends; the holder makes sure every copy
+// from or to it has completed by then (a lease left by an exception keeps
+// its buffer).  Buffers are never freed: a few per thread that solves.
+struct PinnedLease {
+  void* p = nullptr;    // host pointer
+  void* dev = nullptr;  // the same memory as kernels see it
+  size_t bytes = 0;
+  explicit PinnedLease(size_t need);
+  ~PinnedLease();
+  PinnedLease(const PinnedLease&) = delete;
+  PinnedLease& operator=(const PinnedLease&) = delete;
+};
 
 // Per-system 2-norms of a vector block (FP64 accumulation).
 void block_norms(Krylov& K, const void* v, std::vector<double>& out, hipStream_t s);

@@ -370,8 +370,8 @@ void hm_server::build_loop() {
       upload(c->om32, om32, as);
       {
         Batch B({M}, 1, as);
-        B.io({c->eps_d.get<double>()}, {}, 0, nullptr, as);
-        B.gather(B.epsp.get<double>(), 1, 1, as);
+        B.io(Batch::IO_EPS, {c->eps_d.get<double>()}, {}, 0, nullptr, as);
+        B.gather(Batch::IO_EPS, B.epsp.get<double>(), 1, 1, as);
         B.ensure_g({c->eps_d.get<double>()}, as);
         c->g.alloc(n * 8);
         HM_HIP(hipMemcpyAsync(c->g.get(), B.g.get(), n * 8, hipMemcpyDeviceToDevice, as));

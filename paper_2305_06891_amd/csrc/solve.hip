@@ -76,6 +76,30 @@ __global__ void k_cast(const A* __restrict__ a, B* __restrict__ b, int64_t n) {
   if (k < n) b[k] = (B)a[k];
 }
 
+// Right-hand side of an inner correction solve from the FP64 residual src:
+// b32 = (float) src and x32 = 0; with rcopy, also rcopy = src (the residual
+// of a zero start is b itself).
+__global__ void k_inner_rhs(const double* __restrict__ src, float* __restrict__ b32, float* __restrict__ x32,
+                            double* __restrict__ rcopy, int64_t n) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  const double v = src[k];
+  b32[k] = (float)v;
+  x32[k] = 0.f;
+  if (rcopy) rcopy[k] = v;
+}
+
+// b32 = 0 on the systems whose flag is 0 (those already converged take no
+// correction); one workgroup per reduction chunk of a system.
+__global__ void k_zero_done(const SysDev* __restrict__ sys, const ChunkDev* __restrict__ chunks,
+                            const int* __restrict__ on, float* __restrict__ b32, int64_t ld) {
+  const ChunkDev c = chunks[blockIdx.x];
+  if (on[c.sys]) return;
+  const SysDev sy = sys[c.sys];
+  const int64_t base = (int64_t)sy.col * ld + sy.row0 + c.r0;
+  for (int r = threadIdx.x; r < c.nr; r += blockDim.x) b32[base + r] = 0.f;
+}
+
 // y += (double) x
 template <class VT>
 __global__ void k_acc(const VT* __restrict__ x, double* __restrict__ y, int64_t n) {
@@ -177,7 +201,7 @@ Batch::Batch(const std::vector<const hm_matrix*>& m, int nrhs_, hipStream_t s) :
     io.xoff = off;
     off += io.n;
   }
-  d_ios.alloc(ios.size() * sizeof(SlotIO));
+  d_ios.alloc((size_t)IO_ROLES * ios.size() * sizeof(SlotIO));
 }
 
 Krylov& Batch::krylov(int vb, int restart, hipStream_t s) {
@@ -197,48 +221,82 @@ Krylov& Batch::krylov(int vb, int restart, hipStream_t s) {
   return K;
 }
 
-void Batch::io(const std::vector<const double*>& in, const std::vector<double*>& out, int64_t ld_in_default,
-               const std::vector<int64_t>* lds, hipStream_t s) {
-  for (size_t q = 0; q < ios.size(); ++q) {
-    ios[q].in = q < in.size() ? in[q] : nullptr;
-    ios[q].out = q < out.size() ? out[q] : nullptr;
-    ios[q].ld = lds ? (*lds)[q] : (ld_in_default > 0 ? ld_in_default : ios[q].n);
+Batch::~Batch() {
+  for (hipEvent_t& e : io_ev)
+    if (e) {
+      (void)hipEventSynchronize(e);
+      (void)hipEventDestroy(e);
+    }
+  if (ios_h) (void)hipHostFree(ios_h);
+  if (eps_ev) {
+    (void)hipEventSynchronize(eps_ev);
+    (void)hipEventDestroy(eps_ev);
   }
-  HM_HIP(hipMemcpyAsync(d_ios.get(), ios.data(), ios.size() * sizeof(SlotIO), hipMemcpyHostToDevice, s));
-  HM_HIP(hipStreamSynchronize(s));  // the host table is rewritten by the next call
+  if (eps_flag_h) (void)hipHostFree(eps_flag_h);
 }
 
-void Batch::gather(double* dst, int ncol, int dst_cols, hipStream_t s) {
+void Batch::io(int role, const std::vector<const double*>& in, const std::vector<double*>& out,
+               int64_t ld_in_default, const std::vector<int64_t>* lds, hipStream_t s) {
+  HM_REQUIRE(role >= 0 && role < IO_ROLES, "batch: bad io role");
+  const size_t ns = ios.size();
+  static_assert(sizeof(SlotIO) % 8 == 0, "slot tables are copied in 8-byte words");
+  if (!ios_h) ios_h = (SlotIO*)pinned_alloc((size_t)IO_ROLES * ns * sizeof(SlotIO), (void**)&ios_hd);
+  if (io_ev[role])
+    HM_HIP(hipEventSynchronize(io_ev[role]));  // the previous upload of this table has read it
+  else
+    HM_HIP(hipEventCreateWithFlags(&io_ev[role], hipEventDisableTiming));
+  SlotIO* t = ios_h + (size_t)role * ns;
+  for (size_t q = 0; q < ns; ++q) {
+    t[q] = ios[q];
+    t[q].in = q < in.size() ? in[q] : nullptr;
+    t[q].out = q < out.size() ? out[q] : nullptr;
+    t[q].ld = lds ? (*lds)[q] : (ld_in_default > 0 ? ld_in_default : ios[q].n);
+  }
+  copy_small(ios_hd + (size_t)role * ns, d_ios.get<SlotIO>() + (size_t)role * ns, ns * sizeof(SlotIO), s);
+  HM_HIP(hipEventRecord(io_ev[role], s));
+}
+
+void Batch::gather(int role, double* dst, int ncol, int dst_cols, hipStream_t s) {
   // dst holds dst_cols columns of N rows: columns ncol..dst_cols-1 are zeroed
   HM_REQUIRE(ncol >= 1 && ncol <= dst_cols && dst_cols <= W, "gather: bad column counts");
-  hipLaunchKernelGGL(k_gather, grid_rows(N, dst_cols), dim3(256), 0, s, d_ios.get<SlotIO>(), (int)ios.size(), N, ncol,
-                     dst);
+  hipLaunchKernelGGL(k_gather, grid_rows(N, dst_cols), dim3(256), 0, s, d_ios.get<SlotIO>() + (size_t)role * ios.size(),
+                     (int)ios.size(), N, ncol, dst);
   HM_HIP(hipGetLastError());
 }
 
-void Batch::scatter(const double* src, int ncol, hipStream_t s) {
-  hipLaunchKernelGGL(k_scatter, grid_rows(N, ncol), dim3(256), 0, s, d_ios.get<SlotIO>(), (int)ios.size(), N, ncol,
-                     src);
+void Batch::scatter(int role, const double* src, int ncol, hipStream_t s) {
+  hipLaunchKernelGGL(k_scatter, grid_rows(N, ncol), dim3(256), 0, s, d_ios.get<SlotIO>() + (size_t)role * ios.size(),
+                     (int)ios.size(), N, ncol, src);
   HM_HIP(hipGetLastError());
 }
 
 // g = F C^-1 eps per slot (the flux helper of eq. (12)); FP64 vectors with
 // the most accurate stored factors, solved to 1e-13.
+void Batch::compare_eps(hipStream_t s) {
+  eps_pending = false;
+  if (!g_ready) return;
+  if (!eps_flag_h) eps_flag_h = (int*)pinned_alloc(64, &eps_flag_hd);
+  if (!eps_ev) HM_HIP(hipEventCreateWithFlags(&eps_ev, hipEventDisableTiming));
+  HM_HIP(hipMemsetAsync(d_flag.get(), 0, 8, s));
+  hipLaunchKernelGGL(k_differs, grid_rows(N), dim3(256), 0, s, epsp.get<double>(), g_eps.get<double>(), N,
+                     d_flag.get<int>());
+  copy_small(d_flag.get(), eps_flag_hd, 8, s);
+  HM_HIP(hipEventRecord(eps_ev, s));
+  eps_pending = true;
+}
+
 void Batch::ensure_g(const std::vector<const double*>& eps_user, hipStream_t s) {
   // epsp holds the permuted emissivities of this call; g is reused while they are unchanged
   if (g_ready) {
-    int flag = 0;
-    HM_HIP(hipMemsetAsync(d_flag.get(), 0, 4, s));
-    hipLaunchKernelGGL(k_differs, grid_rows(N), dim3(256), 0, s, epsp.get<double>(), g_eps.get<double>(), N,
-                       d_flag.get<int>());
-    HM_HIP(hipMemcpyAsync(&flag, d_flag.get(), 4, hipMemcpyDeviceToHost, s));
-    HM_HIP(hipStreamSynchronize(s));
-    if (!flag) return;
+    if (!eps_pending) compare_eps(s);
+    HM_HIP(hipEventSynchronize(eps_ev));
+    eps_pending = false;
+    if (!*eps_flag_h) return;
   }
   if (!gb) gb = std::make_unique<Batch>(mats, 1, s);
   Batch& B = *gb;
-  B.io(eps_user, {}, 0, nullptr, s);
-  B.gather(B.epsp.get<double>(), 1, 1, s);
+  B.io(IO_EPS, eps_user, {}, 0, nullptr, s);
+  B.gather(IO_EPS, B.epsp.get<double>(), 1, 1, s);
   hipLaunchKernelGGL(k_omeps<double>, grid_rows(B.N), dim3(256), 0, s, B.epsp.get<double>(), B.N,
                      B.omeps64.get<double>());
   HM_HIP(hipMemcpyAsync(B.b64.get(), B.epsp.get(), B.N * 8, hipMemcpyDeviceToDevice, s));
@@ -248,7 +306,7 @@ void Batch::ensure_g(const std::vector<const double*>& eps_user, hipStream_t s) 
   (void)st;
   if (!g.get()) g.alloc(N * 8);
   if (!g_eps.get()) g_eps.alloc(N * 8);
-  if (!d_flag.get()) d_flag.alloc(4);
+  if (!d_flag.get()) d_flag.alloc(8);
   launch_matvec(*B.C, 1, 8, true, B.x64.get(), B.N, g.get(), B.N, Epilogue{}, nullptr, s);
   HM_HIP(hipMemcpyAsync(g_eps.get(), epsp.get(), N * 8, hipMemcpyDeviceToDevice, s));
   HM_HIP(hipStreamSynchronize(s));
@@ -282,11 +340,12 @@ SolveResult Batch::solve(const std::vector<const double*>& eps_user, const std::
   SolveResult R;
   const bool want_q = p.want_q && std::any_of(q_user.begin(), q_user.end(), [](double* v) { return v != nullptr; });
   // permuted inputs
-  io(eps_user, {}, 0, nullptr, s);
-  gather(epsp.get<double>(), 1, 1, s);
+  io(IO_EPS, eps_user, {}, 0, nullptr, s);
+  gather(IO_EPS, epsp.get<double>(), 1, 1, s);
   hipLaunchKernelGGL(k_omeps<double>, grid_rows(N), dim3(256), 0, s, epsp.get<double>(), N, omeps64.get<double>());
-  io(T_user, {}, 0, &ldT, s);
-  gather(Tp.get<double>(), nrhs, W, s);
+  if (want_q) compare_eps(s);
+  io(IO_T, T_user, {}, 0, &ldT, s);
+  gather(IO_T, Tp.get<double>(), nrhs, W, s);
   prepare_rhs(sigma, p, s);
   R = solve_prepared(p, s, false, true, want_q);
   if (want_q) {
@@ -294,11 +353,11 @@ SolveResult Batch::solve(const std::vector<const double*>& eps_user, const std::
     set_ambient(p, s);
     flux(sigma, s, R.fx);
   }
-  io({}, J_user, 0, &ldJ, s);
-  scatter(x64.get<double>(), nrhs, s);
+  io(IO_J, {}, J_user, 0, &ldJ, s);
+  scatter(IO_J, x64.get<double>(), nrhs, s);
   if (want_q) {
-    io({}, q_user, 0, &ldq, s);
-    scatter(H64.get<double>(), nrhs, s);
+    io(IO_Q, {}, q_user, 0, &ldq, s);
+    scatter(IO_Q, H64.get<double>(), nrhs, s);
   }
   return R;
 }
@@ -363,17 +422,28 @@ SolveResult Batch::solve_prepared(const hm_solve_params& p, hipStream_t s, bool 
     Krylov& K8 = krylov(8, p.restart, s);
     Krylov& K4 = krylov(4, p.restart, s);
     if (!warm) HM_HIP(hipMemsetAsync(x64.get(), 0, tot * 8, s));
-    std::vector<double> bn, rn;
+    std::vector<double> bn, rn, inner_bn;
     block_norms(K8, b64.get(), bn, s);
     R.converged = false;
     int outer = 0, inner_total = 0;
     const size_t nslots = mats.size();
+    const size_t nsys = (size_t)S.size();
     bool masked = false;  // the last refinement step left some slots untouched
     int64_t masked_bytes = 0;
+    // per system: still above the tolerance; then per slot: holds such a
+    // system (the next residual product runs on those slots only).  One
+    // pinned upload per step.
+    const size_t flag_bytes = ((nsys + nslots) * 4 + 7) & ~(size_t)7;
+    PinnedLease flags_h(flag_bytes);
+    int* sys_on = (int*)flags_h.p;
+    int* slot_on = sys_on + nsys;
+    if (!res_mask.get() || res_mask.bytes() < flag_bytes) res_mask.alloc(flag_bytes);
+    const int* slot_on_d = res_mask.get<int>() + nsys;
     for (;;) {
-      if (outer == 0 && !warm) {
-        // x = 0: the residual is b itself, no product needed
-        HM_HIP(hipMemcpyAsync(r64.get(), b64.get(), tot * 8, hipMemcpyDeviceToDevice, s));
+      const bool zero_start = outer == 0 && !warm;
+      if (zero_start) {
+        // x = 0: the residual is b itself, no product needed (the inner
+        // right-hand side below copies b into r64)
         R.fx = false;
       } else {
         // with the flux wanted, the product also leaves F x in H64: the last
@@ -381,12 +451,12 @@ SolveResult Batch::solve_prepared(const hm_solve_params& p, hipStream_t s, bool 
         // Slots whose systems had all met the tolerance took a zero
         // correction (x unchanged), so their residual and F x from the
         // previous product stand and the product skips them.
-        residual64(true, s, keep_fx, masked ? res_mask.get<int>() : nullptr);
+        residual64(true, s, keep_fx, masked ? slot_on_d : nullptr);
         R.fx = keep_fx;
         R.matvecs++;
         R.bytes += masked ? masked_bytes : C->bytes_hi;
       }
-      if (outer == 0 && !warm)
+      if (zero_start)
         rn = bn;  // r = b
       else
         block_norms(K8, r64.get(), rn, s);
@@ -403,30 +473,37 @@ SolveResult Batch::solve_prepared(const hm_solve_params& p, hipStream_t s, bool 
       }
       // a residual that is not finite cannot be refined: stop, not converged
       if (nonfinite || outer >= 30 || inner_total >= p.max_iter) break;
-      // systems already converged get a zero right-hand side (no inner work)
-      hipLaunchKernelGGL((k_cast<double, float>), dim3(gb_), dim3(256), 0, s, r64.get<double>(), b32.get<float>(), tot);
-      res_mask_h.assign(nslots, 0);
-      for (size_t q = 0; q < rn.size(); ++q) {
-        if (residual_met(rn[q], bn[q], p.rtol)) {
-          const SysDev& sd = S.sys[q];
-          HM_HIP(hipMemsetAsync(b32.get<float>() + sd.col * N + sd.row0, 0, (size_t)sd.n * 4, s));
+      // the correction starts from zero: x32 = 0, b32 = the residual in
+      // FP32, zero on the systems already converged (no inner work)
+      hipLaunchKernelGGL(k_inner_rhs, dim3(gb_), dim3(256), 0, s, (zero_start ? b64 : r64).get<double>(),
+                         b32.get<float>(), x32.get<float>(), zero_start ? r64.get<double>() : nullptr, tot);
+      std::fill(slot_on, slot_on + nslots, 0);
+      inner_bn.assign(nsys, 0.0);
+      size_t ndone = 0;
+      for (size_t q = 0; q < nsys; ++q) {
+        sys_on[q] = residual_met(rn[q], bn[q], p.rtol) ? 0 : 1;
+        if (sys_on[q]) {
+          slot_on[S.sys[q].slot] = 1;
+          inner_bn[q] = rn[q];
         } else {
-          res_mask_h[S.sys[q].slot] = 1;
+          ++ndone;
         }
       }
       masked_bytes = 0;
       for (size_t q = 0; q < nslots; ++q)
-        if (res_mask_h[q]) masked_bytes += matrix_bytes(*mats[q], true);
+        if (slot_on[q]) masked_bytes += matrix_bytes(*mats[q], true);
       masked = masked_bytes < C->bytes_hi;
-      if (masked) {
-        if (!res_mask.get()) res_mask.alloc(nslots * 4);
-        HM_HIP(hipMemcpyAsync(res_mask.get(), res_mask_h.data(), nslots * 4, hipMemcpyHostToDevice, s));
+      if (ndone > 0 || masked) {
+        copy_small(flags_h.dev, res_mask.get(), flag_bytes, s);
+        if (ndone > 0)
+          hipLaunchKernelGGL(k_zero_done, dim3((unsigned)S.chunks.size()), dim3(256), 0, s, S.d_sys.get<SysDev>(),
+                             S.d_chunks.get<ChunkDev>(), res_mask.get<int>(), b32.get<float>(), N);
       }
-      // correction from zero; the FP64 residual above checks its progress,
-      // so the inner solve stops on its own residual estimate
-      HM_HIP(hipMemsetAsync(x32.get(), 0, tot * 4, s));
+      // the FP64 residual above checks the correction's progress, so the
+      // inner solve stops on its own residual estimate; its right-hand
+      // side's norms are the FP64 residual norms (zero where converged)
       GmresStats st = gmres(K4, false, omeps32.get(), b32.get(), x32.get(), p.ir_inner_rtol, p.max_iter, s,
-                            p.use_graphs != 0, GM_X0_ZERO | GM_TRUST_ESTIMATE);
+                            p.use_graphs != 0, GM_X0_ZERO | GM_TRUST_ESTIMATE, inner_bn.data());
       hipLaunchKernelGGL(k_acc<float>, dim3(gb_), dim3(256), 0, s, x32.get<float>(), x64.get<double>(), tot);
       R.fx = false;  // x changed
       R.iters += st.iters;
@@ -470,23 +547,23 @@ TransientResult Batch::transient(const std::vector<const double*>& eps_user, dou
                                  const double* src_user, int64_t ldS, double sigma, const hm_transient_params& tp,
                                  const hm_solve_params& sp, double* history, hipStream_t s) {
   TransientResult TR;
-  io(eps_user, {}, 0, nullptr, s);
-  gather(epsp.get<double>(), 1, 1, s);
+  io(IO_EPS, eps_user, {}, 0, nullptr, s);
+  gather(IO_EPS, epsp.get<double>(), 1, 1, s);
   hipLaunchKernelGGL(k_omeps<double>, grid_rows(N), dim3(256), 0, s, epsp.get<double>(), N, omeps64.get<double>());
   ensure_g(eps_user, s);
   set_ambient(sp, s);
   const double* ambp = open ? amb.get<double>() : nullptr;
   std::vector<int64_t> ldv{ldT};
-  io({T_user}, {}, 0, &ldv, s);
-  gather(Tp.get<double>(), nrhs, W, s);
+  io(IO_T, {T_user}, {}, 0, &ldv, s);
+  gather(IO_T, Tp.get<double>(), nrhs, W, s);
   std::vector<int64_t> lds{ldS};
   DevBuf srcp(N * W * 8), Tn(N * W * 8), Rv(N * W * 8), d_upd(W * 4);
-  io({src_user}, {}, 0, &lds, s);
-  gather(srcp.get<double>(), nrhs, W, s);
+  io(IO_SRC, {src_user}, {}, 0, &lds, s);
+  gather(IO_SRC, srcp.get<double>(), nrhs, W, s);
   std::vector<int64_t> ldh{ldT};
   if (history) {
-    io({}, {history}, 0, &ldh, s);
-    scatter(Tp.get<double>(), nrhs, s);
+    io(IO_HIST, {}, {history}, 0, &ldh, s);
+    scatter(IO_HIST, Tp.get<double>(), nrhs, s);
   }
   Krylov& K8 = krylov(8, sp.restart, s);
   std::vector<int> upd(W, 0);
@@ -547,12 +624,12 @@ TransientResult Batch::transient(const std::vector<const double*>& eps_user, dou
     if (TR.nonfinite) break;
     have_q = true;
     if (history) {
-      io({}, {history + (int64_t)(step + 1) * ldT * nrhs}, 0, &ldh, s);
-      scatter(Tp.get<double>(), nrhs, s);
+      io(IO_HIST, {}, {history + (int64_t)(step + 1) * ldT * nrhs}, 0, &ldh, s);
+      scatter(IO_HIST, Tp.get<double>(), nrhs, s);
     }
   }
-  io({}, {T_user}, 0, &ldv, s);
-  scatter(Tp.get<double>(), nrhs, s);
+  io(IO_J, {}, {T_user}, 0, &ldv, s);
+  scatter(IO_J, Tp.get<double>(), nrhs, s);
   HM_HIP(hipStreamSynchronize(s));
   return TR;
 }

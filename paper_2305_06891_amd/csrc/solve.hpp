@@ -41,14 +41,30 @@ struct Batch {
   Krylov K64, K32;
   bool k64 = false, k32 = false;
   DevBuf Tp, epsp, omeps64, omeps32, b64, b32, x64, x32, r64, H64, g, g_eps, d_flag;
-  // refinement: slots (matrices) that still hold a system above the
-  // tolerance; the next residual product runs on those only
+  // refinement: per system, still above the tolerance; then per slot
+  // (matrix), holds such a system (the next residual product runs on those
+  // slots only)
   DevBuf res_mask;
-  std::vector<int> res_mask_h;
-  std::vector<SlotIO> ios;
-  DevBuf d_ios;
+  // Tables of the caller's per-slot buffers, one per role, in pinned host
+  // memory and on the device: an upload needs no stream synchronisation; a
+  // role's host table is rewritten only once its previous upload has
+  // completed (the role's event, normally long past).
+  enum IoRole { IO_EPS = 0, IO_T, IO_J, IO_Q, IO_SRC, IO_HIST, IO_ROLES };
+  std::vector<SlotIO> ios;  // per slot: perm, n, xoff
+  SlotIO* ios_h = nullptr;  // pinned, IO_ROLES tables
+  SlotIO* ios_hd = nullptr; // their device view
+  hipEvent_t io_ev[IO_ROLES] = {};
+  DevBuf d_ios;             // IO_ROLES tables
   std::unique_ptr<Batch> gb;  // width-1 batch for g = F C^-1 eps
   bool g_ready = false;
+  // whether this call's emissivities differ from those g was computed for:
+  // compared on the device as soon as they are gathered, read back into
+  // pinned memory, looked at when the flux needs g
+  int* eps_flag_h = nullptr;
+  void* eps_flag_hd = nullptr;
+  hipEvent_t eps_ev = nullptr;
+  bool eps_pending = false;
+  void compare_eps(hipStream_t s);
   // open cavities (eq. (35)): amb = 1 - clamp(F 1, 0, 1) per permuted row,
   // and the ambient's T^4 of the current call (open = false: closed cavity)
   DevBuf amb;
@@ -60,11 +76,14 @@ struct Batch {
   bool power_in = false;
 
   Batch(const std::vector<const hm_matrix*>& mats, int nrhs, hipStream_t s);
+  ~Batch();
+  Batch(const Batch&) = delete;
+  Batch& operator=(const Batch&) = delete;
   Krylov& krylov(int vb, int restart, hipStream_t s);
-  void io(const std::vector<const double*>& in, const std::vector<double*>& out, int64_t ld_in_default,
+  void io(int role, const std::vector<const double*>& in, const std::vector<double*>& out, int64_t ld_in_default,
           const std::vector<int64_t>* lds, hipStream_t s);
-  void gather(double* dst, int ncol, int dst_cols, hipStream_t s);
-  void scatter(const double* src, int ncol, hipStream_t s);
+  void gather(int role, double* dst, int ncol, int dst_cols, hipStream_t s);
+  void scatter(int role, const double* src, int ncol, hipStream_t s);
   void ensure_g(const std::vector<const double*>& eps_user, hipStream_t s);
   // sets open / tamb4 from p and, for an open cavity, computes amb once
   void set_ambient(const hm_solve_params& p, hipStream_t s);
