@@ -283,6 +283,7 @@ def run_c3(args):
     out["matrix"] = {"entries_dense": ent_d, "entries_lowrank": ent_l,
                      "bytes_device_mixed": sum(s["bytes_device"] for s in stx),
                      "n_fallback": sum(s["n_fallback"] for s in stx), "max_rank": max(s["max_rank"] for s in stx)}
+    out["tuning"] = Mx[0].tuning()  # one choice for the whole batch
     out["assembly_s"] = {"mixed_batched": t_asm, "fp32_one_by_one": t_asm32, "trees": t_tree}
 
     # --- the same batch with a BF16 near field too (FP32 copies for the

@@ -388,6 +388,37 @@ hm_status hm_matrix_set_tuning(hm_ctx* ctx, hm_matrix* M, int32_t rows, int32_t 
   });
 }
 
+hm_status hm_matrix_tuning_phase2(const hm_matrix* M, int32_t* p2_waves, double* us) {
+  if (!M) {
+    set_tl_error("hm_matrix_tuning_phase2: NULL matrix");
+    return HM_EINVAL;
+  }
+  if (p2_waves) *p2_waves = M->plan.p2_waves;
+  if (us) *us = M->plan.p2_us;
+  return HM_OK;
+}
+
+hm_status hm_matrix_set_tuning_phase2(hm_ctx* ctx, hm_matrix* M, int32_t p2_waves) {
+  if (!ctx) {
+    set_tl_error("hm_matrix_set_tuning_phase2: NULL ctx");
+    return HM_EINVAL;
+  }
+  return guarded(ctx, [&] {
+    HM_REQUIRE(M, "hm_matrix_set_tuning_phase2: NULL matrix");
+    HM_REQUIRE(M->device == ctx->device, "hm_matrix_set_tuning_phase2: matrix lives on another device");
+    HM_REQUIRE(p2_waves == 0 || p2_waves == 4 || p2_waves == 8,
+               "hm_matrix_set_tuning_phase2: p2_waves must be 0, 4 or 8");
+    std::lock_guard<std::mutex> lk(M->mu);
+    // compositions and captured graphs copied the old shape: drop them as
+    // hm_matrix_set_tuning does
+    HM_HIP(hipDeviceSynchronize());
+    M->cache.reset();
+    M->plan.p2_waves = p2_waves;
+    M->plan.p2_us = 0.0;
+    M->id = g_next_id++;
+  });
+}
+
 void hm_matrix_destroy(hm_matrix* M) {
   if (!M) return;
   (void)hipSetDevice(M->device);
@@ -539,6 +570,7 @@ hm_status hm_hmatvec_noalloc(hm_ctx* ctx, const hm_matrix* M, int32_t nrhs, hm_d
     V.p1_tasks = p1_tasks;
     V.p1_reds = p1_reds;
     V.p2_tiles = p2_tiles;
+    V.p2_waves = M->plan.p2_waves;
     V.nr = W;
     V.dense_dtype = M->dense_dtype;
     V.lr_dtype = M->lr_dtype;

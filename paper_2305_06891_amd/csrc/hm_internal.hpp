@@ -215,6 +215,10 @@ struct Plan {
   std::vector<P1Tau> taus;
   P1Params p1p;
   double p1_us = 0.0;  // measured time of the chosen split (0: not timed)
+  // waves per phase-2 workgroup for one or two right-hand sides: 4 or 8
+  // (the same bits either way), 0 = by tile count (4 from P2_MANY_TILES)
+  int32_t p2_waves = 0;
+  double p2_us = 0.0;  // measured phase-2 time of that choice (0: not timed)
   std::vector<P1Item> p1;
   std::vector<int32_t> p1_task;  // item begin per task, size ntasks + 1
   std::vector<P1Red> p1red;
@@ -302,6 +306,7 @@ struct Composition {
   std::vector<int64_t> xoff;  // row offset per slot
   int64_t N = 0;              // total rows
   int32_t p1_tasks = 0, p1_reds = 0, p2_tiles = 0;
+  int32_t p2_waves = 0;       // the members' common tuned choice, else 0
   std::vector<SlotDev> slots_lo, slots_hi;  // hi: FP32 copies of BF16 factors
   DevBuf d_slots_lo, d_slots_hi;
   // slot of every phase-1 task, then of every reduction, then of every tile
@@ -321,8 +326,9 @@ void plan_phase1(Plan& P, const P1Params& pp);
 // Re-split phase 1 and upload its lists (the matrix must not be in use).
 void replan_phase1(hm_matrix& M, const P1Params& pp, hipStream_t s);
 // Times the candidate phase-1 splits on M (FP32 vectors unless the factors
-// are FP64; products of `width` columns, 1..16) and keeps the fastest.  Call
-// before any composition of M exists.
+// are FP64; products of `width` columns, 1..16) and keeps the fastest; for
+// one or two columns then times phase 2 with 4 and 8 waves per workgroup
+// and keeps the faster.  Call before any composition of M exists.
 void autotune_phase1(hm_matrix& M, hipStream_t s, int width = 1);
 // The same for several matrices multiplied together: one split for all,
 // timed on their batched product.
@@ -361,6 +367,7 @@ struct CompView {
   void* xr = nullptr;  // row-major input rows (16-column products only)
   int64_t N = 0;
   int32_t p1_tasks = 0, p1_reds = 0, p2_tiles = 0;
+  int32_t p2_waves = 0;
   int nr = 1;
   hm_dtype dense_dtype = HM_F32, lr_dtype = HM_F32;
   bool has_hi = false;

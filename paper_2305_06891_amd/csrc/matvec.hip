@@ -326,11 +326,47 @@ void autotune_phase1_joint(const std::vector<hm_matrix*>& mats, hipStream_t s, i
     for (auto& e : ev) (void)hipEventDestroy(e);
     throw;
   }
-  for (auto& e : ev) HM_HIP(hipEventDestroy(e));
   for (hm_matrix* M : ms) {
     replan_phase1(*M, best, s);
     M->plan.p1_us = best_us;
+    M->plan.p2_waves = 0;
+    M->plan.p2_us = 0.0;
   }
+  // phase 2 of one- and two-column products: 4 or 8 waves per workgroup
+  // (both give the same bits); the split above does not affect phase 2
+  int best_w = 0;
+  double best_p2 = 1e30;
+  try {
+    if (W <= 2) {
+      auto comp = make_composition(cms, W, vb, s);
+      for (int w : {4, 8}) {
+        comp->p2_waves = w;
+        double tot = 0;
+        const int reps = 6;
+        for (int k = 0; k < reps + 1; ++k) {
+          launch_matvec(*comp, width, vb, false, X.get(), n, Y.get(), n, Epilogue{}, nullptr, s, ev);
+          HM_HIP(hipEventSynchronize(ev[2]));
+          float a = 0;
+          HM_HIP(hipEventElapsedTime(&a, ev[1], ev[2]));
+          if (k > 0) tot += a;
+        }
+        const double us = 1e3 * tot / reps;
+        if (us < best_p2) {
+          best_p2 = us;
+          best_w = w;
+        }
+      }
+    }
+  } catch (...) {
+    for (auto& e : ev) (void)hipEventDestroy(e);
+    throw;
+  }
+  for (auto& e : ev) HM_HIP(hipEventDestroy(e));
+  if (best_w)
+    for (hm_matrix* M : ms) {
+      M->plan.p2_waves = best_w;
+      M->plan.p2_us = best_p2;
+    }
 }
 
 void autotune_phase1(hm_matrix& M, hipStream_t s, int width) { autotune_phase1_joint({&M}, s, width); }
@@ -402,6 +438,9 @@ std::unique_ptr<Composition> make_composition(const std::vector<const hm_matrix*
   C->p1_tasks = t1;
   C->p1_reds = r1;
   C->p2_tiles = t2;
+  C->p2_waves = mats[0]->plan.p2_waves;
+  for (const hm_matrix* M : mats)
+    if (M->plan.p2_waves != C->p2_waves) C->p2_waves = 0;
   C->slot_of.clear();
   for (int pass = 0; pass < 3; ++pass)
     for (size_t q = 0; q < mats.size(); ++q) {
@@ -1462,10 +1501,11 @@ void launch_typed(const CompView& C, int nrr, bool hi, const void* X, int64_t ld
                          sof + C.p1_tasks + C.p1_reds, slot_active, nrr, (const VT*)X, ldx,
                          (const VT*)C.xr, (VT*)Y, ldy, e);
     else {
-      // four waves per workgroup on many tiles, for one or two right-hand
-      // sides (wider products would spill the second set of sums)
+      // four waves per workgroup (tuned, else on many tiles), for one or
+      // two right-hand sides (wider products would spill the second set of
+      // sums)
       bool four = false;
-      if constexpr (NR <= 2) four = C.p2_tiles >= P2_MANY_TILES;
+      if constexpr (NR <= 2) four = C.p2_waves ? C.p2_waves == 4 : C.p2_tiles >= P2_MANY_TILES;
       if constexpr (NR <= 2) {
         if (four)
           hipLaunchKernelGGL((k_phase2<DT, LT, VT, NR, 4>), dim3(C.p2_tiles), dim3(64 * 4), 0, s, slots,
@@ -1511,6 +1551,7 @@ void launch_matvec(const Composition& C, int nrr, int vb, bool hi, const void* X
   V.p1_tasks = C.p1_tasks;
   V.p1_reds = C.p1_reds;
   V.p2_tiles = C.p2_tiles;
+  V.p2_waves = C.p2_waves;
   V.nr = C.nr;
   V.dense_dtype = M0.dense_dtype;
   V.lr_dtype = M0.lr_dtype;

@@ -113,6 +113,8 @@ _PROTOS = {
                                  C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
     "hm_matrix_tuning": (C.c_int, [_vp, C.POINTER(C.c_int32), C.POINTER(C.c_int32), _dp]),
     "hm_matrix_set_tuning": (C.c_int, [_vp, _vp, C.c_int32, C.c_int32]),
+    "hm_matrix_tuning_phase2": (C.c_int, [_vp, C.POINTER(C.c_int32), _dp]),
+    "hm_matrix_set_tuning_phase2": (C.c_int, [_vp, _vp, C.c_int32]),
     "hm_matrix_destroy": (None, [_vp]),
     "hm_hmatvec": (C.c_int, [_vp, _vp, C.c_int32, C.c_int, _vp, C.c_int64, _vp, C.c_int64, C.c_double,
                              C.c_double]),
@@ -304,12 +306,20 @@ class HMatrix:
         wave task) and its measured time in microseconds (0: not timed)."""
         r, tb, us = C.c_int32(), C.c_int32(), C.c_double()
         _check(lib.hm_matrix_tuning(self._h, C.byref(r), C.byref(tb), C.byref(us)))
-        return {"p1_rows": r.value, "p1_task_bytes": tb.value, "p1_us": us.value}
+        w, us2 = C.c_int32(), C.c_double()
+        _check(lib.hm_matrix_tuning_phase2(self._h, C.byref(w), C.byref(us2)))
+        return {"p1_rows": r.value, "p1_task_bytes": tb.value, "p1_us": us.value, "p2_waves": w.value,
+                "p2_us": us2.value}
 
     def set_tuning(self, ctx, p1_rows, p1_task_bytes):
         """Sets the work split of the product's first kernel (the values
         ``tuning()`` reports)."""
         _check(lib.hm_matrix_set_tuning(ctx._h, self._h, int(p1_rows), int(p1_task_bytes)))
+
+    def set_tuning_phase2(self, ctx, p2_waves):
+        """Sets the second kernel's waves per workgroup (0: by tile count,
+        4 or 8) for products of one or two columns."""
+        _check(lib.hm_matrix_set_tuning_phase2(ctx._h, self._h, int(p2_waves)))
 
     def close(self):
         if self._h:

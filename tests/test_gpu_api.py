@@ -6,6 +6,9 @@ stream-ordered reuse of the library's device memory.
   graph of the matrix is rebuilt: products and solves (also a batched solve
   that was cached under another matrix) equal the ones before the change up
   to the order of partial sums (1e-13 relative, FP64 vectors).
+* The autotuner also picks the second kernel's waves per workgroup (4 or
+  8) and reports its time; every shape (4, 8, or by tile count) gives the
+  same bits for one and two columns, FP32 and FP64 vectors.
 * Two contexts on two streams in one thread, issuing products of the same
   matrices and solves interleaved without synchronising in between, give
   the same bits as the same calls issued one by one with a synchronisation
@@ -67,6 +70,35 @@ def test_set_tuning_rebuilds_cached_state(hm):
     log("rel differences after set_tuning:", ["%.1e" % e for e in errs])
     assert errs[0] <= 1e-13
     assert max(errs[1:]) <= 1e-11
+
+
+def test_phase2_shape_is_tuned_and_changes_no_bits(hm):
+    import torch
+    ctx = hm.Context(0)
+    v, f = meshes.ellipsoid(14, (3.0, 2.0, 1.0))
+    f = meshes.inward(f)
+    c, nrm, a = hm.hm_facets_from_triangles(v, f, orient=1)
+    tree = hm.hm_build_cluster_tree(ctx, c, nrm, a, 64, 1.5)
+    M = hm.hm_assemble_hmatrix(ctx, tree, 1e-6, 256, hm.HM_BF16, hm.HM_F32, 1, autotune=1)
+    n = f.shape[0]
+    t = M.tuning()
+    log("case: phase-2 shapes, ellipsoid %d facets, autotuned: %s" % (n, t))
+    assert t["p2_waves"] in (4, 8) and t["p2_us"] > 0.0
+    dev = torch.device("cuda:0")
+    outs = {}
+    for w in (4, 8, 0):
+        M.set_tuning_phase2(ctx, w)
+        assert M.tuning()["p2_waves"] == w
+        for dt in (torch.float32, torch.float64):
+            for nr in (1, 2):
+                X = torch.as_tensor(np.random.default_rng(nr).uniform(0.5, 1.5, (n, nr)), dtype=dt,
+                                    device=dev).t().contiguous().t()
+                Y = torch.zeros_like(X)
+                hm.hm_hmatvec(ctx, M, X, Y)
+                torch.cuda.synchronize()
+                outs.setdefault((dt, nr), []).append(to_np(Y))
+    for k, ys in outs.items():
+        assert all(np.array_equal(ys[0], y) for y in ys[1:]), k
 
 
 def test_two_streams_interleaved_equal_sequential(hm):

@@ -129,6 +129,8 @@ def test_entry_points_reject_missing_handles():
     assert hm.lib.hm_assemble_hmatrix_batched(None, 1, trees, params, out) == hm.HM_EINVAL
     assert hm.lib.hm_matrix_set_tuning(None, None, 64, 0) == hm.HM_EINVAL
     assert hm.lib.hm_matrix_tuning(None, None, None, None) == hm.HM_EINVAL
+    assert hm.lib.hm_matrix_set_tuning_phase2(None, None, 4) == hm.HM_EINVAL
+    assert hm.lib.hm_matrix_tuning_phase2(None, None, None) == hm.HM_EINVAL
     assert hm.lib.hm_matrix_stats(None, None, None, None, None) == hm.HM_EINVAL
     assert out[0] is None
 
