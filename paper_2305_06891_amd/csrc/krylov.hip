@@ -47,7 +47,6 @@ void Krylov::drop_graphs() {
 Krylov::~Krylov() {
   drop_graphs();
   if (cap) (void)hipStreamDestroy(cap);
-  if (xch_h) (void)hipHostFree(xch_h);
 }
 
 void Krylov::init(const Composition& Cm, SysSet& Ss, int vec_bytes, int restart, hipStream_t s) {
@@ -73,8 +72,13 @@ void Krylov::init(const Composition& Cm, SysSet& Ss, int vec_bytes, int restart,
   const size_t nslots = std::max<size_t>(1, Cm.mats.size());
   xch_bytes = ((size_t)ns * (MAXM + 3)) * 8 + (((2 * (size_t)ns + nslots) * 4 + 7) & ~(size_t)7);
   xch.alloc(xch_bytes);
-  if (xch_h) (void)hipHostFree(xch_h);
-  xch_h = pinned_alloc(xch_bytes + (size_t)ns * 8, &xch_hd);
+  const size_t hb = xch_bytes + (size_t)ns * 8;
+  if (!xch_lease || xch_lease->bytes < hb) {
+    xch_lease.reset();
+    xch_lease = std::make_unique<PinnedLease>(hb);
+  }
+  xch_h = xch_lease->p;
+  xch_hd = xch_lease->dev;
   g = xch.get<double>();
   tol = g + (size_t)ns * (MAXM + 1);
   bnorm = tol + ns;

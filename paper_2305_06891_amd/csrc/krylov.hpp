@@ -2,6 +2,8 @@
 // (I - diag(1 - eps) F) J = b, with F applied as an H-matrix product.
 #pragma once
 
+#include <memory>
+
 #include "hm_internal.hpp"
 
 namespace hm {
@@ -40,6 +42,31 @@ struct GmresStats {
   bool converged = true;
 };
 
+// Copies a few kilobytes between pinned host memory (its device view) and
+// device memory with a kernel on stream s: unlike a runtime copy it needs no
+// DMA engine, whose hand-over to the next kernel costs tens of
+// microseconds.  bytes and both addresses: multiples of 8.
+void copy_small(const void* src, void* dst, size_t bytes, hipStream_t s);
+
+// Pinned host memory, mapped for kernels and coherent, for small exchanges.
+void* pinned_alloc(size_t bytes, void** dev);
+
+// Pinned host memory for small host <-> device exchanges (copies from
+// pageable memory go through a bounce buffer and take tens of microseconds
+// each).  A lease takes a buffer of at least `need` bytes from a process-wide
+// free list and returns it when it ends; the holder makes sure every copy
+// from or to it has completed by then (a lease left by an exception keeps
+// its buffer).  Buffers are never freed: a few per thread that solves.
+struct PinnedLease {
+  void* p = nullptr;    // host pointer
+  void* dev = nullptr;  // the same memory as kernels see it
+  size_t bytes = 0;
+  explicit PinnedLease(size_t need);
+  ~PinnedLease();
+  PinnedLease(const PinnedLease&) = delete;
+  PinnedLease& operator=(const PinnedLease&) = delete;
+};
+
 // Workspace of the Krylov iteration for one composition and vector type.
 // A captured block of Arnoldi steps (kernels only) and what it was captured for.
 struct StepGraph {
@@ -71,7 +98,10 @@ struct Krylov {
   int *act = nullptr, *steps = nullptr, *slot_cnt = nullptr;
   size_t xch_bytes = 0;  // a multiple of 8
   // pinned host side: the exchange block, then ns doubles of norms; the
-  // kernels use its device view xch_hd
+  // kernels use its device view xch_hd.  Leased from the process-wide pool
+  // (workspaces are built per serving round), never touched by the device
+  // once a call on this workspace has returned.
+  std::unique_ptr<PinnedLease> xch_lease;
   void* xch_h = nullptr;
   void* xch_hd = nullptr;
   // graphs of Arnoldi step blocks (valid while the buffers above and the
@@ -103,30 +133,7 @@ enum : unsigned {
 GmresStats gmres(Krylov& K, bool hi, const void* omeps, const void* b, void* x, double rtol, int max_iter,
                  hipStream_t s, bool graphs = false, unsigned opts = 0, const double* bnorm = nullptr);
 
-// Copies a few kilobytes between pinned host memory (its device view) and
-// device memory with a kernel on stream s: unlike a runtime copy it needs no
-// DMA engine, whose hand-over to the next kernel costs tens of
-// microseconds.  bytes and both addresses: multiples of 8.
-void copy_small(const void* src, void* dst, size_t bytes, hipStream_t s);
 
-// Pinned host memory, mapped for kernels and coherent, for small exchanges.
-void* pinned_alloc(size_t bytes, void** dev);
-
-// Pinned host memory for small host <-> device exchanges (copies from
-// pageable memory go through a bounce buffer and take tens of microseconds
-// each).  A lease takes a buffer of at least `need` bytes from a process-wide
-// free list and returns it when it ends; the holder makes sure every copy
-// from or to it has completed by then (a lease left by an exception keeps
-// its buffer).  Buffers are never freed: a few per thread that solves.
-struct PinnedLease {
-  void* p = nullptr;    // host pointer
-  void* dev = nullptr;  // the same memory as kernels see it
-  size_t bytes = 0;
-  explicit PinnedLease(size_t need);
-  ~PinnedLease();
-  PinnedLease(const PinnedLease&) = delete;
-  PinnedLease& operator=(const PinnedLease&) = delete;
-};
 
 // Per-system 2-norms of a vector block (FP64 accumulation).
 void block_norms(Krylov& K, const void* v, std::vector<double>& out, hipStream_t s);

@@ -227,12 +227,12 @@ Batch::~Batch() {
       (void)hipEventSynchronize(e);
       (void)hipEventDestroy(e);
     }
-  if (ios_h) (void)hipHostFree(ios_h);
   if (eps_ev) {
     (void)hipEventSynchronize(eps_ev);
     (void)hipEventDestroy(eps_ev);
   }
-  if (eps_flag_h) (void)hipHostFree(eps_flag_h);
+  // the pinned tables go back to the pool: every upload from them and the
+  // flag's read-back have completed (the events above)
 }
 
 void Batch::io(int role, const std::vector<const double*>& in, const std::vector<double*>& out,
@@ -240,7 +240,11 @@ void Batch::io(int role, const std::vector<const double*>& in, const std::vector
   HM_REQUIRE(role >= 0 && role < IO_ROLES, "batch: bad io role");
   const size_t ns = ios.size();
   static_assert(sizeof(SlotIO) % 8 == 0, "slot tables are copied in 8-byte words");
-  if (!ios_h) ios_h = (SlotIO*)pinned_alloc((size_t)IO_ROLES * ns * sizeof(SlotIO), (void**)&ios_hd);
+  if (!ios_lease) {
+    ios_lease = std::make_unique<PinnedLease>((size_t)IO_ROLES * ns * sizeof(SlotIO));
+    ios_h = (SlotIO*)ios_lease->p;
+    ios_hd = (SlotIO*)ios_lease->dev;
+  }
   if (io_ev[role])
     HM_HIP(hipEventSynchronize(io_ev[role]));  // the previous upload of this table has read it
   else
@@ -275,7 +279,11 @@ void Batch::scatter(int role, const double* src, int ncol, hipStream_t s) {
 void Batch::compare_eps(hipStream_t s) {
   eps_pending = false;
   if (!g_ready) return;
-  if (!eps_flag_h) eps_flag_h = (int*)pinned_alloc(64, &eps_flag_hd);
+  if (!eps_lease) {
+    eps_lease = std::make_unique<PinnedLease>(64);
+    eps_flag_h = (int*)eps_lease->p;
+    eps_flag_hd = eps_lease->dev;
+  }
   if (!eps_ev) HM_HIP(hipEventCreateWithFlags(&eps_ev, hipEventDisableTiming));
   HM_HIP(hipMemsetAsync(d_flag.get(), 0, 8, s));
   hipLaunchKernelGGL(k_differs, grid_rows(N), dim3(256), 0, s, epsp.get<double>(), g_eps.get<double>(), N,

@@ -51,7 +51,8 @@ struct Batch {
   // completed (the role's event, normally long past).
   enum IoRole { IO_EPS = 0, IO_T, IO_J, IO_Q, IO_SRC, IO_HIST, IO_ROLES };
   std::vector<SlotIO> ios;  // per slot: perm, n, xoff
-  SlotIO* ios_h = nullptr;  // pinned, IO_ROLES tables
+  std::unique_ptr<PinnedLease> ios_lease;  // pinned, IO_ROLES tables
+  SlotIO* ios_h = nullptr;
   SlotIO* ios_hd = nullptr; // their device view
   hipEvent_t io_ev[IO_ROLES] = {};
   DevBuf d_ios;             // IO_ROLES tables
@@ -60,6 +61,7 @@ struct Batch {
   // whether this call's emissivities differ from those g was computed for:
   // compared on the device as soon as they are gathered, read back into
   // pinned memory, looked at when the flux needs g
+  std::unique_ptr<PinnedLease> eps_lease;
   int* eps_flag_h = nullptr;
   void* eps_flag_hd = nullptr;
   hipEvent_t eps_ev = nullptr;
