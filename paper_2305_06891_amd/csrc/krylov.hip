@@ -98,6 +98,7 @@ struct GsArgs {
   const SysDev* sys;
   const ChunkDev* chunks;
   int mode;        // 0 dots, 1 update(hA)+dots, 2 update(hB)+norm+Givens, 3 norm -> beta
+  int cgs1;        // mode 2 updates with hA (no mode 1 ran: one pass)
   int j;           // Arnoldi step
   void* w;         // vector block being orthogonalised / normed
   const void* basis;
@@ -132,7 +133,7 @@ __global__ __launch_bounds__(GS_T) void k_gs(GsArgs a) {
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   const int L = (a.mode <= 1) ? a.j + 1 : 0;
   if (a.mode == 1 || a.mode == 2) {
-    const double* src = a.mode == 1 ? a.hA : a.hB;
+    const double* src = (a.mode == 1 || a.cgs1) ? a.hA : a.hB;
     for (int l = tid; l <= a.j; l += GS_T) coef[l] = src[(int64_t)s * (MAXM + 1) + l];
     __syncthreads();
   }
@@ -220,7 +221,8 @@ __global__ __launch_bounds__(64) void k_gs_final(GsArgs a, int nsys) {
     const int j = a.j;
     const double hnrm = sqrt(red[0]);
     double col[MAXM + 1];
-    for (int i = 0; i <= j; ++i) col[i] = a.hA[(int64_t)s * (MAXM + 1) + i] + a.hB[(int64_t)s * (MAXM + 1) + i];
+    for (int i = 0; i <= j; ++i)
+      col[i] = a.hA[(int64_t)s * (MAXM + 1) + i] + (a.cgs1 ? 0.0 : a.hB[(int64_t)s * (MAXM + 1) + i]);
     col[j + 1] = hnrm;
     double* cs = a.cs + (int64_t)s * MAXM;
     double* sn = a.sn + (int64_t)s * MAXM;
@@ -365,8 +367,9 @@ PinnedLease::~PinnedLease() {
 // ------------------------------------------------------------------ driver
 namespace {
 
-GsArgs gs_args(Krylov& K, int mode, int j, void* wvec) {
+GsArgs gs_args(Krylov& K, int mode, int j, void* wvec, bool cgs1 = false) {
   GsArgs a;
+  a.cgs1 = cgs1 ? 1 : 0;
   a.sys = K.S->d_sys.get<SysDev>();
   a.chunks = K.S->d_chunks.get<ChunkDev>();
   a.mode = mode;
@@ -393,10 +396,10 @@ GsArgs gs_args(Krylov& K, int mode, int j, void* wvec) {
 }
 
 template <class VT>
-void run_gs(Krylov& K, int mode, int j, void* wvec, hipStream_t s) {
+void run_gs(Krylov& K, int mode, int j, void* wvec, hipStream_t s, bool cgs1 = false) {
   const unsigned nb = (unsigned)K.S->chunks.size();
   if (nb == 0) return;
-  const GsArgs a = gs_args(K, mode, j, wvec);
+  const GsArgs a = gs_args(K, mode, j, wvec, cgs1);
   hipLaunchKernelGGL(k_gs<VT>, dim3(nb), dim3(GS_T), 0, s, a);
   hipLaunchKernelGGL(k_gs_final, dim3((unsigned)K.S->size()), dim3(64), 0, s, a, K.S->size());
   HM_HIP(hipGetLastError());
@@ -415,9 +418,10 @@ void run_scale(Krylov& K, const double* div, const void* src, void* dst, hipStre
 // workspace's private stream at first use; nullptr when capture is not
 // possible (the caller then launches the block directly).
 template <class F>
-hipGraphExec_t block_graph(Krylov& K, bool hi, const void* omeps, int nrr, int j0, int nsteps, F&& body) {
+hipGraphExec_t block_graph(Krylov& K, bool hi, bool cgs1, const void* omeps, int nrr, int j0, int nsteps, F&& body) {
   for (const auto& g : K.graphs)
-    if (g.hi == hi && g.omeps == omeps && g.nrr == nrr && g.j0 == j0 && g.nsteps == nsteps) return g.exec;
+    if (g.hi == hi && g.cgs1 == cgs1 && g.omeps == omeps && g.nrr == nrr && g.j0 == j0 && g.nsteps == nsteps)
+      return g.exec;
   if (!K.cap && hipStreamCreateWithFlags(&K.cap, hipStreamNonBlocking) != hipSuccess) {
     K.cap = nullptr;
     return nullptr;
@@ -438,6 +442,7 @@ hipGraphExec_t block_graph(Krylov& K, bool hi, const void* omeps, int nrr, int j
   if (!ge) return nullptr;
   StepGraph sg;
   sg.hi = hi;
+  sg.cgs1 = cgs1;
   sg.omeps = omeps;
   sg.nrr = nrr;
   sg.j0 = j0;
@@ -490,6 +495,7 @@ GmresStats gmres_t(Krylov& K, bool hi, const void* omeps, const void* b, void* x
   op_ep.a_acc = -1.0;
   op_ep.a_x = 1.0;
   const int nrr = C.nr;
+  const bool cgs1 = (opts & GM_CGS1) != 0;
   int iters = 0;
   bool first = true;
   for (;;) {
@@ -539,8 +545,8 @@ GmresStats gmres_t(Krylov& K, bool hi, const void* omeps, const void* b, void* x
       char* vj1 = vj + (size_t)K.blk * K.vb;
       launch_matvec(C, nrr, K.vb, hi, vj, K.ld, K.w.get(), K.ld, op_ep, K.slot_cnt, st);
       run_gs<VT>(K, 0, j, K.w.get(), st);
-      run_gs<VT>(K, 1, j, K.w.get(), st);
-      run_gs<VT>(K, 2, j, K.w.get(), st);
+      if (!cgs1) run_gs<VT>(K, 1, j, K.w.get(), st);
+      run_gs<VT>(K, 2, j, K.w.get(), st, cgs1);
       run_scale<VT>(K, K.hn.get<double>(), K.w.get(), vj1, st);
     };
     // blocks of up to SYNC Arnoldi steps; after each the host reads the
@@ -556,7 +562,7 @@ GmresStats gmres_t(Krylov& K, bool hi, const void* omeps, const void* b, void* x
     int left = nact;
     for (int j = 0; j < K.m && iters + j < max_iter;) {
       const int nb = std::min(SYNC, std::min(K.m - j, max_iter - iters - j));
-      hipGraphExec_t ge = use_graphs ? block_graph(K, hi, omeps, nrr, j, nb, block) : nullptr;
+      hipGraphExec_t ge = use_graphs ? block_graph(K, hi, cgs1, omeps, nrr, j, nb, block) : nullptr;
       if (ge)
         HM_HIP(hipGraphLaunch(ge, s));
       else

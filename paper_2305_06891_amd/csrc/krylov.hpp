@@ -71,6 +71,7 @@ struct PinnedLease {
 // A captured block of Arnoldi steps (kernels only) and what it was captured for.
 struct StepGraph {
   bool hi = false;
+  bool cgs1 = false;
   const void* omeps = nullptr;
   int nrr = 0, j0 = 0, nsteps = 0;
   hipGraphExec_t exec = nullptr;
@@ -123,6 +124,10 @@ enum : unsigned {
   // for the true residual; rel_res then holds the estimates.  For inner
   // solves whose result the caller checks with its own residual.
   GM_TRUST_ESTIMATE = 2u,
+  // one Gram-Schmidt pass per Arnoldi step (classical, without the second,
+  // re-orthogonalising pass): for inner solves to a loose tolerance whose
+  // result the caller checks with its own residual
+  GM_CGS1 = 4u,
 };
 
 // Solve C x = b for every system of S.  b, x: vector blocks (ld = C.N) of

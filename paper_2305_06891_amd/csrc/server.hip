@@ -531,8 +531,9 @@ void hm_server::round(std::vector<SrvReq*>& act) {
     HM_HIP(hipMemsetAsync(x32.get(), 0, blk * 4, s));
     K4.init(*C, S, 4, p.solve.restart, s);
     const double inner = p.solve.mixed_precision ? p.solve.ir_inner_rtol : std::min(p.solve.ir_inner_rtol, 1e-5);
+    // one Gram-Schmidt pass per step at the loose tolerance of mixed rounds
     GmresStats gs = gmres(K4, false, om32.get(), b32.get(), x32.get(), inner, p.solve.max_iter, s, false,
-                          GM_X0_ZERO | GM_TRUST_ESTIMATE);
+                          GM_X0_ZERO | GM_TRUST_ESTIMATE | (p.solve.mixed_precision ? GM_CGS1 : 0u));
     hipLaunchKernelGGL(k_srv_acc, dim3((unsigned)((blk + 255) / 256)), dim3(256), 0, s, x32.get<float>(),
                        x64.get<double>(), (int64_t)blk);
     for (size_t q = 0; q < act.size(); ++q) {

@@ -511,7 +511,7 @@ SolveResult Batch::solve_prepared(const hm_solve_params& p, hipStream_t s, bool 
       // inner solve stops on its own residual estimate; its right-hand
       // side's norms are the FP64 residual norms (zero where converged)
       GmresStats st = gmres(K4, false, omeps32.get(), b32.get(), x32.get(), p.ir_inner_rtol, p.max_iter, s,
-                            p.use_graphs != 0, GM_X0_ZERO | GM_TRUST_ESTIMATE, inner_bn.data());
+                            p.use_graphs != 0, GM_X0_ZERO | GM_TRUST_ESTIMATE | GM_CGS1, inner_bn.data());
       hipLaunchKernelGGL(k_acc<float>, dim3(gb_), dim3(256), 0, s, x32.get<float>(), x64.get<double>(), tot);
       R.fx = false;  // x changed
       R.iters += st.iters;
