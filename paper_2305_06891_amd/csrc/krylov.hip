@@ -271,13 +271,27 @@ __global__ __launch_bounds__(GS_T) void k_scale(const SysDev* __restrict__ sys, 
   for (int r = threadIdx.x; r < c.nr; r += GS_T) dst[base + r] = (VT)((double)src[base + r] * inv);
 }
 
-// x += V y with H(0:k,0:k) y = g(0:k) (k = steps of the system).
+// x += V y with H(0:k,0:k) y = g(0:k) (k = steps of the system).  With
+// when_done (the slot counts, launched at the end of a block of Arnoldi
+// steps) only once no system is left active, else nothing: the cycle's
+// update then needs no host round trip.
 template <class VT>
 __global__ __launch_bounds__(GS_T) void k_xupdate(const SysDev* __restrict__ sys, const ChunkDev* __restrict__ chunks,
                                                   const int* __restrict__ steps, const double* __restrict__ H,
                                                   const double* __restrict__ g, const VT* __restrict__ basis,
-                                                  int64_t ld, int64_t blk, VT* __restrict__ x) {
+                                                  int64_t ld, int64_t blk, VT* __restrict__ x,
+                                                  const int* __restrict__ when_done, int nslots) {
   __shared__ double y[MAXM];
+  __shared__ int left;
+  if (when_done) {
+    if (threadIdx.x == 0) {
+      int t = 0;
+      for (int q = 0; q < nslots; ++q) t += when_done[q];
+      left = t;
+    }
+    __syncthreads();
+    if (left) return;  // uniform over the workgroup
+  }
   const ChunkDev c = chunks[blockIdx.x];
   const int s = c.sys;
   const int k = steps[s];
@@ -418,9 +432,11 @@ void run_scale(Krylov& K, const double* div, const void* src, void* dst, hipStre
 // workspace's private stream at first use; nullptr when capture is not
 // possible (the caller then launches the block directly).
 template <class F>
-hipGraphExec_t block_graph(Krylov& K, bool hi, bool cgs1, const void* omeps, int nrr, int j0, int nsteps, F&& body) {
+hipGraphExec_t block_graph(Krylov& K, bool hi, bool cgs1, const void* omeps, const void* x, int nrr, int j0,
+                           int nsteps, F&& body) {
   for (const auto& g : K.graphs)
-    if (g.hi == hi && g.cgs1 == cgs1 && g.omeps == omeps && g.nrr == nrr && g.j0 == j0 && g.nsteps == nsteps)
+    if (g.hi == hi && g.cgs1 == cgs1 && g.omeps == omeps && g.x == x && g.nrr == nrr && g.j0 == j0 &&
+        g.nsteps == nsteps)
       return g.exec;
   if (!K.cap && hipStreamCreateWithFlags(&K.cap, hipStreamNonBlocking) != hipSuccess) {
     K.cap = nullptr;
@@ -444,6 +460,7 @@ hipGraphExec_t block_graph(Krylov& K, bool hi, bool cgs1, const void* omeps, int
   sg.hi = hi;
   sg.cgs1 = cgs1;
   sg.omeps = omeps;
+  sg.x = x;
   sg.nrr = nrr;
   sg.j0 = j0;
   sg.nsteps = nsteps;
@@ -551,18 +568,27 @@ GmresStats gmres_t(Krylov& K, bool hi, const void* omeps, const void* b, void* x
     };
     // blocks of up to SYNC Arnoldi steps; after each the host reads the
     // whole exchange block back (the active counts decide whether to go on;
-    // the step counts and the rotated right-hand sides are then at hand for
-    // the update).  Steps launched after every system has converged find
-    // nothing active and return at once.
+    // the step counts and the rotated right-hand sides are then at hand).
+    // Steps launched after every system has converged find nothing active
+    // and return at once; a block that ends with none active also applies
+    // the update x += V y on the device.
     constexpr int SYNC = 4;
+    const unsigned nchunks = (unsigned)K.S->chunks.size();
+    auto update = [&](hipStream_t st, const int* when_done) {
+      hipLaunchKernelGGL(k_xupdate<VT>, dim3(nchunks), dim3(GS_T), 0, st, K.S->d_sys.get<SysDev>(),
+                         K.S->d_chunks.get<ChunkDev>(), K.steps, K.H.get<double>(), K.g,
+                         (const VT*)K.basis.get(), K.ld, K.blk, (VT*)x, when_done, nslots);
+      HM_HIP(hipGetLastError());
+    };
     auto block = [&](int j0, int nsteps, hipStream_t st) {
       for (int q = 0; q < nsteps; ++q) step(j0 + q, st);
+      update(st, K.slot_cnt);
       copy_small(K.xch.get(), K.xch_hd, K.xch_bytes, st);
     };
     int left = nact;
     for (int j = 0; j < K.m && iters + j < max_iter;) {
       const int nb = std::min(SYNC, std::min(K.m - j, max_iter - iters - j));
-      hipGraphExec_t ge = use_graphs ? block_graph(K, hi, cgs1, omeps, nrr, j, nb, block) : nullptr;
+      hipGraphExec_t ge = use_graphs ? block_graph(K, hi, cgs1, omeps, x, nrr, j, nb, block) : nullptr;
       if (ge)
         HM_HIP(hipGraphLaunch(ge, s));
       else
@@ -579,11 +605,9 @@ GmresStats gmres_t(Krylov& K, bool hi, const void* omeps, const void* b, void* x
     iters += cyc;
     st.matvecs += cyc;
     st.bytes += (int64_t)cyc * mbytes;
-    const unsigned nb = (unsigned)K.S->chunks.size();
-    hipLaunchKernelGGL(k_xupdate<VT>, dim3(nb), dim3(GS_T), 0, s, K.S->d_sys.get<SysDev>(),
-                       K.S->d_chunks.get<ChunkDev>(), K.steps, K.H.get<double>(), K.g,
-                       (const VT*)K.basis.get(), K.ld, K.blk, (VT*)x);
-    HM_HIP(hipGetLastError());
+    // a cycle that ended with systems still active (restart or iteration
+    // cap) applies its update here; otherwise the last block did
+    if (left > 0) update(s, nullptr);
     if (trusted) {
       // every system met the tolerance by its residual estimate
       for (int q = 0; q < ns; ++q) {

@@ -73,6 +73,7 @@ struct StepGraph {
   bool hi = false;
   bool cgs1 = false;
   const void* omeps = nullptr;
+  const void* x = nullptr;  // the iterate the block's update writes
   int nrr = 0, j0 = 0, nsteps = 0;
   hipGraphExec_t exec = nullptr;
 };
