@@ -19,12 +19,17 @@ Prints ONE JSON line on stdout (progress goes to stderr).
 Workload ``fe``: the finite-element coupling (Sec. 3.1-3.4), implicit Euler
 steps of a conducting 20,480-facet ellipsoid shell with cavity radiation.
 
-Default (``--workload all``): the ``c3`` record is the headline; the ``c4``
-transient, ``c5`` serving and ``fe`` coupling records ride along on the same
-JSON line (keys ``c4_transient``, ``c5_serving`` and ``fe_coupling``), each
-with its own value, roofline or latency figures and oracle baseline.
+Workload ``hlu``: the hierarchical block LU (Sec. 5.1-5.2) of four
+geometries up to a 4,992-facet cylinder, factor and solve times beside a
+GMRES solve of the same system.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload all|c3|c2|c4|c5|fe]
+Default (``--workload all``): the ``c3`` record is the headline; the ``c4``
+transient, ``c5`` serving, ``fe`` coupling and ``hlu`` records ride along on
+the same JSON line (keys ``c4_transient``, ``c5_serving``, ``fe_coupling``
+and ``block_lu``), each with its own value, roofline or latency figures and
+oracle baseline.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload all|c3|c2|c4|c5|fe|hlu]
 """
 import argparse
 import json
@@ -616,6 +621,97 @@ def run_fe(args):
     return out
 
 
+def run_hlu(args):
+    """Hierarchical block LU (Sec. 5.1) and its substitutions (Sec. 5.2),
+    FP64, eps_rel 1e-6: factor and solve times of four geometries, the
+    largest being a 4,992-facet cylinder (leaf 64), beside the time of a
+    GMRES solve of the same system on the H-matvec; value = factorisations
+    per second of the cylinder.  The oracle's block LU (plain numpy) is
+    timed on the 1,280-facet ellipsoid, the same case as the first row."""
+    import torch
+    from paper_2305_06891_amd import hm
+    from workloads import configs, meshes
+
+    ctx = hm.Context(0)
+    dev = torch.device("cuda:0")
+    cases = []
+    v, f = meshes.ellipsoid(8, (3.0, 2.0, 1.0))
+    cases.append(("ellipsoid_1280", v, meshes.inward(f), 32, 0))
+    sp = configs.fibonacci_spiral(nu=3)
+    cases.append(("spiral_13_spheres_%d" % sp.n, sp.v, sp.tri, 32, 1))
+    v, f = meshes.ellipsoid(12, (3.0, 2.0, 1.0))
+    cases.append(("ellipsoid_2880", v, meshes.inward(f), 32, 0))
+    v, f = meshes.cylinder_for_count(5000, seed=3)
+    cases.append(("cylinder_%d" % f.shape[0], v, meshes.inward(f), 64, 0))
+    rows = []
+    warm = True
+    for name, v, f, leaf, pivot in cases:
+        n = f.shape[0]
+        eps_h = np.random.default_rng(1).uniform(0.1, 0.9, n)
+        eps = torch.as_tensor(eps_h, device=dev)
+        c, nrm, area = hm.hm_facets_from_triangles(v, f, orient=1)
+        tree = hm.hm_build_cluster_tree(ctx, c, nrm, area, leaf, 1.5)
+        if warm:  # first launches of every kernel
+            hm.hm_hlu_factor(ctx, tree, eps, aca_tol=1e-6, aca_pivot=pivot)
+            warm = False
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        LU = hm.hm_hlu_factor(ctx, tree, eps, aca_tol=1e-6, aca_pivot=pivot)
+        torch.cuda.synchronize()
+        t_f = time.perf_counter() - t0
+        st = LU.stats()
+        b = torch.ones(n, dtype=torch.float64, device=dev)
+        LU.solve(b)
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(5):
+            t0 = time.perf_counter()
+            LU.solve(b)
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t0)
+        # the same system by GMRES on the FP64 H-matvec (assembled at the same tolerance)
+        M = hm.hm_assemble_hmatrix(ctx, tree, 1e-6, 256, hm.HM_F64, hm.HM_F64, aca_pivot=pivot)
+        T = torch.as_tensor(np.full(n, 800.0), device=dev)
+        p = hm.solve_params(rtol=1e-10, want_q=0)
+        hm.hm_solve_radiosity(ctx, M, eps, T, params=p)
+        torch.cuda.synchronize()
+        tg = []
+        for _ in range(5):
+            t0 = time.perf_counter()
+            hm.hm_solve_radiosity(ctx, M, eps, T, params=p)
+            torch.cuda.synchronize()
+            tg.append(time.perf_counter() - t0)
+        rows.append({"case": name, "n": n, "leaf": leaf, "full_pivot_aca": pivot, "factor_s": t_f,
+                     "solve_ms": 1e3 * float(np.median(ts)), "entries": st["entries"], "dense_entries": n * n,
+                     "max_rank": st["max_rank"], "gmres_solve_ms": 1e3 * float(np.median(tg))})
+        log("hlu: %s n %d factor %.2f s, solve %.2f ms, entries %d (dense %d), GMRES %.2f ms"
+            % (name, n, t_f, rows[-1]["solve_ms"], st["entries"], n * n, rows[-1]["gmres_solve_ms"]))
+        del LU, M
+    cyl = rows[-1]
+    out = {"metric": "block-LU factorisations/s (FP64, eps_rel 1e-6)", "value": 1.0 / cyl["factor_s"],
+           "unit": "factorisations/s", "dtype": "f64",
+           "config": {"workload": cyl["case"], "facets": cyl["n"], "leaf": 64, "eta": 1.5, "eps_rel": 1e-6},
+           "cases": rows}
+    if not args.no_cpu_baseline:
+        from oracle import geometry, hlu as ohlu
+        v, f = meshes.ellipsoid(8, (3.0, 2.0, 1.0))
+        f = meshes.inward(f)
+        eps_h = np.random.default_rng(1).uniform(0.1, 0.9, f.shape[0])
+        cg, ng, ag = geometry.facets_from_triangles(v, f)
+
+        def factor():
+            root, _ = ohlu.build_reflection(cg, ng, ag, eps_h, 32, 1.5, 1e-6)
+            ohlu.factorize(root, 1e-6)
+
+        t_o, _ = _best_of(factor, reps=2)
+        out["cpu_baseline"] = {"value": 1.0 / t_o, "unit": "factorisations/s", "cores": _blas_threads(),
+                               "kind": "oracle",
+                               "sample": "the oracle's block LU (assembly of the blocks + factorisation) of the "
+                                         "1,280-facet ellipsoid, warm-up then best of 2; the GPU factors it in "
+                                         "%.2f s" % rows[0]["factor_s"]}
+    return out
+
+
 def run_c5(args):
     """Serving: a stream of radiosity-solve requests on 256 cavity ids
     (1k-100k facets, Zipf 1.1 over ids, 1-8 right-hand sides), BF16 factors
@@ -799,7 +895,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50, help="timed batched solves of the 64-cavity workload")
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="all", choices=["all", "c3", "c2", "c4", "c5", "fe"],
+    ap.add_argument("--workload", default="all", choices=["all", "c3", "c2", "c4", "c5", "fe", "hlu"],
                     help="all: the 64-cavity batch (the headline record) with the transient and serving "
                          "records attached to the same line")
     ap.add_argument("--recompress", type=int, default=1, choices=[0, 1],
@@ -828,8 +924,11 @@ def main():
         out["c5_serving"] = run_c5(args)
         gc.collect()
         out["fe_coupling"] = run_fe(args)
+        gc.collect()
+        out["block_lu"] = run_hlu(args)
     else:
-        out = {"c3": run_c3, "c2": run_c2, "c4": run_c4, "c5": run_c5, "fe": run_fe}[args.workload](args)
+        out = {"c3": run_c3, "c2": run_c2, "c4": run_c4, "c5": run_c5, "fe": run_fe,
+               "hlu": run_hlu}[args.workload](args)
     print(json.dumps(out), flush=True)
 
 
