@@ -108,6 +108,168 @@ __global__ __launch_bounds__(256) void k_fe_dot(const double* __restrict__ a, co
   if (threadIdx.x == 0) part[blockIdx.x] = (sh[0] + sh[1]) + (sh[2] + sh[3]);
 }
 
+// ---- conjugate gradients of the preconditioner with device scalars: the
+// current and next r.z (two slots, alternating with the iteration's
+// parity), p.Ap, r.r, the stopping threshold (pc_rtol |r0|)^2, the done and
+// error flags and the iteration count.  Every kernel after the start reads
+// the done flag first and does nothing once it is set, so iterations
+// launched past convergence change nothing; the host looks at the scalars
+// every few iterations.  Sums over a vector are block partials (fixed tree
+// order) added by one workgroup in block order.
+enum : int { CG_RZ = 0, CG_PAP = 2, CG_RR = 3, CG_TOL2 = 4, CG_DONE = 5, CG_ITS = 6, CG_ERR = 7, CG_N = 8 };
+
+__device__ __forceinline__ double block_sum256(double v, double* sh) {
+  v = wave_sum(v);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+  __syncthreads();
+  const double t = (sh[0] + sh[1]) + (sh[2] + sh[3]);
+  __syncthreads();
+  return t;
+}
+
+// the npart sums of the partials part[q * stride + k], k = 0..npart-1
+// (one workgroup of 256; thread t adds blocks t, t + 256, ... in order)
+__device__ __forceinline__ void sum_partials(const double* __restrict__ part, int64_t nb, int npart, double* out) {
+  __shared__ double sh[4];
+  for (int k = 0; k < npart; ++k) {
+    double v = 0.0;
+    for (int64_t q = threadIdx.x; q < nb; q += 256) v += part[q * npart + k];
+    out[k] = block_sum256(v, sh);
+  }
+}
+
+// z = 0, res = r, zz = r / d, p = zz; partials of r.r and r.zz
+__global__ __launch_bounds__(256) void k_cg_init(const double* __restrict__ r, const double* __restrict__ d,
+                                                 int64_t n, double* __restrict__ z, double* __restrict__ res,
+                                                 double* __restrict__ zz, double* __restrict__ p,
+                                                 double* __restrict__ part) {
+  __shared__ double sh[4];
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  double rr = 0.0, rz = 0.0;
+  if (i < n) {
+    const double v = r[i], w = v / d[i];
+    z[i] = 0.0;
+    res[i] = v;
+    zz[i] = w;
+    p[i] = w;
+    rr = v * v;
+    rz = v * w;
+  }
+  rr = block_sum256(rr, sh);
+  rz = block_sum256(rz, sh);
+  if (threadIdx.x == 0) {
+    part[2 * blockIdx.x] = rr;
+    part[2 * blockIdx.x + 1] = rz;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_cg_fin_init(const double* __restrict__ part, int64_t nb, double rtol2,
+                                                     double* __restrict__ cg) {
+  double t[2];
+  sum_partials(part, nb, 2, t);
+  if (threadIdx.x == 0) {
+    cg[CG_RR] = t[0];
+    cg[CG_RZ] = t[1];
+    cg[CG_RZ + 1] = 0.0;
+    cg[CG_PAP] = 0.0;
+    cg[CG_TOL2] = rtol2 * t[0];
+    cg[CG_DONE] = t[0] == 0.0 ? 1.0 : 0.0;
+    cg[CG_ITS] = 0.0;
+    cg[CG_ERR] = 0.0;
+  }
+}
+
+// ap = A p and partials of p.ap
+__global__ __launch_bounds__(256) void k_cg_ap(const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
+                                               const double* __restrict__ av, const double* __restrict__ p,
+                                               int64_t n, double* __restrict__ ap, const double* __restrict__ cg,
+                                               double* __restrict__ part) {
+  __shared__ double sh[4];
+  if (cg[CG_DONE] != 0.0) return;
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  double v = 0.0;
+  if (i < n) {
+    double s = 0.0;
+    for (int32_t e = rp[i]; e < rp[i + 1]; ++e) s += av[e] * p[ci[e]];
+    ap[i] = s;
+    v = p[i] * s;
+  }
+  v = block_sum256(v, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = v;
+}
+
+__global__ __launch_bounds__(256) void k_cg_fin_pap(const double* __restrict__ part, int64_t nb,
+                                                    double* __restrict__ cg) {
+  if (cg[CG_DONE] != 0.0) return;
+  double t;
+  sum_partials(part, nb, 1, &t);
+  if (threadIdx.x == 0) {
+    if (t > 0.0 && t <= 1.7e308) {
+      cg[CG_PAP] = t;
+    } else {  // not positive definite (or not finite): stop with an error
+      cg[CG_ERR] = 1.0;
+      cg[CG_DONE] = 1.0;
+    }
+  }
+}
+
+// z += alpha p, res -= alpha ap, zz = res / d (alpha = r.z / p.Ap);
+// partials of res.res and res.zz
+__global__ __launch_bounds__(256) void k_cg_step(const double* __restrict__ cg, int par, const double* __restrict__ p,
+                                                 const double* __restrict__ ap, const double* __restrict__ d,
+                                                 int64_t n, double* __restrict__ z, double* __restrict__ res,
+                                                 double* __restrict__ zz, double* __restrict__ part) {
+  __shared__ double sh[4];
+  if (cg[CG_DONE] != 0.0) return;
+  const double alpha = cg[CG_RZ + par] / cg[CG_PAP];
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  double rr = 0.0, rz = 0.0;
+  if (i < n) {
+    z[i] += alpha * p[i];
+    const double v = res[i] - alpha * ap[i], w = v / d[i];
+    res[i] = v;
+    zz[i] = w;
+    rr = v * v;
+    rz = v * w;
+  }
+  rr = block_sum256(rr, sh);
+  rz = block_sum256(rz, sh);
+  if (threadIdx.x == 0) {
+    part[2 * blockIdx.x] = rr;
+    part[2 * blockIdx.x + 1] = rz;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_cg_fin_step(const double* __restrict__ part, int64_t nb, int par,
+                                                     double* __restrict__ cg) {
+  if (cg[CG_DONE] != 0.0) return;
+  double t[2];
+  sum_partials(part, nb, 2, t);
+  if (threadIdx.x == 0) {
+    cg[CG_RR] = t[0];
+    cg[CG_RZ + 1 - par] = t[1];
+    cg[CG_ITS] += 1.0;
+    if (t[0] <= cg[CG_TOL2]) cg[CG_DONE] = 1.0;
+  }
+}
+
+// p = zz + beta p, beta = (new r.z) / (old r.z)
+__global__ __launch_bounds__(256) void k_cg_dir(const double* __restrict__ cg, int par,
+                                                const double* __restrict__ zz, int64_t n, double* __restrict__ p) {
+  if (cg[CG_DONE] != 0.0) return;
+  const double beta = cg[CG_RZ + 1 - par] / cg[CG_RZ + par];
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < n) p[i] = zz[i] + beta * p[i];
+}
+
+// out = the sum of the partials of k_fe_dot (fixed order)
+__global__ __launch_bounds__(256) void k_fe_dot_fin(const double* __restrict__ part, int64_t nb,
+                                                    double* __restrict__ out) {
+  double t;
+  sum_partials(part, nb, 1, &t);
+  if (threadIdx.x == 0) out[0] = t;
+}
+
 }  // namespace
 }  // namespace hm
 
@@ -121,9 +283,10 @@ struct hm_fe {
   hm_fe_params p{};
   DevBuf tri, nptr, nfac, area, eps, rp, ci, mv, kv, pcv, pcd;  // mesh, CSR of M, K and M/dt + K
   std::unique_ptr<Batch> B;
-  // work vectors
-  DevBuf eta, qf, Jf, part;
-  std::vector<double> part_h;
+  // work vectors; device scalars of the conjugate gradients and of dot
+  // products, read back through mapped pinned memory
+  DevBuf eta, qf, Jf, part, cg;
+  std::unique_ptr<hm::PinnedLease> cg_h;
   int cavity_solves = 0, pc_iterations = 0;
 };
 
@@ -131,15 +294,21 @@ namespace hm {
 
 namespace {
 
+// The device scalars (CG_N doubles) on the host.
+const double* fetch_scalars(hm_fe& fe, hipStream_t s) {
+  copy_small(fe.cg.get(), fe.cg_h->dev, CG_N * 8, s);
+  HM_HIP(hipStreamSynchronize(s));
+  return (const double*)fe.cg_h->p;
+}
+
 double fe_dot(hm_fe& fe, const double* a, const double* b, hipStream_t s) {
   const int64_t nb = (fe.nn + 255) / 256;
   hipLaunchKernelGGL(k_fe_dot, dim3((unsigned)nb), dim3(256), 0, s, a, b, fe.nn, fe.part.get<double>());
+  hipLaunchKernelGGL(k_fe_dot_fin, dim3(1), dim3(256), 0, s, fe.part.get<double>(), nb, fe.cg.get<double>() + CG_N);
   HM_HIP(hipGetLastError());
-  HM_HIP(hipMemcpyAsync(fe.part_h.data(), fe.part.get(), nb * 8, hipMemcpyDeviceToHost, s));
+  copy_small(fe.cg.get<double>() + CG_N, fe.cg_h->dev, 8, s);
   HM_HIP(hipStreamSynchronize(s));
-  double v = 0.0;
-  for (int64_t q = 0; q < nb; ++q) v += fe.part_h[q];
-  return v;
+  return *(const double*)fe.cg_h->p;
 }
 
 void axpby(hm_fe& fe, double a, const double* x, double b, double* y, hipStream_t s) {
@@ -171,35 +340,40 @@ void cavity_load(hm_fe& fe, const double* T, double* Q, hipStream_t s) {
 }
 
 // z = (M/dt + K)^-1 r by conjugate gradients with the diagonal as
-// preconditioner, from z = 0, to |r - A z| <= pc_rtol |r|
+// preconditioner, from z = 0, to |r - A z| <= pc_rtol |r|.  The scalars stay
+// on the device; the host launches blocks of CG_BLOCK iterations and reads
+// them back after each.
 void pc_solve(hm_fe& fe, const double* r, double* z, std::vector<DevBuf>& w, hipStream_t s) {
-  const int64_t n = fe.nn;
+  constexpr int CG_BLOCK = 8, CG_MAX = 2000;
+  const int64_t n = fe.nn, nb = (n + 255) / 256;
   double* res = w[0].get<double>();
   double* zz = w[1].get<double>();
   double* pp = w[2].get<double>();
   double* ap = w[3].get<double>();
-  HM_HIP(hipMemsetAsync(z, 0, n * 8, s));
-  HM_HIP(hipMemcpyAsync(res, r, n * 8, hipMemcpyDeviceToDevice, s));
-  const double rn0 = std::sqrt(fe_dot(fe, r, r, s));
-  if (rn0 == 0.0) return;
-  hipLaunchKernelGGL(k_fe_div, rows_grid(n), dim3(256), 0, s, res, fe.pcd.get<double>(), zz, n);
-  HM_HIP(hipMemcpyAsync(pp, zz, n * 8, hipMemcpyDeviceToDevice, s));
-  double rz = fe_dot(fe, res, zz, s);
-  for (int it = 0; it < 2000; ++it) {
-    hipLaunchKernelGGL(k_fe_spmv, rows_grid(n), dim3(256), 0, s, fe.rp.get<int32_t>(), fe.ci.get<int32_t>(),
-                       fe.pcv.get<double>(), pp, n, ap);
-    const double pap = fe_dot(fe, pp, ap, s);
-    HM_REQUIRE(pap > 0.0 && std::isfinite(pap), "fe: the preconditioner's matrix is not positive definite");
-    const double alpha = rz / pap;
-    axpby(fe, alpha, pp, 1.0, z, s);
-    axpby(fe, -alpha, ap, 1.0, res, s);
-    ++fe.pc_iterations;
-    const double rn = std::sqrt(fe_dot(fe, res, res, s));
-    if (rn <= fe.p.pc_rtol * rn0) return;
-    hipLaunchKernelGGL(k_fe_div, rows_grid(n), dim3(256), 0, s, res, fe.pcd.get<double>(), zz, n);
-    const double rz1 = fe_dot(fe, res, zz, s);
-    axpby(fe, 1.0, zz, rz1 / rz, pp, s);
-    rz = rz1;
+  double* cg = fe.cg.get<double>();
+  double* part = fe.part.get<double>();
+  const dim3 g((unsigned)nb);
+  const double rtol2 = fe.p.pc_rtol * fe.p.pc_rtol;
+  hipLaunchKernelGGL(k_cg_init, g, dim3(256), 0, s, r, fe.pcd.get<double>(), n, z, res, zz, pp, part);
+  hipLaunchKernelGGL(k_cg_fin_init, dim3(1), dim3(256), 0, s, part, nb, rtol2, cg);
+  HM_HIP(hipGetLastError());
+  for (int it = 0; it < CG_MAX; it += CG_BLOCK) {
+    for (int q = 0; q < CG_BLOCK; ++q) {
+      const int par = q & 1;  // CG_BLOCK is even: every block starts at parity 0
+      hipLaunchKernelGGL(k_cg_ap, g, dim3(256), 0, s, fe.rp.get<int32_t>(), fe.ci.get<int32_t>(),
+                         fe.pcv.get<double>(), pp, n, ap, cg, part);
+      hipLaunchKernelGGL(k_cg_fin_pap, dim3(1), dim3(256), 0, s, part, nb, cg);
+      hipLaunchKernelGGL(k_cg_step, g, dim3(256), 0, s, cg, par, pp, ap, fe.pcd.get<double>(), n, z, res, zz, part);
+      hipLaunchKernelGGL(k_cg_fin_step, dim3(1), dim3(256), 0, s, part, nb, par, cg);
+      hipLaunchKernelGGL(k_cg_dir, g, dim3(256), 0, s, cg, par, zz, n, pp);
+    }
+    HM_HIP(hipGetLastError());
+    const double* h = fetch_scalars(fe, s);
+    if (h[CG_DONE] != 0.0) {
+      fe.pc_iterations += (int)h[CG_ITS];
+      HM_REQUIRE(h[CG_ERR] == 0.0, "fe: the preconditioner's matrix is not positive definite");
+      return;
+    }
   }
   fail(HM_ENOTCONV, "fe: conjugate gradients for the preconditioner did not converge");
 }
@@ -300,8 +474,9 @@ hm_fe* fe_create(hm_ctx& ctx, const hm_matrix& F, int64_t nn, const double* vtx,
   fe->eta.alloc(nf * 8);
   fe->qf.alloc(nf * 8);
   fe->Jf.alloc(nf * 8);
-  fe->part.alloc(((nn + 255) / 256) * 8);
-  fe->part_h.resize((nn + 255) / 256);
+  fe->part.alloc(((nn + 255) / 256) * 2 * 8);
+  fe->cg.alloc((CG_N + 8) * 8);
+  fe->cg_h = std::make_unique<hm::PinnedLease>((CG_N + 8) * 8);
   fe->B = std::make_unique<Batch>(std::vector<const hm_matrix*>{&F}, 1, s);
   fe->B->power_in = true;
   HM_HIP(hipStreamSynchronize(s));
