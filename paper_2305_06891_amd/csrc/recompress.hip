@@ -28,6 +28,9 @@
 // Cholesky factors (the same Ru, Rv are used on both sides), so rounding in
 // the Gram matrices only perturbs the directions that are cut.
 #include <algorithm>
+#include <map>
+#include <memory>
+#include <mutex>
 #include <cmath>
 #include <climits>
 
@@ -643,6 +646,38 @@ __global__ __launch_bounds__(RC_T) void k_recompress_apply(const RcDev* __restri
   }
 }
 
+namespace {
+
+// One stream per device (default priority) for the bucket of the widest
+// blocks, which then runs beside the others: its blocks are few and long,
+// so alone they would leave most compute units idle.  Created on first use
+// and kept until the process ends; callers on several threads share it (a
+// call's work on it is ordered by that call's own events).
+hipStream_t side_stream(int device) {
+  static std::mutex mu;
+  static std::map<int, hipStream_t> streams;
+  std::lock_guard<std::mutex> lk(mu);
+  hipStream_t& st = streams[device];
+  if (!st) HM_HIP(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+  return st;
+}
+
+struct CallEvents {
+  hipEvent_t fork = nullptr, join = nullptr;
+  CallEvents() {
+    HM_HIP(hipEventCreateWithFlags(&fork, hipEventDisableTiming));
+    HM_HIP(hipEventCreateWithFlags(&join, hipEventDisableTiming));
+  }
+  ~CallEvents() {
+    if (fork) (void)hipEventDestroy(fork);
+    if (join) (void)hipEventDestroy(join);
+  }
+  CallEvents(const CallEvents&) = delete;
+  CallEvents& operator=(const CallEvents&) = delete;
+};
+
+}  // namespace
+
 void recompress_blocks(std::vector<RcDev>& blocks, const double* scratch, void* stage, bool stage_f64,
                        int* d_newrank, hipStream_t s) {
   if (blocks.empty()) return;
@@ -650,54 +685,83 @@ void recompress_blocks(std::vector<RcDev>& blocks, const double* scratch, void* 
   // global-workspace kernel above
   std::vector<RcDev> bucket[4];
   for (const RcDev& b : blocks) bucket[b.k <= 16 ? 0 : b.k <= 32 ? 1 : b.k <= 64 ? 2 : 3].push_back(b);
+  // the widest blocks on the side stream with a workspace of their own when
+  // there are others to run beside them (every block reads only its own
+  // crosses and writes only its own factors and rank)
+  const bool split = !bucket[3].empty() && (!bucket[0].empty() || !bucket[1].empty() || !bucket[2].empty());
   // chunks bounded by a workspace budget (a block needs 8 k^2 doubles): one
   // launch should hold enough blocks for several workgroups per compute
-  // unit, since each block's steps are latency-bound
-  int64_t need_all = 0;
-  for (const RcDev& b : blocks) need_all += recompress_work_doubles(b.k) * 8;
-  const int64_t budget = std::max<int64_t>(recompress_work_doubles(RC_KMAX) * 8,
-                                           std::min<int64_t>(need_all, (int64_t)2 << 30));
-  DevBuf work;
-  work.alloc((size_t)budget);
+  // unit, since each block's steps are latency-bound; at most 2 GB in all
+  int64_t need[2] = {0, 0};  // [0]: the buckets on s, [1]: the side bucket
+  for (int v = 0; v < 4; ++v)
+    for (const RcDev& b : bucket[v]) need[split && v == 3 ? 1 : 0] += recompress_work_doubles(b.k) * 8;
+  const int64_t cap = split ? (int64_t)1 << 30 : (int64_t)2 << 30;
+  int64_t budget[2];
+  DevBuf work[2];
+  for (int w = 0; w < (split ? 2 : 1); ++w) {
+    // the widest rank this workspace serves
+    const int kmax = (w == 1 || (!split && !bucket[3].empty())) ? RC_KMAX : 64;
+    budget[w] = std::max<int64_t>(recompress_work_doubles(kmax) * 8, std::min<int64_t>(need[w], cap));
+    work[w].alloc((size_t)budget[w]);
+  }
+  std::unique_ptr<CallEvents> ev;
+  hipStream_t side = nullptr;
   std::vector<DevBuf> descs;
-  for (int v = 0; v < 4; ++v) {
+  // the side bucket first: its launch is the longest
+  const int order[4] = {3, 0, 1, 2};
+  for (int oi = 0; oi < 4; ++oi) {
+    const int v = order[oi];
     std::vector<RcDev>& bl = bucket[v];
     if (bl.empty()) continue;
+    const int w = split && v == 3 ? 1 : 0;
     std::vector<size_t> starts;
-    int64_t used = budget;
+    int64_t used = budget[w];
     for (size_t q = 0; q < bl.size(); ++q) {
-      const int64_t need = recompress_work_doubles(bl[q].k) * 8;
-      if (used + need > budget) {
+      const int64_t nd = recompress_work_doubles(bl[q].k) * 8;
+      if (used + nd > budget[w]) {
         starts.push_back(q);
         used = 0;
       }
       bl[q].w_off = used / 8;
-      used += need;
+      used += nd;
     }
     starts.push_back(bl.size());
     descs.emplace_back();
     upload(descs.back(), bl, s);
+    hipStream_t st = s;
+    if (w == 1) {
+      int dev = 0;
+      HM_HIP(hipGetDevice(&dev));
+      side = side_stream(dev);
+      ev = std::make_unique<CallEvents>();
+      HM_HIP(hipEventRecord(ev->fork, s));  // after the crosses and the descriptors
+      HM_HIP(hipStreamWaitEvent(side, ev->fork, 0));
+      st = side;
+    }
+    double* wk = work[w].get<double>();
     for (size_t c = 0; c + 1 < starts.size(); ++c) {
       const unsigned cnt = (unsigned)(starts[c + 1] - starts[c]);
       const RcDev* bp = descs.back().get<RcDev>() + starts[c];
       if (v == 0)
-        hipLaunchKernelGGL(k_recompress_lds<16>, dim3(cnt), dim3(RC_T), 0, s, bp, scratch, work.get<double>(), d_newrank);
+        hipLaunchKernelGGL(k_recompress_lds<16>, dim3(cnt), dim3(RC_T), 0, st, bp, scratch, wk, d_newrank);
       else if (v == 1)
-        hipLaunchKernelGGL(k_recompress_lds<32>, dim3(cnt), dim3(RC_T), 0, s, bp, scratch, work.get<double>(), d_newrank);
+        hipLaunchKernelGGL(k_recompress_lds<32>, dim3(cnt), dim3(RC_T), 0, st, bp, scratch, wk, d_newrank);
       else if (v == 2)
-        hipLaunchKernelGGL(k_recompress_lds<64>, dim3(cnt), dim3(RC_T), 0, s, bp, scratch, work.get<double>(), d_newrank);
+        hipLaunchKernelGGL(k_recompress_lds<64>, dim3(cnt), dim3(RC_T), 0, st, bp, scratch, wk, d_newrank);
       else
-        hipLaunchKernelGGL(k_recompress, dim3(cnt), dim3(RC_T), 0, s, bp, scratch, work.get<double>(), d_newrank);
+        hipLaunchKernelGGL(k_recompress, dim3(cnt), dim3(RC_T), 0, st, bp, scratch, wk, d_newrank);
       if (stage_f64)
-        hipLaunchKernelGGL(k_recompress_apply<double>, dim3(cnt), dim3(RC_T), 0, s, bp, scratch, work.get<double>(),
+        hipLaunchKernelGGL(k_recompress_apply<double>, dim3(cnt), dim3(RC_T), 0, st, bp, scratch, wk,
                            (const int*)d_newrank, (double*)stage);
       else
-        hipLaunchKernelGGL(k_recompress_apply<float>, dim3(cnt), dim3(RC_T), 0, s, bp, scratch, work.get<double>(),
+        hipLaunchKernelGGL(k_recompress_apply<float>, dim3(cnt), dim3(RC_T), 0, st, bp, scratch, wk,
                            (const int*)d_newrank, (float*)stage);
       HM_HIP(hipGetLastError());
     }
+    if (w == 1) HM_HIP(hipEventRecord(ev->join, side));
   }
-  // the workspace and the descriptors are released when the work is done
+  if (ev) HM_HIP(hipStreamWaitEvent(s, ev->join, 0));
+  // the workspaces and the descriptors are released when the work is done
   HM_HIP(hipStreamSynchronize(s));
 }
 
