@@ -213,13 +213,13 @@ hm_status hm_matrix_tuning(const hm_matrix* M, int32_t* p1_rows, int32_t* p1_tas
  * product with M on another stream.  HM_EINVAL on bad values. */
 hm_status hm_matrix_set_tuning(hm_ctx* ctx, hm_matrix* M, int32_t p1_rows, int32_t p1_task_bytes);
 /* Launch shape of the product's second kernel for products of one or two
- * columns, chosen at assembly: waves per workgroup, 4 or 8, timed by the
+ * columns, chosen at assembly: waves per workgroup, 2, 4 or 8, timed by the
  * autotuner after the first kernel's split, or 0 when it is chosen by the
- * tile count (4 from 4,096 row tiles on); timing_us receives the measured
+ * tile count (4 from 4,096 row tiles on, else 8); timing_us receives the measured
  * microseconds of that kernel with the chosen shape, or 0 when nothing was
  * timed.  Any pointer may be NULL; HM_EINVAL for a NULL matrix. */
 hm_status hm_matrix_tuning_phase2(const hm_matrix* M, int32_t* p2_waves, double* timing_us);
-/* Sets that shape (0, 4 or 8).  The result does not change: the waves of a
+/* Sets that shape (0, 2, 4 or 8).  The result does not change: the waves of a
  * workgroup add their sums in a fixed order whatever their number.  A batch
  * of matrices uses a shape only when all its members hold the same one.
  * Synchronises ctx's stream; must not overlap a product with M on another

@@ -406,8 +406,8 @@ hm_status hm_matrix_set_tuning_phase2(hm_ctx* ctx, hm_matrix* M, int32_t p2_wave
   return guarded(ctx, [&] {
     HM_REQUIRE(M, "hm_matrix_set_tuning_phase2: NULL matrix");
     HM_REQUIRE(M->device == ctx->device, "hm_matrix_set_tuning_phase2: matrix lives on another device");
-    HM_REQUIRE(p2_waves == 0 || p2_waves == 4 || p2_waves == 8,
-               "hm_matrix_set_tuning_phase2: p2_waves must be 0, 4 or 8");
+    HM_REQUIRE(p2_waves == 0 || p2_waves == 2 || p2_waves == 4 || p2_waves == 8,
+               "hm_matrix_set_tuning_phase2: p2_waves must be 0, 2, 4 or 8");
     std::lock_guard<std::mutex> lk(M->mu);
     // compositions and captured graphs copied the old shape: drop them as
     // hm_matrix_set_tuning does

@@ -215,8 +215,8 @@ struct Plan {
   std::vector<P1Tau> taus;
   P1Params p1p;
   double p1_us = 0.0;  // measured time of the chosen split (0: not timed)
-  // waves per phase-2 workgroup for one or two right-hand sides: 4 or 8
-  // (the same bits either way), 0 = by tile count (4 from P2_MANY_TILES)
+  // waves per phase-2 workgroup for one or two right-hand sides: 2, 4 or 8
+  // (the same bits in every case), 0 = by tile count (4 from P2_MANY_TILES)
   int32_t p2_waves = 0;
   double p2_us = 0.0;  // measured phase-2 time of that choice (0: not timed)
   std::vector<P1Item> p1;
@@ -327,8 +327,8 @@ void plan_phase1(Plan& P, const P1Params& pp);
 void replan_phase1(hm_matrix& M, const P1Params& pp, hipStream_t s);
 // Times the candidate phase-1 splits on M (FP32 vectors unless the factors
 // are FP64; products of `width` columns, 1..16) and keeps the fastest; for
-// one or two columns then times phase 2 with 4 and 8 waves per workgroup
-// and keeps the faster.  Call before any composition of M exists.
+// one or two columns then times phase 2 with 2, 4 and 8 waves per
+// workgroup and keeps the fastest.  Call before any composition of M exists.
 void autotune_phase1(hm_matrix& M, hipStream_t s, int width = 1);
 // The same for several matrices multiplied together: one split for all,
 // timed on their batched product.

@@ -332,14 +332,15 @@ void autotune_phase1_joint(const std::vector<hm_matrix*>& mats, hipStream_t s, i
     M->plan.p2_waves = 0;
     M->plan.p2_us = 0.0;
   }
-  // phase 2 of one- and two-column products: 4 or 8 waves per workgroup
-  // (both give the same bits); the split above does not affect phase 2
+  // phase 2 of one- and two-column products: 2, 4 or 8 waves per
+  // workgroup (all give the same bits); the split above does not affect
+  // phase 2
   int best_w = 0;
   double best_p2 = 1e30;
   try {
     if (W <= 2) {
       auto comp = make_composition(cms, W, vb, s);
-      for (int w : {4, 8}) {
+      for (int w : {2, 4, 8}) {
         comp->p2_waves = w;
         double tot = 0;
         const int reps = 6;
@@ -1501,17 +1502,20 @@ void launch_typed(const CompView& C, int nrr, bool hi, const void* X, int64_t ld
                          sof + C.p1_tasks + C.p1_reds, slot_active, nrr, (const VT*)X, ldx,
                          (const VT*)C.xr, (VT*)Y, ldy, e);
     else {
-      // four waves per workgroup (tuned, else on many tiles), for one or
-      // two right-hand sides (wider products would spill the second set of
-      // sums)
-      bool four = false;
-      if constexpr (NR <= 2) four = C.p2_waves ? C.p2_waves == 4 : C.p2_tiles >= P2_MANY_TILES;
+      // two or four waves per workgroup (tuned, else four on many tiles),
+      // for one or two right-hand sides (wider products would spill the
+      // further sets of sums)
+      int wg = P2_WAVES;
+      if constexpr (NR <= 2) wg = C.p2_waves ? C.p2_waves : (C.p2_tiles >= P2_MANY_TILES ? 4 : P2_WAVES);
       if constexpr (NR <= 2) {
-        if (four)
+        if (wg == 2)
+          hipLaunchKernelGGL((k_phase2<DT, LT, VT, NR, 2>), dim3(C.p2_tiles), dim3(64 * 2), 0, s, slots,
+                             sof + C.p1_tasks + C.p1_reds, slot_active, nrr, (const VT*)X, ldx, (VT*)Y, ldy, e);
+        else if (wg == 4)
           hipLaunchKernelGGL((k_phase2<DT, LT, VT, NR, 4>), dim3(C.p2_tiles), dim3(64 * 4), 0, s, slots,
                              sof + C.p1_tasks + C.p1_reds, slot_active, nrr, (const VT*)X, ldx, (VT*)Y, ldy, e);
       }
-      if (!four)
+      if (wg == P2_WAVES)
         hipLaunchKernelGGL((k_phase2<DT, LT, VT, NR, P2_WAVES>), dim3(C.p2_tiles), dim3(64 * P2_WAVES), 0, s,
                            slots, sof + C.p1_tasks + C.p1_reds, slot_active, nrr, (const VT*)X, ldx, (VT*)Y, ldy, e);
     }

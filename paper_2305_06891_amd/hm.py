@@ -318,7 +318,7 @@ class HMatrix:
 
     def set_tuning_phase2(self, ctx, p2_waves):
         """Sets the second kernel's waves per workgroup (0: by tile count,
-        4 or 8) for products of one or two columns."""
+        2, 4 or 8) for products of one or two columns."""
         _check(lib.hm_matrix_set_tuning_phase2(ctx._h, self._h, int(p2_waves)))
 
     def close(self):
