@@ -25,7 +25,13 @@ void SysSet::build(const Composition& C, const std::vector<std::vector<int>>& co
       SysDev d{C.xoff[q], (int32_t)C.mats[q]->n, col, (int32_t)q, (int32_t)chunks.size()};
       const int32_t sid = (int32_t)sys.size();
       sys.push_back(d);
-      const int32_t nch = (int32_t)((d.n + GS_ROWS - 1) / GS_ROWS);
+      // at most GS_ROWS rows a chunk, and at least GS_MIN_CHUNKS chunks of
+      // at least 256 rows where the system has the rows: a small system's
+      // vector kernels then run on more than a handful of workgroups (the
+      // split depends on the system alone, so a batch member reduces in the
+      // same order as the system solved alone)
+      const int32_t nch = std::max<int32_t>((int32_t)((d.n + GS_ROWS - 1) / GS_ROWS),
+                                            std::min<int32_t>(GS_MIN_CHUNKS, (int32_t)((d.n + 255) / 256)));
       for (int32_t c = 0; c < nch; ++c) {
         const int32_t r0 = (int32_t)((int64_t)d.n * c / nch);
         const int32_t r1 = (int32_t)((int64_t)d.n * (c + 1) / nch);
