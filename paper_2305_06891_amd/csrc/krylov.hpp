@@ -12,7 +12,7 @@ constexpr int MAXM = 64;       // largest restart length
 constexpr int GS_T = 256;      // threads per reduction chunk
 constexpr int GS_RPT = 8;      // rows per thread
 constexpr int GS_ROWS = GS_T * GS_RPT;
-constexpr int GS_MIN_CHUNKS = 32;  // chunks per system, where it has 256 rows a chunk
+constexpr int GS_MIN_CHUNKS = 64;  // chunks per system, where it has 256 rows a chunk
 
 // One independent linear system: rows [row0, row0+n) of column col of the
 // combined N x width vector block, belonging to slot `slot`.
