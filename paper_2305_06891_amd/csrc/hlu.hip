@@ -169,6 +169,40 @@ __global__ void k_dtrsm(const double* __restrict__ T, int m, int64_t ldt, double
   }
 }
 
+// The same solves for modes 0 and 1 with a leaf of at most 64 rows and few
+// right-hand sides: one wave per right-hand side, the block and the column
+// in LDS, lane i owning row i; the solve goes column by column of T (the
+// row-by-row loop above leaves one thread walking the whole block).  Mode
+// 0 subtracts the terms of each row in the same order as above.
+constexpr int TRSM_LDS_M = 64;
+__global__ __launch_bounds__(64) void k_dtrsm_lds(const double* __restrict__ T, int m, int64_t ldt,
+                                                  double* __restrict__ X, int64_t ldx, int mode) {
+  __shared__ double Ts[TRSM_LDS_M * (TRSM_LDS_M + 1)];
+  __shared__ double xs[TRSM_LDS_M];
+  const int i = threadIdx.x;
+  double* x = X + (int64_t)blockIdx.x * ldx;
+  for (int e = i; e < m * m; e += 64) {
+    const int p = e / m, r = e - p * m;
+    Ts[p * (TRSM_LDS_M + 1) + r] = T[(int64_t)p * ldt + r];
+  }
+  xs[i] = i < m ? x[i] : 0.0;
+  __syncthreads();
+  if (mode == 0) {
+    for (int p = 0; p < m - 1; ++p) {
+      if (i > p && i < m) xs[i] -= Ts[p * (TRSM_LDS_M + 1) + i] * xs[p];
+      __syncthreads();
+    }
+  } else {
+    for (int p = m - 1; p >= 0; --p) {
+      if (i == p) xs[p] /= Ts[p * (TRSM_LDS_M + 1) + p];
+      __syncthreads();
+      if (i < p) xs[i] -= Ts[p * (TRSM_LDS_M + 1) + i] * xs[p];
+      __syncthreads();
+    }
+  }
+  if (i < m) x[i] = xs[i];
+}
+
 // One leaf of a flattened subtree for the substitutions: rows [ro, ro+m)
 // and columns [co, co+n) relative to the subtree; dense D (ld m) or low rank
 // U (m x k), V (n x k); toff: first row of its k x c intermediate V^T x in
@@ -345,8 +379,12 @@ struct Hlu {
   void trsm(const Node& T, const MatV& X, int mode) {
     const int64_t c = mode == 3 ? X.rows : X.cols;
     if (c == 0) return;
-    hipLaunchKernelGGL(k_dtrsm, dim3(blocks_for(c)), dim3(256), 0, s, (const double*)T.D.buf.get<double>(), T.m(),
-                       (int64_t)T.m(), X.p, X.ld, c, mode);
+    if (mode <= 1 && T.m() <= TRSM_LDS_M && c <= 64)
+      hipLaunchKernelGGL(k_dtrsm_lds, dim3((unsigned)c), dim3(64), 0, s, (const double*)T.D.buf.get<double>(),
+                         (int)T.m(), (int64_t)T.m(), X.p, X.ld, mode);
+    else
+      hipLaunchKernelGGL(k_dtrsm, dim3(blocks_for(c)), dim3(256), 0, s, (const double*)T.D.buf.get<double>(), T.m(),
+                         (int64_t)T.m(), X.p, X.ld, c, mode);
   }
 
   // ---- products with dense column blocks: Y += alpha op(b) X
