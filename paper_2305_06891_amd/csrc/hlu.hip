@@ -25,6 +25,8 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <memory>
+#include <mutex>
 #include <vector>
 
 #include "dev_common.hpp"
@@ -317,6 +319,24 @@ struct hm_hlu {
     int64_t tsize = 0;
   };
   std::vector<Flat> flat;  // indexed by node
+  // The substitutions for a given number of right-hand sides, captured as
+  // a graph at the first solve with that number (persistent work vector
+  // and per-node intermediates, so that the graph's pointers stay valid);
+  // solves on these factors are serialised by solve_mu.
+  struct SolveGraph {
+    int nrhs = 0;
+    hm::DevBuf W;
+    std::vector<hm::DevBuf> t;  // indexed by node
+    hipGraphExec_t exec = nullptr;
+  };
+  std::mutex solve_mu;
+  std::vector<std::unique_ptr<SolveGraph>> graphs;
+  hipStream_t cap = nullptr;  // private stream used only to capture
+  ~hm_hlu() {
+    for (auto& g : graphs)
+      if (g && g->exec) (void)hipGraphExecDestroy(g->exec);
+    if (cap) (void)hipStreamDestroy(cap);
+  }
 };
 
 namespace hm {
@@ -463,17 +483,26 @@ struct Hlu {
     build_flat(A.ch[1][1]);
   }
   // Y += alpha b X through the flattened leaves of b
+  // per-node intermediates of the substitutions (tbuf[bi] holds at least
+  // tsize x c doubles), or NULL: allocated per call
+  std::vector<DevBuf>* tbuf = nullptr;
   void mulvec_flat(int bi, const MatV& X, const MatV& Y, double alpha) {
     const hm_hlu::Flat& F = H.flat[bi];
     if (F.n == 0 || X.cols == 0) return;
     const int c = (int)X.cols;
-    DevBuf t((size_t)std::max<int64_t>(1, F.tsize * c) * 8);
+    DevBuf own;
+    double* t;
+    if (tbuf) {
+      t = (*tbuf)[bi].get<double>();
+    } else {
+      own.alloc((size_t)std::max<int64_t>(1, F.tsize * c) * 8);
+      t = own.get<double>();
+    }
     const FlatLeaf* lv = F.leaves.get<FlatLeaf>();
     if (F.nlr > 0)
-      hipLaunchKernelGGL(k_flat_t, dim3((unsigned)F.nlr), dim3(256), 0, s, lv, (const double*)X.p, X.ld, c,
-                         t.get<double>());
+      hipLaunchKernelGGL(k_flat_t, dim3((unsigned)F.nlr), dim3(256), 0, s, lv, (const double*)X.p, X.ld, c, t);
     hipLaunchKernelGGL(k_flat_apply, dim3((unsigned)F.n), dim3(256), 0, s, lv, (const double*)X.p, X.ld, c,
-                       (const double*)t.get<double>(), alpha, Y.p, Y.ld);
+                       (const double*)t, alpha, Y.p, Y.ld);
   }
   void solve_lower_flat(int li, const MatV& X) {
     Node& L = nd(li);
@@ -936,19 +965,59 @@ hm_hlu* hlu_factor(hm_ctx& ctx, const hm_tree& t, const double* eps, const hm_as
   return H.release();
 }
 
-void hlu_solve(hm_ctx& ctx, const hm_hlu& H, int nrhs, const double* B, int64_t ldb, double* X, int64_t ldx) {
+void hlu_solve(hm_ctx& ctx, const hm_hlu& Hc, int nrhs, const double* B, int64_t ldb, double* X, int64_t ldx) {
   hipStream_t s = ctx.stream;
+  // the factors are not changed; the graph cache and its buffers are
+  hm_hlu& H = const_cast<hm_hlu&>(Hc);
+  std::lock_guard<std::mutex> lk(H.solve_mu);
   const int64_t n = H.n;
-  MatO W;
-  W.rows = n;
-  W.cols = nrhs;
-  W.buf.alloc((size_t)n * nrhs * 8);
+  hm_hlu::SolveGraph* g = nullptr;
+  for (auto& q : H.graphs)
+    if (q->nrhs == nrhs) g = q.get();
+  bool fresh = false;
+  if (!g) {
+    H.graphs.push_back(std::make_unique<hm_hlu::SolveGraph>());
+    g = H.graphs.back().get();
+    g->nrhs = nrhs;
+    g->W.alloc((size_t)n * nrhs * 8);
+    g->t.resize(H.flat.size());
+    for (size_t b = 0; b < H.flat.size(); ++b)
+      if (H.flat[b].n > 0) g->t[b].alloc((size_t)std::max<int64_t>(1, H.flat[b].tsize * nrhs) * 8);
+    fresh = true;
+  }
+  MatV Wv{g->W.get<double>(), n, nrhs, n};
+  auto substitutions = [&](hipStream_t st) {
+    Hlu f{H, st, H.tol};
+    f.tbuf = &g->t;
+    f.solve_lower_flat(H.root, Wv);
+    f.solve_upper_flat(H.root, Wv);
+  };
+  if (fresh) {
+    // capture once on the private stream (ordered after everything that
+    // built the buffers); a failed capture leaves direct launches
+    HM_HIP(hipStreamSynchronize(s));
+    if (!H.cap && hipStreamCreateWithFlags(&H.cap, hipStreamNonBlocking) != hipSuccess) H.cap = nullptr;
+    if (H.cap && hipStreamBeginCapture(H.cap, hipStreamCaptureModeThreadLocal) == hipSuccess) {
+      bool ok = true;
+      try {
+        substitutions(H.cap);
+      } catch (const Error&) {
+        ok = false;
+      }
+      hipGraph_t gr = nullptr;
+      if (hipStreamEndCapture(H.cap, &gr) != hipSuccess || !gr) ok = false;
+      if (ok && hipGraphInstantiate(&g->exec, gr, nullptr, nullptr, 0) != hipSuccess) g->exec = nullptr;
+      if (gr) (void)hipGraphDestroy(gr);
+      (void)hipGetLastError();
+    }
+  }
   dim3 grid(blocks_for(n), (unsigned)nrhs);
-  hipLaunchKernelGGL(k_hlu_gather<double>, grid, dim3(256), 0, s, H.d_perm.get<int32_t>(), B, ldb, W.buf.get<double>(), n);
-  Hlu f{const_cast<hm_hlu&>(H), s, H.tol};
-  f.solve_lower_flat(H.root, W.v());
-  f.solve_upper_flat(H.root, W.v());
-  hipLaunchKernelGGL(k_hlu_scatter, grid, dim3(256), 0, s, H.d_perm.get<int32_t>(), (const double*)W.buf.get<double>(),
+  hipLaunchKernelGGL(k_hlu_gather<double>, grid, dim3(256), 0, s, H.d_perm.get<int32_t>(), B, ldb, g->W.get<double>(), n);
+  if (g->exec)
+    HM_HIP(hipGraphLaunch(g->exec, s));
+  else
+    substitutions(s);
+  hipLaunchKernelGGL(k_hlu_scatter, grid, dim3(256), 0, s, H.d_perm.get<int32_t>(), (const double*)g->W.get<double>(),
                      X, ldx, n);
   HM_HIP(hipGetLastError());
   HM_HIP(hipStreamSynchronize(s));
