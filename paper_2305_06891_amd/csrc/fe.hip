@@ -204,7 +204,7 @@ __global__ __launch_bounds__(256) void k_cg_fin_pap(const double* __restrict__ p
   double t;
   sum_partials(part, nb, 1, &t);
   if (threadIdx.x == 0) {
-    if (t > 0.0 && t <= 1.7e308) {
+    if (t > 0.0 && isfinite(t)) {
       cg[CG_PAP] = t;
     } else {  // not positive definite (or not finite): stop with an error
       cg[CG_ERR] = 1.0;
