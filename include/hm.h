@@ -391,8 +391,9 @@ hm_status hm_hlu_factor(hm_ctx* ctx, const hm_tree* tree, const double* eps, con
  * FP64 n x nrhs, caller order, leading dimensions ldb, ldx >= n; X may be
  * B).  No further approximation beyond the factors.  The first solve with
  * a given nrhs records the substitutions as a graph kept with the factors
- * (with its own device work buffers); solves on the same factors from
- * several threads are serialised.  Synchronises ctx's stream. */
+ * (with its own device work buffers; the four most recently used counts
+ * are kept); solves on the same factors from several threads are
+ * serialised.  Synchronises ctx's stream. */
 hm_status hm_hlu_solve(hm_ctx* ctx, const hm_hlu* lu, int32_t nrhs, const double* B, int64_t ldb, double* X,
                        int64_t ldx);
 /* Device bytes and stored entries of the factors, their largest rank and the

@@ -322,19 +322,23 @@ struct hm_hlu {
   // The substitutions for a given number of right-hand sides, captured as
   // a graph at the first solve with that number (persistent work vector
   // and per-node intermediates, so that the graph's pointers stay valid);
-  // solves on these factors are serialised by solve_mu.
+  // solves on these factors are serialised by solve_mu.  At most
+  // MAX_GRAPHS counts are kept, the most recently used first.
   struct SolveGraph {
     int nrhs = 0;
     hm::DevBuf W;
     std::vector<hm::DevBuf> t;  // indexed by node
     hipGraphExec_t exec = nullptr;
+    ~SolveGraph() {
+      if (exec) (void)hipGraphExecDestroy(exec);
+    }
   };
+  static constexpr size_t MAX_GRAPHS = 4;
   std::mutex solve_mu;
   std::vector<std::unique_ptr<SolveGraph>> graphs;
   hipStream_t cap = nullptr;  // private stream used only to capture
   ~hm_hlu() {
-    for (auto& g : graphs)
-      if (g && g->exec) (void)hipGraphExecDestroy(g->exec);
+    graphs.clear();
     if (cap) (void)hipStreamDestroy(cap);
   }
 };
@@ -972,17 +976,27 @@ void hlu_solve(hm_ctx& ctx, const hm_hlu& Hc, int nrhs, const double* B, int64_t
   std::lock_guard<std::mutex> lk(H.solve_mu);
   const int64_t n = H.n;
   hm_hlu::SolveGraph* g = nullptr;
-  for (auto& q : H.graphs)
-    if (q->nrhs == nrhs) g = q.get();
+  for (size_t q = 0; q < H.graphs.size() && !g; ++q)
+    if (H.graphs[q]->nrhs == nrhs) {
+      // to the front: the most recently used count
+      std::rotate(H.graphs.begin(), H.graphs.begin() + q, H.graphs.begin() + q + 1);
+      g = H.graphs.front().get();
+    }
   bool fresh = false;
   if (!g) {
-    H.graphs.push_back(std::make_unique<hm_hlu::SolveGraph>());
-    g = H.graphs.back().get();
-    g->nrhs = nrhs;
-    g->W.alloc((size_t)n * nrhs * 8);
-    g->t.resize(H.flat.size());
+    // built whole before it joins the list (an allocation that fails
+    // leaves the list as it was); the least recently used count gives way
+    // (every solve that used its buffers ended with a synchronisation
+    // under solve_mu)
+    auto ng = std::make_unique<hm_hlu::SolveGraph>();
+    ng->nrhs = nrhs;
+    ng->W.alloc((size_t)n * nrhs * 8);
+    ng->t.resize(H.flat.size());
     for (size_t b = 0; b < H.flat.size(); ++b)
-      if (H.flat[b].n > 0) g->t[b].alloc((size_t)std::max<int64_t>(1, H.flat[b].tsize * nrhs) * 8);
+      if (H.flat[b].n > 0) ng->t[b].alloc((size_t)std::max<int64_t>(1, H.flat[b].tsize * nrhs) * 8);
+    if (H.graphs.size() >= hm_hlu::MAX_GRAPHS) H.graphs.pop_back();
+    H.graphs.insert(H.graphs.begin(), std::move(ng));
+    g = H.graphs.front().get();
     fresh = true;
   }
   MatV Wv{g->W.get<double>(), n, nrhs, n};

@@ -10,6 +10,9 @@
 * Radiosity of a 5,000-facet cylinder (leaf 64, eta 1.5, eps_rel 1e-6):
   J = C^-1 (sigma eps T^4) against the dense oracle, e(J) <= 1e-5.
 * The 13-sphere spiral with fully pivoted ACA: the same bound.
+* Solves cycling through more right-hand-side counts than the factors keep
+  substitution graphs for: dense-exact to 10 eps_rel, repeats of a count
+  equal to its first solve to 1e-13.
 """
 import numpy as np
 import pytest
@@ -116,3 +119,35 @@ def test_block_lu_spiral_full_pivoting(hm, ctx):
     e = rel(J, Jo)
     log("factor %.2f s, e(J) %.2e" % (LU.stats()["factor_seconds"], e))
     assert e <= 1e-5
+
+
+def test_block_lu_solves_with_many_rhs_counts(hm, ctx):
+    """The substitutions are kept as graphs for the four most recently used
+    right-hand-side counts: cycling through more counts than that (each
+    evicting the least recently used one, then coming back to evicted ones)
+    gives every solve the dense solution to 10 eps_rel and, for a count seen
+    before, the same columns as its first solve to 1e-13 (the level updates
+    add in FP64 with atomics, so not always bit for bit)."""
+    import torch
+    v, f, eps = _ellipsoid()
+    n = f.shape[0]
+    tol = 1e-6
+    log("case: block LU, ellipsoid %d facets, solves cycling through 7 right-hand-side counts" % n)
+    LU = _setup(hm, ctx, v, f, eps, 32, tol)
+    c, nr, a = geometry.facets_from_triangles(v, f)
+    C = radiosity.reflection_matrix(viewfactor.view_factor_matrix(c, nr, a), eps)
+    B = np.random.default_rng(5).uniform(0.5, 1.5, (n, 16))
+    Xe = np.linalg.solve(C, B)
+    first = {}
+    worst_dense, worst_repeat = 0.0, 0.0
+    for k in [1, 2, 3, 5, 16, 2, 7, 1, 3, 16, 5, 1]:
+        X = to_np(LU.solve(torch.as_tensor(np.asfortranarray(B[:, :k]), device="cuda"))).reshape(n, k)
+        torch.cuda.synchronize()
+        worst_dense = max(worst_dense, rel(X, Xe[:, :k]))
+        if k in first:
+            worst_repeat = max(worst_repeat, rel(X, first[k]))
+        else:
+            first[k] = X
+    log("worst e(X) vs dense %.2e, worst repeat vs first solve %.2e" % (worst_dense, worst_repeat))
+    assert worst_dense <= 10 * tol
+    assert worst_repeat <= 1e-13
