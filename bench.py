@@ -23,13 +23,17 @@ Workload ``hlu``: the hierarchical block LU (Sec. 5.1-5.2) of four
 geometries up to a 4,992-facet cylinder, factor and solve times beside a
 GMRES solve of the same system.
 
-Default (``--workload all``): the ``c3`` record is the headline; the ``c4``
-transient, ``c5`` serving, ``fe`` coupling and ``hlu`` records ride along on
-the same JSON line (keys ``c4_transient``, ``c5_serving``, ``fe_coupling``
-and ``block_lu``), each with its own value, roofline or latency figures and
-oracle baseline.
+Workload ``open``: the 13-sphere spiral at 37,440 facets as an open cavity
+(isolated facets, fully pivoted ACA, the ambient exchange of eq. (35)) with
+the headline's solver.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload all|c3|c2|c4|c5|fe|hlu]
+Default (``--workload all``): the ``c3`` record is the headline; the ``c4``
+transient, ``c5`` serving, ``fe`` coupling, ``hlu`` and ``open`` records ride
+along on the same JSON line (keys ``c4_transient``, ``c5_serving``,
+``fe_coupling``, ``block_lu`` and ``open_spiral``), each with its own value,
+roofline or latency figures and oracle baseline.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload all|c3|c2|c4|c5|fe|hlu|open]
 """
 import argparse
 import json
@@ -890,12 +894,84 @@ def run_c2(args):
     return out
 
 
+def run_open(args):
+    """The 13-sphere spiral of Sec. 6 at its finest mesh level (frequency-12
+    spheres, 37,440 facets) as an open, non-convex cavity: isolated facets
+    (zero rows of F), fully pivoted ACA at 1e-6 (partial pivoting misses
+    parts of this geometry's blocks), recompressed crosses, BF16 factors
+    with an FP32 copy, and the ambient exchange of eq. (35) in the flux.
+    One step is one radiosity solve (J and q, one right-hand side) with the
+    headline's solver: FP32 GMRES on the BF16 factors inside FP64
+    refinement to a residual of 1e-7.  Parity of the same settings against
+    the dense oracle is tested on the 9,360-facet member of the family."""
+    import torch
+    from paper_2305_06891_amd import hm
+    from workloads import configs
+
+    dev = torch.device("cuda:0")
+    cav = configs.fibonacci_spiral(nu=12)
+    n = cav.n
+    T_amb = cav.extra["T_amb"]
+    ctx = hm.Context(0)
+    t0 = time.perf_counter()
+    c, nrm, area = hm.hm_facets_from_triangles(cav.v, cav.tri, orient=1)
+    tree = hm.hm_build_cluster_tree(ctx, c, nrm, area, 64, 1.5)
+    t_tree = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    M = hm.hm_assemble_hmatrix(ctx, tree, 1e-6, 256, hm.HM_BF16, hm.HM_F32, keep_f32_copy=1, autotune=1,
+                               recompress=1, aca_pivot=1, lowrank_rounding=1)
+    torch.cuda.synchronize()
+    t_asm = time.perf_counter() - t0
+    st = M.stats()
+    log("open spiral: %d facets, matrix %s, tree %.2fs assembly %.2fs" % (n, st, t_tree, t_asm))
+    eps = torch.as_tensor(cav.eps, device=dev)
+    T = torch.as_tensor(cav.T[:, 0], device=dev)
+    p = hm.solve_params(rtol=RTOL, restart=30, max_iter=400, mixed_precision=1, ir_inner_rtol=IR_INNER, want_q=1,
+                        open_cavity=1, ambient_temperature=T_amb)
+    J = torch.empty_like(T)
+    q = torch.empty_like(T)
+    for _ in range(args.warmup):
+        hm.hm_solve_radiosity(ctx, M, eps, T, hm.SIGMA, p, J, q)
+    torch.cuda.synchronize()
+    times = []
+    info = None
+    for _ in range(args.steps):
+        t0 = time.perf_counter()
+        _, _, info = hm.hm_solve_radiosity(ctx, M, eps, T, hm.SIGMA, p, J, q)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+    total = sum(times)
+    ms = 1e3 * total / len(times)
+    log("open spiral solve: %.3f ms/step (median %.3f), outer %d inner %d, rel residual %.2e" %
+        (ms, 1e3 * float(np.median(times)), info["outer_iters"], info["iters"], info["rel_residual"]))
+    prof = hm.hm_hmatvec_profile(ctx, M, 1, hm.HM_F32, reps=20, flush_bytes=512 << 20)
+    out = base_record(args, len(times) / total, ms, "f32+f64", {
+        "workload": "open_spiral_%d" % n, "facets": n, "spheres": 13, "leaf": 64, "eta": 1.5, "aca_tol": 1e-6,
+        "aca": "full pivoting", "recompression": "truncated svd at aca_tol",
+        "storage": "bf16 low-rank factors (dithered rounding), fp32 near field, fp32 factor copy for the residual",
+        "solver": "gmres(30) fp32 inside fp64 iterative refinement", "rtol": RTOL, "ir_inner_rtol": IR_INNER,
+        "open_cavity": True, "ambient_temperature_K": T_amb, "nrhs": 1})
+    out["metric"] = "open-cavity radiosity solves/s (13-sphere spiral, ambient exchange)"
+    out["timing"] = {"reps": len(times), "median_ms": 1e3 * float(np.median(times)),
+                     "p90_ms": 1e3 * float(np.percentile(times, 90))}
+    out["roofline"] = roofline(prof)
+    out["matrix"] = {k: st[k] for k in ("bytes_device", "entries_dense", "entries_lowrank", "max_rank",
+                                        "n_dense_blocks", "n_lowrank_blocks", "n_fallback")}
+    out["assembly_s"] = {"trees": t_tree, "full_pivot_aca_and_recompression": t_asm}
+    out["solve"] = {"outer_iters": info["outer_iters"], "inner_iters": info["iters"], "matvecs": info["matvecs"],
+                    "rel_residual": info["rel_residual"]}
+    if not args.no_cpu_baseline:
+        sample = configs.fibonacci_spiral(nu=5)
+        out["cpu_baseline"] = cpu_baseline_dense([sample], [n])
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50, help="timed batched solves of the 64-cavity workload")
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="all", choices=["all", "c3", "c2", "c4", "c5", "fe", "hlu"],
+    ap.add_argument("--workload", default="all", choices=["all", "c3", "c2", "c4", "c5", "fe", "hlu", "open"],
                     help="all: the 64-cavity batch (the headline record) with the transient and serving "
                          "records attached to the same line")
     ap.add_argument("--recompress", type=int, default=1, choices=[0, 1],
@@ -926,9 +1002,11 @@ def main():
         out["fe_coupling"] = run_fe(args)
         gc.collect()
         out["block_lu"] = run_hlu(args)
+        gc.collect()
+        out["open_spiral"] = run_open(args)
     else:
         out = {"c3": run_c3, "c2": run_c2, "c4": run_c4, "c5": run_c5, "fe": run_fe,
-               "hlu": run_hlu}[args.workload](args)
+               "hlu": run_hlu, "open": run_open}[args.workload](args)
     print(json.dumps(out), flush=True)
 
 

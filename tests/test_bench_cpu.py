@@ -21,7 +21,7 @@ def _tree():
 def test_every_name_bench_calls_is_defined():
     tree = _tree()
     defined = {n.name for n in tree.body if isinstance(n, ast.FunctionDef)}
-    for want in ("run_c2", "run_c3", "run_c4", "run_c5", "run_fe", "run_hlu", "run_kernels_only", "cpu_baseline_dense",
+    for want in ("run_c2", "run_c3", "run_c4", "run_c5", "run_fe", "run_hlu", "run_open", "run_kernels_only", "cpu_baseline_dense",
                  "cpu_baseline_transient", "roofline", "measured_traffic", "copy_ceiling_gbps", "base_record"):
         assert want in defined, want
     # every bare-name call to a lower-case module-level name resolves
