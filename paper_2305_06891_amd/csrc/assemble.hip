@@ -47,6 +47,8 @@ struct AcaDev {
 
 constexpr int ACA_T = 256;        // threads per workgroup of k_aca
 constexpr int ACA_T_HUGE = 512;   // ... for blocks with m + n >= ACA_HUGE
+constexpr int ACA_T_FULL_BIG = 1024;           // fully pivoted ACA: threads for blocks of
+constexpr int64_t ACA_FULL_BIG = 1 << 20;      // ... at least this many entries
 constexpr int ACA_HUGE = 4096;
 constexpr int ACA_KMAX = 1024;
 
@@ -385,6 +387,7 @@ __global__ __launch_bounds__(256) void k_aca_wave(const AcaDev* __restrict__ blo
 // |R|_F^2.  The stop test is eq. (31) on the exact residual:
 // |R|_F <= tol |X|_F (or a zero residual, or the rank cap).
 #pragma clang fp contract(off)
+constexpr int FULL_U = 8;  // residual entries per thread in flight
 template <int T>
 __global__ __launch_bounds__(T) void k_aca_full(const AcaDev* __restrict__ blocks, Geo g,
                                                 double* __restrict__ scratch, int* __restrict__ rank,
@@ -399,16 +402,26 @@ __global__ __launch_bounds__(T) void k_aca_full(const AcaDev* __restrict__ block
   double* U = scratch + b.u_off;
   double* V = scratch + b.v_off;
   const int tid = threadIdx.x;
+  // a thread visits entries e = tid, tid + T, ... (i = e mod m, j = e / m):
+  // its row and column advance by T mod m and T / m per visit
+  const int di = T % m, dj = T / m;
+  const int i0 = tid % m, j0 = tid / m;
   ArgMax am{-1.0, 0.0, 0x7fffffff};
   double s2 = 0.0;
+  int i = i0, j = j0;
   for (int64_t e = tid; e < mn; e += T) {
-    const int i = (int)(e % m), j = (int)(e / m);
     const double x = view_factor(g, b.rb + i, b.cb + j);
     R[e] = x;
     s2 += x * x;
     const double a = fabs(x);
     const int key = i * n + j;
     if (a > am.mag || (a == am.mag && key < am.idx)) am = ArgMax{a, x, key};
+    i += di;
+    j += dj;
+    if (i >= m) {
+      i -= m;
+      ++j;
+    }
   }
   {
     double t[1] = {s2};
@@ -427,19 +440,43 @@ __global__ __launch_bounds__(T) void k_aca_full(const AcaDev* __restrict__ block
     const double piv = am.val;
     double* uk = U + (int64_t)k * m;
     double* vk = V + (int64_t)k * n;
-    for (int i = tid; i < m; i += T) uk[i] = R[(int64_t)jp * m + i];
-    for (int j = tid; j < n; j += T) vk[j] = R[(int64_t)j * m + ip] / piv;
+    for (int r = tid; r < m; r += T) uk[r] = R[(int64_t)jp * m + r];
+    for (int c = tid; c < n; c += T) vk[c] = R[(int64_t)c * m + ip] / piv;
     __syncthreads();
     am = ArgMax{-1.0, 0.0, 0x7fffffff};
     double r2 = 0.0;
-    for (int64_t e = tid; e < mn; e += T) {
-      const int i = (int)(e % m), j = (int)(e / m);
-      const double r = R[e] - uk[i] * vk[j];
-      R[e] = r;
-      r2 += r * r;
-      const double a = fabs(r);
-      const int key = i * n + j;
-      if (a > am.mag || (a == am.mag && key < am.idx)) am = ArgMax{a, r, key};
+    i = i0;
+    j = j0;
+    // FULL_U of the thread's entries at a time: all their loads go out
+    // before the first is used (one workgroup streams a block of up to
+    // millions of entries per cross); they are then taken in the same
+    // order as one at a time, so sums and pivots do not change
+    for (int64_t e = tid; e < mn; e += (int64_t)FULL_U * T) {
+      double rv[FULL_U], uv[FULL_U], vv[FULL_U];
+      int key[FULL_U];
+#pragma unroll
+      for (int u = 0; u < FULL_U; ++u) {
+        const bool in = e + (int64_t)u * T < mn;  // then i < m and j < n
+        key[u] = in ? i * n + j : 0;
+        rv[u] = in ? R[e + (int64_t)u * T] : 0.0;
+        uv[u] = in ? uk[i] : 0.0;
+        vv[u] = in ? vk[j] : 0.0;
+        i += di;
+        j += dj;
+        if (i >= m) {
+          i -= m;
+          ++j;
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < FULL_U; ++u) {
+        if (e + (int64_t)u * T >= mn) break;
+        const double r = rv[u] - uv[u] * vv[u];
+        R[e + (int64_t)u * T] = r;
+        r2 += r * r;
+        const double a = fabs(r);
+        if (a > am.mag || (a == am.mag && key[u] < am.idx)) am = ArgMax{a, r, key[u]};
+      }
     }
     {
       double t[1] = {r2};
@@ -797,7 +834,7 @@ std::vector<hm_matrix*> assemble_batch(hm_ctx& ctx, const std::vector<const hm_t
   const int64_t budget = std::max<int64_t>(256ll << 20, std::min<int64_t>(8ll << 30, (int64_t)free_b / 4));
   std::vector<DevBuf> stages;
   std::vector<size_t> stage_last;  // last job with factors in each stage buffer
-  DevBuf scratch, flags, d_blk, d_blk_small, d_blk_huge, d_blk_full, d_rank, d_status, d_cd;
+  DevBuf scratch, flags, d_blk, d_blk_small, d_blk_huge, d_blk_full, d_blk_full_big, d_rank, d_status, d_cd;
   size_t jpos = 0, bpos = 0, next_finish = 0;
   auto finish_ready = [&]() {
     while (next_finish < nj && jobs[next_finish].lr_done == jobs[next_finish].t->lowrank.size()) {
@@ -842,11 +879,12 @@ std::vector<hm_matrix*> assemble_batch(hm_ctx& ctx, const std::vector<const hm_t
     // blocks of at most 64 x 64 (rank cap <= 32): one wave each; larger ones:
     // one workgroup each (512 threads from m + n >= ACA_HUGE), largest
     // first for the hardware dispatcher
-    std::vector<AcaDev> small, large, huge, full;
+    std::vector<AcaDev> small, large, huge, full, full_big;
     for (size_t q = 0; q < batch.size(); ++q) {
       batch[q].out = (int32_t)q;
       const AcaDev& a = batch[q];
-      if (bfull[q]) full.push_back(a);
+      if (bfull[q] && (int64_t)(a.re - a.rb) * (a.ce - a.cb) >= ACA_FULL_BIG) full_big.push_back(a);
+      else if (bfull[q]) full.push_back(a);
       else if (a.re - a.rb <= 64 && a.ce - a.cb <= 64 && a.kcap <= ACAW_K) small.push_back(a);
       else if ((a.re - a.rb) + (a.ce - a.cb) >= ACA_HUGE) huge.push_back(a);
       else large.push_back(a);
@@ -857,20 +895,30 @@ std::vector<hm_matrix*> assemble_batch(hm_ctx& ctx, const std::vector<const hm_t
     std::stable_sort(large.begin(), large.end(), by_size);
     std::stable_sort(huge.begin(), huge.end(), by_size);
     std::stable_sort(full.begin(), full.end(), by_size);
+    std::stable_sort(full_big.begin(), full_big.end(), by_size);
     if ((size_t)sd * 8 > scratch.bytes()) scratch.alloc((size_t)sd * 8);
     if ((size_t)sf * 4 > flags.bytes()) flags.alloc((size_t)sf * 4);
     d_rank.alloc(batch.size() * 4);
     d_status.alloc(batch.size() * 4);
-    if (!huge.empty()) {
+    if (!huge.empty() || !full_big.empty()) {
       // on the side stream, after everything queued so far on s (uploads,
       // scratch), joined back into s before the ranks are read
-      upload(d_blk_huge, huge, s);
+      if (!huge.empty()) upload(d_blk_huge, huge, s);
+      if (!full_big.empty()) upload(d_blk_full_big, full_big, s);
       if (!side) side = std::make_unique<SideStream>();
       HM_HIP(hipEventRecord(side->fork, s));
       HM_HIP(hipStreamWaitEvent(side->st, side->fork, 0));
-      hipLaunchKernelGGL(k_aca<ACA_T_HUGE>, dim3((unsigned)huge.size()), dim3(ACA_T_HUGE), 0, side->st,
-                         d_blk_huge.get<AcaDev>(), g, scratch.get<double>(), flags.get<int>(), d_rank.get<int>(),
-                         d_status.get<int>());
+      if (!huge.empty())
+        hipLaunchKernelGGL(k_aca<ACA_T_HUGE>, dim3((unsigned)huge.size()), dim3(ACA_T_HUGE), 0, side->st,
+                           d_blk_huge.get<AcaDev>(), g, scratch.get<double>(), flags.get<int>(),
+                           d_rank.get<int>(), d_status.get<int>());
+      // fully pivoted blocks of a million entries and more: each cross
+      // streams the whole residual, so they take four times the threads
+      // (and loads in flight) of the others
+      if (!full_big.empty())
+        hipLaunchKernelGGL(k_aca_full<ACA_T_FULL_BIG>, dim3((unsigned)full_big.size()), dim3(ACA_T_FULL_BIG), 0,
+                           side->st, d_blk_full_big.get<AcaDev>(), g, scratch.get<double>(), d_rank.get<int>(),
+                           d_status.get<int>());
       HM_HIP(hipGetLastError());
       HM_HIP(hipEventRecord(side->join, side->st));
     }
@@ -893,7 +941,7 @@ std::vector<hm_matrix*> assemble_batch(hm_ctx& ctx, const std::vector<const hm_t
                          d_rank.get<int>(), d_status.get<int>());
       HM_HIP(hipGetLastError());
     }
-    if (!huge.empty()) HM_HIP(hipStreamWaitEvent(s, side->join, 0));
+    if (!huge.empty() || !full_big.empty()) HM_HIP(hipStreamWaitEvent(s, side->join, 0));
     std::vector<int> rk(batch.size()), st(batch.size());
     HM_HIP(hipMemcpyAsync(rk.data(), d_rank.get(), rk.size() * 4, hipMemcpyDeviceToHost, s));
     HM_HIP(hipMemcpyAsync(st.data(), d_status.get(), st.size() * 4, hipMemcpyDeviceToHost, s));
