@@ -20,6 +20,9 @@ of this geometry's blocks, see the second test).
   solver settings) on the 9,360-facet spiral, open: J and q <= 1e-6.
 * Two implicit Euler steps of the open FP64 transient (2,340 facets, four
   scenarios) against the oracle's: e(T) <= 1e-9.
+* Fully pivoted ACA on sphere-to-sphere blocks of 1.6 M entries (16,640
+  facets, the launch for blocks of a million entries and more): F_H x on
+  sampled rows against the oracle's rows of F times x, <= 1e-5.
 """
 import numpy as np
 import pytest
@@ -179,3 +182,27 @@ def test_spiral_open_transient_fp64(hm, ctx):
     ed = float(np.max(radiosity.relative_l2(to_np(Td) - T0, To - T0)))
     log("newton %d, e(T) %.2e (of the change %.2e)" % (info["newton_total"], e, ed))
     assert e <= 1e-9 and ed <= 1e-7
+
+
+def test_spiral_full_pivot_large_blocks(hm, ctx):
+    """Fully pivoted ACA on blocks of a million entries and more: on the
+    frequency-8 spiral (1,280 facets per sphere) the sphere-to-sphere blocks
+    hold 1.6 M entries and take the launch with 1,024 threads per block.
+    F_H x on 64 sampled rows against the oracle's rows of F (eq. (10)) times
+    x: within 1e-5 of their norm at ACA 1e-6 (eq. (31) bounds each block's
+    error by 1e-6 of its norm)."""
+    cav = configs.fibonacci_spiral(nu=8)
+    n = cav.n
+    log("case: full-pivot ACA with blocks above a million entries, spiral %d facets, FP64, ACA 1e-6" % n)
+    M = _matrix(hm, ctx, cav, 64, 1e-6, hm.HM_F64, hm.HM_F64, pivot=1)
+    st = M.stats()
+    x = np.random.default_rng(81).uniform(0.5, 1.5, n)
+    y = to_np(hm.hm_hmatvec(ctx, M, dt(x), dt(np.zeros(n))))
+    rows = np.sort(np.random.default_rng(82).choice(n, 64, replace=False))
+    c, nr, a = geometry.facets_from_triangles(cav.v, cav.tri)
+    yo = viewfactor.matvec_rows(c, nr, a, rows, x)
+    e = rel(y[rows], yo)
+    log("low-rank blocks %d, rank sum %d, max rank %d; sampled rows of F_H x vs the oracle: %.2e"
+        % (st["n_lowrank_blocks"], st["rank_sum"], st["max_rank"], e))
+    assert st["n_lowrank_blocks"] > 0
+    assert e <= 1e-5
