@@ -47,8 +47,8 @@ struct AcaDev {
 
 constexpr int ACA_T = 256;        // threads per workgroup of k_aca
 constexpr int ACA_T_HUGE = 512;   // ... for blocks with m + n >= ACA_HUGE
-constexpr int ACA_T_FULL_BIG = 1024;           // fully pivoted ACA: threads for blocks of
-constexpr int64_t ACA_FULL_BIG = 1 << 20;      // ... at least this many entries
+constexpr int64_t ACA_FULL_BIG = 1 << 20;  // fully pivoted ACA: blocks of this many entries and more
+                                           // run each pass over many workgroups
 constexpr int ACA_HUGE = 4096;
 constexpr int ACA_KMAX = 1024;
 
@@ -499,6 +499,172 @@ __global__ __launch_bounds__(T) void k_aca_full(const AcaDev* __restrict__ block
     status[b.out] = conv;
   }
 }
+
+// ---- fully pivoted ACA of the largest blocks, each pass over a block's
+// residual spread over many workgroups: slices of FULL_SLICE entries write
+// their partial |R|_F^2 and pivot candidate, and one finishing workgroup
+// per block adds the partials in slice order, takes the pivot, applies the
+// stop test and copies the next cross.  These are k_aca_full's steps and
+// entry arithmetic (so the same pivots); only the order in which the norm's
+// partial sums are added differs.
+constexpr int FULL_T = 256;
+constexpr int FULL_SLICE = FULL_T * FULL_U * 16;  // entries per slice
+struct FullState {
+  double limit;  // tol |X|_F
+  int32_t k;     // current cross (its u, v are column k of U, V)
+  int32_t done;  // 1 once the block has finished (rank and status written)
+};
+struct FullSlice {
+  int32_t blk, s;  // block (index in the launch's list) and slice within it
+};
+
+// Slice pass: the first evaluation of the block (EVAL) or the update of its
+// residual by the current cross; partial |R|_F^2 and pivot candidate to
+// part2[slice], pam[slice].
+template <bool EVAL>
+__global__ __launch_bounds__(FULL_T) void k_full_pass(const AcaDev* __restrict__ blocks,
+                                                      const FullSlice* __restrict__ slices,
+                                                      const FullState* __restrict__ state, Geo g,
+                                                      double* __restrict__ scratch, double* __restrict__ part2,
+                                                      ArgMax* __restrict__ pam) {
+  constexpr int T = FULL_T, W = T / 64;
+  __shared__ ArgMax sh_am[W];
+  __shared__ double sh_sum[W];
+  const FullSlice q = slices[blockIdx.x];
+  if (!EVAL && state[q.blk].done) return;  // uniform over the workgroup
+  const AcaDev b = blocks[q.blk];
+  const int m = b.re - b.rb, n = b.ce - b.cb;
+  const int64_t mn = (int64_t)m * n;
+  const int64_t e0 = (int64_t)q.s * FULL_SLICE;
+  const int64_t e1 = e0 + FULL_SLICE < mn ? e0 + FULL_SLICE : mn;
+  double* R = scratch + b.r_off;
+  const int tid = threadIdx.x;
+  const int64_t et = e0 + tid;
+  const int64_t ec = et < mn ? et : mn - 1;  // a thread past the slice visits nothing
+  const int di = T % m, dj = T / m;
+  int i = (int)(ec % m), j = (int)(ec / m);
+  ArgMax am{-1.0, 0.0, 0x7fffffff};
+  double s2 = 0.0;
+  if (EVAL) {
+    for (int64_t e = et; e < e1; e += T) {
+      const double x = view_factor(g, b.rb + i, b.cb + j);
+      R[e] = x;
+      s2 += x * x;
+      const double a = fabs(x);
+      const int key = i * n + j;
+      if (a > am.mag || (a == am.mag && key < am.idx)) am = ArgMax{a, x, key};
+      i += di;
+      j += dj;
+      if (i >= m) {
+        i -= m;
+        ++j;
+      }
+    }
+  } else {
+    const int k = state[q.blk].k;
+    const double* uk = scratch + b.u_off + (int64_t)k * m;
+    const double* vk = scratch + b.v_off + (int64_t)k * n;
+    for (int64_t e = et; e < e1; e += (int64_t)FULL_U * T) {
+      double rv[FULL_U], uv[FULL_U], vv[FULL_U];
+      int key[FULL_U];
+#pragma unroll
+      for (int u = 0; u < FULL_U; ++u) {
+        const bool in = e + (int64_t)u * T < e1;  // then i < m and j < n
+        key[u] = in ? i * n + j : 0;
+        rv[u] = in ? R[e + (int64_t)u * T] : 0.0;
+        uv[u] = in ? uk[i] : 0.0;
+        vv[u] = in ? vk[j] : 0.0;
+        i += di;
+        j += dj;
+        if (i >= m) {
+          i -= m;
+          ++j;
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < FULL_U; ++u) {
+        if (e + (int64_t)u * T >= e1) break;
+        const double r = rv[u] - uv[u] * vv[u];
+        R[e + (int64_t)u * T] = r;
+        s2 += r * r;
+        const double a = fabs(r);
+        if (a > am.mag || (a == am.mag && key[u] < am.idx)) am = ArgMax{a, r, key[u]};
+      }
+    }
+  }
+  {
+    double t[1] = {s2};
+    block_sum<W, 1>(t, sh_sum);
+    s2 = t[0];
+  }
+  am = block_argmax<W>(am, sh_am);
+  if (tid == 0) {
+    part2[blockIdx.x] = s2;
+    pam[blockIdx.x] = am;
+  }
+}
+
+// Finishing step of a block after a slice pass: the partials of its slices
+// [first[b], first[b + 1]) added in a fixed order; after the first pass the
+// limit tol |X|_F, after an update the cross count, the stop test of eq.
+// (31) and the rank cap; then, unless finished, the next cross u = R(:, jp),
+// v = R(ip, :) / R(ip, jp) into column k of U and V.
+template <bool INIT>
+__global__ __launch_bounds__(FULL_T) void k_full_fin(const AcaDev* __restrict__ blocks, const int* __restrict__ first,
+                                                     FullState* __restrict__ state, double* __restrict__ scratch,
+                                                     const double* __restrict__ part2,
+                                                     const ArgMax* __restrict__ pam, int* __restrict__ rank,
+                                                     int* __restrict__ status) {
+  constexpr int T = FULL_T, W = T / 64;
+  __shared__ ArgMax sh_am[W];
+  __shared__ double sh_sum[W];
+  const int qb = blockIdx.x;
+  FullState st = state[qb];
+  if (!INIT && st.done) return;  // uniform
+  const AcaDev b = blocks[qb];
+  const int m = b.re - b.rb, n = b.ce - b.cb;
+  const int tid = threadIdx.x;
+  double r2 = 0.0;
+  ArgMax am{-1.0, 0.0, 0x7fffffff};
+  for (int s = first[qb] + tid; s < first[qb + 1]; s += T) {
+    r2 += part2[s];
+    am = better(am, pam[s]);
+  }
+  {
+    double t[1] = {r2};
+    block_sum<W, 1>(t, sh_sum);
+    r2 = t[0];
+  }
+  am = block_argmax<W>(am, sh_am);
+  const int k = INIT ? 0 : st.k + 1;
+  const double limit = INIT ? b.tol * sqrt(r2) : st.limit;
+  int done = 0, conv = 0;
+  if (!INIT && sqrt(r2) <= limit) {
+    done = 1;
+    conv = 1;
+  } else if (!INIT && k >= b.kcap) {
+    done = 1;
+  } else if (am.idx == 0x7fffffff || am.val == 0.0) {
+    done = 1;
+    conv = 1;  // zero residual: the crosses so far are exact
+  }
+  if (!done) {
+    const int ip = am.idx / n, jp = am.idx % n;
+    const double piv = am.val;
+    const double* R = scratch + b.r_off;
+    double* uk = scratch + b.u_off + (int64_t)k * m;
+    double* vk = scratch + b.v_off + (int64_t)k * n;
+    for (int r = tid; r < m; r += T) uk[r] = R[(int64_t)jp * m + r];
+    for (int c = tid; c < n; c += T) vk[c] = R[(int64_t)c * m + ip] / piv;
+  }
+  if (tid == 0) {
+    state[qb] = FullState{limit, k, done};
+    if (done) {
+      rank[b.out] = k;
+      status[b.out] = conv;
+    }
+  }
+}
 #pragma clang fp contract(on)
 
 struct CompactDev {
@@ -835,6 +1001,7 @@ std::vector<hm_matrix*> assemble_batch(hm_ctx& ctx, const std::vector<const hm_t
   std::vector<DevBuf> stages;
   std::vector<size_t> stage_last;  // last job with factors in each stage buffer
   DevBuf scratch, flags, d_blk, d_blk_small, d_blk_huge, d_blk_full, d_blk_full_big, d_rank, d_status, d_cd;
+  DevBuf d_full_slices, d_full_first, d_full_state, d_full_part, d_full_pam;  // sliced full pivoting
   size_t jpos = 0, bpos = 0, next_finish = 0;
   auto finish_ready = [&]() {
     while (next_finish < nj && jobs[next_finish].lr_done == jobs[next_finish].t->lowrank.size()) {
@@ -904,7 +1071,27 @@ std::vector<hm_matrix*> assemble_batch(hm_ctx& ctx, const std::vector<const hm_t
       // on the side stream, after everything queued so far on s (uploads,
       // scratch), joined back into s before the ranks are read
       if (!huge.empty()) upload(d_blk_huge, huge, s);
-      if (!full_big.empty()) upload(d_blk_full_big, full_big, s);
+      // the largest fully pivoted blocks: slices of FULL_SLICE entries,
+      // contiguous per block; as many crosses as the widest rank cap
+      std::vector<int> ffirst(full_big.size() + 1, 0);
+      int fkmax = 0;
+      if (!full_big.empty()) {
+        upload(d_blk_full_big, full_big, s);
+        std::vector<FullSlice> fsl;
+        for (size_t q = 0; q < full_big.size(); ++q) {
+          const AcaDev& a = full_big[q];
+          const int64_t mn = (int64_t)(a.re - a.rb) * (a.ce - a.cb);
+          ffirst[q] = (int)fsl.size();
+          for (int64_t e = 0, sq = 0; e < mn; e += FULL_SLICE, ++sq) fsl.push_back(FullSlice{(int32_t)q, (int32_t)sq});
+          fkmax = std::max(fkmax, (int)a.kcap);
+        }
+        ffirst[full_big.size()] = (int)fsl.size();
+        upload(d_full_slices, fsl, s);
+        upload(d_full_first, ffirst, s);
+        d_full_state.alloc(full_big.size() * sizeof(FullState));
+        d_full_part.alloc(fsl.size() * sizeof(double));
+        d_full_pam.alloc(fsl.size() * sizeof(ArgMax));
+      }
       if (!side) side = std::make_unique<SideStream>();
       HM_HIP(hipEventRecord(side->fork, s));
       HM_HIP(hipStreamWaitEvent(side->st, side->fork, 0));
@@ -913,12 +1100,26 @@ std::vector<hm_matrix*> assemble_batch(hm_ctx& ctx, const std::vector<const hm_t
                            d_blk_huge.get<AcaDev>(), g, scratch.get<double>(), flags.get<int>(),
                            d_rank.get<int>(), d_status.get<int>());
       // fully pivoted blocks of a million entries and more: each cross
-      // streams the whole residual, so they take four times the threads
-      // (and loads in flight) of the others
-      if (!full_big.empty())
-        hipLaunchKernelGGL(k_aca_full<ACA_T_FULL_BIG>, dim3((unsigned)full_big.size()), dim3(ACA_T_FULL_BIG), 0,
-                           side->st, d_blk_full_big.get<AcaDev>(), g, scratch.get<double>(), d_rank.get<int>(),
-                           d_status.get<int>());
+      // streams the whole residual, so every pass over it is spread over
+      // many workgroups, with a finishing step per block between passes
+      if (!full_big.empty()) {
+        const unsigned nsl = (unsigned)ffirst[full_big.size()], nbl = (unsigned)full_big.size();
+        const AcaDev* fb = d_blk_full_big.get<AcaDev>();
+        const FullSlice* fs = d_full_slices.get<FullSlice>();
+        FullState* fst = d_full_state.get<FullState>();
+        hipLaunchKernelGGL(k_full_pass<true>, dim3(nsl), dim3(FULL_T), 0, side->st, fb, fs, (const FullState*)fst, g,
+                           scratch.get<double>(), d_full_part.get<double>(), d_full_pam.get<ArgMax>());
+        hipLaunchKernelGGL(k_full_fin<true>, dim3(nbl), dim3(FULL_T), 0, side->st, fb, d_full_first.get<int>(), fst,
+                           scratch.get<double>(), (const double*)d_full_part.get<double>(),
+                           (const ArgMax*)d_full_pam.get<ArgMax>(), d_rank.get<int>(), d_status.get<int>());
+        for (int c = 0; c < fkmax; ++c) {
+          hipLaunchKernelGGL(k_full_pass<false>, dim3(nsl), dim3(FULL_T), 0, side->st, fb, fs, (const FullState*)fst,
+                             g, scratch.get<double>(), d_full_part.get<double>(), d_full_pam.get<ArgMax>());
+          hipLaunchKernelGGL(k_full_fin<false>, dim3(nbl), dim3(FULL_T), 0, side->st, fb, d_full_first.get<int>(),
+                             fst, scratch.get<double>(), (const double*)d_full_part.get<double>(),
+                             (const ArgMax*)d_full_pam.get<ArgMax>(), d_rank.get<int>(), d_status.get<int>());
+        }
+      }
       HM_HIP(hipGetLastError());
       HM_HIP(hipEventRecord(side->join, side->st));
     }
