@@ -47,7 +47,7 @@ struct AcaDev {
 
 constexpr int ACA_T = 256;        // threads per workgroup of k_aca
 constexpr int ACA_T_HUGE = 512;   // ... for blocks with m + n >= ACA_HUGE
-constexpr int64_t ACA_FULL_BIG = 1 << 20;  // fully pivoted ACA: blocks of this many entries and more
+constexpr int64_t ACA_FULL_BIG = 1 << 18;  // fully pivoted ACA: blocks of this many entries and more
                                            // run each pass over many workgroups
 constexpr int ACA_HUGE = 4096;
 constexpr int ACA_KMAX = 1024;
@@ -1099,7 +1099,7 @@ std::vector<hm_matrix*> assemble_batch(hm_ctx& ctx, const std::vector<const hm_t
         hipLaunchKernelGGL(k_aca<ACA_T_HUGE>, dim3((unsigned)huge.size()), dim3(ACA_T_HUGE), 0, side->st,
                            d_blk_huge.get<AcaDev>(), g, scratch.get<double>(), flags.get<int>(),
                            d_rank.get<int>(), d_status.get<int>());
-      // fully pivoted blocks of a million entries and more: each cross
+      // fully pivoted blocks of ACA_FULL_BIG entries and more: each cross
       // streams the whole residual, so every pass over it is spread over
       // many workgroups, with a finishing step per block between passes
       if (!full_big.empty()) {

@@ -21,7 +21,7 @@ of this geometry's blocks, see the second test).
 * Two implicit Euler steps of the open FP64 transient (2,340 facets, four
   scenarios) against the oracle's: e(T) <= 1e-9.
 * Fully pivoted ACA on sphere-to-sphere blocks of 1.6 M entries (16,640
-  facets, the launch for blocks of a million entries and more): F_H x on
+  facets, the sliced passes for blocks of 262,144 entries and more): F_H x on
   sampled rows against the oracle's rows of F times x, <= 1e-5.
 """
 import numpy as np
@@ -185,15 +185,16 @@ def test_spiral_open_transient_fp64(hm, ctx):
 
 
 def test_spiral_full_pivot_large_blocks(hm, ctx):
-    """Fully pivoted ACA on blocks of a million entries and more: on the
-    frequency-8 spiral (1,280 facets per sphere) the sphere-to-sphere blocks
-    hold 1.6 M entries and take the launch with 1,024 threads per block.
+    """Fully pivoted ACA on large blocks: on the frequency-8 spiral (1,280
+    facets per sphere) the sphere-to-sphere blocks hold 1.6 M entries, and
+    blocks of 262,144 entries and more run their residual passes in slices
+    over many workgroups.
     F_H x on 64 sampled rows against the oracle's rows of F (eq. (10)) times
     x: within 1e-5 of their norm at ACA 1e-6 (eq. (31) bounds each block's
     error by 1e-6 of its norm)."""
     cav = configs.fibonacci_spiral(nu=8)
     n = cav.n
-    log("case: full-pivot ACA with blocks above a million entries, spiral %d facets, FP64, ACA 1e-6" % n)
+    log("case: full-pivot ACA with sliced passes over large blocks, spiral %d facets, FP64, ACA 1e-6" % n)
     M = _matrix(hm, ctx, cav, 64, 1e-6, hm.HM_F64, hm.HM_F64, pivot=1)
     st = M.stats()
     x = np.random.default_rng(81).uniform(0.5, 1.5, n)
