@@ -431,7 +431,8 @@ typedef struct {
   double krylov_rtol;      /* relative tolerance of each correction's preconditioned solve */
   int32_t max_krylov;      /* Krylov iterations per correction (>= 1) */
   double pc_rtol;          /* conjugate gradients for (M/dt + K)^-1 to this relative residual */
-  hm_solve_params solve;   /* the cavity solves (want_q and open_cavity ignored: closed cavity) */
+  hm_solve_params solve;   /* the cavity solves (want_q and open_cavity ignored: closed cavity); those
+                              inside Jacobian products stop at max(solve.rtol, krylov_rtol / 100) */
   double sigma;            /* Stefan-Boltzmann constant */
 } hm_fe_params;
 

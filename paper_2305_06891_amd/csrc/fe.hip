@@ -317,9 +317,10 @@ void axpby(hm_fe& fe, double a, const double* x, double b, double* y, hipStream_
 }
 
 // out = S w_nodal for the facet power eta (already in fe.eta): out =
-// P^T diag(A) q(eta), one cavity solve
-void apply_rbar(hm_fe& fe, double* out, hipStream_t s) {
+// P^T diag(A) q(eta), one cavity solve to the relative residual rtol
+void apply_rbar(hm_fe& fe, double* out, double rtol, hipStream_t s) {
   hm_solve_params sp = fe.p.solve;
+  sp.rtol = rtol;
   sp.want_q = 1;
   sp.open_cavity = 0;
   SolveResult R = fe.B->solve({fe.eps.get<double>()}, {fe.eta.get<double>()}, {fe.nf}, fe.p.sigma, sp,
@@ -336,7 +337,7 @@ void cavity_load(hm_fe& fe, const double* T, double* Q, hipStream_t s) {
   hipLaunchKernelGGL(k_fe_facet, rows_grid(fe.nf), dim3(256), 0, s, fe.tri.get<int32_t>(), fe.nf, T,
                      (const double*)nullptr, 0, fe.eta.get<double>());
   HM_HIP(hipGetLastError());
-  apply_rbar(fe, Q, s);
+  apply_rbar(fe, Q, fe.p.solve.rtol, s);
 }
 
 // z = (M/dt + K)^-1 r by conjugate gradients with the diagonal as
@@ -384,7 +385,10 @@ void prec_jacobian(hm_fe& fe, const double* T, const double* v, double* y, std::
   hipLaunchKernelGGL(k_fe_facet, rows_grid(fe.nf), dim3(256), 0, s, fe.tri.get<int32_t>(), fe.nf, T, v, 1,
                      fe.eta.get<double>());
   HM_HIP(hipGetLastError());
-  apply_rbar(fe, tmp, s);
+  // a Jacobian product needs its cavity solve only two orders below the
+  // Krylov tolerance (the product's relative error is about cond(C) times
+  // the solve's residual); the residual's own solves keep solve.rtol
+  apply_rbar(fe, tmp, std::max(fe.p.solve.rtol, 1e-2 * fe.p.krylov_rtol), s);
   pc_solve(fe, tmp, y, w, s);
   axpby(fe, 1.0, v, -1.0, y, s);
 }
